@@ -1,0 +1,377 @@
+"""CPU oracle for the falcON tree step -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library never calls it and shares
+no code with it.  The arithmetic lives in ``ncorp_oracle.c`` (plain C, FP64);
+this file only marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ncorp_oracle.c")
+_LIB = os.path.join(_HERE, "libncorp_oracle.so")
+_lib = None
+
+_f64 = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u64 = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP for the plain sums)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build()
+    L = C.CDLL(_LIB)
+    d, i64, i32, vp = C.c_double, C.c_int64, C.c_int, C.c_void_p
+    L.orc_pair_test.restype = C.c_int
+    L.orc_pair_test.argtypes = [d] * 15
+    L.orc_root_half_width.restype = d
+    L.orc_root_half_width.argtypes = [_f64, _f64, _f64, i64]
+    L.orc_quantize.restype = C.c_uint32
+    L.orc_quantize.argtypes = [d, d]
+    L.orc_hilbert_index.restype = C.c_uint64
+    L.orc_hilbert_index.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, i32]
+    L.orc_hilbert_keys.restype = None
+    L.orc_hilbert_keys.argtypes = [_f64, _f64, _f64, i64, d, _u64]
+    L.orc_tree_build.restype = vp
+    L.orc_tree_build.argtypes = [_f64, _f64, _f64, i64, d, i32]
+    L.orc_tree_free.restype = None
+    L.orc_tree_free.argtypes = [vp]
+    L.orc_tree_ncells.restype = i64
+    L.orc_tree_ncells.argtypes = [vp]
+    L.orc_tree_maxlevel.restype = i32
+    L.orc_tree_maxlevel.argtypes = [vp]
+    L.orc_tree_export.restype = None
+    L.orc_tree_export.argtypes = [vp, _i32, _i32, _i32, _i32, _i32, _i32, _u64, _i64, _u64]
+    L.orc_theta_of_mass.restype = d
+    L.orc_theta_of_mass.argtypes = [d, d, d]
+    L.orc_green_derivs.restype = None
+    L.orc_green_derivs.argtypes = [_f64, i32, _f64]
+    L.orc_green_deriv_full.restype = None
+    L.orc_green_deriv_full.argtypes = [_f64, i32, _f64]
+    L.orc_grav_new.restype = vp
+    L.orc_grav_new.argtypes = [vp, _f64, _f64, _f64, _f64, d, i32, d, i32]
+    L.orc_grav_run.restype = None
+    L.orc_grav_run.argtypes = [vp, i32, i32, i32]
+    L.orc_grav_accel.restype = None
+    L.orc_grav_accel.argtypes = [vp, _f64, _f64, _f64]
+    L.orc_grav_counts.restype = None
+    L.orc_grav_counts.argtypes = [vp, _i64]
+    L.orc_grav_lists.restype = None
+    L.orc_grav_lists.argtypes = [vp, _i32, _i32]
+    L.orc_grav_cells.restype = None
+    L.orc_grav_cells.argtypes = [vp, _f64, _f64, _f64, _f64]
+    L.orc_grav_msize.restype = i32
+    L.orc_grav_msize.argtypes = [vp]
+    L.orc_grav_csize.restype = i32
+    L.orc_grav_csize.argtypes = [vp]
+    L.orc_grav_cell_tensors.restype = None
+    L.orc_grav_cell_tensors.argtypes = [vp, i64, _f64, _f64]
+    L.orc_grav_free.restype = None
+    L.orc_grav_free.argtypes = [vp]
+    L.orc_expansion_field.restype = None
+    L.orc_expansion_field.argtypes = [_f64, _f64, _f64, _f64, i64, _f64, _f64, _f64, _f64,
+                                      i64, i32, _f64, _f64, _f64]
+    L.orc_shift_C.restype = None
+    L.orc_shift_C.argtypes = [_f64, i32, _f64, _f64]
+    L.orc_coll_new.restype = vp
+    L.orc_coll_new.argtypes = [vp, _f64, _f64, _f64, _f64, _f64, _f64, _f64, d]
+    L.orc_coll_run.restype = i64
+    L.orc_coll_run.argtypes = [vp, i32, i32, i32]
+    L.orc_coll_pairs.restype = None
+    L.orc_coll_pairs.argtypes = [vp, _i64]
+    L.orc_coll_ncand.restype = i64
+    L.orc_coll_ncand.argtypes = [vp]
+    L.orc_coll_ntests.restype = i64
+    L.orc_coll_ntests.argtypes = [vp]
+    L.orc_coll_cand.restype = None
+    L.orc_coll_cand.argtypes = [vp, _i32]
+    L.orc_coll_cells.restype = None
+    L.orc_coll_cells.argtypes = [vp, _f64, _f64, _f64]
+    L.orc_coll_free.restype = None
+    L.orc_coll_free.argtypes = [vp]
+    L.orc_direct_sum.restype = None
+    L.orc_direct_sum.argtypes = [_f64, _f64, _f64, _f64, i64, d, _i64, i64, _f64, _f64, _f64]
+    L.orc_pairs_brute.restype = i64
+    L.orc_pairs_brute.argtypes = [_f64] * 7 + [i64, d, _i64, i64]
+    L.orc_pairs_of.restype = i64
+    L.orc_pairs_of.argtypes = [_f64] * 7 + [i64, d, _i64, i64, _i64, i64]
+    _lib = L
+    return L
+
+
+def _c(a, dtype=np.float64):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ---------------------------------------------------------------- plain pieces
+def pair_test(r1, v1, R1, r2, v2, R2, dt) -> bool:
+    return bool(lib().orc_pair_test(*map(float, r1), *map(float, v1), float(R1),
+                                    *map(float, r2), *map(float, v2), float(R2), float(dt)))
+
+
+def root_half_width(x, y, z) -> float:
+    return lib().orc_root_half_width(_c(x), _c(y), _c(z), len(x))
+
+
+def quantize(v: float, L: float) -> int:
+    return int(lib().orc_quantize(float(v), float(L)))
+
+
+def hilbert_index(cx: int, cy: int, cz: int, bits: int) -> int:
+    return int(lib().orc_hilbert_index(cx, cy, cz, bits))
+
+
+def hilbert_keys(x, y, z, L: float) -> np.ndarray:
+    out = np.empty(len(x), dtype=np.uint64)
+    lib().orc_hilbert_keys(_c(x), _c(y), _c(z), len(x), float(L), out)
+    return out
+
+
+def theta_of_mass(M: float, M_root: float, theta_min: float) -> float:
+    return lib().orc_theta_of_mass(float(M), float(M_root), float(theta_min))
+
+
+def green_derivs(R, nmax: int) -> np.ndarray:
+    """D[a, b, c] = d^a/dx^a d^b/dy^b d^c/dz^c (1/|R|), zero above total order nmax."""
+    out = np.zeros(7 ** 3)
+    lib().orc_green_derivs(_c(R), nmax, out)
+    return out.reshape(7, 7, 7)
+
+
+def green_deriv_full(R, n: int) -> np.ndarray:
+    out = np.zeros(3 ** n)
+    lib().orc_green_deriv_full(_c(R), n, out)
+    return out.reshape((3,) * n) if n > 0 else out
+
+
+def expansion_field(src_pos, src_mu, sA, tgt_pos, p: int):
+    xs, ys, zs = (_c(src_pos[:, k]) for k in range(3))
+    xt, yt, zt = (_c(tgt_pos[:, k]) for k in range(3))
+    nt = len(xt)
+    ax, ay, az = np.zeros(nt), np.zeros(nt), np.zeros(nt)
+    lib().orc_expansion_field(xs, ys, zs, _c(src_mu), len(xs), _c(sA), xt, yt, zt, nt, p,
+                              ax, ay, az)
+    return np.stack([ax, ay, az], axis=1)
+
+
+def shift_C(Cin, p: int, d) -> np.ndarray:
+    out = np.zeros_like(_c(Cin))
+    lib().orc_shift_C(_c(Cin), p, _c(d), out)
+    return out
+
+
+# ---------------------------------------------------------------- tree
+class Tree:
+    """Pointer-insertion octree, flattened by level then Hilbert order."""
+
+    def __init__(self, x, y, z, s: int, L: float | None = None):
+        self.x, self.y, self.z = _c(x), _c(y), _c(z)
+        self.n = len(self.x)
+        self.L = root_half_width(self.x, self.y, self.z) if L is None else float(L)
+        self.s = s
+        self._h = lib().orc_tree_build(self.x, self.y, self.z, self.n, self.L, s)
+        if not self._h:
+            raise ValueError("oracle tree build rejected its arguments")
+        nc = lib().orc_tree_ncells(self._h)
+        self.ncells = nc
+        self.maxlevel = lib().orc_tree_maxlevel(self._h)
+        self.level = np.empty(nc, np.int32)
+        self.first = np.empty(nc, np.int32)
+        self.count = np.empty(nc, np.int32)
+        self.child_first = np.empty(nc, np.int32)
+        self.nchild = np.empty(nc, np.int32)
+        self.parent = np.empty(nc, np.int32)
+        self.prefix = np.empty(nc, np.uint64)
+        self.perm = np.empty(self.n, np.int64)
+        self.keys = np.empty(self.n, np.uint64)
+        lib().orc_tree_export(self._h, self.level, self.first, self.count, self.child_first,
+                              self.nchild, self.parent, self.prefix, self.perm, self.keys)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_tree_free(h)
+            self._h = None
+
+
+class Gravity:
+    """Climb + TreeWalk + descent of the oracle tree (FP64, full tensors)."""
+
+    def __init__(self, tree: Tree, m, G: float = 1.0, p: int = 3, theta_min: float = 0.5,
+                 theta_mode: int = 0):
+        self.tree = tree
+        self.p = p
+        self._h = lib().orc_grav_new(tree._h, tree.x, tree.y, tree.z, _c(m), float(G), p,
+                                     float(theta_min), theta_mode)
+
+    def run(self, ncs: int, ncc_pre: int, ncc_post: int):
+        lib().orc_grav_run(self._h, ncs, ncc_pre, ncc_post)
+        return self
+
+    def accel(self) -> np.ndarray:
+        n = self.tree.n
+        ax, ay, az = np.zeros(n), np.zeros(n), np.zeros(n)
+        lib().orc_grav_accel(self._h, ax, ay, az)
+        return np.stack([ax, ay, az], axis=1)
+
+    def counts(self):
+        out = np.zeros(3, np.int64)
+        lib().orc_grav_counts(self._h, out)
+        return {"m2l": int(out[0]), "p2p": int(out[1]), "p2p_moonlet_pairs": int(out[2])}
+
+    def lists(self):
+        c = self.counts()
+        m2l = np.zeros((max(c["m2l"], 1), 2), np.int32)
+        p2p = np.zeros((max(c["p2p"], 1), 2), np.int32)
+        lib().orc_grav_lists(self._h, m2l, p2p)
+        return m2l[: c["m2l"]], p2p[: c["p2p"]]
+
+    def cells(self):
+        nc = self.tree.ncells
+        s = np.zeros((nc, 3)); mass = np.zeros(nc); rmax = np.zeros(nc); rcrit = np.zeros(nc)
+        lib().orc_grav_cells(self._h, s, mass, rmax, rcrit)
+        return {"s": s, "mass": mass, "rmax": rmax, "rcrit": rcrit}
+
+    def cell_tensors(self, c: int):
+        ms, cs = lib().orc_grav_msize(self._h), lib().orc_grav_csize(self._h)
+        M = np.zeros(max(ms, 1)); Cc = np.zeros(max(cs, 1))
+        lib().orc_grav_cell_tensors(self._h, int(c), M, Cc)
+        return M[:ms], Cc[:cs]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_grav_free(h)
+            self._h = None
+
+
+class Collide:
+    """Collision climb + TreeWalk with collision semantics on the oracle tree."""
+
+    def __init__(self, tree: Tree, vx, vy, vz, R, dt: float):
+        self.tree = tree
+        self._h = lib().orc_coll_new(tree._h, tree.x, tree.y, tree.z, _c(vx), _c(vy), _c(vz),
+                                     _c(R), float(dt))
+
+    def run(self, ncs: int = 12, ncc_pre: int = 0, ncc_post: int = 16) -> np.ndarray:
+        n = lib().orc_coll_run(self._h, ncs, ncc_pre, ncc_post)
+        out = np.zeros((max(n, 1), 2), np.int64)
+        lib().orc_coll_pairs(self._h, out)
+        return out[:n]
+
+    def candidates(self) -> np.ndarray:
+        k = lib().orc_coll_ncand(self._h)
+        out = np.zeros((max(k, 1), 2), np.int32)
+        lib().orc_coll_cand(self._h, out)
+        return out[:k]
+
+    def ntests(self) -> int:
+        return int(lib().orc_coll_ntests(self._h))
+
+    def cells(self):
+        nc = self.tree.ncells
+        sbar = np.zeros((nc, 3)); rmax = np.zeros(nc); rcrit = np.zeros(nc)
+        lib().orc_coll_cells(self._h, sbar, rmax, rcrit)
+        return {"sbar": sbar, "rmax": rmax, "rcrit": rcrit}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_coll_free(h)
+            self._h = None
+
+
+# ---------------------------------------------------------------- plain sums
+def direct_sum(x, y, z, m, G: float = 1.0, targets=None) -> np.ndarray:
+    n = len(x)
+    t = np.arange(n, dtype=np.int64) if targets is None else _c(targets, np.int64)
+    ax, ay, az = np.zeros(len(t)), np.zeros(len(t)), np.zeros(len(t))
+    lib().orc_direct_sum(_c(x), _c(y), _c(z), _c(m), n, float(G), t, len(t), ax, ay, az)
+    return np.stack([ax, ay, az], axis=1)
+
+
+def pairs_brute(d: dict, dt: float, cap: int = 1 << 20) -> np.ndarray:
+    n = len(d["x"])
+    out = np.zeros((cap, 2), np.int64)
+    k = lib().orc_pairs_brute(*(_c(d[f]) for f in ("x", "y", "z", "vx", "vy", "vz", "R")), n,
+                              float(dt), out, cap)
+    if k > cap:
+        return pairs_brute(d, dt, cap=int(k))
+    return out[:k]
+
+
+def pairs_of(d: dict, dt: float, targets, cap: int = 1 << 20) -> np.ndarray:
+    n = len(d["x"])
+    t = _c(targets, np.int64)
+    out = np.zeros((cap, 2), np.int64)
+    k = lib().orc_pairs_of(*(_c(d[f]) for f in ("x", "y", "z", "vx", "vy", "vz", "R")), n,
+                           float(dt), t, len(t), out, cap)
+    if k > cap:
+        return pairs_of(d, dt, targets, cap=int(k))
+    res = out[:k]
+    if len(res):
+        res = np.unique(res, axis=0)
+    return res
+
+
+def central_accel(x, y, z, G: float = 1.0, M_central: float = 1.0) -> np.ndarray:
+    """-G M_c r / |r|^3 (App. B.1)."""
+    r2 = x * x + y * y + z * z
+    f = -G * M_central / (r2 * np.sqrt(r2))
+    return np.stack([f * x, f * y, f * z], axis=1)
+
+
+def tree_accel(d: dict, G=1.0, p=3, theta_min=0.5, s=16, ncs=64, ncc_pre=8, ncc_post=64,
+               theta_mode=0, L=None):
+    """Mutual accelerations by the oracle falcON tree, input order."""
+    t = Tree(d["x"], d["y"], d["z"], s, L)
+    g = Gravity(t, d["m"], G, p, theta_min, theta_mode).run(ncs, ncc_pre, ncc_post)
+    return g.accel(), t, g
+
+
+def kdk_steps(d: dict, dt: float, n_steps: int, accel_fn, G=1.0, M_central=1.0,
+              collide_fn=None):
+    """Merged kick-drift-kick leapfrog around the central mass (Sect. 4.1, SBAB1
+    form): v += dt/2 a; [collision search on (x, v)]; x += dt v; a = a(x); v += dt/2 a.
+    Returns the new state and the per-step pair lists."""
+    s = {k: np.array(v, dtype=np.float64) for k, v in d.items()}
+
+    def total_acc():
+        a = central_accel(s["x"], s["y"], s["z"], G, M_central)
+        if accel_fn is not None:
+            a = accel_fn(s) + a
+        return a
+
+    a = total_acc()
+    pairs = []
+    for k in range(n_steps):
+        for c, f in enumerate(("vx", "vy", "vz")):
+            s[f] = s[f] + 0.5 * dt * a[:, c]
+        if collide_fn is not None:
+            pairs.append(collide_fn(s, dt))
+        for c, f in enumerate(("x", "y", "z")):
+            s[f] = s[f] + dt * s[("vx", "vy", "vz")[c]]
+        a = total_acc()
+        for c, f in enumerate(("vx", "vy", "vz")):
+            s[f] = s[f] + 0.5 * dt * a[:, c]
+    return s, pairs
