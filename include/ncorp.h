@@ -1,0 +1,178 @@
+/*
+ * ncorp.h -- C ABI of libncorp, the MI355X (gfx950) falcON tree step.
+ *
+ * The library implements the falcON-style O(N) tree step of NcorpiON
+ * (Couturier, Quillen & Nakajima): Hilbert-key sort and octree build
+ * (Sect. 3.4.1, Sect. 3.4.6), upward pass with Cartesian multipole moments up to
+ * order 6 (Eq. 20, App. C), the dual tree walk (Alg. 2) with interaction tensors
+ * (Eq. 25) and direct sums, the downward shift (Eq. 26), the same walk reused
+ * for collision search (Sect. 3.1 Eqs. 1-2, Eqs. 7-9), and a kick-drift-kick
+ * leapfrog around a central mass (Sect. 4.1, App. B.1).
+ *
+ * Conventions for every entry point:
+ *  - Memory.  Every array argument is a DEVICE pointer owned by the caller.  The
+ *    library never allocates device memory: all scratch space lives in the
+ *    caller's workspace (ncorp_workspace_bytes).  Arrays are plain
+ *    structure-of-arrays, FP64 unless noted, indexed by the caller's (input)
+ *    moonlet index.
+ *  - Streams.  `stream` is a hipStream_t passed as void* (NULL = default
+ *    stream).  Calls only enqueue work and return; nothing waits for the GPU
+ *    except ncorp_get_status, ncorp_tree_info and ncorp_export_host.
+ *  - Errors.  Argument errors are detected on the host and returned at once
+ *    (NCORP_E_INVALID, nothing enqueued).  Conditions only the GPU can see
+ *    (a capacity exceeded, a non-finite position) are latched in a status word
+ *    inside the workspace and reported by ncorp_get_status; outputs of such a
+ *    call are then incomplete and must be discarded.
+ *  - A context is not thread-safe and must not be used on two streams at once.
+ *    Workspace contents persist between calls: ncorp_gravity and ncorp_collide
+ *    use the tree of the last ncorp_build_tree on the same context.
+ */
+#ifndef NCORP_H
+#define NCORP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NCORP_OK = 0,
+    NCORP_E_INVALID = -1,      /* bad argument (host-side check) */
+    NCORP_E_CAPACITY = -2,     /* a device list overflowed; see required size */
+    NCORP_E_HIP = -3,          /* a HIP runtime call failed */
+    NCORP_E_UNSUPPORTED = -4,  /* valid request this build does not provide */
+    NCORP_E_NONFINITE = -5     /* a position was NaN or infinite */
+} ncorp_status;
+
+typedef enum {
+    NCORP_FP64 = 0,            /* every floating-point step in FP64 */
+    NCORP_FP32_BULK = 1        /* direct sums and interaction tensors in FP32 with
+                                  compensated accumulation; positions, offsets,
+                                  climbs, shifts and the integrator in FP64 */
+} ncorp_precision;
+
+/* Parameters of the method.  Defaults: ncorp_params_default. */
+typedef struct {
+    double G;                  /* gravitational constant (paper default 4 pi^2, App. B.1) */
+    double M_central;          /* central mass, not part of the tree (Sect. 3.4.3) */
+    int p;                     /* expansion order 0..6 (Sect. 3.4.3); 0 = no mutual gravity */
+    double theta_min;          /* opening angle of the root cell, 0 < theta_min < 1 */
+    int theta_mode;            /* 0: mass-dependent theta(M) (Sect. 3.4.2, Dehnen's
+                                  relation); 1: constant theta = theta_min */
+    int leaf_size;             /* s: cells with <= s moonlets are leaves (Sect. 3.4.1) */
+    int ncs, ncc_pre, ncc_post;               /* gravity walk thresholds (Alg. 2) */
+    int ncs_col, ncc_pre_col, ncc_post_col;   /* collision walk thresholds (Alg. 2) */
+    int precision;             /* ncorp_precision */
+    double root_half_width;    /* 0 = smallest power of two above every |coordinate| */
+    /* capacities of device lists; 0 = automatic from n_max and leaf_size */
+    int64_t cell_capacity;     /* octree cells */
+    int64_t m2l_capacity;      /* well-separated cell pairs of one walk */
+    int64_t p2p_capacity;      /* cell pairs treated by direct sums in one walk */
+    int64_t queue_capacity;    /* cell pairs visited by one walk */
+} ncorp_params;
+
+typedef struct ncorp_ctx ncorp_ctx;
+
+/* Defaults from the paper's timing runs (Sect. 4.2): order p with s = 17 and
+ * thresholds (64, 8, 64) for p <= 3, s = 52 and (256, 256, 512) above; collision
+ * thresholds (12, 0, 16); theta_min = 0.5, mass-dependent theta; G = 1,
+ * M_central = 1; FP64.  Returns NCORP_E_INVALID for p outside 0..6. */
+int ncorp_params_default(ncorp_params *out, int p);
+
+/* Validates the parameters (p in 0..6, 0 < theta_min < 1, s >= 1, thresholds
+ * >= 0, G >= 0) and creates a host-side context.  No device memory is touched. */
+int ncorp_create(const ncorp_params *params, ncorp_ctx **out);
+void ncorp_destroy(ncorp_ctx *ctx);
+
+/* Bytes of device workspace needed for up to n_max moonlets and a collision
+ * pair buffer of pair_capacity entries; -1 on invalid arguments.  The workspace
+ * must be 256-byte aligned. */
+int64_t ncorp_workspace_bytes(const ncorp_params *params, int64_t n_max,
+                              int64_t pair_capacity);
+
+/* Root cube, 63-bit Hilbert keys, stable radix sort by (key, input index) and
+ * the flat octree: cells ordered by level, then Hilbert order inside a level,
+ * children contiguous (Sect. 3.4.1, Sect. 3.4.6).  x, y, z: n FP64 positions.
+ * The tree stays in the workspace for later calls on this context. */
+int ncorp_build_tree(ncorp_ctx *ctx, const double *x, const double *y, const double *z,
+                     int64_t n, void *workspace, int64_t ws_bytes, void *stream);
+
+/* Mutual gravitational acceleration of every moonlet on the last tree (Eqs. 10-12,
+ * 20, 25, 26 and Alg. 2): a_i = sum_j G m_j (x_j - x_i)/|x_j - x_i|^3 as
+ * approximated by the falcON walk.  m: n masses; ax, ay, az: n outputs, input
+ * order.  The central mass is NOT included here. */
+int ncorp_gravity(ncorp_ctx *ctx, const double *m, double *ax, double *ay, double *az,
+                  void *stream);
+
+/* Collision search on the last tree (Sect. 3.1 and Sect. 3.4.2): every pair i < j
+ * whose straight-line trajectories touch at a time 0 <= t <= dt (Eqs. 1-2).
+ * vx, vy, vz, R: n FP64 velocities and radii.  pairs: cap x 2 int64, written in
+ * lexicographic order, no duplicates; n_pairs_dev: one int64 (device) receiving the
+ * number found (which may exceed cap: then the status is NCORP_E_CAPACITY). */
+int ncorp_collide(ncorp_ctx *ctx, const double *vx, const double *vy, const double *vz,
+                  const double *R, double dt, int64_t *pairs, int64_t cap,
+                  int64_t *n_pairs_dev, void *stream);
+
+/* n_steps of the merged kick-drift-kick leapfrog (Sect. 4.1) around the central
+ * mass (App. B.1): the first call builds the tree and gravity at the start state;
+ * every step then kicks, searches collisions on (x, v) over dt with the current
+ * tree, drifts, rebuilds the tree, recomputes gravity (mutual + central) and
+ * kicks.  x..vz are updated in place.  Collisions are reported, not resolved:
+ * pairs receives (step, i, j) triples, cap x 3 int64, each step's pairs in
+ * lexicographic order; n_pairs_dev receives n_steps int64 counts. */
+int ncorp_step(ncorp_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,
+               double *vz, const double *m, const double *R, int64_t n, double dt,
+               int n_steps, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev,
+               void *workspace, int64_t ws_bytes, void *stream);
+
+/* Waits for the context's last stream, then reports the device status word:
+ * NCORP_OK, NCORP_E_CAPACITY (required_capacity, if not NULL, receives the size
+ * that would have sufficed for the list that overflowed) or NCORP_E_NONFINITE.
+ * The status is cleared by the next ncorp_build_tree / ncorp_step. */
+int ncorp_get_status(ncorp_ctx *ctx, int64_t *required_capacity);
+
+/* Last error message of this context (static storage, never NULL). */
+const char *ncorp_last_error(const ncorp_ctx *ctx);
+
+/* ---- inspection of the last tree and walks (tests, tuning) ---------------- */
+enum {
+    NCORP_INFO_N = 0, NCORP_INFO_NCELLS, NCORP_INFO_NLEAVES, NCORP_INFO_MAXLEVEL,
+    NCORP_INFO_M2L, NCORP_INFO_P2P, NCORP_INFO_VISITED, NCORP_INFO_COL_CAND,
+    NCORP_INFO_COL_TESTS, NCORP_INFO_COUNT
+};
+/* Waits for the stream and fills info[NCORP_INFO_COUNT] with sizes of the last
+ * tree and walks (cells, leaves, deepest level, M2L and P2P cell pairs of the
+ * last gravity walk, visited pairs, collision candidate cell pairs, pair tests). */
+int ncorp_tree_info(ncorp_ctx *ctx, int64_t *info);
+
+enum {
+    NCORP_EXPORT_KEYS = 0,     /* n uint64: sorted Hilbert keys */
+    NCORP_EXPORT_PERM,         /* n int32: tree position -> input index */
+    NCORP_EXPORT_CELLS,        /* ncells x 8 int32: level, first, count,
+                                  child_first (-1 for leaves), nchild, parent,
+                                  prefix low 32 bits, prefix high 32 bits */
+    NCORP_EXPORT_GCELLS,       /* ncells x 8 double: sx, sy, sz, mass, r_max,
+                                  r_crit, theta, 0 (gravity climb) */
+    NCORP_EXPORT_CCELLS,       /* ncells x 4 double: sbar x, y, z, r_crit
+                                  (collision climb); r_max follows as a second
+                                  block of ncells doubles */
+    NCORP_EXPORT_MULTIPOLES,   /* ncells x nm double: M^(n)_a / a! for n = 0, 2..p-1,
+                                  components ordered by order, then (ax, ay, az)
+                                  with ax descending, then ay descending */
+    NCORP_EXPORT_LOCAL,        /* ncells x nc double: C^(m)_a after the walk, m = 1..p,
+                                  same component order (before the descent) */
+    NCORP_EXPORT_M2L,          /* nm2l x 2 int32 cell pairs of the gravity walk */
+    NCORP_EXPORT_P2P,          /* np2p x 2 int32 cell pairs of the gravity walk */
+    NCORP_EXPORT_COL_CAND,     /* ncand x 2 int32 cell pairs of the collision walk */
+    NCORP_EXPORT_COUNT
+};
+/* Copies an internal array to host memory `dst` of `bytes` bytes (waits for the
+ * stream).  Returns the number of bytes the full array needs (copying at most
+ * `bytes`), or a negative ncorp_status. */
+int64_t ncorp_export_host(ncorp_ctx *ctx, int what, void *dst, int64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NCORP_H */

@@ -209,8 +209,11 @@ class Tree:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().orc_tree_free(h)
+        if h and _lib is not None:
+            try:
+                _lib.orc_tree_free(h)
+            except Exception:          # interpreter shutdown
+                pass
             self._h = None
 
 
@@ -260,8 +263,11 @@ class Gravity:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().orc_grav_free(h)
+        if h and _lib is not None:
+            try:
+                _lib.orc_grav_free(h)
+            except Exception:          # interpreter shutdown
+                pass
             self._h = None
 
 
@@ -296,8 +302,11 @@ class Collide:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().orc_coll_free(h)
+        if h and _lib is not None:
+            try:
+                _lib.orc_coll_free(h)
+            except Exception:          # interpreter shutdown
+                pass
             self._h = None
 
 

@@ -1,0 +1,514 @@
+// Host side of libncorp: argument checks, workspace layout and the order in which
+// the kernels of one call are enqueued.  Nothing here allocates device memory and
+// nothing waits for the GPU except the status / inspection calls.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "ncorp_internal.h"
+
+using namespace ncorp;
+
+struct ncorp_ctx {
+    ncorp_params prm;
+    Workspace ws;
+    bool have_tree = false;
+    int64_t n = 0;
+    hipStream_t last = nullptr;
+    char err[256];
+};
+
+static int fail(ncorp_ctx *c, int code, const char *msg) {
+    if (c) std::snprintf(c->err, sizeof(c->err), "%s", msg);
+    return code;
+}
+
+static int hip_fail(ncorp_ctx *c, hipError_t e, const char *where) {
+    if (c)
+        std::snprintf(c->err, sizeof(c->err), "%s: %s", where, hipGetErrorString(e));
+    return NCORP_E_HIP;
+}
+
+#define HIPCHK(ctx, expr)                                      \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+static bool params_ok(const ncorp_params *p, char *why, size_t len) {
+    if (!p) { std::snprintf(why, len, "params is NULL"); return false; }
+    if (p->p < 0 || p->p > kMaxP) { std::snprintf(why, len, "p must be in 0..6"); return false; }
+    if (!(p->theta_min > 0.0 && p->theta_min < 1.0)) {
+        std::snprintf(why, len, "theta_min must be in (0, 1)"); return false;
+    }
+    if (p->theta_mode != 0 && p->theta_mode != 1) {
+        std::snprintf(why, len, "theta_mode must be 0 or 1"); return false;
+    }
+    if (p->leaf_size < 1 || p->leaf_size > 1024) {
+        std::snprintf(why, len, "leaf_size must be in 1..1024"); return false;
+    }
+    if (p->ncs < 0 || p->ncc_pre < 0 || p->ncc_post < 0 || p->ncs_col < 0 ||
+        p->ncc_pre_col < 0 || p->ncc_post_col < 0) {
+        std::snprintf(why, len, "walk thresholds must be >= 0"); return false;
+    }
+    if (!(p->G >= 0.0) || !(p->M_central >= 0.0)) {
+        std::snprintf(why, len, "G and M_central must be >= 0"); return false;
+    }
+    if (p->precision != NCORP_FP64 && p->precision != NCORP_FP32_BULK) {
+        std::snprintf(why, len, "unknown precision"); return false;
+    }
+    if (!(p->root_half_width >= 0.0)) {
+        std::snprintf(why, len, "root_half_width must be >= 0"); return false;
+    }
+    if (p->root_half_width > 0.0) {
+        int e;
+        double f = std::frexp(p->root_half_width, &e);
+        if (f != 0.5) { std::snprintf(why, len, "root_half_width must be a power of two"); return false; }
+    }
+    if (p->cell_capacity < 0 || p->m2l_capacity < 0 || p->p2p_capacity < 0 ||
+        p->queue_capacity < 0) {
+        std::snprintf(why, len, "capacities must be >= 0"); return false;
+    }
+    return true;
+}
+
+extern "C" int ncorp_params_default(ncorp_params *o, int p) {
+    if (!o || p < 0 || p > kMaxP) return NCORP_E_INVALID;
+    std::memset(o, 0, sizeof(*o));
+    o->G = 1.0;
+    o->M_central = 1.0;
+    o->p = p;
+    o->theta_min = 0.5;
+    o->theta_mode = 0;
+    if (p <= 3) { o->leaf_size = 17; o->ncs = 64; o->ncc_pre = 8; o->ncc_post = 64; }
+    else { o->leaf_size = 52; o->ncs = 256; o->ncc_pre = 256; o->ncc_post = 512; }
+    o->ncs_col = 12; o->ncc_pre_col = 0; o->ncc_post_col = 16;
+    o->precision = NCORP_FP64;
+    o->root_half_width = 0.0;
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_create(const ncorp_params *params, ncorp_ctx **out) {
+    char why[128];
+    if (!out) return NCORP_E_INVALID;
+    *out = nullptr;
+    if (!params_ok(params, why, sizeof(why))) return NCORP_E_INVALID;
+    ncorp_ctx *c = new ncorp_ctx();
+    c->prm = *params;
+    c->err[0] = 0;
+    *out = c;
+    return NCORP_OK;
+}
+
+extern "C" void ncorp_destroy(ncorp_ctx *c) { delete c; }
+
+extern "C" const char *ncorp_last_error(const ncorp_ctx *c) {
+    return c ? c->err : "no context";
+}
+
+// ------------------------------------------------------------------ layout
+namespace ncorp {
+
+static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, int64_t pair_cap) {
+    const int64_t n = n_max < 1 ? 1 : n_max;
+    const int s = prm.leaf_size;
+    int64_t cell_cap = prm.cell_capacity > 0 ? prm.cell_capacity : 8 * n / s + 1024;
+    if (cell_cap > (1 << 24) - 2) cell_cap = (1 << 24) - 2;
+    int64_t m2l_cap = prm.m2l_capacity > 0 ? prm.m2l_capacity : 64 * cell_cap + 4096;
+    int64_t p2p_cap = prm.p2p_capacity > 0 ? prm.p2p_capacity : 32 * cell_cap + 4096;
+    int64_t q_cap = prm.queue_capacity > 0 ? prm.queue_capacity
+                                           : m2l_cap + p2p_cap + 16 * cell_cap + 65536;
+    ws.n_max = n;
+    ws.cell_cap = cell_cap;
+    ws.m2l_cap = m2l_cap;
+    ws.p2p_cap = p2p_cap;
+    ws.queue_cap = q_cap;
+    ws.m2l_dir_cap = 2 * m2l_cap;
+    ws.p2p_dir_cap = 4 * p2p_cap + n;
+    ws.pair_cap = pair_cap < 1 ? 1 : pair_cap;
+    ws.p = prm.p;
+    ws.nm = n_mult(prm.p);
+    ws.nl = n_local(prm.p);
+    const int64_t nb = (n + 1023) / 1024;
+    const int64_t ntiles = (n + 4095) / 4096;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off += align256(bytes < 8 ? 8 : bytes);
+        return ws.base ? (void *)(ws.base + o) : nullptr;
+    };
+    ws.st = (DevState *)take(sizeof(DevState));
+    ws.wq = (WalkQueue *)take(sizeof(WalkQueue));
+    ws.keys = (uint64_t *)take(8 * n);
+    ws.keys_alt = (uint64_t *)take(8 * n);
+    ws.idx = (uint32_t *)take(4 * n);
+    ws.idx_alt = (uint32_t *)take(4 * n);
+    ws.code = (uint32_t *)take(4 * n);
+    ws.xs = (double *)take(8 * n);
+    ws.ys = (double *)take(8 * n);
+    ws.zs = (double *)take(8 * n);
+    ws.mus = (double *)take(8 * n);
+    ws.vxs = (double *)take(8 * n);
+    ws.vys = (double *)take(8 * n);
+    ws.vzs = (double *)take(8 * n);
+    ws.rads = (double *)take(8 * n);
+    ws.acc = (double *)take(3 * 8 * n);
+    ws.acc_s = (double *)take(3 * 8 * n);
+    ws.ent_start = (int32_t *)take(4 * n);
+    ws.ent_code = (uint32_t *)take(4 * n);
+    ws.ent_cell = (int32_t *)take(4 * n);
+    ws.c_level = (int32_t *)take(4 * cell_cap);
+    ws.c_first = (int32_t *)take(4 * cell_cap);
+    ws.c_count = (int32_t *)take(4 * cell_cap);
+    ws.c_child = (int32_t *)take(4 * cell_cap);
+    ws.c_nchild = (int32_t *)take(4 * cell_cap);
+    ws.c_parent = (int32_t *)take(4 * cell_cap);
+    ws.c_entry = (int32_t *)take(4 * cell_cap);
+    ws.c_nent = (int32_t *)take(4 * cell_cap);
+    ws.c_prefix = (uint64_t *)take(8 * cell_cap);
+    ws.c_arrive = (int32_t *)take(4 * cell_cap);
+    ws.gcell = (double4 *)take(32 * cell_cap);
+    ws.c_mass = (double *)take(8 * cell_cap);
+    ws.c_rmax = (double *)take(8 * cell_cap);
+    ws.c_theta = (double *)take(8 * cell_cap);
+    ws.mult = (double *)take(8 * cell_cap * (ws.nm > 0 ? ws.nm : 1));
+    ws.mult32 = (float *)take(4 * cell_cap * (ws.nm > 0 ? ws.nm : 1));
+    ws.local = (double *)take(8 * cell_cap * (ws.nl > 0 ? ws.nl : 1));
+    ws.cleaf = (double *)take(8 * (cell_cap < n ? cell_cap : n) * (ws.nl > 0 ? ws.nl : 1));
+    ws.ccell = (double4 *)take(32 * cell_cap);
+    ws.c_crmax = (double *)take(8 * cell_cap);
+    ws.queue = (uint64_t *)take(8 * q_cap);
+    ws.m2l = (int2 *)take(8 * m2l_cap);
+    ws.p2p = (int2 *)take(8 * p2p_cap);
+    ws.cand = (int2 *)take(8 * p2p_cap);
+    ws.m2l_off = (int32_t *)take(4 * (cell_cap + 1));
+    ws.m2l_src = (int32_t *)take(4 * ws.m2l_dir_cap);
+    ws.p2p_off = (int32_t *)take(4 * (n + 1));
+    ws.p2p_src = (int32_t *)take(4 * ws.p2p_dir_cap);
+    int64_t cnt = (cell_cap > n ? cell_cap : n) + 1;
+    if (cnt < nb * (kMaxDepth + 1) + 1) cnt = nb * (kMaxDepth + 1) + 1;
+    ws.cnt_a = (int32_t *)take(4 * cnt);
+    ws.cnt_b = (int32_t *)take(4 * cnt);
+    ws.cnt_tmp = (int32_t *)take(4 * (ws.m2l_dir_cap > ws.p2p_dir_cap ? ws.m2l_dir_cap : ws.p2p_dir_cap));
+    ws.scan_part = (int32_t *)take(4 * (nb + 4096));
+    ws.hist = (uint32_t *)take(4 * 256 * (ntiles + 1));
+    ws.pairs_tmp = (int64_t *)take(8 * ws.pair_cap);
+    ws.pairs_alt = (int64_t *)take(8 * ws.pair_cap);
+    ws.bytes = off;
+    return off;
+}
+
+}  // namespace ncorp
+
+extern "C" int64_t ncorp_workspace_bytes(const ncorp_params *params, int64_t n_max,
+                                         int64_t pair_capacity) {
+    char why[128];
+    if (!params_ok(params, why, sizeof(why)) || n_max < 1 || n_max > INT32_MAX - 1 ||
+        pair_capacity < 0)
+        return -1;
+    Workspace w;
+    return layout_workspace(w, *params, n_max, pair_capacity);
+}
+
+// Fit the layout for n moonlets into the caller's buffer: whatever is left after
+// the fixed part becomes the colliding-pair buffer.
+static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_bytes) {
+    if (!workspace) return fail(c, NCORP_E_INVALID, "workspace is NULL");
+    if (((uintptr_t)workspace & 255u) != 0)
+        return fail(c, NCORP_E_INVALID, "workspace must be 256-byte aligned");
+    Workspace probe;
+    const int64_t fixed = layout_workspace(probe, c->prm, n, 1024);
+    if (ws_bytes < fixed) {
+        std::snprintf(c->err, sizeof(c->err), "workspace too small: %lld bytes needed for n=%lld",
+                      (long long)fixed, (long long)n);
+        return NCORP_E_INVALID;
+    }
+    // whatever is left beyond the fixed part holds colliding pairs (2 x 8 bytes each)
+    int64_t pc = 1024 + (ws_bytes - fixed) / 16;
+    while (layout_workspace(probe, c->prm, n, pc) > ws_bytes) pc -= 64;
+    Workspace ws;
+    ws.base = (char *)workspace;
+    layout_workspace(ws, c->prm, n, pc);
+    // the walk queue keeps tags from earlier walks; a new buffer or layout holds
+    // unknown bytes, so force the next walk to clear it
+    ws.epoch = (c->ws.base == ws.base && c->ws.queue == ws.queue && c->ws.queue_cap == ws.queue_cap)
+                   ? c->ws.epoch : 0xffffu;
+    c->ws = ws;
+    return NCORP_OK;
+}
+
+static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const double *z,
+                           int64_t n, hipStream_t s, bool fresh) {
+    Workspace &ws = c->ws;
+    if (fresh) HIPCHK(c, launch_reset_state(ws, s));
+    else HIPCHK(c, launch_reset_tree_counters(ws, s));
+    HIPCHK(c, launch_keys(ws, x, y, z, n, c->prm.root_half_width, s));
+    HIPCHK(c, launch_sort(ws, n, s));
+    HIPCHK(c, launch_gather_pos(ws, x, y, z, n, s));
+    HIPCHK(c, launch_build_tree(ws, n, c->prm.leaf_size, s));
+    c->have_tree = true;
+    c->n = n;
+    c->last = s;
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_build_tree(ncorp_ctx *c, const double *x, const double *y, const double *z,
+                                int64_t n, void *workspace, int64_t ws_bytes, void *stream) {
+    if (!c) return NCORP_E_INVALID;
+    if (!x || !y || !z) return fail(c, NCORP_E_INVALID, "position pointer is NULL");
+    if (n < 1 || n > INT32_MAX - 1) return fail(c, NCORP_E_INVALID, "n must be in 1..2^31-2");
+    int r = setup_workspace(c, n, workspace, ws_bytes);
+    if (r != NCORP_OK) return r;
+    return build_tree_impl(c, x, y, z, n, (hipStream_t)stream, true);
+}
+
+static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, double *az,
+                        hipStream_t s) {
+    Workspace &ws = c->ws;
+    const int64_t n = c->n;
+    if (c->prm.p == 0) {
+        HIPCHK(c, launch_fill_i64((int64_t *)ax, 0, n, s));
+        HIPCHK(c, launch_fill_i64((int64_t *)ay, 0, n, s));
+        HIPCHK(c, launch_fill_i64((int64_t *)az, 0, n, s));
+        return NCORP_OK;
+    }
+    HIPCHK(c, launch_gather_scaled(ws, m, c->prm.G, ws.mus, n, s));
+    HIPCHK(c, launch_gravity_climb(ws, n, c->prm, s));
+    HIPCHK(c, launch_walk(ws, 0, c->prm.ncs, c->prm.ncc_pre, c->prm.ncc_post, s));
+    HIPCHK(c, launch_build_lists(ws, 0, s));
+    HIPCHK(c, launch_m2l(ws, c->prm.p, c->prm.precision, s));
+    HIPCHK(c, launch_l2l(ws, c->prm.p, s));
+    HIPCHK(c, launch_p2p(ws, n, c->prm.precision, s));
+    HIPCHK(c, launch_l2p(ws, n, c->prm.p, ax, ay, az, s));
+    c->last = s;
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_gravity(ncorp_ctx *c, const double *m, double *ax, double *ay, double *az,
+                             void *stream) {
+    if (!c) return NCORP_E_INVALID;
+    if (!c->have_tree) return fail(c, NCORP_E_INVALID, "no tree: call ncorp_build_tree first");
+    if (!m || !ax || !ay || !az) return fail(c, NCORP_E_INVALID, "array pointer is NULL");
+    return gravity_impl(c, m, ax, ay, az, (hipStream_t)stream);
+}
+
+static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const double *vz,
+                        const double *R, double dt, int64_t *pairs, int64_t cap,
+                        int64_t *n_pairs_dev, int triple, int step, hipStream_t s) {
+    Workspace &ws = c->ws;
+    const int64_t n = c->n;
+    HIPCHK(c, launch_gather(ws, vx, ws.vxs, n, s));
+    HIPCHK(c, launch_gather(ws, vy, ws.vys, n, s));
+    HIPCHK(c, launch_gather(ws, vz, ws.vzs, n, s));
+    HIPCHK(c, launch_gather(ws, R, ws.rads, n, s));
+    HIPCHK(c, launch_collision_climb(ws, n, dt, s));
+    HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col, c->prm.ncc_post_col, s));
+    HIPCHK(c, launch_collide_pairs(ws, n, dt, s));
+    HIPCHK(c, launch_emit_pairs(ws, pairs, cap, n_pairs_dev, triple, step,
+                                &ws.st->pair_cursor, s));
+    c->last = s;
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_collide(ncorp_ctx *c, const double *vx, const double *vy, const double *vz,
+                             const double *R, double dt, int64_t *pairs, int64_t cap,
+                             int64_t *n_pairs_dev, void *stream) {
+    if (!c) return NCORP_E_INVALID;
+    if (!c->have_tree) return fail(c, NCORP_E_INVALID, "no tree: call ncorp_build_tree first");
+    if (!vx || !vy || !vz || !R || !n_pairs_dev || (cap > 0 && !pairs))
+        return fail(c, NCORP_E_INVALID, "array pointer is NULL");
+    if (cap < 0) return fail(c, NCORP_E_INVALID, "cap must be >= 0");
+    if (!(dt >= 0.0)) return fail(c, NCORP_E_INVALID, "dt must be >= 0");
+    return collide_impl(c, vx, vy, vz, R, dt, pairs, cap, n_pairs_dev, 0, 0, (hipStream_t)stream);
+}
+
+namespace ncorp {
+__global__ void k_zero_cursor(DevState *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->pair_cursor = 0;
+}
+}
+
+extern "C" int ncorp_step(ncorp_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
+                          double *vz, const double *m, const double *R, int64_t n, double dt,
+                          int n_steps, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev,
+                          void *workspace, int64_t ws_bytes, void *stream) {
+    if (!c) return NCORP_E_INVALID;
+    if (!x || !y || !z || !vx || !vy || !vz || !m || !R || !n_pairs_dev || (cap > 0 && !pairs))
+        return fail(c, NCORP_E_INVALID, "array pointer is NULL");
+    if (n < 1 || n > INT32_MAX - 1) return fail(c, NCORP_E_INVALID, "n must be in 1..2^31-2");
+    if (n_steps < 1) return fail(c, NCORP_E_INVALID, "n_steps must be >= 1");
+    if (!(dt > 0.0)) return fail(c, NCORP_E_INVALID, "dt must be > 0");
+    if (cap < 0) return fail(c, NCORP_E_INVALID, "cap must be >= 0");
+    int r = setup_workspace(c, n, workspace, ws_bytes);
+    if (r != NCORP_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &ws = c->ws;
+    double *ax = ws.acc, *ay = ws.acc + n, *az = ws.acc + 2 * n;
+    const bool mutual = c->prm.p > 0;
+    r = build_tree_impl(c, x, y, z, n, s, true);
+    if (r != NCORP_OK) return r;
+    k_zero_cursor<<<1, 64, 0, s>>>(ws.st);
+    if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
+    HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, 0.5 * dt,
+                          c->prm.G, c->prm.M_central, s));
+    for (int k = 0; k < n_steps; k++) {
+        r = collide_impl(c, vx, vy, vz, R, dt, pairs, cap, n_pairs_dev + k, 1, k, s);
+        if (r != NCORP_OK) return r;
+        HIPCHK(c, launch_drift(x, y, z, vx, vy, vz, n, dt, s));
+        if ((r = build_tree_impl(c, x, y, z, n, s, false)) != NCORP_OK) return r;
+        if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
+        const double h = (k == n_steps - 1) ? 0.5 * dt : dt;
+        HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, h, c->prm.G,
+                              c->prm.M_central, s));
+    }
+    c->last = s;
+    return NCORP_OK;
+}
+
+static int sync_state(ncorp_ctx *c, DevState &h) {
+    if (!c->ws.base) return fail(c, NCORP_E_INVALID, "no workspace bound yet");
+    HIPCHK(c, hipStreamSynchronize(c->last));
+    HIPCHK(c, hipMemcpy(&h, c->ws.st, sizeof(DevState), hipMemcpyDeviceToHost));
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_get_status(ncorp_ctx *c, int64_t *required) {
+    if (!c) return NCORP_E_INVALID;
+    DevState h;
+    int r = sync_state(c, h);
+    if (r != NCORP_OK) return r;
+    if (required) *required = h.required;
+    if (h.status & (ST_CAP_CELLS | ST_CAP_QUEUE | ST_CAP_M2L | ST_CAP_P2P | ST_CAP_PAIRS | ST_CAP_LISTS)) {
+        std::snprintf(c->err, sizeof(c->err), "device list overflow (flags 0x%x, required %lld)",
+                      h.status, (long long)h.required);
+        return NCORP_E_CAPACITY;
+    }
+    if (h.status & (ST_WALK_STALL | ST_BAD_ITEM)) {
+        std::snprintf(c->err, sizeof(c->err), "a tree pass stopped waiting (flags 0x%x)", h.status);
+        return NCORP_E_HIP;
+    }
+    if (h.status & ST_NONFINITE) return fail(c, NCORP_E_NONFINITE, "non-finite position");
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_tree_info(ncorp_ctx *c, int64_t *info) {
+    if (!c || !info) return NCORP_E_INVALID;
+    DevState h;
+    int r = sync_state(c, h);
+    if (r != NCORP_OK) return r;
+    info[NCORP_INFO_N] = c->n;
+    info[NCORP_INFO_NCELLS] = h.ncells;
+    info[NCORP_INFO_NLEAVES] = h.nleaves;
+    info[NCORP_INFO_MAXLEVEL] = h.maxlevel;
+    info[NCORP_INFO_M2L] = h.nm2l;
+    info[NCORP_INFO_P2P] = h.np2p;
+    info[NCORP_INFO_VISITED] = h.visited;
+    info[NCORP_INFO_COL_CAND] = h.ncand;
+    info[NCORP_INFO_COL_TESTS] = h.col_tests;
+    return NCORP_OK;
+}
+
+template <typename T>
+static int d2h(ncorp_ctx *c, std::vector<T> &v, const T *src, int64_t count) {
+    v.resize(count > 0 ? count : 0);
+    if (count > 0) HIPCHK(c, hipMemcpy(v.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost));
+    return NCORP_OK;
+}
+
+extern "C" int64_t ncorp_export_host(ncorp_ctx *c, int what, void *dst, int64_t bytes) {
+    if (!c || bytes < 0 || (bytes > 0 && !dst)) return NCORP_E_INVALID;
+    DevState h;
+    int r = sync_state(c, h);
+    if (r != NCORP_OK) return r;
+    const Workspace &ws = c->ws;
+    const int64_t n = c->n, nc = h.ncells;
+    std::vector<char> out;
+    auto put = [&](const void *p, int64_t b) {
+        out.resize(b);
+        if (b) std::memcpy(out.data(), p, b);
+    };
+    switch (what) {
+        case NCORP_EXPORT_KEYS: {
+            std::vector<uint64_t> v; if ((r = d2h(c, v, ws.keys, n))) return r;
+            put(v.data(), 8 * n); break;
+        }
+        case NCORP_EXPORT_PERM: {
+            std::vector<uint32_t> v; if ((r = d2h(c, v, ws.idx, n))) return r;
+            put(v.data(), 4 * n); break;
+        }
+        case NCORP_EXPORT_CELLS: {
+            std::vector<int32_t> lv, f, cn, ch, nch, par;
+            std::vector<uint64_t> pre;
+            if ((r = d2h(c, lv, ws.c_level, nc)) || (r = d2h(c, f, ws.c_first, nc)) ||
+                (r = d2h(c, cn, ws.c_count, nc)) || (r = d2h(c, ch, ws.c_child, nc)) ||
+                (r = d2h(c, nch, ws.c_nchild, nc)) || (r = d2h(c, par, ws.c_parent, nc)) ||
+                (r = d2h(c, pre, ws.c_prefix, nc)))
+                return r;
+            std::vector<int32_t> v(8 * nc);
+            for (int64_t i = 0; i < nc; i++) {
+                v[8 * i + 0] = lv[i]; v[8 * i + 1] = f[i]; v[8 * i + 2] = cn[i];
+                v[8 * i + 3] = ch[i]; v[8 * i + 4] = nch[i]; v[8 * i + 5] = par[i];
+                v[8 * i + 6] = (int32_t)(pre[i] & 0xffffffffull);
+                v[8 * i + 7] = (int32_t)(pre[i] >> 32);
+            }
+            put(v.data(), 4 * 8 * nc); break;
+        }
+        case NCORP_EXPORT_GCELLS: {
+            std::vector<double4> g; std::vector<double> ms, rm, th;
+            if ((r = d2h(c, g, ws.gcell, nc)) || (r = d2h(c, ms, ws.c_mass, nc)) ||
+                (r = d2h(c, rm, ws.c_rmax, nc)) || (r = d2h(c, th, ws.c_theta, nc)))
+                return r;
+            std::vector<double> v(8 * nc);
+            for (int64_t i = 0; i < nc; i++) {
+                v[8 * i + 0] = g[i].x; v[8 * i + 1] = g[i].y; v[8 * i + 2] = g[i].z;
+                v[8 * i + 3] = ms[i]; v[8 * i + 4] = rm[i]; v[8 * i + 5] = g[i].w;
+                v[8 * i + 6] = th[i]; v[8 * i + 7] = 0.0;
+            }
+            put(v.data(), 8 * 8 * nc); break;
+        }
+        case NCORP_EXPORT_CCELLS: {
+            std::vector<double4> g; std::vector<double> rm;
+            if ((r = d2h(c, g, ws.ccell, nc)) || (r = d2h(c, rm, ws.c_crmax, nc))) return r;
+            std::vector<double> v(5 * nc);
+            for (int64_t i = 0; i < nc; i++) {
+                v[4 * i + 0] = g[i].x; v[4 * i + 1] = g[i].y; v[4 * i + 2] = g[i].z;
+                v[4 * i + 3] = g[i].w;
+                v[4 * nc + i] = rm[i];
+            }
+            put(v.data(), 8 * 5 * nc); break;
+        }
+        case NCORP_EXPORT_MULTIPOLES: {
+            std::vector<double> v; if ((r = d2h(c, v, ws.mult, nc * ws.nm))) return r;
+            put(v.data(), 8 * nc * ws.nm); break;
+        }
+        case NCORP_EXPORT_LOCAL: {
+            std::vector<double> v; if ((r = d2h(c, v, ws.local, nc * ws.nl))) return r;
+            put(v.data(), 8 * nc * ws.nl); break;
+        }
+        case NCORP_EXPORT_M2L: {
+            int64_t k = h.nm2l < ws.m2l_cap ? h.nm2l : ws.m2l_cap;
+            std::vector<int2> v; if ((r = d2h(c, v, ws.m2l, k))) return r;
+            put(v.data(), 8 * k); break;
+        }
+        case NCORP_EXPORT_P2P: {
+            int64_t k = h.np2p < ws.p2p_cap ? h.np2p : ws.p2p_cap;
+            std::vector<int2> v; if ((r = d2h(c, v, ws.p2p, k))) return r;
+            put(v.data(), 8 * k); break;
+        }
+        case NCORP_EXPORT_COL_CAND: {
+            int64_t k = h.ncand < ws.p2p_cap ? h.ncand : ws.p2p_cap;
+            std::vector<int2> v; if ((r = d2h(c, v, ws.cand, k))) return r;
+            put(v.data(), 8 * k); break;
+        }
+        default:
+            return fail(c, NCORP_E_INVALID, "unknown export");
+    }
+    int64_t full = (int64_t)out.size();
+    int64_t cp = full < bytes ? full : bytes;
+    if (cp > 0) std::memcpy(dst, out.data(), cp);
+    return full;
+}

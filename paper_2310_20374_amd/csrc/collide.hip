@@ -1,0 +1,155 @@
+// Collision search on the candidate cell pairs of the collision walk (Alg. 2 with
+// "do nothing" for well-separated cells) and the pair test of Sect. 3.1:
+//   Delta = (dr.dv)^2 + dv^2 [(R1 + R2)^2 - dr^2]                      (Eq. 1)
+//   dt_c  = -(dr.dv + sqrt(Delta)) / dv^2, collision iff 0 <= dt_c <= dt (Eq. 2)
+// The arithmetic is FP64 with a fixed operation order and no contraction, and it is
+// symmetric under swapping the two moonlets bit for bit (dr and dv only change
+// sign), so the pair set is reproducible exactly.
+#include "ncorp_internal.h"
+
+namespace ncorp {
+
+__device__ __forceinline__ bool pair_test(double x1, double y1, double z1, double vx1,
+                                          double vy1, double vz1, double R1, double x2,
+                                          double y2, double z2, double vx2, double vy2,
+                                          double vz2, double R2, double dt) {
+    double dx = x1 - x2, dy = y1 - y2, dz = z1 - z2;
+    double dvx = vx1 - vx2, dvy = vy1 - vy2, dvz = vz1 - vz2;
+    double rv = dx * dvx + dy * dvy + dz * dvz;
+    double v2 = dvx * dvx + dvy * dvy + dvz * dvz;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double Rs = R1 + R2;
+    double disc = rv * rv + v2 * (Rs * Rs - r2);
+    if (!(v2 > 0.0) || !(disc >= 0.0)) return false;
+    double tc = -(rv + sqrt(disc)) / v2;
+    return tc >= 0.0 && tc <= dt;
+}
+
+__device__ __forceinline__ void record(int64_t *out, int64_t cap, unsigned long long *count,
+                                       uint32_t ia, uint32_t ib) {
+    uint32_t lo = ia < ib ? ia : ib, hi = ia < ib ? ib : ia;
+    unsigned long long k = atomicAdd(count, 1ull);
+    if ((int64_t)k < cap) out[k] = ((int64_t)lo << 32) | (int64_t)hi;
+}
+
+// one wave per candidate cell pair
+__global__ void __launch_bounds__(64)
+k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
+          const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
+          const double *__restrict__ xs, const double *__restrict__ ys,
+          const double *__restrict__ zs, const double *__restrict__ vxs,
+          const double *__restrict__ vys, const double *__restrict__ vzs,
+          const double *__restrict__ rads, const uint32_t *__restrict__ perm, double dt,
+          int64_t *out, int64_t cap) {
+    if (st->status & kSkipMask) return;
+    int nc = st->ncand;
+    if (nc > cand_cap) nc = (int)cand_cap;
+    const int lane = threadIdx.x;
+    unsigned long long tests = 0;
+    for (int q = blockIdx.x; q < nc; q += gridDim.x) {
+        const int2 pr = cand[q];
+        const int fa = c_first[pr.x], na = c_count[pr.x];
+        const int fb = c_first[pr.y], nb = c_count[pr.y];
+        const bool self = pr.x == pr.y;
+        for (int a0 = 0; a0 < na; a0 += 64) {
+            const int ia = a0 + lane;
+            if (ia >= na) continue;
+            const int a = fa + ia;
+            const double x1 = xs[a], y1 = ys[a], z1 = zs[a], vx1 = vxs[a], vy1 = vys[a],
+                         vz1 = vzs[a], R1 = rads[a];
+            const int jb0 = self ? ia + 1 : 0;
+            for (int jb = jb0; jb < nb; jb++) {
+                const int b = fb + jb;
+                tests++;
+                if (pair_test(x1, y1, z1, vx1, vy1, vz1, R1, xs[b], ys[b], zs[b], vxs[b], vys[b],
+                              vzs[b], rads[b], dt))
+                    record(out, cap, (unsigned long long *)&st->npairs, perm[a], perm[b]);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) tests += __shfl_xor(tests, o);
+    if (lane == 0 && tests) atomicAdd((unsigned long long *)&st->col_tests, tests);
+}
+
+__global__ void k_collide_init(DevState *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) { st->npairs = 0; st->col_tests = 0; }
+}
+
+// rank sort of the (distinct) pair keys: rank = number of smaller keys
+__global__ void __launch_bounds__(256)
+k_rank_pairs(const DevState *__restrict__ st, const int64_t *__restrict__ in, int64_t cap,
+             int64_t *__restrict__ out) {
+    __shared__ int64_t tile[1024];
+    int64_t n = st->npairs;
+    if (n > cap) n = cap;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < n ? in[i] : 0;
+        int64_t r = 0;
+        for (int64_t t0 = 0; t0 < n; t0 += 1024) {
+            __syncthreads();
+            for (int k = threadIdx.x; k < 1024; k += 256)
+                tile[k] = t0 + k < n ? in[t0 + k] : INT64_MAX;
+            __syncthreads();
+            const int lim = n - t0 < 1024 ? (int)(n - t0) : 1024;
+            for (int k = 0; k < lim; k++) r += tile[k] < v;
+        }
+        if (i < n) out[r] = v;
+    }
+}
+
+__global__ void k_emit_pairs(const DevState *__restrict__ st, const int64_t *__restrict__ sorted,
+                             int64_t tmp_cap, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev,
+                             int triple, int step, int64_t *cursor) {
+    int64_t n = st->npairs;
+    int64_t m = n < tmp_cap ? n : tmp_cap;
+    int64_t base = triple ? *cursor : 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = sorted[k];
+        const int64_t o = base + k;
+        if (o >= cap) continue;
+        if (triple) {
+            pairs[3 * o] = step;
+            pairs[3 * o + 1] = v >> 32;
+            pairs[3 * o + 2] = v & 0xffffffffll;
+        } else {
+            pairs[2 * o] = v >> 32;
+            pairs[2 * o + 1] = v & 0xffffffffll;
+        }
+    }
+}
+
+__global__ void k_pairs_done(DevState *st, int64_t *n_pairs_dev, int64_t cap, int64_t tmp_cap,
+                             int triple, int64_t *cursor) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t n = st->npairs;
+    *n_pairs_dev = n;
+    int64_t base = triple ? *cursor : 0;
+    if (n > tmp_cap || base + n > cap) {
+        atomicOr(&st->status, (int32_t)ST_CAP_PAIRS);
+        atomicMax((unsigned long long *)&st->required, (unsigned long long)(base + n));
+    }
+    if (triple) *cursor = base + n;
+}
+
+hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipStream_t s) {
+    (void)n;
+    k_collide_init<<<1, 64, 0, s>>>(ws.st);
+    k_collide<<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count, ws.xs,
+                                   ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, ws.idx, dt,
+                                   ws.pairs_tmp, ws.pair_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,
+                             int64_t *n_pairs_dev, int triple, int step, int64_t *cursor,
+                             hipStream_t s) {
+    k_rank_pairs<<<256, 256, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap, ws.pairs_alt);
+    k_emit_pairs<<<256, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, pairs, cap, n_pairs_dev,
+                                     triple, step, cursor);
+    k_pairs_done<<<1, 64, 0, s>>>(ws.st, n_pairs_dev, cap, ws.pair_cap, triple, cursor);
+    return hipGetLastError();
+}
+
+}  // namespace ncorp

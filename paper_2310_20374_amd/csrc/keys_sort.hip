@@ -1,0 +1,375 @@
+// Root cube, 63-bit Hilbert keys and the stable radix sort that puts the moonlets
+// in Hilbert order (Sect. 3.4.6).  All three are bandwidth-bound streaming passes.
+#include "ncorp_internal.h"
+
+namespace ncorp {
+
+// ------------------------------------------------------------------ helpers
+__global__ void k_reset_state(DevState *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        DevState z{};
+        *st = z;
+    }
+}
+
+hipError_t launch_reset_state(const Workspace &ws, hipStream_t s) {
+    k_reset_state<<<1, 64, 0, s>>>(ws.st);
+    return hipGetLastError();
+}
+
+// before every (re)build: only what the build accumulates into
+__global__ void k_reset_tree_counters(DevState *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->max_abs = 0.0;
+}
+
+hipError_t launch_reset_tree_counters(const Workspace &ws, hipStream_t s) {
+    k_reset_tree_counters<<<1, 64, 0, s>>>(ws.st);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_i64(int64_t *p, int64_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static int grid_for(int64_t n, int block, int cap = 4096) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_i64<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ root cube
+// max |coordinate| over finite values; non-finite coordinates latch a status bit.
+// Non-negative doubles order like their bit patterns, so an unsigned 64-bit
+// atomic max gives the maximum.
+__global__ void k_max_abs(const double *__restrict__ x, const double *__restrict__ y,
+                          const double *__restrict__ z, int64_t n, DevState *st) {
+    __shared__ unsigned long long red[256 / kWave];
+    unsigned long long m = 0ull;
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v[3] = {x[i], y[i], z[i]};
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            double a = fabs(v[k]);
+            if (!(a <= 1.79769313486231570e308)) { bad = true; continue; }
+            unsigned long long b = (unsigned long long)__double_as_longlong(a);
+            m = b > m ? b : m;
+        }
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        unsigned long long t = __shfl_xor(m, o);
+        m = t > m ? t : m;
+    }
+    int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) red[w] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x / kWave); k++) m = red[k] > m ? red[k] : m;
+        atomicMax((unsigned long long *)&st->max_abs, m);
+    }
+    if (__any(bad) && l == 0) atomicOr(&st->status, (int32_t)ST_NONFINITE);
+}
+
+// ------------------------------------------------------------------ keys
+// q = floor((x + L) * 2^20 / L), clamped to [0, 2^21 - 1]; with L a power of two the
+// scale is exact, so the result depends only on the correctly rounded x + L.
+__device__ __forceinline__ uint32_t quantize(double x, double L, double scale) {
+    double t = (x + L) * scale;
+    if (!(t >= 0.0)) return 0u;
+    if (t >= 2097152.0) return 2097151u;
+    uint32_t q = (uint32_t)floor(t);
+    return q > 2097151u ? 2097151u : q;
+}
+
+// 3-D Hilbert index of (q0, q1, q2), 21 bits each, in Skilling's transpose form
+// (AIP Conf. Proc. 707, 2004): per level, invert or exchange the lower bits, then
+// Gray-code the axes; the index interleaves the transposed bits x, y, z from the
+// most significant level down.
+__device__ __forceinline__ uint64_t hilbert21(uint32_t q0, uint32_t q1, uint32_t q2) {
+    uint32_t X[3] = {q0, q1, q2};
+#pragma unroll
+    for (int lv = 20; lv >= 1; lv--) {
+        uint32_t Q = 1u << lv, P = Q - 1u;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+#pragma unroll
+    for (int lv = 20; lv >= 1; lv--)
+        if (X[2] & (1u << lv)) t ^= (1u << lv) - 1u;
+    X[0] ^= t; X[1] ^= t; X[2] ^= t;
+    // interleave: bit b of axis i lands at position 3b + (2 - i)
+    uint64_t h = 0;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        uint64_t v = X[i];
+        // spread 21 bits to every third position
+        v = (v | (v << 32)) & 0x1f00000000ffffull;
+        v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+        v = (v | (v << 8)) & 0x100f00f00f00f00full;
+        v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+        v = (v | (v << 2)) & 0x1249249249249249ull;
+        h |= v << (2 - i);
+    }
+    return h;
+}
+
+__global__ void k_keys(const double *__restrict__ x, const double *__restrict__ y,
+                       const double *__restrict__ z, int64_t n, double fixed_L,
+                       DevState *st, uint64_t *__restrict__ keys, uint32_t *__restrict__ idx) {
+    double L = fixed_L;
+    if (!(L > 0.0)) {
+        double mx = st->max_abs;     // holds the bit pattern written by the atomic max
+        if (mx > 0.0) {
+            int e;
+            frexp(mx, &e);           // mx = f 2^e, 0.5 <= f < 1
+            L = ldexp(1.0, e);       // smallest power of two strictly above mx
+        } else {
+            L = 1.0;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->L = L;
+    double scale = 1048576.0 / L;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        keys[i] = hilbert21(quantize(x[i], L, scale), quantize(y[i], L, scale),
+                            quantize(z[i], L, scale));
+        idx[i] = (uint32_t)i;
+    }
+}
+
+hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
+                       const double *z, int64_t n, double root_half_width, hipStream_t s) {
+    // also run with a fixed root: it latches non-finite coordinates
+    k_max_abs<<<grid_for(n, 256, 1024), 256, 0, s>>>(x, y, z, n, ws.st);
+    k_keys<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, n, root_half_width, ws.st, ws.keys,
+                                            ws.idx);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ radix sort
+// LSD radix sort of (key, index) by 8-bit digits, 8 passes over 63 bits.  Each
+// pass: per-tile digit histograms, a per-digit scan over tiles, then a stable
+// scatter in which every wave ranks its 64-item rounds with ballots and keeps
+// wave-private running counters, so the tile needs only two barriers.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                       // per thread
+constexpr int kSortTile = kSortThreads * kSortItems; // 4096
+constexpr int kSortWaves = kSortThreads / kWave;
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t *hist,
+             int ntiles) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int k = 0; k < kSortItems; k++) {
+        int64_t i = base + k * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of that digit's tile counts; digit total out.
+__global__ void __launch_bounds__(256)
+k_radix_scan(uint32_t *hist, int ntiles, uint32_t *totals) {
+    __shared__ uint32_t sh[256];
+    uint32_t *row = hist + (int64_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < ntiles; b0 += 256) {
+        int i = b0 + threadIdx.x;
+        uint32_t v = i < ntiles ? row[i] : 0u;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            uint32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        uint32_t incl = sh[threadIdx.x];
+        if (i < ntiles) row[i] = carry + incl - v;
+        carry += sh[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    uint32_t l = threadIdx.x % kWave;
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
+                int shift, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals,
+                int ntiles) {
+    __shared__ uint32_t dbase[256];              // digit base offsets, global
+    __shared__ uint32_t wcnt[kSortWaves][256];   // per-wave digit counters
+    __shared__ uint32_t scan_tmp[256];
+    const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+    // exclusive scan of digit totals -> global start of each digit
+    uint32_t tot = totals[t];
+    scan_tmp[t] = tot;
+    for (int k = 0; k < kSortWaves; k++) wcnt[k][t] = 0;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        uint32_t v = t >= o ? scan_tmp[t - o] : 0u;
+        __syncthreads();
+        scan_tmp[t] += v;
+        __syncthreads();
+    }
+    dbase[t] = scan_tmp[t] - tot + hist[(int64_t)t * ntiles + blockIdx.x];
+    // phase 1: this wave's items (a contiguous quarter of the tile), kept in registers
+    const int64_t wbase = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortTile / kSortWaves);
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        int64_t i = wbase + r * kWave + lane;
+        if (i < n) {
+            key[r] = kin[i];
+            val[r] = vin[i];
+            atomicAdd(&wcnt[w][(key[r] >> shift) & 255u], 1u);
+        } else {
+            key[r] = 0;
+            val[r] = 0;
+        }
+    }
+    __syncthreads();
+    // phase 2: per digit, exclusive prefix over the waves
+    {
+        uint32_t run = 0;
+        for (int k = 0; k < kSortWaves; k++) {
+            uint32_t c = wcnt[k][t];
+            wcnt[k][t] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    // phase 3: stable ranks inside each 64-item round, wave-private running counts
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        int64_t i = wbase + r * kWave + lane;
+        bool valid = i < n;
+        uint64_t act = __ballot(valid);
+        if (act == 0ull) break;
+        uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+        uint64_t peers = act;
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        if (valid) {
+            uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+            uint32_t before = wcnt[w][d];
+            uint32_t pos = dbase[d] + before + rank;
+            kout[pos] = key[r];
+            vout[pos] = val[r];
+            bool leader = (peers & lanemask_lt()) == 0ull;
+            __builtin_amdgcn_wave_barrier();
+            if (leader) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s) {
+    int ntiles = (int)((n + kSortTile - 1) / kSortTile);
+    uint64_t *ka = ws.keys, *kb = ws.keys_alt;
+    uint32_t *va = ws.idx, *vb = ws.idx_alt;
+    uint32_t *totals = ws.hist + (int64_t)256 * ntiles;
+    for (int pass = 0; pass < 8; pass++) {
+        int shift = 8 * pass;
+        k_radix_hist<<<ntiles, kSortThreads, 0, s>>>(ka, n, shift, ws.hist, ntiles);
+        k_radix_scan<<<256, 256, 0, s>>>(ws.hist, ntiles, totals);
+        k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(ka, va, kb, vb, n, shift, ws.hist,
+                                                        totals, ntiles);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    // 8 passes: the result is back in ws.keys / ws.idx
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ gathers
+__global__ void k_gather3(const double *__restrict__ x, const double *__restrict__ y,
+                          const double *__restrict__ z, const uint32_t *__restrict__ idx,
+                          int64_t n, double *__restrict__ xs, double *__restrict__ ys,
+                          double *__restrict__ zs) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t j = idx[i];
+        xs[i] = x[j];
+        ys[i] = y[j];
+        zs[i] = z[j];
+    }
+}
+
+__global__ void k_gather1(const double *__restrict__ src, const uint32_t *__restrict__ idx,
+                          int64_t n, double *__restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[idx[i]];
+}
+
+hipError_t launch_gather_pos(const Workspace &ws, const double *x, const double *y,
+                             const double *z, int64_t n, hipStream_t s) {
+    k_gather3<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, ws.idx, n, ws.xs, ws.ys, ws.zs);
+    return hipGetLastError();
+}
+
+__global__ void k_gather_scaled(const double *__restrict__ src, const uint32_t *__restrict__ idx,
+                                int64_t n, double scale, double *__restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = scale * src[idx[i]];
+}
+
+hipError_t launch_gather_scaled(const Workspace &ws, const double *src, double scale,
+                                double *dst, int64_t n, hipStream_t s) {
+    k_gather_scaled<<<grid_for(n, 256), 256, 0, s>>>(src, ws.idx, n, scale, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const Workspace &ws, const double *src, double *dst, int64_t n,
+                         hipStream_t s) {
+    k_gather1<<<grid_for(n, 256), 256, 0, s>>>(src, ws.idx, n, dst);
+    return hipGetLastError();
+}
+
+}  // namespace ncorp

@@ -1,0 +1,192 @@
+// Interaction tensors (Eq. 25) for every well-separated pair found by the walk.
+//
+// Target-major: one wave per target cell A, lanes over A's sources B (grouped and
+// sorted by the list builder), each lane accumulating
+//   C^(m)_a(s_A) += sum_{n=0, n!=1}^{p-m} (-1)^n sum_{|b|=n} D_{a+b}(R) Mt_b(B),
+// with R = s_A - s_B, D_g = d^g (1/|R|) and Mt_b = M_b / b! (the n! of Eq. 25 and
+// the multinomial weights of the symmetric inner product cancel into 1/b!).  The
+// wave then sums its 64 partial tensors order by order through LDS.  Both
+// directions of a pair are separate entries of the list, so every target's sum has
+// a fixed order and the result does not depend on scheduling.
+//
+// D comes from the recurrence of McMurchie & Davidson (J. Comput. Phys. 26, 1978)
+// written for 1/r: with R^n_000 = (-1)^n (2n-1)!! r^-(2n+1),
+//   R^n_{a+1,b,c} = a R^{n+1}_{a-1,b,c} + x R^{n+1}_{a,b,c}  (same for y, z),
+// and D_{abc} = R^0_{abc}.
+#include "ncorp_internal.h"
+
+namespace ncorp {
+
+constexpr int kM2LBlock = 64;     // one wave per block, one target per wave
+
+template <int P, typename T>
+__device__ __forceinline__ void green_derivs(T x, T y, T z, T rinv, T *D) {
+    const T rinv2 = rinv * rinv;
+    T g[P + 1];
+    g[0] = rinv;
+#pragma unroll
+    for (int n = 1; n <= P; n++) g[n] = -(T)(2 * n - 1) * rinv2 * g[n - 1];
+    // level n overwrites level n+1 in place: orders are visited from high to low,
+    // so every value still needed (orders k-1, k-2 of level n+1) is intact
+    D[0] = g[P];
+#pragma unroll
+    for (int n = P - 1; n >= 0; n--) {
+#pragma unroll
+        for (int k = P - n; k >= 1; k--)
+#pragma unroll
+            for (int b = 0; b <= k; b++)
+#pragma unroll
+                for (int c = 0; c <= k - b; c++) {
+                    const int a = k - b - c;
+                    T v;
+                    if (a > 0) {
+                        v = x * D[sidx(a - 1, b, c)];
+                        if (a > 1) v += (T)(a - 1) * D[sidx(a - 2, b, c)];
+                    } else if (b > 0) {
+                        v = y * D[sidx(a, b - 1, c)];
+                        if (b > 1) v += (T)(b - 1) * D[sidx(a, b - 2, c)];
+                    } else {
+                        v = z * D[sidx(a, b, c - 1)];
+                        if (c > 1) v += (T)(c - 1) * D[sidx(a, b, c - 2)];
+                    }
+                    D[sidx(a, b, c)] = v;
+                }
+        D[0] = g[n];
+    }
+}
+
+template <typename T> __device__ __forceinline__ T rsqrt_t(T v);
+template <> __device__ __forceinline__ double rsqrt_t<double>(double v) { return 1.0 / sqrt(v); }
+template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return rsqrtf(v); }
+
+template <typename T> __device__ __forceinline__ T fma_t(T a, T b, T c);
+template <> __device__ __forceinline__ double fma_t<double>(double a, double b, double c) {
+    return fma(a, b, c);
+}
+template <> __device__ __forceinline__ float fma_t<float>(float a, float b, float c) {
+    return fmaf(a, b, c);
+}
+
+// acc_a += sum_{b} sign(|b|) D_{a+b} Mt_b over the Eq. (25) index ranges, for
+// the output orders MLO..MHI only (acc indexed from cidx(MLO, 0, 0))
+template <int P, int MLO, int MHI, typename T>
+__device__ __forceinline__ void m2l_contract(const T *D, const T *__restrict__ mb, T *acc) {
+    constexpr int base = cidx(MLO, 0, 0);
+#pragma unroll
+    for (int n = 0; n <= P - MLO; n++) {
+        if (n == 1) continue;
+#pragma unroll
+        for (int b2 = 0; b2 <= n; b2++)
+#pragma unroll
+            for (int c2 = 0; c2 <= n - b2; c2++) {
+                const int a2 = n - b2 - c2;
+                const T mt = mb[midx(a2, b2, c2)];
+                const T mv = (n & 1) ? -mt : mt;
+#pragma unroll
+                for (int m = MLO; m <= (MHI < P - n ? MHI : P - n); m++)
+#pragma unroll
+                    for (int b = 0; b <= m; b++)
+#pragma unroll
+                        for (int c = 0; c <= m - b; c++) {
+                            const int a = m - b - c;
+                            acc[cidx(a, b, c) - base] = fma_t<T>(
+                                D[sidx(a + a2, b + b2, c + c2)], mv, acc[cidx(a, b, c) - base]);
+                        }
+            }
+    }
+}
+
+// one pass over a target's sources for the output orders MLO..MHI
+template <int P, int MLO, int MHI, typename T>
+__device__ __forceinline__ void m2l_pass(const double4 gA, const double4 *__restrict__ gcell,
+                                         const T *__restrict__ mult,
+                                         const int32_t *__restrict__ srcs, int len, double *out,
+                                         T (*red)[ncomp(P) + 1]) {
+    constexpr int NM = n_mult(P), ND = off_order(P + 1);
+    constexpr int NA = cidx(MHI + 1, 0, 0) - cidx(MLO, 0, 0);
+    const int lane = threadIdx.x;
+    T acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; k++) acc[k] = (T)0;
+    for (int i = lane; i < len; i += kWave) {
+        const int B = srcs[i];
+        const double4 gB = gcell[B];
+        const T x = (T)(gA.x - gB.x), y = (T)(gA.y - gB.y), z = (T)(gA.z - gB.z);
+        const T r2 = x * x + y * y + z * z;
+        T D[ND];
+        green_derivs<P, T>(x, y, z, rsqrt_t<T>(r2), D);
+        m2l_contract<P, MLO, MHI, T>(D, mult + (int64_t)B * NM, acc);
+    }
+    // wave sum, one order at a time
+#pragma unroll
+    for (int m = MLO; m <= MHI; m++) {
+        const int base = cidx(m, 0, 0) - cidx(MLO, 0, 0);
+#pragma unroll
+        for (int k = 0; k < ncomp(m); k++) red[lane][k] = acc[base + k];
+        __syncthreads();
+        if (lane < ncomp(m)) {
+            double s = 0.0;
+            for (int l = 0; l < kWave; l++) s += (double)red[l][lane];
+            out[cidx(m, 0, 0) + lane] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// FP64 at high order splits the output orders over passes (D is recomputed per
+// pass) so that the accumulators and D stay in registers.
+template <int P, typename T> struct M2LSplit { static constexpr int K1 = P, K2 = P; };
+template <> struct M2LSplit<6, double> { static constexpr int K1 = 3, K2 = 5; };
+template <> struct M2LSplit<5, double> { static constexpr int K1 = 3, K2 = 5; };
+
+template <int P, typename T>
+__global__ void __launch_bounds__(kM2LBlock)
+k_m2l(const DevState *__restrict__ st, const double4 *__restrict__ gcell,
+      const T *__restrict__ mult, const int32_t *__restrict__ off,
+      const int32_t *__restrict__ src, double *__restrict__ local) {
+    constexpr int NL = n_local(P);
+    constexpr int K1 = M2LSplit<P, T>::K1, K2 = M2LSplit<P, T>::K2;
+    __shared__ T red[kWave][ncomp(P) + 1];
+    if (st->status & kSkipMask) return;
+    const int nc = st->ncells;
+    const int lane = threadIdx.x;
+    for (int A = blockIdx.x; A < nc; A += gridDim.x) {
+        const int b0 = off[A], len = off[A + 1] - b0;
+        double *out = local + (int64_t)A * NL;
+        if (len == 0) {
+            for (int k = lane; k < NL; k += kWave) out[k] = 0.0;
+            continue;
+        }
+        const double4 gA = gcell[A];
+        m2l_pass<P, 1, K1, T>(gA, gcell, mult, src + b0, len, out, red);
+        if (K2 > K1) m2l_pass<P, (K1 < P ? K1 + 1 : P), K2, T>(gA, gcell, mult, src + b0, len, out, red);
+        if (P > K2) m2l_pass<P, (K2 < P ? K2 + 1 : P), P, T>(gA, gcell, mult, src + b0, len, out, red);
+    }
+}
+
+template <int P>
+static void launch_m2l_p(const Workspace &ws, int precision, hipStream_t s) {
+    int g = (int)(ws.cell_cap < 16384 ? ws.cell_cap : 16384);
+    if (g < 1) g = 1;
+    if (precision == NCORP_FP32_BULK)
+        k_m2l<P, float><<<g, kM2LBlock, 0, s>>>(ws.st, ws.gcell, ws.mult32, ws.m2l_off, ws.m2l_src,
+                                                ws.local);
+    else
+        k_m2l<P, double><<<g, kM2LBlock, 0, s>>>(ws.st, ws.gcell, ws.mult, ws.m2l_off, ws.m2l_src,
+                                                 ws.local);
+}
+
+hipError_t launch_m2l(const Workspace &ws, int p, int precision, hipStream_t s) {
+    switch (p) {
+        case 1: launch_m2l_p<1>(ws, precision, s); break;
+        case 2: launch_m2l_p<2>(ws, precision, s); break;
+        case 3: launch_m2l_p<3>(ws, precision, s); break;
+        case 4: launch_m2l_p<4>(ws, precision, s); break;
+        case 5: launch_m2l_p<5>(ws, precision, s); break;
+        case 6: launch_m2l_p<6>(ws, precision, s); break;
+        default: break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ncorp

@@ -1,0 +1,187 @@
+// Internal definitions shared by the HIP translation units of libncorp.
+// Device code targets gfx950 (wave64).  All device memory comes from the caller's
+// workspace; `Workspace` records where each array lives inside it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ncorp.h"
+
+namespace ncorp {
+
+constexpr int kMaxDepth = 21;          // 63-bit keys: 21 levels of 3 bits
+constexpr int kMaxP = 6;
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- tensor sizes
+// Symmetric tensors are stored per order n as the (n+1)(n+2)/2 components
+// a = (ax, ay, az), |a| = n, ordered by ax descending then ay descending.
+__host__ __device__ constexpr int tri(int k) { return k * (k + 1) / 2; }
+__host__ __device__ constexpr int ncomp(int n) { return (n + 1) * (n + 2) / 2; }
+// components of all orders below n
+__host__ __device__ constexpr int off_order(int n) { return n * (n + 1) * (n + 2) / 6; }
+// index of multi-index (a, b, c) among all orders
+__host__ __device__ constexpr int sidx(int a, int b, int c) {
+    return off_order(a + b + c) + tri(b + c) + c;
+}
+// multipoles: orders 0 and 2..p-1 (order 1 vanishes at the centre of mass)
+__host__ __device__ constexpr int n_mult(int p) {
+    return p <= 0 ? 0 : (p == 1 ? 1 : off_order(p) - 3);
+}
+__host__ __device__ constexpr int midx(int a, int b, int c) {
+    return (a + b + c) == 0 ? 0 : sidx(a, b, c) - 3;
+}
+// interaction tensors C^(m), m = 1..p
+__host__ __device__ constexpr int n_local(int p) { return p <= 0 ? 0 : off_order(p + 1) - 1; }
+__host__ __device__ constexpr int cidx(int a, int b, int c) { return sidx(a, b, c) - 1; }
+
+// ---------------------------------------------------------------- status word
+enum StatusBits : int32_t {
+    ST_CAP_CELLS = 1, ST_CAP_QUEUE = 2, ST_CAP_M2L = 4, ST_CAP_P2P = 8,
+    ST_CAP_PAIRS = 16, ST_NONFINITE = 32, ST_CAP_LISTS = 64, ST_WALK_STALL = 128,
+    ST_BAD_ITEM = 256
+};
+// Any of these leaves the tree or the interaction lists incomplete: later passes
+// then do nothing rather than follow indices that were never written.
+constexpr int32_t kSkipMask = ST_CAP_CELLS | ST_CAP_QUEUE | ST_CAP_M2L | ST_CAP_P2P |
+                              ST_CAP_LISTS | ST_WALK_STALL | ST_BAD_ITEM;
+
+// Device-side counters of one tree / walk, kept in the workspace.
+struct DevState {
+    int32_t status;            // StatusBits, latched
+    int32_t pad0;
+    int64_t required;          // size that would have sufficed for an overflow
+    // tree
+    int32_t ncells, nleaves, maxlevel, pad1;
+    int32_t level_count[kMaxDepth + 2];
+    int32_t level_off[kMaxDepth + 3];
+    double L;                  // root half-width
+    double max_abs;            // max |coordinate| (bit pattern max for >= 0 doubles)
+    // gravity walk
+    int32_t nm2l, np2p;        // unordered cell pairs
+    int64_t visited;
+    int32_t m2l_dir, p2p_dir;  // directed list lengths
+    // collision walk
+    int32_t ncand, pad2;
+    int64_t col_tests;
+    int64_t npairs;            // colliding pairs found (may exceed capacity)
+    int64_t pair_cursor;       // pairs already written by earlier steps of ncorp_step
+};
+
+// Work-queue state of a persistent walk.
+struct WalkQueue {
+    uint64_t head;             // next slot to claim
+    uint64_t tail;             // next slot to reserve
+    uint64_t done;             // items fully processed
+    uint32_t epoch;            // tag of valid items in this walk
+    uint32_t pad;
+};
+
+// ---------------------------------------------------------------- workspace
+struct Workspace {
+    char *base = nullptr;
+    int64_t bytes = 0;
+    int64_t n_max = 0, cell_cap = 0, m2l_cap = 0, p2p_cap = 0, queue_cap = 0;
+    int64_t m2l_dir_cap = 0, p2p_dir_cap = 0, pair_cap = 0;
+    int p = 0, nm = 0, nl = 0;
+    // per moonlet (tree order unless noted)
+    uint64_t *keys = nullptr, *keys_alt = nullptr;
+    uint32_t *idx = nullptr, *idx_alt = nullptr;      // tree position -> input index
+    uint32_t *code = nullptr;                         // tree-build per-moonlet code
+    double *xs = nullptr, *ys = nullptr, *zs = nullptr, *mus = nullptr;
+    double *vxs = nullptr, *vys = nullptr, *vzs = nullptr, *rads = nullptr;
+    double *acc = nullptr;                            // 3 x n, input order (step)
+    double *acc_s = nullptr;                          // 3 x n, tree order (direct sums)
+    // leaves in moonlet order ("entries")
+    int32_t *ent_start = nullptr;                     // first moonlet
+    uint32_t *ent_code = nullptr;                     // dv | L << 8
+    int32_t *ent_cell = nullptr;                      // cell index of the leaf
+    // cells, breadth-first
+    int32_t *c_level = nullptr, *c_first = nullptr, *c_count = nullptr;
+    int32_t *c_child = nullptr, *c_nchild = nullptr, *c_parent = nullptr;
+    int32_t *c_entry = nullptr;                       // first leaf (entry index)
+    int32_t *c_nent = nullptr;                        // number of leaves below
+    uint64_t *c_prefix = nullptr;
+    int32_t *c_arrive = nullptr;                      // climb counters
+    double4 *gcell = nullptr;                         // s_x, s_y, s_z, r_crit
+    double *c_mass = nullptr, *c_rmax = nullptr, *c_theta = nullptr;
+    double *mult = nullptr;                           // cell_cap x nm (FP64)
+    float *mult32 = nullptr;                          // cell_cap x nm (FP32)
+    double *local = nullptr;                          // cell_cap x nl (C after walk)
+    double *cleaf = nullptr;                          // n_max x nl (C at each leaf)
+    double4 *ccell = nullptr;                         // sbar, r_crit (collisions)
+    double *c_crmax = nullptr;
+    // walks
+    uint64_t *queue = nullptr;
+    WalkQueue *wq = nullptr;
+    int2 *m2l = nullptr, *p2p = nullptr;              // unordered cell pairs
+    int2 *cand = nullptr;                             // collision candidate cell pairs
+    int32_t *m2l_off = nullptr, *m2l_src = nullptr;   // by target cell
+    int32_t *p2p_off = nullptr, *p2p_src = nullptr;   // by target leaf (entry)
+    int32_t *cnt_a = nullptr, *cnt_b = nullptr;       // per cell / per leaf counters
+    int32_t *cnt_tmp = nullptr;                       // segment-sort scratch
+    int64_t *pairs_tmp = nullptr;                     // colliding pairs (i<<32|j)
+    int64_t *pairs_alt = nullptr;
+    // scratch for scans and sorts
+    int32_t *scan_part = nullptr;                     // block partials
+    uint32_t *hist = nullptr;                         // radix histograms
+    DevState *st = nullptr;
+    uint32_t epoch = 0;
+};
+
+// Layout of the workspace for given capacities; with base == nullptr only the
+// size is computed.
+int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max,
+                         int64_t pair_cap);
+
+// ---------------------------------------------------------------- launchers
+// (each returns hipSuccess or the first launch error)
+hipError_t launch_reset_state(const Workspace &ws, hipStream_t s);
+hipError_t launch_reset_tree_counters(const Workspace &ws, hipStream_t s);
+hipError_t launch_gather_scaled(const Workspace &ws, const double *src, double scale,
+                                double *dst, int64_t n, hipStream_t s);
+hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
+                       const double *z, int64_t n, double root_half_width, hipStream_t s);
+hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s);
+hipError_t launch_gather_pos(const Workspace &ws, const double *x, const double *y,
+                             const double *z, int64_t n, hipStream_t s);
+hipError_t launch_gather(const Workspace &ws, const double *src, double *dst, int64_t n,
+                         hipStream_t s);
+hipError_t launch_build_tree(const Workspace &ws, int64_t n, int leaf_size, hipStream_t s);
+
+hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_params &prm,
+                                hipStream_t s);
+hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hipStream_t s);
+
+// walk: mode 0 gravity (M2L + P2P lists), 1 collisions (candidate list in p2p)
+hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post,
+                       hipStream_t s);
+hipError_t launch_build_lists(const Workspace &ws, int mode, hipStream_t s);
+
+hipError_t launch_m2l(const Workspace &ws, int p, int precision, hipStream_t s);
+hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s);
+hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s);
+hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,
+                      hipStream_t s);
+hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipStream_t s);
+hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,
+                             int64_t *n_pairs_dev, int triple, int step, int64_t *cursor,
+                             hipStream_t s);
+
+hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax,
+                       const double *ay, const double *az, const double *x,
+                       const double *y, const double *z, int64_t n, double h, double G,
+                       double Mc, hipStream_t s);
+hipError_t launch_drift(double *x, double *y, double *z, const double *vx,
+                        const double *vy, const double *vz, int64_t n, double dt,
+                        hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+
+// device-wide exclusive scan of n_dev[0] int32 values (n_cap an upper bound);
+// writes total to *total_dev (may alias out[n]).
+hipError_t launch_scan(const int32_t *in, int32_t *out, const int32_t *n_dev, int64_t n_cap,
+                       int32_t *partials, int32_t *total_dev, hipStream_t s);
+
+}  // namespace ncorp

@@ -1,0 +1,324 @@
+// Downward pass (Eq. 26) and evaluation at the moonlets: direct sums of the
+// walk's brute-force pairs plus the leaf expansion.
+//
+// Descent: C^(m)(s_1) = sum_{|b| <= p-m} C_{a+b}(s_0) (s_1 - s_0)^b / b!.  Applied
+// from the root down the paper's way, every leaf ends up with the sum of its own
+// and its ancestors' walk tensors, each shifted to the leaf's centre; that sum is
+// formed directly per leaf (shifts compose exactly), so no pass waits on another.
+//
+// Evaluation: one wave per leaf.  Its sources (every cell the walk paired with
+// the leaf or one of its ancestors for a direct sum) are streamed through LDS 64
+// moonlets at a time; leaves with fewer than 64 moonlets split each tile over
+// lane groups.  In the FP32-bulk form offsets from the leaf centre are formed in
+// FP64 and rounded, each source tile is summed in FP32, and the tile sums are
+// added with Kahan compensation.  The leaf's C tensors then give
+// a_i += sum_{|b| <= p-1} C_{e+b}(s_leaf) (x_i - s_leaf)^b / b!.
+#include "ncorp_internal.h"
+
+namespace ncorp {
+
+template <int P>
+__device__ __forceinline__ void scaled_pow(double ux, double uy, double uz, double *px,
+                                           double *py, double *pz) {
+    px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+    for (int a = 1; a <= P; a++) {
+        const double inv = 1.0 / (double)a;
+        px[a] = px[a - 1] * ux * inv;
+        py[a] = py[a - 1] * uy * inv;
+        pz[a] = pz[a - 1] * uz * inv;
+    }
+}
+
+// Descent without inter-cell waiting.  Shifting a degree-p local expansion is an
+// exact re-expansion, so shifts compose: C(leaf) = sum over the leaf and its
+// ancestors a of shift(C_walk(a), s_leaf - s_a).  One thread per (leaf, output
+// order m) sums that chain; threads are ordered by m so a wave runs one order.
+template <int P, int M>
+__device__ __forceinline__ void leaf_local_order(int cl, const int32_t *__restrict__ c_parent,
+                                                 const double4 *__restrict__ gcell,
+                                                 const double *__restrict__ local,
+                                                 const int32_t *__restrict__ m2l_off,
+                                                 double *__restrict__ out) {
+    constexpr int NL = n_local(P), NR = P - M, NC = ncomp(M);
+    double acc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; k++) acc[k] = 0.0;
+    const double4 gl = gcell[cl];
+    int a = cl;
+    for (int up = 0; up <= kMaxDepth && a >= 0; up++) {
+        if (m2l_off[a + 1] != m2l_off[a]) {          // cells without M2L hold zeros
+            const double4 ga = gcell[a];
+            double px[NR + 1], py[NR + 1], pz[NR + 1];
+            scaled_pow<NR>(gl.x - ga.x, gl.y - ga.y, gl.z - ga.z, px, py, pz);
+            const double *ca = local + (int64_t)a * NL;
+#pragma unroll
+            for (int b = 0; b <= M; b++)
+#pragma unroll
+                for (int c = 0; c <= M - b; c++) {
+                    const int aa = M - b - c;
+                    double sum = acc[tri(b + c) + c];
+#pragma unroll
+                    for (int n = 0; n <= NR; n++)
+#pragma unroll
+                        for (int b2 = 0; b2 <= n; b2++)
+#pragma unroll
+                            for (int c2 = 0; c2 <= n - b2; c2++) {
+                                const int a2 = n - b2 - c2;
+                                sum += ca[cidx(aa + a2, b + b2, c + c2)] *
+                                       (px[a2] * py[b2] * pz[c2]);
+                            }
+                    acc[tri(b + c) + c] = sum;
+                }
+        }
+        a = c_parent[a];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; k++) out[cidx(M, 0, 0) + k] = acc[k];
+}
+
+template <int P>
+__global__ void __launch_bounds__(128)
+k_leaf_local(const DevState *__restrict__ st, const int32_t *__restrict__ ent_cell,
+             const int32_t *__restrict__ c_parent, const double4 *__restrict__ gcell,
+             const double *__restrict__ local, const int32_t *__restrict__ m2l_off,
+             double *__restrict__ cleaf) {
+    constexpr int NL = n_local(P);
+    if (st->status & kSkipMask) return;
+    const int K = st->nleaves;
+    const int64_t total = (int64_t)K * P;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int m = (int)(t / K) + 1, e = (int)(t % K);
+        const int cl = ent_cell[e];
+        double *out = cleaf + (int64_t)e * NL;
+        switch (m) {
+            case 1: leaf_local_order<P, 1>(cl, c_parent, gcell, local, m2l_off, out); break;
+            case 2: if constexpr (P >= 2) leaf_local_order<P, (P >= 2 ? 2 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
+            case 3: if constexpr (P >= 3) leaf_local_order<P, (P >= 3 ? 3 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
+            case 4: if constexpr (P >= 4) leaf_local_order<P, (P >= 4 ? 4 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
+            case 5: if constexpr (P >= 5) leaf_local_order<P, (P >= 5 ? 5 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
+            case 6: if constexpr (P >= 6) leaf_local_order<P, (P >= 6 ? 6 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
+            default: break;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ evaluation
+template <typename T> struct Acc3;
+template <> struct Acc3<double> {
+    double x = 0, y = 0, z = 0;
+    __device__ void add_tile(double px, double py, double pz) { x += px; y += py; z += pz; }
+    __device__ void fold(double &ox, double &oy, double &oz) const { ox = x; oy = y; oz = z; }
+};
+// Kahan-compensated FP32 sums of FP32 tile partials
+template <> struct Acc3<float> {
+    float x = 0, y = 0, z = 0, cx = 0, cy = 0, cz = 0;
+    __device__ static void kahan(float &s, float &c, float v) {
+        float yv = v - c;
+        float t = s + yv;
+        c = (t - s) - yv;
+        s = t;
+    }
+    __device__ void add_tile(float px, float py, float pz) {
+        kahan(x, cx, px); kahan(y, cy, py); kahan(z, cz, pz);
+    }
+    __device__ void fold(double &ox, double &oy, double &oz) const {
+        ox = (double)x - (double)cx; oy = (double)y - (double)cy; oz = (double)z - (double)cz;
+    }
+};
+
+template <typename T> __device__ __forceinline__ T rsq(T v);
+template <> __device__ __forceinline__ double rsq<double>(double v) { return rsqrt(v); }
+template <> __device__ __forceinline__ float rsq<float>(float v) { return rsqrtf(v); }
+template <typename T> __device__ __forceinline__ T fmat(T a, T b, T c);
+template <> __device__ __forceinline__ double fmat<double>(double a, double b, double c) { return fma(a, b, c); }
+template <> __device__ __forceinline__ float fmat<float>(float a, float b, float c) { return fmaf(a, b, c); }
+
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
+      const double *__restrict__ ys, const double *__restrict__ zs,
+      const double *__restrict__ mus, const int32_t *__restrict__ ent_cell,
+      const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
+      const double4 *__restrict__ gcell, const int32_t *__restrict__ p2p_off,
+      const int32_t *__restrict__ p2p_src, double *__restrict__ acc_s, int64_t n) {
+    __shared__ T sx[64], sy[64], sz[64], sm[64];
+    if (st->status & kSkipMask) return;
+    const int K = st->nleaves;
+    const int lane = threadIdx.x;
+    for (int e = blockIdx.x; e < K; e += gridDim.x) {
+        const int c = ent_cell[e];
+        const int f = c_first[c], nt = c_count[c];
+        const double4 g = gcell[c];
+        const int s0 = p2p_off[e], s1 = p2p_off[e + 1];
+        for (int t0 = 0; t0 < nt; t0 += 64) {
+            const int ntc = nt - t0 < 64 ? nt - t0 : 64;
+            int S = 1;
+            while (S < ntc) S <<= 1;
+            const int G = 64 / S, tl = lane % S, grp = lane / S;
+            const bool act = tl < ntc;
+            const int i = f + t0 + (act ? tl : 0);
+            const T xi = (T)(xs[i] - g.x), yi = (T)(ys[i] - g.y), zi = (T)(zs[i] - g.z);
+            Acc3<T> acc;
+            for (int q = s0; q < s1; q++) {
+                const int B = p2p_src[q];
+                const int bf = c_first[B], bn = c_count[B];
+                for (int j0 = 0; j0 < bn; j0 += 64) {
+                    const int nj = bn - j0 < 64 ? bn - j0 : 64;
+                    __syncthreads();
+                    if (lane < nj) {
+                        const int j = bf + j0 + lane;
+                        sx[lane] = (T)(xs[j] - g.x);
+                        sy[lane] = (T)(ys[j] - g.y);
+                        sz[lane] = (T)(zs[j] - g.z);
+                        sm[lane] = (T)mus[j];
+                    }
+                    __syncthreads();
+                    T px = 0, py = 0, pz = 0;
+                    for (int j = grp; j < nj; j += G) {
+                        const T dx = sx[j] - xi, dy = sy[j] - yi, dz = sz[j] - zi;
+                        const T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, dx * dx));
+                        const T rinv = rsq<T>(r2);
+                        const T w = r2 > (T)0 ? sm[j] * rinv * rinv * rinv : (T)0;
+                        px = fmat<T>(dx, w, px);
+                        py = fmat<T>(dy, w, py);
+                        pz = fmat<T>(dz, w, pz);
+                    }
+                    acc.add_tile(px, py, pz);
+                }
+            }
+            double ox, oy, oz;
+            acc.fold(ox, oy, oz);
+            for (int o = S; o < 64; o <<= 1) {
+                ox += __shfl_xor(ox, o);
+                oy += __shfl_xor(oy, o);
+                oz += __shfl_xor(oz, o);
+            }
+            if (act && grp == 0) {
+                acc_s[i] = ox;
+                acc_s[n + i] = oy;
+                acc_s[2 * n + i] = oz;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// evaluation of the leaf's expansion at its moonlets (Eq. 26 down to C^(1)),
+// added to the direct sums and written in input order
+template <int P>
+__global__ void __launch_bounds__(64)
+k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
+      const double *__restrict__ ys, const double *__restrict__ zs,
+      const uint32_t *__restrict__ perm, const int32_t *__restrict__ ent_cell,
+      const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
+      const double4 *__restrict__ gcell, const double *__restrict__ cleaf,
+      const double *__restrict__ acc_s, int64_t n, double *__restrict__ ax,
+      double *__restrict__ ay, double *__restrict__ az) {
+    constexpr int NL = n_local(P);
+    __shared__ double cl[NL];
+    if (st->status & kSkipMask) return;
+    const int K = st->nleaves;
+    const int lane = threadIdx.x;
+    for (int e = blockIdx.x; e < K; e += gridDim.x) {
+        const int c = ent_cell[e];
+        const int f = c_first[c], nt = c_count[c];
+        const double4 g = gcell[c];
+        __syncthreads();
+        for (int k = lane; k < NL; k += 64) cl[k] = cleaf[(int64_t)e * NL + k];
+        __syncthreads();
+        for (int t0 = 0; t0 < nt; t0 += 64) {
+            const int t = t0 + lane;
+            if (t >= nt) continue;
+            const int i = f + t;
+            double px[P], py[P], pz[P];
+            const double ux = xs[i] - g.x, uy = ys[i] - g.y, uz = zs[i] - g.z;
+            px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+            for (int a = 1; a < P; a++) {
+                const double inv = 1.0 / (double)a;
+                px[a] = px[a - 1] * ux * inv;
+                py[a] = py[a - 1] * uy * inv;
+                pz[a] = pz[a - 1] * uz * inv;
+            }
+            double lx = 0.0, ly = 0.0, lz = 0.0;
+#pragma unroll
+            for (int nn = 0; nn < P; nn++)
+#pragma unroll
+                for (int b2 = 0; b2 <= nn; b2++)
+#pragma unroll
+                    for (int c2 = 0; c2 <= nn - b2; c2++) {
+                        const int a2 = nn - b2 - c2;
+                        const double w = px[a2] * py[b2] * pz[c2];
+                        lx += cl[cidx(1 + a2, b2, c2)] * w;
+                        ly += cl[cidx(a2, 1 + b2, c2)] * w;
+                        lz += cl[cidx(a2, b2, 1 + c2)] * w;
+                    }
+            const uint32_t o = perm[i];
+            ax[o] = acc_s[i] + lx;
+            ay[o] = acc_s[n + i] + ly;
+            az[o] = acc_s[2 * n + i] + lz;
+        }
+    }
+}
+
+template <int P>
+static void launch_leaf_local(const Workspace &ws, hipStream_t s) {
+    int64_t g = ((int64_t)ws.n_max * P + 127) / 128;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    k_leaf_local<P><<<(int)g, 128, 0, s>>>(ws.st, ws.ent_cell, ws.c_parent, ws.gcell, ws.local,
+                                           ws.m2l_off, ws.cleaf);
+}
+
+hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s) {
+    switch (p) {
+        case 1: launch_leaf_local<1>(ws, s); break;
+        case 2: launch_leaf_local<2>(ws, s); break;
+        case 3: launch_leaf_local<3>(ws, s); break;
+        case 4: launch_leaf_local<4>(ws, s); break;
+        case 5: launch_leaf_local<5>(ws, s); break;
+        case 6: launch_leaf_local<6>(ws, s); break;
+        default: break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s) {
+    int g = (int)(ws.n_max < 65536 ? ws.n_max : 65536);
+    if (g < 1) g = 1;
+    if (precision == NCORP_FP32_BULK)
+        k_p2p<float><<<g, 64, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first,
+                                      ws.c_count, ws.gcell, ws.p2p_off, ws.p2p_src, ws.acc_s, n);
+    else
+        k_p2p<double><<<g, 64, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell,
+                                       ws.c_first, ws.c_count, ws.gcell, ws.p2p_off, ws.p2p_src,
+                                       ws.acc_s, n);
+    return hipGetLastError();
+}
+
+template <int P>
+static void launch_l2p_p(const Workspace &ws, int64_t n, double *ax, double *ay, double *az,
+                         hipStream_t s) {
+    int g = (int)(ws.n_max < 65536 ? ws.n_max : 65536);
+    if (g < 1) g = 1;
+    k_l2p<P><<<g, 64, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.idx, ws.ent_cell, ws.c_first,
+                              ws.c_count, ws.gcell, ws.cleaf, ws.acc_s, n, ax, ay, az);
+}
+
+hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,
+                      hipStream_t s) {
+    switch (p) {
+        case 1: launch_l2p_p<1>(ws, n, ax, ay, az, s); break;
+        case 2: launch_l2p_p<2>(ws, n, ax, ay, az, s); break;
+        case 3: launch_l2p_p<3>(ws, n, ax, ay, az, s); break;
+        case 4: launch_l2p_p<4>(ws, n, ax, ay, az, s); break;
+        case 5: launch_l2p_p<5>(ws, n, ax, ay, az, s); break;
+        case 6: launch_l2p_p<6>(ws, n, ax, ay, az, s); break;
+        default: break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ncorp

@@ -1,0 +1,55 @@
+// Kick and drift of the leapfrog (Sect. 4.1) with the central mass computed
+// exactly in the kick (App. B.1: a = -G M_c r / r^3; it is not part of the tree).
+#include "ncorp_internal.h"
+
+namespace ncorp {
+
+__global__ void k_kick(double *__restrict__ vx, double *__restrict__ vy, double *__restrict__ vz,
+                       const double *__restrict__ ax, const double *__restrict__ ay,
+                       const double *__restrict__ az, const double *__restrict__ x,
+                       const double *__restrict__ y, const double *__restrict__ z, int64_t n,
+                       double h, double GM) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double px = x[i], py = y[i], pz = z[i];
+        const double r2 = px * px + py * py + pz * pz;
+        const double r = sqrt(r2);
+        const double f = -GM / (r2 * r);
+        double gx = f * px, gy = f * py, gz = f * pz;
+        if (ax) { gx += ax[i]; gy += ay[i]; gz += az[i]; }
+        vx[i] += h * gx;
+        vy[i] += h * gy;
+        vz[i] += h * gz;
+    }
+}
+
+__global__ void k_drift(double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
+                        const double *__restrict__ vx, const double *__restrict__ vy,
+                        const double *__restrict__ vz, int64_t n, double dt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += dt * vx[i];
+        y[i] += dt * vy[i];
+        z[i] += dt * vz[i];
+    }
+}
+
+static int grid1(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax, const double *ay,
+                       const double *az, const double *x, const double *y, const double *z,
+                       int64_t n, double h, double G, double Mc, hipStream_t s) {
+    k_kick<<<grid1(n), 256, 0, s>>>(vx, vy, vz, ax, ay, az, x, y, z, n, h, G * Mc);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift(double *x, double *y, double *z, const double *vx, const double *vy,
+                        const double *vz, int64_t n, double dt, hipStream_t s) {
+    k_drift<<<grid1(n), 256, 0, s>>>(x, y, z, vx, vy, vz, n, dt);
+    return hipGetLastError();
+}
+
+}  // namespace ncorp

@@ -1,0 +1,68 @@
+"""The C ABI library builds, loads and exports every entry point include/ncorp.h
+declares; host-side argument checks work without a GPU (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def nc():
+    from paper_2310_20374_amd import ncorp
+    if not os.path.exists(ncorp.LIB_PATH):
+        from paper_2310_20374_amd import build
+        build.build()
+    return ncorp
+
+
+def _declared():
+    h = open(os.path.join(ROOT, "include", "ncorp.h")).read()
+    return sorted(set(re.findall(r"\b(ncorp_[a-z_]+)\s*\(", h)))
+
+
+def test_header_symbols_exported(nc):
+    L = nc.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(nc.EXPORTED_SYMBOLS) <= set(names)
+
+
+def test_params_default_and_validation(nc):
+    L = nc.lib()
+    for p in range(7):
+        prm = nc.params_default(p)
+        assert prm.p == p
+        assert prm.leaf_size == (17 if p <= 3 else 52)
+        assert (prm.ncs_col, prm.ncc_pre_col, prm.ncc_post_col) == (12, 0, 16)
+    bad = nc.Params()
+    assert L.ncorp_params_default(C.byref(bad), 7) == nc.E_INVALID
+    h = C.c_void_p()
+    for field, val in (("p", 7), ("theta_min", 1.0), ("theta_min", 0.0), ("leaf_size", 0),
+                       ("ncs", -1), ("theta_mode", 2), ("precision", 5),
+                       ("root_half_width", 3.0), ("G", -1.0)):
+        prm = nc.params_default(3)
+        setattr(prm, field, val)
+        assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.E_INVALID, field
+    prm = nc.params_default(3, root_half_width=16.0)
+    assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.OK
+    assert h.value
+    # calls that need a tree or arrays fail on the host, before any GPU work
+    assert L.ncorp_gravity(h, None, None, None, None, None) == nc.E_INVALID
+    assert b"tree" in L.ncorp_last_error(h)
+    assert L.ncorp_build_tree(h, None, None, None, 10, None, 0, None) == nc.E_INVALID
+    L.ncorp_destroy(h)
+
+
+def test_workspace_bytes(nc):
+    prm = nc.params_default(6)
+    a = nc.workspace_bytes(prm, 1000)
+    b = nc.workspace_bytes(prm, 10 ** 6)
+    assert 0 < a < b
+    assert b % 256 == 0
+    assert nc.workspace_bytes(prm, 1000, 10 ** 6) > a
+    assert nc.lib().ncorp_workspace_bytes(C.byref(prm), 0, 0) == -1

@@ -1,0 +1,61 @@
+"""GPU collision search (Sect. 3.1 Eqs. 1-2 on the walk's candidates, Alg. 2)
+equals the brute-force pair set bit for bit, and its candidate cell pairs equal
+the oracle walk's."""
+import numpy as np
+import pytest
+
+from paper_2310_20374_amd import inputs
+from tests.gpu_util import run_collide
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nc():
+    from paper_2310_20374_amd import ncorp
+    ncorp.lib()
+    return ncorp
+
+
+CASES = {
+    "gas2k": (lambda: inputs.gas_box(2000, seed=1), 0.01, 8),
+    "gas2k_seed3": (lambda: inputs.gas_box(2000, seed=3), 0.01, 16),
+    "disk3k_dt2": (lambda: inputs.disk(3000, seed=2), 2.0, 16),
+    "disk2k_cold": (lambda: inputs.disk(2000, seed=0), 1e-3, 16),
+    "hot3k": (lambda: inputs.hot_disk(3000, seed=0), 0.5, 17),
+    "clumps2e4": (lambda: inputs.clumps(20000, seed=0, n_clumps=20), 0.01, 16),
+    "clumps2e4_s52": (lambda: inputs.clumps(20000, seed=1, n_clumps=20), 0.01, 52),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_pairs_equal_brute_force(nc, orc, case):
+    gen, dt, s = CASES[case]
+    d = gen()
+    print(f"case {case}", flush=True)
+    prm = nc.params_default(3, leaf_size=s)
+    ctx, got = run_collide(nc, d, prm, dt)
+    want = orc.pairs_brute(d, dt)
+    assert np.array_equal(got, want)
+    tr = orc.Tree(d["x"], d["y"], d["z"], s)
+    co = orc.Collide(tr, d["vx"], d["vy"], d["vz"], d["R"], dt)
+    co.run(prm.ncs_col, prm.ncc_pre_col, prm.ncc_post_col)
+    cand = np.sort(co.candidates().astype(np.int64), axis=1)
+    gc = np.sort(ctx.export("col_cand").astype(np.int64), axis=1)
+    assert set(map(tuple, gc.tolist())) == set(map(tuple, cand.tolist()))
+    assert ctx.tree_info()["col_tests"] == co.ntests()
+
+
+def test_pair_capacity_overflow_is_reported(nc):
+    import torch
+    d = inputs.gas_box(2000, seed=1)
+    prm = nc.params_default(3, leaf_size=8)
+    n = len(d["x"])
+    ctx = nc.Context(prm, n, pair_capacity=4096)
+    t = {k: torch.tensor(v, device="cuda:0") for k, v in d.items()}
+    pairs = torch.zeros((3, 2), dtype=torch.int64, device="cuda:0")
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    ctx.build_tree(t["x"], t["y"], t["z"])
+    ctx.collide(t["vx"], t["vy"], t["vz"], t["R"], 0.01, pairs, npairs)
+    r, req, _ = ctx.get_status()
+    assert r == nc.E_CAPACITY and req == int(npairs.item()) > 3

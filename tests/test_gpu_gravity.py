@@ -1,0 +1,103 @@
+"""GPU parity of mutual gravity (Alg. 2, Eqs. 25-26): interaction lists equal to
+the oracle's, accelerations equal to the oracle tree to FP64 rounding, and the
+error against the FP64 direct sum within the stated bounds."""
+import numpy as np
+import pytest
+
+from paper_2310_20374_amd import inputs
+from tests.gpu_util import rel_err, run_gravity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nc():
+    from paper_2310_20374_amd import ncorp
+    ncorp.lib()
+    return ncorp
+
+
+def _pairs_set(arr):
+    a = np.sort(np.asarray(arr, dtype=np.int64), axis=1)
+    return set(map(tuple, a.tolist()))
+
+
+GRAV_CASES = {
+    # name: (generator, p, s, thresholds, theta_mode)
+    "disk2k_p3": (lambda: inputs.disk(2000, seed=0), 3, 16, (64, 8, 64), 0),
+    "disk2k_p1": (lambda: inputs.disk(2000, seed=0), 1, 16, (64, 8, 64), 0),
+    "disk2k_p2": (lambda: inputs.disk(2000, seed=0), 2, 16, (64, 8, 64), 1),
+    "disk2e4_p6": (lambda: inputs.disk(20000, seed=1), 6, 52, (256, 256, 512), 0),
+    "disk2e4_p4_s1": (lambda: inputs.disk(20000, seed=2), 4, 1, (0, 0, 0), 1),
+    "clumps2e4_p5": (lambda: inputs.clumps(20000, seed=0, n_clumps=20), 5, 16, (64, 8, 64), 0),
+    "hot1e4_p6_small_ncs": (lambda: inputs.hot_disk(10000, seed=0), 6, 20, (4, 0, 0), 0),
+}
+
+
+@pytest.mark.parametrize("case", list(GRAV_CASES))
+def test_gravity_matches_oracle_tree(nc, orc, case):
+    gen, p, s, thr, mode = GRAV_CASES[case]
+    d = gen()
+    print(f"case {case}", flush=True)
+    prm = nc.params_default(p, leaf_size=s, ncs=thr[0], ncc_pre=thr[1], ncc_post=thr[2],
+                            theta_mode=mode)
+    ctx, a = run_gravity(nc, d, prm)
+    ref, t, g = orc.tree_accel(d, p=p, s=s, ncs=thr[0], ncc_pre=thr[1], ncc_post=thr[2],
+                               theta_mode=mode)
+    # same walk: identical lists of well-separated and brute-force cell pairs
+    m2l, p2p = g.lists()
+    assert _pairs_set(ctx.export("m2l")) == _pairs_set(m2l)
+    assert _pairs_set(ctx.export("p2p")) == _pairs_set(p2p)
+    info = ctx.tree_info()
+    assert info["m2l"] == len(m2l) and info["p2p"] == len(p2p)
+    rms, mx = rel_err(a, ref)
+    assert mx < 1e-11, (rms, mx)
+    # Newton's third law to rounding (Sect. 3.4.3)
+    f = d["m"][:, None] * a
+    assert np.abs(f.sum(0)).max() < 1e-11 * np.abs(f).sum(0).max()
+
+
+def test_no_opening_equals_direct_sum(nc, orc):
+    d = inputs.disk(3000, seed=7)
+    prm = nc.params_default(3, leaf_size=16, ncs=10 ** 9)
+    _, a = run_gravity(nc, d, prm)
+    ref = orc.direct_sum(d["x"], d["y"], d["z"], d["m"])
+    assert rel_err(a, ref)[1] < 1e-12
+
+
+def test_p0_no_mutual_gravity(nc):
+    d = inputs.disk(1000, seed=0)
+    prm = nc.params_default(0)
+    _, a = run_gravity(nc, d, prm)
+    assert np.all(a == 0.0)
+
+
+def test_two_moonlets(nc):
+    d = {"x": np.array([0.0, 3.0]), "y": np.zeros(2), "z": np.zeros(2),
+         "m": np.array([2.0, 0.5])}
+    prm = nc.params_default(3, leaf_size=1, ncs=0, ncc_pre=0, ncc_post=0, G=1.3)
+    _, a = run_gravity(nc, d, prm)
+    assert a[0, 0] == pytest.approx(1.3 * 0.5 / 9.0, rel=1e-15)
+    assert a[1, 0] == pytest.approx(-1.3 * 2.0 / 9.0, rel=1e-15)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_error_vs_direct_sum(nc, orc, prec):
+    """Config-2-like disk (p = 6, theta_min = 0.5): RMS relative error against the
+    FP64 direct sum on sampled moonlets, for the total acceleration (mutual +
+    central mass, what the moonlets feel) and for the mutual part alone."""
+    N = 100000
+    d = inputs.disk(N, seed=0)
+    prm = nc.params_default(6, precision=nc.FP32_BULK if prec == "fp32" else nc.FP64)
+    _, a = run_gravity(nc, d, prm)
+    tg = inputs.sample_targets(N, 1024)
+    ad = orc.direct_sum(d["x"], d["y"], d["z"], d["m"], targets=tg)
+    ac = orc.central_accel(d["x"][tg], d["y"][tg], d["z"][tg])
+    tot_rms, _ = rel_err(a[tg] + ac, ad + ac)
+    mut_rms, _ = rel_err(a[tg], ad)
+    print(f"{prec}: total rms {tot_rms:.3e}  mutual rms {mut_rms:.3e}")
+    assert tot_rms < 1e-5
+    assert mut_rms < 5e-3
+    if prec == "fp32":
+        ref, _, _ = orc.tree_accel(d, p=6, s=52, ncs=256, ncc_pre=256, ncc_post=512)
+        assert rel_err(a, ref)[0] < 1e-5      # FP32 rounding only
