@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Throughput of the falcON tree step (gravity + collision search) on one MI355X.
+
+Workload: a cold disk of N = 1e6 moonlets around a central mass of 1 (G = 1),
+expansion order p = 6, theta_min = 0.5 with the mass-dependent opening angle,
+leaf size 52 and the walk thresholds of the paper's timing runs, dt = 1e-3.  One
+step = collision climb + walk + pair tests, drift, rebuild (keys, sort, octree),
+gravity climb + walk + M2L + descent + direct sums + evaluation, kicks (one
+ncorp_step call runs all K steps; its extra initial force evaluation is inside
+the timed region).  The headline value is the FP32-bulk form; the plain FP64
+form is measured the same way and reported beside it.
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published)
+PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector (published)
+FLOPS_PER_INTERACTION = 20  # directed moonlet pair, the usual N-body convention
+
+
+def _run(nc, prm, d, dt, steps, warmup, timing, device):
+    import torch
+    n = len(d["x"])
+    ctx = nc.Context(prm, n, pair_capacity=1 << 20, device=device)
+    base = {k: torch.tensor(v, device=device) for k, v in d.items()}
+    st = {k: v.clone() for k, v in base.items()}
+    pairs = torch.zeros((1 << 20, 3), dtype=torch.int64, device=device)
+    npairs = torch.zeros(max(steps, warmup, 1), dtype=torch.int64, device=device)
+
+    def reset():
+        for k in st:
+            st[k].copy_(base[k])
+
+    def go(k):
+        ctx.step(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["m"], st["R"], dt,
+                 k, pairs, npairs)
+
+    if warmup > 0:
+        go(warmup)
+    torch.cuda.synchronize()
+    ctx.check_status()
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    go(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check_status()
+    wall = t1 - t0
+    n_pairs = int(npairs[:steps].sum().item())
+    phases = None
+    info = None
+    if timing:
+        reset()
+        ctx.set_timing(True)
+        go(steps)
+        torch.cuda.synchronize()
+        ctx.check_status()
+        phases = ctx.phase_times()
+        info = ctx.tree_info()
+        ctx.set_timing(False)
+    # accelerations at the initial state, for the error check
+    reset()
+    a = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(3)]
+    ctx.build_tree(st["x"], st["y"], st["z"])
+    ctx.gravity(st["m"], *a)
+    torch.cuda.synchronize()
+    ctx.check_status()
+    acc = torch.stack(a, 1).cpu().numpy()
+    return {"wall_s": wall, "phases": phases, "info": info, "acc": acc, "pairs": n_pairs}
+
+
+def _errors(orc, d, acc, samples):
+    import numpy as np
+    from paper_2310_20374_amd import inputs
+    tg = inputs.sample_targets(len(d["x"]), samples)
+    ad = orc.direct_sum(d["x"], d["y"], d["z"], d["m"], targets=tg)
+    ac = orc.central_accel(d["x"][tg], d["y"][tg], d["z"][tg])
+
+    def stats(a, ref):
+        e = np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        return float(np.sqrt(np.mean(e * e))), float(e.max())
+
+    tot = stats(acc[tg] + ac, ad + ac)
+    mut = stats(acc[tg], ad)
+    return {"rms_total": tot[0], "max_total": tot[1], "rms_mutual": mut[0], "max_mutual": mut[1],
+            "samples": int(len(tg))}
+
+
+def _cpu_baseline(orc, n_sample, p, theta, s, thr, dt):
+    """The oracle as it stands (single-threaded FP64 tree, recursive walk, full
+    3^n tensors) for one step of a sub-disk drawn from the same distribution."""
+    import numpy as np
+    from paper_2310_20374_amd import inputs
+    d = inputs.disk(n_sample, seed=0)
+    t0 = time.perf_counter()
+
+    def accel(st):
+        a, _, _ = orc.tree_accel(st, p=p, theta_min=theta, s=s, ncs=thr[0], ncc_pre=thr[1],
+                                 ncc_post=thr[2])
+        return a
+
+    def collide(st, h):
+        t = orc.Tree(st["x"], st["y"], st["z"], s)
+        c = orc.Collide(t, st["vx"], st["vy"], st["vz"], st["R"], h)
+        return c.run(12, 0, 16)
+
+    orc.kdk_steps(d, dt, 1, accel, collide_fn=collide)
+    el = time.perf_counter() - t0
+    # kdk_steps evaluates gravity twice for one step (start and end); count one step
+    return {"value": n_sample / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one KDK step of an N={n_sample} cold disk (same distribution, p={p}, "
+                      f"theta_min={theta}, s={s}) with the FP64 oracle tree (gravity at both "
+                      f"ends of the step) and its tree collision walk; single-threaded",
+            "seconds": el}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--p", type=int, default=6)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--samples", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=150_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-errors", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(see DESIGN.md for how the step would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+
+    from paper_2310_20374_amd import inputs, ncorp
+    device = "cuda:0"
+    d = inputs.disk(args.n, seed=0)
+    prm64 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP64)
+    prm32 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP32_BULK)
+    thr = (prm64.ncs, prm64.ncc_pre, prm64.ncc_post)
+    print(f"# bench: N={args.n} p={args.p} theta_min={args.theta} s={prm64.leaf_size} "
+          f"steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+
+    r32 = _run(ncorp, prm32, d, args.dt, args.steps, args.warmup, True, device)
+    print(f"# fp32-bulk: {r32['wall_s'] * 1e3 / args.steps:.3f} ms/step", file=sys.stderr,
+          flush=True)
+    r64 = None
+    if not args.fp32_only:
+        r64 = _run(ncorp, prm64, d, args.dt, args.steps, args.warmup, True, device)
+        print(f"# fp64: {r64['wall_s'] * 1e3 / args.steps:.3f} ms/step", file=sys.stderr,
+              flush=True)
+
+    orc = None
+    if not (args.no_errors and args.no_cpu_baseline):
+        import oracle as orc
+    err32 = err64 = None
+    if not args.no_errors:
+        err32 = _errors(orc, d, r32["acc"], args.samples)
+        if r64 is not None:
+            err64 = _errors(orc, d, r64["acc"], args.samples)
+        print(f"# errors fp32 {err32} fp64 {err64}", file=sys.stderr, flush=True)
+
+    value = args.n * args.steps / r32["wall_s"]
+    ph = r32["phases"]
+    info = r32["info"]
+    p2p_ms, p2p_launches = ph["p2p"]
+    p2p_avg_s = p2p_ms / max(p2p_launches, 1) / 1e3
+    flops = FLOPS_PER_INTERACTION * info["p2p_inter"]
+    achieved = flops / p2p_avg_s / 1e12 if p2p_avg_s > 0 else 0.0
+    roofline = {"bound": "alu", "kernel": "k_p2p<float> (direct sums, FP32 VALU)",
+                "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "avg_launch_us": p2p_avg_s * 1e6, "launches": p2p_launches,
+                "interactions_per_launch": info["p2p_inter"],
+                "flops_per_interaction": FLOPS_PER_INTERACTION}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = _cpu_baseline(orc, args.cpu_sample, args.p, args.theta, prm64.leaf_size, thr,
+                            args.dt)
+        cpu["cores"] = 1
+
+    def phase_summary(r):
+        if r is None or r["phases"] is None:
+            return None
+        return {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()}
+
+    out = {
+        "metric": "particle-steps/s (gravity+collision) at N=1M, FP32-bulk vs FP64, @RMS err",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["wall_s"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "cold Keplerian disk of moonlets around a central mass (G=1, M=1): "
+                        "lognormal masses summing to 0.01, a in [2.9,10], Rayleigh e 0.01 and "
+                        "i 0.005; KDK steps with collision search + octree rebuild + falcON "
+                        "gravity each step",
+            "n": args.n, "p": args.p, "theta_min": args.theta, "theta_mode": "mass-dependent",
+            "leaf_size": prm64.leaf_size, "walk_thresholds": list(thr),
+            "collision_thresholds": [prm64.ncs_col, prm64.ncc_pre_col, prm64.ncc_post_col],
+            "dt": args.dt, "precision": "fp32-bulk: direct sums and M2L in f32 (Kahan-summed "
+                                        "tiles), positions/offsets/climbs/integrator in f64",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "errors_fp32": err32,
+        "fp64": None if r64 is None else {
+            "value": args.n * args.steps / r64["wall_s"],
+            "ms_per_step": r64["wall_s"] * 1e3 / args.steps, "errors": err64,
+            "phases_ms_per_step": phase_summary(r64)},
+        "phases_ms_per_step": phase_summary(r32),
+        "tree": info,
+        "collision_pairs_in_timed_steps": r32["pairs"],
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -139,11 +139,13 @@ const char *ncorp_last_error(const ncorp_ctx *ctx);
 enum {
     NCORP_INFO_N = 0, NCORP_INFO_NCELLS, NCORP_INFO_NLEAVES, NCORP_INFO_MAXLEVEL,
     NCORP_INFO_M2L, NCORP_INFO_P2P, NCORP_INFO_VISITED, NCORP_INFO_COL_CAND,
-    NCORP_INFO_COL_TESTS, NCORP_INFO_COUNT
+    NCORP_INFO_COL_TESTS, NCORP_INFO_M2L_DIR, NCORP_INFO_P2P_INTER, NCORP_INFO_COUNT
 };
 /* Waits for the stream and fills info[NCORP_INFO_COUNT] with sizes of the last
  * tree and walks (cells, leaves, deepest level, M2L and P2P cell pairs of the
- * last gravity walk, visited pairs, collision candidate cell pairs, pair tests). */
+ * last gravity walk, visited pairs, collision candidate cell pairs, pair tests,
+ * directed M2L interactions, directed moonlet-moonlet interactions of the direct
+ * sums with i != j). */
 int ncorp_tree_info(ncorp_ctx *ctx, int64_t *info);
 
 enum {
@@ -171,6 +173,22 @@ enum {
  * stream).  Returns the number of bytes the full array needs (copying at most
  * `bytes`), or a negative ncorp_status. */
 int64_t ncorp_export_host(ncorp_ctx *ctx, int what, void *dst, int64_t bytes);
+
+/* ---- phase timing (benchmarks) -------------------------------------------- */
+enum {
+    NCORP_PHASE_KEYS = 0, NCORP_PHASE_SORT, NCORP_PHASE_TREE, NCORP_PHASE_GCLIMB,
+    NCORP_PHASE_GWALK, NCORP_PHASE_LISTS, NCORP_PHASE_M2L, NCORP_PHASE_DESCENT,
+    NCORP_PHASE_P2P, NCORP_PHASE_L2P, NCORP_PHASE_COLLIDE, NCORP_PHASE_INTEGRATE,
+    NCORP_PHASE_COUNT
+};
+/* enable != 0: every later call records a HIP event pair on its stream around each
+ * phase (the P2P phase is exactly one kernel launch).  Costs a few microseconds per
+ * phase; off by default. */
+int ncorp_set_timing(ncorp_ctx *ctx, int enable);
+/* Waits for the recorded events and adds, per phase, the elapsed milliseconds to
+ * ms[NCORP_PHASE_COUNT] and the number of recorded launches to count[...]; then
+ * forgets the records.  Either pointer may be NULL. */
+int ncorp_phase_times(ncorp_ctx *ctx, double *ms, int64_t *count);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,11 @@
 
 using namespace ncorp;
 
+struct PhaseRec {
+    int phase;
+    hipEvent_t a, b;
+};
+
 struct ncorp_ctx {
     ncorp_params prm;
     Workspace ws;
@@ -18,6 +23,41 @@ struct ncorp_ctx {
     int64_t n = 0;
     hipStream_t last = nullptr;
     char err[256];
+    // phase timing
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<PhaseRec> recs;
+    ~ncorp_ctx() {
+        for (auto &r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+        for (auto e : pool) hipEventDestroy(e);
+    }
+};
+
+// Records an event pair around one phase when timing is on.
+struct PhaseTimer {
+    ncorp_ctx *c;
+    hipStream_t s;
+    PhaseRec rec{};
+    bool on;
+    PhaseTimer(ncorp_ctx *c_, int phase, hipStream_t s_) : c(c_), s(s_), on(c_->timing) {
+        if (!on) return;
+        rec.phase = phase;
+        rec.a = take();
+        rec.b = take();
+        if (!rec.a || !rec.b) { on = false; return; }
+        hipEventRecord(rec.a, s);
+    }
+    hipEvent_t take() {
+        if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~PhaseTimer() {
+        if (!on) return;
+        hipEventRecord(rec.b, s);
+        c->recs.push_back(rec);
+    }
 };
 
 static int fail(ncorp_ctx *c, int code, const char *msg) {
@@ -221,15 +261,15 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
     if (((uintptr_t)workspace & 255u) != 0)
         return fail(c, NCORP_E_INVALID, "workspace must be 256-byte aligned");
     Workspace probe;
-    const int64_t fixed = layout_workspace(probe, c->prm, n, 1024);
+    const int64_t fixed = layout_workspace(probe, c->prm, n, 1);
     if (ws_bytes < fixed) {
         std::snprintf(c->err, sizeof(c->err), "workspace too small: %lld bytes needed for n=%lld",
                       (long long)fixed, (long long)n);
         return NCORP_E_INVALID;
     }
     // whatever is left beyond the fixed part holds colliding pairs (2 x 8 bytes each)
-    int64_t pc = 1024 + (ws_bytes - fixed) / 16;
-    while (layout_workspace(probe, c->prm, n, pc) > ws_bytes) pc -= 64;
+    int64_t pc = 1 + (ws_bytes - fixed) / 16;
+    while (pc > 1 && layout_workspace(probe, c->prm, n, pc) > ws_bytes) pc -= pc > 64 ? 64 : 1;
     Workspace ws;
     ws.base = (char *)workspace;
     layout_workspace(ws, c->prm, n, pc);
@@ -244,12 +284,21 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
 static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const double *z,
                            int64_t n, hipStream_t s, bool fresh) {
     Workspace &ws = c->ws;
-    if (fresh) HIPCHK(c, launch_reset_state(ws, s));
-    else HIPCHK(c, launch_reset_tree_counters(ws, s));
-    HIPCHK(c, launch_keys(ws, x, y, z, n, c->prm.root_half_width, s));
-    HIPCHK(c, launch_sort(ws, n, s));
-    HIPCHK(c, launch_gather_pos(ws, x, y, z, n, s));
-    HIPCHK(c, launch_build_tree(ws, n, c->prm.leaf_size, s));
+    {
+        PhaseTimer t(c, NCORP_PHASE_KEYS, s);
+        if (fresh) HIPCHK(c, launch_reset_state(ws, s));
+        else HIPCHK(c, launch_reset_tree_counters(ws, s));
+        HIPCHK(c, launch_keys(ws, x, y, z, n, c->prm.root_half_width, s));
+    }
+    {
+        PhaseTimer t(c, NCORP_PHASE_SORT, s);
+        HIPCHK(c, launch_sort(ws, n, s));
+    }
+    {
+        PhaseTimer t(c, NCORP_PHASE_TREE, s);
+        HIPCHK(c, launch_gather_pos(ws, x, y, z, n, s));
+        HIPCHK(c, launch_build_tree(ws, n, c->prm.leaf_size, s));
+    }
     c->have_tree = true;
     c->n = n;
     c->last = s;
@@ -276,14 +325,36 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
         HIPCHK(c, launch_fill_i64((int64_t *)az, 0, n, s));
         return NCORP_OK;
     }
-    HIPCHK(c, launch_gather_scaled(ws, m, c->prm.G, ws.mus, n, s));
-    HIPCHK(c, launch_gravity_climb(ws, n, c->prm, s));
-    HIPCHK(c, launch_walk(ws, 0, c->prm.ncs, c->prm.ncc_pre, c->prm.ncc_post, s));
-    HIPCHK(c, launch_build_lists(ws, 0, s));
-    HIPCHK(c, launch_m2l(ws, c->prm.p, c->prm.precision, s));
-    HIPCHK(c, launch_l2l(ws, c->prm.p, s));
-    HIPCHK(c, launch_p2p(ws, n, c->prm.precision, s));
-    HIPCHK(c, launch_l2p(ws, n, c->prm.p, ax, ay, az, s));
+    {
+        PhaseTimer t(c, NCORP_PHASE_GCLIMB, s);
+        HIPCHK(c, launch_gather_scaled(ws, m, c->prm.G, ws.mus, n, s));
+        HIPCHK(c, launch_gravity_climb(ws, n, c->prm, s));
+    }
+    {
+        PhaseTimer t(c, NCORP_PHASE_GWALK, s);
+        HIPCHK(c, launch_walk(ws, 0, c->prm.ncs, c->prm.ncc_pre, c->prm.ncc_post, s));
+    }
+    {
+        PhaseTimer t(c, NCORP_PHASE_LISTS, s);
+        HIPCHK(c, launch_build_lists(ws, 0, s));
+    }
+    {
+        PhaseTimer t(c, NCORP_PHASE_M2L, s);
+        HIPCHK(c, launch_m2l(ws, c->prm.p, c->prm.precision, s));
+    }
+    {
+        PhaseTimer t(c, NCORP_PHASE_DESCENT, s);
+        HIPCHK(c, launch_l2l(ws, c->prm.p, s));
+    }
+    {
+        PhaseTimer t(c, NCORP_PHASE_P2P, s);
+        HIPCHK(c, launch_p2p(ws, n, c->prm.precision, s));
+    }
+    {
+        PhaseTimer t(c, NCORP_PHASE_L2P, s);
+        HIPCHK(c, launch_l2p(ws, n, c->prm.p, ax, ay, az, s));
+    }
+    if (c->timing) HIPCHK(c, launch_count_interactions(ws, s));
     c->last = s;
     return NCORP_OK;
 }
@@ -301,6 +372,7 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
                         int64_t *n_pairs_dev, int triple, int step, hipStream_t s) {
     Workspace &ws = c->ws;
     const int64_t n = c->n;
+    PhaseTimer t(c, NCORP_PHASE_COLLIDE, s);
     HIPCHK(c, launch_gather(ws, vx, ws.vxs, n, s));
     HIPCHK(c, launch_gather(ws, vy, ws.vys, n, s));
     HIPCHK(c, launch_gather(ws, vz, ws.vzs, n, s));
@@ -353,15 +425,22 @@ extern "C" int ncorp_step(ncorp_ctx *c, double *x, double *y, double *z, double 
     if (r != NCORP_OK) return r;
     k_zero_cursor<<<1, 64, 0, s>>>(ws.st);
     if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
-    HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, 0.5 * dt,
-                          c->prm.G, c->prm.M_central, s));
+    {
+        PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
+        HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, 0.5 * dt,
+                              c->prm.G, c->prm.M_central, s));
+    }
     for (int k = 0; k < n_steps; k++) {
         r = collide_impl(c, vx, vy, vz, R, dt, pairs, cap, n_pairs_dev + k, 1, k, s);
         if (r != NCORP_OK) return r;
-        HIPCHK(c, launch_drift(x, y, z, vx, vy, vz, n, dt, s));
+        {
+            PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
+            HIPCHK(c, launch_drift(x, y, z, vx, vy, vz, n, dt, s));
+        }
         if ((r = build_tree_impl(c, x, y, z, n, s, false)) != NCORP_OK) return r;
         if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
         const double h = (k == n_steps - 1) ? 0.5 * dt : dt;
+        PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
         HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, h, c->prm.G,
                               c->prm.M_central, s));
     }
@@ -409,6 +488,31 @@ extern "C" int ncorp_tree_info(ncorp_ctx *c, int64_t *info) {
     info[NCORP_INFO_VISITED] = h.visited;
     info[NCORP_INFO_COL_CAND] = h.ncand;
     info[NCORP_INFO_COL_TESTS] = h.col_tests;
+    info[NCORP_INFO_M2L_DIR] = h.m2l_dir;
+    info[NCORP_INFO_P2P_INTER] = h.p2p_inter;
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_set_timing(ncorp_ctx *c, int enable) {
+    if (!c) return NCORP_E_INVALID;
+    c->timing = enable != 0;
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_phase_times(ncorp_ctx *c, double *ms, int64_t *count) {
+    if (!c) return NCORP_E_INVALID;
+    for (auto &r : c->recs) {
+        HIPCHK(c, hipEventSynchronize(r.b));
+        float t = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&t, r.a, r.b));
+        if (r.phase >= 0 && r.phase < NCORP_PHASE_COUNT) {
+            if (ms) ms[r.phase] += (double)t;
+            if (count) count[r.phase] += 1;
+        }
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+    }
+    c->recs.clear();
     return NCORP_OK;
 }
 

@@ -67,6 +67,7 @@ struct DevState {
     int64_t col_tests;
     int64_t npairs;            // colliding pairs found (may exceed capacity)
     int64_t pair_cursor;       // pairs already written by earlier steps of ncorp_step
+    int64_t p2p_inter;         // directed moonlet pairs (i != j) of the direct sums
 };
 
 // Work-queue state of a persistent walk.
@@ -158,6 +159,7 @@ hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hip
 hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post,
                        hipStream_t s);
 hipError_t launch_build_lists(const Workspace &ws, int mode, hipStream_t s);
+hipError_t launch_count_interactions(const Workspace &ws, hipStream_t s);
 
 hipError_t launch_m2l(const Workspace &ws, int p, int precision, hipStream_t s);
 hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s);

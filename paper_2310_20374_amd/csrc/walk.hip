@@ -392,6 +392,35 @@ k_sort_segments(const int32_t *n_dev, const int32_t *__restrict__ off, int32_t *
     }
 }
 
+// directed moonlet interactions of the direct sums: per leaf, its moonlets times
+// the moonlets of all its sources, minus the i == j terms
+__global__ void k_count_inter(DevState *st, const int32_t *__restrict__ ent_cell,
+                              const int32_t *__restrict__ c_count,
+                              const int32_t *__restrict__ p2p_off,
+                              const int32_t *__restrict__ p2p_src) {
+    if (st->status & kSkipMask) return;
+    const int K = st->nleaves;
+    unsigned long long tot = 0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
+        const int nt = c_count[ent_cell[e]];
+        long long srcs = 0;
+        for (int q = p2p_off[e]; q < p2p_off[e + 1]; q++) srcs += c_count[p2p_src[q]];
+        tot += (unsigned long long)(nt * srcs - nt);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+    if (threadIdx.x % kWave == 0 && tot) atomicAdd((unsigned long long *)&st->p2p_inter, tot);
+}
+
+__global__ void k_zero_inter(DevState *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->p2p_inter = 0;
+}
+
+hipError_t launch_count_interactions(const Workspace &ws, hipStream_t s) {
+    k_zero_inter<<<1, 64, 0, s>>>(ws.st);
+    k_count_inter<<<256, 256, 0, s>>>(ws.st, ws.ent_cell, ws.c_count, ws.p2p_off, ws.p2p_src);
+    return hipGetLastError();
+}
+
 static int grid_cap(int64_t n, int block, int cap) {
     int64_t g = (n + block - 1) / block;
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));

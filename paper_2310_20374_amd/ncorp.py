@@ -19,14 +19,17 @@ STATUS_NAMES = {0: "ok", -1: "invalid", -2: "capacity", -3: "hip", -4: "unsuppor
                 -5: "nonfinite"}
 
 INFO_FIELDS = ("n", "ncells", "nleaves", "maxlevel", "m2l", "p2p", "visited", "col_cand",
-               "col_tests")
+               "col_tests", "m2l_dir", "p2p_inter")
+PHASES = ("keys", "sort", "tree", "gclimb", "gwalk", "lists", "m2l", "descent", "p2p", "l2p",
+          "collide", "integrate")
 EXPORT = {"keys": 0, "perm": 1, "cells": 2, "gcells": 3, "ccells": 4, "multipoles": 5,
           "local": 6, "m2l": 7, "p2p": 8, "col_cand": 9}
 
 EXPORTED_SYMBOLS = ("ncorp_params_default", "ncorp_create", "ncorp_destroy",
                     "ncorp_workspace_bytes", "ncorp_build_tree", "ncorp_gravity",
                     "ncorp_collide", "ncorp_step", "ncorp_get_status", "ncorp_last_error",
-                    "ncorp_tree_info", "ncorp_export_host")
+                    "ncorp_tree_info", "ncorp_export_host", "ncorp_set_timing",
+                    "ncorp_phase_times")
 
 
 class Params(C.Structure):
@@ -90,6 +93,10 @@ def lib():
     L.ncorp_tree_info.restype = i32
     L.ncorp_export_host.argtypes = [vp, i32, vp, i64]
     L.ncorp_export_host.restype = i64
+    L.ncorp_set_timing.argtypes = [vp, i32]
+    L.ncorp_set_timing.restype = i32
+    L.ncorp_phase_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
+    L.ncorp_phase_times.restype = i32
     _lib = L
     return L
 
@@ -190,6 +197,16 @@ class Context:
         r, req, msg = self.get_status()
         if r != OK:
             raise NcorpError(r, f"{msg} (required {req})")
+
+    def set_timing(self, enable: bool = True):
+        self._check(lib().ncorp_set_timing(self.h, 1 if enable else 0), "ncorp_set_timing")
+
+    def phase_times(self):
+        """{phase: (milliseconds, launches)} accumulated since the last call."""
+        ms = (C.c_double * len(PHASES))()
+        cnt = (C.c_int64 * len(PHASES))()
+        self._check(lib().ncorp_phase_times(self.h, ms, cnt), "ncorp_phase_times")
+        return {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(PHASES)}
 
     def tree_info(self):
         arr = (C.c_int64 * len(INFO_FIELDS))()
