@@ -221,6 +221,8 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.cleaf = (double *)take(8 * (cell_cap < n ? cell_cap : n) * (ws.nl > 0 ? ws.nl : 1));
     ws.ccell = (double4 *)take(32 * cell_cap);
     ws.c_crmax = (double *)take(8 * cell_cap);
+    ws.wg = (WCell *)take(sizeof(WCell) * cell_cap);
+    ws.wc = (WCell *)take(sizeof(WCell) * cell_cap);
     ws.queue = (uint64_t *)take(8 * q_cap);
     ws.m2l = (int2 *)take(8 * m2l_cap);
     ws.p2p = (int2 *)take(8 * p2p_cap);

@@ -255,14 +255,38 @@ __device__ double theta_of_mass(double M, double Mroot, double tmin) {
 
 __global__ void k_rcrit(const DevState *__restrict__ st, const double *__restrict__ c_mass,
                         const double *__restrict__ c_rmax, double4 *gcell, double *c_theta,
-                        double theta_min, int theta_mode) {
+                        double theta_min, int theta_mode, const int32_t *__restrict__ c_count,
+                        const int32_t *__restrict__ c_child, const int32_t *__restrict__ c_nchild,
+                        WCell *__restrict__ wg) {
     const int nc = st->ncells;
-    if (nc <= 0) return;
+    if (nc <= 0 || (st->status & kSkipMask)) return;
     const double Mroot = c_mass[0];
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
         double th = theta_mode == 1 ? theta_min : theta_of_mass(c_mass[c], Mroot, theta_min);
         c_theta[c] = th;
-        gcell[c].w = c_rmax[c] / th;
+        const double rc = c_rmax[c] / th;
+        double4 g = gcell[c];
+        g.w = rc;
+        gcell[c] = g;
+        WCell w;
+        w.x = g.x; w.y = g.y; w.z = g.z; w.rcrit = rc;
+        w.count = c_count[c]; w.child = c_child[c]; w.nchild = c_nchild[c]; w.pad = 0;
+        wg[c] = w;
+    }
+}
+
+__global__ void k_pack_collision(const DevState *__restrict__ st, const double4 *__restrict__ ccell,
+                                 const int32_t *__restrict__ c_count,
+                                 const int32_t *__restrict__ c_child,
+                                 const int32_t *__restrict__ c_nchild, WCell *__restrict__ wc) {
+    const int nc = st->ncells;
+    if (st->status & kSkipMask) return;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+        const double4 g = ccell[c];
+        WCell w;
+        w.x = g.x; w.y = g.y; w.z = g.z; w.rcrit = g.w;
+        w.count = c_count[c]; w.child = c_child[c]; w.nchild = c_nchild[c]; w.pad = 0;
+        wc[c] = w;
     }
 }
 
@@ -300,7 +324,8 @@ hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_para
         default: launch_gc<6>(ws, s); break;
     }
     k_rcrit<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_mass, ws.c_rmax, ws.gcell,
-                                                        ws.c_theta, prm.theta_min, prm.theta_mode);
+                                                        ws.c_theta, prm.theta_min, prm.theta_mode,
+                                                        ws.c_count, ws.c_child, ws.c_nchild, ws.wg);
     return hipGetLastError();
 }
 
@@ -382,6 +407,8 @@ hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hip
         ws.st, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, dt, ws.ent_cell, ws.c_level,
         ws.c_first, ws.c_count, ws.c_child, ws.c_nchild, ws.c_parent, ws.c_arrive, ws.ccell,
         ws.c_crmax);
+    k_pack_collision<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.ccell, ws.c_count,
+                                                                 ws.c_child, ws.c_nchild, ws.wc);
     return hipGetLastError();
 }
 

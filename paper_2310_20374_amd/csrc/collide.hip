@@ -32,7 +32,14 @@ __device__ __forceinline__ void record(int64_t *out, int64_t cap, unsigned long 
     if ((int64_t)k < cap) out[k] = ((int64_t)lo << 32) | (int64_t)hi;
 }
 
-// one wave per candidate cell pair
+// One wave per candidate cell pair.  B's moonlets are staged in LDS 64 at a time;
+// A's moonlets sit on the lanes, and when A has fewer than 64 the lanes split
+// B's moonlets into groups.  In a self pair only j > i is tested.
+struct PState {
+    double x, y, z, vx, vy, vz, R;
+    uint32_t id;
+};
+
 __global__ void __launch_bounds__(64)
 k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
           const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
@@ -41,6 +48,7 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
           const double *__restrict__ vys, const double *__restrict__ vzs,
           const double *__restrict__ rads, const uint32_t *__restrict__ perm, double dt,
           int64_t *out, int64_t cap) {
+    __shared__ PState sb[64];
     if (st->status & kSkipMask) return;
     int nc = st->ncand;
     if (nc > cand_cap) nc = (int)cand_cap;
@@ -52,18 +60,39 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
         const int fb = c_first[pr.y], nb = c_count[pr.y];
         const bool self = pr.x == pr.y;
         for (int a0 = 0; a0 < na; a0 += 64) {
-            const int ia = a0 + lane;
-            if (ia >= na) continue;
+            const int nac = na - a0 < 64 ? na - a0 : 64;
+            int S = 1;
+            while (S < nac) S <<= 1;
+            const int G = 64 / S, tl = lane % S, grp = lane / S;
+            const bool act = tl < nac;
+            const int ia = a0 + (act ? tl : 0);
             const int a = fa + ia;
             const double x1 = xs[a], y1 = ys[a], z1 = zs[a], vx1 = vxs[a], vy1 = vys[a],
                          vz1 = vzs[a], R1 = rads[a];
-            const int jb0 = self ? ia + 1 : 0;
-            for (int jb = jb0; jb < nb; jb++) {
-                const int b = fb + jb;
-                tests++;
-                if (pair_test(x1, y1, z1, vx1, vy1, vz1, R1, xs[b], ys[b], zs[b], vxs[b], vys[b],
-                              vzs[b], rads[b], dt))
-                    record(out, cap, (unsigned long long *)&st->npairs, perm[a], perm[b]);
+            const uint32_t id1 = perm[a];
+            for (int b0 = self ? a0 : 0; b0 < nb; b0 += 64) {
+                const int nbc = nb - b0 < 64 ? nb - b0 : 64;
+                __syncthreads();
+                if (lane < nbc) {
+                    const int b = fb + b0 + lane;
+                    PState ps;
+                    ps.x = xs[b]; ps.y = ys[b]; ps.z = zs[b];
+                    ps.vx = vxs[b]; ps.vy = vys[b]; ps.vz = vzs[b]; ps.R = rads[b];
+                    ps.id = perm[b];
+                    sb[lane] = ps;
+                }
+                __syncthreads();
+                if (!act) continue;
+                const int jlo = self ? (ia + 1 - b0 > 0 ? ia + 1 - b0 : 0) : 0;
+                // first j >= jlo with j = grp (mod G)
+                int j = jlo + ((grp - jlo % G) % G + G) % G;
+                for (; j < nbc; j += G) {
+                    const PState &o = sb[j];
+                    tests++;
+                    if (pair_test(x1, y1, z1, vx1, vy1, vz1, R1, o.x, o.y, o.z, o.vx, o.vy, o.vz,
+                                  o.R, dt))
+                        record(out, cap, (unsigned long long *)&st->npairs, id1, o.id);
+                }
             }
         }
     }

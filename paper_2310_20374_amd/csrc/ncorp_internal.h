@@ -70,13 +70,23 @@ struct DevState {
     int64_t p2p_inter;         // directed moonlet pairs (i != j) of the direct sums
 };
 
-// Work-queue state of a persistent walk.
+// Work-queue state of a persistent walk; each counter on its own 128-byte line.
 struct WalkQueue {
     uint64_t head;             // next slot to claim
+    uint64_t pad0[15];
     uint64_t tail;             // next slot to reserve
-    uint64_t done;             // items fully processed
+    uint64_t pad1[15];
+    int64_t outstanding;       // items pushed and not yet processed
+    uint64_t pad2[15];
     uint32_t epoch;            // tag of valid items in this walk
-    uint32_t pad;
+    uint32_t pad3[31];
+};
+
+// What the walk reads of a cell, packed: centre, critical radius, moonlet count,
+// first child and number of children (0 for a leaf).
+struct alignas(16) WCell {
+    double x, y, z, rcrit;
+    int32_t count, child, nchild, pad;
 };
 
 // ---------------------------------------------------------------- workspace
@@ -112,6 +122,7 @@ struct Workspace {
     double *local = nullptr;                          // cell_cap x nl (C after walk)
     double *cleaf = nullptr;                          // n_max x nl (C at each leaf)
     double4 *ccell = nullptr;                         // sbar, r_crit (collisions)
+    WCell *wg = nullptr, *wc = nullptr;               // walk records: gravity, collisions
     double *c_crmax = nullptr;
     // walks
     uint64_t *queue = nullptr;

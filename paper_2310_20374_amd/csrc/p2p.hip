@@ -7,9 +7,9 @@
 // formed directly per leaf (shifts compose exactly), so no pass waits on another.
 //
 // Evaluation: one wave per leaf.  Its sources (every cell the walk paired with
-// the leaf or one of its ancestors for a direct sum) are streamed through LDS 64
-// moonlets at a time; leaves with fewer than 64 moonlets split each tile over
-// lane groups.  In the FP32-bulk form offsets from the leaf centre are formed in
+// the leaf or one of its ancestors for a direct sum) are prefix-summed into one
+// flat range and streamed through LDS 256 moonlets at a time; leaves with fewer
+// than 64 moonlets split each tile over lane groups.  In the FP32-bulk form offsets from the leaf centre are formed in
 // FP64 and rounded, each source tile is summed in FP32, and the tile sums are
 // added with Kahan compensation.  The leaf's C tensors then give
 // a_i += sum_{|b| <= p-1} C_{e+b}(s_leaf) (x_i - s_leaf)^b / b!.
@@ -128,12 +128,35 @@ template <> struct Acc3<float> {
     }
 };
 
+__device__ __forceinline__ int wave_excl_sum_p(int v, int lane, int &total) {
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int t = __shfl_up(x, o);
+        if (lane >= o) x += t;
+    }
+    total = __shfl(x, kWave - 1);
+    return x - v;
+}
+
 template <typename T> __device__ __forceinline__ T rsq(T v);
 template <> __device__ __forceinline__ double rsq<double>(double v) { return rsqrt(v); }
 template <> __device__ __forceinline__ float rsq<float>(float v) { return rsqrtf(v); }
 template <typename T> __device__ __forceinline__ T fmat(T a, T b, T c);
 template <> __device__ __forceinline__ double fmat<double>(double a, double b, double c) { return fma(a, b, c); }
 template <> __device__ __forceinline__ float fmat<float>(float a, float b, float c) { return fmaf(a, b, c); }
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+// r^2 floor: a moonlet meets itself (dx = 0) in its own leaf; the floor keeps
+// 1/r^3 finite there so the term is exactly 0, and is far below any pair distance
+template <typename T> __device__ __forceinline__ T r2_floor();
+template <> __device__ __forceinline__ float r2_floor<float>() { return 1e-24f; }
+template <> __device__ __forceinline__ double r2_floor<double>() { return 1e-200; }
+
+constexpr int kP2PTile = 256;       // source moonlets staged per LDS tile
+constexpr int kP2PSrc = 256;        // source cells per batch (prefix sums in LDS)
 
 template <typename T>
 __global__ void __launch_bounds__(64)
@@ -143,10 +166,13 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
       const double4 *__restrict__ gcell, const int32_t *__restrict__ p2p_off,
       const int32_t *__restrict__ p2p_src, double *__restrict__ acc_s, int64_t n) {
-    __shared__ T sx[64], sy[64], sz[64], sm[64];
+    using V = typename Vec4<T>::type;
+    __shared__ V tile[kP2PTile];
+    __shared__ int32_t s_first[kP2PSrc], s_pref[kP2PSrc + 1];
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     const int lane = threadIdx.x;
+    const T floor2 = r2_floor<T>();
     for (int e = blockIdx.x; e < K; e += gridDim.x) {
         const int c = ent_cell[e];
         const int f = c_first[c], nt = c_count[c];
@@ -161,31 +187,71 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
             const int i = f + t0 + (act ? tl : 0);
             const T xi = (T)(xs[i] - g.x), yi = (T)(ys[i] - g.y), zi = (T)(zs[i] - g.z);
             Acc3<T> acc;
-            for (int q = s0; q < s1; q++) {
-                const int B = p2p_src[q];
-                const int bf = c_first[B], bn = c_count[B];
-                for (int j0 = 0; j0 < bn; j0 += 64) {
-                    const int nj = bn - j0 < 64 ? bn - j0 : 64;
-                    __syncthreads();
-                    if (lane < nj) {
-                        const int j = bf + j0 + lane;
-                        sx[lane] = (T)(xs[j] - g.x);
-                        sy[lane] = (T)(ys[j] - g.y);
-                        sz[lane] = (T)(zs[j] - g.z);
-                        sm[lane] = (T)mus[j];
+            for (int sb = s0; sb < s1; sb += kP2PSrc) {
+                const int nsb = s1 - sb < kP2PSrc ? s1 - sb : kP2PSrc;
+                __syncthreads();
+                // particle ranges of this batch of source cells, prefix-summed
+                int cnt4[4], run = 0;
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int q = 4 * lane + k;
+                    int cf = 0, cn = 0;
+                    if (q < nsb) {
+                        const int B = p2p_src[sb + q];
+                        cf = c_first[B];
+                        cn = c_count[B];
+                    }
+                    if (q < kP2PSrc) s_first[q] = cf;
+                    cnt4[k] = cn;
+                    run += cn;
+                }
+                int tot;
+                int ex = wave_excl_sum_p(run, lane, tot);
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    s_pref[4 * lane + k] = ex;
+                    ex += cnt4[k];
+                }
+                if (lane == 0) s_pref[kP2PSrc] = tot;
+                __syncthreads();
+                for (int p0 = 0; p0 < tot; p0 += kP2PTile) {
+                    const int nj = tot - p0 < kP2PTile ? tot - p0 : kP2PTile;
+                    // stage the tile: source moonlet q of the batch -> its cell by
+                    // binary search over the prefix sums
+#pragma unroll
+                    for (int k = 0; k < kP2PTile / 64; k++) {
+                        const int q = p0 + lane + 64 * k;
+                        if (q < tot) {
+                            int lo = 0, hi = nsb;          // s_pref[lo] <= q < s_pref[hi]
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (s_pref[mid] <= q) lo = mid; else hi = mid;
+                            }
+                            const int j = s_first[lo] + (q - s_pref[lo]);
+                            V v;
+                            v.x = (T)(xs[j] - g.x);
+                            v.y = (T)(ys[j] - g.y);
+                            v.z = (T)(zs[j] - g.z);
+                            v.w = (T)mus[j];
+                            tile[lane + 64 * k] = v;
+                        }
                     }
                     __syncthreads();
                     T px = 0, py = 0, pz = 0;
+#pragma unroll 4
                     for (int j = grp; j < nj; j += G) {
-                        const T dx = sx[j] - xi, dy = sy[j] - yi, dz = sz[j] - zi;
-                        const T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, dx * dx));
+                        const V v = tile[j];
+                        const T dx = v.x - xi, dy = v.y - yi, dz = v.z - zi;
+                        T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, dx * dx));
+                        r2 = r2 > floor2 ? r2 : floor2;
                         const T rinv = rsq<T>(r2);
-                        const T w = r2 > (T)0 ? sm[j] * rinv * rinv * rinv : (T)0;
+                        const T w = v.w * (rinv * rinv) * rinv;
                         px = fmat<T>(dx, w, px);
                         py = fmat<T>(dy, w, py);
                         pz = fmat<T>(dz, w, pz);
                     }
                     acc.add_tile(px, py, pz);
+                    __syncthreads();
                 }
             }
             double ox, oy, oz;
@@ -201,7 +267,6 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
                 acc_s[2 * n + i] = oz;
             }
         }
-        __syncthreads();
     }
 }
 

@@ -5,8 +5,9 @@
 // slots, polls them until their items appear, classifies each pair exactly as
 // Alg. 2 does (self pair / brute force before the opening test / well separated /
 // brute force after it / split the cell with the larger critical radius) and
-// pushes the child pairs with one wave-aggregated atomic.  The walk is over when
-// every reserved slot has been processed (done == tail): no more work can appear.
+// pushes the child pairs with one wave-aggregated atomic.  A single signed counter
+// of outstanding items (children added and processed items retired in the same
+// atomic) says when the walk is over: at zero no item exists and none can appear.
 // A wave that polls for too long without progress latches ST_WALK_STALL and
 // leaves, so the kernel always ends.
 //
@@ -18,13 +19,14 @@
 namespace ncorp {
 
 constexpr int kWalkBlock = 256;
-constexpr uint64_t kSpinLimit = 1ull << 22;
+constexpr int kWalkGrid = 256;                 // 1024 persistent waves: 4 per CU
+constexpr uint64_t kSpinLimit = 1ull << 20;    // empty polls in a row before giving up
 
 __device__ __forceinline__ uint64_t make_item(uint32_t epoch, int a, int b) {
     return ((uint64_t)(epoch & 0xffffu) << 48) | ((uint64_t)(uint32_t)a << 24) | (uint32_t)b;
 }
 
-__device__ __forceinline__ uint64_t ld_acq(const uint64_t *p) {
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -44,7 +46,6 @@ __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, uint32
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int nc = st->ncells;
     wq->head = 0;
-    wq->done = 0;
     wq->epoch = epoch;
     if (mode == 0) { st->nm2l = 0; st->np2p = 0; st->visited = 0; }
     else { st->ncand = 0; }
@@ -52,8 +53,10 @@ __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, uint32
         __hip_atomic_store(&queue[0], make_item(epoch, 0, 0), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         wq->tail = 1;
+        wq->outstanding = 1;
     } else {
         wq->tail = 0;
+        wq->outstanding = 0;
     }
 }
 
@@ -62,24 +65,44 @@ struct WalkArgs {
     WalkQueue *wq;
     uint64_t *queue;
     int64_t qcap;
-    const int32_t *count, *child, *nchild;
-    const double4 *cell;                 // centre and critical radius
+    const WCell *cell;
     int ncs, ncc_pre, ncc_post;
     int2 *m2l, *p2p;                     // outputs (p2p = candidates in collision mode)
     int64_t m2l_cap, p2p_cap;
     int32_t *nm2l, *np2p;
     uint32_t epoch;
-    int ncells;                          // read by k_walk from the device state
 };
+
+// Appends the lanes' flagged pairs to a list with one atomic per wave.
+__device__ __forceinline__ void emit(bool flag, int a, int b, int lane, int32_t *count,
+                                     int2 *list, int64_t cap, DevState *st, int32_t bit) {
+    const uint64_t m = __ballot(flag);
+    if (!m) return;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int32_t b0 = 0;
+    if (lane == 0) b0 = atomicAdd(count, (int32_t)__popcll(m));
+    b0 = __shfl(b0, 0);
+    if (flag) {
+        const int64_t k = (int64_t)b0 + __popcll(m & lt);
+        if (k < cap) list[k] = make_int2(a, b);
+    }
+    if (lane == 0 && (int64_t)b0 + __popcll(m) > cap) {
+        atomicOr(&st->status, bit);
+        atomicMax((unsigned long long *)&st->required,
+                  (unsigned long long)((int64_t)b0 + __popcll(m)));
+    }
+}
 
 template <int MODE>
 __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
     const int lane = threadIdx.x % kWave;
     WalkQueue *wq = A.wq;
     const int ncells = A.st->ncells;
+    const uint32_t tag = A.epoch & 0xffffu;
     uint64_t spins = 0;
     int64_t visited = 0;
-    while (true) {
+    bool finished = false;
+    while (!finished) {
         uint64_t base = 0;
         if (lane == 0) base = atomicAdd((unsigned long long *)&wq->head, (unsigned long long)kWave);
         base = __shfl(base, 0);
@@ -87,85 +110,99 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
         if (base >= (uint64_t)A.qcap) break;
         const uint64_t slot = base + lane;
         bool pending = slot < (uint64_t)A.qcap;
-        bool finished = false;
         while (__any(pending)) {
             uint64_t item = 0;
-            bool valid = false;
-            if (pending) {
-                item = ld_acq(&A.queue[slot]);
-                valid = (uint32_t)(item >> 48) == (A.epoch & 0xffffu);
+            if (pending) item = ld_relaxed(&A.queue[slot]);
+            const bool valid = pending && (uint32_t)(item >> 48) == tag;
+            if (!__any(valid)) {
+                // nothing arrived: the walk is over once no pushed item is left
+                int64_t o = 0;
+                if (lane == 0)
+                    o = __hip_atomic_load(&wq->outstanding, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                o = __shfl(o, 0);
+                if (o <= 0) { finished = true; break; }
+                if (++spins > kSpinLimit) {
+                    if (lane == 0) atomicOr(&A.st->status, (int32_t)ST_WALK_STALL);
+                    finished = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+                continue;
             }
+            spins = 0;
             // ---------------- classify the pair (Alg. 2)
-            int na = 0, nb = 0, ca = 0, cb = 0, kind = 0;   // kind: 0 none, 1 m2l, 2 p2p
-            int npush = 0, split = 0;                         // split: 1 self, 2 A, 3 B
-            int a = 0, b = 0;
+            int kind = 0;                       // 0 none, 1 well separated, 2 direct sum
+            int npush = 0, split = 0;           // split: 1 self, 2 A, 3 B
+            int a = 0, b = 0, na = 0, nb = 0, ca = 0, cb = 0;
             if (valid) {
                 a = (int)((item >> 24) & 0xffffffu);
                 b = (int)(item & 0xffffffu);
-                if (a >= ncells || b >= ncells) {          // cannot happen; never follow it
+                if (a >= ncells || b >= ncells) {       // cannot happen; never follow it
                     atomicOr(&A.st->status, (int32_t)ST_BAD_ITEM);
                     a = b = 0;
                 }
-                na = A.nchild[a];
-                int Na = A.count[a];
+                const WCell wa = A.cell[a];
+                na = wa.nchild;
+                ca = wa.child;
                 if (a == b) {
-                    if (Na <= A.ncs || na == 0) kind = 2;
-                    else { split = 1; npush = na * (na + 1) / 2; ca = A.child[a]; }
+                    if (wa.count <= A.ncs || na == 0) kind = 2;
+                    else { split = 1; npush = na * (na + 1) / 2; }
                 } else {
-                    nb = A.nchild[b];
-                    int Nb = A.count[b];
-                    int64_t prod = (int64_t)Na * (int64_t)Nb;
+                    const WCell wb = A.cell[b];
+                    nb = wb.nchild;
+                    cb = wb.child;
+                    const int64_t prod = (int64_t)wa.count * (int64_t)wb.count;
                     if (prod < (int64_t)A.ncc_pre) {
                         kind = 2;
                     } else {
-                        double4 ga = A.cell[a], gb = A.cell[b];
-                        double dx = ga.x - gb.x, dy = ga.y - gb.y, dz = ga.z - gb.z;
-                        double d = sqrt(dx * dx + dy * dy + dz * dz);
-                        if (ga.w + gb.w <= d) {
+                        const double dx = wa.x - wb.x, dy = wa.y - wb.y, dz = wa.z - wb.z;
+                        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                        if (wa.rcrit + wb.rcrit <= d) {
                             kind = MODE == 0 ? 1 : 0;          // collisions: nothing
                         } else if (prod < (int64_t)A.ncc_post || (na == 0 && nb == 0)) {
                             kind = 2;
-                        } else if (nb == 0 || (na != 0 && ga.w > gb.w)) {
-                            split = 2; npush = na; ca = A.child[a];
+                        } else if (nb == 0 || (na != 0 && wa.rcrit > wb.rcrit)) {
+                            split = 2; npush = na;
                         } else {
-                            split = 3; npush = nb; cb = A.child[b];
+                            split = 3; npush = nb;
                         }
                     }
                 }
             }
-            // ---------------- push children
+            // ---------------- push children (one reservation per wave)
             int tot_push;
-            int off = wave_excl_sum(npush, lane, tot_push);
-            int dropped = 0;
+            const int off = wave_excl_sum(npush, lane, tot_push);
+            int written = 0;
             if (tot_push > 0) {
                 uint64_t pbase = 0;
                 if (lane == 0)
                     pbase = atomicAdd((unsigned long long *)&wq->tail, (unsigned long long)tot_push);
                 pbase = __shfl(pbase, 0);
-                uint64_t my = pbase + (uint64_t)off;
+                const uint64_t my = pbase + (uint64_t)off;
                 int j = 0;
                 if (split == 1) {
                     for (int x = 0; x < na; x++)
-                        for (int y = x; y < na; y++, j++) {
-                            if (my + j < (uint64_t)A.qcap)
+                        for (int y = x; y < na; y++, j++)
+                            if (my + j < (uint64_t)A.qcap) {
                                 __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, ca + x, ca + y),
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            else dropped++;
-                        }
+                                written++;
+                            }
                 } else if (split == 2) {
-                    for (; j < na; j++) {
-                        if (my + j < (uint64_t)A.qcap)
+                    for (; j < na; j++)
+                        if (my + j < (uint64_t)A.qcap) {
                             __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, ca + j, b),
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        else dropped++;
-                    }
+                            written++;
+                        }
                 } else if (split == 3) {
-                    for (; j < nb; j++) {
-                        if (my + j < (uint64_t)A.qcap)
+                    for (; j < nb; j++)
+                        if (my + j < (uint64_t)A.qcap) {
                             __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, a, cb + j),
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        else dropped++;
-                    }
+                            written++;
+                        }
                 }
                 if (pbase + (uint64_t)tot_push > (uint64_t)A.qcap && lane == 0) {
                     atomicOr(&A.st->status, (int32_t)ST_CAP_QUEUE);
@@ -173,74 +210,22 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
                               (unsigned long long)(pbase + tot_push));
                 }
             }
-            // ---------------- emit interaction lists
-            {
-                uint64_t mm = __ballot(kind == 1), mp = __ballot(kind == 2);
-                uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-                if (mm) {
-                    int32_t b0 = 0;
-                    if (lane == 0) b0 = atomicAdd(A.nm2l, (int32_t)__popcll(mm));
-                    b0 = __shfl(b0, 0);
-                    if (kind == 1) {
-                        int64_t k = (int64_t)b0 + __popcll(mm & lt);
-                        if (k < A.m2l_cap) A.m2l[k] = make_int2(a, b);
-                    }
-                    if (lane == 0 && (int64_t)b0 + __popcll(mm) > A.m2l_cap) {
-                        atomicOr(&A.st->status, (int32_t)ST_CAP_M2L);
-                        atomicMax((unsigned long long *)&A.st->required,
-                                  (unsigned long long)((int64_t)b0 + __popcll(mm)));
-                    }
-                }
-                if (mp) {
-                    int32_t b0 = 0;
-                    if (lane == 0) b0 = atomicAdd(A.np2p, (int32_t)__popcll(mp));
-                    b0 = __shfl(b0, 0);
-                    if (kind == 2) {
-                        int64_t k = (int64_t)b0 + __popcll(mp & lt);
-                        if (k < A.p2p_cap) A.p2p[k] = make_int2(a, b);
-                    }
-                    if (lane == 0 && (int64_t)b0 + __popcll(mp) > A.p2p_cap) {
-                        atomicOr(&A.st->status, (int32_t)ST_CAP_P2P);
-                        atomicMax((unsigned long long *)&A.st->required,
-                                  (unsigned long long)((int64_t)b0 + __popcll(mp)));
-                    }
-                }
-            }
-            // ---------------- account processed items (after their children exist)
-            int nproc = __popcll(__ballot(valid));
-            int ndrop = dropped;
+            // ---------------- interaction lists
+            if (MODE == 0) emit(kind == 1, a, b, lane, A.nm2l, A.m2l, A.m2l_cap, A.st, ST_CAP_M2L);
+            emit(kind == 2, a, b, lane, A.np2p, A.p2p, A.p2p_cap, A.st, ST_CAP_P2P);
+            // ---------------- retire: children in, processed items out, one atomic
+            const int nproc = __popcll(__ballot(valid));
+            int wsum = written;
 #pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) ndrop += __shfl_xor(ndrop, o);
-            if (nproc + ndrop > 0) {
-                __threadfence();
-                if (lane == 0)
-                    atomicAdd((unsigned long long *)&wq->done, (unsigned long long)(nproc + ndrop));
-                visited += nproc;
-                spins = 0;
-            }
+            for (int o = kWave / 2; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
+            if (lane == 0)
+                atomicAdd((unsigned long long *)&wq->outstanding,
+                          (unsigned long long)(int64_t)(wsum - nproc));
+            visited += nproc;
             pending = pending && !valid;
-            if (__any(pending)) {
-                // termination: read done before tail; equal means nothing can appear.
-                // Lane 0 reads and broadcasts so the wave decides as one.
-                uint64_t d = 0, t = 1;
-                if (lane == 0) {
-                    d = ld_acq(&wq->done);
-                    t = ld_acq(&wq->tail);
-                }
-                d = __shfl(d, 0);
-                t = __shfl(t, 0);
-                if (d == t) { finished = true; break; }
-                if (++spins > kSpinLimit) {
-                    if (lane == 0) atomicOr(&A.st->status, (int32_t)ST_WALK_STALL);
-                    finished = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
         }
-        if (finished) break;
     }
-    if (lane == 0 && MODE == 0 && visited)
+    if (lane == 0 && visited)
         atomicAdd((unsigned long long *)&A.st->visited, (unsigned long long)visited);
 }
 
@@ -255,19 +240,18 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
     k_walk_init<<<1, 64, 0, s>>>(ws.st, ws.wq, ws.queue, ws.epoch, mode);
     WalkArgs A;
     A.st = ws.st; A.wq = ws.wq; A.queue = ws.queue; A.qcap = ws.queue_cap;
-    A.count = ws.c_count; A.child = ws.c_child; A.nchild = ws.c_nchild;
     A.ncs = ncs; A.ncc_pre = ncc_pre; A.ncc_post = ncc_post;
     A.epoch = ws.epoch;
     if (mode == 0) {
-        A.cell = ws.gcell;
+        A.cell = ws.wg;
         A.m2l = ws.m2l; A.m2l_cap = ws.m2l_cap; A.nm2l = &ws.st->nm2l;
         A.p2p = ws.p2p; A.p2p_cap = ws.p2p_cap; A.np2p = &ws.st->np2p;
-        k_walk<0><<<1024, kWalkBlock, 0, s>>>(A);
+        k_walk<0><<<kWalkGrid, kWalkBlock, 0, s>>>(A);
     } else {
-        A.cell = ws.ccell;
+        A.cell = ws.wc;
         A.m2l = ws.m2l; A.m2l_cap = 0; A.nm2l = &ws.st->nm2l;
         A.p2p = ws.cand; A.p2p_cap = ws.p2p_cap; A.np2p = &ws.st->ncand;
-        k_walk<1><<<1024, kWalkBlock, 0, s>>>(A);
+        k_walk<1><<<kWalkGrid, kWalkBlock, 0, s>>>(A);
     }
     return hipGetLastError();
 }
