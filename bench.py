@@ -48,8 +48,8 @@ def _run(nc, prm, d, dt, steps, warmup, timing, device):
 
     if warmup > 0:
         go(warmup)
-    torch.cuda.synchronize()
-    ctx.check_status()
+        torch.cuda.synchronize()
+        ctx.check_status()
     reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -136,10 +136,13 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--samples", type=int, default=4096)
-    ap.add_argument("--cpu-sample", type=int, default=150_000)
+    ap.add_argument("--cpu-sample", type=int, default=400_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (three times) and exit: the "
+                         "reference kernel for scaling the FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -148,6 +151,16 @@ def main():
 
     import numpy as np  # noqa: F401
     import torch
+
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes}))
+        return 0
 
     from paper_2310_20374_amd import inputs, ncorp
     device = "cuda:0"

@@ -70,6 +70,11 @@ typedef struct {
     int64_t m2l_capacity;      /* well-separated cell pairs of one walk */
     int64_t p2p_capacity;      /* cell pairs treated by direct sums in one walk */
     int64_t queue_capacity;    /* cell pairs visited by one walk */
+    /* per-target interaction lists, filled by the gravity walk itself; 0 = automatic
+     * (512 and 1024), at most 8192 each.  A target with more entries makes the call
+     * fail with NCORP_E_CAPACITY, required = the count that would have fitted. */
+    int32_t m2l_per_cell;      /* well-separated partner cells kept per cell */
+    int32_t p2p_per_leaf;      /* direct-sum source cells kept per leaf */
 } ncorp_params;
 
 typedef struct ncorp_ctx ncorp_ctx;
@@ -177,7 +182,7 @@ int64_t ncorp_export_host(ncorp_ctx *ctx, int what, void *dst, int64_t bytes);
 /* ---- phase timing (benchmarks) -------------------------------------------- */
 enum {
     NCORP_PHASE_KEYS = 0, NCORP_PHASE_SORT, NCORP_PHASE_TREE, NCORP_PHASE_GCLIMB,
-    NCORP_PHASE_GWALK, NCORP_PHASE_LISTS, NCORP_PHASE_M2L, NCORP_PHASE_DESCENT,
+    NCORP_PHASE_GWALK, NCORP_PHASE_M2L, NCORP_PHASE_DESCENT,
     NCORP_PHASE_P2P, NCORP_PHASE_L2P, NCORP_PHASE_COLLIDE, NCORP_PHASE_INTEGRATE,
     NCORP_PHASE_COUNT
 };

@@ -111,6 +111,11 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
         p->queue_capacity < 0) {
         std::snprintf(why, len, "capacities must be >= 0"); return false;
     }
+    if (p->m2l_per_cell < 0 || p->m2l_per_cell > kMaxPerTarget || p->p2p_per_leaf < 0 ||
+        p->p2p_per_leaf > kMaxPerTarget) {
+        std::snprintf(why, len, "m2l_per_cell and p2p_per_leaf must be in 0..%d", kMaxPerTarget);
+        return false;
+    }
     return true;
 }
 
@@ -167,8 +172,9 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.m2l_cap = m2l_cap;
     ws.p2p_cap = p2p_cap;
     ws.queue_cap = q_cap;
-    ws.m2l_dir_cap = 2 * m2l_cap;
-    ws.p2p_dir_cap = 4 * p2p_cap + n;
+    ws.leaf_cap = cell_cap < n ? cell_cap : n;
+    ws.m2l_stride = prm.m2l_per_cell > 0 ? prm.m2l_per_cell : kDefaultM2LPerCell;
+    ws.p2p_stride = prm.p2p_per_leaf > 0 ? prm.p2p_per_leaf : kDefaultP2PPerLeaf;
     ws.pair_cap = pair_cap < 1 ? 1 : pair_cap;
     ws.p = prm.p;
     ws.nm = n_mult(prm.p);
@@ -218,7 +224,7 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.mult = (double *)take(8 * cell_cap * (ws.nm > 0 ? ws.nm : 1));
     ws.mult32 = (float *)take(4 * cell_cap * (ws.nm > 0 ? ws.nm : 1));
     ws.local = (double *)take(8 * cell_cap * (ws.nl > 0 ? ws.nl : 1));
-    ws.cleaf = (double *)take(8 * (cell_cap < n ? cell_cap : n) * (ws.nl > 0 ? ws.nl : 1));
+    ws.cleaf = (double *)take(8 * ws.leaf_cap * (ws.nl > 0 ? ws.nl : 1));
     ws.ccell = (double4 *)take(32 * cell_cap);
     ws.c_crmax = (double *)take(8 * cell_cap);
     ws.wg = (WCell *)take(sizeof(WCell) * cell_cap);
@@ -227,15 +233,14 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.m2l = (int2 *)take(8 * m2l_cap);
     ws.p2p = (int2 *)take(8 * p2p_cap);
     ws.cand = (int2 *)take(8 * p2p_cap);
-    ws.m2l_off = (int32_t *)take(4 * (cell_cap + 1));
-    ws.m2l_src = (int32_t *)take(4 * ws.m2l_dir_cap);
-    ws.p2p_off = (int32_t *)take(4 * (n + 1));
-    ws.p2p_src = (int32_t *)take(4 * ws.p2p_dir_cap);
-    int64_t cnt = (cell_cap > n ? cell_cap : n) + 1;
-    if (cnt < nb * (kMaxDepth + 1) + 1) cnt = nb * (kMaxDepth + 1) + 1;
+    if (ws.p > 0) {
+        ws.m2l_cnt = (int32_t *)take(4 * cell_cap);
+        ws.m2l_seg = (int32_t *)take(4 * cell_cap * (int64_t)ws.m2l_stride);
+        ws.p2p_cnt = (int32_t *)take(4 * ws.leaf_cap);
+        ws.p2p_seg = (int32_t *)take(4 * ws.leaf_cap * (int64_t)ws.p2p_stride);
+    }
+    const int64_t cnt = nb * (kMaxDepth + 1) + 1;
     ws.cnt_a = (int32_t *)take(4 * cnt);
-    ws.cnt_b = (int32_t *)take(4 * cnt);
-    ws.cnt_tmp = (int32_t *)take(4 * (ws.m2l_dir_cap > ws.p2p_dir_cap ? ws.m2l_dir_cap : ws.p2p_dir_cap));
     ws.scan_part = (int32_t *)take(4 * (nb + 4096));
     ws.hist = (uint32_t *)take(4 * 256 * (ntiles + 1));
     ws.pairs_tmp = (int64_t *)take(8 * ws.pair_cap);
@@ -335,10 +340,6 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
     {
         PhaseTimer t(c, NCORP_PHASE_GWALK, s);
         HIPCHK(c, launch_walk(ws, 0, c->prm.ncs, c->prm.ncc_pre, c->prm.ncc_post, s));
-    }
-    {
-        PhaseTimer t(c, NCORP_PHASE_LISTS, s);
-        HIPCHK(c, launch_build_lists(ws, 0, s));
     }
     {
         PhaseTimer t(c, NCORP_PHASE_M2L, s);
@@ -490,7 +491,7 @@ extern "C" int ncorp_tree_info(ncorp_ctx *c, int64_t *info) {
     info[NCORP_INFO_VISITED] = h.visited;
     info[NCORP_INFO_COL_CAND] = h.ncand;
     info[NCORP_INFO_COL_TESTS] = h.col_tests;
-    info[NCORP_INFO_M2L_DIR] = h.m2l_dir;
+    info[NCORP_INFO_M2L_DIR] = 2 * (int64_t)h.nm2l;
     info[NCORP_INFO_P2P_INTER] = h.p2p_inter;
     return NCORP_OK;
 }

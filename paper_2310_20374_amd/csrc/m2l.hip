@@ -18,6 +18,7 @@
 namespace ncorp {
 
 constexpr int kM2LBlock = 64;     // one wave per block, one target per wave
+constexpr int kM2LList = 512;     // partner lists up to this length are sorted into LDS
 
 template <int P, typename T>
 __device__ __forceinline__ void green_derivs(T x, T y, T z, T rinv, T *D) {
@@ -139,41 +140,75 @@ template <int P, typename T> struct M2LSplit { static constexpr int K1 = P, K2 =
 template <> struct M2LSplit<6, double> { static constexpr int K1 = 3, K2 = 5; };
 template <> struct M2LSplit<5, double> { static constexpr int K1 = 3, K2 = 5; };
 
+// LDS of the wave-sum buffer, in ints: a target's list is sorted there first
+template <int P, typename T> constexpr int red_ints() {
+    return (int)(sizeof(T) * kWave * (ncomp(P) + 1) / 4) & ~3;
+}
+
 template <int P, typename T>
 __global__ void __launch_bounds__(kM2LBlock)
 k_m2l(const DevState *__restrict__ st, const double4 *__restrict__ gcell,
-      const T *__restrict__ mult, const int32_t *__restrict__ off,
-      const int32_t *__restrict__ src, double *__restrict__ local) {
+      const T *__restrict__ mult, const int32_t *__restrict__ cnt, int32_t *__restrict__ seg,
+      int stride, double *__restrict__ local) {
     constexpr int NL = n_local(P);
     constexpr int K1 = M2LSplit<P, T>::K1, K2 = M2LSplit<P, T>::K2;
-    __shared__ T red[kWave][ncomp(P) + 1];
+    __shared__ __align__(16) T red[kWave][ncomp(P) + 1];
+    __shared__ int32_t s_list[kM2LList];
+    extern __shared__ __align__(16) int32_t dyn[];   // sort scratch if red is too small
     if (st->status & kSkipMask) return;
+    int32_t *scratch = ((stride + 3) & ~3) <= red_ints<P, T>() ? (int32_t *)&red[0][0] : dyn;
     const int nc = st->ncells;
     const int lane = threadIdx.x;
     for (int A = blockIdx.x; A < nc; A += gridDim.x) {
-        const int b0 = off[A], len = off[A + 1] - b0;
+        const int len = cnt[A];
         double *out = local + (int64_t)A * NL;
         if (len == 0) {
             for (int k = lane; k < NL; k += kWave) out[k] = 0.0;
             continue;
         }
+        int32_t *list = seg + (int64_t)A * stride;
+        const int32_t *srcs = list;
+        if (len <= kM2LList) {
+            // usual case: sorted copy in LDS
+            const int len4 = (len + 3) & ~3;
+            for (int i = lane; i < len4; i += kWave) scratch[i] = i < len ? list[i] : 0x7fffffff;
+            __syncthreads();
+            const int4 *s4 = reinterpret_cast<const int4 *>(scratch);
+            for (int i = lane; i < len; i += kWave) {
+                const int v = scratch[i];
+                int r = 0;
+                for (int j = 0; j < len4 / 4; j++) {
+                    const int4 t = s4[j];
+                    r += (t.x < v) + (t.y < v) + (t.z < v) + (t.w < v);
+                }
+                s_list[r] = v;
+            }
+            __syncthreads();
+            srcs = s_list;
+        } else {
+            sort_target_list(list, len, scratch);
+        }
         const double4 gA = gcell[A];
-        m2l_pass<P, 1, K1, T>(gA, gcell, mult, src + b0, len, out, red);
-        if (K2 > K1) m2l_pass<P, (K1 < P ? K1 + 1 : P), K2, T>(gA, gcell, mult, src + b0, len, out, red);
-        if (P > K2) m2l_pass<P, (K2 < P ? K2 + 1 : P), P, T>(gA, gcell, mult, src + b0, len, out, red);
+        m2l_pass<P, 1, K1, T>(gA, gcell, mult, srcs, len, out, red);
+        if (K2 > K1) m2l_pass<P, (K1 < P ? K1 + 1 : P), K2, T>(gA, gcell, mult, srcs, len, out, red);
+        if (P > K2) m2l_pass<P, (K2 < P ? K2 + 1 : P), P, T>(gA, gcell, mult, srcs, len, out, red);
     }
+}
+
+template <int P, typename T>
+static void launch_m2l_t(const Workspace &ws, const T *mult, hipStream_t s) {
+    int g = (int)(ws.cell_cap < 16384 ? ws.cell_cap : 16384);
+    if (g < 1) g = 1;
+    const int s4 = (ws.m2l_stride + 3) & ~3;
+    const size_t dyn = s4 <= red_ints<P, T>() ? 0 : (size_t)s4 * sizeof(int32_t);
+    k_m2l<P, T><<<g, kM2LBlock, dyn, s>>>(ws.st, ws.gcell, mult, ws.m2l_cnt, ws.m2l_seg,
+                                          ws.m2l_stride, ws.local);
 }
 
 template <int P>
 static void launch_m2l_p(const Workspace &ws, int precision, hipStream_t s) {
-    int g = (int)(ws.cell_cap < 16384 ? ws.cell_cap : 16384);
-    if (g < 1) g = 1;
-    if (precision == NCORP_FP32_BULK)
-        k_m2l<P, float><<<g, kM2LBlock, 0, s>>>(ws.st, ws.gcell, ws.mult32, ws.m2l_off, ws.m2l_src,
-                                                ws.local);
-    else
-        k_m2l<P, double><<<g, kM2LBlock, 0, s>>>(ws.st, ws.gcell, ws.mult, ws.m2l_off, ws.m2l_src,
-                                                 ws.local);
+    if (precision == NCORP_FP32_BULK) launch_m2l_t<P, float>(ws, ws.mult32, s);
+    else launch_m2l_t<P, double>(ws, ws.mult, s);
 }
 
 hipError_t launch_m2l(const Workspace &ws, int p, int precision, hipStream_t s) {

@@ -44,6 +44,12 @@ enum StatusBits : int32_t {
 };
 // Any of these leaves the tree or the interaction lists incomplete: later passes
 // then do nothing rather than follow indices that were never written.
+// per-target interaction lists: default and largest slot counts (a consumer
+// sorts a whole list in LDS)
+constexpr int kDefaultM2LPerCell = 512;
+constexpr int kDefaultP2PPerLeaf = 1024;
+constexpr int kMaxPerTarget = 8192;
+
 constexpr int32_t kSkipMask = ST_CAP_CELLS | ST_CAP_QUEUE | ST_CAP_M2L | ST_CAP_P2P |
                               ST_CAP_LISTS | ST_WALK_STALL | ST_BAD_ITEM;
 
@@ -61,7 +67,6 @@ struct DevState {
     // gravity walk
     int32_t nm2l, np2p;        // unordered cell pairs
     int64_t visited;
-    int32_t m2l_dir, p2p_dir;  // directed list lengths
     // collision walk
     int32_t ncand, pad2;
     int64_t col_tests;
@@ -76,7 +81,7 @@ struct WalkQueue {
     uint64_t pad0[15];
     uint64_t tail;             // next slot to reserve
     uint64_t pad1[15];
-    int64_t outstanding;       // items pushed and not yet processed
+    uint64_t processed;        // items processed (children reserved first)
     uint64_t pad2[15];
     uint32_t epoch;            // tag of valid items in this walk
     uint32_t pad3[31];
@@ -89,12 +94,35 @@ struct alignas(16) WCell {
     int32_t count, child, nchild, pad;
 };
 
+// Sorts a per-target list list[0..len) ascending, in place in global memory (its
+// values are distinct).  Called by a whole single-wave block; scratch is LDS of at
+// least round_up(len, 4) ints, 16-byte aligned.  Ends with a block barrier, so the
+// wave's later loads see the sorted list.
+__device__ __forceinline__ void sort_target_list(int32_t *list, int len, int32_t *scratch) {
+    const int lane = threadIdx.x;
+    const int len4 = (len + 3) & ~3;
+    for (int i = lane; i < len4; i += kWave) scratch[i] = i < len ? list[i] : 0x7fffffff;
+    __syncthreads();
+    const int4 *s4 = reinterpret_cast<const int4 *>(scratch);
+    for (int i = lane; i < len; i += kWave) {
+        const int v = scratch[i];
+        int r = 0;
+        for (int j = 0; j < len4 / 4; j++) {
+            const int4 t = s4[j];
+            r += (t.x < v) + (t.y < v) + (t.z < v) + (t.w < v);
+        }
+        list[r] = v;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- workspace
 struct Workspace {
     char *base = nullptr;
     int64_t bytes = 0;
     int64_t n_max = 0, cell_cap = 0, m2l_cap = 0, p2p_cap = 0, queue_cap = 0;
-    int64_t m2l_dir_cap = 0, p2p_dir_cap = 0, pair_cap = 0;
+    int64_t leaf_cap = 0, pair_cap = 0;
+    int m2l_stride = 0, p2p_stride = 0;               // slots per target list
     int p = 0, nm = 0, nl = 0;
     // per moonlet (tree order unless noted)
     uint64_t *keys = nullptr, *keys_alt = nullptr;
@@ -129,10 +157,10 @@ struct Workspace {
     WalkQueue *wq = nullptr;
     int2 *m2l = nullptr, *p2p = nullptr;              // unordered cell pairs
     int2 *cand = nullptr;                             // collision candidate cell pairs
-    int32_t *m2l_off = nullptr, *m2l_src = nullptr;   // by target cell
-    int32_t *p2p_off = nullptr, *p2p_src = nullptr;   // by target leaf (entry)
-    int32_t *cnt_a = nullptr, *cnt_b = nullptr;       // per cell / per leaf counters
-    int32_t *cnt_tmp = nullptr;                       // segment-sort scratch
+    // per-target lists written by the gravity walk (unordered; consumers sort)
+    int32_t *m2l_cnt = nullptr, *m2l_seg = nullptr;   // by target cell, m2l_stride slots
+    int32_t *p2p_cnt = nullptr, *p2p_seg = nullptr;   // by target leaf, p2p_stride slots
+    int32_t *cnt_a = nullptr;                         // tree-build level counters
     int64_t *pairs_tmp = nullptr;                     // colliding pairs (i<<32|j)
     int64_t *pairs_alt = nullptr;
     // scratch for scans and sorts
@@ -169,7 +197,6 @@ hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hip
 // walk: mode 0 gravity (M2L + P2P lists), 1 collisions (candidate list in p2p)
 hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post,
                        hipStream_t s);
-hipError_t launch_build_lists(const Workspace &ws, int mode, hipStream_t s);
 hipError_t launch_count_interactions(const Workspace &ws, hipStream_t s);
 
 hipError_t launch_m2l(const Workspace &ws, int p, int precision, hipStream_t s);

@@ -38,7 +38,7 @@ template <int P, int M>
 __device__ __forceinline__ void leaf_local_order(int cl, const int32_t *__restrict__ c_parent,
                                                  const double4 *__restrict__ gcell,
                                                  const double *__restrict__ local,
-                                                 const int32_t *__restrict__ m2l_off,
+                                                 const int32_t *__restrict__ m2l_cnt,
                                                  double *__restrict__ out) {
     constexpr int NL = n_local(P), NR = P - M, NC = ncomp(M);
     double acc[NC];
@@ -47,7 +47,7 @@ __device__ __forceinline__ void leaf_local_order(int cl, const int32_t *__restri
     const double4 gl = gcell[cl];
     int a = cl;
     for (int up = 0; up <= kMaxDepth && a >= 0; up++) {
-        if (m2l_off[a + 1] != m2l_off[a]) {          // cells without M2L hold zeros
+        if (m2l_cnt[a] != 0) {                       // cells without M2L hold zeros
             const double4 ga = gcell[a];
             double px[NR + 1], py[NR + 1], pz[NR + 1];
             scaled_pow<NR>(gl.x - ga.x, gl.y - ga.y, gl.z - ga.z, px, py, pz);
@@ -81,7 +81,7 @@ template <int P>
 __global__ void __launch_bounds__(128)
 k_leaf_local(const DevState *__restrict__ st, const int32_t *__restrict__ ent_cell,
              const int32_t *__restrict__ c_parent, const double4 *__restrict__ gcell,
-             const double *__restrict__ local, const int32_t *__restrict__ m2l_off,
+             const double *__restrict__ local, const int32_t *__restrict__ m2l_cnt,
              double *__restrict__ cleaf) {
     constexpr int NL = n_local(P);
     if (st->status & kSkipMask) return;
@@ -93,12 +93,12 @@ k_leaf_local(const DevState *__restrict__ st, const int32_t *__restrict__ ent_ce
         const int cl = ent_cell[e];
         double *out = cleaf + (int64_t)e * NL;
         switch (m) {
-            case 1: leaf_local_order<P, 1>(cl, c_parent, gcell, local, m2l_off, out); break;
-            case 2: if constexpr (P >= 2) leaf_local_order<P, (P >= 2 ? 2 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
-            case 3: if constexpr (P >= 3) leaf_local_order<P, (P >= 3 ? 3 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
-            case 4: if constexpr (P >= 4) leaf_local_order<P, (P >= 4 ? 4 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
-            case 5: if constexpr (P >= 5) leaf_local_order<P, (P >= 5 ? 5 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
-            case 6: if constexpr (P >= 6) leaf_local_order<P, (P >= 6 ? 6 : 1)>(cl, c_parent, gcell, local, m2l_off, out); break;
+            case 1: leaf_local_order<P, 1>(cl, c_parent, gcell, local, m2l_cnt, out); break;
+            case 2: if constexpr (P >= 2) leaf_local_order<P, (P >= 2 ? 2 : 1)>(cl, c_parent, gcell, local, m2l_cnt, out); break;
+            case 3: if constexpr (P >= 3) leaf_local_order<P, (P >= 3 ? 3 : 1)>(cl, c_parent, gcell, local, m2l_cnt, out); break;
+            case 4: if constexpr (P >= 4) leaf_local_order<P, (P >= 4 ? 4 : 1)>(cl, c_parent, gcell, local, m2l_cnt, out); break;
+            case 5: if constexpr (P >= 5) leaf_local_order<P, (P >= 5 ? 5 : 1)>(cl, c_parent, gcell, local, m2l_cnt, out); break;
+            case 6: if constexpr (P >= 6) leaf_local_order<P, (P >= 6 ? 6 : 1)>(cl, c_parent, gcell, local, m2l_cnt, out); break;
             default: break;
         }
     }
@@ -157,6 +157,81 @@ template <> __device__ __forceinline__ double r2_floor<double>() { return 1e-200
 
 constexpr int kP2PTile = 256;       // source moonlets staged per LDS tile
 constexpr int kP2PSrc = 256;        // source cells per batch (prefix sums in LDS)
+// the tile in ints: a leaf's source list is sorted there first
+template <typename T> constexpr int tile_ints() {
+    return (int)(sizeof(typename Vec4<T>::type) * kP2PTile / 4);
+}
+
+// Exclusive prefix sums of the 4 counts each lane holds for sources 4*lane..4*lane+3
+// into s_pref[0..256]; returns the total.
+__device__ __forceinline__ int batch_prefix(const int (&cnt4)[4], int32_t *s_pref, int lane) {
+    int run = cnt4[0] + cnt4[1] + cnt4[2] + cnt4[3];
+    int tot;
+    int ex = wave_excl_sum_p(run, lane, tot);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        s_pref[4 * lane + k] = ex;
+        ex += cnt4[k];
+    }
+    if (lane == 0) s_pref[kP2PSrc] = tot;
+    return tot;
+}
+
+// Direct sums of one lane's target over a batch of source cells whose moonlet
+// ranges are s_first[k] .. + (s_pref[k+1] - s_pref[k]), k < nsb, tot moonlets in
+// all; the batch is streamed through LDS kP2PTile moonlets at a time.
+template <typename T>
+__device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_first,
+                                          const int32_t *s_pref,
+                                          typename Vec4<T>::type *tile,
+                                          const double *__restrict__ xs,
+                                          const double *__restrict__ ys,
+                                          const double *__restrict__ zs,
+                                          const double *__restrict__ mus, const double4 g,
+                                          T xi, T yi, T zi, int grp, int G, Acc3<T> &acc) {
+    using V = typename Vec4<T>::type;
+    const int lane = threadIdx.x;
+    const T floor2 = r2_floor<T>();
+    for (int p0 = 0; p0 < tot; p0 += kP2PTile) {
+        const int nj = tot - p0 < kP2PTile ? tot - p0 : kP2PTile;
+        // stage the tile: source moonlet q of the batch -> its cell by binary
+        // search over the prefix sums
+#pragma unroll
+        for (int k = 0; k < kP2PTile / 64; k++) {
+            const int q = p0 + lane + 64 * k;
+            if (q < tot) {
+                int lo = 0, hi = nsb;          // s_pref[lo] <= q < s_pref[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pref[mid] <= q) lo = mid; else hi = mid;
+                }
+                const int j = s_first[lo] + (q - s_pref[lo]);
+                V v;
+                v.x = (T)(xs[j] - g.x);
+                v.y = (T)(ys[j] - g.y);
+                v.z = (T)(zs[j] - g.z);
+                v.w = (T)mus[j];
+                tile[lane + 64 * k] = v;
+            }
+        }
+        __syncthreads();
+        T px = 0, py = 0, pz = 0;
+#pragma unroll 4
+        for (int j = grp; j < nj; j += G) {
+            const V v = tile[j];
+            const T dx = v.x - xi, dy = v.y - yi, dz = v.z - zi;
+            T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, dx * dx));
+            r2 = r2 > floor2 ? r2 : floor2;
+            const T rinv = rsq<T>(r2);
+            const T w = v.w * (rinv * rinv) * rinv;
+            px = fmat<T>(dx, w, px);
+            py = fmat<T>(dy, w, py);
+            pz = fmat<T>(dz, w, pz);
+        }
+        acc.add_tile(px, py, pz);
+        __syncthreads();
+    }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(64)
@@ -164,20 +239,66 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const double *__restrict__ ys, const double *__restrict__ zs,
       const double *__restrict__ mus, const int32_t *__restrict__ ent_cell,
       const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
-      const double4 *__restrict__ gcell, const int32_t *__restrict__ p2p_off,
-      const int32_t *__restrict__ p2p_src, double *__restrict__ acc_s, int64_t n) {
+      const double4 *__restrict__ gcell, const int32_t *__restrict__ p2p_cnt,
+      int32_t *__restrict__ p2p_seg, int stride, double *__restrict__ acc_s, int64_t n) {
     using V = typename Vec4<T>::type;
-    __shared__ V tile[kP2PTile];
+    __shared__ __align__(16) V tile[kP2PTile];
     __shared__ int32_t s_first[kP2PSrc], s_pref[kP2PSrc + 1];
+    extern __shared__ __align__(16) int32_t dyn[];   // sort scratch if the tile is too small
     if (st->status & kSkipMask) return;
+    // the tile doubles as sort scratch before any moonlet is staged
+    int32_t *scratch = ((stride + 3) & ~3) <= tile_ints<T>() ? (int32_t *)tile : dyn;
     const int K = st->nleaves;
     const int lane = threadIdx.x;
-    const T floor2 = r2_floor<T>();
     for (int e = blockIdx.x; e < K; e += gridDim.x) {
         const int c = ent_cell[e];
         const int f = c_first[c], nt = c_count[c];
         const double4 g = gcell[c];
-        const int s0 = p2p_off[e], s1 = p2p_off[e + 1];
+        int32_t *list = p2p_seg + (int64_t)e * stride;
+        const int len = p2p_cnt[e];
+        const bool one = len <= kP2PSrc;
+        int tot1 = 0;
+        __syncthreads();                              // LDS free again
+        if (one) {
+            // the usual case, one batch: rank the sources in LDS and place each
+            // source's moonlet range at its rank directly
+            int v[4], cf[4], cn[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int q = 4 * lane + k;
+                v[k] = 0x7fffffff; cf[k] = 0; cn[k] = 0;
+                if (q < len) {
+                    v[k] = list[q];
+                    cf[k] = c_first[v[k]];
+                    cn[k] = c_count[v[k]];
+                }
+                scratch[q] = v[k];
+            }
+            __syncthreads();
+            const int4 *s4 = reinterpret_cast<const int4 *>(scratch);
+            const int len4 = (len + 3) >> 2;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                if (4 * lane + k < len) {
+                    int r = 0;
+                    for (int j = 0; j < len4; j++) {
+                        const int4 t = s4[j];
+                        r += (t.x < v[k]) + (t.y < v[k]) + (t.z < v[k]) + (t.w < v[k]);
+                    }
+                    s_first[r] = cf[k];
+                    s_pref[r] = cn[k];
+                }
+            }
+            __syncthreads();
+            int c4[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) c4[k] = 4 * lane + k < len ? s_pref[4 * lane + k] : 0;
+            __syncthreads();
+            tot1 = batch_prefix(c4, s_pref, lane);
+            __syncthreads();
+        } else {
+            sort_target_list(list, len, scratch);
+        }
         for (int t0 = 0; t0 < nt; t0 += 64) {
             const int ntc = nt - t0 < 64 ? nt - t0 : 64;
             int S = 1;
@@ -187,71 +308,30 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
             const int i = f + t0 + (act ? tl : 0);
             const T xi = (T)(xs[i] - g.x), yi = (T)(ys[i] - g.y), zi = (T)(zs[i] - g.z);
             Acc3<T> acc;
-            for (int sb = s0; sb < s1; sb += kP2PSrc) {
-                const int nsb = s1 - sb < kP2PSrc ? s1 - sb : kP2PSrc;
-                __syncthreads();
-                // particle ranges of this batch of source cells, prefix-summed
-                int cnt4[4], run = 0;
+            if (one) {
+                p2p_batch<T>(tot1, len, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi,
+                             grp, G, acc);
+            } else {
+                for (int sb = 0; sb < len; sb += kP2PSrc) {
+                    const int nsb = len - sb < kP2PSrc ? len - sb : kP2PSrc;
+                    __syncthreads();
+                    int cnt4[4];
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const int q = 4 * lane + k;
-                    int cf = 0, cn = 0;
-                    if (q < nsb) {
-                        const int B = p2p_src[sb + q];
-                        cf = c_first[B];
-                        cn = c_count[B];
-                    }
-                    if (q < kP2PSrc) s_first[q] = cf;
-                    cnt4[k] = cn;
-                    run += cn;
-                }
-                int tot;
-                int ex = wave_excl_sum_p(run, lane, tot);
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    s_pref[4 * lane + k] = ex;
-                    ex += cnt4[k];
-                }
-                if (lane == 0) s_pref[kP2PSrc] = tot;
-                __syncthreads();
-                for (int p0 = 0; p0 < tot; p0 += kP2PTile) {
-                    const int nj = tot - p0 < kP2PTile ? tot - p0 : kP2PTile;
-                    // stage the tile: source moonlet q of the batch -> its cell by
-                    // binary search over the prefix sums
-#pragma unroll
-                    for (int k = 0; k < kP2PTile / 64; k++) {
-                        const int q = p0 + lane + 64 * k;
-                        if (q < tot) {
-                            int lo = 0, hi = nsb;          // s_pref[lo] <= q < s_pref[hi]
-                            while (hi - lo > 1) {
-                                const int mid = (lo + hi) >> 1;
-                                if (s_pref[mid] <= q) lo = mid; else hi = mid;
-                            }
-                            const int j = s_first[lo] + (q - s_pref[lo]);
-                            V v;
-                            v.x = (T)(xs[j] - g.x);
-                            v.y = (T)(ys[j] - g.y);
-                            v.z = (T)(zs[j] - g.z);
-                            v.w = (T)mus[j];
-                            tile[lane + 64 * k] = v;
+                    for (int k = 0; k < 4; k++) {
+                        const int q = 4 * lane + k;
+                        int cf = 0, cn = 0;
+                        if (q < nsb) {
+                            const int B = list[sb + q];
+                            cf = c_first[B];
+                            cn = c_count[B];
                         }
+                        s_first[q] = cf;
+                        cnt4[k] = cn;
                     }
+                    const int tot = batch_prefix(cnt4, s_pref, lane);
                     __syncthreads();
-                    T px = 0, py = 0, pz = 0;
-#pragma unroll 4
-                    for (int j = grp; j < nj; j += G) {
-                        const V v = tile[j];
-                        const T dx = v.x - xi, dy = v.y - yi, dz = v.z - zi;
-                        T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, dx * dx));
-                        r2 = r2 > floor2 ? r2 : floor2;
-                        const T rinv = rsq<T>(r2);
-                        const T w = v.w * (rinv * rinv) * rinv;
-                        px = fmat<T>(dx, w, px);
-                        py = fmat<T>(dy, w, py);
-                        pz = fmat<T>(dz, w, pz);
-                    }
-                    acc.add_tile(px, py, pz);
-                    __syncthreads();
+                    p2p_batch<T>(tot, nsb, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi,
+                                 zi, grp, G, acc);
                 }
             }
             double ox, oy, oz;
@@ -334,7 +414,7 @@ static void launch_leaf_local(const Workspace &ws, hipStream_t s) {
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
     k_leaf_local<P><<<(int)g, 128, 0, s>>>(ws.st, ws.ent_cell, ws.c_parent, ws.gcell, ws.local,
-                                           ws.m2l_off, ws.cleaf);
+                                           ws.m2l_cnt, ws.cleaf);
 }
 
 hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s) {
@@ -350,16 +430,20 @@ hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s) {
-    int g = (int)(ws.n_max < 65536 ? ws.n_max : 65536);
+template <typename T>
+static void launch_p2p_t(const Workspace &ws, int64_t n, hipStream_t s) {
+    int g = (int)(ws.leaf_cap < 65536 ? ws.leaf_cap : 65536);
     if (g < 1) g = 1;
-    if (precision == NCORP_FP32_BULK)
-        k_p2p<float><<<g, 64, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first,
-                                      ws.c_count, ws.gcell, ws.p2p_off, ws.p2p_src, ws.acc_s, n);
-    else
-        k_p2p<double><<<g, 64, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell,
-                                       ws.c_first, ws.c_count, ws.gcell, ws.p2p_off, ws.p2p_src,
-                                       ws.acc_s, n);
+    const int s4 = (ws.p2p_stride + 3) & ~3;
+    const size_t dyn = s4 <= tile_ints<T>() ? 0 : (size_t)s4 * sizeof(int32_t);
+    k_p2p<T><<<g, 64, dyn, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first,
+                                ws.c_count, ws.gcell, ws.p2p_cnt, ws.p2p_seg, ws.p2p_stride,
+                                ws.acc_s, n);
+}
+
+hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s) {
+    if (precision == NCORP_FP32_BULK) launch_p2p_t<float>(ws, n, s);
+    else launch_p2p_t<double>(ws, n, s);
     return hipGetLastError();
 }
 

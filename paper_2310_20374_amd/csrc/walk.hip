@@ -5,15 +5,21 @@
 // slots, polls them until their items appear, classifies each pair exactly as
 // Alg. 2 does (self pair / brute force before the opening test / well separated /
 // brute force after it / split the cell with the larger critical radius) and
-// pushes the child pairs with one wave-aggregated atomic.  A single signed counter
-// of outstanding items (children added and processed items retired in the same
-// atomic) says when the walk is over: at zero no item exists and none can appear.
-// A wave that polls for too long without progress latches ST_WALK_STALL and
-// leaves, so the kernel always ends.
+// pushes the child pairs with one wave-aggregated atomic on the tail.  Termination:
+// a wave counts its processed items into `processed` only after the tail
+// reservation of their children has returned, so processed <= tail at every
+// moment, with equality only when no item is waiting or being worked on.  A wave
+// that finds no work reads processed, then tail; if they are equal the walk is
+// over (tail can only have grown from an item not yet counted as processed, and
+// there is none).  A wave that polls for too long without progress latches
+// ST_WALK_STALL and leaves, so the kernel always ends.
 //
 // Pairs classified by the walk do not depend on the order of processing, so the
-// lists equal those of the recursive walk; they are then grouped per target and
-// sorted, making every later sum independent of the walk's timing.
+// lists equal those of the recursive walk.  Besides the plain lists of cell pairs
+// the gravity walk appends every pair to per-target lists (each well-separated
+// pair to both cells' M2L lists, each direct-sum pair to the direct-sum lists of
+// every leaf below either cell).  Their order depends on timing; the consumers
+// sort a list before using it, so every sum is independent of the walk's timing.
 #include "ncorp_internal.h"
 
 namespace ncorp {
@@ -41,10 +47,19 @@ __device__ __forceinline__ int wave_excl_sum(int v, int lane, int &total) {
     return x - v;
 }
 
+// Resets the queue and, for the gravity walk, the per-target list counters.
 __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, uint32_t epoch,
-                            int mode) {
+                            int mode, int32_t *m2l_cnt, int32_t *p2p_cnt) {
+    const int nc = st->ncells;
+    if (mode == 0 && m2l_cnt) {
+        const int nl = st->nleaves;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc || i < nl;
+             i += gridDim.x * blockDim.x) {
+            if (i < nc) m2l_cnt[i] = 0;
+            if (i < nl) p2p_cnt[i] = 0;
+        }
+    }
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int nc = st->ncells;
     wq->head = 0;
     wq->epoch = epoch;
     if (mode == 0) { st->nm2l = 0; st->np2p = 0; st->visited = 0; }
@@ -53,10 +68,10 @@ __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, uint32
         __hip_atomic_store(&queue[0], make_item(epoch, 0, 0), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         wq->tail = 1;
-        wq->outstanding = 1;
+        wq->processed = 0;
     } else {
         wq->tail = 0;
-        wq->outstanding = 0;
+        wq->processed = 0;
     }
 }
 
@@ -71,7 +86,23 @@ struct WalkArgs {
     int64_t m2l_cap, p2p_cap;
     int32_t *nm2l, *np2p;
     uint32_t epoch;
+    // gravity: per-target lists
+    const int32_t *c_entry, *c_nent;
+    int32_t *m2l_cnt, *m2l_seg, *p2p_cnt, *p2p_seg;
+    int m2l_stride, p2p_stride;
 };
+
+// Appends v to target t's list (slot order is arbitrary).
+__device__ __forceinline__ void append(int32_t *cnt, int32_t *seg, int stride, int t, int v,
+                                       DevState *st) {
+    const int k = atomicAdd(&cnt[t], 1);
+    if (k < stride) {
+        seg[(int64_t)t * stride + k] = v;
+    } else {
+        atomicOr(&st->status, (int32_t)ST_CAP_LISTS);
+        atomicMax((unsigned long long *)&st->required, (unsigned long long)(k + 1));
+    }
+}
 
 // Appends the lanes' flagged pairs to a list with one atomic per wave.
 __device__ __forceinline__ void emit(bool flag, int a, int b, int lane, int32_t *count,
@@ -115,13 +146,21 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
             if (pending) item = ld_relaxed(&A.queue[slot]);
             const bool valid = pending && (uint32_t)(item >> 48) == tag;
             if (!__any(valid)) {
-                // nothing arrived: the walk is over once no pushed item is left
-                int64_t o = 0;
-                if (lane == 0)
-                    o = __hip_atomic_load(&wq->outstanding, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-                o = __shfl(o, 0);
-                if (o <= 0) { finished = true; break; }
+                // nothing arrived: the walk is over once every pushed item has
+                // been processed (slots beyond the queue were never written)
+                int done = 0;
+                if (lane == 0) {
+                    const uint64_t pr = __hip_atomic_load(&wq->processed, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                    // the tail is read only after `processed` has returned: its
+                    // address depends on that value (pr >> 63 is always 0)
+                    uint64_t t = __hip_atomic_load(&wq->tail + (pr >> 63), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    if (t > (uint64_t)A.qcap) t = (uint64_t)A.qcap;
+                    done = pr >= t;
+                }
+                done = __shfl(done, 0);
+                if (done) { finished = true; break; }
                 if (++spins > kSpinLimit) {
                     if (lane == 0) atomicOr(&A.st->status, (int32_t)ST_WALK_STALL);
                     finished = true;
@@ -173,7 +212,6 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
             // ---------------- push children (one reservation per wave)
             int tot_push;
             const int off = wave_excl_sum(npush, lane, tot_push);
-            int written = 0;
             if (tot_push > 0) {
                 uint64_t pbase = 0;
                 if (lane == 0)
@@ -187,21 +225,18 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
                             if (my + j < (uint64_t)A.qcap) {
                                 __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, ca + x, ca + y),
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                written++;
                             }
                 } else if (split == 2) {
                     for (; j < na; j++)
                         if (my + j < (uint64_t)A.qcap) {
                             __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, ca + j, b),
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            written++;
                         }
                 } else if (split == 3) {
                     for (; j < nb; j++)
                         if (my + j < (uint64_t)A.qcap) {
                             __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, a, cb + j),
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            written++;
                         }
                 }
                 if (pbase + (uint64_t)tot_push > (uint64_t)A.qcap && lane == 0) {
@@ -213,14 +248,30 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
             // ---------------- interaction lists
             if (MODE == 0) emit(kind == 1, a, b, lane, A.nm2l, A.m2l, A.m2l_cap, A.st, ST_CAP_M2L);
             emit(kind == 2, a, b, lane, A.np2p, A.p2p, A.p2p_cap, A.st, ST_CAP_P2P);
-            // ---------------- retire: children in, processed items out, one atomic
+            if (MODE == 0 && A.m2l_cnt) {
+                if (kind == 1) {
+                    append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, a, b, A.st);
+                    append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, b, a, A.st);
+                } else if (kind == 2) {
+                    int e0 = A.c_entry[a], e1 = e0 + A.c_nent[a];
+                    for (int e = e0; e < e1; e++)
+                        append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, b, A.st);
+                    if (a != b) {
+                        e0 = A.c_entry[b];
+                        e1 = e0 + A.c_nent[b];
+                        for (int e = e0; e < e1; e++)
+                            append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, a, A.st);
+                    }
+                }
+            }
+            // ---------------- retire.  The children's tail reservation has returned
+            // (its value addressed their stores); the compiler barrier keeps this
+            // atomic after those stores, so it is performed after the reservation.
             const int nproc = __popcll(__ballot(valid));
-            int wsum = written;
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             if (lane == 0)
-                atomicAdd((unsigned long long *)&wq->outstanding,
-                          (unsigned long long)(int64_t)(wsum - nproc));
+                __hip_atomic_fetch_add(&wq->processed, (uint64_t)nproc, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             visited += nproc;
             pending = pending && !valid;
         }
@@ -237,8 +288,14 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
         launch_fill_i64((int64_t *)ws.queue, 0, ws.queue_cap, s);
         ws.epoch = 1;
     }
-    k_walk_init<<<1, 64, 0, s>>>(ws.st, ws.wq, ws.queue, ws.epoch, mode);
-    WalkArgs A;
+    int gi = 1;
+    if (mode == 0 && ws.m2l_cnt) {
+        const int64_t m = ws.cell_cap > ws.leaf_cap ? ws.cell_cap : ws.leaf_cap;
+        gi = (int)((m + 255) / 256 < 1024 ? (m + 255) / 256 : 1024);
+    }
+    k_walk_init<<<gi, 256, 0, s>>>(ws.st, ws.wq, ws.queue, ws.epoch, mode, ws.m2l_cnt,
+                                   ws.p2p_cnt);
+    WalkArgs A = {};
     A.st = ws.st; A.wq = ws.wq; A.queue = ws.queue; A.qcap = ws.queue_cap;
     A.ncs = ncs; A.ncc_pre = ncc_pre; A.ncc_post = ncc_post;
     A.epoch = ws.epoch;
@@ -246,6 +303,9 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
         A.cell = ws.wg;
         A.m2l = ws.m2l; A.m2l_cap = ws.m2l_cap; A.nm2l = &ws.st->nm2l;
         A.p2p = ws.p2p; A.p2p_cap = ws.p2p_cap; A.np2p = &ws.st->np2p;
+        A.c_entry = ws.c_entry; A.c_nent = ws.c_nent;
+        A.m2l_cnt = ws.m2l_cnt; A.m2l_seg = ws.m2l_seg; A.m2l_stride = ws.m2l_stride;
+        A.p2p_cnt = ws.p2p_cnt; A.p2p_seg = ws.p2p_seg; A.p2p_stride = ws.p2p_stride;
         k_walk<0><<<kWalkGrid, kWalkBlock, 0, s>>>(A);
     } else {
         A.cell = ws.wc;
@@ -256,139 +316,20 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ lists
-// M2L: directed entries grouped by target cell.  P2P: directed entries grouped by
-// target leaf -- a pair involving an internal cell A (possible when N_a N_b is
-// below a threshold, or N_a <= N_cs) reaches every leaf below A.
-__global__ void k_zero_n(int32_t *p, const int32_t *n_dev, int extra) {
-    int n = *n_dev + extra;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        p[i] = 0;
-}
-
-__global__ void k_count_m2l(const int2 *__restrict__ pairs, const int32_t *npairs_dev,
-                            int64_t cap, int32_t *cnt) {
-    int np = *npairs_dev;
-    if (np > cap) np = (int)cap;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
-        int2 q = pairs[i];
-        atomicAdd(&cnt[q.x], 1);
-        atomicAdd(&cnt[q.y], 1);
-    }
-}
-
-__global__ void k_fill_m2l(const int2 *__restrict__ pairs, const int32_t *npairs_dev, int64_t cap,
-                           const int32_t *__restrict__ off, int32_t *cursor, int32_t *src,
-                           int64_t dir_cap) {
-    int np = *npairs_dev;
-    if (np > cap) np = (int)cap;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
-        int2 q = pairs[i];
-        int64_t k = (int64_t)off[q.x] + atomicAdd(&cursor[q.x], 1);
-        if (k < dir_cap) src[k] = q.y;
-        k = (int64_t)off[q.y] + atomicAdd(&cursor[q.y], 1);
-        if (k < dir_cap) src[k] = q.x;
-    }
-}
-
-__global__ void k_count_p2p(const int2 *__restrict__ pairs, const int32_t *npairs_dev, int64_t cap,
-                            const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent,
-                            int32_t *cnt) {
-    int np = *npairs_dev;
-    if (np > cap) np = (int)cap;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
-        int2 q = pairs[i];
-        int e0 = c_entry[q.x], e1 = e0 + c_nent[q.x];
-        for (int e = e0; e < e1; e++) atomicAdd(&cnt[e], 1);
-        if (q.y != q.x) {
-            e0 = c_entry[q.y]; e1 = e0 + c_nent[q.y];
-            for (int e = e0; e < e1; e++) atomicAdd(&cnt[e], 1);
-        }
-    }
-}
-
-__global__ void k_fill_p2p(const int2 *__restrict__ pairs, const int32_t *npairs_dev, int64_t cap,
-                           const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent,
-                           const int32_t *__restrict__ off, int32_t *cursor, int32_t *src,
-                           int64_t dir_cap) {
-    int np = *npairs_dev;
-    if (np > cap) np = (int)cap;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
-        int2 q = pairs[i];
-        int e0 = c_entry[q.x], e1 = e0 + c_nent[q.x];
-        for (int e = e0; e < e1; e++) {
-            int64_t k = (int64_t)off[e] + atomicAdd(&cursor[e], 1);
-            if (k < dir_cap) src[k] = q.y;
-        }
-        if (q.y != q.x) {
-            e0 = c_entry[q.y]; e1 = e0 + c_nent[q.y];
-            for (int e = e0; e < e1; e++) {
-                int64_t k = (int64_t)off[e] + atomicAdd(&cursor[e], 1);
-                if (k < dir_cap) src[k] = q.x;
-            }
-        }
-    }
-}
-
-// off[n] = total; flags an overflow of the directed list
-__global__ void k_set_end(int32_t *off, const int32_t *n_dev, const int32_t *total_dev,
-                          int64_t dir_cap, DevState *st) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int32_t t = *total_dev;
-    off[*n_dev] = t;
-    if ((int64_t)t > dir_cap) {
-        atomicOr(&st->status, (int32_t)ST_CAP_LISTS);
-        atomicMax((unsigned long long *)&st->required, (unsigned long long)t);
-    }
-}
-
-// Sort each target's sources ascending: one single-wave block per segment; the
-// rank of an element is the number of smaller ones (a segment has no repeats).
-__global__ void __launch_bounds__(kWave)
-k_sort_segments(const int32_t *n_dev, const int32_t *__restrict__ off, int32_t *src,
-                int32_t *tmp, const DevState *st) {
-    __shared__ int32_t buf[1024];
-    if (st->status & kSkipMask) return;      // lists incomplete
-    const int lane = threadIdx.x;
-    const int nseg = *n_dev;
-    for (int sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
-        const int b = off[sg], len = off[sg + 1] - b;
-        if (len <= 1) continue;
-        if (len <= 1024) {
-            for (int i = lane; i < len; i += kWave) buf[i] = src[b + i];
-            __syncthreads();
-            for (int i = lane; i < len; i += kWave) {
-                int v = buf[i], r = 0;
-                for (int j = 0; j < len; j++) r += buf[j] < v;
-                src[b + r] = v;
-            }
-            __syncthreads();
-        } else {
-            for (int i = lane; i < len; i += kWave) tmp[b + i] = src[b + i];
-            __syncthreads();
-            for (int i = lane; i < len; i += kWave) {
-                int v = tmp[b + i], r = 0;
-                for (int j = 0; j < len; j++) r += tmp[b + j] < v;
-                src[b + r] = v;
-            }
-            __syncthreads();
-        }
-    }
-}
-
 // directed moonlet interactions of the direct sums: per leaf, its moonlets times
 // the moonlets of all its sources, minus the i == j terms
 __global__ void k_count_inter(DevState *st, const int32_t *__restrict__ ent_cell,
                               const int32_t *__restrict__ c_count,
-                              const int32_t *__restrict__ p2p_off,
-                              const int32_t *__restrict__ p2p_src) {
+                              const int32_t *__restrict__ p2p_cnt,
+                              const int32_t *__restrict__ p2p_seg, int stride) {
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     unsigned long long tot = 0;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
         const int nt = c_count[ent_cell[e]];
+        const int32_t *seg = p2p_seg + (int64_t)e * stride;
         long long srcs = 0;
-        for (int q = p2p_off[e]; q < p2p_off[e + 1]; q++) srcs += c_count[p2p_src[q]];
+        for (int q = 0; q < p2p_cnt[e]; q++) srcs += c_count[seg[q]];
         tot += (unsigned long long)(nt * srcs - nt);
     }
     for (int o = kWave / 2; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
@@ -401,39 +342,9 @@ __global__ void k_zero_inter(DevState *st) {
 
 hipError_t launch_count_interactions(const Workspace &ws, hipStream_t s) {
     k_zero_inter<<<1, 64, 0, s>>>(ws.st);
-    k_count_inter<<<256, 256, 0, s>>>(ws.st, ws.ent_cell, ws.c_count, ws.p2p_off, ws.p2p_src);
-    return hipGetLastError();
-}
-
-static int grid_cap(int64_t n, int block, int cap) {
-    int64_t g = (n + block - 1) / block;
-    return (int)(g < 1 ? 1 : (g > cap ? cap : g));
-}
-
-hipError_t launch_build_lists(const Workspace &ws, int mode, hipStream_t s) {
-    if (mode != 0) return hipSuccess;
-    DevState *st = ws.st;
-    const int gc = grid_cap(ws.cell_cap + 1, 256, 2048);
-    const int ge = grid_cap(ws.n_max + 1, 256, 2048);
-    // ---- M2L: directed entries by target cell
-    k_zero_n<<<gc, 256, 0, s>>>(ws.cnt_a, &st->ncells, 1);
-    k_count_m2l<<<1024, 256, 0, s>>>(ws.m2l, &st->nm2l, ws.m2l_cap, ws.cnt_a);
-    launch_scan(ws.cnt_a, ws.m2l_off, &st->ncells, ws.cell_cap, ws.scan_part, &st->m2l_dir, s);
-    k_set_end<<<1, 64, 0, s>>>(ws.m2l_off, &st->ncells, &st->m2l_dir, ws.m2l_dir_cap, st);
-    k_zero_n<<<gc, 256, 0, s>>>(ws.cnt_b, &st->ncells, 1);
-    k_fill_m2l<<<1024, 256, 0, s>>>(ws.m2l, &st->nm2l, ws.m2l_cap, ws.m2l_off, ws.cnt_b,
-                                    ws.m2l_src, ws.m2l_dir_cap);
-    k_sort_segments<<<4096, kWave, 0, s>>>(&st->ncells, ws.m2l_off, ws.m2l_src, ws.cnt_tmp, st);
-    // ---- P2P: directed entries by target leaf
-    k_zero_n<<<ge, 256, 0, s>>>(ws.cnt_a, &st->nleaves, 1);
-    k_count_p2p<<<1024, 256, 0, s>>>(ws.p2p, &st->np2p, ws.p2p_cap, ws.c_entry, ws.c_nent,
-                                     ws.cnt_a);
-    launch_scan(ws.cnt_a, ws.p2p_off, &st->nleaves, ws.n_max, ws.scan_part, &st->p2p_dir, s);
-    k_set_end<<<1, 64, 0, s>>>(ws.p2p_off, &st->nleaves, &st->p2p_dir, ws.p2p_dir_cap, st);
-    k_zero_n<<<ge, 256, 0, s>>>(ws.cnt_b, &st->nleaves, 1);
-    k_fill_p2p<<<1024, 256, 0, s>>>(ws.p2p, &st->np2p, ws.p2p_cap, ws.c_entry, ws.c_nent,
-                                    ws.p2p_off, ws.cnt_b, ws.p2p_src, ws.p2p_dir_cap);
-    k_sort_segments<<<4096, kWave, 0, s>>>(&st->nleaves, ws.p2p_off, ws.p2p_src, ws.cnt_tmp, st);
+    if (!ws.p2p_cnt) return hipGetLastError();
+    k_count_inter<<<256, 256, 0, s>>>(ws.st, ws.ent_cell, ws.c_count, ws.p2p_cnt, ws.p2p_seg,
+                                      ws.p2p_stride);
     return hipGetLastError();
 }
 

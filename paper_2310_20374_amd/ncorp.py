@@ -20,8 +20,8 @@ STATUS_NAMES = {0: "ok", -1: "invalid", -2: "capacity", -3: "hip", -4: "unsuppor
 
 INFO_FIELDS = ("n", "ncells", "nleaves", "maxlevel", "m2l", "p2p", "visited", "col_cand",
                "col_tests", "m2l_dir", "p2p_inter")
-PHASES = ("keys", "sort", "tree", "gclimb", "gwalk", "lists", "m2l", "descent", "p2p", "l2p",
-          "collide", "integrate")
+PHASES = ("keys", "sort", "tree", "gclimb", "gwalk", "m2l", "descent", "p2p", "l2p", "collide",
+          "integrate")
 EXPORT = {"keys": 0, "perm": 1, "cells": 2, "gcells": 3, "ccells": 4, "multipoles": 5,
           "local": 6, "m2l": 7, "p2p": 8, "col_cand": 9}
 
@@ -41,6 +41,7 @@ class Params(C.Structure):
         ("precision", C.c_int), ("root_half_width", C.c_double),
         ("cell_capacity", C.c_int64), ("m2l_capacity", C.c_int64),
         ("p2p_capacity", C.c_int64), ("queue_capacity", C.c_int64),
+        ("m2l_per_cell", C.c_int32), ("p2p_per_leaf", C.c_int32),
     ]
 
     def as_dict(self):

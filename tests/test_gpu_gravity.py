@@ -101,3 +101,34 @@ def test_error_vs_direct_sum(nc, orc, prec):
     if prec == "fp32":
         ref, _, _ = orc.tree_accel(d, p=6, s=52, ncs=256, ncc_pre=256, ncc_post=512)
         assert rel_err(a, ref)[0] < 1e-5      # FP32 rounding only
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_repeat_is_bit_identical(nc, prec):
+    """The walk fills its per-target lists in a timing-dependent order; the sums
+    must not depend on it: repeated evaluations are bit-identical."""
+    d = inputs.clumps(30000, seed=3, n_clumps=30)
+    prm = nc.params_default(4, precision=nc.FP32_BULK if prec == "fp32" else nc.FP64)
+    ctx, a0 = run_gravity(nc, d, prm)
+    for _ in range(3):
+        _, a1 = run_gravity(nc, d, prm, ctx=ctx)
+        assert np.array_equal(a0, a1)
+
+
+@pytest.mark.parametrize("field", ["m2l_per_cell", "p2p_per_leaf"])
+def test_target_list_overflow_is_reported(nc, field):
+    d = inputs.disk(20000, seed=1)
+    prm = nc.params_default(4, **{field: 4})
+    with pytest.raises(nc.NcorpError) as ei:
+        run_gravity(nc, d, prm)
+    assert ei.value.code == nc.E_CAPACITY
+    # the required size is reported; with it the same call succeeds
+    ctx = nc.Context(prm, len(d["x"]), pair_capacity=1 << 14, device="cuda:0")
+    with pytest.raises(nc.NcorpError):
+        run_gravity(nc, d, prm, ctx=ctx)
+    req = ctx.get_status()[1]
+    assert req > 4
+    prm2 = nc.params_default(4, **{field: int(req)})
+    _, a = run_gravity(nc, d, prm2)
+    _, ref = run_gravity(nc, d, nc.params_default(4))
+    assert np.array_equal(a, ref)
