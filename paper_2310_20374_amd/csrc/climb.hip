@@ -1,7 +1,7 @@
-// Tree climbs (Sect. 3.4.2).  One thread per leaf computes the leaf, then walks up:
-// each finished cell bumps its parent's arrival counter and the thread that
-// arrives last computes the parent from its (complete) children.  No thread ever
-// waits, so the pass is a single launch with no level loop.
+// Tree climbs (Sect. 3.4.2).  One wave per leaf computes the leaf, then walks up:
+// each finished cell bumps its parent's arrival counter and the wave that arrives
+// last computes the parent from its (complete) children.  No wave ever waits, so
+// the pass is a single launch with no level loop.
 //
 // Gravity: centre of mass (Eq. 10), r_max (Eq. 11) clamped to the farthest corner
 // of the cell's cube, scaled multipole moments Mt_a = M_a / a! (Eq. 20 at leaves,
@@ -47,94 +47,108 @@ __device__ double far_corner(double sx, double sy, double sz, double px, double 
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
-__device__ __forceinline__ double ld_coherent(const double *p) {
-    return __builtin_nontemporal_load(p);
+// ---------------------------------------------------------------- wave helpers
+// Cell results are handed from wave to wave inside one launch: they are written
+// with agent-coherent stores and read back with agent-coherent loads, and a wave
+// waits for its stores to complete before it bumps the parent's arrival counter.
+// The arrival counter's returned value orders the parent's loads after it.  (A
+// full device fence here would write back and invalidate the L2 at every cell.)
+__device__ __forceinline__ void st_c(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_c(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// 1 if this wave is the last of the parent's children to arrive
+__device__ __forceinline__ bool arrive_last(int32_t *counter, int nchild) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);                 // this wave's stores are complete
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    int old = 0;
+    if (threadIdx.x == 0) old = atomicAdd(counter, 1);
+    old = __shfl(old, 0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return old == nchild - 1;
 }
 
-template <int P>
-struct Mult {
+// value of lane k (k uniform)
+__device__ __forceinline__ double rl(double v, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double t = __shfl_xor(v, o);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+// multi-index (a, b, c) of multipole slot j (0 <= j < n_mult(p))
+__host__ __device__ constexpr void mult_index(int j, int &a, int &b, int &c) {
+    if (j == 0) { a = b = c = 0; return; }
+    const int s = j + 3;
+    int n = 2;
+    while (off_order(n + 1) <= s) n++;
+    const int r = s - off_order(n);
+    int k = 0;
+    while (tri(k + 1) <= r) k++;
+    c = r - tri(k);
+    b = k - c;
+    a = n - k;
+}
+
+// Terms of the App. C shift Mt_a(s') = sum_{b <= a, |b| != 1} Mt_b(s) u^(a-b)/(a-b)!
+// for every multipole slot: term t of slot j (first[j] <= t < first[j+1]) packs
+// the source slot and the three exponents (6 + 3 x 3 bits).
+template <int P> struct ShiftTerms {
     static constexpr int NM = n_mult(P);
-};
-
-// scaled powers u^a / a! for a = 0..P-1 per axis
-template <int P>
-__device__ __forceinline__ void scaled_powers(double ux, double uy, double uz, double *px,
-                                              double *py, double *pz) {
-    px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-    for (int a = 1; a < (P > 1 ? P : 1); a++) {
-        double inv = 1.0 / (double)a;
-        px[a] = px[a - 1] * ux * inv;
-        py[a] = py[a - 1] * uy * inv;
-        pz[a] = pz[a - 1] * uz * inv;
-    }
-}
-
-// leaf: moments straight from the moonlets (Eq. 20), scaled by 1/a!
-template <int P>
-__device__ void leaf_moments(const double *__restrict__ xs, const double *__restrict__ ys,
-                             const double *__restrict__ zs, const double *__restrict__ mus,
-                             int f, int cnt, double sx, double sy, double sz, double *out) {
-    constexpr int NM = n_mult(P);
-    double acc[NM > 0 ? NM : 1];
-#pragma unroll
-    for (int k = 0; k < NM; k++) acc[k] = 0.0;
-    for (int k = f; k < f + cnt; k++) {
-        double mu = mus[k];
-        double px[P > 1 ? P : 1], py[P > 1 ? P : 1], pz[P > 1 ? P : 1];
-        scaled_powers<P>(xs[k] - sx, ys[k] - sy, zs[k] - sz, px, py, pz);
-#pragma unroll
-        for (int n = 0; n < P; n++) {
-            if (n == 1) continue;
-#pragma unroll
-            for (int b = 0; b <= n; b++)
-#pragma unroll
-                for (int c = 0; c <= n - b; c++) {
-                    int a = n - b - c;
-                    acc[midx(a, b, c)] += mu * px[a] * py[b] * pz[c];
-                }
+    static constexpr int count() {
+        int t = 0;
+        for (int j = 0; j < NM; j++) {
+            int a = 0, b = 0, c = 0;
+            mult_index(j, a, b, c);
+            for (int a2 = 0; a2 <= a; a2++)
+                for (int b2 = 0; b2 <= b; b2++)
+                    for (int c2 = 0; c2 <= c; c2++)
+                        if (a2 + b2 + c2 != 1) t++;
         }
+        return t;
     }
-#pragma unroll
-    for (int k = 0; k < NM; k++) out[k] = acc[k];
-}
-
-// parent moments: sum over children of the shifted child moments (App. C):
-// Mt_a(s_B) = sum_{b <= a} Mt_b(s_b) u^(a-b)/(a-b)!,  u = s_b - s_B
-template <int P>
-__device__ void shift_add(const double *__restrict__ child, double ux, double uy, double uz,
-                          double *acc) {
-    double px[P > 1 ? P : 1], py[P > 1 ? P : 1], pz[P > 1 ? P : 1];
-    scaled_powers<P>(ux, uy, uz, px, py, pz);
-    double m[n_mult(P) > 0 ? n_mult(P) : 1];
-#pragma unroll
-    for (int k = 0; k < n_mult(P); k++) m[k] = ld_coherent(child + k);
-#pragma unroll
-    for (int n = 0; n < P; n++) {
-        if (n == 1) continue;
-#pragma unroll
-        for (int b = 0; b <= n; b++)
-#pragma unroll
-            for (int c = 0; c <= n - b; c++) {
-                const int a = n - b - c;
-                double s = 0.0;
-#pragma unroll
-                for (int a2 = 0; a2 <= a; a2++)
-#pragma unroll
-                    for (int b2 = 0; b2 <= b; b2++)
-#pragma unroll
-                        for (int c2 = 0; c2 <= c; c2++) {
-                            const int n2 = a2 + b2 + c2;
-                            if (n2 == 1) continue;
-                            s += m[midx(a2, b2, c2)] * (px[a - a2] * py[b - b2] * pz[c - c2]);
-                        }
-                acc[midx(a, b, c)] += s;
-            }
+    static constexpr int NT = count() > 0 ? count() : 1;
+    uint16_t first[NM + 1];
+    uint16_t term[NT];
+    constexpr ShiftTerms() : first(), term() {
+        int t = 0;
+        for (int j = 0; j < NM; j++) {
+            first[j] = (uint16_t)t;
+            int a = 0, b = 0, c = 0;
+            mult_index(j, a, b, c);
+            for (int a2 = 0; a2 <= a; a2++)
+                for (int b2 = 0; b2 <= b; b2++)
+                    for (int c2 = 0; c2 <= c; c2++)
+                        if (a2 + b2 + c2 != 1)
+                            term[t++] = (uint16_t)(midx(a2, b2, c2) | ((a - a2) << 6) |
+                                                   ((b - b2) << 9) | ((c - c2) << 12));
+        }
+        first[NM] = (uint16_t)t;
     }
-}
+};
+template <int P> __constant__ ShiftTerms<P> kShift = ShiftTerms<P>();
 
+// Gravity climb.  One wave per cell.  Centre of mass: every lane forms the same
+// sum over moonlets (leaves) or children (internal cells) in a fixed sequential
+// order, so it is reproducible bit for bit; r_max is an exact wave maximum.
+// Moments: lane j owns multipole slot j.  At a leaf each lane first stages its
+// moonlet's scaled powers u^k/k! in LDS, then lane j sums mu u^a/a! over the
+// moonlets in order (Eq. 20).  At an internal cell the children's moments and the
+// scaled powers of their offsets are staged in LDS and lane j applies the shift
+// terms of its slot, child by child.
 template <int P>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(kWave)
 k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
                 const double *__restrict__ ys, const double *__restrict__ zs,
                 const double *__restrict__ mus, const int32_t *__restrict__ ent_cell,
@@ -144,88 +158,159 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
                 int32_t *c_arrive, double4 *gcell, double *c_mass, double *c_rmax,
                 double *mult, float *mult32) {
     constexpr int NM = n_mult(P);
+    constexpr int NP = P > 1 ? P : 1;               // powers 0..P-1
+    constexpr int NMS = NM > 0 ? NM : 1;
+    __shared__ double pw[kWave][3][NP];             // scaled powers per moonlet / child
+    __shared__ double smu[kWave];                   // moonlet masses
+    __shared__ double cm[8][NMS];                   // children's moments
+    __shared__ uint16_t sterm[ShiftTerms<P>::NT];   // shift terms (from constant memory)
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     const double L = st->L;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x;
+    int ja = 0, jb = 0, jc = 0, t0 = 0, t1 = 0;
+    if (lane < NM) {
+        mult_index(lane, ja, jb, jc);
+        t0 = kShift<P>.first[lane];
+        t1 = kShift<P>.first[lane + 1];
+    }
+    for (int t = lane; t < ShiftTerms<P>::NT; t += kWave) sterm[t] = kShift<P>.term[t];
+    __syncthreads();
+    for (int e = blockIdx.x; e < K; e += gridDim.x) {
         int c = ent_cell[e];
-        // ---- leaf
+        // ---- leaf: moonlets f .. f+cnt-1, 64 per chunk
         {
-            int f = c_first[c], cnt = c_count[c];
+            const int f = c_first[c], cnt = c_count[c];
             double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-            for (int k = f; k < f + cnt; k++) {
-                double mu = mus[k];
-                M += mu;
-                sx += mu * xs[k];
-                sy += mu * ys[k];
-                sz += mu * zs[k];
+            for (int c0 = 0; c0 < cnt; c0 += kWave) {
+                const int k = f + c0 + (c0 + lane < cnt ? lane : 0);
+                const double mu = mus[k], x = xs[k], y = ys[k], z = zs[k];
+                const int nk = cnt - c0 < kWave ? cnt - c0 : kWave;
+                for (int q = 0; q < nk; q++) {
+                    const double m = rl(mu, q);
+                    M += m;
+                    sx += m * rl(x, q);
+                    sy += m * rl(y, q);
+                    sz += m * rl(z, q);
+                }
             }
             sx = sx / M; sy = sy / M; sz = sz / M;
-            double rm = 0.0;
-            for (int k = f; k < f + cnt; k++) {
-                double d = 0.0 + dist3(xs[k], ys[k], zs[k], sx, sy, sz);
-                if (d > rm) rm = d;
-            }
-            double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
-            if (fc < rm) rm = fc;
-            gcell[c] = make_double4(sx, sy, sz, 0.0);
-            c_mass[c] = M;
-            c_rmax[c] = rm;
-            if (NM > 0) {
-                double mt[NM > 0 ? NM : 1];
-                leaf_moments<P>(xs, ys, zs, mus, f, cnt, sx, sy, sz, mt);
-                double *o = mult + (int64_t)c * NM;
-                float *o32 = mult32 + (int64_t)c * NM;
+            double rm = 0.0, acc = 0.0;
+            for (int c0 = 0; c0 < cnt; c0 += kWave) {
+                const bool in = c0 + lane < cnt;
+                const int k = f + c0 + (in ? lane : 0);
+                const double mu = mus[k], x = xs[k], y = ys[k], z = zs[k];
+                if (in) {
+                    const double d = 0.0 + dist3(x, y, z, sx, sy, sz);
+                    if (d > rm) rm = d;
+                }
+                if (NM > 0) {
+                    const int nk = cnt - c0 < kWave ? cnt - c0 : kWave;
+                    __syncthreads();
+                    {
+                        const double ux = x - sx, uy = y - sy, uz = z - sz;
+                        double tx = 1.0, ty = 1.0, tz = 1.0;
+                        pw[lane][0][0] = 1.0; pw[lane][1][0] = 1.0; pw[lane][2][0] = 1.0;
 #pragma unroll
-                for (int k = 0; k < NM; k++) { o[k] = mt[k]; o32[k] = (float)mt[k]; }
+                        for (int i = 1; i < NP; i++) {
+                            tx = tx * ux * (1.0 / (double)i);
+                            ty = ty * uy * (1.0 / (double)i);
+                            tz = tz * uz * (1.0 / (double)i);
+                            pw[lane][0][i] = tx; pw[lane][1][i] = ty; pw[lane][2][i] = tz;
+                        }
+                        smu[lane] = mu;
+                    }
+                    __syncthreads();
+                    if (lane < NM) {
+#pragma unroll 4
+                        for (int q = 0; q < nk; q++)
+                            acc += smu[q] * (pw[q][0][ja] * pw[q][1][jb] * pw[q][2][jc]);
+                    }
+                }
+            }
+            rm = wave_max(rm);
+            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
+            if (fc < rm) rm = fc;
+            if (lane == 0) {
+                st_c(&gcell[c].x, sx); st_c(&gcell[c].y, sy); st_c(&gcell[c].z, sz);
+                st_c(&gcell[c].w, 0.0);
+                st_c(&c_mass[c], M);
+                st_c(&c_rmax[c], rm);
+            }
+            if (lane < NM) {
+                st_c(&mult[(int64_t)c * NM + lane], acc);
+                mult32[(int64_t)c * NM + lane] = (float)acc;
             }
         }
-        // ---- walk up while this thread is the last child to arrive
+        // ---- walk up while this wave is the last child to arrive
         for (int up = 0; up < kMaxDepth; up++) {      // at most one step per level
-            int par = c_parent[c];
+            const int par = c_parent[c];
             if (par < 0) break;
-            __threadfence();
-            int old = atomicAdd(&c_arrive[par], 1);
-            if (old != c_nchild[par] - 1) break;
-            __threadfence();
+            if (!arrive_last(&c_arrive[par], c_nchild[par])) break;
             c = par;
-            int a0 = c_child[c], a1 = a0 + c_nchild[c];
+            const int a0 = c_child[c], nch = c_nchild[c];
+            const bool in = lane < nch;
+            const int a = a0 + (in ? lane : 0);
+            const double ma_ = ld_c(&c_mass[a]);
+            const double4 ga = make_double4(ld_c(&gcell[a].x), ld_c(&gcell[a].y),
+                                            ld_c(&gcell[a].z), 0.0);
+            const double ra = ld_c(&c_rmax[a]);
             double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-            for (int a = a0; a < a1; a++) M += ld_coherent(&c_mass[a]);
-            for (int a = a0; a < a1; a++) {
-                double ma = ld_coherent(&c_mass[a]);
-                sx += ma * ld_coherent(&gcell[a].x);
-                sy += ma * ld_coherent(&gcell[a].y);
-                sz += ma * ld_coherent(&gcell[a].z);
+            for (int q = 0; q < nch; q++) M += rl(ma_, q);
+            for (int q = 0; q < nch; q++) {
+                const double m = rl(ma_, q);
+                sx += m * rl(ga.x, q);
+                sy += m * rl(ga.y, q);
+                sz += m * rl(ga.z, q);
             }
             sx = sx / M; sy = sy / M; sz = sz / M;
             double rm = 0.0;
-            for (int a = a0; a < a1; a++) {
-                double d = ld_coherent(&c_rmax[a]) +
-                           dist3(ld_coherent(&gcell[a].x), ld_coherent(&gcell[a].y),
-                                 ld_coherent(&gcell[a].z), sx, sy, sz);
+            if (in) {
+                const double d = ra + dist3(ga.x, ga.y, ga.z, sx, sy, sz);
                 if (d > rm) rm = d;
             }
-            int f = c_first[c];
-            double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
+            rm = wave_max(rm);
+            const int f = c_first[c];
+            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
             if (fc < rm) rm = fc;
-            gcell[c] = make_double4(sx, sy, sz, 0.0);
-            c_mass[c] = M;
-            c_rmax[c] = rm;
+            if (lane == 0) {
+                st_c(&gcell[c].x, sx); st_c(&gcell[c].y, sy); st_c(&gcell[c].z, sz);
+                st_c(&gcell[c].w, 0.0);
+                st_c(&c_mass[c], M);
+                st_c(&c_rmax[c], rm);
+            }
             if (NM > 0) {
-                double acc[NM > 0 ? NM : 1];
+                __syncthreads();
+                // children's moments, and u^k/k! of each child's offset (lane = child)
+                for (int q = 0; q < nch; q++)
+                    if (lane < NM) cm[q][lane] = ld_c(&mult[(int64_t)(a0 + q) * NM + lane]);
+                if (in) {
+                    const double ux = ga.x - sx, uy = ga.y - sy, uz = ga.z - sz;
+                    double tx = 1.0, ty = 1.0, tz = 1.0;
+                    pw[lane][0][0] = 1.0; pw[lane][1][0] = 1.0; pw[lane][2][0] = 1.0;
 #pragma unroll
-                for (int k = 0; k < NM; k++) acc[k] = 0.0;
-                for (int a = a0; a < a1; a++) {
-                    double ux = ld_coherent(&gcell[a].x) - sx;
-                    double uy = ld_coherent(&gcell[a].y) - sy;
-                    double uz = ld_coherent(&gcell[a].z) - sz;
-                    shift_add<P>(mult + (int64_t)a * NM, ux, uy, uz, acc);
+                    for (int i = 1; i < NP; i++) {
+                        tx = tx * ux * (1.0 / (double)i);
+                        ty = ty * uy * (1.0 / (double)i);
+                        tz = tz * uz * (1.0 / (double)i);
+                        pw[lane][0][i] = tx; pw[lane][1][i] = ty; pw[lane][2][i] = tz;
+                    }
                 }
-                double *o = mult + (int64_t)c * NM;
-                float *o32 = mult32 + (int64_t)c * NM;
+                __syncthreads();
+                if (lane < NM) {
+                    double acc = 0.0;
+                    for (int t = t0; t < t1; t++) {
+                        const int w = sterm[t];
+                        const int src = w & 63, ea = (w >> 6) & 7, eb = (w >> 9) & 7,
+                                  ec = (w >> 12) & 7;
 #pragma unroll
-                for (int k = 0; k < NM; k++) { o[k] = acc[k]; o32[k] = (float)acc[k]; }
+                        for (int q = 0; q < 8; q++)
+                            if (q < nch)
+                                acc += cm[q][src] * (pw[q][0][ea] * pw[q][1][eb] * pw[q][2][ec]);
+                    }
+                    st_c(&mult[(int64_t)c * NM + lane], acc);
+                    mult32[(int64_t)c * NM + lane] = (float)acc;
+                }
             }
         }
     }
@@ -303,8 +388,8 @@ static int cell_grid(int64_t cap, int block) {
 
 template <int P>
 static void launch_gc(const Workspace &ws, hipStream_t s) {
-    int g = cell_grid(ws.n_max, 128);
-    k_gravity_climb<P><<<g, 128, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell,
+    const int g = (int)(ws.leaf_cap < 65536 ? (ws.leaf_cap < 1 ? 1 : ws.leaf_cap) : 65536);
+    k_gravity_climb<P><<<g, kWave, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell,
                                          ws.c_level, ws.c_first, ws.c_count, ws.c_child,
                                          ws.c_nchild, ws.c_parent, ws.c_arrive, ws.gcell,
                                          ws.c_mass, ws.c_rmax, ws.mult, ws.mult32);
@@ -330,7 +415,9 @@ hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_para
 }
 
 // ------------------------------------------------------------------ collisions
-__global__ void __launch_bounds__(128)
+// Same scheme: one wave per cell, centroid summed sequentially (bit-reproducible),
+// r_max and the largest R + dt |v| as exact wave maxima.
+__global__ void __launch_bounds__(kWave)
 k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
                   const double *__restrict__ ys, const double *__restrict__ zs,
                   const double *__restrict__ vxs, const double *__restrict__ vys,
@@ -343,59 +430,83 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     const double L = st->L;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x;
+    for (int e = blockIdx.x; e < K; e += gridDim.x) {
         int c = ent_cell[e];
         {
-            int f = c_first[c], cnt = c_count[c];
+            const int f = c_first[c], cnt = c_count[c];
             double sx = 0.0, sy = 0.0, sz = 0.0;
-            for (int k = f; k < f + cnt; k++) { sx += xs[k]; sy += ys[k]; sz += zs[k]; }
-            double NA = (double)cnt;
+            for (int c0 = 0; c0 < cnt; c0 += kWave) {
+                const int k = f + c0 + (c0 + lane < cnt ? lane : 0);
+                const double x = xs[k], y = ys[k], z = zs[k];
+                const int nk = cnt - c0 < kWave ? cnt - c0 : kWave;
+                for (int q = 0; q < nk; q++) {
+                    sx += rl(x, q);
+                    sy += rl(y, q);
+                    sz += rl(z, q);
+                }
+            }
+            const double NA = (double)cnt;
             sx = sx / NA; sy = sy / NA; sz = sz / NA;
             double rm = 0.0, ex = 0.0;
-            for (int k = f; k < f + cnt; k++) {
-                double d = 0.0 + dist3(xs[k], ys[k], zs[k], sx, sy, sz);
-                if (d > rm) rm = d;
-                double v = sqrt(vxs[k] * vxs[k] + vys[k] * vys[k] + vzs[k] * vzs[k]);
-                double ee = (rads[k] + dt * v) - 0.0;
-                if (ee > ex) ex = ee;
+            for (int c0 = 0; c0 < cnt; c0 += kWave) {
+                if (c0 + lane < cnt) {
+                    const int k = f + c0 + lane;
+                    const double d = 0.0 + dist3(xs[k], ys[k], zs[k], sx, sy, sz);
+                    if (d > rm) rm = d;
+                    const double v = sqrt(vxs[k] * vxs[k] + vys[k] * vys[k] + vzs[k] * vzs[k]);
+                    const double ee = (rads[k] + dt * v) - 0.0;
+                    if (ee > ex) ex = ee;
+                }
             }
-            double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
+            rm = wave_max(rm);
+            ex = wave_max(ex);
+            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
             if (fc < rm) rm = fc;
-            ccell[c] = make_double4(sx, sy, sz, rm + ex);
-            c_crmax[c] = rm;
+            if (lane == 0) {
+                st_c(&ccell[c].x, sx); st_c(&ccell[c].y, sy); st_c(&ccell[c].z, sz);
+                st_c(&ccell[c].w, rm + ex);
+                st_c(&c_crmax[c], rm);
+            }
         }
         for (int up = 0; up < kMaxDepth; up++) {      // at most one step per level
-            int par = c_parent[c];
+            const int par = c_parent[c];
             if (par < 0) break;
-            __threadfence();
-            int old = atomicAdd(&c_arrive[par], 1);
-            if (old != c_nchild[par] - 1) break;
-            __threadfence();
+            if (!arrive_last(&c_arrive[par], c_nchild[par])) break;
             c = par;
-            int a0 = c_child[c], a1 = a0 + c_nchild[c];
-            double NA = (double)c_count[c];
+            const int a0 = c_child[c], nch = c_nchild[c];
+            const bool in = lane < nch;
+            const int a = a0 + (in ? lane : 0);
+            const double na = (double)c_count[a];
+            const double4 ca = make_double4(ld_c(&ccell[a].x), ld_c(&ccell[a].y),
+                                            ld_c(&ccell[a].z), ld_c(&ccell[a].w));
+            const double rma = ld_c(&c_crmax[a]);
+            const double NA = (double)c_count[c];
             double sx = 0.0, sy = 0.0, sz = 0.0;
-            for (int a = a0; a < a1; a++) {
-                double na = (double)c_count[a];
-                sx += na * ld_coherent(&ccell[a].x);
-                sy += na * ld_coherent(&ccell[a].y);
-                sz += na * ld_coherent(&ccell[a].z);
+            for (int q = 0; q < nch; q++) {
+                const double w = rl(na, q);
+                sx += w * rl(ca.x, q);
+                sy += w * rl(ca.y, q);
+                sz += w * rl(ca.z, q);
             }
             sx = sx / NA; sy = sy / NA; sz = sz / NA;
             double rm = 0.0, ex = 0.0;
-            for (int a = a0; a < a1; a++) {
-                double rma = ld_coherent(&c_crmax[a]);
-                double d = rma + dist3(ld_coherent(&ccell[a].x), ld_coherent(&ccell[a].y),
-                                       ld_coherent(&ccell[a].z), sx, sy, sz);
+            if (in) {
+                const double d = rma + dist3(ca.x, ca.y, ca.z, sx, sy, sz);
                 if (d > rm) rm = d;
-                double ee = ld_coherent(&ccell[a].w) - rma;
+                const double ee = ca.w - rma;
                 if (ee > ex) ex = ee;
             }
-            int f = c_first[c];
-            double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
+            rm = wave_max(rm);
+            ex = wave_max(ex);
+            const int f = c_first[c];
+            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
             if (fc < rm) rm = fc;
-            ccell[c] = make_double4(sx, sy, sz, rm + ex);
-            c_crmax[c] = rm;
+            if (lane == 0) {
+                st_c(&ccell[c].x, sx); st_c(&ccell[c].y, sy); st_c(&ccell[c].z, sz);
+                st_c(&ccell[c].w, rm + ex);
+                st_c(&c_crmax[c], rm);
+            }
         }
     }
 }
@@ -403,7 +514,8 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
 hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hipStream_t s) {
     (void)n;
     k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive);
-    k_collision_climb<<<cell_grid(ws.n_max, 128), 128, 0, s>>>(
+    const int g = (int)(ws.leaf_cap < 65536 ? (ws.leaf_cap < 1 ? 1 : ws.leaf_cap) : 65536);
+    k_collision_climb<<<g, kWave, 0, s>>>(
         ws.st, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, dt, ws.ent_cell, ws.c_level,
         ws.c_first, ws.c_count, ws.c_child, ws.c_nchild, ws.c_parent, ws.c_arrive, ws.ccell,
         ws.c_crmax);
