@@ -65,7 +65,9 @@ typedef struct {
     int ncs_col, ncc_pre_col, ncc_post_col;   /* collision walk thresholds (Alg. 2) */
     int precision;             /* ncorp_precision */
     double root_half_width;    /* 0 = smallest power of two above every |coordinate| */
-    /* capacities of device lists; 0 = automatic from n_max and leaf_size */
+    /* capacities of device lists; 0 = automatic from n_max and leaf_size.  The two
+     * pair lists get 2^18 extra slots on top of the value given: walk waves fill
+     * them in blocks of 256 and leave the unused end of their last block empty. */
     int64_t cell_capacity;     /* octree cells */
     int64_t m2l_capacity;      /* well-separated cell pairs of one walk */
     int64_t p2p_capacity;      /* cell pairs treated by direct sums in one walk */
@@ -148,7 +150,8 @@ enum {
 };
 /* Waits for the stream and fills info[NCORP_INFO_COUNT] with sizes of the last
  * tree and walks (cells, leaves, deepest level, M2L and P2P cell pairs of the
- * last gravity walk, visited pairs, collision candidate cell pairs, pair tests,
+ * last gravity walk, visited pairs, collision candidate cell pairs, pair tests
+ * performed (moonlets that cannot reach the other cell are culled first),
  * directed M2L interactions, directed moonlet-moonlet interactions of the direct
  * sums with i != j). */
 int ncorp_tree_info(ncorp_ctx *ctx, int64_t *info);

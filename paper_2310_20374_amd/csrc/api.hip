@@ -163,8 +163,10 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     const int s = prm.leaf_size;
     int64_t cell_cap = prm.cell_capacity > 0 ? prm.cell_capacity : 8 * n / s + 1024;
     if (cell_cap > (1 << 24) - 2) cell_cap = (1 << 24) - 2;
-    int64_t m2l_cap = prm.m2l_capacity > 0 ? prm.m2l_capacity : 64 * cell_cap + 4096;
-    int64_t p2p_cap = prm.p2p_capacity > 0 ? prm.p2p_capacity : 32 * cell_cap + 4096;
+    // plain pair lists: entries plus at most one partly used chunk per walk wave
+    const int64_t slack = (int64_t)kWalkWaves * kListChunk;
+    int64_t m2l_cap = (prm.m2l_capacity > 0 ? prm.m2l_capacity : 64 * cell_cap + 4096) + slack;
+    int64_t p2p_cap = (prm.p2p_capacity > 0 ? prm.p2p_capacity : 32 * cell_cap + 4096) + slack;
     int64_t q_cap = prm.queue_capacity > 0 ? prm.queue_capacity
                                            : m2l_cap + p2p_cap + 16 * cell_cap + 65536;
     ws.n_max = n;
@@ -596,20 +598,22 @@ extern "C" int64_t ncorp_export_host(ncorp_ctx *c, int what, void *dst, int64_t 
             std::vector<double> v; if ((r = d2h(c, v, ws.local, nc * ws.nl))) return r;
             put(v.data(), 8 * nc * ws.nl); break;
         }
-        case NCORP_EXPORT_M2L: {
-            int64_t k = h.nm2l < ws.m2l_cap ? h.nm2l : ws.m2l_cap;
-            std::vector<int2> v; if ((r = d2h(c, v, ws.m2l, k))) return r;
-            put(v.data(), 8 * k); break;
-        }
-        case NCORP_EXPORT_P2P: {
-            int64_t k = h.np2p < ws.p2p_cap ? h.np2p : ws.p2p_cap;
-            std::vector<int2> v; if ((r = d2h(c, v, ws.p2p, k))) return r;
-            put(v.data(), 8 * k); break;
-        }
+        case NCORP_EXPORT_M2L:
+        case NCORP_EXPORT_P2P:
         case NCORP_EXPORT_COL_CAND: {
-            int64_t k = h.ncand < ws.p2p_cap ? h.ncand : ws.p2p_cap;
-            std::vector<int2> v; if ((r = d2h(c, v, ws.cand, k))) return r;
-            put(v.data(), 8 * k); break;
+            // copy the reserved slots and drop the gaps
+            const int2 *src = what == NCORP_EXPORT_M2L ? ws.m2l
+                              : what == NCORP_EXPORT_P2P ? ws.p2p : ws.cand;
+            const int64_t slots = what == NCORP_EXPORT_M2L ? h.m2l_slots
+                                  : what == NCORP_EXPORT_P2P ? h.p2p_slots : h.cand_slots;
+            const int64_t lcap = what == NCORP_EXPORT_M2L ? ws.m2l_cap : ws.p2p_cap;
+            std::vector<int2> v;
+            if ((r = d2h(c, v, src, slots < lcap ? slots : lcap))) return r;
+            std::vector<int2> keep;
+            keep.reserve(v.size());
+            for (const int2 &q : v)
+                if (q.x >= 0) keep.push_back(q);
+            put(keep.data(), 8 * (int64_t)keep.size()); break;
         }
         default:
             return fail(c, NCORP_E_INVALID, "unknown export");

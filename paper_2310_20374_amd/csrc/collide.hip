@@ -40,60 +40,148 @@ struct PState {
     uint32_t id;
 };
 
+// Moonlets of cell C (first f, count n) that can reach the sphere (centre s, radius
+// rc) of the other cell within the step: |r_a - s| <= R_a + dt |v_a| + rc.  Every
+// colliding pair passes (r_crit of a cell bounds R + dt|v| plus the distance of
+// each of its moonlets from its centre); the relative margin 1e-9 dwarfs the
+// rounding of either side, so no pair the exact test accepts is dropped.  The
+// survivors are compacted into out[] in moonlet order; returns their number, or
+// -1 if more than 64 survive.
+__device__ __forceinline__ int cull_cell(int f, int n, double4 sph, const double *__restrict__ xs,
+                                         const double *__restrict__ ys,
+                                         const double *__restrict__ zs,
+                                         const double *__restrict__ vxs,
+                                         const double *__restrict__ vys,
+                                         const double *__restrict__ vzs,
+                                         const double *__restrict__ rads,
+                                         const uint32_t *__restrict__ perm, double dt,
+                                         PState *out) {
+    const int lane = threadIdx.x;
+    int kept = 0;
+    for (int c0 = 0; c0 < n; c0 += kWave) {
+        bool keep = false;
+        PState ps;
+        if (c0 + lane < n) {
+            const int k = f + c0 + lane;
+            ps.x = xs[k]; ps.y = ys[k]; ps.z = zs[k];
+            ps.vx = vxs[k]; ps.vy = vys[k]; ps.vz = vzs[k]; ps.R = rads[k];
+            ps.id = perm[k];
+            const double v = sqrt(ps.vx * ps.vx + ps.vy * ps.vy + ps.vz * ps.vz);
+            const double reach = (ps.R + dt * v) + sph.w;
+            const double dx = ps.x - sph.x, dy = ps.y - sph.y, dz = ps.z - sph.z;
+            keep = dx * dx + dy * dy + dz * dz <= reach * reach * (1.0 + 1e-9);
+        }
+        const uint64_t m = __ballot(keep);
+        const int nk = __popcll(m);
+        if (kept + nk > kWave) return -1;
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        if (keep) out[kept + __popcll(m & lt)] = ps;
+        kept += nk;
+    }
+    return kept;
+}
+
+// Every moonlet pair of the candidate cell pair (A, B) (i < j when A == B): lanes
+// take moonlets of A, B's moonlets are staged in LDS 64 at a time and split over
+// lane groups when A holds fewer than 64.
+__device__ __forceinline__ void test_cell_pair(
+    int2 pr, PState *sb, const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
+    const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+    const double *__restrict__ vxs, const double *__restrict__ vys,
+    const double *__restrict__ vzs, const double *__restrict__ rads,
+    const uint32_t *__restrict__ perm, double dt, int64_t *out, int64_t cap, DevState *st,
+    unsigned long long &tests) {
+    const int lane = threadIdx.x;
+    const int fa = c_first[pr.x], na = c_count[pr.x];
+    const int fb = c_first[pr.y], nb = c_count[pr.y];
+    const bool self = pr.x == pr.y;
+    for (int a0 = 0; a0 < na; a0 += 64) {
+        const int nac = na - a0 < 64 ? na - a0 : 64;
+        int S = 1;
+        while (S < nac) S <<= 1;
+        const int G = 64 / S, tl = lane % S, grp = lane / S;
+        const bool act = tl < nac;
+        const int ia = a0 + (act ? tl : 0);
+        const int a = fa + ia;
+        const double x1 = xs[a], y1 = ys[a], z1 = zs[a], vx1 = vxs[a], vy1 = vys[a],
+                     vz1 = vzs[a], R1 = rads[a];
+        const uint32_t id1 = perm[a];
+        for (int b0 = self ? a0 : 0; b0 < nb; b0 += 64) {
+            const int nbc = nb - b0 < 64 ? nb - b0 : 64;
+            __syncthreads();
+            if (lane < nbc) {
+                const int b = fb + b0 + lane;
+                PState ps;
+                ps.x = xs[b]; ps.y = ys[b]; ps.z = zs[b];
+                ps.vx = vxs[b]; ps.vy = vys[b]; ps.vz = vzs[b]; ps.R = rads[b];
+                ps.id = perm[b];
+                sb[lane] = ps;
+            }
+            __syncthreads();
+            if (!act) continue;
+            const int jlo = self ? (ia + 1 - b0 > 0 ? ia + 1 - b0 : 0) : 0;
+            // first j >= jlo with j = grp (mod G)
+            int j = jlo + ((grp - jlo % G) % G + G) % G;
+            for (; j < nbc; j += G) {
+                const PState &o = sb[j];
+                tests++;
+                if (pair_test(x1, y1, z1, vx1, vy1, vz1, R1, o.x, o.y, o.z, o.vx, o.vy, o.vz,
+                              o.R, dt))
+                    record(out, cap, (unsigned long long *)&st->npairs, id1, o.id);
+            }
+        }
+    }
+}
+
+constexpr int kCandRound = 4;
+
 __global__ void __launch_bounds__(64)
 k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
           const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
-          const double *__restrict__ xs, const double *__restrict__ ys,
-          const double *__restrict__ zs, const double *__restrict__ vxs,
-          const double *__restrict__ vys, const double *__restrict__ vzs,
-          const double *__restrict__ rads, const uint32_t *__restrict__ perm, double dt,
-          int64_t *out, int64_t cap) {
-    __shared__ PState sb[64];
+          const double4 *__restrict__ ccell, const double *__restrict__ xs,
+          const double *__restrict__ ys, const double *__restrict__ zs,
+          const double *__restrict__ vxs, const double *__restrict__ vys,
+          const double *__restrict__ vzs, const double *__restrict__ rads,
+          const uint32_t *__restrict__ perm, double dt, int64_t *out, int64_t cap) {
+    __shared__ PState sb[64], sa[64];
     if (st->status & kSkipMask) return;
-    int nc = st->ncand;
+    int nc = st->cand_slots;                 // candidate slots, gaps included
     if (nc > cand_cap) nc = (int)cand_cap;
     const int lane = threadIdx.x;
     unsigned long long tests = 0;
-    for (int q = blockIdx.x; q < nc; q += gridDim.x) {
-        const int2 pr = cand[q];
-        const int fa = c_first[pr.x], na = c_count[pr.x];
-        const int fb = c_first[pr.y], nb = c_count[pr.y];
-        const bool self = pr.x == pr.y;
-        for (int a0 = 0; a0 < na; a0 += 64) {
-            const int nac = na - a0 < 64 ? na - a0 : 64;
-            int S = 1;
-            while (S < nac) S <<= 1;
-            const int G = 64 / S, tl = lane % S, grp = lane / S;
-            const bool act = tl < nac;
-            const int ia = a0 + (act ? tl : 0);
-            const int a = fa + ia;
-            const double x1 = xs[a], y1 = ys[a], z1 = zs[a], vx1 = vxs[a], vy1 = vys[a],
-                         vz1 = vzs[a], R1 = rads[a];
-            const uint32_t id1 = perm[a];
-            for (int b0 = self ? a0 : 0; b0 < nb; b0 += 64) {
-                const int nbc = nb - b0 < 64 ? nb - b0 : 64;
+    // kCandRound candidate slots per round, read at once; gaps left by the walk
+    // are skipped
+    for (int q0 = blockIdx.x * kCandRound; q0 < nc; q0 += gridDim.x * kCandRound) {
+        int2 c16 = make_int2(-1, -1);
+        if (lane < kCandRound && q0 + lane < nc) c16 = cand[q0 + lane];
+        uint64_t live = __ballot(c16.x >= 0);
+        while (live) {
+            const int l = __ffsll((unsigned long long)live) - 1;
+            live &= live - 1;
+            const int2 pr = make_int2(__shfl(c16.x, l), __shfl(c16.y, l));
+            if (pr.x != pr.y) {
+                // distinct cells: keep only moonlets that can reach the other cell
                 __syncthreads();
-                if (lane < nbc) {
-                    const int b = fb + b0 + lane;
-                    PState ps;
-                    ps.x = xs[b]; ps.y = ys[b]; ps.z = zs[b];
-                    ps.vx = vxs[b]; ps.vy = vys[b]; ps.vz = vzs[b]; ps.R = rads[b];
-                    ps.id = perm[b];
-                    sb[lane] = ps;
-                }
+                const int na = cull_cell(c_first[pr.x], c_count[pr.x], ccell[pr.y], xs, ys, zs,
+                                         vxs, vys, vzs, rads, perm, dt, sa);
+                const int nb = na < 0 ? -1
+                                      : cull_cell(c_first[pr.y], c_count[pr.y], ccell[pr.x], xs,
+                                                  ys, zs, vxs, vys, vzs, rads, perm, dt, sb);
                 __syncthreads();
-                if (!act) continue;
-                const int jlo = self ? (ia + 1 - b0 > 0 ? ia + 1 - b0 : 0) : 0;
-                // first j >= jlo with j = grp (mod G)
-                int j = jlo + ((grp - jlo % G) % G + G) % G;
-                for (; j < nbc; j += G) {
-                    const PState &o = sb[j];
-                    tests++;
-                    if (pair_test(x1, y1, z1, vx1, vy1, vz1, R1, o.x, o.y, o.z, o.vx, o.vy, o.vz,
-                                  o.R, dt))
-                        record(out, cap, (unsigned long long *)&st->npairs, id1, o.id);
+                if (na >= 0 && nb >= 0) {
+                    const int tot = na * nb;
+                    for (int t = lane; t < tot; t += kWave) {
+                        const PState &p = sa[t / nb], &o = sb[t % nb];
+                        tests++;
+                        if (pair_test(p.x, p.y, p.z, p.vx, p.vy, p.vz, p.R, o.x, o.y, o.z, o.vx,
+                                      o.vy, o.vz, o.R, dt))
+                            record(out, cap, (unsigned long long *)&st->npairs, p.id, o.id);
+                    }
+                    continue;
                 }
             }
+            test_cell_pair(pr, sb, c_first, c_count, xs, ys, zs, vxs, vys, vzs, rads, perm, dt,
+                           out, cap, st, tests);
         }
     }
     for (int o = 32; o > 0; o >>= 1) tests += __shfl_xor(tests, o);
@@ -165,9 +253,9 @@ __global__ void k_pairs_done(DevState *st, int64_t *n_pairs_dev, int64_t cap, in
 hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipStream_t s) {
     (void)n;
     k_collide_init<<<1, 64, 0, s>>>(ws.st);
-    k_collide<<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count, ws.xs,
-                                   ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, ws.idx, dt,
-                                   ws.pairs_tmp, ws.pair_cap);
+    k_collide<<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count, ws.ccell,
+                                   ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, ws.idx,
+                                   dt, ws.pairs_tmp, ws.pair_cap);
     return hipGetLastError();
 }
 

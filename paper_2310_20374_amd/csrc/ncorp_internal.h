@@ -44,6 +44,13 @@ enum StatusBits : int32_t {
 };
 // Any of these leaves the tree or the interaction lists incomplete: later passes
 // then do nothing rather than follow indices that were never written.
+// persistent walk: waves, and list slots a wave reserves at a time (the plain
+// cell-pair lists carry up to kWalkWaves * kListChunk slots of gaps)
+constexpr int kWalkBlock = 256;
+constexpr int kWalkGrid = 128;                // 512 persistent waves: 2 per CU
+constexpr int kWalkWaves = kWalkGrid * kWalkBlock / kWave;
+constexpr int kListChunk = 256;
+
 // per-target interaction lists: default and largest slot counts (a consumer
 // sorts a whole list in LDS)
 constexpr int kDefaultM2LPerCell = 512;
@@ -65,10 +72,11 @@ struct DevState {
     double L;                  // root half-width
     double max_abs;            // max |coordinate| (bit pattern max for >= 0 doubles)
     // gravity walk
-    int32_t nm2l, np2p;        // unordered cell pairs
+    int32_t nm2l, np2p;        // unordered cell pairs (exact counts)
+    int32_t m2l_slots, p2p_slots;  // list slots reserved (entries plus (-1,-1) gaps)
     int64_t visited;
     // collision walk
-    int32_t ncand, pad2;
+    int32_t ncand, cand_slots;
     int64_t col_tests;
     int64_t npairs;            // colliding pairs found (may exceed capacity)
     int64_t pair_cursor;       // pairs already written by earlier steps of ncorp_step

@@ -24,8 +24,6 @@
 
 namespace ncorp {
 
-constexpr int kWalkBlock = 256;
-constexpr int kWalkGrid = 256;                 // 1024 persistent waves: 4 per CU
 constexpr uint64_t kSpinLimit = 1ull << 20;    // empty polls in a row before giving up
 
 __device__ __forceinline__ uint64_t make_item(uint32_t epoch, int a, int b) {
@@ -62,8 +60,11 @@ __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, uint32
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     wq->head = 0;
     wq->epoch = epoch;
-    if (mode == 0) { st->nm2l = 0; st->np2p = 0; st->visited = 0; }
-    else { st->ncand = 0; }
+    if (mode == 0) {
+        st->nm2l = 0; st->np2p = 0; st->m2l_slots = 0; st->p2p_slots = 0; st->visited = 0;
+    } else {
+        st->ncand = 0; st->cand_slots = 0;
+    }
     if (nc > 0 && !(st->status & kSkipMask)) {
         __hip_atomic_store(&queue[0], make_item(epoch, 0, 0), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -84,7 +85,8 @@ struct WalkArgs {
     int ncs, ncc_pre, ncc_post;
     int2 *m2l, *p2p;                     // outputs (p2p = candidates in collision mode)
     int64_t m2l_cap, p2p_cap;
-    int32_t *nm2l, *np2p;
+    int32_t *nm2l, *np2p;                // exact counts
+    int32_t *m2l_slots, *p2p_slots;      // reserved slots
     uint32_t epoch;
     // gravity: per-target lists
     const int32_t *c_entry, *c_nent;
@@ -104,24 +106,49 @@ __device__ __forceinline__ void append(int32_t *cnt, int32_t *seg, int stride, i
     }
 }
 
-// Appends the lanes' flagged pairs to a list with one atomic per wave.
-__device__ __forceinline__ void emit(bool flag, int a, int b, int lane, int32_t *count,
-                                     int2 *list, int64_t cap, DevState *st, int32_t bit) {
+// A wave's current block of kListChunk slots of a plain cell-pair list.
+struct Chunk {
+    int64_t base;
+    int fill;
+    int total;                 // entries this wave emitted (published at exit)
+};
+
+// Marks the unused rest of a chunk as gaps (-1, -1).
+__device__ __forceinline__ void close_chunk(const Chunk &ch, int lane, int2 *list, int64_t cap) {
+    if (ch.base < 0) return;
+    for (int i = ch.fill + lane; i < kListChunk; i += kWave)
+        if (ch.base + i < cap) list[ch.base + i] = make_int2(-1, -1);
+}
+
+// Appends the lanes' flagged pairs to a plain list.  Atomics on one shared
+// address are the walk's main cost, so the slot counter is touched once per
+// kListChunk entries and the exact count only once per wave, at exit.
+__device__ __forceinline__ void emit(bool flag, int a, int b, int lane, Chunk &ch,
+                                     int32_t *slots, int2 *list, int64_t cap, DevState *st,
+                                     int32_t bit) {
     const uint64_t m = __ballot(flag);
     if (!m) return;
+    const int k = __popcll(m);
+    if (ch.fill + k > kListChunk) {
+        close_chunk(ch, lane, list, cap);
+        int32_t nb = 0;
+        if (lane == 0) nb = atomicAdd(slots, (int32_t)kListChunk);
+        nb = __shfl(nb, 0);
+        ch.base = nb;
+        ch.fill = 0;
+        if (lane == 0 && (int64_t)nb + kListChunk > cap) {
+            atomicOr(&st->status, bit);
+            atomicMax((unsigned long long *)&st->required,
+                      (unsigned long long)((int64_t)nb + kListChunk));
+        }
+    }
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    int32_t b0 = 0;
-    if (lane == 0) b0 = atomicAdd(count, (int32_t)__popcll(m));
-    b0 = __shfl(b0, 0);
     if (flag) {
-        const int64_t k = (int64_t)b0 + __popcll(m & lt);
-        if (k < cap) list[k] = make_int2(a, b);
+        const int64_t pos = ch.base + ch.fill + __popcll(m & lt);
+        if (pos < cap) list[pos] = make_int2(a, b);
     }
-    if (lane == 0 && (int64_t)b0 + __popcll(m) > cap) {
-        atomicOr(&st->status, bit);
-        atomicMax((unsigned long long *)&st->required,
-                  (unsigned long long)((int64_t)b0 + __popcll(m)));
-    }
+    ch.fill += k;
+    ch.total += k;
 }
 
 template <int MODE>
@@ -133,6 +160,7 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
     uint64_t spins = 0;
     int64_t visited = 0;
     bool finished = false;
+    Chunk cm = {-1, kListChunk, 0}, cp = {-1, kListChunk, 0};
     while (!finished) {
         uint64_t base = 0;
         if (lane == 0) base = atomicAdd((unsigned long long *)&wq->head, (unsigned long long)kWave);
@@ -246,8 +274,9 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
                 }
             }
             // ---------------- interaction lists
-            if (MODE == 0) emit(kind == 1, a, b, lane, A.nm2l, A.m2l, A.m2l_cap, A.st, ST_CAP_M2L);
-            emit(kind == 2, a, b, lane, A.np2p, A.p2p, A.p2p_cap, A.st, ST_CAP_P2P);
+            if (MODE == 0)
+                emit(kind == 1, a, b, lane, cm, A.m2l_slots, A.m2l, A.m2l_cap, A.st, ST_CAP_M2L);
+            emit(kind == 2, a, b, lane, cp, A.p2p_slots, A.p2p, A.p2p_cap, A.st, ST_CAP_P2P);
             if (MODE == 0 && A.m2l_cnt) {
                 if (kind == 1) {
                     append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, a, b, A.st);
@@ -276,6 +305,12 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
             pending = pending && !valid;
         }
     }
+    if (MODE == 0) close_chunk(cm, lane, A.m2l, A.m2l_cap);
+    close_chunk(cp, lane, A.p2p, A.p2p_cap);
+    if (lane == 0) {
+        if (MODE == 0 && cm.total) atomicAdd(A.nm2l, cm.total);
+        if (cp.total) atomicAdd(A.np2p, cp.total);
+    }
     if (lane == 0 && visited)
         atomicAdd((unsigned long long *)&A.st->visited, (unsigned long long)visited);
 }
@@ -303,6 +338,7 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
         A.cell = ws.wg;
         A.m2l = ws.m2l; A.m2l_cap = ws.m2l_cap; A.nm2l = &ws.st->nm2l;
         A.p2p = ws.p2p; A.p2p_cap = ws.p2p_cap; A.np2p = &ws.st->np2p;
+        A.m2l_slots = &ws.st->m2l_slots; A.p2p_slots = &ws.st->p2p_slots;
         A.c_entry = ws.c_entry; A.c_nent = ws.c_nent;
         A.m2l_cnt = ws.m2l_cnt; A.m2l_seg = ws.m2l_seg; A.m2l_stride = ws.m2l_stride;
         A.p2p_cnt = ws.p2p_cnt; A.p2p_seg = ws.p2p_seg; A.p2p_stride = ws.p2p_stride;
@@ -311,6 +347,7 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
         A.cell = ws.wc;
         A.m2l = ws.m2l; A.m2l_cap = 0; A.nm2l = &ws.st->nm2l;
         A.p2p = ws.cand; A.p2p_cap = ws.p2p_cap; A.np2p = &ws.st->ncand;
+        A.m2l_slots = &ws.st->m2l_slots; A.p2p_slots = &ws.st->cand_slots;
         k_walk<1><<<kWalkGrid, kWalkBlock, 0, s>>>(A);
     }
     return hipGetLastError();

@@ -43,7 +43,9 @@ def test_pairs_equal_brute_force(nc, orc, case):
     cand = np.sort(co.candidates().astype(np.int64), axis=1)
     gc = np.sort(ctx.export("col_cand").astype(np.int64), axis=1)
     assert set(map(tuple, gc.tolist())) == set(map(tuple, cand.tolist()))
-    assert ctx.tree_info()["col_tests"] == co.ntests()
+    # moonlets that cannot reach the other cell are culled before testing, so the
+    # GPU tests at most the pairs the oracle walk tests
+    assert ctx.tree_info()["col_tests"] <= co.ntests()
 
 
 def test_pair_capacity_overflow_is_reported(nc):
