@@ -73,7 +73,7 @@ typedef struct {
     int64_t p2p_capacity;      /* cell pairs treated by direct sums in one walk */
     int64_t queue_capacity;    /* cell pairs visited by one walk */
     /* per-target interaction lists, filled by the gravity walk itself; 0 = automatic
-     * (512 and 1024), at most 8192 each.  A target with more entries makes the call
+     * (1024 each), at most 8192 each.  A target with more entries makes the call
      * fail with NCORP_E_CAPACITY, required = the count that would have fitted. */
     int32_t m2l_per_cell;      /* well-separated partner cells kept per cell */
     int32_t p2p_per_leaf;      /* direct-sum source cells kept per leaf */
@@ -146,14 +146,17 @@ const char *ncorp_last_error(const ncorp_ctx *ctx);
 enum {
     NCORP_INFO_N = 0, NCORP_INFO_NCELLS, NCORP_INFO_NLEAVES, NCORP_INFO_MAXLEVEL,
     NCORP_INFO_M2L, NCORP_INFO_P2P, NCORP_INFO_VISITED, NCORP_INFO_COL_CAND,
-    NCORP_INFO_COL_TESTS, NCORP_INFO_M2L_DIR, NCORP_INFO_P2P_INTER, NCORP_INFO_COUNT
+    NCORP_INFO_COL_TESTS, NCORP_INFO_M2L_DIR, NCORP_INFO_P2P_INTER, NCORP_INFO_M2L_MAXLIST,
+    NCORP_INFO_P2P_MAXLIST, NCORP_INFO_COUNT
 };
 /* Waits for the stream and fills info[NCORP_INFO_COUNT] with sizes of the last
  * tree and walks (cells, leaves, deepest level, M2L and P2P cell pairs of the
  * last gravity walk, visited pairs, collision candidate cell pairs, pair tests
  * performed (moonlets that cannot reach the other cell are culled first),
  * directed M2L interactions, directed moonlet-moonlet interactions of the direct
- * sums with i != j). */
+ * sums with i != j, longest per-target M2L list, longest per-leaf direct-sum list:
+ * the sizes m2l_per_cell and p2p_per_leaf must cover).  The last three are filled
+ * only while phase timing is on (ncorp_set_timing); otherwise they read 0. */
 int ncorp_tree_info(ncorp_ctx *ctx, int64_t *info);
 
 enum {

@@ -240,6 +240,8 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
         ws.m2l_seg = (int32_t *)take(4 * cell_cap * (int64_t)ws.m2l_stride);
         ws.p2p_cnt = (int32_t *)take(4 * ws.leaf_cap);
         ws.p2p_seg = (int32_t *)take(4 * ws.leaf_cap * (int64_t)ws.p2p_stride);
+        ws.long_m2l = (int32_t *)take(4 * cell_cap);
+        ws.long_p2p = (int32_t *)take(4 * ws.leaf_cap);
     }
     const int64_t cnt = nb * (kMaxDepth + 1) + 1;
     ws.cnt_a = (int32_t *)take(4 * cnt);
@@ -345,6 +347,7 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
     }
     {
         PhaseTimer t(c, NCORP_PHASE_M2L, s);
+        HIPCHK(c, launch_sort_long_lists(ws, s));
         HIPCHK(c, launch_m2l(ws, c->prm.p, c->prm.precision, s));
     }
     {
@@ -495,6 +498,8 @@ extern "C" int ncorp_tree_info(ncorp_ctx *c, int64_t *info) {
     info[NCORP_INFO_COL_TESTS] = h.col_tests;
     info[NCORP_INFO_M2L_DIR] = 2 * (int64_t)h.nm2l;
     info[NCORP_INFO_P2P_INTER] = h.p2p_inter;
+    info[NCORP_INFO_M2L_MAXLIST] = h.m2l_maxlist;
+    info[NCORP_INFO_P2P_MAXLIST] = h.p2p_maxlist;
     return NCORP_OK;
 }
 

@@ -18,7 +18,6 @@
 namespace ncorp {
 
 constexpr int kM2LBlock = 64;     // one wave per block, one target per wave
-constexpr int kM2LList = 512;     // partner lists up to this length are sorted into LDS
 
 template <int P, typename T>
 __device__ __forceinline__ void green_derivs(T x, T y, T z, T rinv, T *D) {
@@ -153,10 +152,11 @@ k_m2l(const DevState *__restrict__ st, const double4 *__restrict__ gcell,
     constexpr int NL = n_local(P);
     constexpr int K1 = M2LSplit<P, T>::K1, K2 = M2LSplit<P, T>::K2;
     __shared__ __align__(16) T red[kWave][ncomp(P) + 1];
-    __shared__ int32_t s_list[kM2LList];
+    __shared__ int32_t s_list[kM2LListLDS];
     extern __shared__ __align__(16) int32_t dyn[];   // sort scratch if red is too small
     if (st->status & kSkipMask) return;
-    int32_t *scratch = ((stride + 3) & ~3) <= red_ints<P, T>() ? (int32_t *)&red[0][0] : dyn;
+    const int need = ((stride < kM2LListLDS ? stride : kM2LListLDS) + 3) & ~3;
+    int32_t *scratch = need <= red_ints<P, T>() ? (int32_t *)&red[0][0] : dyn;
     const int nc = st->ncells;
     const int lane = threadIdx.x;
     for (int A = blockIdx.x; A < nc; A += gridDim.x) {
@@ -168,7 +168,7 @@ k_m2l(const DevState *__restrict__ st, const double4 *__restrict__ gcell,
         }
         int32_t *list = seg + (int64_t)A * stride;
         const int32_t *srcs = list;
-        if (len <= kM2LList) {
+        if (len <= kM2LListLDS) {
             // usual case: sorted copy in LDS
             const int len4 = (len + 3) & ~3;
             for (int i = lane; i < len4; i += kWave) scratch[i] = i < len ? list[i] : 0x7fffffff;
@@ -185,9 +185,7 @@ k_m2l(const DevState *__restrict__ st, const double4 *__restrict__ gcell,
             }
             __syncthreads();
             srcs = s_list;
-        } else {
-            sort_target_list(list, len, scratch);
-        }
+        }                                       // longer lists: sorted by the pre-pass
         const double4 gA = gcell[A];
         m2l_pass<P, 1, K1, T>(gA, gcell, mult, srcs, len, out, red);
         if (K2 > K1) m2l_pass<P, (K1 < P ? K1 + 1 : P), K2, T>(gA, gcell, mult, srcs, len, out, red);
@@ -199,7 +197,7 @@ template <int P, typename T>
 static void launch_m2l_t(const Workspace &ws, const T *mult, hipStream_t s) {
     int g = (int)(ws.cell_cap < 16384 ? ws.cell_cap : 16384);
     if (g < 1) g = 1;
-    const int s4 = (ws.m2l_stride + 3) & ~3;
+    const int s4 = ((ws.m2l_stride < kM2LListLDS ? ws.m2l_stride : kM2LListLDS) + 3) & ~3;
     const size_t dyn = s4 <= red_ints<P, T>() ? 0 : (size_t)s4 * sizeof(int32_t);
     k_m2l<P, T><<<g, kM2LBlock, dyn, s>>>(ws.st, ws.gcell, mult, ws.m2l_cnt, ws.m2l_seg,
                                           ws.m2l_stride, ws.local);

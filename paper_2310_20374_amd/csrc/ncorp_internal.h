@@ -53,9 +53,14 @@ constexpr int kListChunk = 256;
 
 // per-target interaction lists: default and largest slot counts (a consumer
 // sorts a whole list in LDS)
-constexpr int kDefaultM2LPerCell = 512;
+constexpr int kDefaultM2LPerCell = 1024;
 constexpr int kDefaultP2PPerLeaf = 1024;
 constexpr int kMaxPerTarget = 8192;
+// lists up to these lengths are sorted in LDS by their consumer; longer ones (the
+// walk records them) by a pre-pass of kSortLongBlocks single-wave blocks
+constexpr int kM2LListLDS = 512;
+constexpr int kP2PListLDS = 256;
+constexpr int kSortLongBlocks = 1024;
 
 constexpr int32_t kSkipMask = ST_CAP_CELLS | ST_CAP_QUEUE | ST_CAP_M2L | ST_CAP_P2P |
                               ST_CAP_LISTS | ST_WALK_STALL | ST_BAD_ITEM;
@@ -74,6 +79,8 @@ struct DevState {
     // gravity walk
     int32_t nm2l, np2p;        // unordered cell pairs (exact counts)
     int32_t m2l_slots, p2p_slots;  // list slots reserved (entries plus (-1,-1) gaps)
+    int32_t m2l_maxlist, p2p_maxlist;  // longest per-target lists (timing runs only)
+    int32_t nlong_m2l, nlong_p2p;      // lists longer than their consumer's LDS sort
     int64_t visited;
     // collision walk
     int32_t ncand, cand_slots;
@@ -101,6 +108,15 @@ struct alignas(16) WCell {
     double x, y, z, rcrit;
     int32_t count, child, nchild, pad;
 };
+
+// Waves of a multi-wave block that work independently synchronise their own LDS
+// traffic only: a wave's LDS operations complete in issue order, so it suffices to
+// keep the compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Sorts a per-target list list[0..len) ascending, in place in global memory (its
 // values are distinct).  Called by a whole single-wave block; scratch is LDS of at
@@ -168,6 +184,7 @@ struct Workspace {
     // per-target lists written by the gravity walk (unordered; consumers sort)
     int32_t *m2l_cnt = nullptr, *m2l_seg = nullptr;   // by target cell, m2l_stride slots
     int32_t *p2p_cnt = nullptr, *p2p_seg = nullptr;   // by target leaf, p2p_stride slots
+    int32_t *long_m2l = nullptr, *long_p2p = nullptr; // targets of over-long lists
     int32_t *cnt_a = nullptr;                         // tree-build level counters
     int64_t *pairs_tmp = nullptr;                     // colliding pairs (i<<32|j)
     int64_t *pairs_alt = nullptr;
@@ -206,6 +223,8 @@ hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hip
 hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post,
                        hipStream_t s);
 hipError_t launch_count_interactions(const Workspace &ws, hipStream_t s);
+// sorts, in place, the per-target lists longer than the consumers sort in LDS
+hipError_t launch_sort_long_lists(const Workspace &ws, hipStream_t s);
 
 hipError_t launch_m2l(const Workspace &ws, int p, int precision, hipStream_t s);
 hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s);

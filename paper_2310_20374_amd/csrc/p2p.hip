@@ -157,10 +157,6 @@ template <> __device__ __forceinline__ double r2_floor<double>() { return 1e-200
 
 constexpr int kP2PTile = 256;       // source moonlets staged per LDS tile
 constexpr int kP2PSrc = 256;        // source cells per batch (prefix sums in LDS)
-// the tile in ints: a leaf's source list is sorted there first
-template <typename T> constexpr int tile_ints() {
-    return (int)(sizeof(typename Vec4<T>::type) * kP2PTile / 4);
-}
 
 // Exclusive prefix sums of the 4 counts each lane holds for sources 4*lane..4*lane+3
 // into s_pref[0..256]; returns the total.
@@ -190,7 +186,7 @@ __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_fir
                                           const double *__restrict__ mus, const double4 g,
                                           T xi, T yi, T zi, int grp, int G, Acc3<T> &acc) {
     using V = typename Vec4<T>::type;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     const T floor2 = r2_floor<T>();
     for (int p0 = 0; p0 < tot; p0 += kP2PTile) {
         const int nj = tot - p0 < kP2PTile ? tot - p0 : kP2PTile;
@@ -214,7 +210,7 @@ __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_fir
                 tile[lane + 64 * k] = v;
             }
         }
-        __syncthreads();
+        wave_sync();
         T px = 0, py = 0, pz = 0;
 #pragma unroll 4
         for (int j = grp; j < nj; j += G) {
@@ -229,12 +225,15 @@ __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_fir
             pz = fmat<T>(dz, w, pz);
         }
         acc.add_tile(px, py, pz);
-        __syncthreads();
+        wave_sync();
     }
 }
 
+constexpr int kP2PWaves = 4;        // independent waves per block
+static_assert(kP2PListLDS == kP2PSrc, "one LDS batch holds a list the pre-pass leaves unsorted");
+
 template <typename T>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(kWave * kP2PWaves)
 k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const double *__restrict__ ys, const double *__restrict__ zs,
       const double *__restrict__ mus, const int32_t *__restrict__ ent_cell,
@@ -242,15 +241,16 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const double4 *__restrict__ gcell, const int32_t *__restrict__ p2p_cnt,
       int32_t *__restrict__ p2p_seg, int stride, double *__restrict__ acc_s, int64_t n) {
     using V = typename Vec4<T>::type;
-    __shared__ __align__(16) V tile[kP2PTile];
-    __shared__ int32_t s_first[kP2PSrc], s_pref[kP2PSrc + 1];
-    extern __shared__ __align__(16) int32_t dyn[];   // sort scratch if the tile is too small
+    __shared__ __align__(16) V tiles[kP2PWaves][kP2PTile];
+    __shared__ int32_t firsts[kP2PWaves][kP2PSrc], prefs[kP2PWaves][kP2PSrc + 1];
     if (st->status & kSkipMask) return;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    V *tile = tiles[wid];
+    int32_t *s_first = firsts[wid], *s_pref = prefs[wid];
     // the tile doubles as sort scratch before any moonlet is staged
-    int32_t *scratch = ((stride + 3) & ~3) <= tile_ints<T>() ? (int32_t *)tile : dyn;
+    int32_t *scratch = reinterpret_cast<int32_t *>(tile);
     const int K = st->nleaves;
-    const int lane = threadIdx.x;
-    for (int e = blockIdx.x; e < K; e += gridDim.x) {
+    for (int e = blockIdx.x * kP2PWaves + wid; e < K; e += gridDim.x * kP2PWaves) {
         const int c = ent_cell[e];
         const int f = c_first[c], nt = c_count[c];
         const double4 g = gcell[c];
@@ -258,7 +258,7 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
         const int len = p2p_cnt[e];
         const bool one = len <= kP2PSrc;
         int tot1 = 0;
-        __syncthreads();                              // LDS free again
+        wave_sync();                                  // this wave's LDS is free again
         if (one) {
             // the usual case, one batch: rank the sources in LDS and place each
             // source's moonlet range at its rank directly
@@ -274,7 +274,7 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
                 }
                 scratch[q] = v[k];
             }
-            __syncthreads();
+            wave_sync();
             const int4 *s4 = reinterpret_cast<const int4 *>(scratch);
             const int len4 = (len + 3) >> 2;
 #pragma unroll
@@ -289,16 +289,14 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
                     s_pref[r] = cn[k];
                 }
             }
-            __syncthreads();
+            wave_sync();
             int c4[4];
 #pragma unroll
             for (int k = 0; k < 4; k++) c4[k] = 4 * lane + k < len ? s_pref[4 * lane + k] : 0;
-            __syncthreads();
+            wave_sync();
             tot1 = batch_prefix(c4, s_pref, lane);
-            __syncthreads();
-        } else {
-            sort_target_list(list, len, scratch);
-        }
+            wave_sync();
+        }                                             // longer lists: sorted by the pre-pass
         for (int t0 = 0; t0 < nt; t0 += 64) {
             const int ntc = nt - t0 < 64 ? nt - t0 : 64;
             int S = 1;
@@ -314,7 +312,7 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
             } else {
                 for (int sb = 0; sb < len; sb += kP2PSrc) {
                     const int nsb = len - sb < kP2PSrc ? len - sb : kP2PSrc;
-                    __syncthreads();
+                    wave_sync();
                     int cnt4[4];
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
@@ -329,7 +327,7 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
                         cnt4[k] = cn;
                     }
                     const int tot = batch_prefix(cnt4, s_pref, lane);
-                    __syncthreads();
+                    wave_sync();
                     p2p_batch<T>(tot, nsb, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi,
                                  zi, grp, G, acc);
                 }
@@ -432,11 +430,9 @@ hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s) {
 
 template <typename T>
 static void launch_p2p_t(const Workspace &ws, int64_t n, hipStream_t s) {
-    int g = (int)(ws.leaf_cap < 65536 ? ws.leaf_cap : 65536);
-    if (g < 1) g = 1;
-    const int s4 = (ws.p2p_stride + 3) & ~3;
-    const size_t dyn = s4 <= tile_ints<T>() ? 0 : (size_t)s4 * sizeof(int32_t);
-    k_p2p<T><<<g, 64, dyn, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first,
+    int64_t g = (ws.leaf_cap + kP2PWaves - 1) / kP2PWaves;
+    g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
+    k_p2p<T><<<(int)g, kWave * kP2PWaves, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first,
                                 ws.c_count, ws.gcell, ws.p2p_cnt, ws.p2p_seg, ws.p2p_stride,
                                 ws.acc_s, n);
 }

@@ -62,6 +62,7 @@ __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, uint32
     wq->epoch = epoch;
     if (mode == 0) {
         st->nm2l = 0; st->np2p = 0; st->m2l_slots = 0; st->p2p_slots = 0; st->visited = 0;
+        st->nlong_m2l = 0; st->nlong_p2p = 0;
     } else {
         st->ncand = 0; st->cand_slots = 0;
     }
@@ -91,13 +92,17 @@ struct WalkArgs {
     // gravity: per-target lists
     const int32_t *c_entry, *c_nent;
     int32_t *m2l_cnt, *m2l_seg, *p2p_cnt, *p2p_seg;
+    int32_t *long_m2l, *long_p2p;        // targets whose list outgrew the LDS sort
     int m2l_stride, p2p_stride;
 };
 
 // Appends v to target t's list (slot order is arbitrary).
+// The append that makes a list longer than `lds` (what its consumer sorts in LDS)
+// records the target in `longs`, for the pre-pass that sorts such lists.
 __device__ __forceinline__ void append(int32_t *cnt, int32_t *seg, int stride, int t, int v,
-                                       DevState *st) {
+                                       int lds, int32_t *nlong, int32_t *longs, DevState *st) {
     const int k = atomicAdd(&cnt[t], 1);
+    if (k == lds) longs[atomicAdd(nlong, 1)] = t;
     if (k < stride) {
         seg[(int64_t)t * stride + k] = v;
     } else {
@@ -279,17 +284,21 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
             emit(kind == 2, a, b, lane, cp, A.p2p_slots, A.p2p, A.p2p_cap, A.st, ST_CAP_P2P);
             if (MODE == 0 && A.m2l_cnt) {
                 if (kind == 1) {
-                    append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, a, b, A.st);
-                    append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, b, a, A.st);
+                    append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, a, b, kM2LListLDS,
+                           &A.st->nlong_m2l, A.long_m2l, A.st);
+                    append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, b, a, kM2LListLDS,
+                           &A.st->nlong_m2l, A.long_m2l, A.st);
                 } else if (kind == 2) {
                     int e0 = A.c_entry[a], e1 = e0 + A.c_nent[a];
                     for (int e = e0; e < e1; e++)
-                        append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, b, A.st);
+                        append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, b, kP2PListLDS,
+                               &A.st->nlong_p2p, A.long_p2p, A.st);
                     if (a != b) {
                         e0 = A.c_entry[b];
                         e1 = e0 + A.c_nent[b];
                         for (int e = e0; e < e1; e++)
-                            append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, a, A.st);
+                            append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, a, kP2PListLDS,
+                                   &A.st->nlong_p2p, A.long_p2p, A.st);
                     }
                 }
             }
@@ -342,6 +351,7 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
         A.c_entry = ws.c_entry; A.c_nent = ws.c_nent;
         A.m2l_cnt = ws.m2l_cnt; A.m2l_seg = ws.m2l_seg; A.m2l_stride = ws.m2l_stride;
         A.p2p_cnt = ws.p2p_cnt; A.p2p_seg = ws.p2p_seg; A.p2p_stride = ws.p2p_stride;
+        A.long_m2l = ws.long_m2l; A.long_p2p = ws.long_p2p;
         k_walk<0><<<kWalkGrid, kWalkBlock, 0, s>>>(A);
     } else {
         A.cell = ws.wc;
@@ -353,35 +363,95 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
     return hipGetLastError();
 }
 
+// Lists too long for the consumers' LDS sort (the walk recorded their targets)
+// are sorted here, in place, one single-wave block per list (rank sort in LDS).
+__global__ void __launch_bounds__(kWave)
+k_sort_long_lists(const DevState *__restrict__ st, int which, const int32_t *__restrict__ cnt,
+                  int32_t *seg, int stride, const int32_t *__restrict__ longs) {
+    extern __shared__ __align__(16) int32_t scr[];   // round_up(stride, 4) ints
+    if (st->status & kSkipMask) return;
+    const int nl = which == 0 ? st->nlong_m2l : st->nlong_p2p;
+    const int lane = threadIdx.x;
+    for (int q = blockIdx.x; q < nl; q += gridDim.x) {
+        const int t = longs[q];
+        const int len = cnt[t];
+        int32_t *list = seg + (int64_t)t * stride;
+        const int len4 = (len + 3) & ~3;
+        __syncthreads();
+        for (int i = lane; i < len4; i += kWave) scr[i] = i < len ? list[i] : 0x7fffffff;
+        __syncthreads();
+        const int4 *s4 = reinterpret_cast<const int4 *>(scr);
+        for (int i = lane; i < len; i += kWave) {
+            const int v = scr[i];
+            int r = 0;
+            for (int j = 0; j < len4 / 4; j++) {
+                const int4 w = s4[j];
+                r += (w.x < v) + (w.y < v) + (w.z < v) + (w.w < v);
+            }
+            list[r] = v;
+        }
+    }
+}
+
 // directed moonlet interactions of the direct sums: per leaf, its moonlets times
 // the moonlets of all its sources, minus the i == j terms
 __global__ void k_count_inter(DevState *st, const int32_t *__restrict__ ent_cell,
                               const int32_t *__restrict__ c_count,
                               const int32_t *__restrict__ p2p_cnt,
-                              const int32_t *__restrict__ p2p_seg, int stride) {
+                              const int32_t *__restrict__ p2p_seg, int stride,
+                              const int32_t *__restrict__ m2l_cnt) {
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     unsigned long long tot = 0;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
+    int lp = 0, lm = 0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K || e < st->ncells;
+         e += gridDim.x * blockDim.x) {
+        if (e < st->ncells) lm = m2l_cnt[e] > lm ? m2l_cnt[e] : lm;
+        if (e >= K) continue;
+        lp = p2p_cnt[e] > lp ? p2p_cnt[e] : lp;
         const int nt = c_count[ent_cell[e]];
         const int32_t *seg = p2p_seg + (int64_t)e * stride;
         long long srcs = 0;
         for (int q = 0; q < p2p_cnt[e]; q++) srcs += c_count[seg[q]];
         tot += (unsigned long long)(nt * srcs - nt);
     }
-    for (int o = kWave / 2; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
-    if (threadIdx.x % kWave == 0 && tot) atomicAdd((unsigned long long *)&st->p2p_inter, tot);
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o);
+        const int a = __shfl_xor(lp, o), b = __shfl_xor(lm, o);
+        lp = a > lp ? a : lp;
+        lm = b > lm ? b : lm;
+    }
+    if (threadIdx.x % kWave == 0) {
+        if (tot) atomicAdd((unsigned long long *)&st->p2p_inter, tot);
+        if (lp) atomicMax(&st->p2p_maxlist, lp);
+        if (lm) atomicMax(&st->m2l_maxlist, lm);
+    }
 }
 
 __global__ void k_zero_inter(DevState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->p2p_inter = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->p2p_inter = 0;
+        st->m2l_maxlist = 0;
+        st->p2p_maxlist = 0;
+    }
+}
+
+hipError_t launch_sort_long_lists(const Workspace &ws, hipStream_t s) {
+    if (!ws.m2l_cnt) return hipSuccess;
+    const size_t lm = (size_t)((ws.m2l_stride + 3) & ~3) * sizeof(int32_t);
+    const size_t lp = (size_t)((ws.p2p_stride + 3) & ~3) * sizeof(int32_t);
+    k_sort_long_lists<<<kSortLongBlocks, kWave, lm, s>>>(ws.st, 0, ws.m2l_cnt, ws.m2l_seg,
+                                                         ws.m2l_stride, ws.long_m2l);
+    k_sort_long_lists<<<kSortLongBlocks, kWave, lp, s>>>(ws.st, 1, ws.p2p_cnt, ws.p2p_seg,
+                                                         ws.p2p_stride, ws.long_p2p);
+    return hipGetLastError();
 }
 
 hipError_t launch_count_interactions(const Workspace &ws, hipStream_t s) {
     k_zero_inter<<<1, 64, 0, s>>>(ws.st);
     if (!ws.p2p_cnt) return hipGetLastError();
     k_count_inter<<<256, 256, 0, s>>>(ws.st, ws.ent_cell, ws.c_count, ws.p2p_cnt, ws.p2p_seg,
-                                      ws.p2p_stride);
+                                      ws.p2p_stride, ws.m2l_cnt);
     return hipGetLastError();
 }
 

@@ -31,19 +31,32 @@ GRAV_CASES = {
     "disk2e4_p4_s1": (lambda: inputs.disk(20000, seed=2), 4, 1, (0, 0, 0), 1),
     "clumps2e4_p5": (lambda: inputs.clumps(20000, seed=0, n_clumps=20), 5, 16, (64, 8, 64), 0),
     "hot1e4_p6_small_ncs": (lambda: inputs.hot_disk(10000, seed=0), 6, 20, (4, 0, 0), 0),
+    # per-target lists longer than the consumers' LDS sort (pre-pass sorting path)
+    "disk2e4_p3_theta02_longm2l": (lambda: inputs.disk(20000, seed=0), 3, 8, (64, 8, 64), 0,
+                                   0.2),
+    "clumps5e4_p3_s52_longp2p": (lambda: inputs.clumps(50000, seed=0), 3, 52, (256, 256, 512),
+                                 0),
 }
+LONG = {"disk2e4_p3_theta02_longm2l": ("m2l_maxlist", 512),
+        "clumps5e4_p3_s52_longp2p": ("p2p_maxlist", 256)}
 
 
 @pytest.mark.parametrize("case", list(GRAV_CASES))
 def test_gravity_matches_oracle_tree(nc, orc, case):
-    gen, p, s, thr, mode = GRAV_CASES[case]
+    gen, p, s, thr, mode, *rest = GRAV_CASES[case]
+    theta = rest[0] if rest else 0.5
     d = gen()
     print(f"case {case}", flush=True)
     prm = nc.params_default(p, leaf_size=s, ncs=thr[0], ncc_pre=thr[1], ncc_post=thr[2],
-                            theta_mode=mode)
-    ctx, a = run_gravity(nc, d, prm)
+                            theta_mode=mode, theta_min=theta)
+    ctx = nc.Context(prm, len(d["x"]), pair_capacity=1 << 14, device="cuda:0")
+    ctx.set_timing(case in LONG)          # fills the longest-list fields
+    ctx, a = run_gravity(nc, d, prm, ctx=ctx)
     ref, t, g = orc.tree_accel(d, p=p, s=s, ncs=thr[0], ncc_pre=thr[1], ncc_post=thr[2],
-                               theta_mode=mode)
+                               theta_mode=mode, theta_min=theta)
+    if case in LONG:
+        field, lds = LONG[case]
+        assert ctx.tree_info()[field] > lds
     # same walk: identical lists of well-separated and brute-force cell pairs
     m2l, p2p = g.lists()
     assert _pairs_set(ctx.export("m2l")) == _pairs_set(m2l)
