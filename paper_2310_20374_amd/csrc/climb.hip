@@ -47,6 +47,10 @@ __device__ double far_corner(double sx, double sy, double sz, double px, double 
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+// moonlets whose scaled powers are staged in LDS at a time (a leaf holds at most
+// s of them, typically a few dozen)
+constexpr int kPowChunk = 32;
+
 // ---------------------------------------------------------------- wave helpers
 // Cell results are handed from wave to wave inside one launch: they are written
 // with agent-coherent stores and read back with agent-coherent loads, and a wave
@@ -160,8 +164,8 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
     constexpr int NM = n_mult(P);
     constexpr int NP = P > 1 ? P : 1;               // powers 0..P-1
     constexpr int NMS = NM > 0 ? NM : 1;
-    __shared__ double pw[kWave][3][NP];             // scaled powers per moonlet / child
-    __shared__ double smu[kWave];                   // moonlet masses
+    __shared__ double pw[kPowChunk][3][NP];         // scaled powers per moonlet / child
+    __shared__ double smu[kPowChunk];               // moonlet masses
     __shared__ double cm[8][NMS];                   // children's moments
     __shared__ uint16_t sterm[ShiftTerms<P>::NT];   // shift terms (from constant memory)
     if (st->status & kSkipMask) return;
@@ -196,8 +200,8 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
             }
             sx = sx / M; sy = sy / M; sz = sz / M;
             double rm = 0.0, acc = 0.0;
-            for (int c0 = 0; c0 < cnt; c0 += kWave) {
-                const bool in = c0 + lane < cnt;
+            for (int c0 = 0; c0 < cnt; c0 += kPowChunk) {
+                const bool in = lane < kPowChunk && c0 + lane < cnt;
                 const int k = f + c0 + (in ? lane : 0);
                 const double mu = mus[k], x = xs[k], y = ys[k], z = zs[k];
                 if (in) {
@@ -205,9 +209,9 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
                     if (d > rm) rm = d;
                 }
                 if (NM > 0) {
-                    const int nk = cnt - c0 < kWave ? cnt - c0 : kWave;
+                    const int nk = cnt - c0 < kPowChunk ? cnt - c0 : kPowChunk;
                     __syncthreads();
-                    {
+                    if (lane < kPowChunk) {
                         const double ux = x - sx, uy = y - sy, uz = z - sz;
                         double tx = 1.0, ty = 1.0, tz = 1.0;
                         pw[lane][0][0] = 1.0; pw[lane][1][0] = 1.0; pw[lane][2][0] = 1.0;

@@ -350,8 +350,10 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
 
 // evaluation of the leaf's expansion at its moonlets (Eq. 26 down to C^(1)),
 // added to the direct sums and written in input order
+constexpr int kL2PWaves = 4;        // independent waves per block
+
 template <int P>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(kWave * kL2PWaves)
 k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const double *__restrict__ ys, const double *__restrict__ zs,
       const uint32_t *__restrict__ perm, const int32_t *__restrict__ ent_cell,
@@ -360,17 +362,18 @@ k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const double *__restrict__ acc_s, int64_t n, double *__restrict__ ax,
       double *__restrict__ ay, double *__restrict__ az) {
     constexpr int NL = n_local(P);
-    __shared__ double cl[NL];
+    __shared__ double cl_all[kL2PWaves][NL];
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
-    const int lane = threadIdx.x;
-    for (int e = blockIdx.x; e < K; e += gridDim.x) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    double *cl = cl_all[wid];
+    for (int e = blockIdx.x * kL2PWaves + wid; e < K; e += gridDim.x * kL2PWaves) {
         const int c = ent_cell[e];
         const int f = c_first[c], nt = c_count[c];
         const double4 g = gcell[c];
-        __syncthreads();
+        wave_sync();
         for (int k = lane; k < NL; k += 64) cl[k] = cleaf[(int64_t)e * NL + k];
-        __syncthreads();
+        wave_sync();
         for (int t0 = 0; t0 < nt; t0 += 64) {
             const int t = t0 + lane;
             if (t >= nt) continue;
@@ -446,9 +449,9 @@ hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t
 template <int P>
 static void launch_l2p_p(const Workspace &ws, int64_t n, double *ax, double *ay, double *az,
                          hipStream_t s) {
-    int g = (int)(ws.n_max < 65536 ? ws.n_max : 65536);
-    if (g < 1) g = 1;
-    k_l2p<P><<<g, 64, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.idx, ws.ent_cell, ws.c_first,
+    int64_t g = (ws.leaf_cap + kL2PWaves - 1) / kL2PWaves;
+    g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
+    k_l2p<P><<<(int)g, kWave * kL2PWaves, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.idx, ws.ent_cell, ws.c_first,
                               ws.c_count, ws.gcell, ws.cleaf, ws.acc_s, n, ax, ay, az);
 }
 
