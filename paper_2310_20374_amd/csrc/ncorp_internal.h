@@ -47,8 +47,11 @@ enum StatusBits : int32_t {
 // persistent walk: waves, and list slots a wave reserves at a time (the plain
 // cell-pair lists carry up to kWalkWaves * kListChunk slots of gaps)
 constexpr int kWalkBlock = 256;
-constexpr int kWalkGrid = 128;                // 512 persistent waves: 2 per CU
-constexpr int kWalkWaves = kWalkGrid * kWalkBlock / kWave;
+// persistent blocks: the gravity walk runs 1024 waves, the collision walk (less
+// work per item) 512; more only adds contention on the queue counters
+constexpr int kWalkGridGravity = 256;
+constexpr int kWalkGridCollide = 128;
+constexpr int kWalkWaves = kWalkGridGravity * kWalkBlock / kWave;
 constexpr int kListChunk = 256;
 
 // per-target interaction lists: default and largest slot counts (a consumer

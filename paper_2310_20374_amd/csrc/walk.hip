@@ -1,7 +1,7 @@
 // The falcON dual tree walk (Alg. 2) on the GPU.
 //
 // The paper's recursion (run iteratively from a stack) becomes one persistent
-// launch over a global work queue of cell pairs.  Every wave claims 64 queue
+// launch over a global work queue of cell pairs.  Every wave claims 128 queue
 // slots, polls them until their items appear, classifies each pair exactly as
 // Alg. 2 does (self pair / brute force before the opening test / well separated /
 // brute force after it / split the cell with the larger critical radius) and
@@ -156,8 +156,108 @@ __device__ __forceinline__ void emit(bool flag, int a, int b, int lane, Chunk &c
     ch.total += k;
 }
 
+// One cell pair, classified as Alg. 2 does.
+struct Item {
+    int kind;                  // 0 nothing, 1 well separated (M2L), 2 direct sum
+    int split;                 // children to push: 1 self pair, 2 split A, 3 split B
+    int npush;
+    int a, b, na, nb, ca, cb;  // cells, their child counts and first children
+};
+
+template <int MODE>
+__device__ __forceinline__ Item classify(bool valid, uint64_t item, const WalkArgs &A,
+                                         int ncells) {
+    Item it = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (!valid) return it;
+    int a = (int)((item >> 24) & 0xffffffu);
+    int b = (int)(item & 0xffffffu);
+    if (a >= ncells || b >= ncells) {                   // cannot happen; never follow it
+        atomicOr(&A.st->status, (int32_t)ST_BAD_ITEM);
+        a = b = 0;
+    }
+    it.a = a;
+    it.b = b;
+    const WCell wa = A.cell[a];
+    it.na = wa.nchild;
+    it.ca = wa.child;
+    if (a == b) {
+        if (wa.count <= A.ncs || it.na == 0) it.kind = 2;
+        else { it.split = 1; it.npush = it.na * (it.na + 1) / 2; }
+        return it;
+    }
+    const WCell wb = A.cell[b];
+    it.nb = wb.nchild;
+    it.cb = wb.child;
+    const int64_t prod = (int64_t)wa.count * (int64_t)wb.count;
+    if (prod < (int64_t)A.ncc_pre) {
+        it.kind = 2;
+    } else {
+        const double dx = wa.x - wb.x, dy = wa.y - wb.y, dz = wa.z - wb.z;
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        if (wa.rcrit + wb.rcrit <= d) {
+            it.kind = MODE == 0 ? 1 : 0;                 // collisions: nothing
+        } else if (prod < (int64_t)A.ncc_post || (it.na == 0 && it.nb == 0)) {
+            it.kind = 2;
+        } else if (it.nb == 0 || (it.na != 0 && wa.rcrit > wb.rcrit)) {
+            it.split = 2; it.npush = it.na;
+        } else {
+            it.split = 3; it.npush = it.nb;
+        }
+    }
+    return it;
+}
+
+// Stores an item's child pairs at queue slots my, my+1, ...
+__device__ __forceinline__ void push_children(const Item &it, uint64_t my, const WalkArgs &A) {
+    int j = 0;
+    if (it.split == 1) {
+        for (int x = 0; x < it.na; x++)
+            for (int y = x; y < it.na; y++, j++)
+                if (my + j < (uint64_t)A.qcap)
+                    __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, it.ca + x, it.ca + y),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (it.split == 2) {
+        for (; j < it.na; j++)
+            if (my + j < (uint64_t)A.qcap)
+                __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, it.ca + j, it.b),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (it.split == 3) {
+        for (; j < it.nb; j++)
+            if (my + j < (uint64_t)A.qcap)
+                __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, it.a, it.cb + j),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The per-target lists of the gravity walk (see the file header).
+__device__ __forceinline__ void append_targets(const Item &it, const WalkArgs &A) {
+    if (it.kind == 1) {
+        append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, it.a, it.b, kM2LListLDS, &A.st->nlong_m2l,
+               A.long_m2l, A.st);
+        append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, it.b, it.a, kM2LListLDS, &A.st->nlong_m2l,
+               A.long_m2l, A.st);
+    } else if (it.kind == 2) {
+        int e0 = A.c_entry[it.a], e1 = e0 + A.c_nent[it.a];
+        for (int e = e0; e < e1; e++)
+            append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, it.b, kP2PListLDS, &A.st->nlong_p2p,
+                   A.long_p2p, A.st);
+        if (it.a != it.b) {
+            e0 = A.c_entry[it.b];
+            e1 = e0 + A.c_nent[it.b];
+            for (int e = e0; e < e1; e++)
+                append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, it.a, kP2PListLDS,
+                       &A.st->nlong_p2p, A.long_p2p, A.st);
+        }
+    }
+}
+
+// Every wave claims kWave * kItemsPerLane queue slots at a time (lane l takes slots
+// l, l + 64, ...), so the shared counters are touched once per that many items.
+constexpr int kItemsPerLane = 2;
+
 template <int MODE>
 __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
+    constexpr int IPL = kItemsPerLane;
     const int lane = threadIdx.x % kWave;
     WalkQueue *wq = A.wq;
     const int ncells = A.st->ncells;
@@ -168,17 +268,31 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
     Chunk cm = {-1, kListChunk, 0}, cp = {-1, kListChunk, 0};
     while (!finished) {
         uint64_t base = 0;
-        if (lane == 0) base = atomicAdd((unsigned long long *)&wq->head, (unsigned long long)kWave);
+        if (lane == 0)
+            base = atomicAdd((unsigned long long *)&wq->head, (unsigned long long)(kWave * IPL));
         base = __shfl(base, 0);
         // every later claim lies beyond the queue too: this wave can get no more work
         if (base >= (uint64_t)A.qcap) break;
-        const uint64_t slot = base + lane;
-        bool pending = slot < (uint64_t)A.qcap;
-        while (__any(pending)) {
-            uint64_t item = 0;
-            if (pending) item = ld_relaxed(&A.queue[slot]);
-            const bool valid = pending && (uint32_t)(item >> 48) == tag;
-            if (!__any(valid)) {
+        uint64_t slot[IPL];
+        bool pending[IPL];
+        bool any_pending = false;
+#pragma unroll
+        for (int k = 0; k < IPL; k++) {
+            slot[k] = base + lane + (uint64_t)k * kWave;
+            pending[k] = slot[k] < (uint64_t)A.qcap;
+            any_pending = any_pending || pending[k];
+        }
+        while (__any(any_pending)) {
+            bool valid[IPL];
+            uint64_t item[IPL];
+            bool any_valid = false;
+#pragma unroll
+            for (int k = 0; k < IPL; k++) {
+                item[k] = pending[k] ? ld_relaxed(&A.queue[slot[k]]) : 0;
+                valid[k] = pending[k] && (uint32_t)(item[k] >> 48) == tag;
+                any_valid = any_valid || valid[k];
+            }
+            if (!__any(any_valid)) {
                 // nothing arrived: the walk is over once every pushed item has
                 // been processed (slots beyond the queue were never written)
                 int done = 0;
@@ -203,44 +317,12 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
                 continue;
             }
             spins = 0;
-            // ---------------- classify the pair (Alg. 2)
-            int kind = 0;                       // 0 none, 1 well separated, 2 direct sum
-            int npush = 0, split = 0;           // split: 1 self, 2 A, 3 B
-            int a = 0, b = 0, na = 0, nb = 0, ca = 0, cb = 0;
-            if (valid) {
-                a = (int)((item >> 24) & 0xffffffu);
-                b = (int)(item & 0xffffffu);
-                if (a >= ncells || b >= ncells) {       // cannot happen; never follow it
-                    atomicOr(&A.st->status, (int32_t)ST_BAD_ITEM);
-                    a = b = 0;
-                }
-                const WCell wa = A.cell[a];
-                na = wa.nchild;
-                ca = wa.child;
-                if (a == b) {
-                    if (wa.count <= A.ncs || na == 0) kind = 2;
-                    else { split = 1; npush = na * (na + 1) / 2; }
-                } else {
-                    const WCell wb = A.cell[b];
-                    nb = wb.nchild;
-                    cb = wb.child;
-                    const int64_t prod = (int64_t)wa.count * (int64_t)wb.count;
-                    if (prod < (int64_t)A.ncc_pre) {
-                        kind = 2;
-                    } else {
-                        const double dx = wa.x - wb.x, dy = wa.y - wb.y, dz = wa.z - wb.z;
-                        const double d = sqrt(dx * dx + dy * dy + dz * dz);
-                        if (wa.rcrit + wb.rcrit <= d) {
-                            kind = MODE == 0 ? 1 : 0;          // collisions: nothing
-                        } else if (prod < (int64_t)A.ncc_post || (na == 0 && nb == 0)) {
-                            kind = 2;
-                        } else if (nb == 0 || (na != 0 && wa.rcrit > wb.rcrit)) {
-                            split = 2; npush = na;
-                        } else {
-                            split = 3; npush = nb;
-                        }
-                    }
-                }
+            Item it[IPL];
+            int npush = 0;
+#pragma unroll
+            for (int k = 0; k < IPL; k++) {
+                it[k] = classify<MODE>(valid[k], item[k], A, ncells);
+                npush += it[k].npush;
             }
             // ---------------- push children (one reservation per wave)
             int tot_push;
@@ -250,27 +332,11 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
                 if (lane == 0)
                     pbase = atomicAdd((unsigned long long *)&wq->tail, (unsigned long long)tot_push);
                 pbase = __shfl(pbase, 0);
-                const uint64_t my = pbase + (uint64_t)off;
-                int j = 0;
-                if (split == 1) {
-                    for (int x = 0; x < na; x++)
-                        for (int y = x; y < na; y++, j++)
-                            if (my + j < (uint64_t)A.qcap) {
-                                __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, ca + x, ca + y),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            }
-                } else if (split == 2) {
-                    for (; j < na; j++)
-                        if (my + j < (uint64_t)A.qcap) {
-                            __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, ca + j, b),
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                } else if (split == 3) {
-                    for (; j < nb; j++)
-                        if (my + j < (uint64_t)A.qcap) {
-                            __hip_atomic_store(&A.queue[my + j], make_item(A.epoch, a, cb + j),
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
+                uint64_t my = pbase + (uint64_t)off;
+#pragma unroll
+                for (int k = 0; k < IPL; k++) {
+                    push_children(it[k], my, A);
+                    my += (uint64_t)it[k].npush;
                 }
                 if (pbase + (uint64_t)tot_push > (uint64_t)A.qcap && lane == 0) {
                     atomicOr(&A.st->status, (int32_t)ST_CAP_QUEUE);
@@ -279,39 +345,31 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
                 }
             }
             // ---------------- interaction lists
-            if (MODE == 0)
-                emit(kind == 1, a, b, lane, cm, A.m2l_slots, A.m2l, A.m2l_cap, A.st, ST_CAP_M2L);
-            emit(kind == 2, a, b, lane, cp, A.p2p_slots, A.p2p, A.p2p_cap, A.st, ST_CAP_P2P);
-            if (MODE == 0 && A.m2l_cnt) {
-                if (kind == 1) {
-                    append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, a, b, kM2LListLDS,
-                           &A.st->nlong_m2l, A.long_m2l, A.st);
-                    append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, b, a, kM2LListLDS,
-                           &A.st->nlong_m2l, A.long_m2l, A.st);
-                } else if (kind == 2) {
-                    int e0 = A.c_entry[a], e1 = e0 + A.c_nent[a];
-                    for (int e = e0; e < e1; e++)
-                        append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, b, kP2PListLDS,
-                               &A.st->nlong_p2p, A.long_p2p, A.st);
-                    if (a != b) {
-                        e0 = A.c_entry[b];
-                        e1 = e0 + A.c_nent[b];
-                        for (int e = e0; e < e1; e++)
-                            append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, a, kP2PListLDS,
-                                   &A.st->nlong_p2p, A.long_p2p, A.st);
-                    }
-                }
+            int nproc = 0;
+#pragma unroll
+            for (int k = 0; k < IPL; k++) {
+                if (MODE == 0)
+                    emit(it[k].kind == 1, it[k].a, it[k].b, lane, cm, A.m2l_slots, A.m2l,
+                         A.m2l_cap, A.st, ST_CAP_M2L);
+                emit(it[k].kind == 2, it[k].a, it[k].b, lane, cp, A.p2p_slots, A.p2p, A.p2p_cap,
+                     A.st, ST_CAP_P2P);
+                if (MODE == 0 && A.m2l_cnt) append_targets(it[k], A);
+                nproc += __popcll(__ballot(valid[k]));
             }
             // ---------------- retire.  The children's tail reservation has returned
             // (its value addressed their stores); the compiler barrier keeps this
             // atomic after those stores, so it is performed after the reservation.
-            const int nproc = __popcll(__ballot(valid));
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
             if (lane == 0)
                 __hip_atomic_fetch_add(&wq->processed, (uint64_t)nproc, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             visited += nproc;
-            pending = pending && !valid;
+            any_pending = false;
+#pragma unroll
+            for (int k = 0; k < IPL; k++) {
+                pending[k] = pending[k] && !valid[k];
+                any_pending = any_pending || pending[k];
+            }
         }
     }
     if (MODE == 0) close_chunk(cm, lane, A.m2l, A.m2l_cap);
@@ -352,13 +410,13 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
         A.m2l_cnt = ws.m2l_cnt; A.m2l_seg = ws.m2l_seg; A.m2l_stride = ws.m2l_stride;
         A.p2p_cnt = ws.p2p_cnt; A.p2p_seg = ws.p2p_seg; A.p2p_stride = ws.p2p_stride;
         A.long_m2l = ws.long_m2l; A.long_p2p = ws.long_p2p;
-        k_walk<0><<<kWalkGrid, kWalkBlock, 0, s>>>(A);
+        k_walk<0><<<kWalkGridGravity, kWalkBlock, 0, s>>>(A);
     } else {
         A.cell = ws.wc;
         A.m2l = ws.m2l; A.m2l_cap = 0; A.nm2l = &ws.st->nm2l;
         A.p2p = ws.cand; A.p2p_cap = ws.p2p_cap; A.np2p = &ws.st->ncand;
         A.m2l_slots = &ws.st->m2l_slots; A.p2p_slots = &ws.st->cand_slots;
-        k_walk<1><<<kWalkGrid, kWalkBlock, 0, s>>>(A);
+        k_walk<1><<<kWalkGridCollide, kWalkBlock, 0, s>>>(A);
     }
     return hipGetLastError();
 }
