@@ -177,6 +177,7 @@ k_m2l(const DevState *__restrict__ st, const double4 *__restrict__ gcell,
             for (int i = lane; i < len; i += kWave) {
                 const int v = scratch[i];
                 int r = 0;
+                #pragma unroll 8
                 for (int j = 0; j < len4 / 4; j++) {
                     const int4 t = s4[j];
                     r += (t.x < v) + (t.y < v) + (t.z < v) + (t.w < v);

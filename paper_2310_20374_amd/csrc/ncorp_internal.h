@@ -134,6 +134,7 @@ __device__ __forceinline__ void sort_target_list(int32_t *list, int len, int32_t
     for (int i = lane; i < len; i += kWave) {
         const int v = scratch[i];
         int r = 0;
+        #pragma unroll 8
         for (int j = 0; j < len4 / 4; j++) {
             const int4 t = s4[j];
             r += (t.x < v) + (t.y < v) + (t.z < v) + (t.w < v);

@@ -173,10 +173,30 @@ __device__ __forceinline__ int batch_prefix(const int (&cnt4)[4], int32_t *s_pre
     return tot;
 }
 
-// Direct sums of one lane's target over a batch of source cells whose moonlet
-// ranges are s_first[k] .. + (s_pref[k+1] - s_pref[k]), k < nsb, tot moonlets in
-// all; the batch is streamed through LDS kP2PTile moonlets at a time.
-template <typename T>
+// One source against the NT targets a lane holds.
+template <typename T, int NT>
+__device__ __forceinline__ void interact(const typename Vec4<T>::type &v, const T (&xi)[NT],
+                                         const T (&yi)[NT], const T (&zi)[NT], T (&px)[NT],
+                                         T (&py)[NT], T (&pz)[NT]) {
+    const T floor2 = r2_floor<T>();
+#pragma unroll
+    for (int k = 0; k < NT; k++) {
+        const T dx = v.x - xi[k], dy = v.y - yi[k], dz = v.z - zi[k];
+        T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, dx * dx));
+        r2 = r2 > floor2 ? r2 : floor2;
+        const T rinv = rsq<T>(r2);
+        const T w = v.w * (rinv * rinv) * rinv;
+        px[k] = fmat<T>(dx, w, px[k]);
+        py[k] = fmat<T>(dy, w, py[k]);
+        pz[k] = fmat<T>(dz, w, pz[k]);
+    }
+}
+
+// Direct sums of the NT targets a lane holds over a batch of source cells whose
+// moonlet ranges are s_first[k] .. + (s_pref[k+1] - s_pref[k]), k < nsb, tot
+// moonlets in all; the batch is streamed through LDS kP2PTile moonlets at a time and
+// the lane's group takes sources j0, j0 + G, ... of every tile.
+template <typename T, int NT>
 __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_first,
                                           const int32_t *s_pref,
                                           typename Vec4<T>::type *tile,
@@ -184,10 +204,10 @@ __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_fir
                                           const double *__restrict__ ys,
                                           const double *__restrict__ zs,
                                           const double *__restrict__ mus, const double4 g,
-                                          T xi, T yi, T zi, int grp, int G, Acc3<T> &acc) {
+                                          const T (&xi)[NT], const T (&yi)[NT], const T (&zi)[NT],
+                                          int j0, int G, Acc3<T> (&acc)[NT]) {
     using V = typename Vec4<T>::type;
     const int lane = threadIdx.x & (kWave - 1);
-    const T floor2 = r2_floor<T>();
     for (int p0 = 0; p0 < tot; p0 += kP2PTile) {
         const int nj = tot - p0 < kP2PTile ? tot - p0 : kP2PTile;
         // stage the tile: source moonlet q of the batch -> its cell by binary
@@ -211,21 +231,96 @@ __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_fir
             }
         }
         wave_sync();
-        T px = 0, py = 0, pz = 0;
+        T px[NT], py[NT], pz[NT];
+#pragma unroll
+        for (int k = 0; k < NT; k++) px[k] = py[k] = pz[k] = (T)0;
+        if constexpr (NT == 1) {
 #pragma unroll 4
-        for (int j = grp; j < nj; j += G) {
-            const V v = tile[j];
-            const T dx = v.x - xi, dy = v.y - yi, dz = v.z - zi;
-            T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, dx * dx));
-            r2 = r2 > floor2 ? r2 : floor2;
-            const T rinv = rsq<T>(r2);
-            const T w = v.w * (rinv * rinv) * rinv;
-            px = fmat<T>(dx, w, px);
-            py = fmat<T>(dy, w, py);
-            pz = fmat<T>(dz, w, pz);
+            for (int j = j0; j < nj; j += G) interact<T, NT>(tile[j], xi, yi, zi, px, py, pz);
+        } else {
+#pragma unroll 2
+            for (int j = j0; j < nj; j += G) interact<T, NT>(tile[j], xi, yi, zi, px, py, pz);
         }
-        acc.add_tile(px, py, pz);
+#pragma unroll
+        for (int k = 0; k < NT; k++) acc[k].add_tile(px[k], py[k], pz[k]);
         wave_sync();
+    }
+}
+
+// Direct sums for ntc <= 64 targets (moonlets tb .. tb+ntc-1) of one leaf.  The
+// lanes form G = 64 / lpg groups of lpg = ceil(ntc / NT) lanes; lane li of a group
+// holds targets li and li + lpg (NT = 2), and the groups split every tile's
+// sources.  The group partials are added in group order.
+template <typename T, int NT>
+__device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1, int len,
+                                            const int32_t *__restrict__ list, int32_t *s_first,
+                                            int32_t *s_pref, typename Vec4<T>::type *tile,
+                                            const double *__restrict__ xs,
+                                            const double *__restrict__ ys,
+                                            const double *__restrict__ zs,
+                                            const double *__restrict__ mus,
+                                            const int32_t *__restrict__ c_first,
+                                            const int32_t *__restrict__ c_count, const double4 g,
+                                            double *__restrict__ acc_s, int64_t n) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lpg = (ntc + NT - 1) / NT;
+    const int G = kWave / lpg;
+    const int grp = lane / lpg, li = lane % lpg;
+    T xi[NT], yi[NT], zi[NT];
+#pragma unroll
+    for (int k = 0; k < NT; k++) {
+        const int t = li + k * lpg;
+        const int i = tb + (t < ntc ? t : 0);
+        xi[k] = (T)(xs[i] - g.x);
+        yi[k] = (T)(ys[i] - g.y);
+        zi[k] = (T)(zs[i] - g.z);
+    }
+    const int j0 = grp < G ? grp : kP2PTile;       // lanes beyond the groups idle
+    Acc3<T> acc[NT];
+    if (one) {
+        p2p_batch<T, NT>(tot1, len, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi, j0,
+                         G, acc);
+    } else {
+        for (int sb = 0; sb < len; sb += kP2PSrc) {
+            const int nsb = len - sb < kP2PSrc ? len - sb : kP2PSrc;
+            wave_sync();
+            int cnt4[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int q = 4 * lane + k;
+                int cf = 0, cn = 0;
+                if (q < nsb) {
+                    const int B = list[sb + q];
+                    cf = c_first[B];
+                    cn = c_count[B];
+                }
+                s_first[q] = cf;
+                cnt4[k] = cn;
+            }
+            const int tot = batch_prefix(cnt4, s_pref, lane);
+            wave_sync();
+            p2p_batch<T, NT>(tot, nsb, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi,
+                             j0, G, acc);
+        }
+    }
+    // add the partials of groups 1 .. G-1 to group 0's, in group order
+#pragma unroll
+    for (int k = 0; k < NT; k++) {
+        double px, py, pz;                     // this lane's partials
+        acc[k].fold(px, py, pz);
+        double ox = px, oy = py, oz = pz;
+        for (int gi = 1; gi < G; gi++) {
+            const int src = gi * lpg + li;
+            ox += __shfl(px, src);
+            oy += __shfl(py, src);
+            oz += __shfl(pz, src);
+        }
+        const int t = li + k * lpg;
+        if (grp == 0 && t < ntc) {
+            acc_s[tb + t] = ox;
+            acc_s[n + tb + t] = oy;
+            acc_s[2 * n + tb + t] = oz;
+        }
     }
 }
 
@@ -281,6 +376,7 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
             for (int k = 0; k < 4; k++) {
                 if (4 * lane + k < len) {
                     int r = 0;
+#pragma unroll 8
                     for (int j = 0; j < len4; j++) {
                         const int4 t = s4[j];
                         r += (t.x < v[k]) + (t.y < v[k]) + (t.z < v[k]) + (t.w < v[k]);
@@ -297,53 +393,16 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
             tot1 = batch_prefix(c4, s_pref, lane);
             wave_sync();
         }                                             // longer lists: sorted by the pre-pass
-        for (int t0 = 0; t0 < nt; t0 += 64) {
-            const int ntc = nt - t0 < 64 ? nt - t0 : 64;
-            int S = 1;
-            while (S < ntc) S <<= 1;
-            const int G = 64 / S, tl = lane % S, grp = lane / S;
-            const bool act = tl < ntc;
-            const int i = f + t0 + (act ? tl : 0);
-            const T xi = (T)(xs[i] - g.x), yi = (T)(ys[i] - g.y), zi = (T)(zs[i] - g.z);
-            Acc3<T> acc;
-            if (one) {
-                p2p_batch<T>(tot1, len, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi,
-                             grp, G, acc);
-            } else {
-                for (int sb = 0; sb < len; sb += kP2PSrc) {
-                    const int nsb = len - sb < kP2PSrc ? len - sb : kP2PSrc;
-                    wave_sync();
-                    int cnt4[4];
-#pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        const int q = 4 * lane + k;
-                        int cf = 0, cn = 0;
-                        if (q < nsb) {
-                            const int B = list[sb + q];
-                            cf = c_first[B];
-                            cn = c_count[B];
-                        }
-                        s_first[q] = cf;
-                        cnt4[k] = cn;
-                    }
-                    const int tot = batch_prefix(cnt4, s_pref, lane);
-                    wave_sync();
-                    p2p_batch<T>(tot, nsb, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi,
-                                 zi, grp, G, acc);
-                }
-            }
-            double ox, oy, oz;
-            acc.fold(ox, oy, oz);
-            for (int o = S; o < 64; o <<= 1) {
-                ox += __shfl_xor(ox, o);
-                oy += __shfl_xor(oy, o);
-                oz += __shfl_xor(oz, o);
-            }
-            if (act && grp == 0) {
-                acc_s[i] = ox;
-                acc_s[n + i] = oy;
-                acc_s[2 * n + i] = oz;
-            }
+        for (int t0 = 0; t0 < nt; t0 += kWave) {
+            const int ntc = nt - t0 < kWave ? nt - t0 : kWave;
+            // one or two targets per lane, whichever leaves fewer lanes idle
+            const int lpg2 = (ntc + 1) / 2;
+            if ((kWave / lpg2) * ntc > 2 * (kWave / ntc) * ntc)
+                p2p_targets<T, 2>(ntc, f + t0, one, tot1, len, list, s_first, s_pref, tile, xs,
+                                  ys, zs, mus, c_first, c_count, g, acc_s, n);
+            else
+                p2p_targets<T, 1>(ntc, f + t0, one, tot1, len, list, s_first, s_pref, tile, xs,
+                                  ys, zs, mus, c_first, c_count, g, acc_s, n);
         }
     }
 }

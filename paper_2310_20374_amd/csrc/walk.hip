@@ -442,6 +442,7 @@ k_sort_long_lists(const DevState *__restrict__ st, int which, const int32_t *__r
         for (int i = lane; i < len; i += kWave) {
             const int v = scr[i];
             int r = 0;
+            #pragma unroll 8
             for (int j = 0; j < len4 / 4; j++) {
                 const int4 w = s4[j];
                 r += (w.x < v) + (w.y < v) + (w.z < v) + (w.w < v);
