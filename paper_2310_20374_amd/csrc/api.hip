@@ -242,6 +242,7 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
         ws.p2p_seg = (int32_t *)take(4 * ws.leaf_cap * (int64_t)ws.p2p_stride);
         ws.long_m2l = (int32_t *)take(4 * cell_cap);
         ws.long_p2p = (int32_t *)take(4 * ws.leaf_cap);
+        ws.p2p_part = (double *)take(8 * (int64_t)kLongSlots * 3 * n);
     }
     const int64_t cnt = nb * (kMaxDepth + 1) + 1;
     ws.cnt_a = (int32_t *)take(4 * cnt);

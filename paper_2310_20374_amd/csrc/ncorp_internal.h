@@ -62,8 +62,12 @@ constexpr int kMaxPerTarget = 8192;
 // lists up to these lengths are sorted in LDS by their consumer; longer ones (the
 // walk records them) by a pre-pass of kSortLongBlocks single-wave blocks
 constexpr int kM2LListLDS = 512;
-constexpr int kP2PListLDS = 256;
+constexpr int kP2PListLDS = kWave;
 constexpr int kSortLongBlocks = 1024;
+// direct sums of a leaf with a long source list are split over kLongSlots waves
+// (grid of kLongGrid four-wave blocks); their partial sums meet in p2p_part
+constexpr int kLongSlots = 8;
+constexpr int kLongGrid = 2048;
 
 constexpr int32_t kSkipMask = ST_CAP_CELLS | ST_CAP_QUEUE | ST_CAP_M2L | ST_CAP_P2P |
                               ST_CAP_LISTS | ST_WALK_STALL | ST_BAD_ITEM;
@@ -189,6 +193,7 @@ struct Workspace {
     int32_t *m2l_cnt = nullptr, *m2l_seg = nullptr;   // by target cell, m2l_stride slots
     int32_t *p2p_cnt = nullptr, *p2p_seg = nullptr;   // by target leaf, p2p_stride slots
     int32_t *long_m2l = nullptr, *long_p2p = nullptr; // targets of over-long lists
+    double *p2p_part = nullptr;                       // kLongSlots x 3 x n partial sums
     int32_t *cnt_a = nullptr;                         // tree-build level counters
     int64_t *pairs_tmp = nullptr;                     // colliding pairs (i<<32|j)
     int64_t *pairs_alt = nullptr;

@@ -156,19 +156,14 @@ template <> __device__ __forceinline__ float r2_floor<float>() { return 1e-24f; 
 template <> __device__ __forceinline__ double r2_floor<double>() { return 1e-200; }
 
 constexpr int kP2PTile = 256;       // source moonlets staged per LDS tile
-constexpr int kP2PSrc = 256;        // source cells per batch (prefix sums in LDS)
+constexpr int kP2PSrc = kWave;      // source cells per batch, one per lane (prefix sums in LDS)
 
-// Exclusive prefix sums of the 4 counts each lane holds for sources 4*lane..4*lane+3
-// into s_pref[0..256]; returns the total.
-__device__ __forceinline__ int batch_prefix(const int (&cnt4)[4], int32_t *s_pref, int lane) {
-    int run = cnt4[0] + cnt4[1] + cnt4[2] + cnt4[3];
+// Exclusive prefix sums of the moonlet counts of a batch's source cells (one per
+// lane) into s_pref[0..kP2PSrc]; returns the total.
+__device__ __forceinline__ int batch_prefix(int cnt, int32_t *s_pref, int lane) {
     int tot;
-    int ex = wave_excl_sum_p(run, lane, tot);
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        s_pref[4 * lane + k] = ex;
-        ex += cnt4[k];
-    }
+    const int ex = wave_excl_sum_p(cnt, lane, tot);
+    s_pref[lane] = ex;
     if (lane == 0) s_pref[kP2PSrc] = tot;
     return tot;
 }
@@ -247,12 +242,15 @@ __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_fir
     }
 }
 
-// Direct sums for ntc <= 64 targets (moonlets tb .. tb+ntc-1) of one leaf.  The
-// lanes form G = 64 / lpg groups of lpg = ceil(ntc / NT) lanes; lane li of a group
-// holds targets li and li + lpg (NT = 2), and the groups split every tile's
-// sources.  The group partials are added in group order.
+// Direct sums for ntc <= 64 targets (moonlets tb .. tb+ntc-1) of one leaf, over
+// the whole list (one LDS batch) or over its batches b0, b0 + bstep, ... of
+// kP2PSrc source cells.  The lanes form G = 64 / lpg groups of lpg = ceil(ntc / NT)
+// lanes; lane li of a group holds targets li and li + lpg (NT = 2), and the groups
+// split every tile's sources.  The group partials are added in group order and
+// written to out[d * n + i], d = x, y, z.
 template <typename T, int NT>
 __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1, int len,
+                                            int b0, int bstep,
                                             const int32_t *__restrict__ list, int32_t *s_first,
                                             int32_t *s_pref, typename Vec4<T>::type *tile,
                                             const double *__restrict__ xs,
@@ -261,7 +259,7 @@ __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1,
                                             const double *__restrict__ mus,
                                             const int32_t *__restrict__ c_first,
                                             const int32_t *__restrict__ c_count, const double4 g,
-                                            double *__restrict__ acc_s, int64_t n) {
+                                            double *__restrict__ out, int64_t n) {
     const int lane = threadIdx.x & (kWave - 1);
     const int lpg = (ntc + NT - 1) / NT;
     const int G = kWave / lpg;
@@ -281,23 +279,17 @@ __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1,
         p2p_batch<T, NT>(tot1, len, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi, j0,
                          G, acc);
     } else {
-        for (int sb = 0; sb < len; sb += kP2PSrc) {
+        for (int sb = b0 * kP2PSrc; sb < len; sb += bstep * kP2PSrc) {
             const int nsb = len - sb < kP2PSrc ? len - sb : kP2PSrc;
             wave_sync();
-            int cnt4[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const int q = 4 * lane + k;
-                int cf = 0, cn = 0;
-                if (q < nsb) {
-                    const int B = list[sb + q];
-                    cf = c_first[B];
-                    cn = c_count[B];
-                }
-                s_first[q] = cf;
-                cnt4[k] = cn;
+            int cf = 0, cn = 0;
+            if (lane < nsb) {
+                const int B = list[sb + lane];
+                cf = c_first[B];
+                cn = c_count[B];
             }
-            const int tot = batch_prefix(cnt4, s_pref, lane);
+            s_first[lane] = cf;
+            const int tot = batch_prefix(cn, s_pref, lane);
             wave_sync();
             p2p_batch<T, NT>(tot, nsb, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi,
                              j0, G, acc);
@@ -317,9 +309,9 @@ __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1,
         }
         const int t = li + k * lpg;
         if (grp == 0 && t < ntc) {
-            acc_s[tb + t] = ox;
-            acc_s[n + tb + t] = oy;
-            acc_s[2 * n + tb + t] = oz;
+            out[tb + t] = ox;
+            out[n + tb + t] = oy;
+            out[2 * n + tb + t] = oz;
         }
     }
 }
@@ -351,58 +343,84 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
         const double4 g = gcell[c];
         int32_t *list = p2p_seg + (int64_t)e * stride;
         const int len = p2p_cnt[e];
-        const bool one = len <= kP2PSrc;
-        int tot1 = 0;
+        if (len > kP2PSrc) continue;                  // longer lists: k_p2p_long
         wave_sync();                                  // this wave's LDS is free again
-        if (one) {
-            // the usual case, one batch: rank the sources in LDS and place each
-            // source's moonlet range at its rank directly
-            int v[4], cf[4], cn[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const int q = 4 * lane + k;
-                v[k] = 0x7fffffff; cf[k] = 0; cn[k] = 0;
-                if (q < len) {
-                    v[k] = list[q];
-                    cf[k] = c_first[v[k]];
-                    cn[k] = c_count[v[k]];
-                }
-                scratch[q] = v[k];
-            }
-            wave_sync();
+        // one batch: rank the sources in LDS and place each source's moonlet range
+        // at its rank directly
+        const int v = lane < len ? list[lane] : 0x7fffffff;
+        const int cf = lane < len ? c_first[v] : 0;
+        const int cn = lane < len ? c_count[v] : 0;
+        scratch[lane] = v;
+        wave_sync();
+        if (lane < len) {
             const int4 *s4 = reinterpret_cast<const int4 *>(scratch);
-            const int len4 = (len + 3) >> 2;
+            int rk = 0;
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                if (4 * lane + k < len) {
-                    int r = 0;
-#pragma unroll 8
-                    for (int j = 0; j < len4; j++) {
-                        const int4 t = s4[j];
-                        r += (t.x < v[k]) + (t.y < v[k]) + (t.z < v[k]) + (t.w < v[k]);
-                    }
-                    s_first[r] = cf[k];
-                    s_pref[r] = cn[k];
-                }
+            for (int j = 0; j < kP2PSrc / 4; j++) {
+                const int4 t = s4[j];
+                rk += (t.x < v) + (t.y < v) + (t.z < v) + (t.w < v);
             }
-            wave_sync();
-            int c4[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) c4[k] = 4 * lane + k < len ? s_pref[4 * lane + k] : 0;
-            wave_sync();
-            tot1 = batch_prefix(c4, s_pref, lane);
-            wave_sync();
-        }                                             // longer lists: sorted by the pre-pass
+            s_first[rk] = cf;
+            s_pref[rk] = cn;
+        }
+        wave_sync();
+        const int c1 = lane < len ? s_pref[lane] : 0;
+        wave_sync();
+        const int tot1 = batch_prefix(c1, s_pref, lane);
+        wave_sync();
         for (int t0 = 0; t0 < nt; t0 += kWave) {
             const int ntc = nt - t0 < kWave ? nt - t0 : kWave;
             // one or two targets per lane, whichever leaves fewer lanes idle
             const int lpg2 = (ntc + 1) / 2;
             if ((kWave / lpg2) * ntc > 2 * (kWave / ntc) * ntc)
-                p2p_targets<T, 2>(ntc, f + t0, one, tot1, len, list, s_first, s_pref, tile, xs,
-                                  ys, zs, mus, c_first, c_count, g, acc_s, n);
+                p2p_targets<T, 2>(ntc, f + t0, true, tot1, len, 0, 1, list, s_first, s_pref,
+                                  tile, xs, ys, zs, mus, c_first, c_count, g, acc_s, n);
             else
-                p2p_targets<T, 1>(ntc, f + t0, one, tot1, len, list, s_first, s_pref, tile, xs,
-                                  ys, zs, mus, c_first, c_count, g, acc_s, n);
+                p2p_targets<T, 1>(ntc, f + t0, true, tot1, len, 0, 1, list, s_first, s_pref,
+                                  tile, xs, ys, zs, mus, c_first, c_count, g, acc_s, n);
+        }
+    }
+}
+
+// Leaves whose source list is longer than one LDS batch (their lists were sorted
+// by the pre-pass) would keep single waves busy long after all others finished, so
+// each is split over kLongSlots waves: wave `slot` takes the batches slot,
+// slot + kLongSlots, ... and writes its partial sums to part[slot]; the evaluation
+// kernel adds the kLongSlots partials in slot order.
+template <typename T>
+__global__ void __launch_bounds__(kWave * kP2PWaves)
+k_p2p_long(const DevState *__restrict__ st, const double *__restrict__ xs,
+           const double *__restrict__ ys, const double *__restrict__ zs,
+           const double *__restrict__ mus, const int32_t *__restrict__ ent_cell,
+           const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
+           const double4 *__restrict__ gcell, const int32_t *__restrict__ p2p_cnt,
+           const int32_t *__restrict__ p2p_seg, int stride, const int32_t *__restrict__ longs,
+           double *__restrict__ part, int64_t n) {
+    using V = typename Vec4<T>::type;
+    __shared__ __align__(16) V tiles[kP2PWaves][kP2PTile];
+    __shared__ int32_t firsts[kP2PWaves][kP2PSrc], prefs[kP2PWaves][kP2PSrc + 1];
+    if (st->status & kSkipMask) return;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    V *tile = tiles[wid];
+    int32_t *s_first = firsts[wid], *s_pref = prefs[wid];
+    const int items = st->nlong_p2p * kLongSlots;
+    for (int w = blockIdx.x * kP2PWaves + wid; w < items; w += gridDim.x * kP2PWaves) {
+        const int e = longs[w / kLongSlots], slot = w % kLongSlots;
+        const int c = ent_cell[e];
+        const int f = c_first[c], nt = c_count[c];
+        const double4 g = gcell[c];
+        const int32_t *list = p2p_seg + (int64_t)e * stride;
+        const int len = p2p_cnt[e];
+        double *out = part + (int64_t)slot * 3 * n;
+        for (int t0 = 0; t0 < nt; t0 += kWave) {
+            const int ntc = nt - t0 < kWave ? nt - t0 : kWave;
+            const int lpg2 = (ntc + 1) / 2;
+            if ((kWave / lpg2) * ntc > 2 * (kWave / ntc) * ntc)
+                p2p_targets<T, 2>(ntc, f + t0, false, 0, len, slot, kLongSlots, list, s_first,
+                                  s_pref, tile, xs, ys, zs, mus, c_first, c_count, g, out, n);
+            else
+                p2p_targets<T, 1>(ntc, f + t0, false, 0, len, slot, kLongSlots, list, s_first,
+                                  s_pref, tile, xs, ys, zs, mus, c_first, c_count, g, out, n);
         }
     }
 }
@@ -418,7 +436,8 @@ k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const uint32_t *__restrict__ perm, const int32_t *__restrict__ ent_cell,
       const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
       const double4 *__restrict__ gcell, const double *__restrict__ cleaf,
-      const double *__restrict__ acc_s, int64_t n, double *__restrict__ ax,
+      const double *__restrict__ acc_s, const int32_t *__restrict__ p2p_cnt,
+      const double *__restrict__ part, int64_t n, double *__restrict__ ax,
       double *__restrict__ ay, double *__restrict__ az) {
     constexpr int NL = n_local(P);
     __shared__ double cl_all[kL2PWaves][NL];
@@ -430,6 +449,7 @@ k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
         const int c = ent_cell[e];
         const int f = c_first[c], nt = c_count[c];
         const double4 g = gcell[c];
+        const bool longlist = p2p_cnt[e] > kP2PListLDS;   // direct sums in kLongSlots parts
         wave_sync();
         for (int k = lane; k < NL; k += 64) cl[k] = cleaf[(int64_t)e * NL + k];
         wave_sync();
@@ -460,10 +480,24 @@ k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
                         ly += cl[cidx(a2, 1 + b2, c2)] * w;
                         lz += cl[cidx(a2, b2, 1 + c2)] * w;
                     }
+            double dx = 0.0, dy = 0.0, dz = 0.0;       // direct sums
+            if (longlist) {
+#pragma unroll
+                for (int sl = 0; sl < kLongSlots; sl++) {
+                    const double *ps = part + (int64_t)sl * 3 * n;
+                    dx += ps[i];
+                    dy += ps[n + i];
+                    dz += ps[2 * n + i];
+                }
+            } else {
+                dx = acc_s[i];
+                dy = acc_s[n + i];
+                dz = acc_s[2 * n + i];
+            }
             const uint32_t o = perm[i];
-            ax[o] = acc_s[i] + lx;
-            ay[o] = acc_s[n + i] + ly;
-            az[o] = acc_s[2 * n + i] + lz;
+            ax[o] = dx + lx;
+            ay[o] = dy + ly;
+            az[o] = dz + lz;
         }
     }
 }
@@ -497,6 +531,9 @@ static void launch_p2p_t(const Workspace &ws, int64_t n, hipStream_t s) {
     k_p2p<T><<<(int)g, kWave * kP2PWaves, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first,
                                 ws.c_count, ws.gcell, ws.p2p_cnt, ws.p2p_seg, ws.p2p_stride,
                                 ws.acc_s, n);
+    k_p2p_long<T><<<kLongGrid, kWave * kP2PWaves, 0, s>>>(
+        ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first, ws.c_count, ws.gcell,
+        ws.p2p_cnt, ws.p2p_seg, ws.p2p_stride, ws.long_p2p, ws.p2p_part, n);
 }
 
 hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s) {
@@ -511,7 +548,8 @@ static void launch_l2p_p(const Workspace &ws, int64_t n, double *ax, double *ay,
     int64_t g = (ws.leaf_cap + kL2PWaves - 1) / kL2PWaves;
     g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
     k_l2p<P><<<(int)g, kWave * kL2PWaves, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.idx, ws.ent_cell, ws.c_first,
-                              ws.c_count, ws.gcell, ws.cleaf, ws.acc_s, n, ax, ay, az);
+                              ws.c_count, ws.gcell, ws.cleaf, ws.acc_s, ws.p2p_cnt, ws.p2p_part, n,
+                              ax, ay, az);
 }
 
 hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,

@@ -38,7 +38,7 @@ GRAV_CASES = {
                                  0),
 }
 LONG = {"disk2e4_p3_theta02_longm2l": ("m2l_maxlist", 512),
-        "clumps5e4_p3_s52_longp2p": ("p2p_maxlist", 256)}
+        "clumps5e4_p3_s52_longp2p": ("p2p_maxlist", 64)}
 
 
 @pytest.mark.parametrize("case", list(GRAV_CASES))
