@@ -10,6 +10,11 @@ ncorp_step call runs all K steps; its extra initial force evaluation is inside
 the timed region).  The headline value is the FP32-bulk form; the plain FP64
 form is measured the same way and reported beside it.
 
+Beside it (key "batched") the batched form is measured: 64 independent disks of
+log-uniform sizes in [1000, 50000] (about 0.8e6 moonlets in all), p = 4,
+theta_min = 0.5, FP32-bulk, leaf size picked by the autotuner, all disks stepped
+by the same launches, 50 steps captured in one hipGraph and replayed.
+
 Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this build
 runs on one GPU.
 """
@@ -125,6 +130,98 @@ def _errors(orc, d, acc, samples):
             "samples": int(len(tg))}
 
 
+def _run_batched(nc, args, device):
+    """The batched form: autotuned leaf size, then a 50-step ncorp_step_batched call
+    captured in a hipGraph and replayed (the state keeps evolving across replays)."""
+    import numpy as np
+    import torch
+    from paper_2310_20374_amd import autotune, inputs
+    sizes = inputs.batch_sizes(64, seed=0)
+    d, off = inputs.disk_batch(sizes)
+    n = len(d["x"])
+    base = {k: torch.tensor(v, device=device) for k, v in d.items()}
+    offd = torch.tensor(off, device=device)
+    prm = nc.params_default(4, theta_min=0.5, precision=nc.FP32_BULK)
+    t0 = time.perf_counter()
+    best, table = autotune.tune_leaf_size(nc, prm, base, offd, dt=args.dt, steps=3)
+    tune_s = time.perf_counter() - t0
+    prm.leaf_size = best
+    ns = args.batched_steps
+    ctx = nc.Context(prm, n, pair_capacity=1 << 18, device=device)
+    st = {k: v.clone() for k, v in base.items()}
+    pairs = torch.zeros((1 << 18, 3), dtype=torch.int64, device=device)
+    npairs = torch.zeros(ns, dtype=torch.int64, device=device)
+
+    def go():
+        ctx.step_batched(offd, st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["m"],
+                         st["R"], args.dt, ns, pairs, npairs)
+
+    # eager call: warm-up and the non-graph rate
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    go()
+    torch.cuda.synchronize()
+    eager_s = time.perf_counter() - t0
+    ctx.check_status()
+    for k in st:
+        st[k].copy_(base[k])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        go()
+    g.replay()                       # warm replay
+    torch.cuda.synchronize()
+    ctx.check_status()
+    t0 = time.perf_counter()
+    for _ in range(args.batched_replays):
+        g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.check_status()
+    total_steps = ns * args.batched_replays
+    # accuracy at the initial state: sampled moonlets against each disk's FP64 direct sum
+    errors = None
+    if not args.no_errors:
+        import oracle as orc
+        a = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(3)]
+        for k in st:
+            st[k].copy_(base[k])
+        ctx.build_tree_batched(offd, st["x"], st["y"], st["z"])
+        ctx.gravity(st["m"], *a)
+        torch.cuda.synchronize()
+        ctx.check_status()
+        acc = torch.stack(a, 1).cpu().numpy()
+        tg = inputs.sample_targets(n, args.samples)
+        disk_of = np.searchsorted(off, tg, side="right") - 1
+        ad = np.zeros((len(tg), 3))
+        for k in np.unique(disk_of):
+            sel = disk_of == k
+            lo, hi = off[k], off[k + 1]
+            ad[sel] = orc.direct_sum(d["x"][lo:hi], d["y"][lo:hi], d["z"][lo:hi], d["m"][lo:hi],
+                                     targets=tg[sel] - lo)
+        ac = orc.central_accel(d["x"][tg], d["y"][tg], d["z"][tg])
+
+        def stats(x, ref):
+            e = np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            return float(np.sqrt(np.mean(e * e))), float(e.max())
+
+        rt, mt = stats(acc[tg] + ac, ad + ac)
+        rm, mm = stats(acc[tg], ad)
+        errors = {"rms_total": rt, "max_total": mt, "rms_mutual": rm, "max_mutual": mm,
+                  "samples": int(len(tg))}
+    return {
+        "workload": "64 independent cold disks (sizes log-uniform in [1000, 50000], seed 0; "
+                    "disk k drawn with seed 1000+k), one root per disk, no cross-disk terms",
+        "n_disks": 64, "n": int(n), "p": 4, "theta_min": 0.5, "precision": "fp32-bulk",
+        "leaf_size": int(best), "autotune_ms_per_step": table, "autotune_seconds": tune_s,
+        "graph_steps": ns, "replays": args.batched_replays,
+        "value": n * total_steps / wall, "unit": "particle-steps/s",
+        "ms_per_step": wall * 1e3 / total_steps,
+        "eager_value": n * ns / eager_s, "eager_ms_per_step": eager_s * 1e3 / ns,
+        "collision_pairs_per_step": float(npairs.sum().item()) / ns,
+        "errors": errors,
+    }
+
+
 def _cpu_baseline(orc, n_sample, p, theta, s, thr, dt):
     """The oracle as it stands (single-threaded FP64 tree, recursive walk, full
     3^n tensors) for one step of a sub-disk drawn from the same distribution."""
@@ -167,6 +264,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="measure only the batched form (its object is printed alone)")
+    ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--batched-replays", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (three times) and exit: the "
                          "reference kernel for scaling the FETCH_SIZE/WRITE_SIZE counters")
@@ -191,6 +293,9 @@ def main():
 
     from paper_2310_20374_amd import inputs, ncorp
     device = "cuda:0"
+    if args.batched_only:
+        print(json.dumps({"batched": _run_batched(ncorp, args, device)}))
+        return 0
     d = inputs.disk(args.n, seed=0)
     prm64 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP64)
     prm32 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP32_BULK)
@@ -206,6 +311,13 @@ def main():
         r64 = _run(ncorp, prm64, d, args.dt, args.steps, args.warmup, True, device)
         print(f"# fp64: {r64['wall_s'] * 1e3 / args.steps:.3f} ms/step", file=sys.stderr,
               flush=True)
+
+    batched = None
+    if not args.no_batched:
+        batched = _run_batched(ncorp, args, device)
+        print(f"# batched: {batched['ms_per_step']:.3f} ms/step (graph), "
+              f"{batched['eager_ms_per_step']:.3f} eager, s={batched['leaf_size']}",
+              file=sys.stderr, flush=True)
 
     orc = None
     if not (args.no_errors and args.no_cpu_baseline):
@@ -278,6 +390,7 @@ def main():
         "phases_ms_per_step": phase_summary(r32),
         "tree": info,
         "collision_pairs_in_timed_steps": r32["pairs"],
+        "batched": batched,
     }
     print(json.dumps(out))
     return 0

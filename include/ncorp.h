@@ -133,9 +133,47 @@ int ncorp_step(ncorp_ctx *ctx, double *x, double *y, double *z, double *vx, doub
                int n_steps, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev,
                void *workspace, int64_t ws_bytes, void *stream);
 
+/* ---- batched form: many independent disks in one call ---------------------
+ * The moonlets of n_disks independent systems, each around its own central mass
+ * at the origin, are concatenated: disk d holds moonlets [off[d], off[d+1]) of
+ * every array.  The batched calls compute exactly what the plain call would give
+ * for every disk on its own -- one root cube and one tree per disk (a forest whose
+ * level 0 holds one root per non-empty disk), a dual walk started from (root,
+ * root) of every disk, no term and no pair across disks -- in the same launches
+ * for all disks.  Empty disks are allowed.
+ *
+ * disk_offsets: n_disks + 1 int64 in DEVICE memory, owned by the caller, read by
+ * the call's kernels (also on every replay of a captured call); they must be
+ * non-decreasing from 0 to n.  This is checked on the device: a violation makes
+ * every later kernel of the call do nothing and ncorp_get_status return
+ * NCORP_E_INVALID.  1 <= n_disks <= NCORP_MAX_DISKS, checked on the host.
+ *
+ * Graph capture: these calls (like ncorp_step) only enqueue kernels on `stream`
+ * -- no allocation, copy, memset or host synchronisation -- so a call may be
+ * captured into a hipGraph and replayed; the walk-queue tags advance on the
+ * device, so replays stay valid.  Capture after one eager call on the same
+ * workspace (the first walk on a new workspace clears its queue, which would
+ * otherwise be captured too), with phase timing off. */
+#define NCORP_MAX_DISKS 65536
+
+/* ncorp_build_tree for a batch of disks (Sect. 3.4.1, Sect. 3.4.6, applied per
+ * disk).  Later ncorp_gravity / ncorp_collide calls act on the forest. */
+int ncorp_build_tree_batched(ncorp_ctx *ctx, const int64_t *disk_offsets, int n_disks,
+                             const double *x, const double *y, const double *z, int64_t n,
+                             void *workspace, int64_t ws_bytes, void *stream);
+
+/* ncorp_step for a batch of disks (Sect. 4.1, App. B.1, per disk): same arrays,
+ * outputs and pair format as ncorp_step; pairs never join two disks. */
+int ncorp_step_batched(ncorp_ctx *ctx, const int64_t *disk_offsets, int n_disks, double *x,
+                       double *y, double *z, double *vx, double *vy, double *vz,
+                       const double *m, const double *R, int64_t n, double dt, int n_steps,
+                       int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, void *workspace,
+                       int64_t ws_bytes, void *stream);
+
 /* Waits for the context's last stream, then reports the device status word:
  * NCORP_OK, NCORP_E_CAPACITY (required_capacity, if not NULL, receives the size
- * that would have sufficed for the list that overflowed) or NCORP_E_NONFINITE.
+ * that would have sufficed for the list that overflowed), NCORP_E_INVALID (bad
+ * disk offsets of a batched call) or NCORP_E_NONFINITE.
  * The status is cleared by the next ncorp_build_tree / ncorp_step. */
 int ncorp_get_status(ncorp_ctx *ctx, int64_t *required_capacity);
 
@@ -147,7 +185,7 @@ enum {
     NCORP_INFO_N = 0, NCORP_INFO_NCELLS, NCORP_INFO_NLEAVES, NCORP_INFO_MAXLEVEL,
     NCORP_INFO_M2L, NCORP_INFO_P2P, NCORP_INFO_VISITED, NCORP_INFO_COL_CAND,
     NCORP_INFO_COL_TESTS, NCORP_INFO_M2L_DIR, NCORP_INFO_P2P_INTER, NCORP_INFO_M2L_MAXLIST,
-    NCORP_INFO_P2P_MAXLIST, NCORP_INFO_COUNT
+    NCORP_INFO_P2P_MAXLIST, NCORP_INFO_NROOTS, NCORP_INFO_COUNT
 };
 /* Waits for the stream and fills info[NCORP_INFO_COUNT] with sizes of the last
  * tree and walks (cells, leaves, deepest level, M2L and P2P cell pairs of the
@@ -155,8 +193,10 @@ enum {
  * performed (moonlets that cannot reach the other cell are culled first),
  * directed M2L interactions, directed moonlet-moonlet interactions of the direct
  * sums with i != j, longest per-target M2L list, longest per-leaf direct-sum list:
- * the sizes m2l_per_cell and p2p_per_leaf must cover).  The last three are filled
- * only while phase timing is on (ncorp_set_timing); otherwise they read 0. */
+ * the sizes m2l_per_cell and p2p_per_leaf must cover; these three are filled
+ * only while phase timing is on (ncorp_set_timing), otherwise they read 0), and
+ * the number of roots (level-0 cells: 1, or the non-empty disks of a batched
+ * call). */
 int ncorp_tree_info(ncorp_ctx *ctx, int64_t *info);
 
 enum {

@@ -248,6 +248,10 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.cnt_a = (int32_t *)take(4 * cnt);
     ws.scan_part = (int32_t *)take(4 * (nb + 4096));
     ws.hist = (uint32_t *)take(4 * 256 * (ntiles + 1));
+    ws.seg = (uint16_t *)take(2 * n);
+    ws.disk_max = (unsigned long long *)take(8 * (int64_t)kMaxDisks);
+    ws.disk_L = (double *)take(8 * (int64_t)kMaxDisks);
+    ws.disk_root = (int32_t *)take(4 * (int64_t)kMaxDisks);
     ws.pairs_tmp = (int64_t *)take(8 * ws.pair_cap);
     ws.pairs_alt = (int64_t *)take(8 * ws.pair_cap);
     ws.bytes = off;
@@ -286,21 +290,25 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
     ws.base = (char *)workspace;
     layout_workspace(ws, c->prm, n, pc);
     // the walk queue keeps tags from earlier walks; a new buffer or layout holds
-    // unknown bytes, so force the next walk to clear it
-    ws.epoch = (c->ws.base == ws.base && c->ws.queue == ws.queue && c->ws.queue_cap == ws.queue_cap)
-                   ? c->ws.epoch : 0xffffu;
+    // unknown bytes, so the next walk clears it
+    ws.clear_queue = !(c->ws.base == ws.base && c->ws.queue == ws.queue &&
+                       c->ws.queue_cap == ws.queue_cap) || c->ws.clear_queue;
     c->ws = ws;
     return NCORP_OK;
 }
 
+// disk_off: device offsets of a batched call (n_disks + 1 of them), or nullptr
 static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const double *z,
-                           int64_t n, hipStream_t s, bool fresh) {
+                           int64_t n, hipStream_t s, bool fresh, const int64_t *disk_off,
+                           int n_disks) {
     Workspace &ws = c->ws;
+    ws.ndisks = disk_off ? n_disks : 1;
     {
         PhaseTimer t(c, NCORP_PHASE_KEYS, s);
         if (fresh) HIPCHK(c, launch_reset_state(ws, s));
         else HIPCHK(c, launch_reset_tree_counters(ws, s));
-        HIPCHK(c, launch_keys(ws, x, y, z, n, c->prm.root_half_width, s));
+        HIPCHK(c, launch_keys(ws, x, y, z, n, c->prm.root_half_width,
+                              disk_off ? disk_off : nullptr, s));
     }
     {
         PhaseTimer t(c, NCORP_PHASE_SORT, s);
@@ -324,7 +332,28 @@ extern "C" int ncorp_build_tree(ncorp_ctx *c, const double *x, const double *y, 
     if (n < 1 || n > INT32_MAX - 1) return fail(c, NCORP_E_INVALID, "n must be in 1..2^31-2");
     int r = setup_workspace(c, n, workspace, ws_bytes);
     if (r != NCORP_OK) return r;
-    return build_tree_impl(c, x, y, z, n, (hipStream_t)stream, true);
+    return build_tree_impl(c, x, y, z, n, (hipStream_t)stream, true, nullptr, 1);
+}
+
+static int check_disks(ncorp_ctx *c, const int64_t *disk_offsets, int n_disks) {
+    if (!disk_offsets) return fail(c, NCORP_E_INVALID, "disk_offsets is NULL");
+    if (n_disks < 1 || n_disks > NCORP_MAX_DISKS)
+        return fail(c, NCORP_E_INVALID, "n_disks must be in 1..NCORP_MAX_DISKS");
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_build_tree_batched(ncorp_ctx *c, const int64_t *disk_offsets, int n_disks,
+                                        const double *x, const double *y, const double *z,
+                                        int64_t n, void *workspace, int64_t ws_bytes,
+                                        void *stream) {
+    if (!c) return NCORP_E_INVALID;
+    int r = check_disks(c, disk_offsets, n_disks);
+    if (r != NCORP_OK) return r;
+    if (!x || !y || !z) return fail(c, NCORP_E_INVALID, "position pointer is NULL");
+    if (n < 1 || n > INT32_MAX - 1) return fail(c, NCORP_E_INVALID, "n must be in 1..2^31-2");
+    r = setup_workspace(c, n, workspace, ws_bytes);
+    if (r != NCORP_OK) return r;
+    return build_tree_impl(c, x, y, z, n, (hipStream_t)stream, true, disk_offsets, n_disks);
 }
 
 static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, double *az,
@@ -413,11 +442,11 @@ __global__ void k_zero_cursor(DevState *st) {
 }
 }
 
-extern "C" int ncorp_step(ncorp_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
-                          double *vz, const double *m, const double *R, int64_t n, double dt,
-                          int n_steps, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev,
-                          void *workspace, int64_t ws_bytes, void *stream) {
-    if (!c) return NCORP_E_INVALID;
+static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double *x, double *y,
+                     double *z, double *vx, double *vy, double *vz, const double *m,
+                     const double *R, int64_t n, double dt, int n_steps, int64_t *pairs,
+                     int64_t cap, int64_t *n_pairs_dev, void *workspace, int64_t ws_bytes,
+                     void *stream) {
     if (!x || !y || !z || !vx || !vy || !vz || !m || !R || !n_pairs_dev || (cap > 0 && !pairs))
         return fail(c, NCORP_E_INVALID, "array pointer is NULL");
     if (n < 1 || n > INT32_MAX - 1) return fail(c, NCORP_E_INVALID, "n must be in 1..2^31-2");
@@ -430,7 +459,7 @@ extern "C" int ncorp_step(ncorp_ctx *c, double *x, double *y, double *z, double 
     Workspace &ws = c->ws;
     double *ax = ws.acc, *ay = ws.acc + n, *az = ws.acc + 2 * n;
     const bool mutual = c->prm.p > 0;
-    r = build_tree_impl(c, x, y, z, n, s, true);
+    r = build_tree_impl(c, x, y, z, n, s, true, disk_off, n_disks);
     if (r != NCORP_OK) return r;
     k_zero_cursor<<<1, 64, 0, s>>>(ws.st);
     if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
@@ -446,7 +475,8 @@ extern "C" int ncorp_step(ncorp_ctx *c, double *x, double *y, double *z, double 
             PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
             HIPCHK(c, launch_drift(x, y, z, vx, vy, vz, n, dt, s));
         }
-        if ((r = build_tree_impl(c, x, y, z, n, s, false)) != NCORP_OK) return r;
+        if ((r = build_tree_impl(c, x, y, z, n, s, false, disk_off, n_disks)) != NCORP_OK)
+            return r;
         if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
         const double h = (k == n_steps - 1) ? 0.5 * dt : dt;
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
@@ -455,6 +485,28 @@ extern "C" int ncorp_step(ncorp_ctx *c, double *x, double *y, double *z, double 
     }
     c->last = s;
     return NCORP_OK;
+}
+
+extern "C" int ncorp_step(ncorp_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
+                          double *vz, const double *m, const double *R, int64_t n, double dt,
+                          int n_steps, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev,
+                          void *workspace, int64_t ws_bytes, void *stream) {
+    if (!c) return NCORP_E_INVALID;
+    return step_impl(c, nullptr, 1, x, y, z, vx, vy, vz, m, R, n, dt, n_steps, pairs, cap,
+                     n_pairs_dev, workspace, ws_bytes, stream);
+}
+
+extern "C" int ncorp_step_batched(ncorp_ctx *c, const int64_t *disk_offsets, int n_disks,
+                                  double *x, double *y, double *z, double *vx, double *vy,
+                                  double *vz, const double *m, const double *R, int64_t n,
+                                  double dt, int n_steps, int64_t *pairs, int64_t cap,
+                                  int64_t *n_pairs_dev, void *workspace, int64_t ws_bytes,
+                                  void *stream) {
+    if (!c) return NCORP_E_INVALID;
+    int r = check_disks(c, disk_offsets, n_disks);
+    if (r != NCORP_OK) return r;
+    return step_impl(c, disk_offsets, n_disks, x, y, z, vx, vy, vz, m, R, n, dt, n_steps, pairs,
+                     cap, n_pairs_dev, workspace, ws_bytes, stream);
 }
 
 static int sync_state(ncorp_ctx *c, DevState &h) {
@@ -479,6 +531,8 @@ extern "C" int ncorp_get_status(ncorp_ctx *c, int64_t *required) {
         std::snprintf(c->err, sizeof(c->err), "a tree pass stopped waiting (flags 0x%x)", h.status);
         return NCORP_E_HIP;
     }
+    if (h.status & ST_BAD_OFFSETS)
+        return fail(c, NCORP_E_INVALID, "disk offsets are not a non-decreasing 0..n sequence");
     if (h.status & ST_NONFINITE) return fail(c, NCORP_E_NONFINITE, "non-finite position");
     return NCORP_OK;
 }
@@ -498,6 +552,7 @@ extern "C" int ncorp_tree_info(ncorp_ctx *c, int64_t *info) {
     info[NCORP_INFO_COL_CAND] = h.ncand;
     info[NCORP_INFO_COL_TESTS] = h.col_tests;
     info[NCORP_INFO_M2L_DIR] = 2 * (int64_t)h.nm2l;
+    info[NCORP_INFO_NROOTS] = h.level_count[0];
     info[NCORP_INFO_P2P_INTER] = h.p2p_inter;
     info[NCORP_INFO_M2L_MAXLIST] = h.m2l_maxlist;
     info[NCORP_INFO_P2P_MAXLIST] = h.p2p_maxlist;

@@ -160,7 +160,8 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
                 const int32_t *__restrict__ c_count, const int32_t *__restrict__ c_child,
                 const int32_t *__restrict__ c_nchild, const int32_t *__restrict__ c_parent,
                 int32_t *c_arrive, double4 *gcell, double *c_mass, double *c_rmax,
-                double *mult, float *mult32) {
+                double *mult, float *mult32, const uint16_t *__restrict__ seg,
+                const double *__restrict__ disk_L) {
     constexpr int NM = n_mult(P);
     constexpr int NP = P > 1 ? P : 1;               // powers 0..P-1
     constexpr int NMS = NM > 0 ? NM : 1;
@@ -233,7 +234,8 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
                 }
             }
             rm = wave_max(rm);
-            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
+            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c],
+                                         seg ? disk_L[seg[f]] : L);
             if (fc < rm) rm = fc;
             if (lane == 0) {
                 st_c(&gcell[c].x, sx); st_c(&gcell[c].y, sy); st_c(&gcell[c].z, sz);
@@ -275,7 +277,8 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
             }
             rm = wave_max(rm);
             const int f = c_first[c];
-            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
+            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c],
+                                         seg ? disk_L[seg[f]] : L);
             if (fc < rm) rm = fc;
             if (lane == 0) {
                 st_c(&gcell[c].x, sx); st_c(&gcell[c].y, sy); st_c(&gcell[c].z, sz);
@@ -346,11 +349,13 @@ __global__ void k_rcrit(const DevState *__restrict__ st, const double *__restric
                         const double *__restrict__ c_rmax, double4 *gcell, double *c_theta,
                         double theta_min, int theta_mode, const int32_t *__restrict__ c_count,
                         const int32_t *__restrict__ c_child, const int32_t *__restrict__ c_nchild,
-                        WCell *__restrict__ wg) {
+                        WCell *__restrict__ wg, const uint16_t *__restrict__ seg,
+                        const int32_t *__restrict__ c_first, const int32_t *__restrict__ disk_root) {
     const int nc = st->ncells;
     if (nc <= 0 || (st->status & kSkipMask)) return;
-    const double Mroot = c_mass[0];
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+        // M_root: mass of the root of this cell's own tree (its disk's)
+        const double Mroot = c_mass[seg ? disk_root[seg[c_first[c]]] : 0];
         double th = theta_mode == 1 ? theta_min : theta_of_mass(c_mass[c], Mroot, theta_min);
         c_theta[c] = th;
         const double rc = c_rmax[c] / th;
@@ -396,7 +401,8 @@ static void launch_gc(const Workspace &ws, hipStream_t s) {
     k_gravity_climb<P><<<g, kWave, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell,
                                          ws.c_level, ws.c_first, ws.c_count, ws.c_child,
                                          ws.c_nchild, ws.c_parent, ws.c_arrive, ws.gcell,
-                                         ws.c_mass, ws.c_rmax, ws.mult, ws.mult32);
+                                         ws.c_mass, ws.c_rmax, ws.mult, ws.mult32,
+                                         ws.ndisks > 1 ? ws.seg : nullptr, ws.disk_L);
 }
 
 hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_params &prm,
@@ -414,7 +420,9 @@ hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_para
     }
     k_rcrit<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_mass, ws.c_rmax, ws.gcell,
                                                         ws.c_theta, prm.theta_min, prm.theta_mode,
-                                                        ws.c_count, ws.c_child, ws.c_nchild, ws.wg);
+                                                        ws.c_count, ws.c_child, ws.c_nchild, ws.wg,
+                                                        ws.ndisks > 1 ? ws.seg : nullptr,
+                                                        ws.c_first, ws.disk_root);
     return hipGetLastError();
 }
 
@@ -430,7 +438,8 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
                   const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
                   const int32_t *__restrict__ c_child, const int32_t *__restrict__ c_nchild,
                   const int32_t *__restrict__ c_parent, int32_t *c_arrive, double4 *ccell,
-                  double *c_crmax) {
+                  double *c_crmax,
+                  const uint16_t *__restrict__ seg, const double *__restrict__ disk_L) {
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     const double L = st->L;
@@ -465,7 +474,8 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
             }
             rm = wave_max(rm);
             ex = wave_max(ex);
-            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
+            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c],
+                                         seg ? disk_L[seg[f]] : L);
             if (fc < rm) rm = fc;
             if (lane == 0) {
                 st_c(&ccell[c].x, sx); st_c(&ccell[c].y, sy); st_c(&ccell[c].z, sz);
@@ -504,7 +514,8 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
             rm = wave_max(rm);
             ex = wave_max(ex);
             const int f = c_first[c];
-            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c], L);
+            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c],
+                                         seg ? disk_L[seg[f]] : L);
             if (fc < rm) rm = fc;
             if (lane == 0) {
                 st_c(&ccell[c].x, sx); st_c(&ccell[c].y, sy); st_c(&ccell[c].z, sz);
@@ -522,7 +533,7 @@ hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hip
     k_collision_climb<<<g, kWave, 0, s>>>(
         ws.st, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, dt, ws.ent_cell, ws.c_level,
         ws.c_first, ws.c_count, ws.c_child, ws.c_nchild, ws.c_parent, ws.c_arrive, ws.ccell,
-        ws.c_crmax);
+        ws.c_crmax, ws.ndisks > 1 ? ws.seg : nullptr, ws.disk_L);
     k_pack_collision<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.ccell, ws.c_count,
                                                                  ws.c_child, ws.c_nchild, ws.wc);
     return hipGetLastError();

@@ -90,6 +90,68 @@ __global__ void k_max_abs(const double *__restrict__ x, const double *__restrict
     if (__any(bad) && l == 0) atomicOr(&st->status, (int32_t)ST_NONFINITE);
 }
 
+// Batched calls: block d writes the disk id d over moonlets [off[d], off[d+1]) and
+// clears the disk's running max; the offsets are checked on the way (non-decreasing,
+// from 0 to n), a violation latches ST_BAD_OFFSETS and every later pass of the call
+// does nothing.  Ids stay below NCORP_MAX_DISKS whatever the offsets hold.
+__global__ void k_disk_ids(const int64_t *__restrict__ off, int nd, int64_t n,
+                           uint16_t *__restrict__ seg, unsigned long long *__restrict__ disk_max,
+                           DevState *st) {
+    for (int d = blockIdx.x; d < nd; d += gridDim.x) {
+        const int64_t a = off[d], b = off[d + 1];
+        if (threadIdx.x == 0) {
+            disk_max[d] = 0ull;
+            const bool bad = a > b || a < 0 || b > n || (d == 0 && a != 0) ||
+                             (d == nd - 1 && b != n);
+            if (bad) atomicOr(&st->status, (int32_t)ST_BAD_OFFSETS);
+        }
+        const int64_t lo = a < 0 ? 0 : (a > n ? n : a);
+        const int64_t hi = b < lo ? lo : (b > n ? n : b);
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) seg[i] = (uint16_t)d;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->ndisks = nd;
+}
+
+// max |coordinate| per disk: a wave whose 64 moonlets share a disk reduces first
+// and issues one atomic, otherwise every lane issues its own.
+__global__ void k_max_abs_seg(const double *__restrict__ x, const double *__restrict__ y,
+                              const double *__restrict__ z, int64_t n,
+                              const uint16_t *__restrict__ seg,
+                              unsigned long long *__restrict__ disk_max, DevState *st) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t wbase = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t b = wbase; b < n; b += stride) {
+        const int64_t i = b + lane;
+        const bool valid = i < n;
+        unsigned long long m = 0ull;
+        int d = 0;
+        if (valid) {
+            d = seg[i];
+            double v[3] = {x[i], y[i], z[i]};
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                double a = fabs(v[k]);
+                if (!(a <= 1.79769313486231570e308)) { bad = true; continue; }
+                unsigned long long u = (unsigned long long)__double_as_longlong(a);
+                m = u > m ? u : m;
+            }
+        }
+        const int d0 = __shfl(d, 0);
+        if (__all(valid && d == d0)) {
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                unsigned long long t = __shfl_xor(m, o);
+                m = t > m ? t : m;
+            }
+            if (lane == 0) atomicMax(&disk_max[d0], m);
+        } else if (valid) {
+            atomicMax(&disk_max[d], m);
+        }
+    }
+    if (__any(bad) && lane == 0) atomicOr(&st->status, (int32_t)ST_NONFINITE);
+}
+
 // ------------------------------------------------------------------ keys
 // q = floor((x + L) * 2^20 / L), clamped to [0, 2^21 - 1]; with L a power of two the
 // scale is exact, so the result depends only on the correctly rounded x + L.
@@ -144,36 +206,67 @@ __device__ __forceinline__ uint64_t hilbert21(uint32_t q0, uint32_t q1, uint32_t
     return h;
 }
 
+// smallest power of two strictly above mx (1 when every coordinate is 0)
+__device__ __forceinline__ double root_half_width(unsigned long long mx_bits) {
+    const double mx = __longlong_as_double((long long)mx_bits);
+    if (!(mx > 0.0)) return 1.0;
+    int e;
+    frexp(mx, &e);           // mx = f 2^e, 0.5 <= f < 1
+    return ldexp(1.0, e);
+}
+
+// Keys of every moonlet against the root cube of its disk (seg == nullptr: one
+// disk).  mx: per-disk max |coordinate| bit patterns; fixed_L > 0 overrides them.
+// Also records each disk's half-width in disk_L (and disk 0's in st->L).
 __global__ void k_keys(const double *__restrict__ x, const double *__restrict__ y,
                        const double *__restrict__ z, int64_t n, double fixed_L,
+                       const unsigned long long *__restrict__ mx,
+                       const uint16_t *__restrict__ seg, int nd, double *__restrict__ disk_L,
                        DevState *st, uint64_t *__restrict__ keys, uint32_t *__restrict__ idx) {
-    double L = fixed_L;
-    if (!(L > 0.0)) {
-        double mx = st->max_abs;     // holds the bit pattern written by the atomic max
-        if (mx > 0.0) {
-            int e;
-            frexp(mx, &e);           // mx = f 2^e, 0.5 <= f < 1
-            L = ldexp(1.0, e);       // smallest power of two strictly above mx
-        } else {
-            L = 1.0;
-        }
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gid < nd) {
+        const double L = fixed_L > 0.0 ? fixed_L : root_half_width(mx[gid]);
+        disk_L[gid] = L;
+        if (gid == 0) st->L = L;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->L = L;
-    double scale = 1048576.0 / L;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    double L = fixed_L > 0.0 ? fixed_L : root_half_width(mx[0]);
+    for (int64_t i = gid; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (seg && !(fixed_L > 0.0)) L = root_half_width(mx[seg[i]]);
+        const double scale = 1048576.0 / L;
         keys[i] = hilbert21(quantize(x[i], L, scale), quantize(y[i], L, scale),
                             quantize(z[i], L, scale));
         idx[i] = (uint32_t)i;
     }
 }
 
+// radix passes of a build: 8 over the 63-bit keys, then (batched calls) 1 or 2 over
+// the disk id, the most significant digit
+static int disk_passes(int nd) { return nd <= 1 ? 0 : (nd <= 256 ? 1 : 2); }
+
 hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
-                       const double *z, int64_t n, double root_half_width, hipStream_t s) {
-    // also run with a fixed root: it latches non-finite coordinates
-    k_max_abs<<<grid_for(n, 256, 1024), 256, 0, s>>>(x, y, z, n, ws.st);
-    k_keys<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, n, root_half_width, ws.st, ws.keys,
-                                            ws.idx);
+                       const double *z, int64_t n, double root_half_width,
+                       const int64_t *disk_off, hipStream_t s) {
+    // the sort ends in ws.keys / ws.idx: with an odd number of passes start in the
+    // other buffers
+    const bool odd = (8 + disk_passes(ws.ndisks)) % 2 == 1;
+    uint64_t *kout = odd ? ws.keys_alt : ws.keys;
+    uint32_t *vout = odd ? ws.idx_alt : ws.idx;
+    if (disk_off) {
+        const int nd = ws.ndisks;
+        k_disk_ids<<<nd < 4096 ? nd : 4096, 256, 0, s>>>(disk_off, nd, n, ws.seg, ws.disk_max,
+                                                         ws.st);
+        // also run with a fixed root: it latches non-finite coordinates
+        k_max_abs_seg<<<grid_for(n, 256, 1024), 256, 0, s>>>(x, y, z, n, ws.seg, ws.disk_max,
+                                                             ws.st);
+        const int64_t cover = n > nd ? n : nd;
+        k_keys<<<grid_for(cover, 256), 256, 0, s>>>(x, y, z, n, root_half_width, ws.disk_max,
+                                                    ws.seg, nd, ws.disk_L, ws.st, kout, vout);
+    } else {
+        k_max_abs<<<grid_for(n, 256, 1024), 256, 0, s>>>(x, y, z, n, ws.st);
+        k_keys<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, n, root_half_width,
+                                                (const unsigned long long *)&ws.st->max_abs,
+                                                nullptr, 1, ws.disk_L, ws.st, kout, vout);
+    }
     return hipGetLastError();
 }
 
@@ -188,7 +281,8 @@ constexpr int kSortTile = kSortThreads * kSortItems; // 4096
 constexpr int kSortWaves = kSortThreads / kWave;
 
 __global__ void __launch_bounds__(kSortThreads)
-k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t *hist,
+k_radix_hist(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+             const uint16_t *__restrict__ dseg, int64_t n, int shift, uint32_t *hist,
              int ntiles) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -196,7 +290,11 @@ k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t *
     int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int k = 0; k < kSortItems; k++) {
         int64_t i = base + k * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) {
+            const uint32_t d = dseg ? ((uint32_t)dseg[vals[i]] >> shift) & 255u
+                                    : (uint32_t)(keys[i] >> shift) & 255u;
+            atomicAdd(&h[d], 1u);
+        }
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
@@ -234,8 +332,9 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
-                int shift, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals,
+                uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                const uint16_t *__restrict__ dseg, int64_t n, int shift,
+                const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals,
                 int ntiles) {
     __shared__ uint32_t dbase[256];              // digit base offsets, global
     __shared__ uint32_t wcnt[kSortWaves][256];   // per-wave digit counters
@@ -257,16 +356,20 @@ k_radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ v
     const int64_t wbase = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortTile / kSortWaves);
     uint64_t key[kSortItems];
     uint32_t val[kSortItems];
+    uint32_t dig[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         int64_t i = wbase + r * kWave + lane;
         if (i < n) {
             key[r] = kin[i];
             val[r] = vin[i];
-            atomicAdd(&wcnt[w][(key[r] >> shift) & 255u], 1u);
+            dig[r] = dseg ? ((uint32_t)dseg[val[r]] >> shift) & 255u
+                          : (uint32_t)(key[r] >> shift) & 255u;
+            atomicAdd(&wcnt[w][dig[r]], 1u);
         } else {
             key[r] = 0;
             val[r] = 0;
+            dig[r] = 0;
         }
     }
     __syncthreads();
@@ -287,7 +390,7 @@ k_radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ v
         bool valid = i < n;
         uint64_t act = __ballot(valid);
         if (act == 0ull) break;
-        uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+        uint32_t d = dig[r];
         uint64_t peers = act;
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -310,19 +413,26 @@ k_radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ v
 
 hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s) {
     int ntiles = (int)((n + kSortTile - 1) / kSortTile);
+    const int npass = 8 + disk_passes(ws.ndisks);
+    // launch_keys wrote the keys where an even number of swaps later lands in ws.keys
     uint64_t *ka = ws.keys, *kb = ws.keys_alt;
     uint32_t *va = ws.idx, *vb = ws.idx_alt;
+    if (npass % 2 == 1) {
+        ka = ws.keys_alt; kb = ws.keys;
+        va = ws.idx_alt; vb = ws.idx;
+    }
     uint32_t *totals = ws.hist + (int64_t)256 * ntiles;
-    for (int pass = 0; pass < 8; pass++) {
-        int shift = 8 * pass;
-        k_radix_hist<<<ntiles, kSortThreads, 0, s>>>(ka, n, shift, ws.hist, ntiles);
+    for (int pass = 0; pass < npass; pass++) {
+        // passes 0-7: key digits; then the disk id, low byte first
+        const uint16_t *dseg = pass < 8 ? nullptr : ws.seg;
+        const int shift = pass < 8 ? 8 * pass : 8 * (pass - 8);
+        k_radix_hist<<<ntiles, kSortThreads, 0, s>>>(ka, va, dseg, n, shift, ws.hist, ntiles);
         k_radix_scan<<<256, 256, 0, s>>>(ws.hist, ntiles, totals);
-        k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(ka, va, kb, vb, n, shift, ws.hist,
+        k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(ka, va, kb, vb, dseg, n, shift, ws.hist,
                                                         totals, ntiles);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
-    // 8 passes: the result is back in ws.keys / ws.idx
     return hipGetLastError();
 }
 

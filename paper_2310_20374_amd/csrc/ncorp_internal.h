@@ -40,7 +40,7 @@ __host__ __device__ constexpr int cidx(int a, int b, int c) { return sidx(a, b, 
 enum StatusBits : int32_t {
     ST_CAP_CELLS = 1, ST_CAP_QUEUE = 2, ST_CAP_M2L = 4, ST_CAP_P2P = 8,
     ST_CAP_PAIRS = 16, ST_NONFINITE = 32, ST_CAP_LISTS = 64, ST_WALK_STALL = 128,
-    ST_BAD_ITEM = 256
+    ST_BAD_ITEM = 256, ST_BAD_OFFSETS = 512
 };
 // Any of these leaves the tree or the interaction lists incomplete: later passes
 // then do nothing rather than follow indices that were never written.
@@ -70,7 +70,10 @@ constexpr int kLongSlots = 8;
 constexpr int kLongGrid = 2048;
 
 constexpr int32_t kSkipMask = ST_CAP_CELLS | ST_CAP_QUEUE | ST_CAP_M2L | ST_CAP_P2P |
-                              ST_CAP_LISTS | ST_WALK_STALL | ST_BAD_ITEM;
+                              ST_CAP_LISTS | ST_WALK_STALL | ST_BAD_ITEM | ST_BAD_OFFSETS;
+
+// independent disks of one batched call (a forest with one root per non-empty disk)
+constexpr int kMaxDisks = NCORP_MAX_DISKS;
 
 // Device-side counters of one tree / walk, kept in the workspace.
 struct DevState {
@@ -81,8 +84,9 @@ struct DevState {
     int32_t ncells, nleaves, maxlevel, pad1;
     int32_t level_count[kMaxDepth + 2];
     int32_t level_off[kMaxDepth + 3];
-    double L;                  // root half-width
+    double L;                  // root half-width (of disk 0 in a batched call)
     double max_abs;            // max |coordinate| (bit pattern max for >= 0 doubles)
+    int32_t ndisks, nroots;    // disks of the call; level-0 cells (non-empty disks)
     // gravity walk
     int32_t nm2l, np2p;        // unordered cell pairs (exact counts)
     int32_t m2l_slots, p2p_slots;  // list slots reserved (entries plus (-1,-1) gaps)
@@ -105,8 +109,9 @@ struct WalkQueue {
     uint64_t pad1[15];
     uint64_t processed;        // items processed (children reserved first)
     uint64_t pad2[15];
-    uint32_t epoch;            // tag of valid items in this walk
-    uint32_t pad3[31];
+    uint32_t epoch;            // tag of valid items in this walk (advanced on the device)
+    uint32_t wrapped;          // the tag wrapped: the queue must be cleared first
+    uint32_t pad3[30];
 };
 
 // What the walk reads of a cell, packed: centre, critical radius, moonlet count,
@@ -200,8 +205,16 @@ struct Workspace {
     // scratch for scans and sorts
     int32_t *scan_part = nullptr;                     // block partials
     uint32_t *hist = nullptr;                         // radix histograms
+    // batched calls: disk of each moonlet (input order; the sort keeps disks
+    // contiguous, so it is also the disk of each tree position), per-disk max
+    // |coordinate| and root half-width
+    uint16_t *seg = nullptr;
+    unsigned long long *disk_max = nullptr;
+    double *disk_L = nullptr;
+    int32_t *disk_root = nullptr;                     // level-0 cell of each disk
+    int ndisks = 1;                                   // host copy; 1 = plain call
     DevState *st = nullptr;
-    uint32_t epoch = 0;
+    bool clear_queue = false;                         // new buffer: clear before next walk
 };
 
 // Layout of the workspace for given capacities; with base == nullptr only the
@@ -215,8 +228,10 @@ hipError_t launch_reset_state(const Workspace &ws, hipStream_t s);
 hipError_t launch_reset_tree_counters(const Workspace &ws, hipStream_t s);
 hipError_t launch_gather_scaled(const Workspace &ws, const double *src, double scale,
                                 double *dst, int64_t n, hipStream_t s);
+// disk_off: n_disks + 1 device offsets of a batched call (nullptr for a plain call)
 hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
-                       const double *z, int64_t n, double root_half_width, hipStream_t s);
+                       const double *z, int64_t n, double root_half_width,
+                       const int64_t *disk_off, hipStream_t s);
 hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s);
 hipError_t launch_gather_pos(const Workspace &ws, const double *x, const double *y,
                              const double *z, int64_t n, hipStream_t s);

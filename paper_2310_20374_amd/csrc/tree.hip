@@ -10,6 +10,10 @@
 // level gives each cell's breadth-first index directly: cells are ordered by
 // level, then by key prefix, so children of consecutive parents are contiguous --
 // the ordering the paper's flat tree uses.  No per-level kernel launches.
+//
+// Batched calls build a forest: moonlets of different disks share no cell (their
+// common-prefix length counts as -1), each disk's first moonlet starts all levels
+// from 0, so level 0 holds one root per non-empty disk, in disk order.
 #include "ncorp_internal.h"
 
 namespace ncorp {
@@ -24,21 +28,24 @@ __device__ __forceinline__ int cpl_digits(uint64_t a, uint64_t b) {
 
 // code: L (bits 0-7), dv (bits 8-15), leaf-start flag (bit 16)
 __global__ void __launch_bounds__(kTreeBlock)
-k_leaf_levels(const uint64_t *__restrict__ keys, int64_t n, int s, uint32_t *__restrict__ code,
-              int32_t *__restrict__ partials) {
+k_leaf_levels(const uint64_t *__restrict__ keys, const uint16_t *__restrict__ seg, int64_t n,
+              int s, uint32_t *__restrict__ code, int32_t *__restrict__ partials) {
     extern __shared__ uint64_t sk[];                 // keys [b0 - s, b0 + B + s)
     int32_t *sc = (int32_t *)(sk + kTreeBlock + 2 * s);   // c(j), j in [b0 - s, b0 + B)
+    uint16_t *sd = (uint16_t *)(sc + kTreeBlock + s);      // disk ids, same span as sk
     __shared__ int32_t red[kTreeBlock / kWave];
     const int64_t b0 = (int64_t)blockIdx.x * kTreeBlock;
     const int span = kTreeBlock + 2 * s;
     for (int k = threadIdx.x; k < span; k += kTreeBlock) {
         int64_t j = b0 - s + k;
-        sk[k] = (j >= 0 && j < n) ? keys[j] : 0ull;
+        const bool in = j >= 0 && j < n;
+        sk[k] = in ? keys[j] : 0ull;
+        sd[k] = (in && seg) ? seg[j] : (uint16_t)0;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kTreeBlock + s; k += kTreeBlock) {
         int64_t j = b0 - s + k;
-        sc[k] = (j >= 0 && j + s < n) ? cpl_digits(sk[k], sk[k + s]) : -1;
+        sc[k] = (j >= 0 && j + s < n && sd[k] == sd[k + s]) ? cpl_digits(sk[k], sk[k + s]) : -1;
     }
     __syncthreads();
     const int64_t i = b0 + threadIdx.x;
@@ -52,7 +59,7 @@ k_leaf_levels(const uint64_t *__restrict__ keys, int64_t n, int s, uint32_t *__r
         }
         int L = M + 1 < kMaxDepth ? M + 1 : kMaxDepth;
         int dv;
-        if (i == 0) dv = 0;
+        if (i == 0 || sd[threadIdx.x + s - 1] != sd[threadIdx.x + s]) dv = 0;
         else {
             uint64_t a = sk[threadIdx.x + s - 1], b = sk[threadIdx.x + s];
             dv = (a == b) ? kMaxDepth + 1 : cpl_digits(a, b) + 1;
@@ -193,7 +200,8 @@ k_emit_cells(const int32_t *__restrict__ ent_start, const uint32_t *__restrict__
              int32_t *__restrict__ c_first, int32_t *__restrict__ c_child,
              int32_t *__restrict__ c_nchild, int32_t *__restrict__ c_parent,
              int32_t *__restrict__ c_entry, uint64_t *__restrict__ c_prefix,
-             int32_t *__restrict__ ent_cell) {
+             int32_t *__restrict__ ent_cell, const uint16_t *__restrict__ seg,
+             int32_t *__restrict__ disk_root) {
     __shared__ int32_t wcnt[kTreeBlock / kWave][kNLev];
     __shared__ int32_t loff[kNLev];
     const int K = st->nleaves;
@@ -239,6 +247,7 @@ k_emit_cells(const int32_t *__restrict__ ent_start, const uint32_t *__restrict__
         c_first[ci] = start;
         c_entry[ci] = (int32_t)e;
         c_prefix[ci] = key >> (3 * (kMaxDepth - l));
+        if (l == 0) disk_root[seg ? seg[start] : 0] = (int32_t)ci;
         if (l < L) {
             c_child[ci] = loff[l + 1] + excl(l + 1);
         } else {
@@ -267,15 +276,16 @@ __global__ void k_cell_ranges(const DevState *__restrict__ st, int64_t n,
         int par = c_parent[c];
         bool last_child = par >= 0 && (c + 1 >= nc || c_parent[c + 1] != par);
         if (last_child) c_nchild[par] = c - c_child[par] + 1;
+        // roots (parent -1) are siblings of each other: the next root starts where
+        // a root ends, and the last root ends at n
         int x = c;
-        for (int up = 0; up <= kMaxDepth && x > 0; up++) {   // bounded by the depth cap
+        for (int up = 0; up <= kMaxDepth + 1 && x >= 0; up++) {   // bounded by the depth cap
             int px = c_parent[x];
             if (x + 1 < nc && c_parent[x + 1] == px) break;
             x = px;
         }
-        if (x < 0) x = 0;
         int end, eend;
-        if (x == 0) { end = (int)n; eend = K; }
+        if (x < 0) { end = (int)n; eend = K; }
         else { end = c_first[x + 1]; eend = c_entry[x + 1]; }
         c_count[c] = end - c_first[c];
         c_nent[c] = eend - c_entry[c];
@@ -293,8 +303,10 @@ __global__ void k_tree_guard(DevState *st) {
 hipError_t launch_build_tree(const Workspace &ws, int64_t n, int s, hipStream_t st) {
     int nb = (int)((n + kTreeBlock - 1) / kTreeBlock);
     size_t shmem = (size_t)(kTreeBlock + 2 * s) * sizeof(uint64_t) +
-                   (size_t)(kTreeBlock + s) * sizeof(int32_t);
-    k_leaf_levels<<<nb, kTreeBlock, shmem, st>>>(ws.keys, n, s, ws.code, ws.scan_part);
+                   (size_t)(kTreeBlock + s) * sizeof(int32_t) +
+                   (size_t)(kTreeBlock + 2 * s) * sizeof(uint16_t);
+    const uint16_t *seg = ws.ndisks > 1 ? ws.seg : nullptr;
+    k_leaf_levels<<<nb, kTreeBlock, shmem, st>>>(ws.keys, seg, n, s, ws.code, ws.scan_part);
     k_scan_small<<<1, kTreeBlock, 0, st>>>(ws.scan_part, nb, &ws.st->nleaves);
     k_emit_entries<<<nb, kTreeBlock, 0, st>>>(ws.code, n, ws.scan_part, ws.ent_start, ws.ent_code);
     // entries: at most n; launch for the worst case, blocks past K exit
@@ -305,7 +317,7 @@ hipError_t launch_build_tree(const Workspace &ws, int64_t n, int s, hipStream_t 
     k_emit_cells<<<nb, kTreeBlock, 0, st>>>(ws.ent_start, ws.ent_code, ws.keys, lcount, ws.st,
                                             ws.cell_cap, ws.c_level, ws.c_first, ws.c_child,
                                             ws.c_nchild, ws.c_parent, ws.c_entry, ws.c_prefix,
-                                            ws.ent_cell);
+                                            ws.ent_cell, seg, ws.disk_root);
     int g = (int)((ws.cell_cap + 255) / 256);
     if (g > 2048) g = 2048;
     k_cell_ranges<<<g, 256, 0, st>>>(ws.st, n, ws.c_first, ws.c_child, ws.c_parent, ws.c_entry,

@@ -45,36 +45,50 @@ __device__ __forceinline__ int wave_excl_sum(int v, int lane, int &total) {
     return x - v;
 }
 
-// Resets the queue and, for the gravity walk, the per-target list counters.
-__global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, uint32_t epoch,
+// Advances the queue tag on the device, so a captured and replayed sequence of
+// walks never meets a stale item carrying its own tag.  When the 16-bit tag wraps
+// (or the host asks, for a new buffer) the queue is cleared before the walk.
+__global__ void k_walk_epoch(WalkQueue *wq, int force_clear) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t e = (wq->epoch + 1u) & 0xffffu;
+    uint32_t w = force_clear ? 1u : 0u;
+    if (e == 0u) { e = 1u; w = 1u; }
+    wq->epoch = e;
+    wq->wrapped = w;
+}
+
+// Resets the queue (one root pair (r, r) per tree of the forest) and, for the
+// gravity walk, the per-target list counters.
+__global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, int64_t qcap,
                             int mode, int32_t *m2l_cnt, int32_t *p2p_cnt) {
     const int nc = st->ncells;
+    const uint32_t epoch = wq->epoch;
+    const bool go = nc > 0 && !(st->status & kSkipMask);
+    const int nroots = go ? st->level_count[0] : 0;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+    if (wq->wrapped)
+        for (int64_t i = nroots + gid; i < qcap; i += gstride) queue[i] = 0ull;
     if (mode == 0 && m2l_cnt) {
         const int nl = st->nleaves;
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc || i < nl;
-             i += gridDim.x * blockDim.x) {
+        for (int64_t i = gid; i < nc || i < nl; i += gstride) {
             if (i < nc) m2l_cnt[i] = 0;
             if (i < nl) p2p_cnt[i] = 0;
         }
     }
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int64_t r = gid; r < nroots; r += gstride)
+        __hip_atomic_store(&queue[r], make_item(epoch, (int)r, (int)r), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (gid != 0) return;
     wq->head = 0;
-    wq->epoch = epoch;
     if (mode == 0) {
         st->nm2l = 0; st->np2p = 0; st->m2l_slots = 0; st->p2p_slots = 0; st->visited = 0;
         st->nlong_m2l = 0; st->nlong_p2p = 0;
     } else {
         st->ncand = 0; st->cand_slots = 0;
     }
-    if (nc > 0 && !(st->status & kSkipMask)) {
-        __hip_atomic_store(&queue[0], make_item(epoch, 0, 0), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        wq->tail = 1;
-        wq->processed = 0;
-    } else {
-        wq->tail = 0;
-        wq->processed = 0;
-    }
+    wq->tail = (uint64_t)nroots;
+    wq->processed = 0;
 }
 
 struct WalkArgs {
@@ -88,7 +102,7 @@ struct WalkArgs {
     int64_t m2l_cap, p2p_cap;
     int32_t *nm2l, *np2p;                // exact counts
     int32_t *m2l_slots, *p2p_slots;      // reserved slots
-    uint32_t epoch;
+    uint32_t epoch;                      // read from the queue state at kernel start
     // gravity: per-target lists
     const int32_t *c_entry, *c_nent;
     int32_t *m2l_cnt, *m2l_seg, *p2p_cnt, *p2p_seg;
@@ -256,8 +270,10 @@ __device__ __forceinline__ void append_targets(const Item &it, const WalkArgs &A
 constexpr int kItemsPerLane = 2;
 
 template <int MODE>
-__global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
+__global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
     constexpr int IPL = kItemsPerLane;
+    WalkArgs A = A0;
+    A.epoch = A0.wq->epoch;
     const int lane = threadIdx.x % kWave;
     WalkQueue *wq = A.wq;
     const int ncells = A.st->ncells;
@@ -384,23 +400,13 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A) {
 
 hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post,
                        hipStream_t s) {
-    ws.epoch = (ws.epoch + 1) & 0xffffu;
-    if (ws.epoch == 0) {
-        // tags wrapped: clear the queue so no stale slot can look valid
-        launch_fill_i64((int64_t *)ws.queue, 0, ws.queue_cap, s);
-        ws.epoch = 1;
-    }
-    int gi = 1;
-    if (mode == 0 && ws.m2l_cnt) {
-        const int64_t m = ws.cell_cap > ws.leaf_cap ? ws.cell_cap : ws.leaf_cap;
-        gi = (int)((m + 255) / 256 < 1024 ? (m + 255) / 256 : 1024);
-    }
-    k_walk_init<<<gi, 256, 0, s>>>(ws.st, ws.wq, ws.queue, ws.epoch, mode, ws.m2l_cnt,
-                                   ws.p2p_cnt);
+    k_walk_epoch<<<1, 64, 0, s>>>(ws.wq, ws.clear_queue ? 1 : 0);
+    ws.clear_queue = false;
+    k_walk_init<<<1024, 256, 0, s>>>(ws.st, ws.wq, ws.queue, ws.queue_cap, mode, ws.m2l_cnt,
+                                     ws.p2p_cnt);
     WalkArgs A = {};
     A.st = ws.st; A.wq = ws.wq; A.queue = ws.queue; A.qcap = ws.queue_cap;
     A.ncs = ncs; A.ncc_pre = ncc_pre; A.ncc_post = ncc_post;
-    A.epoch = ws.epoch;
     if (mode == 0) {
         A.cell = ws.wg;
         A.m2l = ws.m2l; A.m2l_cap = ws.m2l_cap; A.nm2l = &ws.st->nm2l;

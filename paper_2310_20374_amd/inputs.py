@@ -17,6 +17,8 @@ Workloads (the paper uses synthetic disks only; no public dataset is involved):
 * ``gas_box``   -- a unit box of equal spheres with Maxwellian velocities, used to
                    exercise the collision test (a closed-form pair count exists).
 * ``clumps``    -- half a disk plus 200 Plummer spheres placed on disk orbits.
+* ``disk_batch`` -- many independent disks (sizes log-uniform, ``batch_sizes``)
+                   concatenated, with the offsets of each disk.
 """
 from __future__ import annotations
 
@@ -224,6 +226,25 @@ def batch_sizes(n_disks: int = 64, seed: int = 0, lo: int = 1000, hi: int = 5000
     """Per-disk sizes, log-uniform in [lo, hi]."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), n_disks))).astype(np.int64)
+
+
+def disk_batch(sizes, seed_base: int = 1000, kind: str = "disk"):
+    """Independent disks concatenated: disk k has sizes[k] moonlets drawn with seed
+    seed_base + k (each with its own total mass and central mass at the origin).
+    Returns (arrays, offsets) with offsets[k] = first moonlet of disk k and
+    offsets[-1] = total.  Empty disks are allowed."""
+    gen = {"disk": disk, "hot_disk": hot_disk}[kind]
+    parts = []
+    for k, nk in enumerate(int(v) for v in sizes):
+        if nk > 0:
+            parts.append(gen(nk, seed=seed_base + k))
+    offsets = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(np.asarray(sizes, dtype=np.int64))
+    if parts:
+        out = {key: np.concatenate([p_[key] for p_ in parts]) for key in FIELDS}
+    else:
+        out = {key: np.zeros(0) for key in FIELDS}
+    return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in out.items()}, offsets
 
 
 def sample_targets(n: int, count: int = 4096, seed: int = 12345) -> np.ndarray:

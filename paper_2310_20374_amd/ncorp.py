@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "ok", -1: "invalid", -2: "capacity", -3: "hip", -4: "unsuppor
                 -5: "nonfinite"}
 
 INFO_FIELDS = ("n", "ncells", "nleaves", "maxlevel", "m2l", "p2p", "visited", "col_cand",
-               "col_tests", "m2l_dir", "p2p_inter", "m2l_maxlist", "p2p_maxlist")
+               "col_tests", "m2l_dir", "p2p_inter", "m2l_maxlist", "p2p_maxlist", "nroots")
 PHASES = ("keys", "sort", "tree", "gclimb", "gwalk", "m2l", "descent", "p2p", "l2p", "collide",
           "integrate")
 EXPORT = {"keys": 0, "perm": 1, "cells": 2, "gcells": 3, "ccells": 4, "multipoles": 5,
@@ -29,7 +29,8 @@ EXPORTED_SYMBOLS = ("ncorp_params_default", "ncorp_create", "ncorp_destroy",
                     "ncorp_workspace_bytes", "ncorp_build_tree", "ncorp_gravity",
                     "ncorp_collide", "ncorp_step", "ncorp_get_status", "ncorp_last_error",
                     "ncorp_tree_info", "ncorp_export_host", "ncorp_set_timing",
-                    "ncorp_phase_times")
+                    "ncorp_phase_times", "ncorp_build_tree_batched", "ncorp_step_batched")
+MAX_DISKS = 65536
 
 
 class Params(C.Structure):
@@ -86,6 +87,11 @@ def lib():
     L.ncorp_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, d, i32, vp, i64, vp, vp,
                              i64, vp]
     L.ncorp_step.restype = i32
+    L.ncorp_build_tree_batched.argtypes = [vp, vp, i32, vp, vp, vp, i64, vp, i64, vp]
+    L.ncorp_build_tree_batched.restype = i32
+    L.ncorp_step_batched.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i64, d, i32,
+                                     vp, i64, vp, vp, i64, vp]
+    L.ncorp_step_batched.restype = i32
     L.ncorp_get_status.argtypes = [vp, C.POINTER(i64)]
     L.ncorp_get_status.restype = i32
     L.ncorp_last_error.argtypes = [vp]
@@ -188,6 +194,24 @@ class Context:
                                      int(n_steps), _ptr(pairs), cap, _ptr(n_pairs_dev),
                                      _ptr(self.ws), self.ws_bytes, _stream(stream)),
                     "ncorp_step")
+
+    def build_tree_batched(self, offsets, x, y, z, stream=None):
+        """offsets: int64 device tensor of n_disks + 1 entries."""
+        self._check(lib().ncorp_build_tree_batched(self.h, _ptr(offsets), offsets.numel() - 1,
+                                                   _ptr(x), _ptr(y), _ptr(z), x.numel(),
+                                                   _ptr(self.ws), self.ws_bytes,
+                                                   _stream(stream)),
+                    "ncorp_build_tree_batched")
+
+    def step_batched(self, offsets, x, y, z, vx, vy, vz, m, R, dt, n_steps, pairs, n_pairs_dev,
+                     stream=None):
+        cap = pairs.shape[0] if pairs is not None else 0
+        self._check(lib().ncorp_step_batched(self.h, _ptr(offsets), offsets.numel() - 1,
+                                             _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy),
+                                             _ptr(vz), _ptr(m), _ptr(R), x.numel(), float(dt),
+                                             int(n_steps), _ptr(pairs), cap, _ptr(n_pairs_dev),
+                                             _ptr(self.ws), self.ws_bytes, _stream(stream)),
+                    "ncorp_step_batched")
 
     def get_status(self):
         req = C.c_int64(0)
