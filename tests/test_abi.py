@@ -66,3 +66,36 @@ def test_workspace_bytes(nc):
     assert b % 256 == 0
     assert nc.workspace_bytes(prm, 1000, 10 ** 6) > a
     assert nc.lib().ncorp_workspace_bytes(C.byref(prm), 0, 0) == -1
+
+
+def test_batched_argument_checks(nc):
+    """The batched entry points reject a missing offset array and a disk count
+    outside 1..NCORP_MAX_DISKS on the host, before any GPU work."""
+    L = nc.lib()
+    h = C.c_void_p()
+    prm = nc.params_default(3)
+    assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.OK
+    dummy = C.c_void_p(256)          # never dereferenced: the checks come first
+    assert L.ncorp_build_tree_batched(h, None, 4, dummy, dummy, dummy, 10, None, 0,
+                                      None) == nc.E_INVALID
+    assert b"disk_offsets" in L.ncorp_last_error(h)
+    for nd in (0, -3, nc.MAX_DISKS + 1):
+        assert L.ncorp_build_tree_batched(h, dummy, nd, dummy, dummy, dummy, 10, None, 0,
+                                          None) == nc.E_INVALID
+        assert b"n_disks" in L.ncorp_last_error(h)
+        assert L.ncorp_step_batched(h, dummy, nd, *([dummy] * 8), 10, 1e-3, 1, None, 0, dummy,
+                                    None, 0, None) == nc.E_INVALID
+    # a valid disk count still needs positions and a workspace
+    assert L.ncorp_build_tree_batched(h, dummy, 2, None, None, None, 10, None, 0,
+                                      None) == nc.E_INVALID
+    assert L.ncorp_build_tree_batched(h, dummy, 2, dummy, dummy, dummy, 10, None, 0,
+                                      None) == nc.E_INVALID
+    assert b"workspace" in L.ncorp_last_error(h)
+    L.ncorp_destroy(h)
+
+
+def test_autotune_cache_key():
+    from paper_2310_20374_amd import autotune
+    assert autotune.cache_key(4, 1, 788736) == "p4-prec1-n2^19"
+    assert autotune.cache_key(6, 0, 1) == "p6-prec0-n2^0"
+    assert autotune.CANDIDATES == tuple(sorted(autotune.CANDIDATES))
