@@ -73,7 +73,8 @@ typedef struct {
     int64_t p2p_capacity;      /* cell pairs treated by direct sums in one walk */
     int64_t queue_capacity;    /* cell pairs visited by one walk */
     /* per-target interaction lists, filled by the gravity walk itself; 0 = automatic
-     * (1024 each), at most 8192 each.  A target with more entries makes the call
+     * (2048 M2L partners per cell, 4096 source cells per leaf: enough for clustered
+     * disks of 4e6 moonlets at the default thresholds), at most 8192 each.  A target with more entries makes the call
      * fail with NCORP_E_CAPACITY, required = the count that would have fitted. */
     int32_t m2l_per_cell;      /* well-separated partner cells kept per cell */
     int32_t p2p_per_leaf;      /* direct-sum source cells kept per leaf */

@@ -56,8 +56,8 @@ constexpr int kListChunk = 256;
 
 // per-target interaction lists: default and largest slot counts (a consumer
 // sorts a whole list in LDS)
-constexpr int kDefaultM2LPerCell = 1024;
-constexpr int kDefaultP2PPerLeaf = 1024;
+constexpr int kDefaultM2LPerCell = 2048;
+constexpr int kDefaultP2PPerLeaf = 4096;
 constexpr int kMaxPerTarget = 8192;
 // lists up to these lengths are sorted in LDS by their consumer; longer ones (the
 // walk records them) by a pre-pass of kSortLongBlocks single-wave blocks

@@ -196,21 +196,22 @@ def clumps(n: int, seed: int = 0, n_clumps: int = 200, scale: float = 0.05,
     cnt[np.argmax(w)] += n_cl - cnt.sum()
     centres = disk(n_clumps, seed=seed + 104729, total_mass=1.0, mu=mu)
     m_cl = rng.lognormal(0.0, 1.0, n_cl)
+    # every mass is rescaled so that the moonlets sum to total_mass; a clump's
+    # internal velocities follow from its members' final mass
+    fac = total_mass / (base["m"].sum() + m_cl.sum())
     xs, ys, zs, vxs, vys, vzs = [], [], [], [], [], []
     off = 0
     for k in range(n_clumps):
         c = int(cnt[k])
         if c == 0:
             continue
-        pos, vel = _plummer(rng, c, scale, mass=m_cl[off:off + c].sum() * total_mass / 2.0,
-                            G=1.0)
+        pos, vel = _plummer(rng, c, scale, mass=m_cl[off:off + c].sum() * fac, G=1.0)
         xs.append(pos[0] + centres["x"][k]); ys.append(pos[1] + centres["y"][k])
         zs.append(pos[2] + centres["z"][k])
         vxs.append(vel[0] + centres["vx"][k]); vys.append(vel[1] + centres["vy"][k])
         vzs.append(vel[2] + centres["vz"][k])
         off += c
-    m_all = np.concatenate([base["m"], m_cl])
-    m_all *= total_mass / m_all.sum()
+    m_all = np.concatenate([base["m"], m_cl]) * fac
     out = {
         "x": np.concatenate([base["x"]] + xs), "y": np.concatenate([base["y"]] + ys),
         "z": np.concatenate([base["z"]] + zs),
