@@ -71,7 +71,7 @@ typedef struct {
     int64_t cell_capacity;     /* octree cells */
     int64_t m2l_capacity;      /* well-separated cell pairs of one walk */
     int64_t p2p_capacity;      /* cell pairs treated by direct sums in one walk */
-    int64_t queue_capacity;    /* cell pairs visited by one walk */
+    int64_t queue_capacity;    /* cell pairs visited by one walk (at most 1e8) */
     /* per-target interaction lists, filled by the gravity walk itself; 0 = automatic
      * (2048 M2L partners per cell, 4096 source cells per leaf: enough for clustered
      * disks of 4e6 moonlets at the default thresholds), at most 8192 each.  A target with more entries makes the call

@@ -111,6 +111,10 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
         p->queue_capacity < 0) {
         std::snprintf(why, len, "capacities must be >= 0"); return false;
     }
+    if (p->queue_capacity > kMaxQueue) {
+        std::snprintf(why, len, "queue_capacity must be at most %lld", (long long)kMaxQueue);
+        return false;
+    }
     if (p->m2l_per_cell < 0 || p->m2l_per_cell > kMaxPerTarget || p->p2p_per_leaf < 0 ||
         p->p2p_per_leaf > kMaxPerTarget) {
         std::snprintf(why, len, "m2l_per_cell and p2p_per_leaf must be in 0..%d", kMaxPerTarget);
@@ -169,6 +173,7 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     int64_t p2p_cap = (prm.p2p_capacity > 0 ? prm.p2p_capacity : 32 * cell_cap + 4096) + slack;
     int64_t q_cap = prm.queue_capacity > 0 ? prm.queue_capacity
                                            : m2l_cap + p2p_cap + 16 * cell_cap + 65536;
+    if (q_cap > kMaxQueue) q_cap = kMaxQueue;
     ws.n_max = n;
     ws.cell_cap = cell_cap;
     ws.m2l_cap = m2l_cap;

@@ -112,42 +112,50 @@ __global__ void k_disk_ids(const int64_t *__restrict__ off, int nd, int64_t n,
     if (blockIdx.x == 0 && threadIdx.x == 0) st->ndisks = nd;
 }
 
-// max |coordinate| per disk: a wave whose 64 moonlets share a disk reduces first
-// and issues one atomic, otherwise every lane issues its own.
+// max |coordinate| per disk.  Every wave scans one contiguous chunk of moonlets in
+// coalesced rounds of 64; each lane keeps a running max for the disk it is in and
+// publishes it (one atomic) only when it enters another disk, and at the end the
+// wave reduces first if all its lanes ended in the same disk.
 __global__ void k_max_abs_seg(const double *__restrict__ x, const double *__restrict__ y,
                               const double *__restrict__ z, int64_t n,
                               const uint16_t *__restrict__ seg,
                               unsigned long long *__restrict__ disk_max, DevState *st) {
     const int lane = threadIdx.x % kWave;
-    const int64_t wbase = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int64_t chunk = ((n + nw - 1) / nw + kWave - 1) / kWave * kWave;
+    const int64_t b0 = w * chunk;
+    const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
     bool bad = false;
-    for (int64_t b = wbase; b < n; b += stride) {
+    int cur = -1;
+    unsigned long long run = 0ull;
+    for (int64_t b = b0; b < b1; b += kWave) {
         const int64_t i = b + lane;
-        const bool valid = i < n;
-        unsigned long long m = 0ull;
-        int d = 0;
-        if (valid) {
-            d = seg[i];
-            double v[3] = {x[i], y[i], z[i]};
+        if (i >= b1) continue;
+        const int d = seg[i];
+        if (d != cur) {
+            if (cur >= 0) atomicMax(&disk_max[cur], run);
+            cur = d;
+            run = 0ull;
+        }
+        double v[3] = {x[i], y[i], z[i]};
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-                double a = fabs(v[k]);
-                if (!(a <= 1.79769313486231570e308)) { bad = true; continue; }
-                unsigned long long u = (unsigned long long)__double_as_longlong(a);
-                m = u > m ? u : m;
-            }
+        for (int k = 0; k < 3; k++) {
+            double a = fabs(v[k]);
+            if (!(a <= 1.79769313486231570e308)) { bad = true; continue; }
+            unsigned long long u = (unsigned long long)__double_as_longlong(a);
+            run = u > run ? u : run;
         }
-        const int d0 = __shfl(d, 0);
-        if (__all(valid && d == d0)) {
-            for (int o = kWave / 2; o > 0; o >>= 1) {
-                unsigned long long t = __shfl_xor(m, o);
-                m = t > m ? t : m;
-            }
-            if (lane == 0) atomicMax(&disk_max[d0], m);
-        } else if (valid) {
-            atomicMax(&disk_max[d], m);
+    }
+    const int c0 = __shfl(cur, 0);
+    if (__all(cur == c0)) {
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            unsigned long long t = __shfl_xor(run, o);
+            run = t > run ? t : run;
         }
+        if (lane == 0 && c0 >= 0) atomicMax(&disk_max[c0], run);
+    } else if (cur >= 0) {
+        atomicMax(&disk_max[cur], run);
     }
     if (__any(bad) && lane == 0) atomicOr(&st->status, (int32_t)ST_NONFINITE);
 }
@@ -256,8 +264,8 @@ hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
         k_disk_ids<<<nd < 4096 ? nd : 4096, 256, 0, s>>>(disk_off, nd, n, ws.seg, ws.disk_max,
                                                          ws.st);
         // also run with a fixed root: it latches non-finite coordinates
-        k_max_abs_seg<<<grid_for(n, 256, 1024), 256, 0, s>>>(x, y, z, n, ws.seg, ws.disk_max,
-                                                             ws.st);
+        k_max_abs_seg<<<grid_for(n, 256, 512), 256, 0, s>>>(x, y, z, n, ws.seg, ws.disk_max,
+                                                            ws.st);
         const int64_t cover = n > nd ? n : nd;
         k_keys<<<grid_for(cover, 256), 256, 0, s>>>(x, y, z, n, root_half_width, ws.disk_max,
                                                     ws.seg, nd, ws.disk_L, ws.st, kout, vout);

@@ -53,6 +53,10 @@ constexpr int kWalkGridGravity = 256;
 constexpr int kWalkGridCollide = 128;
 constexpr int kWalkWaves = kWalkGridGravity * kWalkBlock / kWave;
 constexpr int kListChunk = 256;
+// the walk's tail shares a 64-bit word with the processed count (32 bits each); an
+// item pushes at most 36 children, so a queue of this many slots keeps the tail
+// below 2^32 even when it overflows
+constexpr int64_t kMaxQueue = 100000000;
 
 // per-target interaction lists: default and largest slot counts (a consumer
 // sorts a whole list in LDS)
@@ -105,10 +109,10 @@ struct DevState {
 struct WalkQueue {
     uint64_t head;             // next slot to claim
     uint64_t pad0[15];
-    uint64_t tail;             // next slot to reserve
+    uint64_t tp;               // next slot to reserve (high 32 bits) and items
+                               // processed (low 32 bits), updated by one atomic
     uint64_t pad1[15];
-    uint64_t processed;        // items processed (children reserved first)
-    uint64_t pad2[15];
+    uint64_t pad2[16];
     uint32_t epoch;            // tag of valid items in this walk (advanced on the device)
     uint32_t wrapped;          // the tag wrapped: the queue must be cleared first
     uint32_t pad3[30];

@@ -6,12 +6,12 @@
 // Alg. 2 does (self pair / brute force before the opening test / well separated /
 // brute force after it / split the cell with the larger critical radius) and
 // pushes the child pairs with one wave-aggregated atomic on the tail.  Termination:
-// a wave counts its processed items into `processed` only after the tail
-// reservation of their children has returned, so processed <= tail at every
-// moment, with equality only when no item is waiting or being worked on.  A wave
-// that finds no work reads processed, then tail; if they are equal the walk is
-// over (tail can only have grown from an item not yet counted as processed, and
-// there is none).  A wave that polls for too long without progress latches
+// the tail and the count of processed items share one 64-bit word, and a wave
+// reserves its items' children and counts those items as processed in the same
+// atomic, so processed <= tail at every moment, with equality only when no item
+// is waiting or being worked on.  A wave that finds no work reads the word; if
+// the two halves are equal the walk is over (the tail can only grow from an item
+// not yet counted as processed, and there is none).  A wave that polls for too long without progress latches
 // ST_WALK_STALL and leaves, so the kernel always ends.
 //
 // Pairs classified by the walk do not depend on the order of processing, so the
@@ -87,8 +87,7 @@ __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, int64_
     } else {
         st->ncand = 0; st->cand_slots = 0;
     }
-    wq->tail = (uint64_t)nroots;
-    wq->processed = 0;
+    wq->tp = (uint64_t)nroots << 32;
 }
 
 struct WalkArgs {
@@ -110,12 +109,13 @@ struct WalkArgs {
     int m2l_stride, p2p_stride;
 };
 
-// Appends v to target t's list (slot order is arbitrary).
-// The append that makes a list longer than `lds` (what its consumer sorts in LDS)
-// records the target in `longs`, for the pre-pass that sorts such lists.
-__device__ __forceinline__ void append(int32_t *cnt, int32_t *seg, int stride, int t, int v,
-                                       int lds, int32_t *nlong, int32_t *longs, DevState *st) {
-    const int k = atomicAdd(&cnt[t], 1);
+// Stores v at slot k of target t's list (slot order is arbitrary); k came from
+// the target's counter.  The append that makes a list longer than `lds` (what its
+// consumer sorts in LDS) records the target in `longs`, for the pre-pass that sorts
+// such lists.
+__device__ __forceinline__ void store_slot(int k, int32_t *seg, int stride, int t, int v,
+                                           int lds, int32_t *nlong, int32_t *longs,
+                                           DevState *st) {
     if (k == lds) longs[atomicAdd(nlong, 1)] = t;
     if (k < stride) {
         seg[(int64_t)t * stride + k] = v;
@@ -243,24 +243,68 @@ __device__ __forceinline__ void push_children(const Item &it, uint64_t my, const
     }
 }
 
-// The per-target lists of the gravity walk (see the file header).
-__device__ __forceinline__ void append_targets(const Item &it, const WalkArgs &A) {
-    if (it.kind == 1) {
-        append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, it.a, it.b, kM2LListLDS, &A.st->nlong_m2l,
-               A.long_m2l, A.st);
-        append(A.m2l_cnt, A.m2l_seg, A.m2l_stride, it.b, it.a, kM2LListLDS, &A.st->nlong_m2l,
-               A.long_m2l, A.st);
-    } else if (it.kind == 2) {
-        int e0 = A.c_entry[it.a], e1 = e0 + A.c_nent[it.a];
-        for (int e = e0; e < e1; e++)
-            append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, it.b, kP2PListLDS, &A.st->nlong_p2p,
-                   A.long_p2p, A.st);
-        if (it.a != it.b) {
-            e0 = A.c_entry[it.b];
-            e1 = e0 + A.c_nent[it.b];
-            for (int e = e0; e < e1; e++)
-                append(A.p2p_cnt, A.p2p_seg, A.p2p_stride, e, it.a, kP2PListLDS,
-                       &A.st->nlong_p2p, A.long_p2p, A.st);
+// The per-target lists of the gravity walk (see the file header).  A lane's items
+// make a stream of appends -- a well-separated pair one to each cell's M2L list, a
+// direct-sum pair one to the list of every leaf below either cell -- whose counter
+// atomics are issued kAppendBatch at a time, so their latencies overlap.
+constexpr int kAppendBatch = 4;
+
+template <int IPL>
+__device__ __forceinline__ void append_targets(const Item (&it)[IPL], const WalkArgs &A) {
+    int nreq[IPL], ea[IPL], nla[IPL], eb[IPL];
+    int total = 0;
+#pragma unroll
+    for (int k = 0; k < IPL; k++) {
+        ea[k] = eb[k] = nla[k] = 0;
+        int nlb = 0;
+        if (it[k].kind == 2) {
+            ea[k] = A.c_entry[it[k].a];
+            nla[k] = A.c_nent[it[k].a];
+            if (it[k].a != it[k].b) {
+                eb[k] = A.c_entry[it[k].b];
+                nlb = A.c_nent[it[k].b];
+            }
+        }
+        nreq[k] = it[k].kind == 1 ? 2 : (it[k].kind == 2 ? nla[k] + nlb : 0);
+        total += nreq[k];
+    }
+    for (int r0 = 0; r0 < total; r0 += kAppendBatch) {
+        int slot[kAppendBatch], tgt[kAppendBatch], val[kAppendBatch];
+        bool p2p[kAppendBatch];
+#pragma unroll
+        for (int q = 0; q < kAppendBatch; q++) {
+            int r = r0 + q, k = 0;
+#pragma unroll
+            for (int m = 0; m + 1 < IPL; m++)
+                if (k == m && r >= nreq[m]) { r -= nreq[m]; k = m + 1; }
+            int t = 0, v = 0;
+            bool isp = false;
+#pragma unroll
+            for (int m = 0; m < IPL; m++) {
+                if (m != k) continue;
+                if (it[m].kind == 1) {
+                    t = r == 0 ? it[m].a : it[m].b;
+                    v = r == 0 ? it[m].b : it[m].a;
+                } else {
+                    isp = true;
+                    t = r < nla[m] ? ea[m] + r : eb[m] + (r - nla[m]);
+                    v = r < nla[m] ? it[m].b : it[m].a;
+                }
+            }
+            tgt[q] = t;
+            val[q] = v;
+            p2p[q] = isp;
+            slot[q] = r0 + q < total ? atomicAdd(isp ? &A.p2p_cnt[t] : &A.m2l_cnt[t], 1) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < kAppendBatch; q++) {
+            if (r0 + q >= total) continue;
+            if (p2p[q])
+                store_slot(slot[q], A.p2p_seg, A.p2p_stride, tgt[q], val[q], kP2PListLDS,
+                           &A.st->nlong_p2p, A.long_p2p, A.st);
+            else
+                store_slot(slot[q], A.m2l_seg, A.m2l_stride, tgt[q], val[q], kM2LListLDS,
+                           &A.st->nlong_m2l, A.long_m2l, A.st);
         }
     }
 }
@@ -313,12 +357,10 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
                 // been processed (slots beyond the queue were never written)
                 int done = 0;
                 if (lane == 0) {
-                    const uint64_t pr = __hip_atomic_load(&wq->processed, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                    // the tail is read only after `processed` has returned: its
-                    // address depends on that value (pr >> 63 is always 0)
-                    uint64_t t = __hip_atomic_load(&wq->tail + (pr >> 63), __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t v = __hip_atomic_load(&wq->tp, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t pr = v & 0xffffffffull;
+                    uint64_t t = v >> 32;
                     if (t > (uint64_t)A.qcap) t = (uint64_t)A.qcap;
                     done = pr >= t;
                 }
@@ -340,13 +382,19 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
                 it[k] = classify<MODE>(valid[k], item[k], A, ncells);
                 npush += it[k].npush;
             }
-            // ---------------- push children (one reservation per wave)
+            int nproc = 0;
+#pragma unroll
+            for (int k = 0; k < IPL; k++) nproc += __popcll(__ballot(valid[k]));
+            // ---------------- push children and retire this round's items (one
+            // atomic per wave: tail += children, processed += items)
             int tot_push;
             const int off = wave_excl_sum(npush, lane, tot_push);
             if (tot_push > 0) {
                 uint64_t pbase = 0;
                 if (lane == 0)
-                    pbase = atomicAdd((unsigned long long *)&wq->tail, (unsigned long long)tot_push);
+                    pbase = atomicAdd((unsigned long long *)&wq->tp,
+                                      ((unsigned long long)tot_push << 32) +
+                                          (unsigned long long)nproc) >> 32;
                 pbase = __shfl(pbase, 0);
                 uint64_t my = pbase + (uint64_t)off;
 #pragma unroll
@@ -359,9 +407,11 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
                     atomicMax((unsigned long long *)&A.st->required,
                               (unsigned long long)(pbase + tot_push));
                 }
+            } else if (lane == 0) {
+                __hip_atomic_fetch_add(&wq->tp, (uint64_t)nproc, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
             // ---------------- interaction lists
-            int nproc = 0;
 #pragma unroll
             for (int k = 0; k < IPL; k++) {
                 if (MODE == 0)
@@ -369,16 +419,8 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
                          A.m2l_cap, A.st, ST_CAP_M2L);
                 emit(it[k].kind == 2, it[k].a, it[k].b, lane, cp, A.p2p_slots, A.p2p, A.p2p_cap,
                      A.st, ST_CAP_P2P);
-                if (MODE == 0 && A.m2l_cnt) append_targets(it[k], A);
-                nproc += __popcll(__ballot(valid[k]));
             }
-            // ---------------- retire.  The children's tail reservation has returned
-            // (its value addressed their stores); the compiler barrier keeps this
-            // atomic after those stores, so it is performed after the reservation.
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            if (lane == 0)
-                __hip_atomic_fetch_add(&wq->processed, (uint64_t)nproc, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (MODE == 0 && A.m2l_cnt) append_targets<IPL>(it, A);
             visited += nproc;
             any_pending = false;
 #pragma unroll
