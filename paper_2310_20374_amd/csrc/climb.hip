@@ -350,7 +350,8 @@ __global__ void k_rcrit(const DevState *__restrict__ st, const double *__restric
                         double theta_min, int theta_mode, const int32_t *__restrict__ c_count,
                         const int32_t *__restrict__ c_child, const int32_t *__restrict__ c_nchild,
                         WCell *__restrict__ wg, const uint16_t *__restrict__ seg,
-                        const int32_t *__restrict__ c_first, const int32_t *__restrict__ disk_root) {
+                        const int32_t *__restrict__ c_first, const int32_t *__restrict__ disk_root,
+                        const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent) {
     const int nc = st->ncells;
     if (nc <= 0 || (st->status & kSkipMask)) return;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
@@ -364,7 +365,8 @@ __global__ void k_rcrit(const DevState *__restrict__ st, const double *__restric
         gcell[c] = g;
         WCell w;
         w.x = g.x; w.y = g.y; w.z = g.z; w.rcrit = rc;
-        w.count = c_count[c]; w.child = c_child[c]; w.nchild = c_nchild[c]; w.pad = 0;
+        w.count = c_count[c]; w.child = c_child[c]; w.nchild = c_nchild[c];
+        w.entry = c_entry[c]; w.nent = c_nent[c]; w.pad[0] = w.pad[1] = w.pad[2] = 0;
         wg[c] = w;
     }
 }
@@ -372,14 +374,17 @@ __global__ void k_rcrit(const DevState *__restrict__ st, const double *__restric
 __global__ void k_pack_collision(const DevState *__restrict__ st, const double4 *__restrict__ ccell,
                                  const int32_t *__restrict__ c_count,
                                  const int32_t *__restrict__ c_child,
-                                 const int32_t *__restrict__ c_nchild, WCell *__restrict__ wc) {
+                                 const int32_t *__restrict__ c_nchild, WCell *__restrict__ wc,
+                                 const int32_t *__restrict__ c_entry,
+                                 const int32_t *__restrict__ c_nent) {
     const int nc = st->ncells;
     if (st->status & kSkipMask) return;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
         const double4 g = ccell[c];
         WCell w;
         w.x = g.x; w.y = g.y; w.z = g.z; w.rcrit = g.w;
-        w.count = c_count[c]; w.child = c_child[c]; w.nchild = c_nchild[c]; w.pad = 0;
+        w.count = c_count[c]; w.child = c_child[c]; w.nchild = c_nchild[c];
+        w.entry = c_entry[c]; w.nent = c_nent[c]; w.pad[0] = w.pad[1] = w.pad[2] = 0;
         wc[c] = w;
     }
 }
@@ -422,7 +427,8 @@ hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_para
                                                         ws.c_theta, prm.theta_min, prm.theta_mode,
                                                         ws.c_count, ws.c_child, ws.c_nchild, ws.wg,
                                                         ws.ndisks > 1 ? ws.seg : nullptr,
-                                                        ws.c_first, ws.disk_root);
+                                                        ws.c_first, ws.disk_root, ws.c_entry,
+                                                        ws.c_nent);
     return hipGetLastError();
 }
 
@@ -535,7 +541,8 @@ hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hip
         ws.c_first, ws.c_count, ws.c_child, ws.c_nchild, ws.c_parent, ws.c_arrive, ws.ccell,
         ws.c_crmax, ws.ndisks > 1 ? ws.seg : nullptr, ws.disk_L);
     k_pack_collision<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.ccell, ws.c_count,
-                                                                 ws.c_child, ws.c_nchild, ws.wc);
+                                                                 ws.c_child, ws.c_nchild, ws.wc,
+                                                                 ws.c_entry, ws.c_nent);
     return hipGetLastError();
 }
 

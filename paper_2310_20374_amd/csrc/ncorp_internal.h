@@ -118,11 +118,12 @@ struct WalkQueue {
     uint32_t pad3[30];
 };
 
-// What the walk reads of a cell, packed: centre, critical radius, moonlet count,
-// first child and number of children (0 for a leaf).
-struct alignas(16) WCell {
+// What the walk reads of a cell, one 64-byte line: centre, critical radius,
+// moonlet count, first child, number of children (0 for a leaf), first leaf and
+// number of leaves below it.
+struct alignas(64) WCell {
     double x, y, z, rcrit;
-    int32_t count, child, nchild, pad;
+    int32_t count, child, nchild, entry, nent, pad[3];
 };
 
 // Waves of a multi-wave block that work independently synchronise their own LDS

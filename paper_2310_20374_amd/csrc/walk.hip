@@ -103,7 +103,6 @@ struct WalkArgs {
     int32_t *m2l_slots, *p2p_slots;      // reserved slots
     uint32_t epoch;                      // read from the queue state at kernel start
     // gravity: per-target lists
-    const int32_t *c_entry, *c_nent;
     int32_t *m2l_cnt, *m2l_seg, *p2p_cnt, *p2p_seg;
     int32_t *long_m2l, *long_p2p;        // targets whose list outgrew the LDS sort
     int m2l_stride, p2p_stride;
@@ -176,12 +175,13 @@ struct Item {
     int split;                 // children to push: 1 self pair, 2 split A, 3 split B
     int npush;
     int a, b, na, nb, ca, cb;  // cells, their child counts and first children
+    int ea, la, eb, lb;        // first leaf and number of leaves below a and b
 };
 
 template <int MODE>
 __device__ __forceinline__ Item classify(bool valid, uint64_t item, const WalkArgs &A,
                                          int ncells) {
-    Item it = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    Item it = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (!valid) return it;
     int a = (int)((item >> 24) & 0xffffffu);
     int b = (int)(item & 0xffffffu);
@@ -194,6 +194,8 @@ __device__ __forceinline__ Item classify(bool valid, uint64_t item, const WalkAr
     const WCell wa = A.cell[a];
     it.na = wa.nchild;
     it.ca = wa.child;
+    it.ea = wa.entry;
+    it.la = wa.nent;
     if (a == b) {
         if (wa.count <= A.ncs || it.na == 0) it.kind = 2;
         else { it.split = 1; it.npush = it.na * (it.na + 1) / 2; }
@@ -202,6 +204,8 @@ __device__ __forceinline__ Item classify(bool valid, uint64_t item, const WalkAr
     const WCell wb = A.cell[b];
     it.nb = wb.nchild;
     it.cb = wb.child;
+    it.eb = wb.entry;
+    it.lb = wb.nent;
     const int64_t prod = (int64_t)wa.count * (int64_t)wb.count;
     if (prod < (int64_t)A.ncc_pre) {
         it.kind = 2;
@@ -258,11 +262,11 @@ __device__ __forceinline__ void append_targets(const Item (&it)[IPL], const Walk
         ea[k] = eb[k] = nla[k] = 0;
         int nlb = 0;
         if (it[k].kind == 2) {
-            ea[k] = A.c_entry[it[k].a];
-            nla[k] = A.c_nent[it[k].a];
+            ea[k] = it[k].ea;
+            nla[k] = it[k].la;
             if (it[k].a != it[k].b) {
-                eb[k] = A.c_entry[it[k].b];
-                nlb = A.c_nent[it[k].b];
+                eb[k] = it[k].eb;
+                nlb = it[k].lb;
             }
         }
         nreq[k] = it[k].kind == 1 ? 2 : (it[k].kind == 2 ? nla[k] + nlb : 0);
@@ -454,7 +458,6 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
         A.m2l = ws.m2l; A.m2l_cap = ws.m2l_cap; A.nm2l = &ws.st->nm2l;
         A.p2p = ws.p2p; A.p2p_cap = ws.p2p_cap; A.np2p = &ws.st->np2p;
         A.m2l_slots = &ws.st->m2l_slots; A.p2p_slots = &ws.st->p2p_slots;
-        A.c_entry = ws.c_entry; A.c_nent = ws.c_nent;
         A.m2l_cnt = ws.m2l_cnt; A.m2l_seg = ws.m2l_seg; A.m2l_stride = ws.m2l_stride;
         A.p2p_cnt = ws.p2p_cnt; A.p2p_seg = ws.p2p_seg; A.p2p_stride = ws.p2p_stride;
         A.long_m2l = ws.long_m2l; A.long_p2p = ws.long_p2p;
