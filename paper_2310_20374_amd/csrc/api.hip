@@ -209,6 +209,7 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.vys = (double *)take(8 * n);
     ws.vzs = (double *)take(8 * n);
     ws.rads = (double *)take(8 * n);
+    ws.pcol = (double4 *)take(32 * n);
     ws.acc = (double *)take(3 * 8 * n);
     ws.acc_s = (double *)take(3 * 8 * n);
     ws.ent_start = (int32_t *)take(4 * n);
@@ -416,10 +417,7 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
     Workspace &ws = c->ws;
     const int64_t n = c->n;
     PhaseTimer t(c, NCORP_PHASE_COLLIDE, s);
-    HIPCHK(c, launch_gather(ws, vx, ws.vxs, n, s));
-    HIPCHK(c, launch_gather(ws, vy, ws.vys, n, s));
-    HIPCHK(c, launch_gather(ws, vz, ws.vzs, n, s));
-    HIPCHK(c, launch_gather(ws, R, ws.rads, n, s));
+    HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
     HIPCHK(c, launch_collision_climb(ws, n, dt, s));
     HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col, c->prm.ncc_post_col, s));
     HIPCHK(c, launch_collide_pairs(ws, n, dt, s));

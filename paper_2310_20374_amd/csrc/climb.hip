@@ -445,7 +445,8 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
                   const int32_t *__restrict__ c_child, const int32_t *__restrict__ c_nchild,
                   const int32_t *__restrict__ c_parent, int32_t *c_arrive, double4 *ccell,
                   double *c_crmax,
-                  const uint16_t *__restrict__ seg, const double *__restrict__ disk_L) {
+                  const uint16_t *__restrict__ seg, const double *__restrict__ disk_L,
+                  double4 *__restrict__ pcol) {
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     const double L = st->L;
@@ -476,6 +477,7 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
                     const double v = sqrt(vxs[k] * vxs[k] + vys[k] * vys[k] + vzs[k] * vzs[k]);
                     const double ee = (rads[k] + dt * v) - 0.0;
                     if (ee > ex) ex = ee;
+                    pcol[k] = make_double4(xs[k], ys[k], zs[k], ee);
                 }
             }
             rm = wave_max(rm);
@@ -539,7 +541,7 @@ hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hip
     k_collision_climb<<<g, kWave, 0, s>>>(
         ws.st, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, dt, ws.ent_cell, ws.c_level,
         ws.c_first, ws.c_count, ws.c_child, ws.c_nchild, ws.c_parent, ws.c_arrive, ws.ccell,
-        ws.c_crmax, ws.ndisks > 1 ? ws.seg : nullptr, ws.disk_L);
+        ws.c_crmax, ws.ndisks > 1 ? ws.seg : nullptr, ws.disk_L, ws.pcol);
     k_pack_collision<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.ccell, ws.c_count,
                                                                  ws.c_child, ws.c_nchild, ws.wc,
                                                                  ws.c_entry, ws.c_nent);

@@ -46,34 +46,37 @@ struct PState {
 // each of its moonlets from its centre); the relative margin 1e-9 dwarfs the
 // rounding of either side, so no pair the exact test accepts is dropped.  The
 // survivors are compacted into out[] in moonlet order; returns their number, or
-// -1 if more than 64 survive.
-__device__ __forceinline__ int cull_cell(int f, int n, double4 sph, const double *__restrict__ xs,
-                                         const double *__restrict__ ys,
-                                         const double *__restrict__ zs,
+// -1 if more than `limit` survive.
+__device__ __forceinline__ int cull_cell(int f, int n, double4 sph,
+                                         const double4 *__restrict__ pcol,
                                          const double *__restrict__ vxs,
                                          const double *__restrict__ vys,
                                          const double *__restrict__ vzs,
                                          const double *__restrict__ rads,
-                                         const uint32_t *__restrict__ perm, double dt,
-                                         PState *out) {
+                                         const uint32_t *__restrict__ perm, PState *out,
+                                         int limit) {
     const int lane = threadIdx.x;
     int kept = 0;
     for (int c0 = 0; c0 < n; c0 += kWave) {
         bool keep = false;
         PState ps;
+        int k = 0;
         if (c0 + lane < n) {
-            const int k = f + c0 + lane;
-            ps.x = xs[k]; ps.y = ys[k]; ps.z = zs[k];
-            ps.vx = vxs[k]; ps.vy = vys[k]; ps.vz = vzs[k]; ps.R = rads[k];
-            ps.id = perm[k];
-            const double v = sqrt(ps.vx * ps.vx + ps.vy * ps.vy + ps.vz * ps.vz);
-            const double reach = (ps.R + dt * v) + sph.w;
+            k = f + c0 + lane;
+            // position and R + dt |v|, as the collision climb stored them
+            const double4 p = pcol[k];
+            ps.x = p.x; ps.y = p.y; ps.z = p.z;
+            const double reach = p.w + sph.w;
             const double dx = ps.x - sph.x, dy = ps.y - sph.y, dz = ps.z - sph.z;
             keep = dx * dx + dy * dy + dz * dz <= reach * reach * (1.0 + 1e-9);
         }
+        if (keep) {
+            ps.vx = vxs[k]; ps.vy = vys[k]; ps.vz = vzs[k]; ps.R = rads[k];
+            ps.id = perm[k];
+        }
         const uint64_t m = __ballot(keep);
         const int nk = __popcll(m);
-        if (kept + nk > kWave) return -1;
+        if (kept + nk > limit) return -1;
         const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
         if (keep) out[kept + __popcll(m & lt)] = ps;
         kept += nk;
@@ -133,7 +136,9 @@ __device__ __forceinline__ void test_cell_pair(
     }
 }
 
-constexpr int kCandRound = 4;
+// candidate slots a wave reads at a time; the cell ranges and spheres of both
+// sides of all of them are loaded in one go
+constexpr int kCandRound = 8;
 
 __global__ void __launch_bounds__(64)
 k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
@@ -142,36 +147,84 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
           const double *__restrict__ ys, const double *__restrict__ zs,
           const double *__restrict__ vxs, const double *__restrict__ vys,
           const double *__restrict__ vzs, const double *__restrict__ rads,
-          const uint32_t *__restrict__ perm, double dt, int64_t *out, int64_t cap) {
-    __shared__ PState sb[64], sa[64];
+          const uint32_t *__restrict__ perm, const double4 *__restrict__ pcol, double dt,
+          int64_t *out, int64_t cap) {
+    __shared__ PState sp[kWave];    // survivors of both sides (or a staged tile of B)
     if (st->status & kSkipMask) return;
     int nc = st->cand_slots;                 // candidate slots, gaps included
     if (nc > cand_cap) nc = (int)cand_cap;
     const int lane = threadIdx.x;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     unsigned long long tests = 0;
-    // kCandRound candidate slots per round, read at once; gaps left by the walk
-    // are skipped
     for (int q0 = blockIdx.x * kCandRound; q0 < nc; q0 += gridDim.x * kCandRound) {
-        int2 c16 = make_int2(-1, -1);
-        if (lane < kCandRound && q0 + lane < nc) c16 = cand[q0 + lane];
-        uint64_t live = __ballot(c16.x >= 0);
+        int2 cq = make_int2(-1, -1);
+        if (lane < kCandRound && q0 + lane < nc) cq = cand[q0 + lane];
+        // lane l < R: side A of candidate l (with B's sphere, for its cull); lane R + l:
+        // side B (with A's sphere)
+        const int src = lane < kCandRound ? lane : lane - kCandRound;
+        const int qa = __shfl(cq.x, src & (kWave - 1)), qb = __shfl(cq.y, src & (kWave - 1));
+        const bool side = lane < 2 * kCandRound && qa >= 0;
+        const int mine = lane < kCandRound ? qa : qb, other = lane < kCandRound ? qb : qa;
+        int cf = 0, cn = 0;
+        double4 sph = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (side) {
+            cf = c_first[mine];
+            cn = c_count[mine];
+            sph = ccell[other];
+        }
+        uint64_t live = __ballot(lane < kCandRound && cq.x >= 0);   // gaps are skipped
         while (live) {
             const int l = __ffsll((unsigned long long)live) - 1;
             live &= live - 1;
-            const int2 pr = make_int2(__shfl(c16.x, l), __shfl(c16.y, l));
+            const int2 pr = make_int2(__shfl(cq.x, l), __shfl(cq.y, l));
             if (pr.x != pr.y) {
                 // distinct cells: keep only moonlets that can reach the other cell
+                const int lb = kCandRound + l;
+                const int fa = __shfl(cf, l), na = __shfl(cn, l);
+                const int fb = __shfl(cf, lb), nb = __shfl(cn, lb);
+                int ka = -1, kb = -1;
                 __syncthreads();
-                const int na = cull_cell(c_first[pr.x], c_count[pr.x], ccell[pr.y], xs, ys, zs,
-                                         vxs, vys, vzs, rads, perm, dt, sa);
-                const int nb = na < 0 ? -1
-                                      : cull_cell(c_first[pr.y], c_count[pr.y], ccell[pr.x], xs,
-                                                  ys, zs, vxs, vys, vzs, rads, perm, dt, sb);
+                if (na + nb <= kWave) {
+                    // both sides in one round: lanes [0, na) hold A, [na, na + nb) hold B
+                    const bool inA = lane < na, inB = !inA && lane < na + nb;
+                    const int sl = inA ? l : lb;
+                    const double4 s4 = make_double4(__shfl(sph.x, sl), __shfl(sph.y, sl),
+                                                    __shfl(sph.z, sl), __shfl(sph.w, sl));
+                    bool keep = false;
+                    int k = 0;
+                    double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+                    if (inA || inB) {
+                        k = inA ? fa + lane : fb + (lane - na);
+                        p = pcol[k];
+                        const double reach = p.w + s4.w;
+                        const double dx = p.x - s4.x, dy = p.y - s4.y, dz = p.z - s4.z;
+                        keep = dx * dx + dy * dy + dz * dz <= reach * reach * (1.0 + 1e-9);
+                    }
+                    const uint64_t mA = __ballot(keep && inA), mB = __ballot(keep && inB);
+                    ka = __popcll(mA);
+                    kb = __popcll(mB);
+                    if (keep) {
+                        PState ps;
+                        ps.x = p.x; ps.y = p.y; ps.z = p.z;
+                        ps.vx = vxs[k]; ps.vy = vys[k]; ps.vz = vzs[k]; ps.R = rads[k];
+                        ps.id = perm[k];
+                        sp[inA ? __popcll(mA & lt) : ka + __popcll(mB & lt)] = ps;
+                    }
+                } else {
+                    const double4 sA = make_double4(__shfl(sph.x, l), __shfl(sph.y, l),
+                                                    __shfl(sph.z, l), __shfl(sph.w, l));
+                    const double4 sB = make_double4(__shfl(sph.x, lb), __shfl(sph.y, lb),
+                                                    __shfl(sph.z, lb), __shfl(sph.w, lb));
+                    ka = cull_cell(fa, na, sA, pcol, vxs, vys, vzs, rads, perm, sp, kWave);
+                    kb = ka < 0 ? -1
+                                : cull_cell(fb, nb, sB, pcol, vxs, vys, vzs, rads, perm, sp + ka,
+                                            kWave - ka);
+                }
                 __syncthreads();
-                if (na >= 0 && nb >= 0) {
-                    const int tot = na * nb;
+                if (ka >= 0 && kb >= 0) {
+                    const int tot = ka * kb;
                     for (int t = lane; t < tot; t += kWave) {
-                        const PState &p = sa[t / nb], &o = sb[t % nb];
+                        const PState &p = sp[t / kb], &o = sp[ka + t % kb];
                         tests++;
                         if (pair_test(p.x, p.y, p.z, p.vx, p.vy, p.vz, p.R, o.x, o.y, o.z, o.vx,
                                       o.vy, o.vz, o.R, dt))
@@ -180,7 +233,7 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
                     continue;
                 }
             }
-            test_cell_pair(pr, sb, c_first, c_count, xs, ys, zs, vxs, vys, vzs, rads, perm, dt,
+            test_cell_pair(pr, sp, c_first, c_count, xs, ys, zs, vxs, vys, vzs, rads, perm, dt,
                            out, cap, st, tests);
         }
     }
@@ -255,7 +308,7 @@ hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipSt
     k_collide_init<<<1, 64, 0, s>>>(ws.st);
     k_collide<<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count, ws.ccell,
                                    ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, ws.idx,
-                                   dt, ws.pairs_tmp, ws.pair_cap);
+                                   ws.pcol, dt, ws.pairs_tmp, ws.pair_cap);
     return hipGetLastError();
 }
 

@@ -484,6 +484,28 @@ hipError_t launch_gather_scaled(const Workspace &ws, const double *src, double s
     return hipGetLastError();
 }
 
+__global__ void k_gather4(const double *__restrict__ a, const double *__restrict__ b,
+                          const double *__restrict__ c, const double *__restrict__ d,
+                          const uint32_t *__restrict__ idx, int64_t n, double *__restrict__ as,
+                          double *__restrict__ bs, double *__restrict__ cs,
+                          double *__restrict__ ds) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t j = idx[i];
+        as[i] = a[j];
+        bs[i] = b[j];
+        cs[i] = c[j];
+        ds[i] = d[j];
+    }
+}
+
+hipError_t launch_gather_vr(const Workspace &ws, const double *vx, const double *vy,
+                            const double *vz, const double *R, int64_t n, hipStream_t s) {
+    k_gather4<<<grid_for(n, 256), 256, 0, s>>>(vx, vy, vz, R, ws.idx, n, ws.vxs, ws.vys, ws.vzs,
+                                               ws.rads);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather(const Workspace &ws, const double *src, double *dst, int64_t n,
                          hipStream_t s) {
     k_gather1<<<grid_for(n, 256), 256, 0, s>>>(src, ws.idx, n, dst);

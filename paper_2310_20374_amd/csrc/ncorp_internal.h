@@ -172,6 +172,7 @@ struct Workspace {
     uint32_t *code = nullptr;                         // tree-build per-moonlet code
     double *xs = nullptr, *ys = nullptr, *zs = nullptr, *mus = nullptr;
     double *vxs = nullptr, *vys = nullptr, *vzs = nullptr, *rads = nullptr;
+    double4 *pcol = nullptr;                          // x, y, z, R + dt |v| (collisions)
     double *acc = nullptr;                            // 3 x n, input order (step)
     double *acc_s = nullptr;                          // 3 x n, tree order (direct sums)
     // leaves in moonlet order ("entries")
@@ -242,6 +243,9 @@ hipError_t launch_gather_pos(const Workspace &ws, const double *x, const double 
                              const double *z, int64_t n, hipStream_t s);
 hipError_t launch_gather(const Workspace &ws, const double *src, double *dst, int64_t n,
                          hipStream_t s);
+// velocities and radii into tree order, one pass
+hipError_t launch_gather_vr(const Workspace &ws, const double *vx, const double *vy,
+                            const double *vz, const double *R, int64_t n, hipStream_t s);
 hipError_t launch_build_tree(const Workspace &ws, int64_t n, int leaf_size, hipStream_t s);
 
 hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_params &prm,
