@@ -165,9 +165,15 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
     constexpr int NM = n_mult(P);
     constexpr int NP = P > 1 ? P : 1;               // powers 0..P-1
     constexpr int NMS = NM > 0 ? NM : 1;
-    __shared__ double pw[kPowChunk][3][NP];         // scaled powers per moonlet / child
-    __shared__ double smu[kPowChunk];               // moonlet masses
-    __shared__ double cm[8][NMS];                   // children's moments
+    // LDS, reused between the two phases: the leaf (P2M) holds scaled powers and
+    // masses of kPowChunk moonlets, a parent (M2M) the powers of its <= 8 children's
+    // offsets and their moments (placed after those 8 entries)
+    constexpr int kLeafDbl = kPowChunk * 3 * NP + kPowChunk;
+    constexpr int kParentDbl = 8 * 3 * NP + 8 * NMS;
+    __shared__ double buf[kLeafDbl > kParentDbl ? kLeafDbl : kParentDbl];
+    double (*pw)[3][NP] = reinterpret_cast<double (*)[3][NP]>(buf);   // [moonlet/child][axis][k]
+    double *smu = buf + kPowChunk * 3 * NP;                           // leaf: moonlet masses
+    double (*cm)[NMS] = reinterpret_cast<double (*)[NMS]>(buf + 8 * 3 * NP);  // parent
     __shared__ uint16_t sterm[ShiftTerms<P>::NT];   // shift terms (from constant memory)
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
