@@ -97,11 +97,25 @@ __device__ __forceinline__ void m2l_contract(const T *D, const T *__restrict__ m
 }
 
 // one pass over a target's sources for the output orders MLO..MHI
+// FP64 at high order splits the output orders over passes (D is recomputed per
+// pass) so that the accumulators and D stay in registers.
+template <int P, typename T> struct M2LSplit { static constexpr int K1 = P, K2 = P; };
+template <> struct M2LSplit<6, double> { static constexpr int K1 = 3, K2 = 5; };
+template <> struct M2LSplit<5, double> { static constexpr int K1 = 3, K2 = 5; };
+
+// Row stride (elements) of the wave-sum buffer: the whole C of a lane when one pass
+// covers every order, else one order; odd, so a lane's row and a column are both
+// free of bank conflicts.
+template <int P, typename T> constexpr int red_stride() {
+    return (M2LSplit<P, T>::K1 == P ? n_local(P) : ncomp(P)) | 1;
+}
+
 template <int P, int MLO, int MHI, typename T>
 __device__ __forceinline__ void m2l_pass(const double4 gA, const double4 *__restrict__ gcell,
                                          const T *__restrict__ mult,
                                          const int32_t *__restrict__ srcs, int len, double *out,
-                                         T (*red)[ncomp(P) + 1]) {
+                                         T *red) {
+    constexpr int RS = red_stride<P, T>();
     constexpr int NM = n_mult(P), ND = off_order(P + 1);
     constexpr int NA = cidx(MHI + 1, 0, 0) - cidx(MLO, 0, 0);
     const int lane = threadIdx.x;
@@ -117,46 +131,53 @@ __device__ __forceinline__ void m2l_pass(const double4 gA, const double4 *__rest
         green_derivs<P, T>(x, y, z, rsqrt_t<T>(r2), D);
         m2l_contract<P, MLO, MHI, T>(D, mult + (int64_t)B * NM, acc);
     }
-    // wave sum, one order at a time
+    // wave sum of every component in lane order (FP64)
+    if constexpr (MLO == 1 && MHI == P && M2LSplit<P, T>::K1 == P) {
+        // all orders at once: lane k sums component k (and k + 64)
 #pragma unroll
-    for (int m = MLO; m <= MHI; m++) {
-        const int base = cidx(m, 0, 0) - cidx(MLO, 0, 0);
-#pragma unroll
-        for (int k = 0; k < ncomp(m); k++) red[lane][k] = acc[base + k];
+        for (int k = 0; k < NA; k++) red[lane * RS + k] = acc[k];
         __syncthreads();
-        if (lane < ncomp(m)) {
+        for (int k = lane; k < NA; k += kWave) {
             double s = 0.0;
-            for (int l = 0; l < kWave; l++) s += (double)red[l][lane];
-            out[cidx(m, 0, 0) + lane] = s;
+            for (int l = 0; l < kWave; l++) s += (double)red[l * RS + k];
+            out[cidx(MLO, 0, 0) + k] = s;
         }
         __syncthreads();
+    } else {
+#pragma unroll
+        for (int m = MLO; m <= MHI; m++) {
+            const int base = cidx(m, 0, 0) - cidx(MLO, 0, 0);
+#pragma unroll
+            for (int k = 0; k < ncomp(m); k++) red[lane * RS + k] = acc[base + k];
+            __syncthreads();
+            if (lane < ncomp(m)) {
+                double s = 0.0;
+                for (int l = 0; l < kWave; l++) s += (double)red[l * RS + lane];
+                out[cidx(m, 0, 0) + lane] = s;
+            }
+            __syncthreads();
+        }
     }
 }
 
-// FP64 at high order splits the output orders over passes (D is recomputed per
-// pass) so that the accumulators and D stay in registers.
-template <int P, typename T> struct M2LSplit { static constexpr int K1 = P, K2 = P; };
-template <> struct M2LSplit<6, double> { static constexpr int K1 = 3, K2 = 5; };
-template <> struct M2LSplit<5, double> { static constexpr int K1 = 3, K2 = 5; };
-
 // LDS of the wave-sum buffer, in ints: a target's list is sorted there first
 template <int P, typename T> constexpr int red_ints() {
-    return (int)(sizeof(T) * kWave * (ncomp(P) + 1) / 4) & ~3;
+    return (int)(sizeof(T) * kWave * red_stride<P, T>() / 4) & ~3;
 }
 
 template <int P, typename T>
-__global__ void __launch_bounds__(kM2LBlock)
+__global__ void __launch_bounds__(kM2LBlock, 2)
 k_m2l(const DevState *__restrict__ st, const double4 *__restrict__ gcell,
       const T *__restrict__ mult, const int32_t *__restrict__ cnt, int32_t *__restrict__ seg,
       int stride, double *__restrict__ local) {
     constexpr int NL = n_local(P);
     constexpr int K1 = M2LSplit<P, T>::K1, K2 = M2LSplit<P, T>::K2;
-    __shared__ __align__(16) T red[kWave][ncomp(P) + 1];
+    __shared__ __align__(16) T red[kWave * red_stride<P, T>()];
     __shared__ int32_t s_list[kM2LListLDS];
     extern __shared__ __align__(16) int32_t dyn[];   // sort scratch if red is too small
     if (st->status & kSkipMask) return;
     const int need = ((stride < kM2LListLDS ? stride : kM2LListLDS) + 3) & ~3;
-    int32_t *scratch = need <= red_ints<P, T>() ? (int32_t *)&red[0][0] : dyn;
+    int32_t *scratch = need <= red_ints<P, T>() ? (int32_t *)red : dyn;
     const int nc = st->ncells;
     const int lane = threadIdx.x;
     for (int A = blockIdx.x; A < nc; A += gridDim.x) {
