@@ -44,6 +44,11 @@ def lib():
     d, i64, i32, vp = C.c_double, C.c_int64, C.c_int, C.c_void_p
     L.orc_pair_test.restype = C.c_int
     L.orc_pair_test.argtypes = [d] * 15
+    L.orc_collision_time.restype = d
+    L.orc_collision_time.argtypes = [d] * 15
+    L.orc_resolve.restype = i64
+    L.orc_resolve.argtypes = [i64, _i64, i64, _f64, _f64, _f64, _f64, _f64, _f64, _f64, _f64,
+                              d, d, _i32]
     L.orc_root_half_width.restype = d
     L.orc_root_half_width.argtypes = [_f64, _f64, _f64, i64]
     L.orc_quantize.restype = C.c_uint32
@@ -127,6 +132,25 @@ def _c(a, dtype=np.float64):
 def pair_test(r1, v1, R1, r2, v2, R2, dt) -> bool:
     return bool(lib().orc_pair_test(*map(float, r1), *map(float, v1), float(R1),
                                     *map(float, r2), *map(float, v2), float(R2), float(dt)))
+
+
+def collision_time(r1, v1, R1, r2, v2, R2, dt) -> float:
+    """dt_c of Eq. (2) if the pair collides within [0, dt], else -1."""
+    return lib().orc_collision_time(*map(float, r1), *map(float, v1), float(R1),
+                                    *map(float, r2), *map(float, v2), float(R2), float(dt))
+
+
+def resolve(s: dict, pairs, dt: float, f: float = 2.0) -> np.ndarray:
+    """Resolves the colliding pairs (rows i < j) of state s in place (Sect. 5.1-5.2,
+    greedy in increasing contact time); returns the resolved rows, sorted."""
+    pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    n = len(s["x"])
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        s[k] = np.ascontiguousarray(s[k], dtype=np.float64)
+    flags = np.zeros(len(pairs), np.int32)
+    lib().orc_resolve(len(pairs), pairs, n, s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"],
+                      _c(s["m"]), _c(s["R"]), float(dt), float(f), flags)
+    return pairs[flags == 1]
 
 
 def root_half_width(x, y, z) -> float:
@@ -359,9 +383,11 @@ def tree_accel(d: dict, G=1.0, p=3, theta_min=0.5, s=16, ncs=64, ncc_pre=8, ncc_
 
 
 def kdk_steps(d: dict, dt: float, n_steps: int, accel_fn, G=1.0, M_central=1.0,
-              collide_fn=None):
+              collide_fn=None, resolve_f=None):
     """Merged kick-drift-kick leapfrog around the central mass (Sect. 4.1, SBAB1
     form): v += dt/2 a; [collision search on (x, v)]; x += dt v; a = a(x); v += dt/2 a.
+    With resolve_f, the pairs found are resolved (``resolve``, coefficient f) before
+    the drift and the per-step lists hold the resolved pairs.
     Returns the new state and the per-step pair lists."""
     s = {k: np.array(v, dtype=np.float64) for k, v in d.items()}
 
@@ -377,7 +403,10 @@ def kdk_steps(d: dict, dt: float, n_steps: int, accel_fn, G=1.0, M_central=1.0,
         for c, f in enumerate(("vx", "vy", "vz")):
             s[f] = s[f] + 0.5 * dt * a[:, c]
         if collide_fn is not None:
-            pairs.append(collide_fn(s, dt))
+            found = collide_fn(s, dt)
+            if resolve_f is not None:
+                found = resolve(s, found, dt, resolve_f)
+            pairs.append(found)
         for c, f in enumerate(("x", "y", "z")):
             s[f] = s[f] + dt * s[("vx", "vy", "vz")[c]]
         a = total_acc()

@@ -75,6 +75,93 @@ int orc_pair_test(double x1, double y1, double z1, double vx1, double vy1, doubl
     return (tc >= 0.0 && tc <= dt) ? 1 : 0;
 }
 
+/* Time of contact dt_c of Eq. (2) when 0 <= dt_c <= dt, else -1. */
+double orc_collision_time(double x1, double y1, double z1, double vx1, double vy1, double vz1,
+                          double R1, double x2, double y2, double z2, double vx2, double vy2,
+                          double vz2, double R2, double dt)
+{
+    double dx = x1 - x2, dy = y1 - y2, dz = z1 - z2;
+    double dvx = vx1 - vx2, dvy = vy1 - vy2, dvz = vz1 - vz2;
+    double rv = dx * dvx + dy * dvy + dz * dvz;
+    double v2 = dvx * dvx + dvy * dvy + dvz * dvz;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double Rs = R1 + R2;
+    double disc = rv * rv + v2 * (Rs * Rs - r2);
+    if (!(v2 > 0.0) || !(disc >= 0.0)) return -1.0;
+    double tc = -(rv + sqrt(disc)) / v2;
+    return (tc >= 0.0 && tc <= dt) ? tc : -1.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Collision resolution, Sect. 5.1 and 5.2 (readings R28-R30).                 */
+/* The colliding pairs (i < j, one row each) are taken in increasing order of  */
+/* (dt_c, i, j); a pair is resolved unless one of its moonlets already was in  */
+/* this step.  Resolving (1 = i, 2 = j): both move on straight lines to the    */
+/* contact time dt_c, dr = r1 - r2 and dv = v1 - v2 there, the impulse          */
+/*   J = alpha (dr . dv) dr,  alpha = f m1 m2 / ((m1 + m2) (R1 + R2)^2)         */
+/* changes v1 by -J/m1 and v2 by +J/m2 (f = 2: elastic), and the rest of the    */
+/* drift uses the new velocity.  The state given is (r, v) at the start of the */
+/* drift; on return v holds v' and r holds r + dt_c (v - v'), so that the      */
+/* drift r + dt v' that follows lands where the moonlet ends the step.         */
+/* resolved[k] = 1 for the pairs resolved.  Returns their number.              */
+/* ------------------------------------------------------------------------- */
+typedef struct { double t; int64_t i, j, k; } orc_hit;
+
+static int hit_cmp(const void *a, const void *b)
+{
+    const orc_hit *p = (const orc_hit *)a, *q = (const orc_hit *)b;
+    if (p->t != q->t) return p->t < q->t ? -1 : 1;
+    if (p->i != q->i) return p->i < q->i ? -1 : 1;
+    if (p->j != q->j) return p->j < q->j ? -1 : 1;
+    return 0;
+}
+
+int64_t orc_resolve(int64_t npairs, const int64_t *pairs, int64_t n, double *x, double *y,
+                    double *z, double *vx, double *vy, double *vz, const double *m,
+                    const double *R, double dt, double f, int32_t *resolved)
+{
+    orc_hit *h = (orc_hit *)malloc(sizeof(orc_hit) * (size_t)(npairs > 0 ? npairs : 1));
+    char *used = (char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t nh = 0, nres = 0;
+    for (int64_t k = 0; k < npairs; k++) {
+        int64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+        resolved[k] = 0;
+        double t = orc_collision_time(x[i], y[i], z[i], vx[i], vy[i], vz[i], R[i], x[j], y[j],
+                                      z[j], vx[j], vy[j], vz[j], R[j], dt);
+        if (t < 0.0) continue;            /* not a collision of this step */
+        h[nh].t = t; h[nh].i = i; h[nh].j = j; h[nh].k = k;
+        nh++;
+    }
+    qsort(h, (size_t)nh, sizeof(orc_hit), hit_cmp);
+    for (int64_t q = 0; q < nh; q++) {
+        int64_t i = h[q].i, j = h[q].j;
+        if (used[i] || used[j]) continue;
+        used[i] = used[j] = 1;
+        resolved[h[q].k] = 1;
+        nres++;
+        double t = h[q].t;
+        double x1 = x[i] + t * vx[i], y1 = y[i] + t * vy[i], z1 = z[i] + t * vz[i];
+        double x2 = x[j] + t * vx[j], y2 = y[j] + t * vy[j], z2 = z[j] + t * vz[j];
+        double drx = x1 - x2, dry = y1 - y2, drz = z1 - z2;
+        double dvx = vx[i] - vx[j], dvy = vy[i] - vy[j], dvz = vz[i] - vz[j];
+        double s = drx * dvx + dry * dvy + drz * dvz;
+        double Rs = R[i] + R[j];
+        double alpha = f * m[i] * m[j] / ((m[i] + m[j]) * (Rs * Rs));
+        double Jx = alpha * s * drx, Jy = alpha * s * dry, Jz = alpha * s * drz;
+        double u1x = vx[i] - Jx / m[i], u1y = vy[i] - Jy / m[i], u1z = vz[i] - Jz / m[i];
+        double u2x = vx[j] + Jx / m[j], u2y = vy[j] + Jy / m[j], u2z = vz[j] + Jz / m[j];
+        x[i] = x[i] + t * (vx[i] - u1x); y[i] = y[i] + t * (vy[i] - u1y);
+        z[i] = z[i] + t * (vz[i] - u1z);
+        x[j] = x[j] + t * (vx[j] - u2x); y[j] = y[j] + t * (vy[j] - u2y);
+        z[j] = z[j] + t * (vz[j] - u2z);
+        vx[i] = u1x; vy[i] = u1y; vz[i] = u1z;
+        vx[j] = u2x; vy[j] = u2y; vz[j] = u2z;
+    }
+    free(h);
+    free(used);
+    return nres;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Root cube and Hilbert keys (Sect. 3.4.6; readings R1, R2).                  */
 /* ------------------------------------------------------------------------- */
