@@ -78,7 +78,21 @@ typedef struct {
      * fail with NCORP_E_CAPACITY, required = the count that would have fitted. */
     int32_t m2l_per_cell;      /* well-separated partner cells kept per cell */
     int32_t p2p_per_leaf;      /* direct-sum source cells kept per leaf */
+    /* collisions in ncorp_step / ncorp_step_batched: NCORP_COLLISIONS_REPORT (0,
+     * default) lists every pair found and changes nothing; NCORP_COLLISIONS_RESOLVE
+     * (1) also resolves them as hard-sphere impacts (Sect. 5.1-5.2): the impulse
+     * J = alpha (dr . dv) dr with alpha = f m1 m2 / ((m1 + m2) (R1 + R2)^2) at the
+     * contact time of Eq. (2), f = collision_f in [1, 2] (2: elastic, the default;
+     * 1: the normal relative velocity is removed).  A moonlet collides at most once
+     * per step: pairs are taken in increasing contact time (ties by i, then j) and
+     * a pair is dropped when one of its moonlets has already collided.  Each
+     * resolved moonlet moves on its old velocity up to contact and on the new one
+     * for the rest of the drift. */
+    int32_t collision_mode;
+    double collision_f;
 } ncorp_params;
+
+enum { NCORP_COLLISIONS_REPORT = 0, NCORP_COLLISIONS_RESOLVE = 1 };
 
 typedef struct ncorp_ctx ncorp_ctx;
 
@@ -126,9 +140,11 @@ int ncorp_collide(ncorp_ctx *ctx, const double *vx, const double *vy, const doub
  * mass (App. B.1): the first call builds the tree and gravity at the start state;
  * every step then kicks, searches collisions on (x, v) over dt with the current
  * tree, drifts, rebuilds the tree, recomputes gravity (mutual + central) and
- * kicks.  x..vz are updated in place.  Collisions are reported, not resolved:
- * pairs receives (step, i, j) triples, cap x 3 int64, each step's pairs in
- * lexicographic order; n_pairs_dev receives n_steps int64 counts. */
+ * kicks.  x..vz are updated in place.  pairs receives (step, i, j) triples,
+ * cap x 3 int64, each step's pairs in lexicographic order; n_pairs_dev receives
+ * n_steps int64 counts.  With collision_mode NCORP_COLLISIONS_REPORT these are all
+ * pairs found and nothing is changed; with NCORP_COLLISIONS_RESOLVE they are the
+ * pairs resolved (see ncorp_params). */
 int ncorp_step(ncorp_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,
                double *vz, const double *m, const double *R, int64_t n, double dt,
                int n_steps, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev,

@@ -120,6 +120,13 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
         std::snprintf(why, len, "m2l_per_cell and p2p_per_leaf must be in 0..%d", kMaxPerTarget);
         return false;
     }
+    if (p->collision_mode != NCORP_COLLISIONS_REPORT &&
+        p->collision_mode != NCORP_COLLISIONS_RESOLVE) {
+        std::snprintf(why, len, "collision_mode must be 0 or 1"); return false;
+    }
+    if (!(p->collision_f >= 1.0 && p->collision_f <= 2.0)) {
+        std::snprintf(why, len, "collision_f must be in [1, 2]"); return false;
+    }
     return true;
 }
 
@@ -136,6 +143,8 @@ extern "C" int ncorp_params_default(ncorp_params *o, int p) {
     o->ncs_col = 12; o->ncc_pre_col = 0; o->ncc_post_col = 16;
     o->precision = NCORP_FP64;
     o->root_half_width = 0.0;
+    o->collision_mode = NCORP_COLLISIONS_REPORT;
+    o->collision_f = 2.0;
     return NCORP_OK;
 }
 
@@ -260,6 +269,10 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.disk_root = (int32_t *)take(4 * (int64_t)kMaxDisks);
     ws.pairs_tmp = (int64_t *)take(8 * ws.pair_cap);
     ws.pairs_alt = (int64_t *)take(8 * ws.pair_cap);
+    ws.pair_dt = (double *)take(8 * ws.pair_cap);
+    ws.pair_flag = (int32_t *)take(4 * ws.pair_cap);
+    ws.mbest = (int32_t *)take(4 * n);
+    ws.mmatch = (int32_t *)take(4 * n);
     ws.bytes = off;
     return off;
 }
@@ -290,7 +303,8 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
         return NCORP_E_INVALID;
     }
     // whatever is left beyond the fixed part holds colliding pairs (2 x 8 bytes each)
-    int64_t pc = 1 + (ws_bytes - fixed) / 16;
+    int64_t pc = 1 + (ws_bytes - fixed) / kPairBytes;
+    if (pc > INT32_MAX) pc = INT32_MAX;           // pair indices are 32-bit
     while (pc > 1 && layout_workspace(probe, c->prm, n, pc) > ws_bytes) pc -= pc > 64 ? 64 : 1;
     Workspace ws;
     ws.base = (char *)workspace;
@@ -411,9 +425,12 @@ extern "C" int ncorp_gravity(ncorp_ctx *c, const double *m, double *ax, double *
     return gravity_impl(c, m, ax, ay, az, (hipStream_t)stream);
 }
 
+// state: x, y, z, vx, vy, vz of a step (resolved in place when collisions are
+// resolved), or nullptr for the search alone
 static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const double *vz,
                         const double *R, double dt, int64_t *pairs, int64_t cap,
-                        int64_t *n_pairs_dev, int triple, int step, hipStream_t s) {
+                        int64_t *n_pairs_dev, int triple, int step, hipStream_t s,
+                        double *const *state = nullptr, const double *m = nullptr) {
     Workspace &ws = c->ws;
     const int64_t n = c->n;
     PhaseTimer t(c, NCORP_PHASE_COLLIDE, s);
@@ -421,8 +438,13 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
     HIPCHK(c, launch_collision_climb(ws, n, dt, s));
     HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col, c->prm.ncc_post_col, s));
     HIPCHK(c, launch_collide_pairs(ws, n, dt, s));
-    HIPCHK(c, launch_emit_pairs(ws, pairs, cap, n_pairs_dev, triple, step,
-                                &ws.st->pair_cursor, s));
+    if (state && c->prm.collision_mode == NCORP_COLLISIONS_RESOLVE)
+        HIPCHK(c, launch_resolve(ws, state[0], state[1], state[2], state[3], state[4], state[5],
+                                 m, R, dt, c->prm.collision_f, pairs, cap, n_pairs_dev, step,
+                                 &ws.st->pair_cursor, s));
+    else
+        HIPCHK(c, launch_emit_pairs(ws, pairs, cap, n_pairs_dev, triple, step,
+                                    &ws.st->pair_cursor, s));
     c->last = s;
     return NCORP_OK;
 }
@@ -472,7 +494,8 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
                               c->prm.G, c->prm.M_central, s));
     }
     for (int k = 0; k < n_steps; k++) {
-        r = collide_impl(c, vx, vy, vz, R, dt, pairs, cap, n_pairs_dev + k, 1, k, s);
+        double *const state[6] = {x, y, z, vx, vy, vz};
+        r = collide_impl(c, vx, vy, vz, R, dt, pairs, cap, n_pairs_dev + k, 1, k, s, state, m);
         if (r != NCORP_OK) return r;
         {
             PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);

@@ -9,10 +9,11 @@
 
 namespace ncorp {
 
-__device__ __forceinline__ bool pair_test(double x1, double y1, double z1, double vx1,
-                                          double vy1, double vz1, double R1, double x2,
-                                          double y2, double z2, double vx2, double vy2,
-                                          double vz2, double R2, double dt) {
+// contact time dt_c of Eq. (2) when 0 <= dt_c <= dt, else -1
+__device__ __forceinline__ double contact_time(double x1, double y1, double z1, double vx1,
+                                               double vy1, double vz1, double R1, double x2,
+                                               double y2, double z2, double vx2, double vy2,
+                                               double vz2, double R2, double dt) {
     double dx = x1 - x2, dy = y1 - y2, dz = z1 - z2;
     double dvx = vx1 - vx2, dvy = vy1 - vy2, dvz = vz1 - vz2;
     double rv = dx * dvx + dy * dvy + dz * dvz;
@@ -20,9 +21,16 @@ __device__ __forceinline__ bool pair_test(double x1, double y1, double z1, doubl
     double r2 = dx * dx + dy * dy + dz * dz;
     double Rs = R1 + R2;
     double disc = rv * rv + v2 * (Rs * Rs - r2);
-    if (!(v2 > 0.0) || !(disc >= 0.0)) return false;
+    if (!(v2 > 0.0) || !(disc >= 0.0)) return -1.0;
     double tc = -(rv + sqrt(disc)) / v2;
-    return tc >= 0.0 && tc <= dt;
+    return (tc >= 0.0 && tc <= dt) ? tc : -1.0;
+}
+
+__device__ __forceinline__ bool pair_test(double x1, double y1, double z1, double vx1,
+                                          double vy1, double vz1, double R1, double x2,
+                                          double y2, double z2, double vx2, double vy2,
+                                          double vz2, double R2, double dt) {
+    return contact_time(x1, y1, z1, vx1, vy1, vz1, R1, x2, y2, z2, vx2, vy2, vz2, R2, dt) >= 0.0;
 }
 
 __device__ __forceinline__ void record(int64_t *out, int64_t cap, unsigned long long *count,
@@ -301,6 +309,162 @@ __global__ void k_pairs_done(DevState *st, int64_t *n_pairs_dev, int64_t cap, in
         atomicMax((unsigned long long *)&st->required, (unsigned long long)(base + n));
     }
     if (triple) *cursor = base + n;
+}
+
+// ---------------------------------------------------------------- resolution
+// Hard-sphere resolution of the pairs found (Sect. 5.1-5.2), one block.  Pairs are
+// taken in increasing (dt_c, i, j) and a moonlet collides at most once per step:
+// this greedy matching is reached in rounds, each accepting every live pair that
+// is the earliest live pair of both its moonlets (the earliest live pair of all is
+// always one, so every round makes progress) and dropping the live pairs that
+// touch a moonlet just matched -- the same set as taking the pairs one by one.
+// The pair list is sorted by (i, j), so its index breaks ties of dt_c.
+__device__ __forceinline__ bool earlier(const double *dtc, int p, int q) {
+    return dtc[p] < dtc[q] || (dtc[p] == dtc[q] && p < q);
+}
+
+__device__ __forceinline__ void keep_earliest(int32_t *slot, int p, const double *dtc) {
+    int cur = *slot;
+    while (cur < 0 || earlier(dtc, p, cur)) {
+        const int old = atomicCAS(slot, cur, p);
+        if (old == cur) break;
+        cur = old;
+    }
+}
+
+constexpr int kResolveThreads = 1024;
+
+__global__ void __launch_bounds__(kResolveThreads)
+k_resolve(DevState *st, const int64_t *__restrict__ keys, int64_t pair_cap, double *x,
+          double *y, double *z, double *vx, double *vy, double *vz,
+          const double *__restrict__ m, const double *__restrict__ R, double dt, double f,
+          double *dtc, int32_t *flag, int32_t *mbest, int32_t *mmatch, int64_t *pairs,
+          int64_t cap, int64_t *n_pairs_dev, int step, int64_t *cursor) {
+    __shared__ int wsum[kResolveThreads / kWave];
+    __shared__ int64_t s_run, s_base;
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+    const int T = blockDim.x;
+    int64_t np = st->npairs;
+    if (np > pair_cap) {                  // the list is incomplete: resolve nothing
+        if (tid == 0) {
+            atomicOr(&st->status, (int32_t)ST_CAP_PAIRS);
+            atomicMax((unsigned long long *)&st->required, (unsigned long long)np);
+        }
+        np = 0;
+    }
+    if (st->status & kSkipMask) np = 0;
+    // flag: 0 dropped, 1 live, 2 resolved
+    for (int64_t p = tid; p < np; p += T) {
+        const int i = (int)(keys[p] >> 32), j = (int)(keys[p] & 0xffffffffll);
+        const double t = contact_time(x[i], y[i], z[i], vx[i], vy[i], vz[i], R[i], x[j], y[j],
+                                      z[j], vx[j], vy[j], vz[j], R[j], dt);
+        dtc[p] = t;
+        flag[p] = t >= 0.0 ? 1 : 0;
+        mmatch[i] = 0;
+        mmatch[j] = 0;
+    }
+    __syncthreads();
+    for (int64_t round = 0; round <= np; round++) {
+        for (int64_t p = tid; p < np; p += T)
+            if (flag[p] == 1) {
+                mbest[(int)(keys[p] >> 32)] = -1;
+                mbest[(int)(keys[p] & 0xffffffffll)] = -1;
+            }
+        __syncthreads();
+        for (int64_t p = tid; p < np; p += T)
+            if (flag[p] == 1) {
+                keep_earliest(&mbest[(int)(keys[p] >> 32)], (int)p, dtc);
+                keep_earliest(&mbest[(int)(keys[p] & 0xffffffffll)], (int)p, dtc);
+            }
+        __syncthreads();
+        for (int64_t p = tid; p < np; p += T)
+            if (flag[p] == 1) {
+                const int i = (int)(keys[p] >> 32), j = (int)(keys[p] & 0xffffffffll);
+                if (mbest[i] == (int)p && mbest[j] == (int)p) {
+                    flag[p] = 2;
+                    mmatch[i] = 1;
+                    mmatch[j] = 1;
+                }
+            }
+        __syncthreads();
+        int live = 0;
+        for (int64_t p = tid; p < np; p += T)
+            if (flag[p] == 1) {
+                const int i = (int)(keys[p] >> 32), j = (int)(keys[p] & 0xffffffffll);
+                if (mmatch[i] || mmatch[j]) flag[p] = 0;
+                else live = 1;
+            }
+        if (!__syncthreads_or(live)) break;
+    }
+    // impulses of the resolved pairs (disjoint moonlets): 1 = i, 2 = j
+    for (int64_t p = tid; p < np; p += T) {
+        if (flag[p] != 2) continue;
+        const int i = (int)(keys[p] >> 32), j = (int)(keys[p] & 0xffffffffll);
+        const double t = dtc[p];
+        const double x1 = x[i] + t * vx[i], y1 = y[i] + t * vy[i], z1 = z[i] + t * vz[i];
+        const double x2 = x[j] + t * vx[j], y2 = y[j] + t * vy[j], z2 = z[j] + t * vz[j];
+        const double drx = x1 - x2, dry = y1 - y2, drz = z1 - z2;
+        const double dvx = vx[i] - vx[j], dvy = vy[i] - vy[j], dvz = vz[i] - vz[j];
+        const double sdot = drx * dvx + dry * dvy + drz * dvz;
+        const double Rs = R[i] + R[j];
+        const double alpha = f * m[i] * m[j] / ((m[i] + m[j]) * (Rs * Rs));
+        const double Jx = alpha * sdot * drx, Jy = alpha * sdot * dry, Jz = alpha * sdot * drz;
+        const double u1x = vx[i] - Jx / m[i], u1y = vy[i] - Jy / m[i], u1z = vz[i] - Jz / m[i];
+        const double u2x = vx[j] + Jx / m[j], u2y = vy[j] + Jy / m[j], u2z = vz[j] + Jz / m[j];
+        // old velocity up to contact, new one after: the drift adds dt u
+        x[i] = x[i] + t * (vx[i] - u1x); y[i] = y[i] + t * (vy[i] - u1y);
+        z[i] = z[i] + t * (vz[i] - u1z);
+        x[j] = x[j] + t * (vx[j] - u2x); y[j] = y[j] + t * (vy[j] - u2y);
+        z[j] = z[j] + t * (vz[j] - u2z);
+        vx[i] = u1x; vy[i] = u1y; vz[i] = u1z;
+        vx[j] = u2x; vy[j] = u2y; vz[j] = u2z;
+    }
+    // the resolved pairs, in (i, j) order, as (step, i, j) after the earlier steps'
+    if (tid == 0) { s_run = 0; s_base = *cursor; }
+    __syncthreads();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t c0 = 0; c0 < np; c0 += T) {
+        const int64_t p = c0 + tid;
+        const bool acc = p < np && flag[p] == 2;
+        const uint64_t b = __ballot(acc);
+        if (lane == 0) wsum[w] = __popcll(b);
+        __syncthreads();
+        int before = 0, tot = 0;
+        for (int k = 0; k < T / kWave; k++) {
+            if (k < w) before += wsum[k];
+            tot += wsum[k];
+        }
+        if (acc) {
+            const int64_t o = s_base + s_run + before + __popcll(b & lt);
+            if (o < cap) {
+                pairs[3 * o] = step;
+                pairs[3 * o + 1] = keys[p] >> 32;
+                pairs[3 * o + 2] = keys[p] & 0xffffffffll;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_run += tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        *n_pairs_dev = s_run;
+        if (s_base + s_run > cap) {
+            atomicOr(&st->status, (int32_t)ST_CAP_PAIRS);
+            atomicMax((unsigned long long *)&st->required, (unsigned long long)(s_base + s_run));
+        }
+        *cursor = s_base + s_run;
+    }
+}
+
+hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, double *vx,
+                          double *vy, double *vz, const double *m, const double *R, double dt,
+                          double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
+                          int64_t *cursor, hipStream_t s) {
+    k_rank_pairs<<<256, 256, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap, ws.pairs_alt);
+    k_resolve<<<1, kResolveThreads, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, x, y, z, vx, vy,
+                                            vz, m, R, dt, f, ws.pair_dt, ws.pair_flag, ws.mbest,
+                                            ws.mmatch, pairs, cap, n_pairs_dev, step, cursor);
+    return hipGetLastError();
 }
 
 hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipStream_t s) {

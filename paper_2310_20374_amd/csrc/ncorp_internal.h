@@ -57,6 +57,8 @@ constexpr int kListChunk = 256;
 // item pushes at most 36 children, so a queue of this many slots keeps the tail
 // below 2^32 even when it overflows
 constexpr int64_t kMaxQueue = 100000000;
+// workspace bytes per colliding-pair slot: two key buffers, contact time, state
+constexpr int64_t kPairBytes = 8 + 8 + 8 + 4;
 
 // per-target interaction lists: default and largest slot counts (a consumer
 // sorts a whole list in LDS)
@@ -208,6 +210,11 @@ struct Workspace {
     int32_t *cnt_a = nullptr;                         // tree-build level counters
     int64_t *pairs_tmp = nullptr;                     // colliding pairs (i<<32|j)
     int64_t *pairs_alt = nullptr;
+    // collision resolution: contact time and state of each pair, best pair and
+    // "already collided" flag of each moonlet (input order)
+    double *pair_dt = nullptr;
+    int32_t *pair_flag = nullptr;
+    int32_t *mbest = nullptr, *mmatch = nullptr;
     // scratch for scans and sorts
     int32_t *scan_part = nullptr;                     // block partials
     uint32_t *hist = nullptr;                         // radix histograms
@@ -268,6 +275,12 @@ hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipSt
 hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,
                              int64_t *n_pairs_dev, int triple, int step, int64_t *cursor,
                              hipStream_t s);
+// sorts the pairs found, resolves them (caller arrays in input order, updated in
+// place) and writes the resolved ones as (step, i, j) triples
+hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, double *vx,
+                          double *vy, double *vz, const double *m, const double *R, double dt,
+                          double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
+                          int64_t *cursor, hipStream_t s);
 
 hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax,
                        const double *ay, const double *az, const double *x,

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libncorp.so")
 
 OK, E_INVALID, E_CAPACITY, E_HIP, E_UNSUPPORTED, E_NONFINITE = 0, -1, -2, -3, -4, -5
 FP64, FP32_BULK = 0, 1
+COLLISIONS_REPORT, COLLISIONS_RESOLVE = 0, 1
 STATUS_NAMES = {0: "ok", -1: "invalid", -2: "capacity", -3: "hip", -4: "unsupported",
                 -5: "nonfinite"}
 
@@ -43,6 +44,7 @@ class Params(C.Structure):
         ("cell_capacity", C.c_int64), ("m2l_capacity", C.c_int64),
         ("p2p_capacity", C.c_int64), ("queue_capacity", C.c_int64),
         ("m2l_per_cell", C.c_int32), ("p2p_per_leaf", C.c_int32),
+        ("collision_mode", C.c_int32), ("collision_f", C.c_double),
     ]
 
     def as_dict(self):

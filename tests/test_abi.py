@@ -39,12 +39,14 @@ def test_params_default_and_validation(nc):
         assert prm.p == p
         assert prm.leaf_size == (17 if p <= 3 else 52)
         assert (prm.ncs_col, prm.ncc_pre_col, prm.ncc_post_col) == (12, 0, 16)
+        assert (prm.collision_mode, prm.collision_f) == (nc.COLLISIONS_REPORT, 2.0)
     bad = nc.Params()
     assert L.ncorp_params_default(C.byref(bad), 7) == nc.E_INVALID
     h = C.c_void_p()
     for field, val in (("p", 7), ("theta_min", 1.0), ("theta_min", 0.0), ("leaf_size", 0),
                        ("ncs", -1), ("theta_mode", 2), ("precision", 5),
-                       ("root_half_width", 3.0), ("G", -1.0)):
+                       ("root_half_width", 3.0), ("G", -1.0), ("collision_mode", 2),
+                       ("collision_f", 0.9), ("collision_f", 2.1)):
         prm = nc.params_default(3)
         setattr(prm, field, val)
         assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.E_INVALID, field

@@ -1,0 +1,135 @@
+"""GPU collision resolution in the leapfrog (Sect. 5.1-5.2, readings R28-R30) against
+the oracle: without gravity the arithmetic is the same on both sides, so states and
+resolved pairs must agree bit for bit; with tree gravity the states agree to FP64
+rounding and the resolved pairs exactly.  Momentum and (for f = 2) kinetic energy
+are conserved by the GPU steps on their own."""
+import numpy as np
+import pytest
+
+from paper_2310_20374_amd import inputs
+from tests.gpu_util import dev_arrays
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("x", "y", "z", "vx", "vy", "vz")
+
+
+@pytest.fixture(scope="module")
+def nc():
+    from paper_2310_20374_amd import ncorp
+    ncorp.lib()
+    return ncorp
+
+
+def _gpu_steps(nc, d, prm, dt, ns, offsets=None, cap=1 << 16):
+    import torch
+    n = len(d["x"])
+    ctx = nc.Context(prm, n, pair_capacity=cap)
+    t = dev_arrays(d)
+    pairs = torch.zeros((cap, 3), dtype=torch.int64, device="cuda:0")
+    npairs = torch.zeros(ns, dtype=torch.int64, device="cuda:0")
+    args = (t["x"], t["y"], t["z"], t["vx"], t["vy"], t["vz"], t["m"], t["R"], dt, ns, pairs,
+            npairs)
+    if offsets is None:
+        ctx.step(*args)
+    else:
+        ctx.step_batched(torch.tensor(offsets, device="cuda:0"), *args)
+    torch.cuda.synchronize()
+    ctx.check_status()
+    cnt = npairs.cpu().numpy()
+    out = {k: t[k].cpu().numpy() for k in FIELDS}
+    return out, pairs[: int(cnt.sum())].cpu().numpy(), cnt
+
+
+def _per_step(pairs, cnt):
+    out, o = [], 0
+    for c in cnt:
+        out.append(pairs[o: o + c, 1:])
+        o += c
+    return out
+
+
+@pytest.mark.parametrize("f", [2.0, 1.3, 1.0])
+def test_ballistic_gas_matches_oracle_bitwise(nc, orc, f):
+    """No mutual gravity and no central mass: three steps of a dense gas box, every
+    collision resolved; states and resolved pairs identical to the oracle's."""
+    d = inputs.gas_box(3000, seed=7, radius=0.012)
+    dt, ns = 0.01, 3
+    prm = nc.params_default(0, M_central=0.0, leaf_size=8,
+                            collision_mode=nc.COLLISIONS_RESOLVE, collision_f=f)
+    print(f"gas f={f}", flush=True)
+    got, pairs, cnt = _gpu_steps(nc, d, prm, dt, ns)
+    ref, ref_pairs = orc.kdk_steps(d, dt, ns, None, M_central=0.0,
+                                   collide_fn=lambda s, h: orc.pairs_brute(s, h), resolve_f=f)
+    assert cnt.sum() > 30
+    for st, (g, r) in enumerate(zip(_per_step(pairs, cnt), ref_pairs)):
+        assert np.array_equal(g, r), st
+    for k in FIELDS:
+        assert np.array_equal(got[k], ref[k]), k
+
+
+def test_clumps_with_gravity_match_oracle(nc, orc):
+    """Clumped disk, p = 4 tree gravity, f = 1.5: states to FP64 rounding, resolved
+    pairs exactly."""
+    d = inputs.clumps(4000, seed=2, n_clumps=8)
+    dt, ns = 2e-3, 3
+    prm = nc.params_default(4, leaf_size=16, collision_mode=nc.COLLISIONS_RESOLVE,
+                            collision_f=1.5)
+    got, pairs, cnt = _gpu_steps(nc, d, prm, dt, ns)
+
+    def accel(s):
+        return orc.tree_accel(s, p=4, s=16, ncs=prm.ncs, ncc_pre=prm.ncc_pre,
+                              ncc_post=prm.ncc_post)[0]
+
+    ref, ref_pairs = orc.kdk_steps(d, dt, ns, accel, collide_fn=lambda s, h: orc.pairs_brute(s, h),
+                                   resolve_f=1.5)
+    assert cnt.sum() > 0
+    for st, (g, r) in enumerate(zip(_per_step(pairs, cnt), ref_pairs)):
+        assert np.array_equal(g, r), st
+    for k in ("x", "y", "z"):
+        assert np.abs(got[k] - ref[k]).max() < 1e-11, k
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(got[k] - ref[k]).max() < 1e-11, k
+
+
+@pytest.mark.parametrize("f", [2.0, 1.2])
+def test_momentum_and_energy(nc, f):
+    """Ten ballistic steps of a gas box with unequal masses: total momentum conserved;
+    kinetic energy conserved for f = 2 and decreasing for f < 2."""
+    d = inputs.gas_box(4000, seed=11, radius=0.01)
+    d["m"] = d["m"] * (1.0 + np.arange(4000) % 5)
+    prm = nc.params_default(0, M_central=0.0, leaf_size=8,
+                            collision_mode=nc.COLLISIONS_RESOLVE, collision_f=f)
+    got, pairs, cnt = _gpu_steps(nc, d, prm, 0.01, 10)
+    assert cnt.sum() > 100
+    p0 = np.array([(d["m"] * d[k]).sum() for k in ("vx", "vy", "vz")])
+    p1 = np.array([(d["m"] * got[k]).sum() for k in ("vx", "vy", "vz")])
+    assert np.abs(p1 - p0).max() < 1e-13 * (d["m"] * np.abs(d["vx"])).sum()
+    ke = lambda s: 0.5 * (d["m"] * (s["vx"] ** 2 + s["vy"] ** 2 + s["vz"] ** 2)).sum()
+    if f == 2.0:
+        assert abs(ke(got) - ke(d)) < 1e-12 * ke(d)
+    else:
+        assert ke(got) < ke(d) * (1 - 1e-4)
+
+
+def test_batched_resolution_equals_per_disk(nc):
+    """Independent gas boxes in one batched call resolve exactly as each alone (no pair
+    across boxes even though they overlap in space)."""
+    parts = [inputs.gas_box(1500 + 300 * k, seed=20 + k, radius=0.012) for k in range(3)]
+    off = np.zeros(4, np.int64)
+    off[1:] = np.cumsum([len(p["x"]) for p in parts])
+    d = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    prm = nc.params_default(0, M_central=0.0, leaf_size=8,
+                            collision_mode=nc.COLLISIONS_RESOLVE, collision_f=1.7)
+    got, pairs, cnt = _gpu_steps(nc, d, prm, 0.01, 2, offsets=off)
+    want_steps = [[], []]
+    for k, part in enumerate(parts):
+        g, pk, ck = _gpu_steps(nc, part, prm, 0.01, 2)
+        for f in FIELDS:
+            assert np.array_equal(got[f][off[k]:off[k + 1]], g[f]), (k, f)
+        for st, rows in enumerate(_per_step(pk, ck)):
+            want_steps[st].append(rows + off[k])
+    for st, rows in enumerate(_per_step(pairs, cnt)):
+        w = np.concatenate(want_steps[st])
+        w = w[np.lexsort((w[:, 1], w[:, 0]))]
+        assert np.array_equal(rows, w), st
