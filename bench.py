@@ -4,7 +4,8 @@
 Workload: a cold disk of N = 1e6 moonlets around a central mass of 1 (G = 1),
 expansion order p = 6, theta_min = 0.5 with the mass-dependent opening angle,
 leaf size 52 and the walk thresholds of the paper's timing runs, dt = 1e-3.  One
-step = collision climb + walk + pair tests, drift, rebuild (keys, sort, octree),
+step = collision climb + walk + pair tests + elastic resolution of the pairs found
+(as in the paper's timing runs), drift, rebuild (keys, sort, octree),
 gravity climb + walk + M2L + descent + direct sums + evaluation, kicks (one
 ncorp_step call runs all K steps; its extra initial force evaluation is inside
 the timed region).  The headline value is the FP32-bulk form; the plain FP64
@@ -141,7 +142,9 @@ def _run_batched(nc, args, device):
     n = len(d["x"])
     base = {k: torch.tensor(v, device=device) for k, v in d.items()}
     offd = torch.tensor(off, device=device)
-    prm = nc.params_default(4, theta_min=0.5, precision=nc.FP32_BULK)
+    prm = nc.params_default(4, theta_min=0.5, precision=nc.FP32_BULK,
+                            collision_mode=nc.COLLISIONS_RESOLVE if args.collisions == "resolve"
+                            else nc.COLLISIONS_REPORT, collision_f=2.0)
     t0 = time.perf_counter()
     best, table = autotune.tune_leaf_size(nc, prm, base, offd, dt=args.dt, steps=3)
     tune_s = time.perf_counter() - t0
@@ -212,6 +215,7 @@ def _run_batched(nc, args, device):
         "workload": "64 independent cold disks (sizes log-uniform in [1000, 50000], seed 0; "
                     "disk k drawn with seed 1000+k), one root per disk, no cross-disk terms",
         "n_disks": 64, "n": int(n), "p": 4, "theta_min": 0.5, "precision": "fp32-bulk",
+        "collisions": args.collisions,
         "leaf_size": int(best), "autotune_ms_per_step": table, "autotune_seconds": tune_s,
         "graph_steps": ns, "replays": args.batched_replays,
         "value": n * total_steps / wall, "unit": "particle-steps/s",
@@ -264,6 +268,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--collisions", choices=("resolve", "report"), default="resolve",
+                    help="resolve the pairs found elastically (f = 2, as in the paper's timing "
+                         "runs, keeping N constant) or only report them")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="measure only the batched form (its object is printed alone)")
@@ -297,8 +304,11 @@ def main():
         print(json.dumps({"batched": _run_batched(ncorp, args, device)}))
         return 0
     d = inputs.disk(args.n, seed=0)
-    prm64 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP64)
-    prm32 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP32_BULK)
+    cmode = ncorp.COLLISIONS_RESOLVE if args.collisions == "resolve" else ncorp.COLLISIONS_REPORT
+    prm64 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP64,
+                                 collision_mode=cmode, collision_f=2.0)
+    prm32 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP32_BULK,
+                                 collision_mode=cmode, collision_f=2.0)
     thr = (prm64.ncs, prm64.ncc_pre, prm64.ncc_post)
     print(f"# bench: N={args.n} p={args.p} theta_min={args.theta} s={prm64.leaf_size} "
           f"steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
@@ -377,7 +387,10 @@ def main():
             "n": args.n, "p": args.p, "theta_min": args.theta, "theta_mode": "mass-dependent",
             "leaf_size": prm64.leaf_size, "walk_thresholds": list(thr),
             "collision_thresholds": [prm64.ncs_col, prm64.ncc_pre_col, prm64.ncc_post_col],
-            "dt": args.dt, "precision": "fp32-bulk: direct sums and M2L in f32 (Kahan-summed "
+            "dt": args.dt,
+            "collisions": "resolved elastically (hard spheres, f = 2)" if args.collisions ==
+                          "resolve" else "found and reported, not resolved",
+            "precision": "fp32-bulk: direct sums and M2L in f32 (Kahan-summed "
                                         "tiles), positions/offsets/climbs/integrator in f64",
         },
         "roofline": roofline,
