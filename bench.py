@@ -37,12 +37,12 @@ FLOPS_PER_INTERACTION = 20  # directed moonlet pair, the usual N-body convention
 # HBM traffic of one direct-sum evaluation (k_p2p<float> + k_p2p_long<float>) on the
 # default workload: FETCH_SIZE and WRITE_SIZE from two rocprofv3 --pmc runs (KiB per
 # dispatch), scaled by what the same counters read for a 1 GiB device copy
-# (bench.py --copy-calibration 1024: FETCH 524305 KiB -> x2.00, WRITE 1048576 KiB ->
+# (bench.py --copy-calibration 1024: FETCH 524303 KiB -> x2.00, WRITE 1048576 KiB ->
 # x1.00).  The figures belong to the kernel source with this git blob hash and are
 # reported only while it is unchanged.
 P2P_TRAFFIC = {"source": "paper_2310_20374_amd/csrc/p2p.hip",
-               "blob": "39b2f6e5757897bf0c5a1ec69102d0b76e1939df",
-               "fetch_kib": (175608.3, 4729.2), "write_kib": (25777.7, 670.9),
+               "blob": "ee1bc0982888890114e874ada789c9430c72d37a",
+               "fetch_kib": (175587.7, 4754.2), "write_kib": (25781.1, 671.1),
                "fetch_scale": 2.00, "write_scale": 1.00}
 
 

@@ -151,6 +151,7 @@ template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 // r^2 floor: a moonlet meets itself (dx = 0) in its own leaf; the floor keeps
 // 1/r^3 finite there so the term is exactly 0, and is far below any pair distance
+// (FP32: added to r^2; FP64: a lower bound on r^2)
 template <typename T> __device__ __forceinline__ T r2_floor();
 template <> __device__ __forceinline__ float r2_floor<float>() { return 1e-24f; }
 template <> __device__ __forceinline__ double r2_floor<double>() { return 1e-200; }
@@ -177,9 +178,17 @@ __device__ __forceinline__ void interact(const typename Vec4<T>::type &v, const 
 #pragma unroll
     for (int k = 0; k < NT; k++) {
         const T dx = v.x - xi[k], dy = v.y - yi[k], dz = v.z - zi[k];
-        T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, dx * dx));
-        r2 = r2 > floor2 ? r2 : floor2;
-        const T rinv = rsq<T>(r2);
+        T rinv;
+        if constexpr (sizeof(T) == 4) {
+            // the floor enters as an addend, so r2 >= 1e-24 is a normal float and the
+            // hardware reciprocal square root needs no denormal handling
+            const T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, fmat<T>(dx, dx, floor2)));
+            rinv = __builtin_amdgcn_rsqf(r2);
+        } else {
+            T r2 = fmat<T>(dz, dz, fmat<T>(dy, dy, dx * dx));
+            r2 = r2 > floor2 ? r2 : floor2;
+            rinv = rsq<T>(r2);
+        }
         const T w = v.w * (rinv * rinv) * rinv;
         px[k] = fmat<T>(dx, w, px[k]);
         py[k] = fmat<T>(dy, w, py[k]);
