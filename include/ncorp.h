@@ -90,6 +90,19 @@ typedef struct {
      * for the rest of the drift. */
     int32_t collision_mode;
     double collision_f;
+    /* central-body extras, added to the central mass in the kicks of ncorp_step
+     * (0 disables each; the gravity of ncorp_gravity is unchanged):
+     *   J2, R_central: the central body's equatorial bulge, potential
+     *     -G M_c R_central^2 J2 (r^2 - 3 z^2) / (2 r^5), its axis along z;
+     *   M_sun, a_sun, obliquity: a distant body on a circular orbit of radius a_sun
+     *     in the plane tilted by `obliquity` about x, to quadrupolar order, at
+     *     longitude lambda = t sqrt(G M_sun / a_sun^3);
+     *   t_start: the time of the first ncorp_step call; the context's clock then
+     *     advances by n_steps dt per call (on the host, so a captured call replays
+     *     the times it was captured with). */
+    double J2, R_central;
+    double M_sun, a_sun, obliquity;
+    double t_start;
 } ncorp_params;
 
 enum { NCORP_COLLISIONS_REPORT = 0, NCORP_COLLISIONS_RESOLVE = 1 };

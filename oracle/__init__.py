@@ -8,6 +8,7 @@ this file only marshals numpy arrays through ctypes.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -367,11 +368,38 @@ def pairs_of(d: dict, dt: float, targets, cap: int = 1 << 20) -> np.ndarray:
     return res
 
 
-def central_accel(x, y, z, G: float = 1.0, M_central: float = 1.0) -> np.ndarray:
-    """-G M_c r / |r|^3 (App. B.1)."""
+def sun_position(t: float, G: float, M_sun: float, a_sun: float, obliquity: float):
+    """Distant body on a circular orbit of radius a_sun, tilted by the obliquity about
+    x, at longitude n t with n = sqrt(G M_sun / a_sun^3) (App. B)."""
+    lam = t * math.sqrt(G * M_sun / (a_sun * a_sun * a_sun))
+    return (a_sun * math.cos(lam), a_sun * math.sin(lam) * math.cos(obliquity),
+            a_sun * math.sin(lam) * math.sin(obliquity))
+
+
+def central_accel(x, y, z, G: float = 1.0, M_central: float = 1.0, J2: float = 0.0,
+                  R_central: float = 1.0, M_sun: float = 0.0, a_sun: float = 0.0,
+                  obliquity: float = 0.0, t: float = 0.0) -> np.ndarray:
+    """-G M_c r / |r|^3 (App. B.1), plus the central body's J2 bulge
+    G M_c R^2 J2 / r^5 [(15 z^2 - 3 r^2) / (2 r^2) r - 3 z e_z] and the quadrupolar
+    tide of a distant body -G M_sun / a^3 (r - 3 (r . r_sun) / a^2 r_sun) (App. B)."""
     r2 = x * x + y * y + z * z
-    f = -G * M_central / (r2 * np.sqrt(r2))
-    return np.stack([f * x, f * y, f * z], axis=1)
+    r = np.sqrt(r2)
+    f = -(G * M_central) / (r2 * r)
+    ax, ay, az = f * x, f * y, f * z
+    if J2 != 0.0:
+        c = (G * M_central * R_central * R_central * J2) / (r2 * r2 * r)
+        k = (15.0 * z * z - 3.0 * r2) / (2.0 * r2)
+        ax = ax + c * (k * x)
+        ay = ay + c * (k * y)
+        az = az + c * (k * z - 3.0 * z)
+    if M_sun > 0.0:
+        sx, sy, sz = sun_position(t, G, M_sun, a_sun, obliquity)
+        q = 3.0 * (x * sx + y * sy + z * sz) / (a_sun * a_sun)
+        g = -(G * M_sun) / (a_sun * a_sun * a_sun)
+        ax = ax + g * (x - q * sx)
+        ay = ay + g * (y - q * sy)
+        az = az + g * (z - q * sz)
+    return np.stack([ax, ay, az], axis=1)
 
 
 def tree_accel(d: dict, G=1.0, p=3, theta_min=0.5, s=16, ncs=64, ncc_pre=8, ncc_post=64,
@@ -383,21 +411,25 @@ def tree_accel(d: dict, G=1.0, p=3, theta_min=0.5, s=16, ncs=64, ncc_pre=8, ncc_
 
 
 def kdk_steps(d: dict, dt: float, n_steps: int, accel_fn, G=1.0, M_central=1.0,
-              collide_fn=None, resolve_f=None):
+              collide_fn=None, resolve_f=None, central=None, t_start: float = 0.0):
     """Merged kick-drift-kick leapfrog around the central mass (Sect. 4.1, SBAB1
     form): v += dt/2 a; [collision search on (x, v)]; x += dt v; a = a(x); v += dt/2 a.
     With resolve_f, the pairs found are resolved (``resolve``, coefficient f) before
-    the drift and the per-step lists hold the resolved pairs.
+    the drift and the per-step lists hold the resolved pairs.  ``central`` holds the
+    extra keyword arguments of ``central_accel`` (J2, R_central, M_sun, a_sun,
+    obliquity); the kicks happen at t_start + k dt.
     Returns the new state and the per-step pair lists."""
     s = {k: np.array(v, dtype=np.float64) for k, v in d.items()}
 
-    def total_acc():
-        a = central_accel(s["x"], s["y"], s["z"], G, M_central)
+    extra = dict(central or {})
+
+    def total_acc(t):
+        a = central_accel(s["x"], s["y"], s["z"], G, M_central, t=t, **extra)
         if accel_fn is not None:
             a = accel_fn(s) + a
         return a
 
-    a = total_acc()
+    a = total_acc(t_start)
     pairs = []
     for k in range(n_steps):
         for c, f in enumerate(("vx", "vy", "vz")):
@@ -409,7 +441,7 @@ def kdk_steps(d: dict, dt: float, n_steps: int, accel_fn, G=1.0, M_central=1.0,
             pairs.append(found)
         for c, f in enumerate(("x", "y", "z")):
             s[f] = s[f] + dt * s[("vx", "vy", "vz")[c]]
-        a = total_acc()
+        a = total_acc(t_start + (k + 1) * dt)
         for c, f in enumerate(("vx", "vy", "vz")):
             s[f] = s[f] + 0.5 * dt * a[:, c]
     return s, pairs

@@ -3,6 +3,7 @@
 // nothing waits for the GPU except the status / inspection calls.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -21,6 +22,7 @@ struct ncorp_ctx {
     Workspace ws;
     bool have_tree = false;
     int64_t n = 0;
+    double clock = 0.0;                 // time of the next ncorp_step call
     hipStream_t last = nullptr;
     char err[256];
     // phase timing
@@ -127,6 +129,14 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
     if (!(p->collision_f >= 1.0 && p->collision_f <= 2.0)) {
         std::snprintf(why, len, "collision_f must be in [1, 2]"); return false;
     }
+    if (!std::isfinite(p->J2) || (p->J2 != 0.0 && !(p->R_central > 0.0))) {
+        std::snprintf(why, len, "J2 needs a finite value and R_central > 0"); return false;
+    }
+    if (!(p->M_sun >= 0.0) || (p->M_sun > 0.0 && !(p->a_sun > 0.0)) ||
+        !std::isfinite(p->obliquity) || !std::isfinite(p->t_start)) {
+        std::snprintf(why, len, "M_sun >= 0 (then a_sun > 0), finite obliquity and t_start");
+        return false;
+    }
     return true;
 }
 
@@ -145,6 +155,12 @@ extern "C" int ncorp_params_default(ncorp_params *o, int p) {
     o->root_half_width = 0.0;
     o->collision_mode = NCORP_COLLISIONS_REPORT;
     o->collision_f = 2.0;
+    o->J2 = 0.0;
+    o->R_central = 1.0;
+    o->M_sun = 0.0;
+    o->a_sun = 0.0;
+    o->obliquity = 0.0;
+    o->t_start = 0.0;
     return NCORP_OK;
 }
 
@@ -155,6 +171,7 @@ extern "C" int ncorp_create(const ncorp_params *params, ncorp_ctx **out) {
     if (!params_ok(params, why, sizeof(why))) return NCORP_E_INVALID;
     ncorp_ctx *c = new ncorp_ctx();
     c->prm = *params;
+    c->clock = params->t_start;
     c->err[0] = 0;
     *out = c;
     return NCORP_OK;
@@ -467,6 +484,28 @@ __global__ void k_zero_cursor(DevState *st) {
 }
 }
 
+// What the kick adds to the mutual gravity at time t: the central mass (App. B.1),
+// the bulge of the central body and the quadrupolar tide of a distant body on a
+// circular orbit (its position at t).
+static CentralBody central_body(const ncorp_params &p, double t) {
+    CentralBody b;
+    b.GM = p.G * p.M_central;
+    b.GMR2J2 = p.G * p.M_central * p.R_central * p.R_central * p.J2;
+    b.GMsun = p.G * p.M_sun;
+    b.sx = b.sy = b.sz = 0.0;
+    b.a2 = b.a3 = 1.0;
+    if (p.M_sun > 0.0) {
+        const double a = p.a_sun;
+        const double lam = t * std::sqrt(p.G * p.M_sun / (a * a * a));
+        b.sx = a * std::cos(lam);
+        b.sy = a * std::sin(lam) * std::cos(p.obliquity);
+        b.sz = a * std::sin(lam) * std::sin(p.obliquity);
+        b.a2 = a * a;
+        b.a3 = a * a * a;
+    }
+    return b;
+}
+
 static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double *x, double *y,
                      double *z, double *vx, double *vy, double *vz, const double *m,
                      const double *R, int64_t n, double dt, int n_steps, int64_t *pairs,
@@ -491,7 +530,7 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
     {
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
         HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, 0.5 * dt,
-                              c->prm.G, c->prm.M_central, s));
+                              central_body(c->prm, c->clock), s));
     }
     for (int k = 0; k < n_steps; k++) {
         double *const state[6] = {x, y, z, vx, vy, vz};
@@ -506,9 +545,10 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
         if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
         const double h = (k == n_steps - 1) ? 0.5 * dt : dt;
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
-        HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, h, c->prm.G,
-                              c->prm.M_central, s));
+        HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, h,
+                              central_body(c->prm, c->clock + (double)(k + 1) * dt), s));
     }
+    c->clock += (double)n_steps * dt;
     c->last = s;
     return NCORP_OK;
 }

@@ -282,10 +282,15 @@ hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, 
                           double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
                           int64_t *cursor, hipStream_t s);
 
+// what the kick adds besides the mutual gravity: G M_c, G M_c R^2 J2, and the
+// distant body (G M_sun, its position, a^2, a^3); zero factors switch terms off
+struct CentralBody {
+    double GM, GMR2J2, GMsun, sx, sy, sz, a2, a3;
+};
 hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax,
                        const double *ay, const double *az, const double *x,
-                       const double *y, const double *z, int64_t n, double h, double G,
-                       double Mc, hipStream_t s);
+                       const double *y, const double *z, int64_t n, double h,
+                       const CentralBody &b, hipStream_t s);
 hipError_t launch_drift(double *x, double *y, double *z, const double *vx,
                         const double *vy, const double *vz, int64_t n, double dt,
                         hipStream_t s);

@@ -1,5 +1,9 @@
 // Kick and drift of the leapfrog (Sect. 4.1) with the central mass computed
-// exactly in the kick (App. B.1: a = -G M_c r / r^3; it is not part of the tree).
+// exactly in the kick (App. B.1: a = -G M_c r / r^3; it is not part of the tree),
+// optionally with the central body's J2 bulge and the quadrupolar tide of a distant
+// body (App. B):
+//   a_J2  = G M_c R^2 J2 / r^5 [ (15 z^2 - 3 r^2) / (2 r^2) r - 3 z e_z ]
+//   a_sun = -G M_sun / a^3 ( r - 3 (r . r_sun) / a^2 r_sun ).
 #include "ncorp_internal.h"
 
 namespace ncorp {
@@ -8,14 +12,28 @@ __global__ void k_kick(double *__restrict__ vx, double *__restrict__ vy, double 
                        const double *__restrict__ ax, const double *__restrict__ ay,
                        const double *__restrict__ az, const double *__restrict__ x,
                        const double *__restrict__ y, const double *__restrict__ z, int64_t n,
-                       double h, double GM) {
+                       double h, CentralBody b) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double px = x[i], py = y[i], pz = z[i];
         const double r2 = px * px + py * py + pz * pz;
         const double r = sqrt(r2);
-        const double f = -GM / (r2 * r);
+        const double f = -b.GM / (r2 * r);
         double gx = f * px, gy = f * py, gz = f * pz;
+        if (b.GMR2J2 != 0.0) {
+            const double c = b.GMR2J2 / (r2 * r2 * r);
+            const double k = (15.0 * pz * pz - 3.0 * r2) / (2.0 * r2);
+            gx += c * (k * px);
+            gy += c * (k * py);
+            gz += c * (k * pz - 3.0 * pz);
+        }
+        if (b.GMsun != 0.0) {
+            const double q = 3.0 * (px * b.sx + py * b.sy + pz * b.sz) / b.a2;
+            const double g = -b.GMsun / b.a3;
+            gx += g * (px - q * b.sx);
+            gy += g * (py - q * b.sy);
+            gz += g * (pz - q * b.sz);
+        }
         if (ax) { gx += ax[i]; gy += ay[i]; gz += az[i]; }
         vx[i] += h * gx;
         vy[i] += h * gy;
@@ -41,8 +59,8 @@ static int grid1(int64_t n) {
 
 hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax, const double *ay,
                        const double *az, const double *x, const double *y, const double *z,
-                       int64_t n, double h, double G, double Mc, hipStream_t s) {
-    k_kick<<<grid1(n), 256, 0, s>>>(vx, vy, vz, ax, ay, az, x, y, z, n, h, G * Mc);
+                       int64_t n, double h, const CentralBody &b, hipStream_t s) {
+    k_kick<<<grid1(n), 256, 0, s>>>(vx, vy, vz, ax, ay, az, x, y, z, n, h, b);
     return hipGetLastError();
 }
 

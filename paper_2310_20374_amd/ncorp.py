@@ -45,6 +45,8 @@ class Params(C.Structure):
         ("p2p_capacity", C.c_int64), ("queue_capacity", C.c_int64),
         ("m2l_per_cell", C.c_int32), ("p2p_per_leaf", C.c_int32),
         ("collision_mode", C.c_int32), ("collision_f", C.c_double),
+        ("J2", C.c_double), ("R_central", C.c_double), ("M_sun", C.c_double),
+        ("a_sun", C.c_double), ("obliquity", C.c_double), ("t_start", C.c_double),
     ]
 
     def as_dict(self):

@@ -46,10 +46,15 @@ def test_params_default_and_validation(nc):
     for field, val in (("p", 7), ("theta_min", 1.0), ("theta_min", 0.0), ("leaf_size", 0),
                        ("ncs", -1), ("theta_mode", 2), ("precision", 5),
                        ("root_half_width", 3.0), ("G", -1.0), ("collision_mode", 2),
-                       ("collision_f", 0.9), ("collision_f", 2.1)):
+                       ("collision_f", 0.9), ("collision_f", 2.1), ("M_sun", -1.0),
+                       ("obliquity", float("nan"))):
         prm = nc.params_default(3)
         setattr(prm, field, val)
         assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.E_INVALID, field
+    prm = nc.params_default(3, J2=1e-3, R_central=0.0)       # J2 needs a radius
+    assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.E_INVALID
+    prm = nc.params_default(3, M_sun=1.0, a_sun=0.0)         # a distant body needs its orbit
+    assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.E_INVALID
     prm = nc.params_default(3, root_half_width=16.0)
     assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.OK
     assert h.value
