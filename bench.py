@@ -131,6 +131,56 @@ def _errors(orc, d, acc, samples):
             "samples": int(len(tg))}
 
 
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E (published)
+
+
+def _phase_rooflines(phases, info, n, p, precision_fp32):
+    """Roofline time per phase call from its algorithmic traffic or arithmetic (lower
+    bounds: each array read or written once, the paper's operation counts), against
+    the phase's measured time per call.  The walks are latency-bound and have no
+    roofline; the step's fraction is the sum of roofline times over the sum of the
+    measured times of all phases."""
+    nm = {0: 0, 1: 1}.get(p, p * (p + 1) * (p + 2) // 6 - 3)
+    nl = (p + 1) * (p + 2) * (p + 3) // 6 - 1 if p > 0 else 0
+    cells, leaves = info["ncells"], info["nleaves"]
+    fpeak = (PEAK_FP32_TFLOPS if precision_fp32 else PEAK_FP64_TFLOPS) * 1e12
+    hbm = PEAK_HBM_GBS * 1e9
+    m2l_flops = {6: 1650, 5: 1000, 4: 536, 3: 194, 2: 60, 1: 20}.get(p, 0)
+    model = {
+        "keys": ("hbm", 36.0 * n / hbm, "read x, y, z; write key, index"),
+        "sort": ("hbm", 24.0 * n / hbm, "read and write (key, index) once"),
+        "tree": ("hbm", (52.0 * n + 8.0 * n + 64.0 * cells) / hbm,
+                 "gather positions (read, write, index); read keys; write cell records"),
+        "gclimb": ("hbm", (20.0 * n + 32.0 * n + (8.0 * nm + 56.0) * cells) / hbm,
+                   "gather masses; read positions and masses once; write moments and cell data"),
+        "m2l": ("valu", m2l_flops * info["m2l_dir"] / fpeak,
+                "D tensors and the Eq. (25) contraction per directed interaction"),
+        "descent": ("hbm", (8.0 * nl * (cells + leaves)) / hbm,
+                    "read every cell's C once, write every leaf's"),
+        "p2p": ("valu", FLOPS_PER_INTERACTION * info["p2p_inter"] / fpeak,
+                "20 flop per directed moonlet pair"),
+        "l2p": ("hbm", (72.0 * n + 8.0 * nl * leaves) / hbm,
+                "read positions and direct sums, leaf C; write accelerations"),
+        "collide": ("hbm+valu", (124.0 * n) / hbm + 25.0 * info["col_tests"] / (PEAK_FP64_TFLOPS * 1e12),
+                    "gather velocities and radii, read the climb's inputs; 25 flop per pair test"),
+        "integrate": ("hbm", 84.0 * n / hbm, "a kick or a drift: about 84 B per moonlet"),
+    }
+    out, roof_sum, meas_sum = {}, 0.0, 0.0
+    for ph, (ms, cnt) in phases.items():
+        if cnt <= 0:
+            continue
+        per_call = ms / cnt / 1e3
+        meas_sum += ms
+        if ph not in model:
+            out[ph] = {"bound": "latency", "ms_per_call": per_call * 1e3}
+            continue
+        bound, t, basis = model[ph]
+        roof_sum += t * cnt * 1e3
+        out[ph] = {"bound": bound, "ms_per_call": per_call * 1e3, "roof_ms_per_call": t * 1e3,
+                   "frac": t / per_call if per_call > 0 else None, "basis": basis}
+    return out, (roof_sum / meas_sum if meas_sum > 0 else None)
+
+
 def _run_batched(nc, args, device):
     """The batched form: autotuned leaf size, then a 50-step ncorp_step_batched call
     captured in a hipGraph and replayed (the state keeps evolving across replays)."""
@@ -361,6 +411,8 @@ def main():
                             args.dt)
         cpu["cores"] = 1
 
+    phase_roof, step_frac = _phase_rooflines(ph, info, args.n, args.p, True)
+
     def phase_summary(r):
         if r is None or r["phases"] is None:
             return None
@@ -401,6 +453,8 @@ def main():
             "ms_per_step": r64["wall_s"] * 1e3 / args.steps, "errors": err64,
             "phases_ms_per_step": phase_summary(r64)},
         "phases_ms_per_step": phase_summary(r32),
+        "phase_rooflines": phase_roof,
+        "step_roofline_frac": step_frac,
         "tree": info,
         "collision_pairs_in_timed_steps": r32["pairs"],
         "batched": batched,
