@@ -23,6 +23,7 @@ struct ncorp_ctx {
     bool have_tree = false;
     int64_t n = 0;
     double clock = 0.0;                 // time of the next ncorp_step call
+    bool grav_lists = false;            // the gravity walk ran on the current tree
     hipStream_t last = nullptr;
     char err[256];
     // phase timing
@@ -357,6 +358,7 @@ static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const
         HIPCHK(c, launch_build_tree(ws, n, c->prm.leaf_size, s));
     }
     c->have_tree = true;
+    c->grav_lists = false;
     c->n = n;
     c->last = s;
     return NCORP_OK;
@@ -430,6 +432,7 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
         HIPCHK(c, launch_l2p(ws, n, c->prm.p, ax, ay, az, s));
     }
     if (c->timing) HIPCHK(c, launch_count_interactions(ws, s));
+    c->grav_lists = true;
     c->last = s;
     return NCORP_OK;
 }
@@ -453,7 +456,10 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
     PhaseTimer t(c, NCORP_PHASE_COLLIDE, s);
     HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
     HIPCHK(c, launch_collision_climb(ws, n, dt, s));
-    HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col, c->prm.ncc_post_col, s));
+    if (c->grav_lists)
+        HIPCHK(c, launch_candidates_from_lists(ws, s));
+    else
+        HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col, c->prm.ncc_post_col, s));
     HIPCHK(c, launch_collide_pairs(ws, n, dt, s));
     if (state && c->prm.collision_mode == NCORP_COLLISIONS_RESOLVE)
         HIPCHK(c, launch_resolve(ws, state[0], state[1], state[2], state[3], state[4], state[5],

@@ -9,6 +9,17 @@
 
 namespace ncorp {
 
+__device__ __forceinline__ int wave_excl_sum_c(int v, int lane, int &total) {
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(x, o);
+        if (lane >= o) x += t;
+    }
+    total = __shfl(x, kWave - 1);
+    return x - v;
+}
+
 // contact time dt_c of Eq. (2) when 0 <= dt_c <= dt, else -1
 __device__ __forceinline__ double contact_time(double x1, double y1, double z1, double vx1,
                                                double vy1, double vz1, double R1, double x2,
@@ -309,6 +320,111 @@ __global__ void k_pairs_done(DevState *st, int64_t *n_pairs_dev, int64_t cap, in
         atomicMax((unsigned long long *)&st->required, (unsigned long long)(base + n));
     }
     if (triple) *cursor = base + n;
+}
+
+// ---------------------------------------------------------------- candidates
+// Collision candidates from the gravity walk of the same tree.  That walk splits
+// the set of all moonlet pairs into its interactions exactly once each (well-
+// separated cell pairs, direct-sum cell pairs, direct-sum self cells).  A moonlet
+// pair of an interaction (A, B) can collide only if the collision spheres of the
+// two leaves holding them overlap (Eqs. 8-9 bound every moonlet's reach by its
+// leaf's r_crit), and, for a well-separated pair, only if the spheres of A and B
+// themselves overlap.  So the leaf pairs of all interactions whose spheres overlap
+// (and every leaf with two moonlets or more, with itself) are candidates covering
+// every colliding pair exactly once: the pair set is the collision walk's.  The
+// spheres are compared with a relative margin of 1e-9, far above rounding.
+__device__ __forceinline__ bool spheres_meet(const double4 &a, const double4 &b) {
+    const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    const double rs = (a.w + b.w) * (1.0 + 1e-9);
+    return dx * dx + dy * dy + dz * dz < rs * rs;
+}
+
+// Counts (out == nullptr) or writes the candidate leaf pairs of one interaction.
+__device__ __forceinline__ int leaf_candidates(int2 pr, bool separated,
+                                               const double4 *__restrict__ ccell,
+                                               const int32_t *__restrict__ c_entry,
+                                               const int32_t *__restrict__ c_nent,
+                                               const int32_t *__restrict__ c_count,
+                                               const int32_t *__restrict__ ent_cell, int2 *out,
+                                               int64_t pos, int64_t cap) {
+    if (pr.x < 0) return 0;
+    if (separated && !spheres_meet(ccell[pr.x], ccell[pr.y])) return 0;
+    const bool self = pr.x == pr.y;
+    const int ea = c_entry[pr.x], na = c_nent[pr.x];
+    const int eb = c_entry[pr.y], nb = c_nent[pr.y];
+    int k = 0;
+    for (int i = 0; i < na; i++) {
+        const int la = ent_cell[ea + i];
+        const double4 sa = ccell[la];
+        for (int j = self ? i : 0; j < nb; j++) {
+            const int lb = ent_cell[eb + j];
+            const bool take = la == lb ? c_count[la] > 1 : spheres_meet(sa, ccell[lb]);
+            if (!take) continue;
+            if (out && pos + k < cap) out[pos + k] = make_int2(la, lb);
+            k++;
+        }
+    }
+    return k;
+}
+
+constexpr int kCandBlock = 256;
+
+__global__ void __launch_bounds__(kCandBlock)
+k_cand_from_lists(DevState *st, const int2 *__restrict__ m2l, int64_t m2l_cap,
+                  const int2 *__restrict__ p2p, int64_t p2p_cap,
+                  const double4 *__restrict__ ccell, const int32_t *__restrict__ c_entry,
+                  const int32_t *__restrict__ c_nent, const int32_t *__restrict__ c_count,
+                  const int32_t *__restrict__ ent_cell, int2 *cand, int64_t cand_cap) {
+    __shared__ int wtot[kCandBlock / kWave];
+    __shared__ int s_base;
+    if (st->status & kSkipMask) return;
+    const int64_t nm = st->m2l_slots < m2l_cap ? st->m2l_slots : m2l_cap;
+    const int64_t np = st->p2p_slots < p2p_cap ? st->p2p_slots : p2p_cap;
+    const int64_t total = nm + np;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    for (int64_t q0 = (int64_t)blockIdx.x * kCandBlock; q0 < total;
+         q0 += (int64_t)gridDim.x * kCandBlock) {
+        const int64_t q = q0 + threadIdx.x;
+        int2 pr = make_int2(-1, -1);
+        const bool sep = q < nm;
+        if (q < total) pr = sep ? m2l[q] : p2p[q - nm];        // gaps are (-1, -1)
+        const int cnt = leaf_candidates(pr, sep, ccell, c_entry, c_nent, c_count, ent_cell,
+                                        nullptr, 0, 0);
+        int tot;
+        const int off = wave_excl_sum_c(cnt, lane, tot);
+        if (lane == 0) wtot[w] = tot;
+        __syncthreads();
+        int before = 0, all = 0;
+        for (int k = 0; k < kCandBlock / kWave; k++) {
+            if (k < w) before += wtot[k];
+            all += wtot[k];
+        }
+        if (threadIdx.x == 0) {
+            s_base = all ? atomicAdd(&st->cand_slots, all) : 0;
+            if (all) atomicAdd(&st->ncand, all);
+        }
+        __syncthreads();
+        const int64_t pos = (int64_t)s_base + before + off;
+        if (cnt) leaf_candidates(pr, sep, ccell, c_entry, c_nent, c_count, ent_cell, cand, pos,
+                                 cand_cap);
+        if (cnt && pos + cnt > cand_cap) {
+            atomicOr(&st->status, (int32_t)ST_CAP_P2P);
+            atomicMax((unsigned long long *)&st->required, (unsigned long long)(pos + cnt));
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_cand_init(DevState *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) { st->ncand = 0; st->cand_slots = 0; }
+}
+
+hipError_t launch_candidates_from_lists(const Workspace &ws, hipStream_t s) {
+    k_cand_init<<<1, 64, 0, s>>>(ws.st);
+    k_cand_from_lists<<<1024, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap,
+                                                  ws.ccell, ws.c_entry, ws.c_nent, ws.c_count,
+                                                  ws.ent_cell, ws.cand, ws.p2p_cap);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- resolution

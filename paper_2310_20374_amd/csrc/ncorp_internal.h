@@ -272,6 +272,9 @@ hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t
 hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,
                       hipStream_t s);
 hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipStream_t s);
+// collision candidates from the gravity walk's lists of the same tree (in place of
+// the collision walk)
+hipError_t launch_candidates_from_lists(const Workspace &ws, hipStream_t s);
 hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,
                              int64_t *n_pairs_dev, int triple, int step, int64_t *cursor,
                              hipStream_t s);

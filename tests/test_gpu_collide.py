@@ -61,3 +61,36 @@ def test_pair_capacity_overflow_is_reported(nc):
     ctx.collide(t["vx"], t["vy"], t["vz"], t["R"], 0.01, pairs, npairs)
     r, req, _ = ctx.get_status()
     assert r == nc.E_CAPACITY and req == int(npairs.item()) > 3
+
+
+@pytest.mark.parametrize("case", ["gas2k", "hot3k", "clumps2e4", "clumps2e4_s52", "disk3k_dt2"])
+@pytest.mark.parametrize("p", [3, 6])
+def test_pairs_after_gravity_equal_brute_force(nc, orc, case, p):
+    """After a gravity evaluation on the same tree the candidates come from the gravity
+    walk's interaction lists instead of the collision walk: the pair set is still
+    exactly the brute-force one, and every candidate leaf pair is a pair of leaves."""
+    import torch
+    gen, dt, s = CASES[case]
+    d = gen()
+    print(f"case {case} p={p}", flush=True)
+    prm = nc.params_default(p, leaf_size=s)
+    n = len(d["x"])
+    cap = 1 << 18
+    ctx = nc.Context(prm, n, pair_capacity=cap)
+    t = {k: torch.tensor(v, device="cuda:0") for k, v in d.items()}
+    a = [torch.empty(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    pairs = torch.zeros((cap, 2), dtype=torch.int64, device="cuda:0")
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    ctx.build_tree(t["x"], t["y"], t["z"])
+    ctx.gravity(t["m"], *a)
+    ctx.collide(t["vx"], t["vy"], t["vz"], t["R"], dt, pairs, npairs)
+    torch.cuda.synchronize()
+    ctx.check_status()
+    got = pairs[: int(npairs.item())].cpu().numpy()
+    assert np.array_equal(got, orc.pairs_brute(d, dt))
+    cells = ctx.export("cells")
+    cand = ctx.export("col_cand")
+    assert len(cand) > 0
+    assert np.all(cells[cand[:, 0], 4] == 0) and np.all(cells[cand[:, 1], 4] == 0)
+    key = np.sort(cand.astype(np.int64), axis=1)
+    assert len(np.unique(key[:, 0] * (1 << 32) + key[:, 1])) == len(key)
