@@ -291,6 +291,7 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.pair_flag = (int32_t *)take(4 * ws.pair_cap);
     ws.mbest = (int32_t *)take(4 * n);
     ws.mmatch = (int32_t *)take(4 * n);
+    ws.cand_blk = (int32_t *)take(4 * 8192);
     ws.bytes = off;
     return off;
 }

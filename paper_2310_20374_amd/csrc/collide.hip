@@ -356,74 +356,159 @@ __device__ __forceinline__ int leaf_candidates(int2 pr, bool separated,
     for (int i = 0; i < na; i++) {
         const int la = ent_cell[ea + i];
         const double4 sa = ccell[la];
-        for (int j = self ? i : 0; j < nb; j++) {
-            const int lb = ent_cell[eb + j];
-            const bool take = la == lb ? c_count[la] > 1 : spheres_meet(sa, ccell[lb]);
-            if (!take) continue;
-            if (out && pos + k < cap) out[pos + k] = make_int2(la, lb);
-            k++;
+        // four leaves of B at a time: their loads are independent of each other
+        for (int j0 = self ? i : 0; j0 < nb; j0 += 4) {
+            int lb[4];
+            double4 sb[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) lb[u] = j0 + u < nb ? ent_cell[eb + j0 + u] : la;
+#pragma unroll
+            for (int u = 0; u < 4; u++) sb[u] = ccell[lb[u]];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (j0 + u >= nb) continue;
+                const bool take = la == lb[u] ? c_count[la] > 1 : spheres_meet(sa, sb[u]);
+                if (!take) continue;
+                if (out && pos + k < cap) out[pos + k] = make_int2(la, lb[u]);
+                k++;
+            }
         }
     }
     return k;
 }
 
 constexpr int kCandBlock = 256;
+constexpr int kCandGrid = 8192;
+
+// The candidates are counted per block, the block counts scanned, and the blocks
+// write their candidates at their offsets: no contended atomics, no gaps.  Block b
+// takes list slots (r * grid + b) * kCandBlock + t, r = 0, 1, ... in both passes.
+struct CandLists {
+    const int2 *m2l, *p2p;
+    int64_t nm, total;
+};
+
+__device__ __forceinline__ CandLists cand_lists(const DevState *st, const int2 *m2l,
+                                                int64_t m2l_cap, const int2 *p2p,
+                                                int64_t p2p_cap) {
+    CandLists L;
+    L.m2l = m2l;
+    L.p2p = p2p;
+    L.nm = st->m2l_slots < m2l_cap ? st->m2l_slots : m2l_cap;
+    const int64_t np = st->p2p_slots < p2p_cap ? st->p2p_slots : p2p_cap;
+    L.total = L.nm + np;
+    return L;
+}
+
+// block-wide exclusive prefix of v (kCandBlock threads); returns the block total
+__device__ __forceinline__ int block_excl(int v, int &excl, int *wtot) {
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int tot;
+    const int off = wave_excl_sum_c(v, lane, tot);
+    if (lane == 0) wtot[w] = tot;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int k = 0; k < kCandBlock / kWave; k++) {
+        if (k < w) before += wtot[k];
+        all += wtot[k];
+    }
+    __syncthreads();
+    excl = before + off;
+    return all;
+}
 
 __global__ void __launch_bounds__(kCandBlock)
-k_cand_from_lists(DevState *st, const int2 *__restrict__ m2l, int64_t m2l_cap,
-                  const int2 *__restrict__ p2p, int64_t p2p_cap,
-                  const double4 *__restrict__ ccell, const int32_t *__restrict__ c_entry,
-                  const int32_t *__restrict__ c_nent, const int32_t *__restrict__ c_count,
-                  const int32_t *__restrict__ ent_cell, int2 *cand, int64_t cand_cap) {
+k_cand_count(const DevState *__restrict__ st, const int2 *__restrict__ m2l, int64_t m2l_cap,
+             const int2 *__restrict__ p2p, int64_t p2p_cap, const double4 *__restrict__ ccell,
+             const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent,
+             const int32_t *__restrict__ c_count, const int32_t *__restrict__ ent_cell,
+             int32_t *__restrict__ blk) {
     __shared__ int wtot[kCandBlock / kWave];
-    __shared__ int s_base;
-    if (st->status & kSkipMask) return;
-    const int64_t nm = st->m2l_slots < m2l_cap ? st->m2l_slots : m2l_cap;
-    const int64_t np = st->p2p_slots < p2p_cap ? st->p2p_slots : p2p_cap;
-    const int64_t total = nm + np;
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    for (int64_t q0 = (int64_t)blockIdx.x * kCandBlock; q0 < total;
+    const CandLists L = cand_lists(st, m2l, m2l_cap, p2p, p2p_cap);
+    const bool skip = (st->status & kSkipMask) != 0;
+    int sum = 0;
+    for (int64_t q0 = (int64_t)blockIdx.x * kCandBlock; q0 < L.total && !skip;
          q0 += (int64_t)gridDim.x * kCandBlock) {
         const int64_t q = q0 + threadIdx.x;
         int2 pr = make_int2(-1, -1);
-        const bool sep = q < nm;
-        if (q < total) pr = sep ? m2l[q] : p2p[q - nm];        // gaps are (-1, -1)
+        const bool sep = q < L.nm;
+        if (q < L.total) pr = sep ? L.m2l[q] : L.p2p[q - L.nm];        // gaps are (-1, -1)
         const int cnt = leaf_candidates(pr, sep, ccell, c_entry, c_nent, c_count, ent_cell,
                                         nullptr, 0, 0);
-        int tot;
-        const int off = wave_excl_sum_c(cnt, lane, tot);
-        if (lane == 0) wtot[w] = tot;
+        int excl;
+        sum += block_excl(cnt, excl, wtot);
+    }
+    if (threadIdx.x == 0) blk[blockIdx.x] = sum;
+}
+
+// exclusive scan of the block counts (one block); the total is the candidate count
+__global__ void __launch_bounds__(1024) k_cand_scan(DevState *st, int32_t *blk, int nb) {
+    __shared__ int32_t sh[1024];
+    int32_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int i = b0 + threadIdx.x;
+        const int32_t x = i < nb ? blk[i] : 0;
+        sh[threadIdx.x] = x;
         __syncthreads();
-        int before = 0, all = 0;
-        for (int k = 0; k < kCandBlock / kWave; k++) {
-            if (k < w) before += wtot[k];
-            all += wtot[k];
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            s_base = all ? atomicAdd(&st->cand_slots, all) : 0;
-            if (all) atomicAdd(&st->ncand, all);
-        }
+        if (i < nb) blk[i] = carry + sh[threadIdx.x] - x;
+        carry += sh[1023];
         __syncthreads();
-        const int64_t pos = (int64_t)s_base + before + off;
+    }
+    if (threadIdx.x == 0) {
+        st->ncand = carry;
+        st->cand_slots = carry;
+    }
+}
+
+__global__ void __launch_bounds__(kCandBlock)
+k_cand_write(DevState *st, const int2 *__restrict__ m2l, int64_t m2l_cap,
+             const int2 *__restrict__ p2p, int64_t p2p_cap, const double4 *__restrict__ ccell,
+             const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent,
+             const int32_t *__restrict__ c_count, const int32_t *__restrict__ ent_cell,
+             const int32_t *__restrict__ blk, int2 *cand, int64_t cand_cap) {
+    __shared__ int wtot[kCandBlock / kWave];
+    if (st->status & kSkipMask) return;
+    const CandLists L = cand_lists(st, m2l, m2l_cap, p2p, p2p_cap);
+    int64_t run = blk[blockIdx.x];
+    for (int64_t q0 = (int64_t)blockIdx.x * kCandBlock; q0 < L.total;
+         q0 += (int64_t)gridDim.x * kCandBlock) {
+        const int64_t q = q0 + threadIdx.x;
+        int2 pr = make_int2(-1, -1);
+        const bool sep = q < L.nm;
+        if (q < L.total) pr = sep ? L.m2l[q] : L.p2p[q - L.nm];
+        const int cnt = leaf_candidates(pr, sep, ccell, c_entry, c_nent, c_count, ent_cell,
+                                        nullptr, 0, 0);
+        int excl;
+        const int all = block_excl(cnt, excl, wtot);
+        const int64_t pos = run + excl;
         if (cnt) leaf_candidates(pr, sep, ccell, c_entry, c_nent, c_count, ent_cell, cand, pos,
                                  cand_cap);
         if (cnt && pos + cnt > cand_cap) {
             atomicOr(&st->status, (int32_t)ST_CAP_P2P);
             atomicMax((unsigned long long *)&st->required, (unsigned long long)(pos + cnt));
         }
-        __syncthreads();
+        run += all;
     }
 }
 
-__global__ void k_cand_init(DevState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) { st->ncand = 0; st->cand_slots = 0; }
-}
-
 hipError_t launch_candidates_from_lists(const Workspace &ws, hipStream_t s) {
-    k_cand_init<<<1, 64, 0, s>>>(ws.st);
-    k_cand_from_lists<<<1024, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap,
-                                                  ws.ccell, ws.c_entry, ws.c_nent, ws.c_count,
-                                                  ws.ent_cell, ws.cand, ws.p2p_cap);
+    // one pass of blocks over the list slots when the lists are short enough
+    int64_t g = (ws.m2l_cap + ws.p2p_cap + kCandBlock - 1) / kCandBlock;
+    if (g > kCandGrid) g = kCandGrid;
+    if (g < 1) g = 1;
+    k_cand_count<<<(int)g, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap,
+                                               ws.ccell, ws.c_entry, ws.c_nent, ws.c_count,
+                                               ws.ent_cell, ws.cand_blk);
+    k_cand_scan<<<1, 1024, 0, s>>>(ws.st, ws.cand_blk, (int)g);
+    k_cand_write<<<(int)g, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap,
+                                               ws.ccell, ws.c_entry, ws.c_nent, ws.c_count,
+                                               ws.ent_cell, ws.cand_blk, ws.cand, ws.p2p_cap);
     return hipGetLastError();
 }
 

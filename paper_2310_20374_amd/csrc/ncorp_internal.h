@@ -215,6 +215,7 @@ struct Workspace {
     double *pair_dt = nullptr;
     int32_t *pair_flag = nullptr;
     int32_t *mbest = nullptr, *mmatch = nullptr;
+    int32_t *cand_blk = nullptr;                      // per-block candidate counts
     // scratch for scans and sorts
     int32_t *scan_part = nullptr;                     // block partials
     uint32_t *hist = nullptr;                         // radix histograms
