@@ -50,6 +50,8 @@ def lib():
     L.orc_resolve.restype = i64
     L.orc_resolve.argtypes = [i64, _i64, i64, _f64, _f64, _f64, _f64, _f64, _f64, _f64, _f64,
                               d, d, _i32]
+    L.orc_grav_run_std.restype = None
+    L.orc_grav_run_std.argtypes = [vp, i32, i32]
     L.orc_root_half_width.restype = d
     L.orc_root_half_width.argtypes = [_f64, _f64, _f64, i64]
     L.orc_quantize.restype = C.c_uint32
@@ -256,6 +258,11 @@ class Gravity:
         lib().orc_grav_run(self._h, ncs, ncc_pre, ncc_post)
         return self
 
+    def run_standard(self, ncb_pre: int, ncb_post: int):
+        """The standard tree code (Alg. 1) instead of the falcON walk."""
+        lib().orc_grav_run_std(self._h, ncb_pre, ncb_post)
+        return self
+
     def accel(self) -> np.ndarray:
         n = self.tree.n
         ax, ay, az = np.zeros(n), np.zeros(n), np.zeros(n)
@@ -407,6 +414,14 @@ def tree_accel(d: dict, G=1.0, p=3, theta_min=0.5, s=16, ncs=64, ncc_pre=8, ncc_
     """Mutual accelerations by the oracle falcON tree, input order."""
     t = Tree(d["x"], d["y"], d["z"], s, L)
     g = Gravity(t, d["m"], G, p, theta_min, theta_mode).run(ncs, ncc_pre, ncc_post)
+    return g.accel(), t, g
+
+
+def standard_tree_accel(d: dict, G=1.0, p=3, theta_min=0.5, s=102, ncb_pre=6, ncb_post=16,
+                        theta_mode=0, L=None):
+    """Mutual accelerations by the oracle's standard tree code (Alg. 1), input order."""
+    t = Tree(d["x"], d["y"], d["z"], s, L)
+    g = Gravity(t, d["m"], G, p, theta_min, theta_mode).run_standard(ncb_pre, ncb_post)
     return g.accel(), t, g
 
 

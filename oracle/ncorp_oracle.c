@@ -905,6 +905,67 @@ void orc_grav_run(orc_grav *g, int ncs, int ncc_pre, int ncc_post)
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* Standard tree code (Alg. 1, Sect. 3.4.4): every moonlet walks the tree from  */
+/* the root on its own.  A cell B with fewer than N_cb,pre moonlets is summed   */
+/* directly; a cell well separated from the moonlet (|x - s_B| >= r_crit,B)     */
+/* contributes C^(1)(x) = sum_{n=0, n!=1}^{p-1} (-1)^n/n! grad^(n+1) g(R) (.)   */
+/* M^(n)_B with R = x - s_B; a leaf or a cell with fewer than N_cb,post moonlets */
+/* is summed directly; otherwise the walk goes on into B's children.            */
+/* ------------------------------------------------------------------------- */
+static void std_walk(orc_grav *g, int64_t k, int64_t B, int ncb_pre, int ncb_post, double *acc)
+{
+    const orc_tree *t = g->t;
+    const int64_t Nb = t->count[B];
+    const double x[3] = {g->xs[k], g->ys[k], g->zs[k]};
+    int direct = 0;
+    if (Nb < (int64_t)ncb_pre) {
+        direct = 1;
+    } else if (dist3(x, &g->s[3 * B]) >= g->rcrit[B]) {
+        int p = g->p;
+        double R[3] = {x[0] - g->s[3 * B], x[1] - g->s[3 * B + 1], x[2] - g->s[3 * B + 2]};
+        double sym[JD * JD * JD];
+        orc_green_derivs(R, p, sym);
+        static double Dfull[ORC_MAXP + 1][729];
+        for (int q = 1; q <= p; q++) full_from_sym(sym, q, Dfull[q]);
+        for (int nn = 0; nn <= p - 1; nn++) {
+            if (nn == 1) continue;
+            double w = ((nn & 1) ? -1.0 : 1.0) / fact(nn);
+            inner_acc(Dfull[nn + 1], nn + 1, g->M[B] + g->moff[nn], 1, w, acc);
+        }
+        return;
+    } else if (Nb < (int64_t)ncb_post || is_leaf(t, B)) {
+        direct = 1;
+    }
+    if (direct) {
+        for (int64_t j = t->first[B]; j < t->first[B] + Nb; j++) {
+            double dx = g->xs[j] - x[0], dy = g->ys[j] - x[1], dz = g->zs[j] - x[2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2), r3 = r2 * r;
+            acc[0] += g->mu[j] * dx / r3;
+            acc[1] += g->mu[j] * dy / r3;
+            acc[2] += g->mu[j] * dz / r3;
+        }
+        return;
+    }
+    for (int64_t b = t->child_first[B]; b < t->child_first[B] + t->nchild[B]; b++)
+        std_walk(g, k, b, ncb_pre, ncb_post, acc);
+}
+
+/* Accelerations by the standard tree code, replacing the falcON ones of g
+ * (input order through orc_grav_accel).  p = 0: no mutual gravity. */
+void orc_grav_run_std(orc_grav *g, int ncb_pre, int ncb_post)
+{
+    for (int64_t k = 0; k < g->n; k++) { g->ax[k] = 0.0; g->ay[k] = 0.0; g->az[k] = 0.0; }
+    if (g->p == 0) return;
+    for (int64_t k = 0; k < g->n; k++) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        std_walk(g, k, 0, ncb_pre, ncb_post, acc);
+        g->ax[k] = acc[0]; g->ay[k] = acc[1]; g->az[k] = acc[2];
+    }
+}
+
 void orc_grav_accel(const orc_grav *g, double *ax, double *ay, double *az)
 {
     for (int64_t k = 0; k < g->n; k++) {
