@@ -103,9 +103,22 @@ typedef struct {
     double J2, R_central;
     double M_sun, a_sun, obliquity;
     double t_start;
+    /* gravity method (Sect. 3.4): NCORP_GRAVITY_FALCON (0, default) is the dual
+     * walk of Alg. 2 with its cell-cell terms; NCORP_GRAVITY_STANDARD_TREE (1) is
+     * the standard tree code of Alg. 1: every moonlet walks the tree from its root
+     * on its own, a cell B with fewer than ncb_pre moonlets is summed directly, a
+     * cell with |x - s_B| >= r_crit,B contributes its cell-moonlet C^(1) term
+     * (orders 0 and 2..p-1 of the multipoles), a cell with fewer than ncb_post
+     * moonlets or a leaf is summed directly, and any other cell is opened.  The
+     * standard tree computes in FP64 whatever `precision` says, keeps no
+     * interaction lists, and leaves collision search to the collision walk.
+     * Paper settings: leaf_size 102, ncb_pre 6, ncb_post 16 (Sect. 6). */
+    int32_t gravity_method;
+    int32_t ncb_pre, ncb_post;
 } ncorp_params;
 
 enum { NCORP_COLLISIONS_REPORT = 0, NCORP_COLLISIONS_RESOLVE = 1 };
+enum { NCORP_GRAVITY_FALCON = 0, NCORP_GRAVITY_STANDARD_TREE = 1 };
 
 typedef struct ncorp_ctx ncorp_ctx;
 

@@ -908,7 +908,9 @@ void orc_grav_run(orc_grav *g, int ncs, int ncc_pre, int ncc_post)
 /* ------------------------------------------------------------------------- */
 /* Standard tree code (Alg. 1, Sect. 3.4.4): every moonlet walks the tree from  */
 /* the root on its own.  A cell B with fewer than N_cb,pre moonlets is summed   */
-/* directly; a cell well separated from the moonlet (|x - s_B| >= r_crit,B)     */
+/* directly; a cell well separated from the moonlet (|x - s_B| >= r_crit,B, and */
+/* x != s_B: a cell whose moonlets all sit at x, r_crit = 0, is not separated   */
+/* from a moonlet there, where C^(1) would be singular)                          */
 /* contributes C^(1)(x) = sum_{n=0, n!=1}^{p-1} (-1)^n/n! grad^(n+1) g(R) (.)   */
 /* M^(n)_B with R = x - s_B; a leaf or a cell with fewer than N_cb,post moonlets */
 /* is summed directly; otherwise the walk goes on into B's children.            */
@@ -921,7 +923,7 @@ static void std_walk(orc_grav *g, int64_t k, int64_t B, int ncb_pre, int ncb_pos
     int direct = 0;
     if (Nb < (int64_t)ncb_pre) {
         direct = 1;
-    } else if (dist3(x, &g->s[3 * B]) >= g->rcrit[B]) {
+    } else if (dist3(x, &g->s[3 * B]) >= g->rcrit[B] && dist3(x, &g->s[3 * B]) > 0.0) {
         int p = g->p;
         double R[3] = {x[0] - g->s[3 * B], x[1] - g->s[3 * B + 1], x[2] - g->s[3 * B + 2]};
         double sym[JD * JD * JD];

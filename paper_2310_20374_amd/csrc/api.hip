@@ -138,6 +138,13 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
         std::snprintf(why, len, "M_sun >= 0 (then a_sun > 0), finite obliquity and t_start");
         return false;
     }
+    if (p->gravity_method != NCORP_GRAVITY_FALCON &&
+        p->gravity_method != NCORP_GRAVITY_STANDARD_TREE) {
+        std::snprintf(why, len, "gravity_method must be 0 or 1"); return false;
+    }
+    if (p->ncb_pre < 0 || p->ncb_post < 0) {
+        std::snprintf(why, len, "ncb_pre and ncb_post must be >= 0"); return false;
+    }
     return true;
 }
 
@@ -162,6 +169,9 @@ extern "C" int ncorp_params_default(ncorp_params *o, int p) {
     o->a_sun = 0.0;
     o->obliquity = 0.0;
     o->t_start = 0.0;
+    o->gravity_method = NCORP_GRAVITY_FALCON;
+    o->ncb_pre = 6;
+    o->ncb_post = 16;
     return NCORP_OK;
 }
 
@@ -410,6 +420,14 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
         PhaseTimer t(c, NCORP_PHASE_GCLIMB, s);
         HIPCHK(c, launch_gather_scaled(ws, m, c->prm.G, ws.mus, n, s));
         HIPCHK(c, launch_gravity_climb(ws, n, c->prm, s));
+    }
+    if (c->prm.gravity_method == NCORP_GRAVITY_STANDARD_TREE) {
+        PhaseTimer t(c, NCORP_PHASE_GWALK, s);
+        HIPCHK(c, launch_standard_tree(ws, n, c->prm.p, c->prm.ncb_pre, c->prm.ncb_post, ax, ay,
+                                       az, s));
+        c->grav_lists = false;
+        c->last = s;
+        return NCORP_OK;
     }
     {
         PhaseTimer t(c, NCORP_PHASE_GWALK, s);

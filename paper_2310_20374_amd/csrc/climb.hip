@@ -372,7 +372,7 @@ __global__ void k_rcrit(const DevState *__restrict__ st, const double *__restric
         WCell w;
         w.x = g.x; w.y = g.y; w.z = g.z; w.rcrit = rc;
         w.count = c_count[c]; w.child = c_child[c]; w.nchild = c_nchild[c];
-        w.entry = c_entry[c]; w.nent = c_nent[c]; w.pad[0] = w.pad[1] = w.pad[2] = 0;
+        w.entry = c_entry[c]; w.nent = c_nent[c]; w.first = c_first[c]; w.pad[0] = w.pad[1] = 0;
         wg[c] = w;
     }
 }
@@ -382,7 +382,8 @@ __global__ void k_pack_collision(const DevState *__restrict__ st, const double4 
                                  const int32_t *__restrict__ c_child,
                                  const int32_t *__restrict__ c_nchild, WCell *__restrict__ wc,
                                  const int32_t *__restrict__ c_entry,
-                                 const int32_t *__restrict__ c_nent) {
+                                 const int32_t *__restrict__ c_nent,
+                                 const int32_t *__restrict__ c_first) {
     const int nc = st->ncells;
     if (st->status & kSkipMask) return;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
@@ -390,7 +391,7 @@ __global__ void k_pack_collision(const DevState *__restrict__ st, const double4 
         WCell w;
         w.x = g.x; w.y = g.y; w.z = g.z; w.rcrit = g.w;
         w.count = c_count[c]; w.child = c_child[c]; w.nchild = c_nchild[c];
-        w.entry = c_entry[c]; w.nent = c_nent[c]; w.pad[0] = w.pad[1] = w.pad[2] = 0;
+        w.entry = c_entry[c]; w.nent = c_nent[c]; w.first = c_first[c]; w.pad[0] = w.pad[1] = 0;
         wc[c] = w;
     }
 }
@@ -550,7 +551,7 @@ hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hip
         ws.c_crmax, ws.ndisks > 1 ? ws.seg : nullptr, ws.disk_L, ws.pcol);
     k_pack_collision<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.ccell, ws.c_count,
                                                                  ws.c_child, ws.c_nchild, ws.wc,
-                                                                 ws.c_entry, ws.c_nent);
+                                                                 ws.c_entry, ws.c_nent, ws.c_first);
     return hipGetLastError();
 }
 

@@ -125,7 +125,7 @@ struct WalkQueue {
 // number of leaves below it.
 struct alignas(64) WCell {
     double x, y, z, rcrit;
-    int32_t count, child, nchild, entry, nent, pad[3];
+    int32_t count, child, nchild, entry, nent, first, pad[2];
 };
 
 // Waves of a multi-wave block that work independently synchronise their own LDS
@@ -272,6 +272,9 @@ hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s);
 hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s);
 hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,
                       hipStream_t s);
+// standard tree code (Alg. 1): accelerations of all moonlets, input order
+hipError_t launch_standard_tree(const Workspace &ws, int64_t n, int p, int ncb_pre, int ncb_post,
+                                double *ax, double *ay, double *az, hipStream_t s);
 hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipStream_t s);
 // collision candidates from the gravity walk's lists of the same tree (in place of
 // the collision walk)

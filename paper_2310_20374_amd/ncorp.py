@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libncorp.so")
 OK, E_INVALID, E_CAPACITY, E_HIP, E_UNSUPPORTED, E_NONFINITE = 0, -1, -2, -3, -4, -5
 FP64, FP32_BULK = 0, 1
 COLLISIONS_REPORT, COLLISIONS_RESOLVE = 0, 1
+GRAVITY_FALCON, GRAVITY_STANDARD_TREE = 0, 1
 STATUS_NAMES = {0: "ok", -1: "invalid", -2: "capacity", -3: "hip", -4: "unsupported",
                 -5: "nonfinite"}
 
@@ -47,6 +48,7 @@ class Params(C.Structure):
         ("collision_mode", C.c_int32), ("collision_f", C.c_double),
         ("J2", C.c_double), ("R_central", C.c_double), ("M_sun", C.c_double),
         ("a_sun", C.c_double), ("obliquity", C.c_double), ("t_start", C.c_double),
+        ("gravity_method", C.c_int32), ("ncb_pre", C.c_int32), ("ncb_post", C.c_int32),
     ]
 
     def as_dict(self):

@@ -95,3 +95,15 @@ def test_thresholds_do_not_change_far_field_exactness(orc, pre, post):
     a, _, _ = orc.standard_tree_accel(d, p=6, theta_min=0.2, theta_mode=1, ncb_pre=pre,
                                       ncb_post=post)
     assert np.median(_rel(a, ex)) < 1e-6
+
+
+def test_zero_thresholds_stay_finite(orc):
+    """N_cb,pre = N_cb,post = 0 on small leaves: single-moonlet cells have r_crit = 0
+    and are not separated from their own moonlet (reading of the MAC at x = s_B);
+    the result is finite and as precise as with the paper's thresholds."""
+    d = inputs.hot_disk(3000, seed=2)
+    ex = orc.direct_sum(d["x"], d["y"], d["z"], d["m"])
+    a, _, _ = orc.standard_tree_accel(d, p=5, s=8, ncb_pre=0, ncb_post=0)
+    assert np.all(np.isfinite(a))
+    b, _, _ = orc.standard_tree_accel(d, p=5, s=8)
+    assert np.median(_rel(a, ex)) < 3 * np.median(_rel(b, ex))
