@@ -113,6 +113,46 @@ def _run(nc, prm, d, dt, steps, warmup, timing, device):
     return {"wall_s": wall, "phases": phases, "info": info, "acc": acc, "pairs": n_pairs}
 
 
+def _gravity_method_comparison(nc, d, p_list, reps, device):
+    """One tree build plus one gravity evaluation by falcON (Alg. 2, default thresholds,
+    FP64) and by the standard tree code (Alg. 1, leaf size 102, N_cb,pre 6, N_cb,post
+    16: the settings of the paper's speed comparison), at each order in p_list."""
+    import torch
+    n = len(d["x"])
+    t = {k: torch.tensor(d[k], device=device) for k in ("x", "y", "z", "m")}
+    a = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(3)]
+    out = {}
+    for p in p_list:
+        for name, prm in (("falcon", nc.params_default(p)),
+                          ("standard_tree", nc.params_default(
+                              p, leaf_size=102, gravity_method=nc.GRAVITY_STANDARD_TREE,
+                              ncb_pre=6, ncb_post=16))):
+            ctx = nc.Context(prm, n, pair_capacity=1 << 10, device=device)
+
+            def once():
+                ctx.build_tree(t["x"], t["y"], t["z"])
+                ctx.gravity(t["m"], *a)
+
+            once()
+            torch.cuda.synchronize()
+            ctx.check_status()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                once()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            ctx.check_status()
+            ctx.set_timing(True)
+            once()
+            torch.cuda.synchronize()
+            ph = {k: round(v[0], 4) for k, v in ctx.phase_times().items() if v[1] > 0}
+            out[f"{name}_p{p}"] = {"ms_tree_and_gravity": ms, "phases_ms": ph,
+                                   "leaf_size": prm.leaf_size,
+                                   "acc": torch.stack(a, 1).cpu().numpy()}
+            del ctx
+    return out
+
+
 def _errors(orc, d, acc, samples):
     import numpy as np
     from paper_2310_20374_amd import inputs
@@ -322,6 +362,9 @@ def main():
                     help="resolve the pairs found elastically (f = 2, as in the paper's timing "
                          "runs, keeping N constant) or only report them")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-method-comparison", action="store_true",
+                    help="skip the falcON / standard tree comparison (one gravity evaluation "
+                         "each at p = 3 and at --p)")
     ap.add_argument("--batched-only", action="store_true",
                     help="measure only the batched form (its object is printed alone)")
     ap.add_argument("--batched-steps", type=int, default=50)
@@ -379,6 +422,13 @@ def main():
               f"{batched['eager_ms_per_step']:.3f} eager, s={batched['leaf_size']}",
               file=sys.stderr, flush=True)
 
+    methods = None
+    if not args.no_method_comparison:
+        methods = _gravity_method_comparison(ncorp, d, sorted({3, args.p}), 5, device)
+        print("# gravity methods: " + ", ".join(
+            f"{k} {v['ms_tree_and_gravity']:.3f} ms" for k, v in methods.items()),
+            file=sys.stderr, flush=True)
+
     orc = None
     if not (args.no_errors and args.no_cpu_baseline):
         import oracle as orc
@@ -388,6 +438,14 @@ def main():
         if r64 is not None:
             err64 = _errors(orc, d, r64["acc"], args.samples)
         print(f"# errors fp32 {err32} fp64 {err64}", file=sys.stderr, flush=True)
+    if methods is not None:
+        for v in methods.values():
+            acc = v.pop("acc")
+            if not args.no_errors:
+                v["errors"] = _errors(orc, d, acc, args.samples)
+        for p in sorted({3, args.p}):
+            f, st = methods[f"falcon_p{p}"], methods[f"standard_tree_p{p}"]
+            st["falcon_speedup"] = st["ms_tree_and_gravity"] / f["ms_tree_and_gravity"]
 
     value = args.n * args.steps / r32["wall_s"]
     ph = r32["phases"]
@@ -458,6 +516,7 @@ def main():
         "tree": info,
         "collision_pairs_in_timed_steps": r32["pairs"],
         "batched": batched,
+        "gravity_methods": methods,
     }
     print(json.dumps(out))
     return 0

@@ -50,6 +50,20 @@ def lib():
     L.orc_resolve.restype = i64
     L.orc_resolve.argtypes = [i64, _i64, i64, _f64, _f64, _f64, _f64, _f64, _f64, _f64, _f64,
                               d, d, _i32]
+    L.orc_mesh_gamma_crit.restype = d
+    L.orc_mesh_gamma_crit.argtypes = [d, d, d, d]
+    L.orc_mesh_aspect_crit.restype = d
+    L.orc_mesh_aspect_crit.argtypes = [d, d]
+    L.orc_mesh_gamma_next.restype = d
+    L.orc_mesh_gamma_next.argtypes = [d, d, d, d]
+    L.orc_mesh_flags.restype = None
+    L.orc_mesh_flags.argtypes = [_f64, _f64, i64, d, _i32]
+    L.orc_mesh_neighbours.restype = d
+    L.orc_mesh_neighbours.argtypes = [_f64, _f64, _f64, _f64, i64, d]
+    L.orc_mesh_accel.restype = None
+    L.orc_mesh_accel.argtypes = [_f64, _f64, _f64, _f64, _f64, i64, d, d, _f64, _f64, _f64]
+    L.orc_mesh_pairs.restype = i64
+    L.orc_mesh_pairs.argtypes = [_f64] * 8 + [i64, d, d, _i64, i64]
     L.orc_grav_run_std.restype = None
     L.orc_grav_run_std.argtypes = [vp, i32, i32]
     L.orc_root_half_width.restype = d
@@ -423,6 +437,96 @@ def standard_tree_accel(d: dict, G=1.0, p=3, theta_min=0.5, s=102, ncb_pre=6, nc
     t = Tree(d["x"], d["y"], d["z"], s, L)
     g = Gravity(t, d["m"], G, p, theta_min, theta_mode).run_standard(ncb_pre, ncb_post)
     return g.accel(), t, g
+
+
+# ---------------------------------------------------------------- mesh module
+def mesh_gamma_crit(x: float, N: float, aspect: float, R_max: float) -> float:
+    """Eq. (4): mesh size for x neighbours on average in a disk of aspect h/r."""
+    return lib().orc_mesh_gamma_crit(float(x), float(N), float(aspect), float(R_max))
+
+
+def mesh_aspect_crit(x: float, moon_over_rmax: float) -> float:
+    """Eq. (5): smallest h/r for which moonlets of one Moon mass in total fit the mesh."""
+    return lib().orc_mesh_aspect_crit(float(x), float(moon_over_rmax))
+
+
+def mesh_gamma_next(gamma_prev: float, x: float, x_measured: float,
+                    gamma_min: float = 0.0) -> float:
+    """Eq. (6), clamped below by gamma_min (x' = 0 doubles the mesh)."""
+    return lib().orc_mesh_gamma_next(float(gamma_prev), float(x), float(x_measured),
+                                     float(gamma_min))
+
+
+def mesh_flags(m, R, gamma: float) -> np.ndarray:
+    """1: out of the mesh (2R > gamma); 2: one of the three most massive; 3: both."""
+    n = len(m)
+    out = np.zeros(n, np.int32)
+    lib().orc_mesh_flags(_c(m), _c(R), n, float(gamma), out)
+    return out
+
+
+def mesh_neighbours(d: dict, gamma: float) -> float:
+    """x' of Eq. (6): mean number of other moonlets in a mesh moonlet's neighbourhood."""
+    return lib().orc_mesh_neighbours(_c(d["x"]), _c(d["y"]), _c(d["z"]), _c(d["R"]),
+                                     len(d["x"]), float(gamma))
+
+
+def mesh_accel(d: dict, gamma: float, G: float = 1.0) -> np.ndarray:
+    """Mutual accelerations of the mesh module (Sect. 3.3), input order."""
+    n = len(d["x"])
+    ax, ay, az = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_mesh_accel(_c(d["x"]), _c(d["y"]), _c(d["z"]), _c(d["m"]), _c(d["R"]), n,
+                         float(G), float(gamma), ax, ay, az)
+    return np.stack([ax, ay, az], axis=1)
+
+
+def mesh_pairs(d: dict, gamma: float, dt: float, cap: int = 1 << 20) -> np.ndarray:
+    """Colliding pairs (i < j, increasing) among the pairs the mesh tests."""
+    n = len(d["x"])
+    out = np.zeros((cap, 2), np.int64)
+    k = lib().orc_mesh_pairs(*(_c(d[f]) for f in ("x", "y", "z", "vx", "vy", "vz", "m", "R")),
+                             n, float(gamma), float(dt), out, cap)
+    if k > cap:
+        return mesh_pairs(d, gamma, dt, cap=int(k))
+    return out[:k]
+
+
+class MeshClock:
+    """The mesh size along a run (Sect. 3.3): gamma_0 from Eq. (4) at the first mesh
+    (R_max = the largest distance to the central mass unless given), then Eq. (6) from
+    the previous mesh's neighbour count at every new mesh.  ``accel`` and ``collide``
+    fit ``kdk_steps``: each ``accel`` call builds a new mesh at the current positions,
+    and ``collide`` uses the mesh of the last ``accel`` call."""
+
+    def __init__(self, x_target: float, aspect: float, R_max: float = 0.0,
+                 gamma_min: float = 0.0, G: float = 1.0, gamma0: float = 0.0):
+        self.x, self.aspect, self.R_max, self.gamma_min, self.G = (
+            x_target, aspect, R_max, gamma_min, G)
+        self.gamma0 = gamma0
+        self.gamma = None
+        self.measured = None
+        self.history = []
+
+    def _new_mesh(self, s):
+        if self.gamma is None:
+            if self.gamma0 > 0.0:
+                g = self.gamma0
+            else:
+                rmax = self.R_max if self.R_max > 0.0 else float(
+                    np.sqrt(s["x"] ** 2 + s["y"] ** 2 + s["z"] ** 2).max())
+                g = mesh_gamma_crit(self.x, len(s["x"]), self.aspect, rmax)
+            self.gamma = max(g, self.gamma_min)
+        else:
+            self.gamma = mesh_gamma_next(self.gamma, self.x, self.measured, self.gamma_min)
+        self.measured = mesh_neighbours(s, self.gamma)
+        self.history.append((self.gamma, self.measured))
+
+    def accel(self, s):
+        self._new_mesh(s)
+        return mesh_accel(s, self.gamma, self.G)
+
+    def collide(self, s, dt):
+        return mesh_pairs(s, self.gamma, dt)
 
 
 def kdk_steps(d: dict, dt: float, n_steps: int, accel_fn, G=1.0, M_central=1.0,

@@ -1350,3 +1350,152 @@ int64_t orc_pairs_of(const double *x, const double *y, const double *z, const do
     if (total <= cap) qsort(out, (size_t)total, 2 * sizeof(int64_t), cmp_pair);
     return total;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Mesh module (Sect. 3.3).  A gamma-mesh of cubic cells of side gamma, cell    */
+/* (floor(x/gamma), floor(y/gamma), floor(z/gamma)); the neighbourhood of a     */
+/* moonlet is its own cell and the 26 adjacent ones.  Pairs of moonlets in each */
+/* other's neighbourhood interact (gravity) and are tested for collision.       */
+/* A moonlet with diameter 2R > gamma is kept out of the mesh and interacts     */
+/* with every other moonlet; for gravity, so do the three most massive          */
+/* moonlets.  Everything here is brute force over all pairs.                    */
+/* ------------------------------------------------------------------------- */
+
+#define ORC_PI 3.14159265358979323846
+
+/* Eq. (4): the largest mesh size that leaves x moonlets on average in a        */
+/* neighbourhood (27 cells) of a disk of aspect ratio h/r inside radius R_max. */
+double orc_mesh_gamma_crit(double x, double N, double aspect, double R_max)
+{
+    double s = aspect * aspect / (1.0 + aspect * aspect);
+    return pow(4.0 * ORC_PI * x / (81.0 * N), 1.0 / 3.0) * pow(s, 1.0 / 6.0) * R_max;
+}
+
+/* Eq. (5): the smallest aspect ratio for which moonlets of the mean radius of  */
+/* N moonlets of total mass one Moon fit the critical mesh (2R <= gamma); the  */
+/* argument is R_Moon / R_max.                                                  */
+double orc_mesh_aspect_crit(double x, double moon_over_rmax)
+{
+    return 162.0 / (ORC_PI * x) * moon_over_rmax * moon_over_rmax * moon_over_rmax;
+}
+
+/* Eq. (6): the next mesh size from the measured mean neighbour count x'; no   */
+/* smaller than gamma_min; with no neighbour at all (x' = 0) the mesh doubles. */
+double orc_mesh_gamma_next(double gamma_prev, double x, double x_measured, double gamma_min)
+{
+    double g = x_measured > 0.0 ? gamma_prev * cbrt(x / x_measured) : 2.0 * gamma_prev;
+    return g > gamma_min ? g : gamma_min;
+}
+
+static void mesh_cell(double x, double y, double z, double gamma, int64_t c[3])
+{
+    c[0] = (int64_t)floor(x / gamma);
+    c[1] = (int64_t)floor(y / gamma);
+    c[2] = (int64_t)floor(z / gamma);
+}
+
+static int mesh_adjacent(const int64_t a[3], const int64_t b[3])
+{
+    for (int k = 0; k < 3; k++)
+        if (a[k] - b[k] > 1 || b[k] - a[k] > 1) return 0;
+    return 1;
+}
+
+/* flags[i]: 1 = out of the mesh (2R > gamma), 2 = one of the three most massive */
+/* moonlets (larger mass first, equal masses by smaller index), 3 = both.        */
+void orc_mesh_flags(const double *m, const double *R, int64_t n, double gamma, int32_t *flags)
+{
+    int64_t top[3] = {-1, -1, -1};
+    for (int64_t i = 0; i < n; i++) {
+        flags[i] = 2.0 * R[i] > gamma ? 1 : 0;
+        /* insert i into the running top three (strictly larger mass goes first) */
+        for (int k = 0; k < 3; k++) {
+            if (top[k] < 0 || m[i] > m[top[k]]) {
+                for (int q = 2; q > k; q--) top[q] = top[q - 1];
+                top[k] = i;
+                break;
+            }
+        }
+    }
+    for (int k = 0; k < 3; k++)
+        if (top[k] >= 0) flags[top[k]] |= 2;
+}
+
+/* mean over the moonlets in the mesh of the number of other moonlets of the   */
+/* mesh in their neighbourhood (the x' of Eq. 6)                                */
+double orc_mesh_neighbours(const double *x, const double *y, const double *z, const double *R,
+                           int64_t n, double gamma)
+{
+    int64_t in = 0, pairs = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (2.0 * R[i] > gamma) continue;
+        in++;
+        int64_t ci[3];
+        mesh_cell(x[i], y[i], z[i], gamma, ci);
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i || 2.0 * R[j] > gamma) continue;
+            int64_t cj[3];
+            mesh_cell(x[j], y[j], z[j], gamma, cj);
+            if (mesh_adjacent(ci, cj)) pairs++;
+        }
+    }
+    return in > 0 ? (double)pairs / (double)in : 0.0;
+}
+
+/* does the pair (i, j) interact?  gravity: big = flags != 0; collisions:       */
+/* big = out of the mesh only                                                    */
+static int mesh_pair(const double *x, const double *y, const double *z, const int32_t *flags,
+                     int big_mask, int64_t i, int64_t j, double gamma)
+{
+    if ((flags[i] & big_mask) || (flags[j] & big_mask)) return 1;
+    if ((flags[i] & 1) || (flags[j] & 1)) return 0;
+    int64_t ci[3], cj[3];
+    mesh_cell(x[i], y[i], z[i], gamma, ci);
+    mesh_cell(x[j], y[j], z[j], gamma, cj);
+    return mesh_adjacent(ci, cj);
+}
+
+/* mutual accelerations over the interacting pairs (mu = G m) */
+void orc_mesh_accel(const double *x, const double *y, const double *z, const double *m,
+                    const double *R, int64_t n, double G, double gamma, double *ax, double *ay,
+                    double *az)
+{
+    int32_t *flags = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    orc_mesh_flags(m, R, n, gamma, flags);
+    for (int64_t i = 0; i < n; i++) {
+        double a[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i || !mesh_pair(x, y, z, flags, 3, i, j, gamma)) continue;
+            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2), r3 = r2 * r, mu = G * m[j];
+            a[0] += mu * dx / r3;
+            a[1] += mu * dy / r3;
+            a[2] += mu * dz / r3;
+        }
+        ax[i] = a[0]; ay[i] = a[1]; az[i] = a[2];
+    }
+    free(flags);
+}
+
+/* colliding pairs (i < j, increasing) among the pairs the mesh tests */
+int64_t orc_mesh_pairs(const double *x, const double *y, const double *z, const double *vx,
+                       const double *vy, const double *vz, const double *m, const double *R,
+                       int64_t n, double gamma, double dt, int64_t *out, int64_t cap)
+{
+    int32_t *flags = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    orc_mesh_flags(m, R, n, gamma, flags);
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = i + 1; j < n; j++) {
+            if (!mesh_pair(x, y, z, flags, 1, i, j, gamma)) continue;
+            if (!orc_pair_test(x[i], y[i], z[i], vx[i], vy[i], vz[i], R[i], x[j], y[j], z[j],
+                               vx[j], vy[j], vz[j], R[j], dt))
+                continue;
+            if (total < cap) { out[2 * total] = i; out[2 * total + 1] = j; }
+            total++;
+        }
+    free(flags);
+    return total;
+}

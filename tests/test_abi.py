@@ -40,6 +40,7 @@ def test_params_default_and_validation(nc):
         assert prm.leaf_size == (17 if p <= 3 else 52)
         assert (prm.ncs_col, prm.ncc_pre_col, prm.ncc_post_col) == (12, 0, 16)
         assert (prm.collision_mode, prm.collision_f) == (nc.COLLISIONS_REPORT, 2.0)
+        assert (prm.gravity_method, prm.ncb_pre, prm.ncb_post) == (nc.GRAVITY_FALCON, 6, 16)
     bad = nc.Params()
     assert L.ncorp_params_default(C.byref(bad), 7) == nc.E_INVALID
     h = C.c_void_p()
@@ -47,7 +48,8 @@ def test_params_default_and_validation(nc):
                        ("ncs", -1), ("theta_mode", 2), ("precision", 5),
                        ("root_half_width", 3.0), ("G", -1.0), ("collision_mode", 2),
                        ("collision_f", 0.9), ("collision_f", 2.1), ("M_sun", -1.0),
-                       ("obliquity", float("nan"))):
+                       ("obliquity", float("nan")), ("gravity_method", 2), ("ncb_pre", -1),
+                       ("ncb_post", -1)):
         prm = nc.params_default(3)
         setattr(prm, field, val)
         assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.E_INVALID, field
