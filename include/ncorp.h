@@ -115,10 +115,33 @@ typedef struct {
      * Paper settings: leaf_size 102, ncb_pre 6, ncb_post 16 (Sect. 6). */
     int32_t gravity_method;
     int32_t ncb_pre, ncb_post;
+    /* mesh module (Sect. 3.3), used by gravity_method NCORP_GRAVITY_MESH and by
+     * collision_method NCORP_COLLISIONS_MESH.  Cubic cells of side gamma, cell
+     * (floor(x/gamma), floor(y/gamma), floor(z/gamma)); a moonlet's neighbourhood
+     * is its cell and the 26 adjacent ones.  Moonlets in each other's
+     * neighbourhood attract each other and are tested for collision; a moonlet
+     * with 2R > gamma stays out of the mesh and interacts with every moonlet; for
+     * gravity, so do the three most massive moonlets (equal masses: smaller input
+     * index first).  Nothing else interacts.  The cells are hashed into a table of
+     * mesh_cells^3 buckets (cells that share a bucket are told apart exactly).
+     *   mesh_cells: buckets per axis, 3..1024 (16 bytes of workspace per bucket);
+     *   mesh_neighbours: x, the mean number of neighbours aimed at;
+     *   mesh_gamma: the first mesh size; 0 = Eq. (4) with aspect ratio
+     *     mesh_aspect and radius mesh_rmax (0 = the largest distance of a moonlet
+     *     to the central mass at the first mesh);
+     *   every later mesh: gamma = gamma' (x / x')^(1/3) (Eq. 6), x' the mean
+     *     number of neighbours of the moonlets of the previous mesh (x' = 0
+     *     doubles gamma), and never below mesh_min_side / mesh_cells.
+     * The mesh size lives in the workspace and restarts from mesh_gamma or Eq. (4)
+     * when a new workspace buffer is bound.  Plain (not batched) calls only. */
+    int32_t collision_method;
+    int32_t mesh_cells;
+    double mesh_neighbours, mesh_aspect, mesh_rmax, mesh_min_side, mesh_gamma;
 } ncorp_params;
 
 enum { NCORP_COLLISIONS_REPORT = 0, NCORP_COLLISIONS_RESOLVE = 1 };
-enum { NCORP_GRAVITY_FALCON = 0, NCORP_GRAVITY_STANDARD_TREE = 1 };
+enum { NCORP_GRAVITY_FALCON = 0, NCORP_GRAVITY_STANDARD_TREE = 1, NCORP_GRAVITY_MESH = 2 };
+enum { NCORP_COLLISIONS_TREE = 0, NCORP_COLLISIONS_MESH = 1 };
 
 typedef struct ncorp_ctx ncorp_ctx;
 
@@ -146,15 +169,35 @@ int64_t ncorp_workspace_bytes(const ncorp_params *params, int64_t n_max,
 int ncorp_build_tree(ncorp_ctx *ctx, const double *x, const double *y, const double *z,
                      int64_t n, void *workspace, int64_t ws_bytes, void *stream);
 
-/* Mutual gravitational acceleration of every moonlet on the last tree (Eqs. 10-12,
- * 20, 25, 26 and Alg. 2): a_i = sum_j G m_j (x_j - x_i)/|x_j - x_i|^3 as
- * approximated by the falcON walk.  m: n masses; ax, ay, az: n outputs, input
- * order.  The central mass is NOT included here. */
+/* The mesh of the mesh module (Sect. 3.3, see ncorp_params) at positions x, y, z
+ * for moonlets of radii R (n FP64 each): the mesh size for this mesh (Eq. 4 at the
+ * first, Eq. 6 after), the cell of every moonlet, the moonlets sorted by hash
+ * bucket, the bucket table.  Needed before ncorp_gravity / ncorp_collide when
+ * their method is the mesh (ncorp_step builds it itself).  A cell coordinate
+ * beyond +-2^30 makes ncorp_get_status return NCORP_E_INVALID; more than 1021
+ * moonlets with 2R > gamma, NCORP_E_CAPACITY. */
+int ncorp_build_mesh(ncorp_ctx *ctx, const double *x, const double *y, const double *z,
+                     const double *R, int64_t n, void *workspace, int64_t ws_bytes,
+                     void *stream);
+
+/* Waits for the stream and reports the last mesh: out[0] its mesh size gamma,
+ * out[1] the mean number of neighbours x' measured on it (NaN before a gravity or
+ * collision pass counted them), out[2] the moonlets in the mesh, out[3] those
+ * kept out of it (2R > gamma).  out: 4 doubles, host memory. */
+int ncorp_mesh_state(ncorp_ctx *ctx, double *out);
+
+/* Mutual gravitational acceleration of every moonlet: a_i = sum_j G m_j (x_j -
+ * x_i)/|x_j - x_i|^3 as approximated by the chosen method -- the falcON walk on
+ * the last tree (Eqs. 10-12, 20, 25, 26 and Alg. 2), the standard tree code
+ * (Alg. 1), or the mesh module on the last mesh (Sect. 3.3).  m: n masses; ax, ay,
+ * az: n outputs, input order.  The central mass is NOT included here. */
 int ncorp_gravity(ncorp_ctx *ctx, const double *m, double *ax, double *ay, double *az,
                   void *stream);
 
-/* Collision search on the last tree (Sect. 3.1 and Sect. 3.4.2): every pair i < j
- * whose straight-line trajectories touch at a time 0 <= t <= dt (Eqs. 1-2).
+/* Collision search (Sect. 3.1) on the last tree (Sect. 3.4.2; every pair i < j
+ * whose straight-line trajectories touch at a time 0 <= t <= dt, Eqs. 1-2) or, with
+ * collision_method NCORP_COLLISIONS_MESH, on the last mesh (the pairs of
+ * neighbours and of moonlets kept out of the mesh that touch, Sect. 3.3).
  * vx, vy, vz, R: n FP64 velocities and radii.  pairs: cap x 2 int64, written in
  * lexicographic order, no duplicates; n_pairs_dev: one int64 (device) receiving the
  * number found (which may exceed cap: then the status is NCORP_E_CAPACITY). */

@@ -24,6 +24,9 @@ struct ncorp_ctx {
     int64_t n = 0;
     double clock = 0.0;                 // time of the next ncorp_step call
     bool grav_lists = false;            // the gravity walk ran on the current tree
+    bool have_mesh = false;             // a mesh was built (mesh module)
+    bool mesh_init = false;             // the workspace's mesh state has been set up
+    bool mesh_counted = false;          // neighbours counted on the current mesh
     hipStream_t last = nullptr;
     char err[256];
     // phase timing
@@ -139,11 +142,32 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
         return false;
     }
     if (p->gravity_method != NCORP_GRAVITY_FALCON &&
-        p->gravity_method != NCORP_GRAVITY_STANDARD_TREE) {
-        std::snprintf(why, len, "gravity_method must be 0 or 1"); return false;
+        p->gravity_method != NCORP_GRAVITY_STANDARD_TREE &&
+        p->gravity_method != NCORP_GRAVITY_MESH) {
+        std::snprintf(why, len, "gravity_method must be 0, 1 or 2"); return false;
     }
     if (p->ncb_pre < 0 || p->ncb_post < 0) {
         std::snprintf(why, len, "ncb_pre and ncb_post must be >= 0"); return false;
+    }
+    if (p->collision_method != NCORP_COLLISIONS_TREE &&
+        p->collision_method != NCORP_COLLISIONS_MESH) {
+        std::snprintf(why, len, "collision_method must be 0 or 1"); return false;
+    }
+    if (p->mesh_cells < 3 || p->mesh_cells > kMaxMeshCells) {
+        std::snprintf(why, len, "mesh_cells must be in 3..%d", kMaxMeshCells); return false;
+    }
+    if (!(p->mesh_neighbours > 0.0 && std::isfinite(p->mesh_neighbours)) ||
+        !(p->mesh_aspect >= 0.0 && std::isfinite(p->mesh_aspect)) ||
+        !(p->mesh_rmax >= 0.0 && std::isfinite(p->mesh_rmax)) ||
+        !(p->mesh_min_side >= 0.0 && std::isfinite(p->mesh_min_side)) ||
+        !(p->mesh_gamma >= 0.0 && std::isfinite(p->mesh_gamma))) {
+        std::snprintf(why, len, "mesh_neighbours > 0; mesh_aspect, mesh_rmax, mesh_min_side, "
+                                "mesh_gamma finite and >= 0");
+        return false;
+    }
+    if (p->mesh_gamma == 0.0 && p->mesh_aspect == 0.0 && p->mesh_min_side == 0.0) {
+        std::snprintf(why, len, "Eq. (4) needs mesh_aspect > 0 (or give mesh_gamma)");
+        return false;
     }
     return true;
 }
@@ -172,6 +196,13 @@ extern "C" int ncorp_params_default(ncorp_params *o, int p) {
     o->gravity_method = NCORP_GRAVITY_FALCON;
     o->ncb_pre = 6;
     o->ncb_post = 16;
+    o->collision_method = NCORP_COLLISIONS_TREE;
+    o->mesh_cells = 256;
+    o->mesh_neighbours = 8.0;
+    o->mesh_aspect = 0.05;
+    o->mesh_rmax = 0.0;
+    o->mesh_min_side = 0.0;
+    o->mesh_gamma = 0.0;
     return NCORP_OK;
 }
 
@@ -302,6 +333,23 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.mbest = (int32_t *)take(4 * n);
     ws.mmatch = (int32_t *)take(4 * n);
     ws.cand_blk = (int32_t *)take(4 * 8192);
+    if (prm.gravity_method == NCORP_GRAVITY_MESH ||
+        prm.collision_method == NCORP_COLLISIONS_MESH) {
+        ws.mesh_M = prm.mesh_cells;
+        ws.mtab_n = (int64_t)ws.mesh_M * ws.mesh_M * ws.mesh_M;
+        ws.mesh = (MeshState *)take(sizeof(MeshState));
+        ws.mtab = (int4 *)take(16 * ws.mtab_n);
+        ws.mkeys = (uint64_t *)take(8 * n);
+        ws.mkeys_alt = (uint64_t *)take(8 * n);
+        ws.midx = (uint32_t *)take(4 * n);
+        ws.midx_alt = (uint32_t *)take(4 * n);
+        ws.mpos = (double4 *)take(32 * n);
+        ws.mcell = (int4 *)take(16 * n);
+        ws.mvel = (double4 *)take(32 * n);
+        ws.mbig = (int32_t *)take(4 * (int64_t)kMaxMeshBig);
+        ws.mtop_part = (int32_t *)take(4 * 3 * 256);
+        ws.mbig_part = (double *)take(8 * 3 * 64 * (int64_t)kMaxMeshBig);
+    }
     ws.bytes = off;
     return off;
 }
@@ -342,6 +390,13 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
     // unknown bytes, so the next walk clears it
     ws.clear_queue = !(c->ws.base == ws.base && c->ws.queue == ws.queue &&
                        c->ws.queue_cap == ws.queue_cap) || c->ws.clear_queue;
+    // so does the mesh state (and its table's stamps)
+    if (ws.mesh) {
+        const bool same = c->ws.base == ws.base && c->ws.mesh == ws.mesh &&
+                          c->ws.mtab == ws.mtab && c->mesh_init;
+        ws.clear_mesh = !same || c->ws.clear_mesh;
+        if (!same) { c->mesh_init = false; c->have_mesh = false; }
+    }
     c->ws = ws;
     return NCORP_OK;
 }
@@ -385,6 +440,56 @@ extern "C" int ncorp_build_tree(ncorp_ctx *c, const double *x, const double *y, 
     return build_tree_impl(c, x, y, z, n, (hipStream_t)stream, true, nullptr, 1);
 }
 
+static bool mesh_gravity(const ncorp_params &p) {
+    return p.gravity_method == NCORP_GRAVITY_MESH;
+}
+static bool mesh_collisions(const ncorp_params &p) {
+    return p.collision_method == NCORP_COLLISIONS_MESH;
+}
+
+// fresh: also reset the device state (no tree build precedes this one)
+static int build_mesh_impl(ncorp_ctx *c, const double *x, const double *y, const double *z,
+                           const double *R, int64_t n, hipStream_t s, bool fresh) {
+    Workspace &ws = c->ws;
+    PhaseTimer t(c, NCORP_PHASE_TREE, s);
+    if (fresh) HIPCHK(c, launch_reset_state(ws, s));
+    HIPCHK(c, launch_mesh_build(ws, x, y, z, R, n, c->prm, !c->mesh_init, s));
+    ws.clear_mesh = false;
+    c->mesh_init = true;
+    c->have_mesh = true;
+    c->mesh_counted = false;
+    c->n = n;
+    c->last = s;
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_build_mesh(ncorp_ctx *c, const double *x, const double *y, const double *z,
+                                const double *R, int64_t n, void *workspace, int64_t ws_bytes,
+                                void *stream) {
+    if (!c) return NCORP_E_INVALID;
+    if (!x || !y || !z || !R) return fail(c, NCORP_E_INVALID, "array pointer is NULL");
+    if (n < 1 || n > INT32_MAX - 1) return fail(c, NCORP_E_INVALID, "n must be in 1..2^31-2");
+    if (!mesh_gravity(c->prm) && !mesh_collisions(c->prm))
+        return fail(c, NCORP_E_INVALID, "no method of this context uses the mesh");
+    int r = setup_workspace(c, n, workspace, ws_bytes);
+    if (r != NCORP_OK) return r;
+    const bool tree_too = !mesh_gravity(c->prm) || !mesh_collisions(c->prm);
+    return build_mesh_impl(c, x, y, z, R, n, (hipStream_t)stream, !tree_too);
+}
+
+extern "C" int ncorp_mesh_state(ncorp_ctx *c, double *out) {
+    if (!c || !out) return NCORP_E_INVALID;
+    if (!c->have_mesh || !c->ws.mesh) return fail(c, NCORP_E_INVALID, "no mesh built yet");
+    HIPCHK(c, hipStreamSynchronize(c->last));
+    MeshState h;
+    HIPCHK(c, hipMemcpy(&h, c->ws.mesh, sizeof(MeshState), hipMemcpyDeviceToHost));
+    out[0] = h.gamma;
+    out[1] = h.measured ? (h.n_in > 0 ? (double)h.nbr_sum / (double)h.n_in : 0.0) : NAN;
+    out[2] = (double)h.n_in;
+    out[3] = (double)(c->n - h.n_in);
+    return NCORP_OK;
+}
+
 static int check_disks(ncorp_ctx *c, const int64_t *disk_offsets, int n_disks) {
     if (!disk_offsets) return fail(c, NCORP_E_INVALID, "disk_offsets is NULL");
     if (n_disks < 1 || n_disks > NCORP_MAX_DISKS)
@@ -414,6 +519,13 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
         HIPCHK(c, launch_fill_i64((int64_t *)ax, 0, n, s));
         HIPCHK(c, launch_fill_i64((int64_t *)ay, 0, n, s));
         HIPCHK(c, launch_fill_i64((int64_t *)az, 0, n, s));
+        return NCORP_OK;
+    }
+    if (mesh_gravity(c->prm)) {
+        PhaseTimer t(c, NCORP_PHASE_GWALK, s);
+        HIPCHK(c, launch_mesh_gravity(ws, m, c->prm.G, n, !c->mesh_counted, ax, ay, az, s));
+        c->mesh_counted = true;
+        c->last = s;
         return NCORP_OK;
     }
     {
@@ -459,7 +571,10 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
 extern "C" int ncorp_gravity(ncorp_ctx *c, const double *m, double *ax, double *ay, double *az,
                              void *stream) {
     if (!c) return NCORP_E_INVALID;
-    if (!c->have_tree) return fail(c, NCORP_E_INVALID, "no tree: call ncorp_build_tree first");
+    if (mesh_gravity(c->prm) ? !c->have_mesh : !c->have_tree)
+        return fail(c, NCORP_E_INVALID, mesh_gravity(c->prm)
+                                            ? "no mesh: call ncorp_build_mesh first"
+                                            : "no tree: call ncorp_build_tree first");
     if (!m || !ax || !ay || !az) return fail(c, NCORP_E_INVALID, "array pointer is NULL");
     return gravity_impl(c, m, ax, ay, az, (hipStream_t)stream);
 }
@@ -473,13 +588,19 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
     Workspace &ws = c->ws;
     const int64_t n = c->n;
     PhaseTimer t(c, NCORP_PHASE_COLLIDE, s);
-    HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
-    HIPCHK(c, launch_collision_climb(ws, n, dt, s));
-    if (c->grav_lists)
-        HIPCHK(c, launch_candidates_from_lists(ws, s));
-    else
-        HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col, c->prm.ncc_post_col, s));
-    HIPCHK(c, launch_collide_pairs(ws, n, dt, s));
+    if (mesh_collisions(c->prm)) {
+        HIPCHK(c, launch_mesh_collide(ws, vx, vy, vz, R, n, dt, !c->mesh_counted, s));
+        c->mesh_counted = true;
+    } else {
+        HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
+        HIPCHK(c, launch_collision_climb(ws, n, dt, s));
+        if (c->grav_lists)
+            HIPCHK(c, launch_candidates_from_lists(ws, s));
+        else
+            HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col,
+                                  c->prm.ncc_post_col, s));
+        HIPCHK(c, launch_collide_pairs(ws, n, dt, s));
+    }
     if (state && c->prm.collision_mode == NCORP_COLLISIONS_RESOLVE)
         HIPCHK(c, launch_resolve(ws, state[0], state[1], state[2], state[3], state[4], state[5],
                                  m, R, dt, c->prm.collision_f, pairs, cap, n_pairs_dev, step,
@@ -495,7 +616,10 @@ extern "C" int ncorp_collide(ncorp_ctx *c, const double *vx, const double *vy, c
                              const double *R, double dt, int64_t *pairs, int64_t cap,
                              int64_t *n_pairs_dev, void *stream) {
     if (!c) return NCORP_E_INVALID;
-    if (!c->have_tree) return fail(c, NCORP_E_INVALID, "no tree: call ncorp_build_tree first");
+    if (mesh_collisions(c->prm) ? !c->have_mesh : !c->have_tree)
+        return fail(c, NCORP_E_INVALID, mesh_collisions(c->prm)
+                                            ? "no mesh: call ncorp_build_mesh first"
+                                            : "no tree: call ncorp_build_tree first");
     if (!vx || !vy || !vz || !R || !n_pairs_dev || (cap > 0 && !pairs))
         return fail(c, NCORP_E_INVALID, "array pointer is NULL");
     if (cap < 0) return fail(c, NCORP_E_INVALID, "cap must be >= 0");
@@ -548,8 +672,19 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
     Workspace &ws = c->ws;
     double *ax = ws.acc, *ay = ws.acc + n, *az = ws.acc + 2 * n;
     const bool mutual = c->prm.p > 0;
-    r = build_tree_impl(c, x, y, z, n, s, true, disk_off, n_disks);
-    if (r != NCORP_OK) return r;
+    const bool need_mesh = (mutual && mesh_gravity(c->prm)) || mesh_collisions(c->prm);
+    const bool need_tree = (mutual && !mesh_gravity(c->prm)) || !mesh_collisions(c->prm);
+    if (need_mesh && disk_off)
+        return fail(c, NCORP_E_UNSUPPORTED, "the mesh module takes plain (not batched) calls");
+    auto rebuild = [&](bool fresh) -> int {
+        int q = NCORP_OK;
+        if (need_tree && (q = build_tree_impl(c, x, y, z, n, s, fresh, disk_off, n_disks)) !=
+                             NCORP_OK)
+            return q;
+        if (need_mesh) q = build_mesh_impl(c, x, y, z, R, n, s, fresh && !need_tree);
+        return q;
+    };
+    if ((r = rebuild(true)) != NCORP_OK) return r;
     k_zero_cursor<<<1, 64, 0, s>>>(ws.st);
     if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
     {
@@ -565,8 +700,7 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
             PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
             HIPCHK(c, launch_drift(x, y, z, vx, vy, vz, n, dt, s));
         }
-        if ((r = build_tree_impl(c, x, y, z, n, s, false, disk_off, n_disks)) != NCORP_OK)
-            return r;
+        if ((r = rebuild(false)) != NCORP_OK) return r;
         if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
         const double h = (k == n_steps - 1) ? 0.5 * dt : dt;
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
@@ -613,7 +747,8 @@ extern "C" int ncorp_get_status(ncorp_ctx *c, int64_t *required) {
     int r = sync_state(c, h);
     if (r != NCORP_OK) return r;
     if (required) *required = h.required;
-    if (h.status & (ST_CAP_CELLS | ST_CAP_QUEUE | ST_CAP_M2L | ST_CAP_P2P | ST_CAP_PAIRS | ST_CAP_LISTS)) {
+    if (h.status & (ST_CAP_CELLS | ST_CAP_QUEUE | ST_CAP_M2L | ST_CAP_P2P | ST_CAP_PAIRS |
+                    ST_CAP_LISTS | ST_CAP_MESH)) {
         std::snprintf(c->err, sizeof(c->err), "device list overflow (flags 0x%x, required %lld)",
                       h.status, (long long)h.required);
         return NCORP_E_CAPACITY;
@@ -624,6 +759,9 @@ extern "C" int ncorp_get_status(ncorp_ctx *c, int64_t *required) {
     }
     if (h.status & ST_BAD_OFFSETS)
         return fail(c, NCORP_E_INVALID, "disk offsets are not a non-decreasing 0..n sequence");
+    if (h.status & ST_MESH_RANGE)
+        return fail(c, NCORP_E_INVALID,
+                    "mesh: a cell coordinate beyond 2^30 or a mesh size that is not > 0");
     if (h.status & ST_NONFINITE) return fail(c, NCORP_E_NONFINITE, "non-finite position");
     return NCORP_OK;
 }

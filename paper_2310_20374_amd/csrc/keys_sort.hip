@@ -444,6 +444,25 @@ hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Stable sort of (key, value) by the low `bits` bits of the keys, ping-ponging
+// between the a and b buffers; returns in *in_b whether the result sits in b.
+hipError_t launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
+                             int bits, uint32_t *hist, bool *in_b, hipStream_t s) {
+    const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
+    const int npass = (bits + 7) / 8;
+    uint32_t *totals = hist + (int64_t)256 * ntiles;
+    for (int pass = 0; pass < npass; pass++) {
+        k_radix_hist<<<ntiles, kSortThreads, 0, s>>>(ka, va, nullptr, n, 8 * pass, hist, ntiles);
+        k_radix_scan<<<256, 256, 0, s>>>(hist, ntiles, totals);
+        k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(ka, va, kb, vb, nullptr, n, 8 * pass,
+                                                        hist, totals, ntiles);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    *in_b = npass % 2 == 1;
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ gathers
 __global__ void k_gather3(const double *__restrict__ x, const double *__restrict__ y,
                           const double *__restrict__ z, const uint32_t *__restrict__ idx,

@@ -40,7 +40,7 @@ __host__ __device__ constexpr int cidx(int a, int b, int c) { return sidx(a, b, 
 enum StatusBits : int32_t {
     ST_CAP_CELLS = 1, ST_CAP_QUEUE = 2, ST_CAP_M2L = 4, ST_CAP_P2P = 8,
     ST_CAP_PAIRS = 16, ST_NONFINITE = 32, ST_CAP_LISTS = 64, ST_WALK_STALL = 128,
-    ST_BAD_ITEM = 256, ST_BAD_OFFSETS = 512
+    ST_BAD_ITEM = 256, ST_BAD_OFFSETS = 512, ST_MESH_RANGE = 1024, ST_CAP_MESH = 2048
 };
 // Any of these leaves the tree or the interaction lists incomplete: later passes
 // then do nothing rather than follow indices that were never written.
@@ -76,7 +76,8 @@ constexpr int kLongSlots = 8;
 constexpr int kLongGrid = 2048;
 
 constexpr int32_t kSkipMask = ST_CAP_CELLS | ST_CAP_QUEUE | ST_CAP_M2L | ST_CAP_P2P |
-                              ST_CAP_LISTS | ST_WALK_STALL | ST_BAD_ITEM | ST_BAD_OFFSETS;
+                              ST_CAP_LISTS | ST_WALK_STALL | ST_BAD_ITEM | ST_BAD_OFFSETS |
+                              ST_MESH_RANGE | ST_CAP_MESH;
 
 // independent disks of one batched call (a forest with one root per non-empty disk)
 constexpr int kMaxDisks = NCORP_MAX_DISKS;
@@ -105,6 +106,28 @@ struct DevState {
     int64_t npairs;            // colliding pairs found (may exceed capacity)
     int64_t pair_cursor;       // pairs already written by earlier steps of ncorp_step
     int64_t p2p_inter;         // directed moonlet pairs (i != j) of the direct sums
+};
+
+// ---------------------------------------------------------------- mesh module
+// Moonlets that interact with every other one in the mesh module: those too large
+// for the mesh (2R > gamma) and, for gravity, the three most massive.
+constexpr int kMaxMeshBig = 1024;
+constexpr int kMaxMeshCells = 1024;    // hash-table cells per axis
+constexpr int kMeshCellLimit = 1 << 30;  // |cell coordinate| bound
+// State of the mesh across builds (lives in the workspace, cleared when a new
+// workspace buffer is bound).
+struct MeshState {
+    double gamma;                      // mesh size of the current mesh
+    double rmax2;                      // max |r|^2 at the first mesh (R_max of Eq. 4)
+    unsigned long long nbr_sum;        // (moonlet, neighbour) pairs counted on it
+    int32_t n_in;                      // moonlets in the mesh: the sorted prefix
+    int32_t stamp;                     // build counter, carried by its table entries
+    int32_t init;                      // gamma has been set
+    int32_t measured;                  // nbr_sum counted on the current mesh
+    int32_t ntop;                      // the three most massive (sorted positions)
+    int32_t top[3];
+    int32_t nbig;                      // gravity's all-pairs list (mesh_big)
+    int32_t pad[5];
 };
 
 // Work-queue state of a persistent walk; each counter on its own 128-byte line.
@@ -227,8 +250,23 @@ struct Workspace {
     double *disk_L = nullptr;
     int32_t *disk_root = nullptr;                     // level-0 cell of each disk
     int ndisks = 1;                                   // host copy; 1 = plain call
+    // mesh module (present when a method uses it): hash table of M^3 buckets
+    // (first, end, stamp), moonlets sorted by bucket (oversized ones last)
+    MeshState *mesh = nullptr;
+    int4 *mtab = nullptr;
+    int mesh_M = 0;
+    int64_t mtab_n = 0;
+    uint64_t *mkeys = nullptr, *mkeys_alt = nullptr;
+    uint32_t *midx = nullptr, *midx_alt = nullptr;   // sorted position -> input index
+    double4 *mpos = nullptr;                          // x, y, z, mu (sorted)
+    int4 *mcell = nullptr;                            // cell coordinates (sorted)
+    double4 *mvel = nullptr;                          // vx, vy, vz, R (sorted)
+    int32_t *mbig = nullptr;                          // kMaxMeshBig sorted positions
+    int32_t *mtop_part = nullptr;                     // per-block top-three candidates
+    double *mbig_part = nullptr;                      // partial sums of the big ones
     DevState *st = nullptr;
     bool clear_queue = false;                         // new buffer: clear before next walk
+    bool clear_mesh = false;                          // new buffer: clear the mesh state
 };
 
 // Layout of the workspace for given capacities; with base == nullptr only the
@@ -288,6 +326,18 @@ hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, 
                           double *vy, double *vz, const double *m, const double *R, double dt,
                           double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
                           int64_t *cursor, hipStream_t s);
+
+// mesh module (Sect. 3.3)
+hipError_t launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
+                             int bits, uint32_t *hist, bool *in_b, hipStream_t s);
+hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double *y,
+                             const double *z, const double *R, int64_t n, const ncorp_params &prm,
+                             bool first, hipStream_t s);
+hipError_t launch_mesh_gravity(const Workspace &ws, const double *m, double G, int64_t n,
+                               bool count, double *ax, double *ay, double *az, hipStream_t s);
+hipError_t launch_mesh_collide(const Workspace &ws, const double *vx, const double *vy,
+                               const double *vz, const double *R, int64_t n, double dt,
+                               bool count, hipStream_t s);
 
 // what the kick adds besides the mutual gravity: G M_c, G M_c R^2 J2, and the
 // distant body (G M_sun, its position, a^2, a^3); zero factors switch terms off

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libncorp.so")
 OK, E_INVALID, E_CAPACITY, E_HIP, E_UNSUPPORTED, E_NONFINITE = 0, -1, -2, -3, -4, -5
 FP64, FP32_BULK = 0, 1
 COLLISIONS_REPORT, COLLISIONS_RESOLVE = 0, 1
-GRAVITY_FALCON, GRAVITY_STANDARD_TREE = 0, 1
+GRAVITY_FALCON, GRAVITY_STANDARD_TREE, GRAVITY_MESH = 0, 1, 2
+COLLISIONS_TREE, COLLISIONS_MESH = 0, 1
 STATUS_NAMES = {0: "ok", -1: "invalid", -2: "capacity", -3: "hip", -4: "unsupported",
                 -5: "nonfinite"}
 
@@ -31,7 +32,8 @@ EXPORTED_SYMBOLS = ("ncorp_params_default", "ncorp_create", "ncorp_destroy",
                     "ncorp_workspace_bytes", "ncorp_build_tree", "ncorp_gravity",
                     "ncorp_collide", "ncorp_step", "ncorp_get_status", "ncorp_last_error",
                     "ncorp_tree_info", "ncorp_export_host", "ncorp_set_timing",
-                    "ncorp_phase_times", "ncorp_build_tree_batched", "ncorp_step_batched")
+                    "ncorp_phase_times", "ncorp_build_tree_batched", "ncorp_step_batched",
+                    "ncorp_build_mesh", "ncorp_mesh_state")
 MAX_DISKS = 65536
 
 
@@ -49,6 +51,9 @@ class Params(C.Structure):
         ("J2", C.c_double), ("R_central", C.c_double), ("M_sun", C.c_double),
         ("a_sun", C.c_double), ("obliquity", C.c_double), ("t_start", C.c_double),
         ("gravity_method", C.c_int32), ("ncb_pre", C.c_int32), ("ncb_post", C.c_int32),
+        ("collision_method", C.c_int32), ("mesh_cells", C.c_int32),
+        ("mesh_neighbours", C.c_double), ("mesh_aspect", C.c_double),
+        ("mesh_rmax", C.c_double), ("mesh_min_side", C.c_double), ("mesh_gamma", C.c_double),
     ]
 
     def as_dict(self):
@@ -86,6 +91,10 @@ def lib():
     L.ncorp_workspace_bytes.restype = i64
     L.ncorp_build_tree.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp]
     L.ncorp_build_tree.restype = i32
+    L.ncorp_build_mesh.argtypes = [vp, vp, vp, vp, vp, i64, vp, i64, vp]
+    L.ncorp_build_mesh.restype = i32
+    L.ncorp_mesh_state.argtypes = [vp, C.POINTER(C.c_double)]
+    L.ncorp_mesh_state.restype = i32
     L.ncorp_gravity.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ncorp_gravity.restype = i32
     L.ncorp_collide.argtypes = [vp, vp, vp, vp, vp, d, vp, i64, vp, vp]
@@ -182,6 +191,19 @@ class Context:
         self._check(lib().ncorp_build_tree(self.h, _ptr(x), _ptr(y), _ptr(z), n,
                                            _ptr(self.ws), self.ws_bytes, _stream(stream)),
                     "ncorp_build_tree")
+
+    def build_mesh(self, x, y, z, R, stream=None):
+        n = x.numel()
+        self._check(lib().ncorp_build_mesh(self.h, _ptr(x), _ptr(y), _ptr(z), _ptr(R), n,
+                                           _ptr(self.ws), self.ws_bytes, _stream(stream)),
+                    "ncorp_build_mesh")
+
+    def mesh_state(self):
+        """(gamma, measured mean neighbours x' or nan, moonlets in the mesh, out of it)."""
+        out = (C.c_double * 4)()
+        self._check(lib().ncorp_mesh_state(self.h, out), "ncorp_mesh_state")
+        return {"gamma": out[0], "neighbours": out[1], "n_in": int(out[2]),
+                "n_out": int(out[3])}
 
     def gravity(self, m, ax, ay, az, stream=None):
         self._check(lib().ncorp_gravity(self.h, _ptr(m), _ptr(ax), _ptr(ay), _ptr(az),

@@ -41,6 +41,8 @@ def test_params_default_and_validation(nc):
         assert (prm.ncs_col, prm.ncc_pre_col, prm.ncc_post_col) == (12, 0, 16)
         assert (prm.collision_mode, prm.collision_f) == (nc.COLLISIONS_REPORT, 2.0)
         assert (prm.gravity_method, prm.ncb_pre, prm.ncb_post) == (nc.GRAVITY_FALCON, 6, 16)
+        assert (prm.collision_method, prm.mesh_cells, prm.mesh_neighbours,
+                prm.mesh_aspect, prm.mesh_gamma) == (nc.COLLISIONS_TREE, 256, 8.0, 0.05, 0.0)
     bad = nc.Params()
     assert L.ncorp_params_default(C.byref(bad), 7) == nc.E_INVALID
     h = C.c_void_p()
@@ -48,8 +50,10 @@ def test_params_default_and_validation(nc):
                        ("ncs", -1), ("theta_mode", 2), ("precision", 5),
                        ("root_half_width", 3.0), ("G", -1.0), ("collision_mode", 2),
                        ("collision_f", 0.9), ("collision_f", 2.1), ("M_sun", -1.0),
-                       ("obliquity", float("nan")), ("gravity_method", 2), ("ncb_pre", -1),
-                       ("ncb_post", -1)):
+                       ("obliquity", float("nan")), ("gravity_method", 3), ("ncb_pre", -1),
+                       ("ncb_post", -1), ("collision_method", 2), ("mesh_cells", 2),
+                       ("mesh_cells", 1025), ("mesh_neighbours", 0.0), ("mesh_gamma", -1.0),
+                       ("mesh_aspect", float("inf")), ("mesh_rmax", -1.0)):
         prm = nc.params_default(3)
         setattr(prm, field, val)
         assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.E_INVALID, field
