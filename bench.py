@@ -110,7 +110,11 @@ def _run(nc, prm, d, dt, steps, warmup, timing, device):
     torch.cuda.synchronize()
     ctx.check_status()
     acc = torch.stack(a, 1).cpu().numpy()
-    return {"wall_s": wall, "phases": phases, "info": info, "acc": acc, "pairs": n_pairs}
+    mesh = None
+    if prm.gravity_method == nc.GRAVITY_MESH or prm.collision_method == nc.COLLISIONS_MESH:
+        mesh = ctx.mesh_state()
+    return {"wall_s": wall, "phases": phases, "info": info, "acc": acc, "pairs": n_pairs,
+            "mesh": mesh}
 
 
 def _gravity_method_comparison(nc, d, p_list, reps, device):
@@ -151,6 +155,25 @@ def _gravity_method_comparison(nc, d, p_list, reps, device):
                                    "acc": torch.stack(a, 1).cpu().numpy()}
             del ctx
     return out
+
+
+def _run_mesh(nc, d, args, device):
+    """The mesh module (Sect. 3.3) for both gravity and collisions on the same disk and
+    step loop: x = 8 neighbours, Eq. (4) with h/r = 0.05 at the first mesh, Eq. (6)
+    after; elastic resolution as in the main line."""
+    cmode = nc.COLLISIONS_RESOLVE if args.collisions == "resolve" else nc.COLLISIONS_REPORT
+    prm = nc.params_default(args.p, gravity_method=nc.GRAVITY_MESH,
+                            collision_method=nc.COLLISIONS_MESH, mesh_neighbours=8.0,
+                            mesh_aspect=0.05, mesh_cells=256, collision_mode=cmode,
+                            collision_f=2.0)
+    r = _run(nc, prm, d, args.dt, args.steps, args.warmup, True, device)
+    out = {"ms_per_step": r["wall_s"] * 1e3 / args.steps,
+           "value": len(d["x"]) * args.steps / r["wall_s"],
+           "phases_ms_per_step": {k: round(v[0] / args.steps, 4)
+                                  for k, v in r["phases"].items() if v[1] > 0},
+           "collision_pairs_in_timed_steps": r["pairs"], "mesh": r.get("mesh"),
+           "mesh_cells": prm.mesh_cells, "neighbours_target": prm.mesh_neighbours}
+    return out, r["acc"]
 
 
 def _errors(orc, d, acc, samples):
@@ -362,6 +385,8 @@ def main():
                     help="resolve the pairs found elastically (f = 2, as in the paper's timing "
                          "runs, keeping N constant) or only report them")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-mesh", action="store_true",
+                    help="skip the mesh-module step loop (gravity and collisions on the mesh)")
     ap.add_argument("--no-method-comparison", action="store_true",
                     help="skip the falcON / standard tree comparison (one gravity evaluation "
                          "each at p = 3 and at --p)")
@@ -422,6 +447,12 @@ def main():
               f"{batched['eager_ms_per_step']:.3f} eager, s={batched['leaf_size']}",
               file=sys.stderr, flush=True)
 
+    mesh = mesh_acc = None
+    if not args.no_mesh:
+        mesh, mesh_acc = _run_mesh(ncorp, d, args, device)
+        print(f"# mesh module: {mesh['ms_per_step']:.3f} ms/step, {mesh['mesh']}",
+              file=sys.stderr, flush=True)
+
     methods = None
     if not args.no_method_comparison:
         methods = _gravity_method_comparison(ncorp, d, sorted({3, args.p}), 5, device)
@@ -438,6 +469,8 @@ def main():
         if r64 is not None:
             err64 = _errors(orc, d, r64["acc"], args.samples)
         print(f"# errors fp32 {err32} fp64 {err64}", file=sys.stderr, flush=True)
+    if mesh is not None and not args.no_errors:
+        mesh["errors"] = _errors(orc, d, mesh_acc, args.samples)
     if methods is not None:
         for v in methods.values():
             acc = v.pop("acc")
@@ -517,6 +550,7 @@ def main():
         "collision_pairs_in_timed_steps": r32["pairs"],
         "batched": batched,
         "gravity_methods": methods,
+        "mesh_module": mesh,
     }
     print(json.dumps(out))
     return 0

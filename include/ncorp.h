@@ -122,16 +122,18 @@ typedef struct {
      * neighbourhood attract each other and are tested for collision; a moonlet
      * with 2R > gamma stays out of the mesh and interacts with every moonlet; for
      * gravity, so do the three most massive moonlets (equal masses: smaller input
-     * index first).  Nothing else interacts.  The cells are hashed into a table of
-     * mesh_cells^3 buckets (cells that share a bucket are told apart exactly).
-     *   mesh_cells: buckets per axis, 3..1024 (16 bytes of workspace per bucket);
+     * index first).  Nothing else interacts.  Occupied cells are found through a
+     * hash table keyed by the exact cell (2 n_max slots or more, 16 bytes each);
+     * cell coordinates must stay within +-(2^20 - 2).
+     *   mesh_cells, mesh_min_side: the whole grid spans at least mesh_min_side
+     *     with mesh_cells cells per axis, so gamma >= mesh_min_side / mesh_cells;
      *   mesh_neighbours: x, the mean number of neighbours aimed at;
      *   mesh_gamma: the first mesh size; 0 = Eq. (4) with aspect ratio
      *     mesh_aspect and radius mesh_rmax (0 = the largest distance of a moonlet
      *     to the central mass at the first mesh);
      *   every later mesh: gamma = gamma' (x / x')^(1/3) (Eq. 6), x' the mean
      *     number of neighbours of the moonlets of the previous mesh (x' = 0
-     *     doubles gamma), and never below mesh_min_side / mesh_cells.
+     *     doubles gamma), and never below mesh_min_side / mesh_cells (1 or more).
      * The mesh size lives in the workspace and restarts from mesh_gamma or Eq. (4)
      * when a new workspace buffer is bound.  Plain (not batched) calls only. */
     int32_t collision_method;
@@ -171,10 +173,10 @@ int ncorp_build_tree(ncorp_ctx *ctx, const double *x, const double *y, const dou
 
 /* The mesh of the mesh module (Sect. 3.3, see ncorp_params) at positions x, y, z
  * for moonlets of radii R (n FP64 each): the mesh size for this mesh (Eq. 4 at the
- * first, Eq. 6 after), the cell of every moonlet, the moonlets sorted by hash
- * bucket, the bucket table.  Needed before ncorp_gravity / ncorp_collide when
+ * first, Eq. 6 after), the cell of every moonlet, the moonlets sorted by the
+ * Morton key of their cell, the table of occupied cells.  Needed before ncorp_gravity / ncorp_collide when
  * their method is the mesh (ncorp_step builds it itself).  A cell coordinate
- * beyond +-2^30 makes ncorp_get_status return NCORP_E_INVALID; more than 1021
+ * beyond +-(2^20 - 2) makes ncorp_get_status return NCORP_E_INVALID; more than 1021
  * moonlets with 2R > gamma, NCORP_E_CAPACITY. */
 int ncorp_build_mesh(ncorp_ctx *ctx, const double *x, const double *y, const double *z,
                      const double *R, int64_t n, void *workspace, int64_t ws_bytes,

@@ -153,8 +153,8 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
         p->collision_method != NCORP_COLLISIONS_MESH) {
         std::snprintf(why, len, "collision_method must be 0 or 1"); return false;
     }
-    if (p->mesh_cells < 3 || p->mesh_cells > kMaxMeshCells) {
-        std::snprintf(why, len, "mesh_cells must be in 3..%d", kMaxMeshCells); return false;
+    if (p->mesh_cells < 1) {
+        std::snprintf(why, len, "mesh_cells must be >= 1"); return false;
     }
     if (!(p->mesh_neighbours > 0.0 && std::isfinite(p->mesh_neighbours)) ||
         !(p->mesh_aspect >= 0.0 && std::isfinite(p->mesh_aspect)) ||
@@ -335,10 +335,10 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.cand_blk = (int32_t *)take(4 * 8192);
     if (prm.gravity_method == NCORP_GRAVITY_MESH ||
         prm.collision_method == NCORP_COLLISIONS_MESH) {
-        ws.mesh_M = prm.mesh_cells;
-        ws.mtab_n = (int64_t)ws.mesh_M * ws.mesh_M * ws.mesh_M;
+        ws.mtab_n = 1024;
+        while (ws.mtab_n < 2 * n) ws.mtab_n *= 2;
         ws.mesh = (MeshState *)take(sizeof(MeshState));
-        ws.mtab = (int4 *)take(16 * ws.mtab_n);
+        ws.mtab = (MeshSlot *)take(sizeof(MeshSlot) * ws.mtab_n);
         ws.mkeys = (uint64_t *)take(8 * n);
         ws.mkeys_alt = (uint64_t *)take(8 * n);
         ws.midx = (uint32_t *)take(4 * n);
@@ -347,7 +347,8 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
         ws.mcell = (int4 *)take(16 * n);
         ws.mvel = (double4 *)take(32 * n);
         ws.mbig = (int32_t *)take(4 * (int64_t)kMaxMeshBig);
-        ws.mtop_part = (int32_t *)take(4 * 3 * 256);
+        ws.mmass = (double *)take(8 * n);
+        ws.mtop_part = take(16 * 3 * 256);
         ws.mbig_part = (double *)take(8 * 3 * 64 * (int64_t)kMaxMeshBig);
     }
     ws.bytes = off;
@@ -390,7 +391,7 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
     // unknown bytes, so the next walk clears it
     ws.clear_queue = !(c->ws.base == ws.base && c->ws.queue == ws.queue &&
                        c->ws.queue_cap == ws.queue_cap) || c->ws.clear_queue;
-    // so does the mesh state (and its table's stamps)
+    // so does the mesh state
     if (ws.mesh) {
         const bool same = c->ws.base == ws.base && c->ws.mesh == ws.mesh &&
                           c->ws.mtab == ws.mtab && c->mesh_init;

@@ -3,16 +3,15 @@
 // plus the moonlets that interact with everyone (too large for the mesh, and for
 // gravity the three most massive).
 //
-// Build: every moonlet gets its cell c = floor(r / gamma) and the hash bucket of
-// c in an M^3 table (each coordinate taken modulo M); the moonlets are sorted by
-// bucket with a stable radix sort (input order inside a bucket; moonlets kept out
-// of the mesh get the key M^3 and end up last), and each bucket records the range
-// [first, end) of its moonlets together with the build's stamp, so the table never
-// needs clearing.  A neighbourhood scan reads the 27 buckets around a cell and
-// keeps the moonlets whose cell is exactly the neighbouring cell (with M >= 3 the
-// 27 cells fall into distinct buckets, so a cell that shares a bucket is never a
-// neighbour).  Moonlets sorted by bucket sit next to the moonlets of their own
-// cell, so the lanes of a wave read overlapping buckets.
+// Build: every moonlet gets its cell c = floor(r / gamma); the moonlets are sorted
+// by the Morton key of their cell with a stable radix sort (input order inside a
+// cell; moonlets kept out of the mesh get the largest key and end up last), so each
+// occupied cell is one run of the sorted array and nearby cells sit close together.
+// The runs go into an open-addressing hash table keyed by the cell's Morton key
+// (linear probing, at most half full), which maps a cell to its range [start,
+// end).  A neighbourhood scan looks up the 27 cells around a moonlet's cell and
+// reads their moonlets: exactly the neighbours, no other cell shares an entry.  The
+// lanes of a wave hold neighbouring moonlets and look up overlapping cells.
 //
 // The mesh size: Eq. (4) at the first mesh (or the value given), then Eq. (6) from
 // the neighbour count of the previous mesh, kept on the device so that a step
@@ -27,19 +26,52 @@ constexpr int kMeshTopBlocks = 256;
 constexpr int kMeshChunks = 64;      // source chunks of the all-pairs sums
 constexpr int kMeshBigRows = 16;     // big moonlets handled side by side
 
-__device__ __forceinline__ int64_t wrap(int64_t a, int64_t M) {
-    const int64_t r = a % M;
-    return r < 0 ? r + M : r;
+// 21 bits of v spread to every third bit
+__device__ __forceinline__ unsigned long long spread3(unsigned long long v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
 }
 
-__device__ __forceinline__ int64_t bucket_of(int cx, int cy, int cz, int M) {
-    return wrap(cx, M) + (int64_t)M * (wrap(cy, M) + (int64_t)M * wrap(cz, M));
+// Morton key of a cell (coordinates within +-kMeshCellLimit)
+__device__ __forceinline__ unsigned long long cell_key(int x, int y, int z) {
+    return spread3((unsigned)(x + kMeshCellLimit)) |
+           (spread3((unsigned)(y + kMeshCellLimit)) << 1) |
+           (spread3((unsigned)(z + kMeshCellLimit)) << 2);
 }
 
-// cell of a position; false if a coordinate leaves +-kMeshCellLimit
+// table slot where the probe for a key starts (a 64-bit mixing step, then the
+// table's power-of-two mask)
+__device__ __forceinline__ int64_t slot_of(unsigned long long k, int64_t mask) {
+    k ^= k >> 31;
+    k *= 0x7fb5d329728ea185ull;
+    k ^= k >> 27;
+    k *= 0x81dadef4bc2dd44dull;
+    k ^= k >> 33;
+    return (int64_t)(k & (unsigned long long)mask);
+}
+
+// range of the moonlets of a cell, (0, 0) if it holds none
+__device__ __forceinline__ int2 lookup(const MeshSlot *__restrict__ tab, int64_t mask,
+                                      unsigned long long k) {
+    int64_t h = slot_of(k, mask);
+    for (int64_t probes = 0; probes <= mask; probes++) {
+        const MeshSlot e = tab[h];
+        if (e.key == k) return make_int2(e.start, e.end);
+        if (e.key == kMeshEmpty) break;
+        h = (h + 1) & mask;
+    }
+    return make_int2(0, 0);
+}
+
+// cell of a position; false if a coordinate reaches +-(kMeshCellLimit - 1)
 __device__ __forceinline__ bool cell_of(double x, double y, double z, double g, int4 &c) {
     const double fx = floor(x / g), fy = floor(y / g), fz = floor(z / g);
-    const double lim = (double)kMeshCellLimit;
+    const double lim = (double)(kMeshCellLimit - 1);  // neighbours stay in 21 bits
     if (!(fabs(fx) < lim && fabs(fy) < lim && fabs(fz) < lim)) return false;
     c.x = (int)fx; c.y = (int)fy; c.z = (int)fz; c.w = 0;
     return true;
@@ -57,14 +89,17 @@ __device__ __forceinline__ void add_pull(double4 src, double x, double y, double
 }
 
 // ------------------------------------------------------------------ build
-__global__ void k_mesh_clear(int4 *tab, int64_t nb, MeshState *ms) {
-    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
-         b += (int64_t)gridDim.x * blockDim.x)
-        tab[b] = make_int4(0, 0, 0, 0);
+__global__ void k_mesh_clear_state(MeshState *ms) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         MeshState z = {};
         *ms = z;
     }
+}
+
+__global__ void k_mesh_clear_table(MeshSlot *tab, int64_t nslots) {
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nslots;
+         b += (int64_t)gridDim.x * blockDim.x)
+        tab[b].key = kMeshEmpty;
 }
 
 __global__ void k_mesh_rmax(const double *__restrict__ x, const double *__restrict__ y,
@@ -84,7 +119,7 @@ __global__ void k_mesh_rmax(const double *__restrict__ x, const double *__restri
         atomicMax((unsigned long long *)&ms->rmax2, (unsigned long long)__double_as_longlong(m));
 }
 
-// the mesh size of the new mesh (Eq. 4 at the first mesh, Eq. 6 after), new stamp
+// the mesh size of the new mesh (Eq. 4 at the first mesh, Eq. 6 after)
 __global__ void k_mesh_begin(MeshState *ms, DevState *st, int64_t n, double x_target,
                              double aspect, double rmax, double gamma0, double gamma_min) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -119,15 +154,15 @@ __global__ void k_mesh_begin(MeshState *ms, DevState *st, int64_t n, double x_ta
 __global__ void k_mesh_keys(DevState *st, const MeshState *__restrict__ ms,
                             const double *__restrict__ x, const double *__restrict__ y,
                             const double *__restrict__ z, const double *__restrict__ R, int64_t n,
-                            int M, uint64_t *keys, uint32_t *vals) {
+                            uint64_t *keys, uint32_t *vals) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double g = ms->gamma;
-    uint64_t key = (uint64_t)M * M * M;            // out of the mesh: sorted last
+    uint64_t key = kMeshEmpty;                     // out of the mesh: sorted last
     if (!(2.0 * R[i] > g)) {
         int4 c;
         if (cell_of(x[i], y[i], z[i], g, c))
-            key = (uint64_t)bucket_of(c.x, c.y, c.z, M);
+            key = cell_key(c.x, c.y, c.z);
         else if (isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i]))
             atomicOr(&st->status, (int32_t)ST_MESH_RANGE);
         else
@@ -137,116 +172,179 @@ __global__ void k_mesh_keys(DevState *st, const MeshState *__restrict__ ms,
     vals[i] = (uint32_t)i;
 }
 
-// sorted positions, cells, bucket ranges; the first out-of-mesh position is n_in
-__global__ void k_mesh_table(DevState *st, MeshState *ms, const uint64_t *__restrict__ keys,
-                             const uint32_t *__restrict__ idx, const double *__restrict__ x,
-                             const double *__restrict__ y, const double *__restrict__ z,
-                             int64_t n, int M, int4 *tab, double4 *mpos, int4 *mcell) {
+// sorted positions and cells; the first out-of-mesh position is n_in; the first
+// moonlet of every cell claims the cell's slot
+__global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restrict__ keys,
+                            const uint32_t *__restrict__ idx, const double *__restrict__ x,
+                            const double *__restrict__ y, const double *__restrict__ z,
+                            int64_t n, MeshSlot *tab, int64_t mask, double4 *mpos, int4 *mcell) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n || (st->status & kSkipMask)) return;
     const uint32_t i = idx[q];
     const double g = ms->gamma;
     mpos[q] = make_double4(x[i], y[i], z[i], 0.0);
-    const uint64_t out = (uint64_t)M * M * M;
     const uint64_t k = keys[q];
-    if (k == out) {
-        if (q == 0 || keys[q - 1] != out) ms->n_in = (int32_t)q;
+    if (k == kMeshEmpty) {
+        if (q == 0 || keys[q - 1] != kMeshEmpty) ms->n_in = (int32_t)q;
         mcell[q] = make_int4(0, 0, 0, 0);
         return;
     }
     int4 c;
     cell_of(x[i], y[i], z[i], g, c);               // in range: checked by k_mesh_keys
     mcell[q] = c;
-    const int stamp = ms->stamp;
-    if (q == 0 || keys[q - 1] != k) {
-        tab[k].x = (int)q;
-        tab[k].z = stamp;
+    if (q > 0 && keys[q - 1] == k) return;
+    // the table holds at most n_in <= half its slots, so a free slot is always found
+    int64_t h = slot_of(k, mask);
+    for (int64_t probes = 0; probes <= mask; probes++) {
+        const unsigned long long prev = atomicCAS(&tab[h].key, kMeshEmpty, k);
+        if (prev == kMeshEmpty) {
+            tab[h].start = (int32_t)q;
+            return;
+        }
+        h = (h + 1) & mask;
     }
-    if (q == n - 1 || keys[q + 1] != k) tab[k].y = (int)(q + 1);
+    atomicOr(&st->status, (int32_t)ST_CAP_MESH);   // unreachable at half load
+}
+
+// the last moonlet of every cell closes its range
+__global__ void k_mesh_run_ends(const DevState *__restrict__ st, const uint64_t *__restrict__ keys,
+                                int64_t n, MeshSlot *tab, int64_t mask) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n || (st->status & kSkipMask)) return;
+    const uint64_t k = keys[q];
+    if (k == kMeshEmpty || (q + 1 < n && keys[q + 1] == k)) return;
+    int64_t h = slot_of(k, mask);
+    for (int64_t probes = 0; probes <= mask; probes++) {
+        if (tab[h].key == k) {
+            tab[h].end = (int32_t)(q + 1);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
 }
 
 // ------------------------------------------------------------------ gravity
-// mu = G m in sorted order
+// mu = G m and m in sorted order
 __global__ void k_mesh_mu(const uint32_t *__restrict__ idx, const double *__restrict__ m,
-                          double G, int64_t n, double4 *mpos) {
+                          double G, int64_t n, double4 *mpos, double *mmass) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q < n) mpos[q].w = G * m[idx[q]];
+    if (q < n) {
+        const double mi = m[idx[q]];
+        mpos[q].w = G * mi;
+        mmass[q] = mi;
+    }
 }
+
+// a candidate for the three most massive: mass, input index, sorted position
+struct Cand {
+    double m;
+    uint32_t i;
+    int q;                     // -1: none
+};
+static_assert(sizeof(Cand) == 16, "top-three candidates take 16 bytes");
 
 // a before b: larger mass, then smaller input index
-__device__ __forceinline__ bool heavier(const double *m, const uint32_t *idx, int a, int b) {
-    if (b < 0) return a >= 0;
-    if (a < 0) return false;
-    const double ma = m[idx[a]], mb = m[idx[b]];
-    return ma > mb || (ma == mb && idx[a] < idx[b]);
+__device__ __forceinline__ bool heavier(const Cand &a, const Cand &b) {
+    if (a.q < 0) return false;
+    if (b.q < 0) return true;
+    return a.m > b.m || (a.m == b.m && a.i < b.i);
 }
 
-__device__ __forceinline__ void keep_top3(const double *m, const uint32_t *idx, int t[3], int c) {
-    if (heavier(m, idx, c, t[0])) { t[2] = t[1]; t[1] = t[0]; t[0] = c; }
-    else if (heavier(m, idx, c, t[1])) { t[2] = t[1]; t[1] = c; }
-    else if (heavier(m, idx, c, t[2])) t[2] = c;
+__device__ __forceinline__ void insert3(Cand t[3], const Cand &c) {
+    if (heavier(c, t[0])) { t[2] = t[1]; t[1] = t[0]; t[0] = c; }
+    else if (heavier(c, t[1])) { t[2] = t[1]; t[1] = c; }
+    else if (heavier(c, t[2])) t[2] = c;
+}
+
+// the best three of a wave's lists (every lane ends with them)
+__device__ __forceinline__ void wave_top3(Cand t[3]) {
+    for (int o = 32; o > 0; o >>= 1) {
+        Cand u[3];
+        for (int k = 0; k < 3; k++) {
+            u[k].m = __shfl_xor(t[k].m, o);
+            u[k].i = (uint32_t)__shfl_xor((int)t[k].i, o);
+            u[k].q = __shfl_xor(t[k].q, o);
+        }
+        for (int k = 0; k < 3; k++) insert3(t, u[k]);
+    }
+}
+
+// block-wide best three into t of thread 0
+__device__ __forceinline__ void block_top3(Cand t[3], Cand *lds) {
+    wave_top3(t);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        for (int k = 0; k < 3; k++) lds[3 * w + k] = t[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int v = 1; v < (int)(blockDim.x / kWave); v++)
+            for (int k = 0; k < 3; k++) insert3(t, lds[3 * v + k]);
 }
 
 __global__ void __launch_bounds__(kMeshBlock)
-k_mesh_top_part(const DevState *__restrict__ st, const double *__restrict__ m,
-                const uint32_t *__restrict__ idx, int64_t n, int32_t *part) {
-    __shared__ int cand[kMeshBlock * 3];
+k_mesh_top_part(const DevState *__restrict__ st, const double *__restrict__ mmass,
+                const uint32_t *__restrict__ idx, int64_t n, Cand *part) {
+    __shared__ Cand lds[3 * kMeshBlock / kWave];
     if (st->status & kSkipMask) return;
-    int t[3] = {-1, -1, -1};
+    Cand t[3];
+    for (int k = 0; k < 3; k++) t[k] = Cand{0.0, 0u, -1};
     for (int64_t q = blockIdx.x * (int64_t)kMeshBlock + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * kMeshBlock)
-        keep_top3(m, idx, t, (int)q);
-    for (int k = 0; k < 3; k++) cand[3 * threadIdx.x + k] = t[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int b[3] = {-1, -1, -1};
-        for (int k = 0; k < kMeshBlock * 3; k++) keep_top3(m, idx, b, cand[k]);
-        for (int k = 0; k < 3; k++) part[3 * blockIdx.x + k] = b[k];
-    }
+        insert3(t, Cand{mmass[q], idx[q], (int)q});
+    block_top3(t, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; k++) part[3 * blockIdx.x + k] = t[k];
 }
 
 // the three most massive, and gravity's all-pairs list: the moonlets out of the
 // mesh (sorted positions n_in..n-1), then the three most massive that are in it
-__global__ void k_mesh_top_final(DevState *st, MeshState *ms, const double *__restrict__ m,
-                                 const uint32_t *__restrict__ idx, int64_t n,
-                                 const int32_t *__restrict__ part, int32_t *big) {
-    if (threadIdx.x != 0 || blockIdx.x != 0 || (st->status & kSkipMask)) return;
-    int b[3] = {-1, -1, -1};
-    for (int k = 0; k < kMeshTopBlocks * 3; k++) keep_top3(m, idx, b, part[k]);
-    int ntop = 0;
-    for (int k = 0; k < 3; k++)
-        if (b[k] >= 0) ms->top[ntop++] = b[k];
-    for (int k = ntop; k < 3; k++) ms->top[k] = -1;
-    ms->ntop = ntop;
+__global__ void __launch_bounds__(kMeshTopBlocks)
+k_mesh_top_final(DevState *st, MeshState *ms, int64_t n, const Cand *__restrict__ part,
+                 int32_t *big) {
+    __shared__ Cand lds[3 * kMeshTopBlocks / kWave];
+    __shared__ int s_nbig;
+    if (st->status & kSkipMask) return;
+    Cand t[3];
+    for (int k = 0; k < 3; k++) t[k] = part[3 * threadIdx.x + k];
+    block_top3(t, lds);
     const int n_in = ms->n_in;
     const int nover = (int)n - n_in;
-    int nbig = 0;
-    for (int k = 0; k < ntop; k++) nbig += ms->top[k] < n_in;
-    if (nover + nbig > kMaxMeshBig) {
-        atomicOr(&st->status, (int32_t)ST_CAP_MESH);
-        atomicMax((unsigned long long *)&st->required, (unsigned long long)(nover + nbig));
-        ms->nbig = 0;
-        return;
+    if (threadIdx.x == 0) {
+        int ntop = 0, nbig = nover;
+        for (int k = 0; k < 3; k++)
+            if (t[k].q >= 0) ms->top[ntop++] = t[k].q;
+        for (int k = ntop; k < 3; k++) ms->top[k] = -1;
+        ms->ntop = ntop;
+        for (int k = 0; k < ntop; k++) nbig += ms->top[k] < n_in;
+        if (nbig > kMaxMeshBig) {
+            atomicOr(&st->status, (int32_t)ST_CAP_MESH);
+            atomicMax((unsigned long long *)&st->required, (unsigned long long)nbig);
+            nbig = 0;
+        } else {
+            int b = nover;
+            for (int k = 0; k < ntop; k++)
+                if (ms->top[k] < n_in) big[b++] = ms->top[k];
+        }
+        ms->nbig = nbig;
+        s_nbig = nbig;
     }
-    for (int k = 0; k < nover; k++) big[k] = n_in + k;
-    nbig = nover;
-    for (int k = 0; k < ntop; k++)
-        if (ms->top[k] < n_in) big[nbig++] = ms->top[k];
-    ms->nbig = nbig;
+    __syncthreads();
+    if (s_nbig > 0)
+        for (int k = threadIdx.x; k < nover; k += blockDim.x) big[k] = n_in + k;
 }
 
 // One thread per moonlet of the mesh (sorted order): its neighbours (not among the
-// all-pairs moonlets) in bucket order, then the all-pairs moonlets.  The three most
+// all-pairs moonlets) cell by cell, then the all-pairs moonlets.  The three most
 // massive only count their neighbours here; their sums come from k_mesh_big_sum.
 __global__ void __launch_bounds__(kMeshBlock)
-k_mesh_gravity(DevState *st, MeshState *ms, const int4 *__restrict__ tab,
+k_mesh_gravity(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, int64_t mask,
                const double4 *__restrict__ mpos, const int4 *__restrict__ mcell,
-               const uint32_t *__restrict__ idx, const int32_t *__restrict__ big, int M,
+               const uint32_t *__restrict__ idx, const int32_t *__restrict__ big,
                int count, double *__restrict__ ax, double *__restrict__ ay,
                double *__restrict__ az) {
     if (st->status & kSkipMask) return;
     const int64_t q = blockIdx.x * (int64_t)kMeshBlock + threadIdx.x;
-    const int n_in = ms->n_in, stamp = ms->stamp, nbig = ms->nbig;
+    const int n_in = ms->n_in, nbig = ms->nbig;
     const int t0 = ms->top[0], t1 = ms->top[1], t2 = ms->top[2];
     unsigned long long cnt = 0;
     if (q < n_in) {
@@ -257,12 +355,9 @@ k_mesh_gravity(DevState *st, MeshState *ms, const int4 *__restrict__ tab,
         for (int dz = -1; dz <= 1; dz++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dx = -1; dx <= 1; dx++) {
-                    const int4 e = tab[bucket_of(c.x + dx, c.y + dy, c.z + dz, M)];
-                    if (e.z != stamp) continue;
+                    const int2 e = lookup(tab, mask, cell_key(c.x + dx, c.y + dy, c.z + dz));
                     for (int r = e.x; r < e.y; r++) {
                         if (r == q) continue;
-                        const int4 cr = mcell[r];
-                        if (cr.x != c.x + dx || cr.y != c.y + dy || cr.z != c.z + dz) continue;
                         cnt++;
                         if (top || r == t0 || r == t1 || r == t2) continue;
                         add_pull(mpos[r], p.x, p.y, p.z, a0, a1, a2);
@@ -350,13 +445,13 @@ __global__ void k_mesh_col_init(DevState *st) {
 
 // one thread per moonlet of the mesh: its neighbours later in sorted order
 __global__ void __launch_bounds__(kMeshBlock)
-k_mesh_collide(DevState *st, MeshState *ms, const int4 *__restrict__ tab,
+k_mesh_collide(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, int64_t mask,
                const double4 *__restrict__ mpos, const double4 *__restrict__ mvel,
-               const int4 *__restrict__ mcell, const uint32_t *__restrict__ idx, int M, double dt,
+               const int4 *__restrict__ mcell, const uint32_t *__restrict__ idx, double dt,
                int count, int64_t *out, int64_t cap) {
     if (st->status & kSkipMask) return;
     const int64_t q = blockIdx.x * (int64_t)kMeshBlock + threadIdx.x;
-    const int n_in = ms->n_in, stamp = ms->stamp;
+    const int n_in = ms->n_in;
     unsigned long long cnt = 0, tests = 0;
     if (q < n_in) {
         const double4 p = mpos[q], v = mvel[q];
@@ -364,12 +459,9 @@ k_mesh_collide(DevState *st, MeshState *ms, const int4 *__restrict__ tab,
         for (int dz = -1; dz <= 1; dz++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dx = -1; dx <= 1; dx++) {
-                    const int4 e = tab[bucket_of(c.x + dx, c.y + dy, c.z + dz, M)];
-                    if (e.z != stamp) continue;
+                    const int2 e = lookup(tab, mask, cell_key(c.x + dx, c.y + dy, c.z + dz));
                     for (int r = e.x; r < e.y; r++) {
                         if (r == q) continue;
-                        const int4 cr = mcell[r];
-                        if (cr.x != c.x + dx || cr.y != c.y + dy || cr.z != c.z + dz) continue;
                         cnt++;
                         if (r < q) continue;
                         const double4 pr = mpos[r], vr = mvel[r];
@@ -435,37 +527,38 @@ int grid_of(int64_t n, int block) { return (int)((n + block - 1) / block); }
 hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double *y,
                              const double *z, const double *R, int64_t n, const ncorp_params &prm,
                              bool first, hipStream_t s) {
-    const int M = ws.mesh_M;
-    if (ws.clear_mesh)
-        k_mesh_clear<<<4096, 256, 0, s>>>(ws.mtab, ws.mtab_n, ws.mesh);
+    const int64_t mask = ws.mtab_n - 1;
+    if (ws.clear_mesh) k_mesh_clear_state<<<1, 64, 0, s>>>(ws.mesh);
     if (first && prm.mesh_gamma <= 0.0 && prm.mesh_rmax <= 0.0)
         k_mesh_rmax<<<1024, 256, 0, s>>>(x, y, z, n, ws.mesh);
     k_mesh_begin<<<1, 64, 0, s>>>(ws.mesh, ws.st, n, prm.mesh_neighbours, prm.mesh_aspect,
-                                  prm.mesh_rmax, prm.mesh_gamma, prm.mesh_min_side / M);
-    k_mesh_keys<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, x, y, z, R, n, M, ws.mkeys,
+                                  prm.mesh_rmax, prm.mesh_gamma,
+                                  prm.mesh_min_side / prm.mesh_cells);
+    k_mesh_clear_table<<<grid_of(ws.mtab_n, 256) < 4096 ? grid_of(ws.mtab_n, 256) : 4096, 256, 0,
+                         s>>>(ws.mtab, ws.mtab_n);
+    k_mesh_keys<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, x, y, z, R, n, ws.mkeys,
                                                 ws.midx);
-    // key M^3 marks the moonlets out of the mesh; whole 16-bit digit pairs keep
-    // the sorted result in mkeys / midx
-    int bits = 1;
-    while (bits < 62 && ((uint64_t)1 << bits) <= (uint64_t)M * M * M) bits++;
-    bits = (bits + 15) / 16 * 16;
+    // 64-bit keys: eight 8-bit passes leave the result in mkeys / midx
     bool in_b = false;
-    hipError_t e = launch_radix_sort(ws.mkeys, ws.midx, ws.mkeys_alt, ws.midx_alt, n, bits,
-                                     ws.hist, &in_b, s);
+    hipError_t e = launch_radix_sort(ws.mkeys, ws.midx, ws.mkeys_alt, ws.midx_alt, n, 64, ws.hist,
+                                     &in_b, s);
     if (e != hipSuccess) return e;
     if (in_b) return hipErrorInvalidValue;
-    k_mesh_table<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, ws.midx, x, y, z, n,
-                                                 M, ws.mtab, ws.mpos, ws.mcell);
+    k_mesh_runs<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, ws.midx, x, y, z, n,
+                                                ws.mtab, mask, ws.mpos, ws.mcell);
+    k_mesh_run_ends<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mkeys, n, ws.mtab, mask);
     return hipGetLastError();
 }
 
 hipError_t launch_mesh_gravity(const Workspace &ws, const double *m, double G, int64_t n,
                                bool count, double *ax, double *ay, double *az, hipStream_t s) {
-    k_mesh_mu<<<grid_of(n, 256), 256, 0, s>>>(ws.midx, m, G, n, ws.mpos);
-    k_mesh_top_part<<<kMeshTopBlocks, kMeshBlock, 0, s>>>(ws.st, m, ws.midx, n, ws.mtop_part);
-    k_mesh_top_final<<<1, 64, 0, s>>>(ws.st, ws.mesh, m, ws.midx, n, ws.mtop_part, ws.mbig);
+    k_mesh_mu<<<grid_of(n, 256), 256, 0, s>>>(ws.midx, m, G, n, ws.mpos, ws.mmass);
+    Cand *part = reinterpret_cast<Cand *>(ws.mtop_part);
+    k_mesh_top_part<<<kMeshTopBlocks, kMeshBlock, 0, s>>>(ws.st, ws.mmass, ws.midx, n, part);
+    k_mesh_top_final<<<1, kMeshTopBlocks, 0, s>>>(ws.st, ws.mesh, n, part, ws.mbig);
     k_mesh_gravity<<<grid_of(n, kMeshBlock), kMeshBlock, 0, s>>>(
-        ws.st, ws.mesh, ws.mtab, ws.mpos, ws.mcell, ws.midx, ws.mbig, ws.mesh_M, count ? 1 : 0,
+        ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mpos, ws.mcell, ws.midx, ws.mbig,
+        count ? 1 : 0,
         ax, ay, az);
     k_mesh_big_sum<<<dim3(kMeshChunks, kMeshBigRows), kMeshBlock, 0, s>>>(ws.st, ws.mesh,
                                                                          ws.mpos, ws.mbig, n,
@@ -481,7 +574,7 @@ hipError_t launch_mesh_collide(const Workspace &ws, const double *vx, const doub
     k_mesh_vel<<<grid_of(n, 256), 256, 0, s>>>(ws.midx, vx, vy, vz, R, n, ws.mvel);
     k_mesh_col_init<<<1, 64, 0, s>>>(ws.st);
     k_mesh_collide<<<grid_of(n, kMeshBlock), kMeshBlock, 0, s>>>(
-        ws.st, ws.mesh, ws.mtab, ws.mpos, ws.mvel, ws.mcell, ws.midx, ws.mesh_M, dt,
+        ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mpos, ws.mvel, ws.mcell, ws.midx, dt,
         count ? 1 : 0, ws.pairs_tmp, ws.pair_cap);
     k_mesh_collide_out<<<dim3(kMeshChunks, kMeshBigRows), kMeshBlock, 0, s>>>(
         ws.st, ws.mesh, ws.mpos, ws.mvel, ws.midx, n, dt, ws.pairs_tmp, ws.pair_cap);

@@ -112,8 +112,14 @@ struct DevState {
 // Moonlets that interact with every other one in the mesh module: those too large
 // for the mesh (2R > gamma) and, for gravity, the three most massive.
 constexpr int kMaxMeshBig = 1024;
-constexpr int kMaxMeshCells = 1024;    // hash-table cells per axis
-constexpr int kMeshCellLimit = 1 << 30;  // |cell coordinate| bound
+constexpr int kMeshCellLimit = 1 << 20;  // |cell coordinate| bound (21-bit Morton axes)
+// a slot of the mesh's cell table: the Morton key of an occupied cell and the
+// range [start, end) of its moonlets in sorted order
+struct MeshSlot {
+    unsigned long long key;            // kMeshEmpty: free
+    int32_t start, end;
+};
+constexpr unsigned long long kMeshEmpty = ~0ull;
 // State of the mesh across builds (lives in the workspace, cleared when a new
 // workspace buffer is bound).
 struct MeshState {
@@ -121,7 +127,7 @@ struct MeshState {
     double rmax2;                      // max |r|^2 at the first mesh (R_max of Eq. 4)
     unsigned long long nbr_sum;        // (moonlet, neighbour) pairs counted on it
     int32_t n_in;                      // moonlets in the mesh: the sorted prefix
-    int32_t stamp;                     // build counter, carried by its table entries
+    int32_t stamp;                     // build counter
     int32_t init;                      // gamma has been set
     int32_t measured;                  // nbr_sum counted on the current mesh
     int32_t ntop;                      // the three most massive (sorted positions)
@@ -250,11 +256,11 @@ struct Workspace {
     double *disk_L = nullptr;
     int32_t *disk_root = nullptr;                     // level-0 cell of each disk
     int ndisks = 1;                                   // host copy; 1 = plain call
-    // mesh module (present when a method uses it): hash table of M^3 buckets
-    // (first, end, stamp), moonlets sorted by bucket (oversized ones last)
+    // mesh module (present when a method uses it): moonlets sorted by the Morton
+    // key of their cell (those out of the mesh last), and an open-addressing table
+    // of the occupied cells (a power of two >= 2 n_max slots)
     MeshState *mesh = nullptr;
-    int4 *mtab = nullptr;
-    int mesh_M = 0;
+    MeshSlot *mtab = nullptr;
     int64_t mtab_n = 0;
     uint64_t *mkeys = nullptr, *mkeys_alt = nullptr;
     uint32_t *midx = nullptr, *midx_alt = nullptr;   // sorted position -> input index
@@ -262,7 +268,8 @@ struct Workspace {
     int4 *mcell = nullptr;                            // cell coordinates (sorted)
     double4 *mvel = nullptr;                          // vx, vy, vz, R (sorted)
     int32_t *mbig = nullptr;                          // kMaxMeshBig sorted positions
-    int32_t *mtop_part = nullptr;                     // per-block top-three candidates
+    double *mmass = nullptr;                          // masses (sorted)
+    void *mtop_part = nullptr;                        // per-block top-three candidates
     double *mbig_part = nullptr;                      // partial sums of the big ones
     DevState *st = nullptr;
     bool clear_queue = false;                         // new buffer: clear before next walk

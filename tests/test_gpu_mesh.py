@@ -1,8 +1,8 @@
 """GPU parity of the mesh module (Sect. 3.3): accelerations equal to the oracle's
 neighbour + three-most-massive + oversized pair set to FP64 rounding, colliding
 pairs bit for bit, the mesh size of Eq. (4) and the neighbour count of Eq. (6),
-hash tables small enough that far cells share buckets, moonlets too large for the
-mesh, and leapfrog steps with the mesh size following Eq. (6) from step to step."""
+meshes from a single cell to cells barely larger than the moonlets, moonlets too
+large for the mesh, and leapfrog steps with the mesh size following Eq. (6) from step to step."""
 
 import numpy as np
 import pytest
@@ -51,10 +51,10 @@ def _big_masses(d, idx, factor=1000.0):
 
 
 CASES = {
-    # name: (generator, gamma, table cells per axis, dt)
+    # name: (generator, gamma, cells per axis of the whole grid, dt)
     "gas5k_g0.05_M64": (lambda: inputs.gas_box(5000, seed=1, radius=0.01), 0.05, 64, 0.005),
-    "gas5k_g0.05_M3_aliased": (lambda: inputs.gas_box(5000, seed=1, radius=0.01), 0.05, 3,
-                               0.005),
+    "gas5k_g0.021_fine": (lambda: inputs.gas_box(5000, seed=1, radius=0.01), 0.021, 3,
+                          0.005),
     "disk8k_g0.15_M16": (lambda: inputs.disk(8000, seed=2), 0.15, 16, 1e-3),
     "disk8k_big3_g0.3_M5": (lambda: _big_masses(inputs.disk(8000, seed=3), [7, 4000, 7999]),
                             0.3, 5, 1e-3),
