@@ -64,6 +64,12 @@ def lib():
     L.orc_mesh_accel.argtypes = [_f64, _f64, _f64, _f64, _f64, i64, d, d, _f64, _f64, _f64]
     L.orc_mesh_pairs.restype = i64
     L.orc_mesh_pairs.argtypes = [_f64] * 8 + [i64, d, d, _i64, i64]
+    L.orc_grav_run_std_targets.restype = None
+    L.orc_grav_run_std_targets.argtypes = [vp, i32, i32, _i64, i64, _f64]
+    L.orc_mesh_accel_targets.restype = None
+    L.orc_mesh_accel_targets.argtypes = [_f64] * 5 + [i64, d, d, _i64, i64, _f64]
+    L.orc_mesh_pairs_of.restype = i64
+    L.orc_mesh_pairs_of.argtypes = [_f64] * 8 + [i64, d, d, _i64, i64, _i64, i64]
     L.orc_grav_run_std.restype = None
     L.orc_grav_run_std.argtypes = [vp, i32, i32]
     L.orc_root_half_width.restype = d
@@ -277,6 +283,13 @@ class Gravity:
         lib().orc_grav_run_std(self._h, ncb_pre, ncb_post)
         return self
 
+    def standard_targets(self, ncb_pre: int, ncb_post: int, targets) -> np.ndarray:
+        """Standard-tree accelerations of the given moonlets only (input indices)."""
+        t = _c(targets, np.int64)
+        out = np.zeros((len(t), 3))
+        lib().orc_grav_run_std_targets(self._h, ncb_pre, ncb_post, t, len(t), out)
+        return out
+
     def accel(self) -> np.ndarray:
         n = self.tree.n
         ax, ay, az = np.zeros(n), np.zeros(n), np.zeros(n)
@@ -478,6 +491,26 @@ def mesh_accel(d: dict, gamma: float, G: float = 1.0) -> np.ndarray:
     lib().orc_mesh_accel(_c(d["x"]), _c(d["y"]), _c(d["z"]), _c(d["m"]), _c(d["R"]), n,
                          float(G), float(gamma), ax, ay, az)
     return np.stack([ax, ay, az], axis=1)
+
+
+def mesh_accel_of(d: dict, gamma: float, targets, G: float = 1.0) -> np.ndarray:
+    """Mesh-module accelerations of the given moonlets only (input indices)."""
+    t = _c(targets, np.int64)
+    out = np.zeros((len(t), 3))
+    lib().orc_mesh_accel_targets(_c(d["x"]), _c(d["y"]), _c(d["z"]), _c(d["m"]), _c(d["R"]),
+                                 len(d["x"]), float(G), float(gamma), t, len(t), out)
+    return out
+
+
+def mesh_pairs_of(d: dict, gamma: float, dt: float, targets, cap: int = 1 << 20) -> np.ndarray:
+    """Colliding mesh pairs that involve one of the targets (sorted, distinct)."""
+    t = np.unique(_c(targets, np.int64))
+    out = np.zeros((cap, 2), np.int64)
+    k = lib().orc_mesh_pairs_of(*(_c(d[f]) for f in ("x", "y", "z", "vx", "vy", "vz", "m", "R")),
+                                len(d["x"]), float(gamma), float(dt), t, len(t), out, cap)
+    if k > cap:
+        return mesh_pairs_of(d, gamma, dt, targets, cap=int(k))
+    return out[:k]
 
 
 def mesh_pairs(d: dict, gamma: float, dt: float, cap: int = 1 << 20) -> np.ndarray:

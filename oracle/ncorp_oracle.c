@@ -968,6 +968,21 @@ void orc_grav_run_std(orc_grav *g, int ncb_pre, int ncb_post)
     }
 }
 
+/* The standard tree's accelerations of a few moonlets only (input indices in     */
+/* targets; out: nt x 3), for checks at sizes where walking every moonlet is slow. */
+void orc_grav_run_std_targets(orc_grav *g, int ncb_pre, int ncb_post, const int64_t *targets,
+                              int64_t nt, double *out)
+{
+    int64_t *where = (int64_t *)malloc((size_t)g->n * sizeof(int64_t));
+    for (int64_t k = 0; k < g->n; k++) where[g->t->perm[k]] = k;
+    for (int64_t q = 0; q < nt; q++) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (g->p > 0) std_walk(g, where[targets[q]], 0, ncb_pre, ncb_post, acc);
+        out[3 * q] = acc[0]; out[3 * q + 1] = acc[1]; out[3 * q + 2] = acc[2];
+    }
+    free(where);
+}
+
 void orc_grav_accel(const orc_grav *g, double *ax, double *ay, double *az)
 {
     for (int64_t k = 0; k < g->n; k++) {
@@ -1497,5 +1512,64 @@ int64_t orc_mesh_pairs(const double *x, const double *y, const double *z, const 
             total++;
         }
     free(flags);
+    return total;
+}
+
+/* mesh accelerations of a few moonlets only (input indices; out: nt x 3) */
+void orc_mesh_accel_targets(const double *x, const double *y, const double *z, const double *m,
+                            const double *R, int64_t n, double G, double gamma,
+                            const int64_t *targets, int64_t nt, double *out)
+{
+    int32_t *flags = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    orc_mesh_flags(m, R, n, gamma, flags);
+    for (int64_t q = 0; q < nt; q++) {
+        const int64_t i = targets[q];
+        double a[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i || !mesh_pair(x, y, z, flags, 3, i, j, gamma)) continue;
+            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2), r3 = r2 * r, mu = G * m[j];
+            a[0] += mu * dx / r3;
+            a[1] += mu * dy / r3;
+            a[2] += mu * dz / r3;
+        }
+        out[3 * q] = a[0]; out[3 * q + 1] = a[1]; out[3 * q + 2] = a[2];
+    }
+    free(flags);
+}
+
+/* colliding pairs of the mesh that involve one of the targets (i < j, increasing,
+ * each once; targets sorted increasing and distinct) */
+int64_t orc_mesh_pairs_of(const double *x, const double *y, const double *z, const double *vx,
+                          const double *vy, const double *vz, const double *m, const double *R,
+                          int64_t n, double gamma, double dt, const int64_t *targets, int64_t nt,
+                          int64_t *out, int64_t cap)
+{
+    int32_t *flags = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    char *is_t = (char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    orc_mesh_flags(m, R, n, gamma, flags);
+    for (int64_t q = 0; q < nt; q++) is_t[targets[q]] = 1;
+    int64_t total = 0;
+    for (int64_t q = 0; q < nt; q++) {
+        const int64_t t = targets[q];
+        for (int64_t j = 0; j < n; j++) {
+            if (j == t) continue;
+            if (is_t[j] && j < t) continue;           /* a pair of two targets once */
+            if (!mesh_pair(x, y, z, flags, 1, t, j, gamma)) continue;
+            if (!orc_pair_test(x[t], y[t], z[t], vx[t], vy[t], vz[t], R[t], x[j], y[j], z[j],
+                               vx[j], vy[j], vz[j], R[j], dt))
+                continue;
+            if (total < cap) {
+                out[2 * total] = t < j ? t : j;
+                out[2 * total + 1] = t < j ? j : t;
+            }
+            total++;
+        }
+    }
+    if (total <= cap) qsort(out, (size_t)total, 2 * sizeof(int64_t), cmp_pair);
+    free(flags);
+    free(is_t);
     return total;
 }

@@ -197,3 +197,15 @@ def test_three_most_massive_ties_and_small_n(orc):
     m = np.full(5, 1.0)
     assert orc.mesh_flags(m, np.full(5, 1e-3), 1.0).tolist() == [2, 2, 2, 0, 0]
     assert orc.mesh_flags(np.array([1.0, 2.0]), np.full(2, 1e-3), 1.0).tolist() == [2, 2]
+
+
+def test_sampled_forms_equal_full_forms(orc):
+    """Per-target accelerations and pairs equal the full results restricted to them."""
+    d = inputs.gas_box(3000, seed=13, radius=0.01)
+    d["R"][[3, 30]] = 0.08                      # two oversized moonlets for gamma = 0.1
+    tg = np.arange(0, 3000, 7)
+    assert np.array_equal(orc.mesh_accel_of(d, 0.1, tg), orc.mesh_accel(d, 0.1)[tg])
+    allp = orc.mesh_pairs(d, 0.1, 0.005)
+    want = allp[np.isin(allp[:, 0], tg) | np.isin(allp[:, 1], tg)]
+    assert len(want) > 5
+    assert np.array_equal(orc.mesh_pairs_of(d, 0.1, 0.005, tg), want)

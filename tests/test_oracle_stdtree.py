@@ -107,3 +107,11 @@ def test_zero_thresholds_stay_finite(orc):
     assert np.all(np.isfinite(a))
     b, _, _ = orc.standard_tree_accel(d, p=5, s=8)
     assert np.median(_rel(a, ex)) < 3 * np.median(_rel(b, ex))
+
+
+def test_sampled_walks_equal_full_run(orc):
+    """The per-target entry point gives the full run's values for those moonlets."""
+    d = inputs.disk(3000, seed=26)
+    a, _, g = orc.standard_tree_accel(d, p=4, s=32)
+    tg = np.array([0, 17, 999, 2999, 1500])
+    assert np.array_equal(g.standard_targets(6, 16, tg), a[tg])
