@@ -40,10 +40,18 @@ FLOPS_PER_INTERACTION = 20  # directed moonlet pair, the usual N-body convention
 # (bench.py --copy-calibration 1024: FETCH 524303 KiB -> x2.00, WRITE 1048576 KiB ->
 # x1.00).  The figures belong to the kernel source with this git blob hash and are
 # reported only while it is unchanged.
+# Measured per leaf size (the direct sums' work depends on it).
 P2P_TRAFFIC = {"source": "paper_2310_20374_amd/csrc/p2p.hip",
                "blob": "ee1bc0982888890114e874ada789c9430c72d37a",
-               "fetch_kib": (175587.7, 4754.2), "write_kib": (25781.1, 671.1),
-               "fetch_scale": 2.00, "write_scale": 1.00}
+               "fetch_scale": 2.00, "write_scale": 1.00,
+               "by_leaf_size": {52: {"fetch_kib": (175587.7, 4754.2),
+                                     "write_kib": (25781.1, 671.1)},
+                                80: {"fetch_kib": (188924.4, 2271.7),
+                                     "write_kib": (25761.7, 196.1)},
+                                96: {"fetch_kib": (212861.5, 2061.1),
+                                     "write_kib": (25637.8, 139.2)},
+                                112: {"fetch_kib": (241790.5, 2102.2),
+                                      "write_kib": (25476.3, 139.3)}}}
 
 
 def _git_blob(path):
@@ -52,12 +60,13 @@ def _git_blob(path):
     return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
 
 
-def _p2p_traffic(args):
+def _p2p_traffic(args, leaf_size):
     t = P2P_TRAFFIC
     default = args.n == 1_000_000 and args.p == 6 and args.theta == 0.5
-    if not default or _git_blob(os.path.join(ROOT, t["source"])) != t["blob"]:
+    m = t["by_leaf_size"].get(int(leaf_size))
+    if not default or m is None or _git_blob(os.path.join(ROOT, t["source"])) != t["blob"]:
         return None
-    kib = sum(t["fetch_kib"]) * t["fetch_scale"] + sum(t["write_kib"]) * t["write_scale"]
+    kib = sum(m["fetch_kib"]) * t["fetch_scale"] + sum(m["write_kib"]) * t["write_scale"]
     return kib * 1024.0
 
 
@@ -176,12 +185,18 @@ def _run_mesh(nc, d, args, device):
     return out, r["acc"]
 
 
+_DIRECT = {}
+
+
 def _errors(orc, d, acc, samples):
     import numpy as np
     from paper_2310_20374_amd import inputs
     tg = inputs.sample_targets(len(d["x"]), samples)
-    ad = orc.direct_sum(d["x"], d["y"], d["z"], d["m"], targets=tg)
-    ac = orc.central_accel(d["x"][tg], d["y"][tg], d["z"][tg])
+    key = (id(d), samples)
+    if key not in _DIRECT:          # the FP64 direct sums of one input, computed once
+        _DIRECT[key] = (orc.direct_sum(d["x"], d["y"], d["z"], d["m"], targets=tg),
+                        orc.central_accel(d["x"][tg], d["y"][tg], d["z"][tg]))
+    ad, ac = _DIRECT[key]
 
     def stats(a, ref):
         e = np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
@@ -193,6 +208,11 @@ def _errors(orc, d, acc, samples):
             "rms_mutual": mut[0], "max_mutual": mut[1], "median_mutual": mut[2],
             "samples": int(len(tg))}
 
+
+# leaf sizes the main line's autotuner tries (FP64 direct sums cost twice as much, so
+# its optimum sits lower)
+LEAF_CANDIDATES_FP32 = (52, 64, 80, 96, 112, 128)
+LEAF_CANDIDATES_FP64 = (40, 52, 64, 80, 96)
 
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E (published)
 
@@ -384,6 +404,12 @@ def main():
     ap.add_argument("--collisions", choices=("resolve", "report"), default="resolve",
                     help="resolve the pairs found elastically (f = 2, as in the paper's timing "
                          "runs, keeping N constant) or only report them")
+    ap.add_argument("--leaf-size", default="auto",
+                    help="leaf size s of the main line: 'auto' (the autotuner, each precision "
+                         "form on its own) or an integer")
+    ap.add_argument("--thetas", default="0.3,0.7",
+                    help="extra opening angles timed and error-checked beside --theta "
+                         "(both precision forms, 10 steps each); '' for none")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-mesh", action="store_true",
                     help="skip the mesh-module step loop (gravity and collisions on the mesh)")
@@ -399,8 +425,8 @@ def main():
                          "reference kernel for scaling the FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(see DESIGN.md for how the step would shard).", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np  # noqa: F401
@@ -427,6 +453,23 @@ def main():
                                  collision_mode=cmode, collision_f=2.0)
     prm32 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP32_BULK,
                                  collision_mode=cmode, collision_f=2.0)
+    tuned = None
+    if args.leaf_size == "auto":
+        from paper_2310_20374_amd import autotune
+        base = {k: torch.tensor(v, device=device) for k, v in d.items()}
+        tuned = {}
+        for name, prm, cands in (("fp32", prm32, LEAF_CANDIDATES_FP32),
+                                 ("fp64", prm64, LEAF_CANDIDATES_FP64)):
+            if name == "fp64" and args.fp32_only:
+                continue
+            best, table = autotune.tune_leaf_size(ncorp, prm, base, dt=args.dt, steps=3,
+                                                  candidates=cands, device=device)
+            prm.leaf_size = int(best)
+            tuned[name] = {"leaf_size": int(best), "ms_per_step": table}
+        del base
+        print(f"# autotuned leaf sizes: {tuned}", file=sys.stderr, flush=True)
+    else:
+        prm32.leaf_size = prm64.leaf_size = int(args.leaf_size)
     thr = (prm64.ncs, prm64.ncc_pre, prm64.ncc_post)
     print(f"# bench: N={args.n} p={args.p} theta_min={args.theta} s={prm64.leaf_size} "
           f"steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
@@ -439,6 +482,23 @@ def main():
         r64 = _run(ncorp, prm64, d, args.dt, args.steps, args.warmup, True, device)
         print(f"# fp64: {r64['wall_s'] * 1e3 / args.steps:.3f} ms/step", file=sys.stderr,
               flush=True)
+
+    thetas = [float(v) for v in args.thetas.split(",") if v.strip()]
+    theta_runs = []
+    for th in thetas:
+        row = {"theta_min": th}
+        for name, prm in (("fp32", prm32), ("fp64", prm64)):
+            if name == "fp64" and args.fp32_only:
+                continue
+            p2 = ncorp.Params.from_buffer_copy(prm)
+            p2.theta_min = th
+            r = _run(ncorp, p2, d, args.dt, 10, 2, False, device)
+            row[name] = {"ms_per_step": r["wall_s"] * 1e3 / 10, "acc": r["acc"],
+                         "leaf_size": p2.leaf_size}
+        theta_runs.append(row)
+        print(f"# theta {th}: " + ", ".join(f"{k} {v['ms_per_step']:.3f} ms/step"
+                                            for k, v in row.items() if k != "theta_min"),
+              file=sys.stderr, flush=True)
 
     batched = None
     if not args.no_batched:
@@ -469,6 +529,12 @@ def main():
         if r64 is not None:
             err64 = _errors(orc, d, r64["acc"], args.samples)
         print(f"# errors fp32 {err32} fp64 {err64}", file=sys.stderr, flush=True)
+    for row in theta_runs:
+        for name in ("fp32", "fp64"):
+            if name in row:
+                acc = row[name].pop("acc")
+                if not args.no_errors:
+                    row[name]["errors"] = _errors(orc, d, acc, args.samples)
     if mesh is not None and not args.no_errors:
         mesh["errors"] = _errors(orc, d, mesh_acc, args.samples)
     if methods is not None:
@@ -491,7 +557,7 @@ def main():
                 "kernel": "direct sums, FP32 VALU (k_p2p<float> + k_p2p_long<float>, one "
                           "gravity evaluation)",
                 "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": _p2p_traffic(args),
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": _p2p_traffic(args, prm32.leaf_size),
                 "avg_launch_us": p2p_avg_s * 1e6, "launches": p2p_launches,
                 "interactions_per_launch": info["p2p_inter"],
                 "flops_per_interaction": FLOPS_PER_INTERACTION}
@@ -528,7 +594,8 @@ def main():
                         "i 0.005; KDK steps with collision search + octree rebuild + falcON "
                         "gravity each step",
             "n": args.n, "p": args.p, "theta_min": args.theta, "theta_mode": "mass-dependent",
-            "leaf_size": prm64.leaf_size, "walk_thresholds": list(thr),
+            "leaf_size": {"fp32": prm32.leaf_size, "fp64": prm64.leaf_size},
+            "walk_thresholds": list(thr),
             "collision_thresholds": [prm64.ncs_col, prm64.ncc_pre_col, prm64.ncc_post_col],
             "dt": args.dt,
             "collisions": "resolved elastically (hard spheres, f = 2)" if args.collisions ==
@@ -551,6 +618,8 @@ def main():
         "batched": batched,
         "gravity_methods": methods,
         "mesh_module": mesh,
+        "leaf_size_autotune": tuned,
+        "theta_sweep": theta_runs,
     }
     print(json.dumps(out))
     return 0
