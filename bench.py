@@ -34,7 +34,7 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published)
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector (published)
 FLOPS_PER_INTERACTION = 20  # directed moonlet pair, the usual N-body convention
 
-# HBM traffic of one direct-sum evaluation (k_p2p<float> + k_p2p_long<float>) on the
+# HBM traffic of one direct-sum evaluation (k_p2p<float>) on the
 # default workload: FETCH_SIZE and WRITE_SIZE from two rocprofv3 --pmc runs (KiB per
 # dispatch), scaled by what the same counters read for a 1 GiB device copy
 # (bench.py --copy-calibration 1024: FETCH 524303 KiB -> x2.00, WRITE 1048576 KiB ->
@@ -554,7 +554,7 @@ def main():
     flops = FLOPS_PER_INTERACTION * info["p2p_inter"]
     achieved = flops / p2p_avg_s / 1e12 if p2p_avg_s > 0 else 0.0
     roofline = {"bound": "alu",
-                "kernel": "direct sums, FP32 VALU (k_p2p<float> + k_p2p_long<float>, one "
+                "kernel": "direct sums, FP32 VALU (k_p2p<float>, one "
                           "gravity evaluation)",
                 "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": _p2p_traffic(args, prm32.leaf_size),

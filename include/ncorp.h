@@ -273,7 +273,8 @@ enum {
     NCORP_INFO_N = 0, NCORP_INFO_NCELLS, NCORP_INFO_NLEAVES, NCORP_INFO_MAXLEVEL,
     NCORP_INFO_M2L, NCORP_INFO_P2P, NCORP_INFO_VISITED, NCORP_INFO_COL_CAND,
     NCORP_INFO_COL_TESTS, NCORP_INFO_M2L_DIR, NCORP_INFO_P2P_INTER, NCORP_INFO_M2L_MAXLIST,
-    NCORP_INFO_P2P_MAXLIST, NCORP_INFO_NROOTS, NCORP_INFO_COUNT
+    NCORP_INFO_P2P_MAXLIST, NCORP_INFO_NROOTS, NCORP_INFO_LONG_M2L, NCORP_INFO_LONG_P2P,
+    NCORP_INFO_COUNT
 };
 /* Waits for the stream and fills info[NCORP_INFO_COUNT] with sizes of the last
  * tree and walks (cells, leaves, deepest level, M2L and P2P cell pairs of the
@@ -284,7 +285,9 @@ enum {
  * the sizes m2l_per_cell and p2p_per_leaf must cover; these three are filled
  * only while phase timing is on (ncorp_set_timing), otherwise they read 0), and
  * the number of roots (level-0 cells: 1, or the non-empty disks of a batched
- * call). */
+ * call), and the numbers of cells and leaves whose M2L or direct-sum lists were too
+ * long for one LDS batch of their consumer (sorted by a pre-pass; the direct sums of
+ * such leaves are split over several waves). */
 int ncorp_tree_info(ncorp_ctx *ctx, int64_t *info);
 
 enum {

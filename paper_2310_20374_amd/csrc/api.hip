@@ -333,6 +333,8 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.mbest = (int32_t *)take(4 * n);
     ws.mmatch = (int32_t *)take(4 * n);
     ws.cand_blk = (int32_t *)take(4 * 8192);
+    ws.count_part_n = 2 * ((n / 256 + 64) > 16384 ? (n / 256 + 64) : 16384) + 1024;
+    ws.count_part = (unsigned long long *)take(8 * ws.count_part_n);
     if (prm.gravity_method == NCORP_GRAVITY_MESH ||
         prm.collision_method == NCORP_COLLISIONS_MESH) {
         ws.mtab_n = 1024;
@@ -783,6 +785,8 @@ extern "C" int ncorp_tree_info(ncorp_ctx *c, int64_t *info) {
     info[NCORP_INFO_COL_TESTS] = h.col_tests;
     info[NCORP_INFO_M2L_DIR] = 2 * (int64_t)h.nm2l;
     info[NCORP_INFO_NROOTS] = h.level_count[0];
+    info[NCORP_INFO_LONG_M2L] = h.nlong_m2l;
+    info[NCORP_INFO_LONG_P2P] = h.nlong_p2p;
     info[NCORP_INFO_P2P_INTER] = h.p2p_inter;
     info[NCORP_INFO_M2L_MAXLIST] = h.m2l_maxlist;
     info[NCORP_INFO_P2P_MAXLIST] = h.p2p_maxlist;

@@ -136,9 +136,12 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
           const double *__restrict__ vxs, const double *__restrict__ vys,
           const double *__restrict__ vzs, const double *__restrict__ rads,
           const uint32_t *__restrict__ perm, const double4 *__restrict__ pcol, double dt,
-          int64_t *out, int64_t cap) {
+          int64_t *out, int64_t cap, unsigned long long *tests_part) {
     __shared__ PState sp[kWave];    // survivors of both sides (or a staged tile of B)
-    if (st->status & kSkipMask) return;
+    if (st->status & kSkipMask) {
+        if (threadIdx.x == 0) tests_part[blockIdx.x] = 0;
+        return;
+    }
     int nc = st->cand_slots;                 // candidate slots, gaps included
     if (nc > cand_cap) nc = (int)cand_cap;
     const int lane = threadIdx.x;
@@ -225,8 +228,33 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
                            out, cap, st, tests);
         }
     }
+    // per-block partials, summed by k_sum_u64: one atomic per wave on a single
+    // counter would serialise all blocks of the grid
     for (int o = 32; o > 0; o >>= 1) tests += __shfl_xor(tests, o);
-    if (lane == 0 && tests) atomicAdd((unsigned long long *)&st->col_tests, tests);
+    if (lane == 0) tests_part[blockIdx.x] = tests;
+}
+
+// dst (+)= the sum of n partials, in a fixed order
+__global__ void __launch_bounds__(1024)
+k_sum_u64(const unsigned long long *__restrict__ part, int64_t n, unsigned long long *dst,
+          int add) {
+    __shared__ unsigned long long red[1024 / kWave];
+    unsigned long long v = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) v += part[i];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < 1024 / kWave; k++) t += red[k];
+        *dst = add ? *dst + t : t;
+    }
+}
+
+hipError_t launch_sum_u64(const unsigned long long *part, int64_t n, unsigned long long *dst,
+                          bool add, hipStream_t s) {
+    k_sum_u64<<<1, 1024, 0, s>>>(part, n, dst, add ? 1 : 0);
+    return hipGetLastError();
 }
 
 __global__ void k_collide_init(DevState *st) {
@@ -642,8 +670,9 @@ hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipSt
     k_collide_init<<<1, 64, 0, s>>>(ws.st);
     k_collide<<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count, ws.ccell,
                                    ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, ws.idx,
-                                   ws.pcol, dt, ws.pairs_tmp, ws.pair_cap);
-    return hipGetLastError();
+                                   ws.pcol, dt, ws.pairs_tmp, ws.pair_cap, ws.count_part);
+    return launch_sum_u64(ws.count_part, 16384, (unsigned long long *)&ws.st->col_tests, true,
+                          s);
 }
 
 hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,

@@ -16,6 +16,8 @@
 // The mesh size: Eq. (4) at the first mesh (or the value given), then Eq. (6) from
 // the neighbour count of the previous mesh, kept on the device so that a step
 // loop (and a captured graph of it) needs no host round trip.
+#include <climits>
+
 #include "contact.h"
 
 namespace ncorp {
@@ -86,6 +88,85 @@ __device__ __forceinline__ void add_pull(double4 src, double x, double y, double
     a0 += src.w * dx / r3;
     a1 += src.w * dy / r3;
     a2 += src.w * dz / r3;
+}
+
+// The cells a wave's moonlets look up, gathered once per wave: the box of cells
+// spanned by the wave's moonlets (consecutive in Morton order, so usually a small
+// block), widened by one cell on every side, is looked up by the lanes together into
+// LDS, and each lane then reads its 27 neighbour ranges from there.  A wave whose box
+// holds more than kMeshBox cells (a Morton run that jumps) looks up per lane.  Both
+// ways give the same ranges, so the results do not depend on which one ran.
+constexpr int kMeshBox = 1024;
+
+struct CellBox {
+    int x0, y0, z0, bx, by;
+    bool used;
+};
+
+__device__ __forceinline__ int wave_min_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// called by every lane of the wave (uniform control flow)
+__device__ __forceinline__ CellBox gather_box(const MeshSlot *__restrict__ tab, int64_t mask,
+                                              int4 c, bool live, int2 *box) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int mnx = wave_min_i(live ? c.x : INT_MAX), mxx = wave_max_i(live ? c.x : INT_MIN);
+    const int mny = wave_min_i(live ? c.y : INT_MAX), mxy = wave_max_i(live ? c.y : INT_MIN);
+    const int mnz = wave_min_i(live ? c.z : INT_MAX), mxz = wave_max_i(live ? c.z : INT_MIN);
+    CellBox b = {0, 0, 0, 0, 0, false};
+    if (mnx > mxx) return b;                       // no moonlet of the mesh in this wave
+    const int64_t bx = (int64_t)mxx - mnx + 3, by = (int64_t)mxy - mny + 3,
+                  bz = (int64_t)mxz - mnz + 3;
+    if (bx * by * bz > kMeshBox) return b;
+    b.x0 = mnx - 1; b.y0 = mny - 1; b.z0 = mnz - 1;
+    b.bx = (int)bx; b.by = (int)by;
+    const int vol = (int)(bx * by * bz);
+    for (int t = lane; t < vol; t += kWave) {
+        const int ix = t % b.bx, iy = (t / b.bx) % b.by, iz = t / (b.bx * b.by);
+        box[t] = lookup(tab, mask, cell_key(b.x0 + ix, b.y0 + iy, b.z0 + iz));
+    }
+    wave_sync();
+    b.used = true;
+    return b;
+}
+
+__device__ __forceinline__ int2 cell_range(const CellBox &b, const int2 *box,
+                                           const MeshSlot *__restrict__ tab, int64_t mask, int x,
+                                           int y, int z) {
+    if (b.used) return box[(x - b.x0) + b.bx * ((y - b.y0) + b.by * (z - b.z0))];
+    return lookup(tab, mask, cell_key(x, y, z));
+}
+
+// sum of v over the block, valid in thread 0 (every thread calls it)
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
+                                                            unsigned long long *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x / kWave); k++) t += red[k];
+    __syncthreads();
+    return t;
+}
+
+// the neighbour count of the current mesh, from the scan's per-block partials
+__global__ void __launch_bounds__(1024)
+k_mesh_count_done(const unsigned long long *__restrict__ part, int64_t n, MeshState *ms) {
+    __shared__ unsigned long long red[1024 / kWave];
+    unsigned long long v = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) v += part[i];
+    const unsigned long long t = block_sum_u64(v, red);
+    if (threadIdx.x == 0) {
+        ms->nbr_sum = t;
+        ms->measured = 1;
+    }
 }
 
 // ------------------------------------------------------------------ build
@@ -341,21 +422,29 @@ k_mesh_gravity(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, in
                const double4 *__restrict__ mpos, const int4 *__restrict__ mcell,
                const uint32_t *__restrict__ idx, const int32_t *__restrict__ big,
                int count, double *__restrict__ ax, double *__restrict__ ay,
-               double *__restrict__ az) {
-    if (st->status & kSkipMask) return;
+               double *__restrict__ az, unsigned long long *cnt_part) {
+    __shared__ int2 s_box[kMeshBlock / kWave][kMeshBox];
+    __shared__ unsigned long long s_red[kMeshBlock / kWave];
+    if (st->status & kSkipMask) {
+        if (threadIdx.x == 0) cnt_part[blockIdx.x] = 0;
+        return;
+    }
     const int64_t q = blockIdx.x * (int64_t)kMeshBlock + threadIdx.x;
     const int n_in = ms->n_in, nbig = ms->nbig;
     const int t0 = ms->top[0], t1 = ms->top[1], t2 = ms->top[2];
     unsigned long long cnt = 0;
-    if (q < n_in) {
+    const bool live = q < n_in;
+    const int4 c = live ? mcell[q] : make_int4(0, 0, 0, 0);
+    int2 *box = s_box[threadIdx.x / kWave];
+    const CellBox cb = gather_box(tab, mask, c, live, box);
+    if (live) {
         const double4 p = mpos[q];
-        const int4 c = mcell[q];
         const bool top = q == t0 || q == t1 || q == t2;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (int dz = -1; dz <= 1; dz++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dx = -1; dx <= 1; dx++) {
-                    const int2 e = lookup(tab, mask, cell_key(c.x + dx, c.y + dy, c.z + dz));
+                    const int2 e = cell_range(cb, box, tab, mask, c.x + dx, c.y + dy, c.z + dz);
                     for (int r = e.x; r < e.y; r++) {
                         if (r == q) continue;
                         cnt++;
@@ -373,9 +462,8 @@ k_mesh_gravity(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, in
         }
     }
     if (count) {
-        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-        if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(&ms->nbr_sum, cnt);
-        if (q == 0) ms->measured = 1;
+        const unsigned long long t = block_sum_u64(cnt, s_red);
+        if (threadIdx.x == 0) cnt_part[blockIdx.x] = t;
     }
 }
 
@@ -448,18 +536,27 @@ __global__ void __launch_bounds__(kMeshBlock)
 k_mesh_collide(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, int64_t mask,
                const double4 *__restrict__ mpos, const double4 *__restrict__ mvel,
                const int4 *__restrict__ mcell, const uint32_t *__restrict__ idx, double dt,
-               int count, int64_t *out, int64_t cap) {
-    if (st->status & kSkipMask) return;
+               int count, int64_t *out, int64_t cap, unsigned long long *cnt_part,
+               unsigned long long *tests_part) {
+    __shared__ int2 s_box[kMeshBlock / kWave][kMeshBox];
+    __shared__ unsigned long long s_red[kMeshBlock / kWave];
+    if (st->status & kSkipMask) {
+        if (threadIdx.x == 0) { cnt_part[blockIdx.x] = 0; tests_part[blockIdx.x] = 0; }
+        return;
+    }
     const int64_t q = blockIdx.x * (int64_t)kMeshBlock + threadIdx.x;
     const int n_in = ms->n_in;
     unsigned long long cnt = 0, tests = 0;
-    if (q < n_in) {
+    const bool live = q < n_in;
+    const int4 c = live ? mcell[q] : make_int4(0, 0, 0, 0);
+    int2 *box = s_box[threadIdx.x / kWave];
+    const CellBox cb = gather_box(tab, mask, c, live, box);
+    if (live) {
         const double4 p = mpos[q], v = mvel[q];
-        const int4 c = mcell[q];
         for (int dz = -1; dz <= 1; dz++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dx = -1; dx <= 1; dx++) {
-                    const int2 e = lookup(tab, mask, cell_key(c.x + dx, c.y + dy, c.z + dz));
+                    const int2 e = cell_range(cb, box, tab, mask, c.x + dx, c.y + dy, c.z + dz);
                     for (int r = e.x; r < e.y; r++) {
                         if (r == q) continue;
                         cnt++;
@@ -472,15 +569,12 @@ k_mesh_collide(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, in
                     }
                 }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        cnt += __shfl_xor(cnt, o);
-        tests += __shfl_xor(tests, o);
+    const unsigned long long tt = block_sum_u64(tests, s_red);
+    const unsigned long long tc = block_sum_u64(cnt, s_red);
+    if (threadIdx.x == 0) {
+        tests_part[blockIdx.x] = tt;
+        if (count) cnt_part[blockIdx.x] = tc;
     }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (tests) atomicAdd((unsigned long long *)&st->col_tests, tests);
-        if (count && cnt) atomicAdd(&ms->nbr_sum, cnt);
-    }
-    if (count && q == 0) ms->measured = 1;
 }
 
 // the moonlets out of the mesh against every moonlet (each pair of two of them once)
@@ -488,7 +582,10 @@ __global__ void __launch_bounds__(kMeshBlock)
 k_mesh_collide_out(DevState *st, const MeshState *__restrict__ ms,
                    const double4 *__restrict__ mpos, const double4 *__restrict__ mvel,
                    const uint32_t *__restrict__ idx, int64_t n, double dt, int64_t *out,
-                   int64_t cap) {
+                   int64_t cap, unsigned long long *tests_part) {
+    __shared__ unsigned long long s_red[kMeshBlock / kWave];
+    const int64_t slot = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0) tests_part[slot] = 0;
     if (st->status & kSkipMask) return;
     const int n_in = ms->n_in;
     const int nover = (int)n - n_in;
@@ -515,9 +612,8 @@ k_mesh_collide_out(DevState *st, const MeshState *__restrict__ ms,
                 record(out, cap, (unsigned long long *)&st->npairs, idx[b], idx[j]);
         }
     }
-    for (int o = 32; o > 0; o >>= 1) tests += __shfl_xor(tests, o);
-    if ((threadIdx.x & (kWave - 1)) == 0 && tests)
-        atomicAdd((unsigned long long *)&st->col_tests, tests);
+    const unsigned long long t = block_sum_u64(tests, s_red);
+    if (threadIdx.x == 0) tests_part[slot] = t;
 }
 
 int grid_of(int64_t n, int block) { return (int)((n + block - 1) / block); }
@@ -556,10 +652,11 @@ hipError_t launch_mesh_gravity(const Workspace &ws, const double *m, double G, i
     Cand *part = reinterpret_cast<Cand *>(ws.mtop_part);
     k_mesh_top_part<<<kMeshTopBlocks, kMeshBlock, 0, s>>>(ws.st, ws.mmass, ws.midx, n, part);
     k_mesh_top_final<<<1, kMeshTopBlocks, 0, s>>>(ws.st, ws.mesh, n, part, ws.mbig);
-    k_mesh_gravity<<<grid_of(n, kMeshBlock), kMeshBlock, 0, s>>>(
-        ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mpos, ws.mcell, ws.midx, ws.mbig,
-        count ? 1 : 0,
-        ax, ay, az);
+    const int nblk = grid_of(n, kMeshBlock);
+    k_mesh_gravity<<<nblk, kMeshBlock, 0, s>>>(ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mpos,
+                                               ws.mcell, ws.midx, ws.mbig, count ? 1 : 0, ax, ay,
+                                               az, ws.count_part);
+    if (count) k_mesh_count_done<<<1, 1024, 0, s>>>(ws.count_part, nblk, ws.mesh);
     k_mesh_big_sum<<<dim3(kMeshChunks, kMeshBigRows), kMeshBlock, 0, s>>>(ws.st, ws.mesh,
                                                                          ws.mpos, ws.mbig, n,
                                                                          ws.mbig_part);
@@ -573,12 +670,19 @@ hipError_t launch_mesh_collide(const Workspace &ws, const double *vx, const doub
                                bool count, hipStream_t s) {
     k_mesh_vel<<<grid_of(n, 256), 256, 0, s>>>(ws.midx, vx, vy, vz, R, n, ws.mvel);
     k_mesh_col_init<<<1, 64, 0, s>>>(ws.st);
-    k_mesh_collide<<<grid_of(n, kMeshBlock), kMeshBlock, 0, s>>>(
-        ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mpos, ws.mvel, ws.mcell, ws.midx, dt,
-        count ? 1 : 0, ws.pairs_tmp, ws.pair_cap);
+    // partials: neighbour counts [0, nblk), tests [nblk, 2 nblk), tests of the moonlets
+    // out of the mesh [2 nblk, 2 nblk + kMeshChunks * kMeshBigRows)
+    const int nblk = grid_of(n, kMeshBlock);
+    unsigned long long *cnt = ws.count_part, *tst = ws.count_part + nblk;
+    k_mesh_collide<<<nblk, kMeshBlock, 0, s>>>(ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mpos,
+                                               ws.mvel, ws.mcell, ws.midx, dt, count ? 1 : 0,
+                                               ws.pairs_tmp, ws.pair_cap, cnt, tst);
     k_mesh_collide_out<<<dim3(kMeshChunks, kMeshBigRows), kMeshBlock, 0, s>>>(
-        ws.st, ws.mesh, ws.mpos, ws.mvel, ws.midx, n, dt, ws.pairs_tmp, ws.pair_cap);
-    return hipGetLastError();
+        ws.st, ws.mesh, ws.mpos, ws.mvel, ws.midx, n, dt, ws.pairs_tmp, ws.pair_cap,
+        tst + nblk);
+    if (count) k_mesh_count_done<<<1, 1024, 0, s>>>(cnt, nblk, ws.mesh);
+    return launch_sum_u64(tst, nblk + kMeshChunks * kMeshBigRows,
+                          (unsigned long long *)&ws.st->col_tests, true, s);
 }
 
 }  // namespace ncorp

@@ -71,7 +71,7 @@ constexpr int kM2LListLDS = 512;
 constexpr int kP2PListLDS = kWave;
 constexpr int kSortLongBlocks = 1024;
 // direct sums of a leaf with a long source list are split over kLongSlots waves
-// (grid of kLongGrid four-wave blocks); their partial sums meet in p2p_part
+// (kLongGrid extra four-wave blocks); their partial sums meet in p2p_part
 constexpr int kLongSlots = 8;
 constexpr int kLongGrid = 2048;
 
@@ -271,6 +271,8 @@ struct Workspace {
     double *mmass = nullptr;                          // masses (sorted)
     void *mtop_part = nullptr;                        // per-block top-three candidates
     double *mbig_part = nullptr;                      // partial sums of the big ones
+    unsigned long long *count_part = nullptr;         // per-block counter partials
+    int64_t count_part_n = 0;
     DevState *st = nullptr;
     bool clear_queue = false;                         // new buffer: clear before next walk
     bool clear_mesh = false;                          // new buffer: clear the mesh state
@@ -334,6 +336,9 @@ hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, 
                           double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
                           int64_t *cursor, hipStream_t s);
 
+// dst (+)= sum of n per-block partials (one block, fixed order)
+hipError_t launch_sum_u64(const unsigned long long *part, int64_t n, unsigned long long *dst,
+                          bool add, hipStream_t s);
 // mesh module (Sect. 3.3)
 hipError_t launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
                              int bits, uint32_t *hist, bool *in_b, hipStream_t s);

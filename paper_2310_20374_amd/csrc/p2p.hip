@@ -328,6 +328,13 @@ __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1,
 constexpr int kP2PWaves = 4;        // independent waves per block
 static_assert(kP2PListLDS == kP2PSrc, "one LDS batch holds a list the pre-pass leaves unsorted");
 
+// Direct sums of every leaf, one wave per work item.  A leaf whose source list fits
+// one LDS batch is one item.  A leaf whose list is longer (the pre-pass sorted it)
+// would keep a single wave busy long after all others finished, so it is split over
+// kLongSlots items: item `slot` takes the batches slot, slot + kLongSlots, ... and
+// writes its partial sums to part[slot], which the evaluation kernel adds in slot
+// order.  The split items come first, so they start first and the short leaves fill
+// in around them within the same launch.
 template <typename T>
 __global__ void __launch_bounds__(kWave * kP2PWaves)
 k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
@@ -335,7 +342,8 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const double *__restrict__ mus, const int32_t *__restrict__ ent_cell,
       const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
       const double4 *__restrict__ gcell, const int32_t *__restrict__ p2p_cnt,
-      int32_t *__restrict__ p2p_seg, int stride, double *__restrict__ acc_s, int64_t n) {
+      int32_t *__restrict__ p2p_seg, int stride, const int32_t *__restrict__ longs,
+      double *__restrict__ part, double *__restrict__ acc_s, int64_t n) {
     using V = typename Vec4<T>::type;
     __shared__ __align__(16) V tiles[kP2PWaves][kP2PTile];
     __shared__ int32_t firsts[kP2PWaves][kP2PSrc], prefs[kP2PWaves][kP2PSrc + 1];
@@ -346,13 +354,38 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
     // the tile doubles as sort scratch before any moonlet is staged
     int32_t *scratch = reinterpret_cast<int32_t *>(tile);
     const int K = st->nleaves;
-    for (int e = blockIdx.x * kP2PWaves + wid; e < K; e += gridDim.x * kP2PWaves) {
+    const int nlong = st->nlong_p2p * kLongSlots;
+    for (int w = blockIdx.x * kP2PWaves + wid; w < nlong + K; w += gridDim.x * kP2PWaves) {
+        if (w < nlong) {
+            const int e = longs[w / kLongSlots], slot = w % kLongSlots;
+            const int c = ent_cell[e];
+            const int f = c_first[c], nt = c_count[c];
+            const double4 g = gcell[c];
+            const int32_t *list = p2p_seg + (int64_t)e * stride;
+            const int len = p2p_cnt[e];
+            double *out = part + (int64_t)slot * 3 * n;
+            wave_sync();                              // this wave's LDS is free again
+            for (int t0 = 0; t0 < nt; t0 += kWave) {
+                const int ntc = nt - t0 < kWave ? nt - t0 : kWave;
+                const int lpg2 = (ntc + 1) / 2;
+                if ((kWave / lpg2) * ntc > 2 * (kWave / ntc) * ntc)
+                    p2p_targets<T, 2>(ntc, f + t0, false, 0, len, slot, kLongSlots, list,
+                                      s_first, s_pref, tile, xs, ys, zs, mus, c_first, c_count,
+                                      g, out, n);
+                else
+                    p2p_targets<T, 1>(ntc, f + t0, false, 0, len, slot, kLongSlots, list,
+                                      s_first, s_pref, tile, xs, ys, zs, mus, c_first, c_count,
+                                      g, out, n);
+            }
+            continue;
+        }
+        const int e = w - nlong;
         const int c = ent_cell[e];
         const int f = c_first[c], nt = c_count[c];
         const double4 g = gcell[c];
         int32_t *list = p2p_seg + (int64_t)e * stride;
         const int len = p2p_cnt[e];
-        if (len > kP2PSrc) continue;                  // longer lists: k_p2p_long
+        if (len > kP2PSrc) continue;                  // split into the items above
         wave_sync();                                  // this wave's LDS is free again
         // one batch: rank the sources in LDS and place each source's moonlet range
         // at its rank directly
@@ -387,49 +420,6 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
             else
                 p2p_targets<T, 1>(ntc, f + t0, true, tot1, len, 0, 1, list, s_first, s_pref,
                                   tile, xs, ys, zs, mus, c_first, c_count, g, acc_s, n);
-        }
-    }
-}
-
-// Leaves whose source list is longer than one LDS batch (their lists were sorted
-// by the pre-pass) would keep single waves busy long after all others finished, so
-// each is split over kLongSlots waves: wave `slot` takes the batches slot,
-// slot + kLongSlots, ... and writes its partial sums to part[slot]; the evaluation
-// kernel adds the kLongSlots partials in slot order.
-template <typename T>
-__global__ void __launch_bounds__(kWave * kP2PWaves)
-k_p2p_long(const DevState *__restrict__ st, const double *__restrict__ xs,
-           const double *__restrict__ ys, const double *__restrict__ zs,
-           const double *__restrict__ mus, const int32_t *__restrict__ ent_cell,
-           const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
-           const double4 *__restrict__ gcell, const int32_t *__restrict__ p2p_cnt,
-           const int32_t *__restrict__ p2p_seg, int stride, const int32_t *__restrict__ longs,
-           double *__restrict__ part, int64_t n) {
-    using V = typename Vec4<T>::type;
-    __shared__ __align__(16) V tiles[kP2PWaves][kP2PTile];
-    __shared__ int32_t firsts[kP2PWaves][kP2PSrc], prefs[kP2PWaves][kP2PSrc + 1];
-    if (st->status & kSkipMask) return;
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    V *tile = tiles[wid];
-    int32_t *s_first = firsts[wid], *s_pref = prefs[wid];
-    const int items = st->nlong_p2p * kLongSlots;
-    for (int w = blockIdx.x * kP2PWaves + wid; w < items; w += gridDim.x * kP2PWaves) {
-        const int e = longs[w / kLongSlots], slot = w % kLongSlots;
-        const int c = ent_cell[e];
-        const int f = c_first[c], nt = c_count[c];
-        const double4 g = gcell[c];
-        const int32_t *list = p2p_seg + (int64_t)e * stride;
-        const int len = p2p_cnt[e];
-        double *out = part + (int64_t)slot * 3 * n;
-        for (int t0 = 0; t0 < nt; t0 += kWave) {
-            const int ntc = nt - t0 < kWave ? nt - t0 : kWave;
-            const int lpg2 = (ntc + 1) / 2;
-            if ((kWave / lpg2) * ntc > 2 * (kWave / ntc) * ntc)
-                p2p_targets<T, 2>(ntc, f + t0, false, 0, len, slot, kLongSlots, list, s_first,
-                                  s_pref, tile, xs, ys, zs, mus, c_first, c_count, g, out, n);
-            else
-                p2p_targets<T, 1>(ntc, f + t0, false, 0, len, slot, kLongSlots, list, s_first,
-                                  s_pref, tile, xs, ys, zs, mus, c_first, c_count, g, out, n);
         }
     }
 }
@@ -535,14 +525,13 @@ hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s) {
 
 template <typename T>
 static void launch_p2p_t(const Workspace &ws, int64_t n, hipStream_t s) {
-    int64_t g = (ws.leaf_cap + kP2PWaves - 1) / kP2PWaves;
+    // one item per leaf plus kLongSlots - 1 more per long leaf; the grid strides
+    int64_t g = (ws.leaf_cap + kP2PWaves - 1) / kP2PWaves + kLongGrid;
     g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
-    k_p2p<T><<<(int)g, kWave * kP2PWaves, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first,
-                                ws.c_count, ws.gcell, ws.p2p_cnt, ws.p2p_seg, ws.p2p_stride,
-                                ws.acc_s, n);
-    k_p2p_long<T><<<kLongGrid, kWave * kP2PWaves, 0, s>>>(
-        ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first, ws.c_count, ws.gcell,
-        ws.p2p_cnt, ws.p2p_seg, ws.p2p_stride, ws.long_p2p, ws.p2p_part, n);
+    k_p2p<T><<<(int)g, kWave * kP2PWaves, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell,
+                                                   ws.c_first, ws.c_count, ws.gcell, ws.p2p_cnt,
+                                                   ws.p2p_seg, ws.p2p_stride, ws.long_p2p,
+                                                   ws.p2p_part, ws.acc_s, n);
 }
 
 hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s) {
