@@ -42,16 +42,11 @@ FLOPS_PER_INTERACTION = 20  # directed moonlet pair, the usual N-body convention
 # reported only while it is unchanged.
 # Measured per leaf size (the direct sums' work depends on it).
 P2P_TRAFFIC = {"source": "paper_2310_20374_amd/csrc/p2p.hip",
-               "blob": "ee1bc0982888890114e874ada789c9430c72d37a",
+               "blob": "bb1912686fb499fa373cca5a1a1e89a038232ea5",
                "fetch_scale": 2.00, "write_scale": 1.00,
-               "by_leaf_size": {52: {"fetch_kib": (175587.7, 4754.2),
-                                     "write_kib": (25781.1, 671.1)},
-                                80: {"fetch_kib": (188924.4, 2271.7),
-                                     "write_kib": (25761.7, 196.1)},
-                                96: {"fetch_kib": (212861.5, 2061.1),
-                                     "write_kib": (25637.8, 139.2)},
-                                112: {"fetch_kib": (241790.5, 2102.2),
-                                      "write_kib": (25476.3, 139.3)}}}
+               "by_leaf_size": {80: {"fetch_kib": (182036.7,), "write_kib": (25559.4,)},
+                                96: {"fetch_kib": (198651.1,), "write_kib": (25617.4,)},
+                                112: {"fetch_kib": (221137.4,), "write_kib": (25600.2,)}}}
 
 
 def _git_blob(path):
