@@ -143,7 +143,11 @@ typedef struct {
 
 enum { NCORP_COLLISIONS_REPORT = 0, NCORP_COLLISIONS_RESOLVE = 1 };
 enum { NCORP_GRAVITY_FALCON = 0, NCORP_GRAVITY_STANDARD_TREE = 1, NCORP_GRAVITY_MESH = 2 };
-enum { NCORP_COLLISIONS_TREE = 0, NCORP_COLLISIONS_MESH = 1 };
+/* collision search: the falcON walk (or the gravity walk's lists of the same tree),
+ * the mesh, or the standard tree code's per-moonlet walk (Alg. 1, collision form: a
+ * cell whose sphere cannot meet the moonlet's reach R + dt |v| is skipped, other cells
+ * are brute-forced below ncb_pre / ncb_post moonlets or at leaves, or opened) */
+enum { NCORP_COLLISIONS_TREE = 0, NCORP_COLLISIONS_MESH = 1, NCORP_COLLISIONS_STANDARD_TREE = 2 };
 
 typedef struct ncorp_ctx ncorp_ctx;
 

@@ -150,8 +150,9 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
         std::snprintf(why, len, "ncb_pre and ncb_post must be >= 0"); return false;
     }
     if (p->collision_method != NCORP_COLLISIONS_TREE &&
-        p->collision_method != NCORP_COLLISIONS_MESH) {
-        std::snprintf(why, len, "collision_method must be 0 or 1"); return false;
+        p->collision_method != NCORP_COLLISIONS_MESH &&
+        p->collision_method != NCORP_COLLISIONS_STANDARD_TREE) {
+        std::snprintf(why, len, "collision_method must be 0, 1 or 2"); return false;
     }
     if (p->mesh_cells < 1) {
         std::snprintf(why, len, "mesh_cells must be >= 1"); return false;
@@ -333,7 +334,9 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.mbest = (int32_t *)take(4 * n);
     ws.mmatch = (int32_t *)take(4 * n);
     ws.cand_blk = (int32_t *)take(4 * 8192);
-    ws.count_part_n = 2 * ((n / 256 + 64) > 16384 ? (n / 256 + 64) : 16384) + 1024;
+    // per-block partials: 16384 collision blocks, 2 per mesh block plus 1024, or one per
+    // standard-tree wave, whichever needs most
+    ws.count_part_n = n / 64 + 2 * 16384 + 1024 + 128;
     ws.count_part = (unsigned long long *)take(8 * ws.count_part_n);
     if (prm.gravity_method == NCORP_GRAVITY_MESH ||
         prm.collision_method == NCORP_COLLISIONS_MESH) {
@@ -594,6 +597,11 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
     if (mesh_collisions(c->prm)) {
         HIPCHK(c, launch_mesh_collide(ws, vx, vy, vz, R, n, dt, !c->mesh_counted, s));
         c->mesh_counted = true;
+    } else if (c->prm.collision_method == NCORP_COLLISIONS_STANDARD_TREE) {
+        HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
+        HIPCHK(c, launch_collision_climb(ws, n, dt, s));
+        HIPCHK(c, launch_collide_reset(ws, s));
+        HIPCHK(c, launch_standard_tree_collide(ws, n, c->prm.ncb_pre, c->prm.ncb_post, dt, s));
     } else {
         HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
         HIPCHK(c, launch_collision_climb(ws, n, dt, s));

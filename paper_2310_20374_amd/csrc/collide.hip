@@ -261,6 +261,11 @@ __global__ void k_collide_init(DevState *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) { st->npairs = 0; st->col_tests = 0; }
 }
 
+hipError_t launch_collide_reset(const Workspace &ws, hipStream_t s) {
+    k_collide_init<<<1, 64, 0, s>>>(ws.st);
+    return hipGetLastError();
+}
+
 // rank sort of the (distinct) pair keys: rank = number of smaller keys
 __global__ void __launch_bounds__(256)
 k_rank_pairs(const DevState *__restrict__ st, const int64_t *__restrict__ in, int64_t cap,

@@ -319,6 +319,11 @@ hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s);
 hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s);
 hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,
                       hipStream_t s);
+// clears the pair and test counters before a collision search
+hipError_t launch_collide_reset(const Workspace &ws, hipStream_t s);
+// standard tree code (Alg. 1), collision form: colliding pairs into pairs_tmp
+hipError_t launch_standard_tree_collide(const Workspace &ws, int64_t n, int ncb_pre,
+                                        int ncb_post, double dt, hipStream_t s);
 // standard tree code (Alg. 1): accelerations of all moonlets, input order
 hipError_t launch_standard_tree(const Workspace &ws, int64_t n, int p, int ncb_pre, int ncb_post,
                                 double *ax, double *ay, double *az, hipStream_t s);

@@ -23,6 +23,7 @@
 //   a_i = sum_{n=0, n!=1}^{p-1} (-1)^n sum_{|b|=n} D_{e_i+b}(x - s_B) Mt_b(B),
 // D_g = d^g (1/|R|), Mt_b = M_b / b!, the moments of the gravity climb; the
 // orders 0 and 2..p-1 are exactly the moments the climb keeps.
+#include "contact.h"
 #include "expansion.h"
 
 namespace ncorp {
@@ -144,6 +145,96 @@ __global__ __launch_bounds__(kStdBlock) void k_std_tree(
     }
 }
 
+// Collision search by the standard tree code (Alg. 1 in its collision form): the same
+// per-moonlet walk over the collision climb's cells (centre s_B, radius r_crit,B that
+// holds every moonlet of B with its reach R + dt |v|).  A cell is separated from
+// moonlet a when |x_a - s_B| >= (R_a + dt |v_a| + r_crit,B)(1 + 1e-9): no moonlet of B
+// can then meet a within the step, and the walk does nothing; the margin dwarfs the
+// rounding of either radius.  Brute-forced cells test every (a, j) with input index
+// i_a < i_j exactly (Eqs. 1-2); since no colliding partner of a is ever in a
+// separated cell, a's own walk finds all pairs (a, j) with i_a < i_j, so every
+// colliding pair is found exactly once.
+__global__ __launch_bounds__(kStdBlock) void k_std_collide(
+    DevState *st, const WCell *__restrict__ wc, const double4 *__restrict__ pcol,
+    const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+    const double *__restrict__ vxs, const double *__restrict__ vys, const double *__restrict__ vzs,
+    const double *__restrict__ rads, const uint32_t *__restrict__ idx,
+    const uint16_t *__restrict__ seg, const int32_t *__restrict__ disk_root, int64_t n,
+    int ncb_pre, int ncb_post, double dt, int64_t *out, int64_t cap,
+    unsigned long long *tests_part) {
+    __shared__ int32_t s_cell[kStdWaves][kStdStack];
+    __shared__ uint64_t s_mask[kStdWaves][kStdStack];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t wave = (int64_t)blockIdx.x * kStdWaves + w;
+    if (st->status & kSkipMask) {
+        if (lane == 0) tests_part[wave] = 0;
+        return;
+    }
+    const int64_t k = wave * kWave + lane;
+    const bool live = k < n;
+    double4 me = make_double4(0.0, 0.0, 0.0, 0.0);
+    double vx = 0.0, vy = 0.0, vz = 0.0, R = 0.0;
+    uint32_t id = 0;
+    int root = 0;
+    if (live) {
+        me = pcol[k];
+        vx = vxs[k]; vy = vys[k]; vz = vzs[k]; R = rads[k];
+        id = idx[k];
+        root = seg ? disk_root[seg[k]] : 0;
+    }
+    unsigned long long tests = 0;
+    bool overflow = false;
+    uint64_t todo = __ballot(live);
+    while (todo && !overflow) {
+        const int r = __builtin_amdgcn_readlane(root, (int)__builtin_ctzll(todo));
+        const uint64_t rm = __ballot(live && root == r);
+        todo &= ~rm;
+        if (lane == 0) { s_cell[w][0] = r; s_mask[w][0] = rm; }
+        int sp = 1;
+        while (sp > 0) {
+            wave_sync();
+            sp--;
+            const int c = uniform_i32(s_cell[w][sp]);
+            const uint64_t m = uniform_u64(s_mask[w][sp]);
+            const WCell cw = wc[c];
+            int action = 0;
+            if ((m >> lane) & 1) {
+                const double dx = me.x - cw.x, dy = me.y - cw.y, dz = me.z - cw.z;
+                const double rs = (me.w + cw.rcrit) * (1.0 + 1e-9);
+                if (cw.count < ncb_pre) action = 1;
+                else if (dx * dx + dy * dy + dz * dz >= rs * rs) action = 0;
+                else if (cw.count < ncb_post || cw.nchild == 0) action = 1;
+                else action = 3;
+            }
+            const uint64_t open = __ballot(action == 3);
+            if (open) {
+                if (sp + cw.nchild > kStdStack) { overflow = true; break; }
+                if (lane == 0)
+                    for (int i = 0; i < cw.nchild; i++) {
+                        s_cell[w][sp + i] = cw.child + cw.nchild - 1 - i;
+                        s_mask[w][sp + i] = open;
+                    }
+                sp += cw.nchild;
+            }
+            if (__ballot(action == 1)) {
+                if (action == 1) {
+                    for (int j = cw.first; j < cw.first + cw.count; j++) {
+                        const uint32_t jd = idx[j];
+                        if (jd <= id) continue;
+                        tests++;
+                        if (pair_test(me.x, me.y, me.z, vx, vy, vz, R, xs[j], ys[j], zs[j],
+                                      vxs[j], vys[j], vzs[j], rads[j], dt))
+                            record(out, cap, (unsigned long long *)&st->npairs, id, jd);
+                    }
+                }
+            }
+        }
+    }
+    if (overflow && lane == 0) atomicOr(&st->status, (int32_t)ST_BAD_ITEM);
+    for (int o = 32; o > 0; o >>= 1) tests += __shfl_xor(tests, o);
+    if (lane == 0) tests_part[wave] = tests;
+}
+
 template <int P>
 hipError_t launch_std_t(const Workspace &ws, int64_t n, int ncb_pre, int ncb_post, double *ax,
                         double *ay, double *az, hipStream_t s) {
@@ -155,6 +246,20 @@ hipError_t launch_std_t(const Workspace &ws, int64_t n, int ncb_pre, int ncb_pos
 }
 
 }  // namespace
+
+hipError_t launch_standard_tree_collide(const Workspace &ws, int64_t n, int ncb_pre,
+                                        int ncb_post, double dt, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + kStdBlock - 1) / kStdBlock;
+    k_std_collide<<<(unsigned)blocks, kStdBlock, 0, s>>>(
+        ws.st, ws.wc, ws.pcol, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, ws.idx,
+        ws.ndisks > 1 ? ws.seg : nullptr, ws.disk_root, n, ncb_pre, ncb_post, dt, ws.pairs_tmp,
+        ws.pair_cap, ws.count_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_sum_u64(ws.count_part, blocks * kStdWaves,
+                          (unsigned long long *)&ws.st->col_tests, true, s);
+}
 
 hipError_t launch_standard_tree(const Workspace &ws, int64_t n, int p, int ncb_pre, int ncb_post,
                                 double *ax, double *ay, double *az, hipStream_t s) {

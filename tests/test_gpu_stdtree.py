@@ -138,3 +138,90 @@ def test_step_with_standard_tree(nc, orc):
     for k in ("x", "y", "z", "vx", "vy", "vz"):
         got = t[k].cpu().numpy()
         assert np.abs(got - ref[k]).max() < 1e-11, k
+
+
+# ---------------------------------------------------------------- collisions
+from tests.gpu_util import run_collide  # noqa: E402
+
+COL_CASES = {
+    # name: (generator, dt, leaf size, (ncb_pre, ncb_post))
+    "gas2k_s8": (lambda: inputs.gas_box(2000, seed=1), 0.01, 8, (6, 16)),
+    "gas2k_s102_no_thresholds": (lambda: inputs.gas_box(2000, seed=3), 0.01, 102, (0, 0)),
+    "disk3k_dt2": (lambda: inputs.disk(3000, seed=2), 2.0, 16, (6, 16)),
+    "hot3k_wide": (lambda: inputs.hot_disk(3000, seed=0), 0.5, 17, (64, 200)),
+    "clumps2e4_s102": (lambda: inputs.clumps(20000, seed=0, n_clumps=20), 0.01, 102, (6, 16)),
+    "clumps2e4_s1": (lambda: inputs.clumps(20000, seed=1, n_clumps=20), 0.01, 1, (1, 1)),
+}
+
+
+@pytest.mark.parametrize("case", list(COL_CASES))
+def test_standard_tree_collisions_equal_brute_force(nc, orc, case):
+    """Alg. 1 in its collision form finds exactly the brute-force pairs (Sect. 3.1)."""
+    gen, dt, s, (pre, post) = COL_CASES[case]
+    d = gen()
+    print(f"case {case}", flush=True)
+    prm = nc.params_default(3, leaf_size=s, collision_method=nc.COLLISIONS_STANDARD_TREE,
+                            ncb_pre=pre, ncb_post=post)
+    _, pairs = run_collide(nc, d, prm, dt)
+    want = orc.pairs_brute(d, dt)
+    assert len(want) > 0
+    assert np.array_equal(pairs, want)
+
+
+def test_standard_tree_collisions_forest(nc, orc):
+    import torch
+    sizes = [2000, 1, 0, 40, 3001, 17]
+    d, off = inputs.disk_batch(sizes)
+    n = len(d["x"])
+    prm = nc.params_default(3, leaf_size=16, collision_method=nc.COLLISIONS_STANDARD_TREE)
+    ctx = nc.Context(prm, n, pair_capacity=1 << 16, device="cuda:0")
+    t = dev_arrays(d)
+    offd = torch.tensor(off, device="cuda:0")
+    pairs = torch.zeros((1 << 16, 2), dtype=torch.int64, device="cuda:0")
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    ctx.build_tree_batched(offd, t["x"], t["y"], t["z"])
+    ctx.collide(t["vx"], t["vy"], t["vz"], t["R"], 5.0, pairs, npairs)
+    torch.cuda.synchronize()
+    ctx.check_status()
+    got = pairs[: int(npairs.item())].cpu().numpy()
+    want = []
+    for k in range(len(sizes)):
+        part = {key: v[off[k]:off[k + 1]] for key, v in d.items()}
+        if len(part["x"]) > 1:
+            want.append(orc.pairs_brute(part, 5.0) + off[k])
+    want = np.concatenate(want)
+    want = want[np.lexsort((want[:, 1], want[:, 0]))]
+    assert len(want) > 20
+    assert np.array_equal(got, want)
+
+
+def test_step_standard_tree_everywhere(nc, orc):
+    """ncorp_step with the standard tree for gravity and collisions, elastic resolution:
+    states and resolved pairs against the oracle's leapfrog with its standard tree and
+    brute-force pairs."""
+    import torch
+    d = inputs.clumps(4000, seed=2, n_clumps=8)
+    n, dt, ns = len(d["x"]), 2e-3, 3
+    prm = nc.params_default(3, leaf_size=32, gravity_method=nc.GRAVITY_STANDARD_TREE,
+                            collision_method=nc.COLLISIONS_STANDARD_TREE,
+                            collision_mode=nc.COLLISIONS_RESOLVE)
+    ctx = nc.Context(prm, n, pair_capacity=1 << 16, device="cuda:0")
+    t = dev_arrays(d)
+    pairs = torch.zeros((1 << 16, 3), dtype=torch.int64, device="cuda:0")
+    npairs = torch.zeros(ns, dtype=torch.int64, device="cuda:0")
+    ctx.step(t["x"], t["y"], t["z"], t["vx"], t["vy"], t["vz"], t["m"], t["R"], dt, ns, pairs,
+             npairs)
+    torch.cuda.synchronize()
+    ctx.check_status()
+    ref, ref_pairs = orc.kdk_steps(d, dt, ns, lambda s: orc.standard_tree_accel(s, p=3, s=32)[0],
+                                   collide_fn=orc.pairs_brute, resolve_f=2.0)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.abs(t[k].cpu().numpy() - ref[k]).max() < 1e-11, k
+    cnt = npairs.cpu().numpy()
+    got = pairs[: int(cnt.sum())].cpu().numpy()
+    off = 0
+    for step in range(ns):
+        mine = got[off: off + cnt[step]]
+        off += cnt[step]
+        assert np.array_equal(mine[:, 1:], ref_pairs[step]), step
+    assert cnt.sum() > 0
