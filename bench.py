@@ -124,18 +124,23 @@ def _run(nc, prm, d, dt, steps, warmup, timing, device):
 def _gravity_method_comparison(nc, d, p_list, reps, device):
     """One tree build plus one gravity evaluation by falcON (Alg. 2, default thresholds,
     FP64) and by the standard tree code (Alg. 1, leaf size 102, N_cb,pre 6, N_cb,post
-    16: the settings of the paper's speed comparison), at each order in p_list."""
+    16: the settings of the paper's speed comparison), at each order in p_list; then a
+    collision search (dt = 1e-3) by each on its own tree."""
     import torch
     n = len(d["x"])
-    t = {k: torch.tensor(d[k], device=device) for k in ("x", "y", "z", "m")}
+    t = {k: torch.tensor(d[k], device=device) for k in ("x", "y", "z", "m", "vx", "vy", "vz",
+                                                        "R")}
     a = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(3)]
+    pairs = torch.zeros((1 << 16, 2), dtype=torch.int64, device=device)
+    npairs = torch.zeros(1, dtype=torch.int64, device=device)
     out = {}
     for p in p_list:
         for name, prm in (("falcon", nc.params_default(p)),
                           ("standard_tree", nc.params_default(
                               p, leaf_size=102, gravity_method=nc.GRAVITY_STANDARD_TREE,
+                              collision_method=nc.COLLISIONS_STANDARD_TREE,
                               ncb_pre=6, ncb_post=16))):
-            ctx = nc.Context(prm, n, pair_capacity=1 << 10, device=device)
+            ctx = nc.Context(prm, n, pair_capacity=1 << 16, device=device)
 
             def once():
                 ctx.build_tree(t["x"], t["y"], t["z"])
@@ -150,11 +155,20 @@ def _gravity_method_comparison(nc, d, p_list, reps, device):
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / reps
             ctx.check_status()
+            # collision search on the same tree (falcON: from the gravity walk's lists)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.collide(t["vx"], t["vy"], t["vz"], t["R"], 1e-3, pairs, npairs)
+            torch.cuda.synchronize()
+            ms_col = (time.perf_counter() - t0) * 1e3 / reps
+            ctx.check_status()
+            n_pairs = int(npairs.item())
             ctx.set_timing(True)
             once()
             torch.cuda.synchronize()
             ph = {k: round(v[0], 4) for k, v in ctx.phase_times().items() if v[1] > 0}
-            out[f"{name}_p{p}"] = {"ms_tree_and_gravity": ms, "phases_ms": ph,
+            out[f"{name}_p{p}"] = {"ms_tree_and_gravity": ms, "ms_collision_search": ms_col,
+                                   "collision_pairs": n_pairs, "phases_ms": ph,
                                    "leaf_size": prm.leaf_size,
                                    "acc": torch.stack(a, 1).cpu().numpy()}
             del ctx
@@ -540,6 +554,7 @@ def main():
         for p in sorted({3, args.p}):
             f, st = methods[f"falcon_p{p}"], methods[f"standard_tree_p{p}"]
             st["falcon_speedup"] = st["ms_tree_and_gravity"] / f["ms_tree_and_gravity"]
+            st["falcon_speedup_collisions"] = st["ms_collision_search"] / f["ms_collision_search"]
 
     value = args.n * args.steps / r32["wall_s"]
     ph = r32["phases"]
