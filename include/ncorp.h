@@ -142,12 +142,20 @@ typedef struct {
 } ncorp_params;
 
 enum { NCORP_COLLISIONS_REPORT = 0, NCORP_COLLISIONS_RESOLVE = 1 };
-enum { NCORP_GRAVITY_FALCON = 0, NCORP_GRAVITY_STANDARD_TREE = 1, NCORP_GRAVITY_MESH = 2 };
+/* gravity: the falcON walk, the standard tree code, the mesh module, or every pair
+ * (Sect. 3.2: the plain sum, O(N^2), on the tree-ordered moonlets of the last build) */
+enum {
+    NCORP_GRAVITY_FALCON = 0, NCORP_GRAVITY_STANDARD_TREE = 1, NCORP_GRAVITY_MESH = 2,
+    NCORP_GRAVITY_BRUTE_FORCE = 3
+};
 /* collision search: the falcON walk (or the gravity walk's lists of the same tree),
  * the mesh, or the standard tree code's per-moonlet walk (Alg. 1, collision form: a
  * cell whose sphere cannot meet the moonlet's reach R + dt |v| is skipped, other cells
  * are brute-forced below ncb_pre / ncb_post moonlets or at leaves, or opened) */
-enum { NCORP_COLLISIONS_TREE = 0, NCORP_COLLISIONS_MESH = 1, NCORP_COLLISIONS_STANDARD_TREE = 2 };
+enum {
+    NCORP_COLLISIONS_TREE = 0, NCORP_COLLISIONS_MESH = 1, NCORP_COLLISIONS_STANDARD_TREE = 2,
+    NCORP_COLLISIONS_BRUTE_FORCE = 3     /* every pair i < j (Sect. 3.2), O(N^2) */
+};
 
 typedef struct ncorp_ctx ncorp_ctx;
 

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build", "ncorp")
 LIB = os.path.join(HERE, "libncorp.so")
 SOURCES = ["api.hip", "keys_sort.hip", "scan.hip", "tree.hip", "climb.hip", "walk.hip",
-           "m2l.hip", "p2p.hip", "collide.hip", "step.hip", "stdtree.hip", "mesh.hip"]
+           "m2l.hip", "p2p.hip", "collide.hip", "step.hip", "stdtree.hip", "mesh.hip", "brute.hip"]
 ARCH = os.environ.get("NCORP_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

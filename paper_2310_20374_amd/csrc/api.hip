@@ -143,16 +143,18 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
     }
     if (p->gravity_method != NCORP_GRAVITY_FALCON &&
         p->gravity_method != NCORP_GRAVITY_STANDARD_TREE &&
-        p->gravity_method != NCORP_GRAVITY_MESH) {
-        std::snprintf(why, len, "gravity_method must be 0, 1 or 2"); return false;
+        p->gravity_method != NCORP_GRAVITY_MESH &&
+        p->gravity_method != NCORP_GRAVITY_BRUTE_FORCE) {
+        std::snprintf(why, len, "gravity_method must be 0..3"); return false;
     }
     if (p->ncb_pre < 0 || p->ncb_post < 0) {
         std::snprintf(why, len, "ncb_pre and ncb_post must be >= 0"); return false;
     }
     if (p->collision_method != NCORP_COLLISIONS_TREE &&
         p->collision_method != NCORP_COLLISIONS_MESH &&
-        p->collision_method != NCORP_COLLISIONS_STANDARD_TREE) {
-        std::snprintf(why, len, "collision_method must be 0, 1 or 2"); return false;
+        p->collision_method != NCORP_COLLISIONS_STANDARD_TREE &&
+        p->collision_method != NCORP_COLLISIONS_BRUTE_FORCE) {
+        std::snprintf(why, len, "collision_method must be 0..3"); return false;
     }
     if (p->mesh_cells < 1) {
         std::snprintf(why, len, "mesh_cells must be >= 1"); return false;
@@ -527,6 +529,16 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
         HIPCHK(c, launch_fill_i64((int64_t *)az, 0, n, s));
         return NCORP_OK;
     }
+    if (c->prm.gravity_method == NCORP_GRAVITY_BRUTE_FORCE) {
+        if (ws.ndisks > 1)
+            return fail(c, NCORP_E_UNSUPPORTED, "brute-force gravity takes plain calls only");
+        PhaseTimer t(c, NCORP_PHASE_P2P, s);
+        HIPCHK(c, launch_gather_scaled(ws, m, c->prm.G, ws.mus, n, s));
+        HIPCHK(c, launch_brute_gravity(ws, n, ax, ay, az, s));
+        c->grav_lists = false;
+        c->last = s;
+        return NCORP_OK;
+    }
     if (mesh_gravity(c->prm)) {
         PhaseTimer t(c, NCORP_PHASE_GWALK, s);
         HIPCHK(c, launch_mesh_gravity(ws, m, c->prm.G, n, !c->mesh_counted, ax, ay, az, s));
@@ -597,6 +609,12 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
     if (mesh_collisions(c->prm)) {
         HIPCHK(c, launch_mesh_collide(ws, vx, vy, vz, R, n, dt, !c->mesh_counted, s));
         c->mesh_counted = true;
+    } else if (c->prm.collision_method == NCORP_COLLISIONS_BRUTE_FORCE) {
+        if (ws.ndisks > 1)
+            return fail(c, NCORP_E_UNSUPPORTED, "brute-force collisions take plain calls only");
+        HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
+        HIPCHK(c, launch_collide_reset(ws, s));
+        HIPCHK(c, launch_brute_collide(ws, n, dt, s));
     } else if (c->prm.collision_method == NCORP_COLLISIONS_STANDARD_TREE) {
         HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
         HIPCHK(c, launch_collision_climb(ws, n, dt, s));

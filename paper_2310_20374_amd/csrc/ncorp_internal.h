@@ -319,6 +319,10 @@ hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s);
 hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s);
 hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,
                       hipStream_t s);
+// brute-force module (every pair): accelerations by input index; colliding pairs
+hipError_t launch_brute_gravity(const Workspace &ws, int64_t n, double *ax, double *ay,
+                                double *az, hipStream_t s);
+hipError_t launch_brute_collide(const Workspace &ws, int64_t n, double dt, hipStream_t s);
 // clears the pair and test counters before a collision search
 hipError_t launch_collide_reset(const Workspace &ws, hipStream_t s);
 // standard tree code (Alg. 1), collision form: colliding pairs into pairs_tmp

@@ -16,8 +16,8 @@ LIB_PATH = os.path.join(HERE, "libncorp.so")
 OK, E_INVALID, E_CAPACITY, E_HIP, E_UNSUPPORTED, E_NONFINITE = 0, -1, -2, -3, -4, -5
 FP64, FP32_BULK = 0, 1
 COLLISIONS_REPORT, COLLISIONS_RESOLVE = 0, 1
-GRAVITY_FALCON, GRAVITY_STANDARD_TREE, GRAVITY_MESH = 0, 1, 2
-COLLISIONS_TREE, COLLISIONS_MESH, COLLISIONS_STANDARD_TREE = 0, 1, 2
+GRAVITY_FALCON, GRAVITY_STANDARD_TREE, GRAVITY_MESH, GRAVITY_BRUTE_FORCE = 0, 1, 2, 3
+COLLISIONS_TREE, COLLISIONS_MESH, COLLISIONS_STANDARD_TREE, COLLISIONS_BRUTE_FORCE = 0, 1, 2, 3
 STATUS_NAMES = {0: "ok", -1: "invalid", -2: "capacity", -3: "hip", -4: "unsupported",
                 -5: "nonfinite"}
 

@@ -50,8 +50,8 @@ def test_params_default_and_validation(nc):
                        ("ncs", -1), ("theta_mode", 2), ("precision", 5),
                        ("root_half_width", 3.0), ("G", -1.0), ("collision_mode", 2),
                        ("collision_f", 0.9), ("collision_f", 2.1), ("M_sun", -1.0),
-                       ("obliquity", float("nan")), ("gravity_method", 3), ("ncb_pre", -1),
-                       ("ncb_post", -1), ("collision_method", 3), ("mesh_cells", 0),
+                       ("obliquity", float("nan")), ("gravity_method", 4), ("ncb_pre", -1),
+                       ("ncb_post", -1), ("collision_method", 4), ("mesh_cells", 0),
                        ("mesh_cells", -3), ("mesh_neighbours", 0.0), ("mesh_gamma", -1.0),
                        ("mesh_aspect", float("inf")), ("mesh_rmax", -1.0)):
         prm = nc.params_default(3)
