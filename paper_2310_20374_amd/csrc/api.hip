@@ -346,6 +346,8 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
         while (ws.mtab_n < 2 * n) ws.mtab_n *= 2;
         ws.mesh = (MeshState *)take(sizeof(MeshState));
         ws.mtab = (MeshSlot *)take(sizeof(MeshSlot) * ws.mtab_n);
+        ws.mgrid_n = 32 * n > (1 << 20) ? 32 * n : (1 << 20);
+        ws.mgrid = (int2 *)take(8 * ws.mgrid_n);
         ws.mkeys = (uint64_t *)take(8 * n);
         ws.mkeys_alt = (uint64_t *)take(8 * n);
         ws.midx = (uint32_t *)take(4 * n);

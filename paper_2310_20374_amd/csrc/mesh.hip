@@ -7,9 +7,10 @@
 // by the Morton key of their cell with a stable radix sort (input order inside a
 // cell; moonlets kept out of the mesh get the largest key and end up last), so each
 // occupied cell is one run of the sorted array and nearby cells sit close together.
-// The runs go into an open-addressing hash table keyed by the cell's Morton key
-// (linear probing, at most half full), which maps a cell to its range [start,
-// end).  A neighbourhood scan looks up the 27 cells around a moonlet's cell and
+// Each run is recorded as the cell's range [start, end): in a dense grid over the
+// box of occupied cells when that box fits the grid buffer (32 cells per moonlet of
+// capacity), else in an open-addressing hash table keyed by the cell's Morton key
+// (linear probing, at most half full).  A neighbourhood scan looks up the 27 cells around a moonlet's cell and
 // reads their moonlets: exactly the neighbours, no other cell shares an entry.  The
 // lanes of a wave hold neighbouring moonlets and look up overlapping cells.
 //
@@ -90,57 +91,42 @@ __device__ __forceinline__ void add_pull(double4 src, double x, double y, double
     a2 += src.w * dz / r3;
 }
 
-// The cells a wave's moonlets look up, gathered once per wave: the box of cells
-// spanned by the wave's moonlets (consecutive in Morton order, so usually a small
-// block), widened by one cell on every side, is looked up by the lanes together into
-// LDS, and each lane then reads its 27 neighbour ranges from there.  A wave whose box
-// holds more than kMeshBox cells (a Morton run that jumps) looks up per lane.  Both
-// ways give the same ranges, so the results do not depend on which one ran.
-constexpr int kMeshBox = 1024;
-
-struct CellBox {
-    int x0, y0, z0, bx, by;
-    bool used;
+// How a scan finds the moonlets of a cell: directly in the dense grid of the box of
+// occupied cells when that box fits the grid buffer (neighbouring cells then sit next
+// to each other in memory), else through the hash table.  Cells outside the box are
+// empty.
+struct CellIndex {
+    const int2 *grid;
+    const MeshSlot *tab;
+    int64_t mask;
+    int x0, y0, z0, dx, dy, dz;
+    bool dense;
 };
 
-__device__ __forceinline__ int wave_min_i(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
+__device__ __forceinline__ CellIndex cell_index(const MeshState *__restrict__ ms,
+                                                const int2 *grid, const MeshSlot *tab,
+                                                int64_t mask) {
+    CellIndex ci;
+    ci.grid = grid; ci.tab = tab; ci.mask = mask;
+    ci.x0 = ms->box_x0; ci.y0 = ms->box_y0; ci.z0 = ms->box_z0;
+    ci.dx = ms->box_dx; ci.dy = ms->box_dy; ci.dz = ms->box_dz;
+    ci.dense = ms->dense != 0;
+    return ci;
 }
 
-// called by every lane of the wave (uniform control flow)
-__device__ __forceinline__ CellBox gather_box(const MeshSlot *__restrict__ tab, int64_t mask,
-                                              int4 c, bool live, int2 *box) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int mnx = wave_min_i(live ? c.x : INT_MAX), mxx = wave_max_i(live ? c.x : INT_MIN);
-    const int mny = wave_min_i(live ? c.y : INT_MAX), mxy = wave_max_i(live ? c.y : INT_MIN);
-    const int mnz = wave_min_i(live ? c.z : INT_MAX), mxz = wave_max_i(live ? c.z : INT_MIN);
-    CellBox b = {0, 0, 0, 0, 0, false};
-    if (mnx > mxx) return b;                       // no moonlet of the mesh in this wave
-    const int64_t bx = (int64_t)mxx - mnx + 3, by = (int64_t)mxy - mny + 3,
-                  bz = (int64_t)mxz - mnz + 3;
-    if (bx * by * bz > kMeshBox) return b;
-    b.x0 = mnx - 1; b.y0 = mny - 1; b.z0 = mnz - 1;
-    b.bx = (int)bx; b.by = (int)by;
-    const int vol = (int)(bx * by * bz);
-    for (int t = lane; t < vol; t += kWave) {
-        const int ix = t % b.bx, iy = (t / b.bx) % b.by, iz = t / (b.bx * b.by);
-        box[t] = lookup(tab, mask, cell_key(b.x0 + ix, b.y0 + iy, b.z0 + iz));
+__device__ __forceinline__ int2 cell_range(const CellIndex &ci, int x, int y, int z) {
+    if (ci.dense) {
+        const int ix = x - ci.x0, iy = y - ci.y0, iz = z - ci.z0;
+        if ((unsigned)ix >= (unsigned)ci.dx || (unsigned)iy >= (unsigned)ci.dy ||
+            (unsigned)iz >= (unsigned)ci.dz)
+            return make_int2(0, 0);
+        return ci.grid[ix + (int64_t)ci.dx * (iy + (int64_t)ci.dy * iz)];
     }
-    wave_sync();
-    b.used = true;
-    return b;
+    return lookup(ci.tab, ci.mask, cell_key(x, y, z));
 }
 
-__device__ __forceinline__ int2 cell_range(const CellBox &b, const int2 *box,
-                                           const MeshSlot *__restrict__ tab, int64_t mask, int x,
-                                           int y, int z) {
-    if (b.used) return box[(x - b.x0) + b.bx * ((y - b.y0) + b.by * (z - b.z0))];
-    return lookup(tab, mask, cell_key(x, y, z));
+__device__ __forceinline__ int64_t grid_cell(const CellIndex &ci, int4 c) {
+    return (c.x - ci.x0) + (int64_t)ci.dx * ((c.y - ci.y0) + (int64_t)ci.dy * (c.z - ci.z0));
 }
 
 // sum of v over the block, valid in thread 0 (every thread calls it)
@@ -177,7 +163,15 @@ __global__ void k_mesh_clear_state(MeshState *ms) {
     }
 }
 
-__global__ void k_mesh_clear_table(MeshSlot *tab, int64_t nslots) {
+__global__ void k_mesh_clear_table(const MeshState *__restrict__ ms, MeshSlot *tab,
+                                   int64_t nslots, int2 *grid) {
+    if (ms->dense) {
+        const int64_t nc = (int64_t)ms->box_dx * ms->box_dy * ms->box_dz;
+        for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nc;
+             b += (int64_t)gridDim.x * blockDim.x)
+            grid[b] = make_int2(0, 0);
+        return;
+    }
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nslots;
          b += (int64_t)gridDim.x * blockDim.x)
         tab[b].key = kMeshEmpty;
@@ -232,25 +226,86 @@ __global__ void k_mesh_begin(MeshState *ms, DevState *st, int64_t n, double x_ta
     ms->nbig = 0;
 }
 
-__global__ void k_mesh_keys(DevState *st, const MeshState *__restrict__ ms,
-                            const double *__restrict__ x, const double *__restrict__ y,
-                            const double *__restrict__ z, const double *__restrict__ R, int64_t n,
-                            uint64_t *keys, uint32_t *vals) {
+__device__ __forceinline__ int wave_min_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+// minimum over the block (every thread calls it; all get the result)
+__device__ __forceinline__ int block_min_i(int v, int *red) {
+    v = wave_min_i(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    int t = INT_MAX;
+    for (int k = 0; k < (int)(blockDim.x / kWave); k++) t = min(t, red[k]);
+    __syncthreads();
+    return t;
+}
+
+// keys (the cell's Morton key; moonlets out of the mesh sorted last) and, per
+// block, the box of the cells seen: part[6 b .. 6 b + 5] = min x, y, z, -max x, y, z
+__global__ void __launch_bounds__(256)
+k_mesh_keys(DevState *st, const MeshState *__restrict__ ms, const double *__restrict__ x,
+            const double *__restrict__ y, const double *__restrict__ z,
+            const double *__restrict__ R, int64_t n, uint64_t *keys, uint32_t *vals,
+            int32_t *box_part) {
+    __shared__ int red[256 / kWave];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const double g = ms->gamma;
-    uint64_t key = kMeshEmpty;                     // out of the mesh: sorted last
-    if (!(2.0 * R[i] > g)) {
-        int4 c;
-        if (cell_of(x[i], y[i], z[i], g, c))
-            key = cell_key(c.x, c.y, c.z);
-        else if (isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i]))
-            atomicOr(&st->status, (int32_t)ST_MESH_RANGE);
-        else
-            atomicOr(&st->status, (int32_t)ST_NONFINITE);   // kept out: never indexed
+    int4 c = make_int4(INT_MAX, INT_MAX, INT_MAX, 0);
+    bool in = false;
+    if (i < n) {
+        uint64_t key = kMeshEmpty;                 // out of the mesh: sorted last
+        if (!(2.0 * R[i] > g)) {
+            if (cell_of(x[i], y[i], z[i], g, c)) {
+                key = cell_key(c.x, c.y, c.z);
+                in = true;
+            } else if (isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i])) {
+                atomicOr(&st->status, (int32_t)ST_MESH_RANGE);
+            } else {
+                atomicOr(&st->status, (int32_t)ST_NONFINITE);   // kept out: never indexed
+            }
+        }
+        keys[i] = key;
+        vals[i] = (uint32_t)i;
     }
-    keys[i] = key;
-    vals[i] = (uint32_t)i;
+    const int mnx = block_min_i(in ? c.x : INT_MAX, red);
+    const int mny = block_min_i(in ? c.y : INT_MAX, red);
+    const int mnz = block_min_i(in ? c.z : INT_MAX, red);
+    const int mxx = block_min_i(in ? -c.x : INT_MAX, red);
+    const int mxy = block_min_i(in ? -c.y : INT_MAX, red);
+    const int mxz = block_min_i(in ? -c.z : INT_MAX, red);
+    if (threadIdx.x == 0) {
+        int32_t *b = box_part + 6 * (int64_t)blockIdx.x;
+        b[0] = mnx; b[1] = mny; b[2] = mnz; b[3] = mxx; b[4] = mxy; b[5] = mxz;
+    }
+}
+
+// the box of occupied cells and whether the dense grid holds it
+__global__ void __launch_bounds__(1024)
+k_mesh_box(const int32_t *__restrict__ box_part, int nblk, MeshState *ms, int64_t grid_cap) {
+    __shared__ int red[1024 / kWave];
+    int v[6];
+    for (int k = 0; k < 6; k++) v[k] = INT_MAX;
+    for (int b = threadIdx.x; b < nblk; b += 1024)
+        for (int k = 0; k < 6; k++) v[k] = min(v[k], box_part[6 * (int64_t)b + k]);
+    for (int k = 0; k < 6; k++) v[k] = block_min_i(v[k], red);
+    if (threadIdx.x == 0) {
+        if (v[0] == INT_MAX) {                    // no moonlet in the mesh
+            ms->box_x0 = ms->box_y0 = ms->box_z0 = 0;
+            ms->box_dx = ms->box_dy = ms->box_dz = 0;
+            ms->dense = 1;
+            return;
+        }
+        const int64_t dx = (int64_t)(-v[3]) - v[0] + 1, dy = (int64_t)(-v[4]) - v[1] + 1,
+                      dz = (int64_t)(-v[5]) - v[2] + 1;
+        ms->box_x0 = v[0]; ms->box_y0 = v[1]; ms->box_z0 = v[2];
+        const bool dense = dx * dy * dz <= grid_cap;
+        ms->box_dx = dense ? (int)dx : 0;
+        ms->box_dy = dense ? (int)dy : 0;
+        ms->box_dz = dense ? (int)dz : 0;
+        ms->dense = dense ? 1 : 0;
+    }
 }
 
 // sorted positions and cells; the first out-of-mesh position is n_in; the first
@@ -258,7 +313,8 @@ __global__ void k_mesh_keys(DevState *st, const MeshState *__restrict__ ms,
 __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restrict__ keys,
                             const uint32_t *__restrict__ idx, const double *__restrict__ x,
                             const double *__restrict__ y, const double *__restrict__ z,
-                            int64_t n, MeshSlot *tab, int64_t mask, double4 *mpos, int4 *mcell) {
+                            int64_t n, MeshSlot *tab, int64_t mask, int2 *grid, double4 *mpos,
+                            int4 *mcell) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n || (st->status & kSkipMask)) return;
     const uint32_t i = idx[q];
@@ -274,6 +330,11 @@ __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restr
     cell_of(x[i], y[i], z[i], g, c);               // in range: checked by k_mesh_keys
     mcell[q] = c;
     if (q > 0 && keys[q - 1] == k) return;
+    if (ms->dense) {
+        const CellIndex ci = cell_index(ms, grid, tab, mask);
+        grid[grid_cell(ci, c)].x = (int32_t)q;
+        return;
+    }
     // the table holds at most n_in <= half its slots, so a free slot is always found
     int64_t h = slot_of(k, mask);
     for (int64_t probes = 0; probes <= mask; probes++) {
@@ -288,12 +349,18 @@ __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restr
 }
 
 // the last moonlet of every cell closes its range
-__global__ void k_mesh_run_ends(const DevState *__restrict__ st, const uint64_t *__restrict__ keys,
-                                int64_t n, MeshSlot *tab, int64_t mask) {
+__global__ void k_mesh_run_ends(const DevState *__restrict__ st, const MeshState *__restrict__ ms,
+                                const uint64_t *__restrict__ keys, const int4 *__restrict__ mcell,
+                                int64_t n, MeshSlot *tab, int64_t mask, int2 *grid) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n || (st->status & kSkipMask)) return;
     const uint64_t k = keys[q];
     if (k == kMeshEmpty || (q + 1 < n && keys[q + 1] == k)) return;
+    if (ms->dense) {
+        const CellIndex ci = cell_index(ms, grid, tab, mask);
+        grid[grid_cell(ci, mcell[q])].y = (int32_t)(q + 1);
+        return;
+    }
     int64_t h = slot_of(k, mask);
     for (int64_t probes = 0; probes <= mask; probes++) {
         if (tab[h].key == k) {
@@ -419,11 +486,11 @@ k_mesh_top_final(DevState *st, MeshState *ms, int64_t n, const Cand *__restrict_
 // massive only count their neighbours here; their sums come from k_mesh_big_sum.
 __global__ void __launch_bounds__(kMeshBlock)
 k_mesh_gravity(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, int64_t mask,
+               const int2 *__restrict__ grid,
                const double4 *__restrict__ mpos, const int4 *__restrict__ mcell,
                const uint32_t *__restrict__ idx, const int32_t *__restrict__ big,
                int count, double *__restrict__ ax, double *__restrict__ ay,
                double *__restrict__ az, unsigned long long *cnt_part) {
-    __shared__ int2 s_box[kMeshBlock / kWave][kMeshBox];
     __shared__ unsigned long long s_red[kMeshBlock / kWave];
     if (st->status & kSkipMask) {
         if (threadIdx.x == 0) cnt_part[blockIdx.x] = 0;
@@ -434,17 +501,16 @@ k_mesh_gravity(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, in
     const int t0 = ms->top[0], t1 = ms->top[1], t2 = ms->top[2];
     unsigned long long cnt = 0;
     const bool live = q < n_in;
-    const int4 c = live ? mcell[q] : make_int4(0, 0, 0, 0);
-    int2 *box = s_box[threadIdx.x / kWave];
-    const CellBox cb = gather_box(tab, mask, c, live, box);
+    const CellIndex ci = cell_index(ms, grid, tab, mask);
     if (live) {
+        const int4 c = mcell[q];
         const double4 p = mpos[q];
         const bool top = q == t0 || q == t1 || q == t2;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (int dz = -1; dz <= 1; dz++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dx = -1; dx <= 1; dx++) {
-                    const int2 e = cell_range(cb, box, tab, mask, c.x + dx, c.y + dy, c.z + dz);
+                    const int2 e = cell_range(ci, c.x + dx, c.y + dy, c.z + dz);
                     for (int r = e.x; r < e.y; r++) {
                         if (r == q) continue;
                         cnt++;
@@ -534,11 +600,11 @@ __global__ void k_mesh_col_init(DevState *st) {
 // one thread per moonlet of the mesh: its neighbours later in sorted order
 __global__ void __launch_bounds__(kMeshBlock)
 k_mesh_collide(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, int64_t mask,
+               const int2 *__restrict__ grid,
                const double4 *__restrict__ mpos, const double4 *__restrict__ mvel,
                const int4 *__restrict__ mcell, const uint32_t *__restrict__ idx, double dt,
                int count, int64_t *out, int64_t cap, unsigned long long *cnt_part,
                unsigned long long *tests_part) {
-    __shared__ int2 s_box[kMeshBlock / kWave][kMeshBox];
     __shared__ unsigned long long s_red[kMeshBlock / kWave];
     if (st->status & kSkipMask) {
         if (threadIdx.x == 0) { cnt_part[blockIdx.x] = 0; tests_part[blockIdx.x] = 0; }
@@ -548,15 +614,14 @@ k_mesh_collide(DevState *st, MeshState *ms, const MeshSlot *__restrict__ tab, in
     const int n_in = ms->n_in;
     unsigned long long cnt = 0, tests = 0;
     const bool live = q < n_in;
-    const int4 c = live ? mcell[q] : make_int4(0, 0, 0, 0);
-    int2 *box = s_box[threadIdx.x / kWave];
-    const CellBox cb = gather_box(tab, mask, c, live, box);
+    const CellIndex ci = cell_index(ms, grid, tab, mask);
     if (live) {
+        const int4 c = mcell[q];
         const double4 p = mpos[q], v = mvel[q];
         for (int dz = -1; dz <= 1; dz++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dx = -1; dx <= 1; dx++) {
-                    const int2 e = cell_range(cb, box, tab, mask, c.x + dx, c.y + dy, c.z + dz);
+                    const int2 e = cell_range(ci, c.x + dx, c.y + dy, c.z + dz);
                     for (int r = e.x; r < e.y; r++) {
                         if (r == q) continue;
                         cnt++;
@@ -630,10 +695,13 @@ hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double 
     k_mesh_begin<<<1, 64, 0, s>>>(ws.mesh, ws.st, n, prm.mesh_neighbours, prm.mesh_aspect,
                                   prm.mesh_rmax, prm.mesh_gamma,
                                   prm.mesh_min_side / prm.mesh_cells);
-    k_mesh_clear_table<<<grid_of(ws.mtab_n, 256) < 4096 ? grid_of(ws.mtab_n, 256) : 4096, 256, 0,
-                         s>>>(ws.mtab, ws.mtab_n);
-    k_mesh_keys<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, x, y, z, R, n, ws.mkeys,
-                                                ws.midx);
+    // the box partials use the counter partials' buffer (free during a build)
+    int32_t *box_part = reinterpret_cast<int32_t *>(ws.count_part);
+    const int kblk = grid_of(n, 256);
+    k_mesh_keys<<<kblk, 256, 0, s>>>(ws.st, ws.mesh, x, y, z, R, n, ws.mkeys, ws.midx,
+                                     box_part);
+    k_mesh_box<<<1, 1024, 0, s>>>(box_part, kblk, ws.mesh, ws.mgrid_n);
+    k_mesh_clear_table<<<4096, 256, 0, s>>>(ws.mesh, ws.mtab, ws.mtab_n, ws.mgrid);
     // 64-bit keys: eight 8-bit passes leave the result in mkeys / midx
     bool in_b = false;
     hipError_t e = launch_radix_sort(ws.mkeys, ws.midx, ws.mkeys_alt, ws.midx_alt, n, 64, ws.hist,
@@ -641,8 +709,9 @@ hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double 
     if (e != hipSuccess) return e;
     if (in_b) return hipErrorInvalidValue;
     k_mesh_runs<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, ws.midx, x, y, z, n,
-                                                ws.mtab, mask, ws.mpos, ws.mcell);
-    k_mesh_run_ends<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mkeys, n, ws.mtab, mask);
+                                                ws.mtab, mask, ws.mgrid, ws.mpos, ws.mcell);
+    k_mesh_run_ends<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, ws.mcell, n,
+                                                    ws.mtab, mask, ws.mgrid);
     return hipGetLastError();
 }
 
@@ -653,7 +722,8 @@ hipError_t launch_mesh_gravity(const Workspace &ws, const double *m, double G, i
     k_mesh_top_part<<<kMeshTopBlocks, kMeshBlock, 0, s>>>(ws.st, ws.mmass, ws.midx, n, part);
     k_mesh_top_final<<<1, kMeshTopBlocks, 0, s>>>(ws.st, ws.mesh, n, part, ws.mbig);
     const int nblk = grid_of(n, kMeshBlock);
-    k_mesh_gravity<<<nblk, kMeshBlock, 0, s>>>(ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mpos,
+    k_mesh_gravity<<<nblk, kMeshBlock, 0, s>>>(ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mgrid,
+                                               ws.mpos,
                                                ws.mcell, ws.midx, ws.mbig, count ? 1 : 0, ax, ay,
                                                az, ws.count_part);
     if (count) k_mesh_count_done<<<1, 1024, 0, s>>>(ws.count_part, nblk, ws.mesh);
@@ -674,7 +744,8 @@ hipError_t launch_mesh_collide(const Workspace &ws, const double *vx, const doub
     // out of the mesh [2 nblk, 2 nblk + kMeshChunks * kMeshBigRows)
     const int nblk = grid_of(n, kMeshBlock);
     unsigned long long *cnt = ws.count_part, *tst = ws.count_part + nblk;
-    k_mesh_collide<<<nblk, kMeshBlock, 0, s>>>(ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mpos,
+    k_mesh_collide<<<nblk, kMeshBlock, 0, s>>>(ws.st, ws.mesh, ws.mtab, ws.mtab_n - 1, ws.mgrid,
+                                               ws.mpos,
                                                ws.mvel, ws.mcell, ws.midx, dt, count ? 1 : 0,
                                                ws.pairs_tmp, ws.pair_cap, cnt, tst);
     k_mesh_collide_out<<<dim3(kMeshChunks, kMeshBigRows), kMeshBlock, 0, s>>>(

@@ -133,7 +133,11 @@ struct MeshState {
     int32_t ntop;                      // the three most massive (sorted positions)
     int32_t top[3];
     int32_t nbig;                      // gravity's all-pairs list (mesh_big)
-    int32_t pad[5];
+    // the box of occupied cells; dense = its cells are indexed directly (mgrid)
+    // instead of through the hash table
+    int32_t box_x0, box_y0, box_z0, box_dx, box_dy, box_dz;
+    int32_t dense;
+    int32_t pad[6];
 };
 
 // Work-queue state of a persistent walk; each counter on its own 128-byte line.
@@ -262,6 +266,8 @@ struct Workspace {
     MeshState *mesh = nullptr;
     MeshSlot *mtab = nullptr;
     int64_t mtab_n = 0;
+    int2 *mgrid = nullptr;                            // dense cell index of the box
+    int64_t mgrid_n = 0;
     uint64_t *mkeys = nullptr, *mkeys_alt = nullptr;
     uint32_t *midx = nullptr, *midx_alt = nullptr;   // sorted position -> input index
     double4 *mpos = nullptr;                          // x, y, z, mu (sorted)

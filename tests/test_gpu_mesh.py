@@ -1,7 +1,8 @@
 """GPU parity of the mesh module (Sect. 3.3): accelerations equal to the oracle's
 neighbour + three-most-massive + oversized pair set to FP64 rounding, colliding
 pairs bit for bit, the mesh size of Eq. (4) and the neighbour count of Eq. (6),
-meshes from a single cell to cells barely larger than the moonlets, moonlets too
+meshes from a single cell to cells barely larger than the moonlets (cells found in
+the dense grid of their box or, for a box too large for it, by hashing), moonlets too
 large for the mesh, and leapfrog steps with the mesh size following Eq. (6) from step to step."""
 
 import numpy as np
@@ -61,6 +62,10 @@ CASES = {
     "clumps6k_g0.05_M128_200out": (lambda: inputs.clumps(6000, seed=4, n_clumps=10), 0.05, 128,
                                    2e-3),
     "gas3k_one_cell": (lambda: inputs.gas_box(3000, seed=5, radius=0.01), 100.0, 4, 0.01),
+    # 250^3 cells around the moonlets: more than the dense grid holds, so the cells
+    # are found through the hash table
+    "gas3k_g0.004_hashed": (lambda: inputs.gas_box(3000, seed=6, radius=1e-3), 0.004, 8,
+                            0.002),
 }
 
 
