@@ -445,21 +445,27 @@ k_cand_count(const DevState *__restrict__ st, const int2 *__restrict__ m2l, int6
 
 // exclusive scan of the block counts (one block); the total is the candidate count
 __global__ void __launch_bounds__(1024) k_cand_scan(DevState *st, int32_t *blk, int nb) {
-    __shared__ int32_t sh[1024];
+    __shared__ int32_t wtot[1024 / kWave];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     int32_t carry = 0;
     for (int b0 = 0; b0 < nb; b0 += 1024) {
         const int i = b0 + threadIdx.x;
         const int32_t x = i < nb ? blk[i] : 0;
-        sh[threadIdx.x] = x;
-        __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            const int32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += t;
-            __syncthreads();
+        int32_t v = x;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int32_t y = __shfl_up(v, o);
+            if (lane >= o) v += y;
         }
-        if (i < nb) blk[i] = carry + sh[threadIdx.x] - x;
-        carry += sh[1023];
+        if (lane == kWave - 1) wtot[w] = v;
+        __syncthreads();
+        int32_t before = 0, all = 0;
+        for (int k = 0; k < 1024 / kWave; k++) {
+            if (k < w) before += wtot[k];
+            all += wtot[k];
+        }
+        if (i < nb) blk[i] = carry + before + v - x;
+        carry += all;
         __syncthreads();
     }
     if (threadIdx.x == 0) {

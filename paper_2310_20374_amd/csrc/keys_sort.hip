@@ -281,53 +281,68 @@ hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
 // ------------------------------------------------------------------ radix sort
 // LSD radix sort of (key, index) by 8-bit digits, 8 passes over 63 bits.  Each
 // pass: per-tile digit histograms, a per-digit scan over tiles, then a stable
-// scatter in which every wave ranks its 64-item rounds with ballots and keeps
-// wave-private running counters, so the tile needs only two barriers.
+// scatter.  The scatter ranks each wave's 64-item rounds with ballots (wave-private
+// running counters), places the tile in LDS in digit order, and then writes it out
+// so that each digit's run of the tile leaves as consecutive stores.
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;                       // per thread
 constexpr int kSortTile = kSortThreads * kSortItems; // 4096
 constexpr int kSortWaves = kSortThreads / kWave;
 
+__device__ __forceinline__ uint32_t sort_digit(const uint64_t *keys, const uint32_t *vals,
+                                               const uint16_t *dseg, int64_t i, int shift) {
+    return dseg ? ((uint32_t)dseg[vals[i]] >> shift) & 255u
+                : (uint32_t)(keys[i] >> shift) & 255u;
+}
+
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_hist(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
              const uint16_t *__restrict__ dseg, int64_t n, int shift, uint32_t *hist,
-             int ntiles) {
+             int ntiles, const int32_t *__restrict__ skip) {
     __shared__ uint32_t h[256];
+    if (skip && *skip) return;
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    uint32_t d[kSortItems];
+#pragma unroll
     for (int k = 0; k < kSortItems; k++) {
-        int64_t i = base + k * kSortThreads + threadIdx.x;
-        if (i < n) {
-            const uint32_t d = dseg ? ((uint32_t)dseg[vals[i]] >> shift) & 255u
-                                    : (uint32_t)(keys[i] >> shift) & 255u;
-            atomicAdd(&h[d], 1u);
-        }
+        const int64_t i = base + k * kSortThreads + threadIdx.x;
+        d[k] = i < n ? sort_digit(keys, vals, dseg, i, shift) : 256u;
     }
+#pragma unroll
+    for (int k = 0; k < kSortItems; k++)
+        if (d[k] < 256u) atomicAdd(&h[d[k]], 1u);
     __syncthreads();
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
 // One block per digit: exclusive scan of that digit's tile counts; digit total out.
 __global__ void __launch_bounds__(256)
-k_radix_scan(uint32_t *hist, int ntiles, uint32_t *totals) {
-    __shared__ uint32_t sh[256];
+k_radix_scan(uint32_t *hist, int ntiles, uint32_t *totals, const int32_t *__restrict__ skip) {
+    __shared__ uint32_t wtot[256 / kWave];
+    if (skip && *skip) return;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     uint32_t *row = hist + (int64_t)blockIdx.x * ntiles;
     uint32_t carry = 0;
     for (int b0 = 0; b0 < ntiles; b0 += 256) {
-        int i = b0 + threadIdx.x;
-        uint32_t v = i < ntiles ? row[i] : 0u;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {
-            uint32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0u;
-            __syncthreads();
-            sh[threadIdx.x] += t;
-            __syncthreads();
+        const int i = b0 + threadIdx.x;
+        const uint32_t x = i < ntiles ? row[i] : 0u;
+        uint32_t v = x;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t y = __shfl_up(v, o);
+            if (lane >= o) v += y;
         }
-        uint32_t incl = sh[threadIdx.x];
-        if (i < ntiles) row[i] = carry + incl - v;
-        carry += sh[255];
+        if (lane == kWave - 1) wtot[w] = v;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (int k = 0; k < 256 / kWave; k++) {
+            if (k < w) before += wtot[k];
+            all += wtot[k];
+        }
+        if (i < ntiles) row[i] = carry + before + v - x;
+        carry += all;
         __syncthreads();
     }
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
@@ -338,84 +353,115 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
+// exclusive prefix sum over the block's 256 threads; wsum (4 entries) must not be
+// reused by the caller before its next barrier
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *wsum) {
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int k = 0; k < w; k++) add += wsum[k];
+    return add + x - v;
+}
+
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                 uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
                 const uint16_t *__restrict__ dseg, int64_t n, int shift,
                 const uint32_t *__restrict__ hist, const uint32_t *__restrict__ totals,
-                int ntiles) {
-    __shared__ uint32_t dbase[256];              // digit base offsets, global
+                int ntiles, const int32_t *__restrict__ skip) {
+    __shared__ uint64_t lkey[kSortTile];         // the tile in digit order
+    __shared__ uint32_t lval[kSortTile];
+    __shared__ uint8_t ldig[kSortTile];
     __shared__ uint32_t wcnt[kSortWaves][256];   // per-wave digit counters
-    __shared__ uint32_t scan_tmp[256];
+    __shared__ uint32_t lstart[256];             // start of each digit's run in the tile
+    __shared__ int32_t delta[256];               // global start minus tile start, per digit
+    __shared__ uint32_t wsum_a[kSortWaves], wsum_b[kSortWaves];
+    if (skip && *skip) return;
     const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
-    // exclusive scan of digit totals -> global start of each digit
-    uint32_t tot = totals[t];
-    scan_tmp[t] = tot;
     for (int k = 0; k < kSortWaves; k++) wcnt[k][t] = 0;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        uint32_t v = t >= o ? scan_tmp[t - o] : 0u;
-        __syncthreads();
-        scan_tmp[t] += v;
-        __syncthreads();
-    }
-    dbase[t] = scan_tmp[t] - tot + hist[(int64_t)t * ntiles + blockIdx.x];
+    // global start of digit t's run from this tile: digits below t, then earlier tiles
+    const uint32_t gstart = block_excl_scan256(totals[t], wsum_a) +
+                            hist[(int64_t)t * ntiles + blockIdx.x];
     // phase 1: this wave's items (a contiguous quarter of the tile), kept in registers
-    const int64_t wbase = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortTile / kSortWaves);
+    const int64_t tbase = (int64_t)blockIdx.x * kSortTile;
+    const int64_t wbase = tbase + (int64_t)w * (kSortTile / kSortWaves);
     uint64_t key[kSortItems];
     uint32_t val[kSortItems];
     uint32_t dig[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
-        int64_t i = wbase + r * kWave + lane;
+        const int64_t i = wbase + r * kWave + lane;
         if (i < n) {
             key[r] = kin[i];
             val[r] = vin[i];
             dig[r] = dseg ? ((uint32_t)dseg[val[r]] >> shift) & 255u
                           : (uint32_t)(key[r] >> shift) & 255u;
-            atomicAdd(&wcnt[w][dig[r]], 1u);
         } else {
             key[r] = 0;
             val[r] = 0;
             dig[r] = 0;
         }
     }
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++)
+        if (wbase + r * kWave + lane < n) atomicAdd(&wcnt[w][dig[r]], 1u);
     __syncthreads();
-    // phase 2: per digit, exclusive prefix over the waves
-    {
-        uint32_t run = 0;
-        for (int k = 0; k < kSortWaves; k++) {
-            uint32_t c = wcnt[k][t];
-            wcnt[k][t] = run;
-            run += c;
-        }
+    // phase 2: per digit, exclusive prefix over the waves, then over the digits
+    uint32_t run = 0;
+    for (int k = 0; k < kSortWaves; k++) {
+        const uint32_t c = wcnt[k][t];
+        wcnt[k][t] = run;
+        run += c;
     }
+    const uint32_t ls = block_excl_scan256(run, wsum_b);
+    lstart[t] = ls;
+    delta[t] = (int32_t)(gstart - ls);           // gstart >= ls: see the digit counts
     __syncthreads();
-    // phase 3: stable ranks inside each 64-item round, wave-private running counts
+    // phase 3: stable ranks inside each 64-item round, wave-private running counts;
+    // items go to their place in the tile's digit order
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
-        int64_t i = wbase + r * kWave + lane;
-        bool valid = i < n;
-        uint64_t act = __ballot(valid);
+        const int64_t i = wbase + r * kWave + lane;
+        const bool valid = i < n;
+        const uint64_t act = __ballot(valid);
         if (act == 0ull) break;
-        uint32_t d = dig[r];
+        const uint32_t d = dig[r];
         uint64_t peers = act;
 #pragma unroll
         for (int b = 0; b < 8; b++) {
-            uint64_t m = __ballot((d >> b) & 1u);
+            const uint64_t m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         if (valid) {
-            uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
-            uint32_t before = wcnt[w][d];
-            uint32_t pos = dbase[d] + before + rank;
-            kout[pos] = key[r];
-            vout[pos] = val[r];
-            bool leader = (peers & lanemask_lt()) == 0ull;
+            const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+            const uint32_t before = wcnt[w][d];
+            const uint32_t lpos = lstart[d] + before + rank;
+            lkey[lpos] = key[r];
+            lval[lpos] = val[r];
+            ldig[lpos] = (uint8_t)d;
+            const bool leader = (peers & lanemask_lt()) == 0ull;
             __builtin_amdgcn_wave_barrier();
             if (leader) wcnt[w][d] = before + (uint32_t)__popcll(peers);
         }
         __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // phase 4: write the tile out in digit order; a digit's run is contiguous in the
+    // output too
+    const int cnt = n - tbase < kSortTile ? (int)(n - tbase) : kSortTile;
+    for (int j = t; j < cnt; j += kSortThreads) {
+        const int64_t pos = (int64_t)delta[ldig[j]] + j;
+        if (pos >= 0 && pos < n) {                // always, by the counts; kept as a guard
+            kout[pos] = lkey[j];
+            vout[pos] = lval[j];
+        }
     }
 }
 
@@ -434,10 +480,11 @@ hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s) {
         // passes 0-7: key digits; then the disk id, low byte first
         const uint16_t *dseg = pass < 8 ? nullptr : ws.seg;
         const int shift = pass < 8 ? 8 * pass : 8 * (pass - 8);
-        k_radix_hist<<<ntiles, kSortThreads, 0, s>>>(ka, va, dseg, n, shift, ws.hist, ntiles);
-        k_radix_scan<<<256, 256, 0, s>>>(ws.hist, ntiles, totals);
+        k_radix_hist<<<ntiles, kSortThreads, 0, s>>>(ka, va, dseg, n, shift, ws.hist, ntiles,
+                                                     nullptr);
+        k_radix_scan<<<256, 256, 0, s>>>(ws.hist, ntiles, totals, nullptr);
         k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(ka, va, kb, vb, dseg, n, shift, ws.hist,
-                                                        totals, ntiles);
+                                                        totals, ntiles, nullptr);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
@@ -445,17 +492,23 @@ hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s) {
 }
 
 // Stable sort of (key, value) by the low `bits` bits of the keys, ping-ponging
-// between the a and b buffers; returns in *in_b whether the result sits in b.
+// between the a and b buffers; returns in *in_b whether the result sits in b.  With
+// `skip` given, the passes from `skip_from` on do nothing when *skip is set on the
+// device (keys known there to fit the lower digits); an even number of them keeps
+// the result where the full sort leaves it.
 hipError_t launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
-                             int bits, uint32_t *hist, bool *in_b, hipStream_t s) {
+                             int bits, uint32_t *hist, bool *in_b, hipStream_t s,
+                             const int32_t *skip, int skip_from) {
     const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
     const int npass = (bits + 7) / 8;
     uint32_t *totals = hist + (int64_t)256 * ntiles;
     for (int pass = 0; pass < npass; pass++) {
-        k_radix_hist<<<ntiles, kSortThreads, 0, s>>>(ka, va, nullptr, n, 8 * pass, hist, ntiles);
-        k_radix_scan<<<256, 256, 0, s>>>(hist, ntiles, totals);
+        const int32_t *sk = skip && pass >= skip_from ? skip : nullptr;
+        k_radix_hist<<<ntiles, kSortThreads, 0, s>>>(ka, va, nullptr, n, 8 * pass, hist, ntiles,
+                                                     sk);
+        k_radix_scan<<<256, 256, 0, s>>>(hist, ntiles, totals, sk);
         k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(ka, va, kb, vb, nullptr, n, 8 * pass,
-                                                        hist, totals, ntiles);
+                                                        hist, totals, ntiles, sk);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }

@@ -40,6 +40,17 @@ __device__ __forceinline__ unsigned long long spread3(unsigned long long v) {
     return v;
 }
 
+// every third bit of v (from bit 0) packed into 21 bits: the inverse of spread3
+__device__ __forceinline__ unsigned long long compact3(unsigned long long v) {
+    v &= 0x1249249249249249ull;
+    v = (v | (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v | (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v | (v >> 16)) & 0x1f00000000ffffull;
+    v = (v | (v >> 32)) & 0x1fffffull;
+    return v;
+}
+
 // Morton key of a cell (coordinates within +-kMeshCellLimit)
 __device__ __forceinline__ unsigned long long cell_key(int x, int y, int z) {
     return spread3((unsigned)(x + kMeshCellLimit)) |
@@ -85,10 +96,11 @@ __device__ __forceinline__ void add_pull(double4 src, double x, double y, double
     const double dx = src.x - x, dy = src.y - y, dz = src.z - z;
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 == 0.0) return;
-    const double r = sqrt(r2), r3 = r2 * r;
-    a0 += src.w * dx / r3;
-    a1 += src.w * dy / r3;
-    a2 += src.w * dz / r3;
+    const double r = sqrt(r2);
+    const double f = src.w / (r2 * r);          // one division per pair
+    a0 += f * dx;
+    a1 += f * dy;
+    a2 += f * dz;
 }
 
 // How a scan finds the moonlets of a cell: directly in the dense grid of the box of
@@ -125,10 +137,6 @@ __device__ __forceinline__ int2 cell_range(const CellIndex &ci, int x, int y, in
     return lookup(ci.tab, ci.mask, cell_key(x, y, z));
 }
 
-__device__ __forceinline__ int64_t grid_cell(const CellIndex &ci, int4 c) {
-    return (c.x - ci.x0) + (int64_t)ci.dx * ((c.y - ci.y0) + (int64_t)ci.dy * (c.z - ci.z0));
-}
-
 // sum of v over the block, valid in thread 0 (every thread calls it)
 __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
                                                             unsigned long long *red) {
@@ -163,18 +171,33 @@ __global__ void k_mesh_clear_state(MeshState *ms) {
     }
 }
 
+// Clears the cell index of the new mesh.  With the dense grid, also replaces each
+// Morton key by the cell's grid index (empty: dense_empty, above every index), so
+// that the sort needs only the digits of the grid's size.
 __global__ void k_mesh_clear_table(const MeshState *__restrict__ ms, MeshSlot *tab,
-                                   int64_t nslots, int2 *grid) {
+                                   int64_t nslots, int2 *grid, uint64_t *keys, int64_t n,
+                                   uint64_t dense_empty) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (ms->dense) {
         const int64_t nc = (int64_t)ms->box_dx * ms->box_dy * ms->box_dz;
-        for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nc;
-             b += (int64_t)gridDim.x * blockDim.x)
-            grid[b] = make_int2(0, 0);
+        for (int64_t b = t0; b < nc; b += stride) grid[b] = make_int2(0, 0);
+        const int x0 = ms->box_x0, y0 = ms->box_y0, z0 = ms->box_z0;
+        const int64_t dx = ms->box_dx, dy = ms->box_dy;
+        for (int64_t i = t0; i < n; i += stride) {
+            const unsigned long long k = keys[i];
+            if (k == kMeshEmpty) {
+                keys[i] = dense_empty;
+                continue;
+            }
+            const int cx = (int)compact3(k) - kMeshCellLimit;
+            const int cy = (int)compact3(k >> 1) - kMeshCellLimit;
+            const int cz = (int)compact3(k >> 2) - kMeshCellLimit;
+            keys[i] = (uint64_t)((cx - x0) + dx * ((cy - y0) + dy * (int64_t)(cz - z0)));
+        }
         return;
     }
-    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nslots;
-         b += (int64_t)gridDim.x * blockDim.x)
-        tab[b].key = kMeshEmpty;
+    for (int64_t b = t0; b < nslots; b += stride) tab[b].key = kMeshEmpty;
 }
 
 __global__ void k_mesh_rmax(const double *__restrict__ x, const double *__restrict__ y,
@@ -309,20 +332,23 @@ k_mesh_box(const int32_t *__restrict__ box_part, int nblk, MeshState *ms, int64_
 }
 
 // sorted positions and cells; the first out-of-mesh position is n_in; the first
-// moonlet of every cell claims the cell's slot
+// moonlet of every cell claims the cell's slot.  Keys are grid indices (empty:
+// dense_empty) with the dense grid, Morton keys (empty: kMeshEmpty) otherwise.
 __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restrict__ keys,
                             const uint32_t *__restrict__ idx, const double *__restrict__ x,
                             const double *__restrict__ y, const double *__restrict__ z,
                             int64_t n, MeshSlot *tab, int64_t mask, int2 *grid, double4 *mpos,
-                            int4 *mcell) {
+                            int4 *mcell, uint64_t dense_empty) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n || (st->status & kSkipMask)) return;
     const uint32_t i = idx[q];
     const double g = ms->gamma;
+    const bool dense = ms->dense != 0;
+    const uint64_t empty = dense ? dense_empty : kMeshEmpty;
     mpos[q] = make_double4(x[i], y[i], z[i], 0.0);
     const uint64_t k = keys[q];
-    if (k == kMeshEmpty) {
-        if (q == 0 || keys[q - 1] != kMeshEmpty) ms->n_in = (int32_t)q;
+    if (k == empty) {
+        if (q == 0 || keys[q - 1] != empty) ms->n_in = (int32_t)q;
         mcell[q] = make_int4(0, 0, 0, 0);
         return;
     }
@@ -330,9 +356,8 @@ __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restr
     cell_of(x[i], y[i], z[i], g, c);               // in range: checked by k_mesh_keys
     mcell[q] = c;
     if (q > 0 && keys[q - 1] == k) return;
-    if (ms->dense) {
-        const CellIndex ci = cell_index(ms, grid, tab, mask);
-        grid[grid_cell(ci, c)].x = (int32_t)q;
+    if (dense) {
+        grid[k].x = (int32_t)q;
         return;
     }
     // the table holds at most n_in <= half its slots, so a free slot is always found
@@ -350,15 +375,15 @@ __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restr
 
 // the last moonlet of every cell closes its range
 __global__ void k_mesh_run_ends(const DevState *__restrict__ st, const MeshState *__restrict__ ms,
-                                const uint64_t *__restrict__ keys, const int4 *__restrict__ mcell,
-                                int64_t n, MeshSlot *tab, int64_t mask, int2 *grid) {
+                                const uint64_t *__restrict__ keys, int64_t n, MeshSlot *tab,
+                                int64_t mask, int2 *grid, uint64_t dense_empty) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n || (st->status & kSkipMask)) return;
+    const bool dense = ms->dense != 0;
     const uint64_t k = keys[q];
-    if (k == kMeshEmpty || (q + 1 < n && keys[q + 1] == k)) return;
-    if (ms->dense) {
-        const CellIndex ci = cell_index(ms, grid, tab, mask);
-        grid[grid_cell(ci, mcell[q])].y = (int32_t)(q + 1);
+    if (k == (dense ? dense_empty : kMeshEmpty) || (q + 1 < n && keys[q + 1] == k)) return;
+    if (dense) {
+        grid[k].y = (int32_t)(q + 1);
         return;
     }
     int64_t h = slot_of(k, mask);
@@ -701,17 +726,27 @@ hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double 
     k_mesh_keys<<<kblk, 256, 0, s>>>(ws.st, ws.mesh, x, y, z, R, n, ws.mkeys, ws.midx,
                                      box_part);
     k_mesh_box<<<1, 1024, 0, s>>>(box_part, kblk, ws.mesh, ws.mgrid_n);
-    k_mesh_clear_table<<<4096, 256, 0, s>>>(ws.mesh, ws.mtab, ws.mtab_n, ws.mgrid);
-    // 64-bit keys: eight 8-bit passes leave the result in mkeys / midx
+    // dense grid: keys become grid indices below 2^gbits, all-ones in those bits when
+    // empty, and the sort skips the digits above (an even number of passes, so that
+    // the result lands where the full sort leaves it)
+    int gbits = 1;
+    while (gbits < 63 && (1ll << gbits) <= ws.mgrid_n) gbits++;
+    const uint64_t dense_empty = (1ull << gbits) - 1ull;
+    int keep = (gbits + 7) / 8;
+    if ((8 - keep) % 2) keep++;
+    k_mesh_clear_table<<<4096, 256, 0, s>>>(ws.mesh, ws.mtab, ws.mtab_n, ws.mgrid, ws.mkeys, n,
+                                            dense_empty);
+    // eight 8-bit passes (or `keep` of them) leave the result in mkeys / midx
     bool in_b = false;
     hipError_t e = launch_radix_sort(ws.mkeys, ws.midx, ws.mkeys_alt, ws.midx_alt, n, 64, ws.hist,
-                                     &in_b, s);
+                                     &in_b, s, &ws.mesh->dense, keep);
     if (e != hipSuccess) return e;
     if (in_b) return hipErrorInvalidValue;
     k_mesh_runs<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, ws.midx, x, y, z, n,
-                                                ws.mtab, mask, ws.mgrid, ws.mpos, ws.mcell);
-    k_mesh_run_ends<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, ws.mcell, n,
-                                                    ws.mtab, mask, ws.mgrid);
+                                                ws.mtab, mask, ws.mgrid, ws.mpos, ws.mcell,
+                                                dense_empty);
+    k_mesh_run_ends<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, n, ws.mtab, mask,
+                                                    ws.mgrid, dense_empty);
     return hipGetLastError();
 }
 

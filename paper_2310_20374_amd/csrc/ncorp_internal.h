@@ -356,7 +356,8 @@ hipError_t launch_sum_u64(const unsigned long long *part, int64_t n, unsigned lo
                           bool add, hipStream_t s);
 // mesh module (Sect. 3.3)
 hipError_t launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
-                             int bits, uint32_t *hist, bool *in_b, hipStream_t s);
+                             int bits, uint32_t *hist, bool *in_b, hipStream_t s,
+                             const int32_t *skip = nullptr, int skip_from = 0);
 hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double *y,
                              const double *z, const double *R, int64_t n, const ncorp_params &prm,
                              bool first, hipStream_t s);

@@ -54,11 +54,11 @@ __device__ __forceinline__ void direct_sum(const double *__restrict__ xs,
         const double dx = xs[j] - x, dy = ys[j] - y, dz = zs[j] - z;
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 == 0.0) continue;
-        const double r = sqrt(r2), r3 = r2 * r;
-        const double mu = mus[j];
-        a0 += mu * dx / r3;
-        a1 += mu * dy / r3;
-        a2 += mu * dz / r3;
+        const double r = sqrt(r2);
+        const double f = mus[j] / (r2 * r);      // one division per pair
+        a0 += f * dx;
+        a1 += f * dy;
+        a2 += f * dz;
     }
 }
 
