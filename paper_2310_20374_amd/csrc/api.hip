@@ -272,6 +272,7 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.idx = (uint32_t *)take(4 * n);
     ws.idx_alt = (uint32_t *)take(4 * n);
     ws.code = (uint32_t *)take(4 * n);
+    ws.pack4 = (double4 *)take(32 * n);
     ws.xs = (double *)take(8 * n);
     ws.ys = (double *)take(8 * n);
     ws.zs = (double *)take(8 * n);
@@ -430,7 +431,7 @@ static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const
     }
     {
         PhaseTimer t(c, NCORP_PHASE_TREE, s);
-        HIPCHK(c, launch_gather_pos(ws, x, y, z, n, s));
+        HIPCHK(c, launch_gather_pos(ws, n, s));
         HIPCHK(c, launch_build_tree(ws, n, c->prm.leaf_size, s));
     }
     c->have_tree = true;

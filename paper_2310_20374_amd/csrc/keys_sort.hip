@@ -230,7 +230,8 @@ __global__ void k_keys(const double *__restrict__ x, const double *__restrict__ 
                        const double *__restrict__ z, int64_t n, double fixed_L,
                        const unsigned long long *__restrict__ mx,
                        const uint16_t *__restrict__ seg, int nd, double *__restrict__ disk_L,
-                       DevState *st, uint64_t *__restrict__ keys, uint32_t *__restrict__ idx) {
+                       DevState *st, uint64_t *__restrict__ keys, uint32_t *__restrict__ idx,
+                       double4 *__restrict__ pack4) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gid < nd) {
         const double L = fixed_L > 0.0 ? fixed_L : root_half_width(mx[gid]);
@@ -241,9 +242,11 @@ __global__ void k_keys(const double *__restrict__ x, const double *__restrict__ 
     for (int64_t i = gid; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         if (seg && !(fixed_L > 0.0)) L = root_half_width(mx[seg[i]]);
         const double scale = 1048576.0 / L;
-        keys[i] = hilbert21(quantize(x[i], L, scale), quantize(y[i], L, scale),
-                            quantize(z[i], L, scale));
+        const double px = x[i], py = y[i], pz = z[i];
+        keys[i] = hilbert21(quantize(px, L, scale), quantize(py, L, scale),
+                            quantize(pz, L, scale));
         idx[i] = (uint32_t)i;
+        pack4[i] = make_double4(px, py, pz, 0.0);   // one record per moonlet for the gather
     }
 }
 
@@ -268,12 +271,14 @@ hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                                                             ws.st);
         const int64_t cover = n > nd ? n : nd;
         k_keys<<<grid_for(cover, 256), 256, 0, s>>>(x, y, z, n, root_half_width, ws.disk_max,
-                                                    ws.seg, nd, ws.disk_L, ws.st, kout, vout);
+                                                    ws.seg, nd, ws.disk_L, ws.st, kout, vout,
+                                                    ws.pack4);
     } else {
         k_max_abs<<<grid_for(n, 256, 1024), 256, 0, s>>>(x, y, z, n, ws.st);
         k_keys<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, n, root_half_width,
                                                 (const unsigned long long *)&ws.st->max_abs,
-                                                nullptr, 1, ws.disk_L, ws.st, kout, vout);
+                                                nullptr, 1, ws.disk_L, ws.st, kout, vout,
+                                                ws.pack4);
     }
     return hipGetLastError();
 }
@@ -517,16 +522,17 @@ hipError_t launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t 
 }
 
 // ------------------------------------------------------------------ gathers
-__global__ void k_gather3(const double *__restrict__ x, const double *__restrict__ y,
-                          const double *__restrict__ z, const uint32_t *__restrict__ idx,
-                          int64_t n, double *__restrict__ xs, double *__restrict__ ys,
-                          double *__restrict__ zs) {
+// Positions in tree order from the packed records k_keys wrote in input order: one
+// 32-byte record per moonlet instead of three scattered 8-byte words.
+__global__ void k_gather_pack4(const double4 *__restrict__ pack4, const uint32_t *__restrict__ idx,
+                              int64_t n, double *__restrict__ xs, double *__restrict__ ys,
+                              double *__restrict__ zs) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t j = idx[i];
-        xs[i] = x[j];
-        ys[i] = y[j];
-        zs[i] = z[j];
+        const double4 p = pack4[idx[i]];
+        xs[i] = p.x;
+        ys[i] = p.y;
+        zs[i] = p.z;
     }
 }
 
@@ -537,9 +543,8 @@ __global__ void k_gather1(const double *__restrict__ src, const uint32_t *__rest
         dst[i] = src[idx[i]];
 }
 
-hipError_t launch_gather_pos(const Workspace &ws, const double *x, const double *y,
-                             const double *z, int64_t n, hipStream_t s) {
-    k_gather3<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, ws.idx, n, ws.xs, ws.ys, ws.zs);
+hipError_t launch_gather_pos(const Workspace &ws, int64_t n, hipStream_t s) {
+    k_gather_pack4<<<grid_for(n, 256), 256, 0, s>>>(ws.pack4, ws.idx, n, ws.xs, ws.ys, ws.zs);
     return hipGetLastError();
 }
 
@@ -556,25 +561,43 @@ hipError_t launch_gather_scaled(const Workspace &ws, const double *src, double s
     return hipGetLastError();
 }
 
-__global__ void k_gather4(const double *__restrict__ a, const double *__restrict__ b,
-                          const double *__restrict__ c, const double *__restrict__ d,
-                          const uint32_t *__restrict__ idx, int64_t n, double *__restrict__ as,
-                          double *__restrict__ bs, double *__restrict__ cs,
-                          double *__restrict__ ds) {
+// (a, b, c, d)[i] packed into one 32-byte record, in input order (coalesced)
+__global__ void k_pack4(const double *__restrict__ a, const double *__restrict__ b,
+                        const double *__restrict__ c, const double *__restrict__ d, int64_t n,
+                        double4 *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = make_double4(a[i], b[i], c[i], d[i]);
+}
+
+__global__ void k_gather_vr(const double4 *__restrict__ pack4, const uint32_t *__restrict__ idx,
+                            int64_t n, double *__restrict__ as, double *__restrict__ bs,
+                            double *__restrict__ cs, double *__restrict__ ds) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t j = idx[i];
-        as[i] = a[j];
-        bs[i] = b[j];
-        cs[i] = c[j];
-        ds[i] = d[j];
+        const double4 v = pack4[idx[i]];
+        as[i] = v.x;
+        bs[i] = v.y;
+        cs[i] = v.z;
+        ds[i] = v.w;
     }
 }
 
+// velocities and radii packed in input order (for a gather into tree or mesh order)
+hipError_t launch_pack_vr(const Workspace &ws, const double *vx, const double *vy,
+                          const double *vz, const double *R, int64_t n, hipStream_t s) {
+    k_pack4<<<grid_for(n, 256), 256, 0, s>>>(vx, vy, vz, R, n, ws.pack4);
+    return hipGetLastError();
+}
+
+// velocities and radii in tree order: packed first, then one record per moonlet
+// instead of four scattered words
 hipError_t launch_gather_vr(const Workspace &ws, const double *vx, const double *vy,
                             const double *vz, const double *R, int64_t n, hipStream_t s) {
-    k_gather4<<<grid_for(n, 256), 256, 0, s>>>(vx, vy, vz, R, ws.idx, n, ws.vxs, ws.vys, ws.vzs,
-                                               ws.rads);
+    hipError_t e = launch_pack_vr(ws, vx, vy, vz, R, n, s);
+    if (e != hipSuccess) return e;
+    k_gather_vr<<<grid_for(n, 256), 256, 0, s>>>(ws.pack4, ws.idx, n, ws.vxs, ws.vys, ws.vzs,
+                                                 ws.rads);
     return hipGetLastError();
 }
 

@@ -271,19 +271,21 @@ __global__ void __launch_bounds__(256)
 k_mesh_keys(DevState *st, const MeshState *__restrict__ ms, const double *__restrict__ x,
             const double *__restrict__ y, const double *__restrict__ z,
             const double *__restrict__ R, int64_t n, uint64_t *keys, uint32_t *vals,
-            int32_t *box_part) {
+            int32_t *box_part, double4 *__restrict__ pack4) {
     __shared__ int red[256 / kWave];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const double g = ms->gamma;
     int4 c = make_int4(INT_MAX, INT_MAX, INT_MAX, 0);
     bool in = false;
     if (i < n) {
+        const double px = x[i], py = y[i], pz = z[i];
+        pack4[i] = make_double4(px, py, pz, 0.0);   // one record per moonlet for the gather
         uint64_t key = kMeshEmpty;                 // out of the mesh: sorted last
         if (!(2.0 * R[i] > g)) {
-            if (cell_of(x[i], y[i], z[i], g, c)) {
+            if (cell_of(px, py, pz, g, c)) {
                 key = cell_key(c.x, c.y, c.z);
                 in = true;
-            } else if (isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i])) {
+            } else if (isfinite(px) && isfinite(py) && isfinite(pz)) {
                 atomicOr(&st->status, (int32_t)ST_MESH_RANGE);
             } else {
                 atomicOr(&st->status, (int32_t)ST_NONFINITE);   // kept out: never indexed
@@ -335,8 +337,7 @@ k_mesh_box(const int32_t *__restrict__ box_part, int nblk, MeshState *ms, int64_
 // moonlet of every cell claims the cell's slot.  Keys are grid indices (empty:
 // dense_empty) with the dense grid, Morton keys (empty: kMeshEmpty) otherwise.
 __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restrict__ keys,
-                            const uint32_t *__restrict__ idx, const double *__restrict__ x,
-                            const double *__restrict__ y, const double *__restrict__ z,
+                            const uint32_t *__restrict__ idx, const double4 *__restrict__ pack4,
                             int64_t n, MeshSlot *tab, int64_t mask, int2 *grid, double4 *mpos,
                             int4 *mcell, uint64_t dense_empty) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -345,7 +346,8 @@ __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restr
     const double g = ms->gamma;
     const bool dense = ms->dense != 0;
     const uint64_t empty = dense ? dense_empty : kMeshEmpty;
-    mpos[q] = make_double4(x[i], y[i], z[i], 0.0);
+    const double4 p = pack4[i];
+    mpos[q] = p;
     const uint64_t k = keys[q];
     if (k == empty) {
         if (q == 0 || keys[q - 1] != empty) ms->n_in = (int32_t)q;
@@ -353,7 +355,7 @@ __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restr
         return;
     }
     int4 c;
-    cell_of(x[i], y[i], z[i], g, c);               // in range: checked by k_mesh_keys
+    cell_of(p.x, p.y, p.z, g, c);                  // in range: checked by k_mesh_keys
     mcell[q] = c;
     if (q > 0 && keys[q - 1] == k) return;
     if (dense) {
@@ -608,14 +610,12 @@ __global__ void k_mesh_big_final(const DevState *__restrict__ st,
 }
 
 // ------------------------------------------------------------------ collisions
-__global__ void k_mesh_vel(const uint32_t *__restrict__ idx, const double *__restrict__ vx,
-                           const double *__restrict__ vy, const double *__restrict__ vz,
-                           const double *__restrict__ R, int64_t n, double4 *mvel) {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q < n) {
-        const uint32_t i = idx[q];
-        mvel[q] = make_double4(vx[i], vy[i], vz[i], R[i]);
-    }
+// velocities and radii in mesh order, from their packed records
+__global__ void k_mesh_vel(const uint32_t *__restrict__ idx, const double4 *__restrict__ pack4,
+                           int64_t n, double4 *mvel) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        mvel[q] = pack4[idx[q]];
 }
 
 __global__ void k_mesh_col_init(DevState *st) {
@@ -724,7 +724,7 @@ hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double 
     int32_t *box_part = reinterpret_cast<int32_t *>(ws.count_part);
     const int kblk = grid_of(n, 256);
     k_mesh_keys<<<kblk, 256, 0, s>>>(ws.st, ws.mesh, x, y, z, R, n, ws.mkeys, ws.midx,
-                                     box_part);
+                                     box_part, ws.pack4);
     k_mesh_box<<<1, 1024, 0, s>>>(box_part, kblk, ws.mesh, ws.mgrid_n);
     // dense grid: keys become grid indices below 2^gbits, all-ones in those bits when
     // empty, and the sort skips the digits above (an even number of passes, so that
@@ -742,7 +742,7 @@ hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double 
                                      &in_b, s, &ws.mesh->dense, keep);
     if (e != hipSuccess) return e;
     if (in_b) return hipErrorInvalidValue;
-    k_mesh_runs<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, ws.midx, x, y, z, n,
+    k_mesh_runs<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, ws.midx, ws.pack4, n,
                                                 ws.mtab, mask, ws.mgrid, ws.mpos, ws.mcell,
                                                 dense_empty);
     k_mesh_run_ends<<<grid_of(n, 256), 256, 0, s>>>(ws.st, ws.mesh, ws.mkeys, n, ws.mtab, mask,
@@ -773,7 +773,9 @@ hipError_t launch_mesh_gravity(const Workspace &ws, const double *m, double G, i
 hipError_t launch_mesh_collide(const Workspace &ws, const double *vx, const double *vy,
                                const double *vz, const double *R, int64_t n, double dt,
                                bool count, hipStream_t s) {
-    k_mesh_vel<<<grid_of(n, 256), 256, 0, s>>>(ws.midx, vx, vy, vz, R, n, ws.mvel);
+    hipError_t e0 = launch_pack_vr(ws, vx, vy, vz, R, n, s);
+    if (e0 != hipSuccess) return e0;
+    k_mesh_vel<<<grid_of(n, 256), 256, 0, s>>>(ws.midx, ws.pack4, n, ws.mvel);
     k_mesh_col_init<<<1, 64, 0, s>>>(ws.st);
     // partials: neighbour counts [0, nblk), tests [nblk, 2 nblk), tests of the moonlets
     // out of the mesh [2 nblk, 2 nblk + kMeshChunks * kMeshBigRows)

@@ -207,6 +207,10 @@ struct Workspace {
     uint32_t *code = nullptr;                         // tree-build per-moonlet code
     double *xs = nullptr, *ys = nullptr, *zs = nullptr, *mus = nullptr;
     double *vxs = nullptr, *vys = nullptr, *vzs = nullptr, *rads = nullptr;
+    // packed 32-byte records in input order, staging for the gathers into tree or
+    // mesh order: (x, y, z, 0) from the key passes, (vx, vy, vz, R) before a
+    // collision search
+    double4 *pack4 = nullptr;
     double4 *pcol = nullptr;                          // x, y, z, R + dt |v| (collisions)
     double *acc = nullptr;                            // 3 x n, input order (step)
     double *acc_s = nullptr;                          // 3 x n, tree order (direct sums)
@@ -300,11 +304,12 @@ hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                        const double *z, int64_t n, double root_half_width,
                        const int64_t *disk_off, hipStream_t s);
 hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s);
-hipError_t launch_gather_pos(const Workspace &ws, const double *x, const double *y,
-                             const double *z, int64_t n, hipStream_t s);
+hipError_t launch_gather_pos(const Workspace &ws, int64_t n, hipStream_t s);
 hipError_t launch_gather(const Workspace &ws, const double *src, double *dst, int64_t n,
                          hipStream_t s);
 // velocities and radii into tree order, one pass
+hipError_t launch_pack_vr(const Workspace &ws, const double *vx, const double *vy,
+                          const double *vz, const double *R, int64_t n, hipStream_t s);
 hipError_t launch_gather_vr(const Workspace &ws, const double *vx, const double *vy,
                             const double *vz, const double *R, int64_t n, hipStream_t s);
 hipError_t launch_build_tree(const Workspace &ws, int64_t n, int leaf_size, hipStream_t s);
