@@ -65,16 +65,29 @@ __global__ void k_max_abs(const double *__restrict__ x, const double *__restrict
     __shared__ unsigned long long red[256 / kWave];
     unsigned long long m = 0ull;
     bool bad = false;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double v[3] = {x[i], y[i], z[i]};
+    // four strided moonlets per round, their loads issued together
+    constexpr int kBatch = 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < n;
+         i0 += kBatch * stride) {
+        double v[kBatch][3];
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            double a = fabs(v[k]);
-            if (!(a <= 1.79769313486231570e308)) { bad = true; continue; }
-            unsigned long long b = (unsigned long long)__double_as_longlong(a);
-            m = b > m ? b : m;
+        for (int b = 0; b < kBatch; b++) {
+            const int64_t i = i0 + b * stride;
+            const bool in = i < n;
+            v[b][0] = in ? x[i] : 0.0;
+            v[b][1] = in ? y[i] : 0.0;
+            v[b][2] = in ? z[i] : 0.0;
         }
+#pragma unroll
+        for (int b = 0; b < kBatch; b++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const double a = fabs(v[b][k]);
+                if (!(a <= 1.79769313486231570e308)) { bad = true; continue; }
+                const unsigned long long u = (unsigned long long)__double_as_longlong(a);
+                m = u > m ? u : m;
+            }
     }
     for (int o = kWave / 2; o > 0; o >>= 1) {
         unsigned long long t = __shfl_xor(m, o);
@@ -274,7 +287,8 @@ hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                                                     ws.seg, nd, ws.disk_L, ws.st, kout, vout,
                                                     ws.pack4);
     } else {
-        k_max_abs<<<grid_for(n, 256, 1024), 256, 0, s>>>(x, y, z, n, ws.st);
+        // few blocks: each ends with one atomic on the same word
+        k_max_abs<<<grid_for(n, 256, 256), 256, 0, s>>>(x, y, z, n, ws.st);
         k_keys<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, n, root_half_width,
                                                 (const unsigned long long *)&ws.st->max_abs,
                                                 nullptr, 1, ws.disk_L, ws.st, kout, vout,

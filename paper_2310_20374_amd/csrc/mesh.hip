@@ -419,41 +419,64 @@ struct Cand {
 static_assert(sizeof(Cand) == 16, "top-three candidates take 16 bytes");
 
 // a before b: larger mass, then smaller input index
-__device__ __forceinline__ bool heavier(const Cand &a, const Cand &b) {
-    if (a.q < 0) return false;
-    if (b.q < 0) return true;
-    return a.m > b.m || (a.m == b.m && a.i < b.i);
+__device__ __forceinline__ bool heavier(double ma, uint32_t ia, int qa, double mb, uint32_t ib,
+                                        int qb) {
+    if (qa < 0) return false;
+    if (qb < 0) return true;
+    return ma > mb || (ma == mb && ia < ib);
 }
 
-__device__ __forceinline__ void insert3(Cand t[3], const Cand &c) {
-    if (heavier(c, t[0])) { t[2] = t[1]; t[1] = t[0]; t[0] = c; }
-    else if (heavier(c, t[1])) { t[2] = t[1]; t[1] = c; }
-    else if (heavier(c, t[2])) t[2] = c;
-}
+// The best three so far, heaviest first, as plain scalars (they stay in registers).
+struct Top3 {
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    uint32_t i0 = 0u, i1 = 0u, i2 = 0u;
+    int q0 = -1, q1 = -1, q2 = -1;
 
-// the best three of a wave's lists (every lane ends with them)
-__device__ __forceinline__ void wave_top3(Cand t[3]) {
-    for (int o = 32; o > 0; o >>= 1) {
-        Cand u[3];
-        for (int k = 0; k < 3; k++) {
-            u[k].m = __shfl_xor(t[k].m, o);
-            u[k].i = (uint32_t)__shfl_xor((int)t[k].i, o);
-            u[k].q = __shfl_xor(t[k].q, o);
+    __device__ __forceinline__ void insert(double m, uint32_t i, int q) {
+        if (heavier(m, i, q, m0, i0, q0)) {
+            m2 = m1; i2 = i1; q2 = q1;
+            m1 = m0; i1 = i0; q1 = q0;
+            m0 = m; i0 = i; q0 = q;
+        } else if (heavier(m, i, q, m1, i1, q1)) {
+            m2 = m1; i2 = i1; q2 = q1;
+            m1 = m; i1 = i; q1 = q;
+        } else if (heavier(m, i, q, m2, i2, q2)) {
+            m2 = m; i2 = i; q2 = q;
         }
-        for (int k = 0; k < 3; k++) insert3(t, u[k]);
     }
-}
+    __device__ __forceinline__ void insert(const Cand &c) { insert(c.m, c.i, c.q); }
+    __device__ __forceinline__ Cand get(int k) const {
+        return k == 0 ? Cand{m0, i0, q0} : (k == 1 ? Cand{m1, i1, q1} : Cand{m2, i2, q2});
+    }
+    // merge lane (this ^ o)'s three
+    __device__ __forceinline__ void merge_xor(int o) {
+        const double a = __shfl_xor(m0, o), b = __shfl_xor(m1, o), c = __shfl_xor(m2, o);
+        const uint32_t ia = (uint32_t)__shfl_xor((int)i0, o), ib = (uint32_t)__shfl_xor((int)i1, o),
+                       ic = (uint32_t)__shfl_xor((int)i2, o);
+        const int qa = __shfl_xor(q0, o), qb = __shfl_xor(q1, o), qc = __shfl_xor(q2, o);
+        insert(a, ia, qa);
+        insert(b, ib, qb);
+        insert(c, ic, qc);
+    }
+};
 
-// block-wide best three into t of thread 0
-__device__ __forceinline__ void block_top3(Cand t[3], Cand *lds) {
-    wave_top3(t);
+// block-wide best three, valid in thread 0
+__device__ __forceinline__ void block_top3(Top3 &t, Cand *lds) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t.merge_xor(o);
     const int w = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0)
-        for (int k = 0; k < 3; k++) lds[3 * w + k] = t[k];
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        lds[3 * w] = t.get(0);
+        lds[3 * w + 1] = t.get(1);
+        lds[3 * w + 2] = t.get(2);
+    }
     __syncthreads();
     if (threadIdx.x == 0)
-        for (int v = 1; v < (int)(blockDim.x / kWave); v++)
-            for (int k = 0; k < 3; k++) insert3(t, lds[3 * v + k]);
+        for (int v = 1; v < (int)(blockDim.x / kWave); v++) {
+            t.insert(lds[3 * v]);
+            t.insert(lds[3 * v + 1]);
+            t.insert(lds[3 * v + 2]);
+        }
 }
 
 __global__ void __launch_bounds__(kMeshBlock)
@@ -461,14 +484,32 @@ k_mesh_top_part(const DevState *__restrict__ st, const double *__restrict__ mmas
                 const uint32_t *__restrict__ idx, int64_t n, Cand *part) {
     __shared__ Cand lds[3 * kMeshBlock / kWave];
     if (st->status & kSkipMask) return;
-    Cand t[3];
-    for (int k = 0; k < 3; k++) t[k] = Cand{0.0, 0u, -1};
-    for (int64_t q = blockIdx.x * (int64_t)kMeshBlock + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * kMeshBlock)
-        insert3(t, Cand{mmass[q], idx[q], (int)q});
+    Top3 t;
+    // eight strided items per round, their loads issued together
+    constexpr int kBatch = 8;
+    const int64_t stride = (int64_t)gridDim.x * kMeshBlock;
+    for (int64_t q0 = blockIdx.x * (int64_t)kMeshBlock + threadIdx.x; q0 < n;
+         q0 += kBatch * stride) {
+        double m[kBatch];
+        uint32_t id[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; b++) {
+            const int64_t q = q0 + b * stride;
+            m[b] = q < n ? mmass[q] : 0.0;
+            id[b] = q < n ? idx[q] : 0u;
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; b++) {
+            const int64_t q = q0 + b * stride;
+            if (q < n) t.insert(m[b], id[b], (int)q);
+        }
+    }
     block_top3(t, lds);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 3; k++) part[3 * blockIdx.x + k] = t[k];
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = t.get(0);
+        part[3 * blockIdx.x + 1] = t.get(1);
+        part[3 * blockIdx.x + 2] = t.get(2);
+    }
 }
 
 // the three most massive, and gravity's all-pairs list: the moonlets out of the
@@ -479,18 +520,21 @@ k_mesh_top_final(DevState *st, MeshState *ms, int64_t n, const Cand *__restrict_
     __shared__ Cand lds[3 * kMeshTopBlocks / kWave];
     __shared__ int s_nbig;
     if (st->status & kSkipMask) return;
-    Cand t[3];
-    for (int k = 0; k < 3; k++) t[k] = part[3 * threadIdx.x + k];
+    Top3 t;
+    t.insert(part[3 * threadIdx.x]);
+    t.insert(part[3 * threadIdx.x + 1]);
+    t.insert(part[3 * threadIdx.x + 2]);
     block_top3(t, lds);
     const int n_in = ms->n_in;
     const int nover = (int)n - n_in;
     if (threadIdx.x == 0) {
         int ntop = 0, nbig = nover;
-        for (int k = 0; k < 3; k++)
-            if (t[k].q >= 0) ms->top[ntop++] = t[k].q;
-        for (int k = ntop; k < 3; k++) ms->top[k] = -1;
+        // the three are heaviest first, the missing ones (q = -1) last
+        const int top[3] = {t.q0, t.q1, t.q2};
+        ntop = (t.q0 >= 0) + (t.q1 >= 0) + (t.q2 >= 0);
+        for (int k = 0; k < 3; k++) ms->top[k] = top[k];
         ms->ntop = ntop;
-        for (int k = 0; k < ntop; k++) nbig += ms->top[k] < n_in;
+        for (int k = 0; k < ntop; k++) nbig += top[k] < n_in;
         if (nbig > kMaxMeshBig) {
             atomicOr(&st->status, (int32_t)ST_CAP_MESH);
             atomicMax((unsigned long long *)&st->required, (unsigned long long)nbig);
@@ -498,7 +542,7 @@ k_mesh_top_final(DevState *st, MeshState *ms, int64_t n, const Cand *__restrict_
         } else {
             int b = nover;
             for (int k = 0; k < ntop; k++)
-                if (ms->top[k] < n_in) big[b++] = ms->top[k];
+                if (top[k] < n_in) big[b++] = top[k];
         }
         ms->nbig = nbig;
         s_nbig = nbig;
