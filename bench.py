@@ -121,11 +121,12 @@ def _run(nc, prm, d, dt, steps, warmup, timing, device):
             "mesh": mesh}
 
 
-def _gravity_method_comparison(nc, d, p_list, reps, device):
+def _gravity_method_comparison(nc, d, p_list, reps, device, falcon_leaf=None):
     """One tree build plus one gravity evaluation by falcON (Alg. 2, default thresholds,
-    FP64) and by the standard tree code (Alg. 1, leaf size 102, N_cb,pre 6, N_cb,post
-    16: the settings of the paper's speed comparison), at each order in p_list; then a
-    collision search (dt = 1e-3) by each on its own tree."""
+    FP64, leaf size falcon_leaf: the main line's FP64 leaf size; the order's default
+    when None) and by the standard tree code (Alg. 1, leaf size 102, N_cb,pre 6,
+    N_cb,post 16: the settings of the paper's speed comparison), at each order in
+    p_list; then a collision search (dt = 1e-3) by each on its own tree."""
     import torch
     n = len(d["x"])
     t = {k: torch.tensor(d[k], device=device) for k in ("x", "y", "z", "m", "vx", "vy", "vz",
@@ -135,7 +136,9 @@ def _gravity_method_comparison(nc, d, p_list, reps, device):
     npairs = torch.zeros(1, dtype=torch.int64, device=device)
     out = {}
     for p in p_list:
-        for name, prm in (("falcon", nc.params_default(p)),
+        fprm = (nc.params_default(p) if falcon_leaf is None
+                else nc.params_default(p, leaf_size=int(falcon_leaf)))
+        for name, prm in (("falcon", fprm),
                           ("standard_tree", nc.params_default(
                               p, leaf_size=102, gravity_method=nc.GRAVITY_STANDARD_TREE,
                               collision_method=nc.COLLISIONS_STANDARD_TREE,
@@ -524,7 +527,8 @@ def main():
 
     methods = None
     if not args.no_method_comparison:
-        methods = _gravity_method_comparison(ncorp, d, sorted({3, args.p}), 5, device)
+        methods = _gravity_method_comparison(ncorp, d, sorted({3, args.p}), 5, device,
+                                             falcon_leaf=prm64.leaf_size)
         print("# gravity methods: " + ", ".join(
             f"{k} {v['ms_tree_and_gravity']:.3f} ms" for k, v in methods.items()),
             file=sys.stderr, flush=True)
