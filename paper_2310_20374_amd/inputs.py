@@ -223,6 +223,20 @@ def clumps(n: int, seed: int = 0, n_clumps: int = 200, scale: float = 0.05,
     return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in out.items()}
 
 
+def coincident(n: int, seed: int = 0, copies: int = 3, stack: int = 40):
+    """Degenerate positions: a cold disk whose every moonlet appears `copies` times at
+    the same place (equal keys, kept in input order by the stable sort), then `stack`
+    moonlets on one point, more than a leaf holds, so the tree ends there in a cell
+    at the depth cap."""
+    base_n = max(1, -(-(n - stack) // copies))
+    base = disk(base_n, seed=seed)
+    rep = {k: np.repeat(v, copies)[:max(n - stack, 0)] for k, v in base.items()}
+    out = {}
+    for k, v in rep.items():
+        out[k] = np.concatenate([v, np.full(n - len(v), base[k][0])])
+    return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in out.items()}
+
+
 def batch_sizes(n_disks: int = 64, seed: int = 0, lo: int = 1000, hi: int = 50000):
     """Per-disk sizes, log-uniform in [lo, hi]."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -36,6 +36,8 @@ GRAV_CASES = {
                                    0.2),
     "clumps5e4_p3_s52_longp2p": (lambda: inputs.clumps(50000, seed=0), 3, 52, (256, 256, 512),
                                  0),
+    # equal positions: zero-distance pairs and a leaf at the depth cap
+    "coincident3k_p4": (lambda: inputs.coincident(3000, seed=5), 4, 16, (64, 8, 64), 0),
 }
 LONG = {"disk2e4_p3_theta02_longm2l": ("m2l_maxlist", 512),
         "clumps5e4_p3_s52_longp2p": ("p2p_maxlist", 64)}

@@ -33,6 +33,8 @@ STD_CASES = {
     "hot6k_p5_no_thresholds": (lambda: inputs.hot_disk(6000, seed=2), 5, 8, (0, 0), 0, 0.5),
     "disk5e3_p2_wide_thresholds": (lambda: inputs.disk(5000, seed=6), 2, 64, (64, 200), 0, 0.3),
     "gas1e4_p3_s1": (lambda: inputs.gas_box(10000, seed=7), 3, 1, (1, 1), 0, 0.5),
+    # equal positions: zero-distance pairs and a leaf at the depth cap
+    "coincident3k_p4": (lambda: inputs.coincident(3000, seed=5), 4, 16, (6, 16), 0, 0.5),
 }
 
 

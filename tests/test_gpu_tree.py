@@ -22,6 +22,8 @@ CASES = {
     "tiny_root_leaf": (lambda: inputs.disk(40, seed=2), 64),
     "single": (lambda: inputs.disk(1, seed=3), 16),
     "ragged_4097": (lambda: inputs.hot_disk(4097, seed=4), 17),
+    # every position three times, 43 moonlets on one point: a leaf at the depth cap
+    "coincident3k_s16": (lambda: inputs.coincident(3000, seed=5), 16),
 }
 
 
