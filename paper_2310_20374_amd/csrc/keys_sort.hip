@@ -323,15 +323,10 @@ k_radix_hist(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ val
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    uint32_t d[kSortItems];
-#pragma unroll
     for (int k = 0; k < kSortItems; k++) {
         const int64_t i = base + k * kSortThreads + threadIdx.x;
-        d[k] = i < n ? sort_digit(keys, vals, dseg, i, shift) : 256u;
+        if (i < n) atomicAdd(&h[sort_digit(keys, vals, dseg, i, shift)], 1u);
     }
-#pragma unroll
-    for (int k = 0; k < kSortItems; k++)
-        if (d[k] < 256u) atomicAdd(&h[d[k]], 1u);
     __syncthreads();
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
