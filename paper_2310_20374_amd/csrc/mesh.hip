@@ -171,16 +171,34 @@ __global__ void k_mesh_clear_state(MeshState *ms) {
     }
 }
 
+// Start of a build: when the last build was dense and completed, its cells are the
+// only non-zero entries of the grid buffer and their indices are still its sorted
+// keys, so clearing those entries leaves the whole buffer zero (O(N) instead of the
+// box).  grid_sparse is only read here; k_mesh_box resets it after this launch.
+__global__ void k_mesh_unset(MeshState *ms, const uint64_t *__restrict__ keys, int2 *grid,
+                             int64_t grid_n) {
+    const bool sparse = ms->grid_sparse != 0;
+    const int64_t m = sparse ? ms->prev_n : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ms->grid_zero = sparse ? 1 : 0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < m;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[q];
+        if (k < (uint64_t)grid_n && (q == 0 || keys[q - 1] != k)) grid[k] = make_int2(0, 0);
+    }
+}
+
 // Clears the cell index of the new mesh.  With the dense grid, also replaces each
 // Morton key by the cell's grid index (empty: dense_empty, above every index), so
 // that the sort needs only the digits of the grid's size.
 __global__ void k_mesh_clear_table(const MeshState *__restrict__ ms, MeshSlot *tab,
-                                   int64_t nslots, int2 *grid, uint64_t *keys, int64_t n,
-                                   uint64_t dense_empty) {
+                                   int64_t nslots, int2 *grid, int64_t grid_n, uint64_t *keys,
+                                   int64_t n, uint64_t dense_empty) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (ms->dense) {
-        const int64_t nc = (int64_t)ms->box_dx * ms->box_dy * ms->box_dz;
+        // unless k_mesh_unset left it zero, the whole buffer (later boxes may be larger
+        // than this one, and the next build clears only this build's cells)
+        const int64_t nc = ms->grid_zero ? 0 : grid_n;
         for (int64_t b = t0; b < nc; b += stride) grid[b] = make_int2(0, 0);
         const int x0 = ms->box_x0, y0 = ms->box_y0, z0 = ms->box_z0;
         const int64_t dx = ms->box_dx, dy = ms->box_dy;
@@ -316,6 +334,7 @@ k_mesh_box(const int32_t *__restrict__ box_part, int nblk, MeshState *ms, int64_
         for (int k = 0; k < 6; k++) v[k] = min(v[k], box_part[6 * (int64_t)b + k]);
     for (int k = 0; k < 6; k++) v[k] = block_min_i(v[k], red);
     if (threadIdx.x == 0) {
+        ms->grid_sparse = 0;                      // set again by a completed dense build
         if (v[0] == INT_MAX) {                    // no moonlet in the mesh
             ms->box_x0 = ms->box_y0 = ms->box_z0 = 0;
             ms->box_dx = ms->box_dy = ms->box_dz = 0;
@@ -376,12 +395,16 @@ __global__ void k_mesh_runs(DevState *st, MeshState *ms, const uint64_t *__restr
 }
 
 // the last moonlet of every cell closes its range
-__global__ void k_mesh_run_ends(const DevState *__restrict__ st, const MeshState *__restrict__ ms,
+__global__ void k_mesh_run_ends(const DevState *__restrict__ st, MeshState *ms,
                                 const uint64_t *__restrict__ keys, int64_t n, MeshSlot *tab,
                                 int64_t mask, int2 *grid, uint64_t dense_empty) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n || (st->status & kSkipMask)) return;
     const bool dense = ms->dense != 0;
+    if (q == 0 && dense) {                         // the grid now holds this build's cells
+        ms->grid_sparse = 1;
+        ms->prev_n = (int32_t)n;
+    }
     const uint64_t k = keys[q];
     if (k == (dense ? dense_empty : kMeshEmpty) || (q + 1 < n && keys[q + 1] == k)) return;
     if (dense) {
@@ -764,6 +787,7 @@ hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double 
     k_mesh_begin<<<1, 64, 0, s>>>(ws.mesh, ws.st, n, prm.mesh_neighbours, prm.mesh_aspect,
                                   prm.mesh_rmax, prm.mesh_gamma,
                                   prm.mesh_min_side / prm.mesh_cells);
+    k_mesh_unset<<<1024, 256, 0, s>>>(ws.mesh, ws.mkeys, ws.mgrid, ws.mgrid_n);
     // the box partials use the counter partials' buffer (free during a build)
     int32_t *box_part = reinterpret_cast<int32_t *>(ws.count_part);
     const int kblk = grid_of(n, 256);
@@ -778,8 +802,8 @@ hipError_t launch_mesh_build(const Workspace &ws, const double *x, const double 
     const uint64_t dense_empty = (1ull << gbits) - 1ull;
     int keep = (gbits + 7) / 8;
     if ((8 - keep) % 2) keep++;
-    k_mesh_clear_table<<<4096, 256, 0, s>>>(ws.mesh, ws.mtab, ws.mtab_n, ws.mgrid, ws.mkeys, n,
-                                            dense_empty);
+    k_mesh_clear_table<<<4096, 256, 0, s>>>(ws.mesh, ws.mtab, ws.mtab_n, ws.mgrid, ws.mgrid_n,
+                                            ws.mkeys, n, dense_empty);
     // eight 8-bit passes (or `keep` of them) leave the result in mkeys / midx
     bool in_b = false;
     hipError_t e = launch_radix_sort(ws.mkeys, ws.midx, ws.mkeys_alt, ws.midx_alt, n, 64, ws.hist,

@@ -137,7 +137,11 @@ struct MeshState {
     // instead of through the hash table
     int32_t box_x0, box_y0, box_z0, box_dx, box_dy, box_dz;
     int32_t dense;
-    int32_t pad[6];
+    // grid_sparse: the last build was dense and completed, so the whole grid buffer is
+    // zero except at the first prev_n sorted keys (its cells); grid_zero: this build
+    // found it so and cleared those cells
+    int32_t grid_sparse, prev_n, grid_zero;
+    int32_t pad[3];
 };
 
 // Work-queue state of a persistent walk; each counter on its own 128-byte line.
