@@ -141,6 +141,8 @@ def lib():
     L.orc_direct_sum.argtypes = [_f64, _f64, _f64, _f64, i64, d, _i64, i64, _f64, _f64, _f64]
     L.orc_pairs_brute.restype = i64
     L.orc_pairs_brute.argtypes = [_f64] * 7 + [i64, d, _i64, i64]
+    L.orc_pairs_grid.restype = i64
+    L.orc_pairs_grid.argtypes = [_f64] * 7 + [i64, d, _i64, i64]
     L.orc_pairs_of.restype = i64
     L.orc_pairs_of.argtypes = [_f64] * 7 + [i64, d, _i64, i64, _i64, i64]
     _lib = L
@@ -385,6 +387,19 @@ def pairs_brute(d: dict, dt: float, cap: int = 1 << 20) -> np.ndarray:
                               float(dt), out, cap)
     if k > cap:
         return pairs_brute(d, dt, cap=int(k))
+    return out[:k]
+
+
+def pairs_grid(d: dict, dt: float, cap: int = 1 << 20) -> np.ndarray:
+    """Every colliding pair (i < j) of Eqs. (1)-(2), candidates taken from a uniform
+    grid of cells wider than twice the largest reach R + dt |v| (the same set as
+    pairs_brute, in O(N) for spread-out inputs)."""
+    n = len(d["x"])
+    out = np.zeros((cap, 2), np.int64)
+    k = lib().orc_pairs_grid(*(_c(d[f]) for f in ("x", "y", "z", "vx", "vy", "vz", "R")), n,
+                             float(dt), out, cap)
+    if k > cap:
+        return pairs_grid(d, dt, cap=int(k))
     return out[:k]
 
 

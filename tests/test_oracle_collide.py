@@ -73,6 +73,53 @@ def test_tree_pairs_equal_brute_force(orc, case):
     assert c.ntests() < n * (n - 1) // 2
 
 
+@pytest.mark.parametrize("case", ["gas", "disk_big_dt", "hot", "clumps", "clumps_1e5",
+                                  "coincident", "static"])
+def test_grid_pairs_equal_brute_force(orc, case):
+    """The grid-filtered scan (the exact pair oracle for inputs too large for the
+    all-pairs scan) returns exactly the all-pairs set of Eqs. (1)-(2): a pair that
+    touches within dt started at most R_i + R_j + dt(|v_i| + |v_j|) apart, so it sits
+    in the same or adjacent grid cells."""
+    if case == "gas":
+        d, dt = inputs.gas_box(2000, seed=3), 0.01
+    elif case == "disk_big_dt":
+        d, dt = inputs.disk(20000, seed=4), 1.0
+    elif case == "hot":
+        d, dt = inputs.hot_disk(20000, seed=5), 3.0
+    elif case == "clumps":
+        d, dt = inputs.clumps(20000, seed=6, n_clumps=10), 0.01
+    elif case == "clumps_1e5":
+        d, dt = inputs.clumps(100000, seed=7, n_clumps=50), 1e-3
+    elif case == "coincident":
+        d, dt = inputs.coincident(3000, seed=8), 0.3
+    else:
+        # nothing moves: only pairs already overlapping, and Eq. (2) rejects those
+        d, dt = inputs.gas_box(2000, seed=9, radius=0.02), 0.1
+        for k in ("vx", "vy", "vz"):
+            d[k] = np.zeros_like(d[k])
+    want = orc.pairs_brute(d, dt)
+    got = orc.pairs_grid(d, dt)
+    assert np.array_equal(got, want)
+    if case in ("gas", "disk_big_dt", "hot", "clumps", "clumps_1e5"):
+        assert len(want) > 20
+    if case == "static":
+        assert len(want) == 0
+
+
+def test_grid_pairs_catch_reach_at_the_cell_edge(orc):
+    """Two moonlets heading at each other from just under the largest possible
+    separation R1 + R2 + dt (|v1| + |v2|) collide exactly at dt; the grid scan must
+    still list them (the cells are sized from the largest reach)."""
+    R, u, dt = 0.01, 0.5, 0.2
+    sep = 2 * R + 2 * u * dt * (1 - 1e-9)
+    for shift in (0.0, 0.37, -1.91):
+        d = {"x": np.array([shift, shift + sep, 5.0]), "y": np.zeros(3), "z": np.zeros(3),
+             "vx": np.array([u, -u, 0.0]), "vy": np.zeros(3), "vz": np.zeros(3),
+             "R": np.array([R, R, R])}
+        assert orc.pairs_brute(d, dt).tolist() == [[0, 1]]
+        assert orc.pairs_grid(d, dt).tolist() == [[0, 1]]
+
+
 def test_collision_climb_bounds(orc):
     """r_max bounds every moonlet's distance from the centre and r_crit - r_max
     bounds R + dt |v| of every moonlet (Eqs. 8-9 by induction)."""
