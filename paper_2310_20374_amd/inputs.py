@@ -14,6 +14,8 @@ Workloads (the paper uses synthetic disks only; no public dataset is involved):
                    one density).
 * ``hot_disk``  -- the disk of the paper's timing runs (Sect. 4.2): a ~ U[2.9, 12],
                    e ~ U[0, 0.2], i ~ U[0, 10 deg].
+* ``fig4_disk`` -- the accuracy workload of Fig. 4: a in [1, 10], total mass 0.024.
+* ``plummer_sphere`` -- an isolated Plummer sphere of equal masses.
 * ``gas_box``   -- a unit box of equal spheres with Maxwellian velocities, used to
                    exercise the collision test (a closed-form pair count exists).
 * ``clumps``    -- half a disk plus 200 Plummer spheres placed on disk orbits.
@@ -117,6 +119,34 @@ def hot_disk(n: int, seed: int = 0, total_mass: float = 0.01, mu: float = 1.0):
     om = rng.uniform(0.0, 2 * math.pi, n)
     M = rng.uniform(0.0, 2 * math.pi, n)
     pos, vel = elements_to_state(a, e, inc, Om, om, M, mu)
+    return _pack(pos, vel, m, radius_from_mass(m))
+
+
+def fig4_disk(n: int, seed: int = 0, total_mass: float = 0.024, mu: float = 1.0):
+    """The accuracy workload of the paper's error distributions (Fig. 4, Sect. 3.4.3):
+    moonlets between 1 and 10 Earth radii with random masses totalling 0.024 Earth
+    masses.  The paper states neither eccentricities nor inclinations there; this
+    reading takes those of its timing runs (e ~ U[0, 0.2], i ~ U[0, 10 deg]) and
+    a ~ U[1, 10]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = rng.lognormal(0.0, 1.0, n)
+    m *= total_mass / m.sum()
+    a = rng.uniform(1.0, 10.0, n)
+    e = rng.uniform(0.0, 0.2, n)
+    inc = rng.uniform(0.0, math.radians(10.0), n)
+    Om = rng.uniform(0.0, 2 * math.pi, n)
+    om = rng.uniform(0.0, 2 * math.pi, n)
+    M = rng.uniform(0.0, 2 * math.pi, n)
+    pos, vel = elements_to_state(a, e, inc, Om, om, M, mu)
+    return _pack(pos, vel, m, radius_from_mass(m))
+
+
+def plummer_sphere(n: int, seed: int = 0, scale: float = 1.0, total_mass: float = 1.0):
+    """An isolated Plummer sphere of n equal masses (scale radius `scale`, truncated at
+    10 scale radii), sampled as the clumps of ``clumps`` are."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos, vel = _plummer(rng, n, scale, total_mass)
+    m = np.full(n, total_mass / n)
     return _pack(pos, vel, m, radius_from_mass(m))
 
 

@@ -174,6 +174,8 @@ def test_shift_is_exact_reexpansion(orc):
 
 # --------------------------------------------------------------- reading R3
 def test_theta_of_mass(orc):
+    """Self-consistency of the bisection only (the relation is reading R3); what pins
+    theta(M) to the paper is the Fig. 4 accuracy test below."""
     tmin = 0.5
     assert orc.theta_of_mass(1.0, 1.0, tmin) == tmin
     prev = tmin
@@ -269,36 +271,89 @@ def test_uniform_sphere_field(orc):
     assert _errs(a[tg], ad)[0] < 1e-2
 
 
-def test_error_falls_with_p_and_matches_paper_scale(orc):
-    """Sect. 4.2 / Fig. 4: with theta_min = 0.5 the acceleration error is ~1e-5 at
-    p = 3 and ~1e-7 at p = 6.  The magnitudes quoted there are reproduced for the
-    total acceleration a moonlet feels (mutual + central mass); the mutual part
-    alone has a larger relative error, since a thin disk's mutual field is a
-    small residual of near-cancelling contributions."""
-    gold = json.load(open(GOLDEN))["accuracy_theta_min_0.5"]
-    N = 20000
-    d = inputs.disk(N, seed=0)
-    tg = inputs.sample_targets(N, 1500)
+def _fig4_errors(orc, p, theta_mode, N=100_000, n_targets=2048):
+    """Median of the paper's scalar relative error | |a| - |a_ref| | / |a_ref| on the
+    Fig. 4 workload, for the mutual acceleration alone and with the central mass
+    (the two families of curves of Fig. 4), at the leaf size and thresholds of the
+    paper's runs at that order (Sect. 4.2)."""
+    d = inputs.fig4_disk(N, seed=0)
+    tg = inputs.sample_targets(N, n_targets)
     ad = orc.direct_sum(d["x"], d["y"], d["z"], d["m"], targets=tg)
     ac = orc.central_accel(d["x"][tg], d["y"][tg], d["z"][tg])
-    res = {}
-    for p, s, thr in ((3, 17, (64, 8, 64)), (6, 52, (256, 256, 512))):
-        for mode in (0, 1):
-            a, _, _ = orc.tree_accel(d, p=p, s=s, ncs=thr[0], ncc_pre=thr[1], ncc_post=thr[2],
-                                     theta_mode=mode)
-            at = a[tg] + ac
-            es = np.abs(np.linalg.norm(at, axis=1) - np.linalg.norm(ad + ac, axis=1)) \
-                / np.linalg.norm(ad + ac, axis=1)
-            res[(p, mode)] = (np.median(es), _errs(a[tg], ad)[0])
-    # the error drops by well over an order of magnitude from p = 3 to p = 6
-    for mode in (0, 1):
-        assert res[(6, mode)][0] < 0.1 * res[(3, mode)][0]
-        assert res[(6, mode)][1] < 0.1 * res[(3, mode)][1]
-    # within a factor 10 of the printed orders of magnitude (constant theta runs
-    # closest; the mass-dependent angle trades accuracy for speed)
-    assert res[(3, 1)][0] < 10 * gold["p3"] and res[(3, 0)][0] < 10 * gold["p3"]
-    assert res[(6, 1)][0] < 10 * gold["p6"]
-    assert res[(6, 0)][0] < 30 * gold["p6"]
+    s, thr = (17, (64, 8, 64)) if p <= 3 else (52, (256, 256, 512))
+    a, _, _ = orc.tree_accel(d, p=p, s=s, ncs=thr[0], ncc_pre=thr[1], ncc_post=thr[2],
+                             theta_mode=theta_mode)
+    a = a[tg]
+
+    def scalar(x, ref):
+        return np.abs(np.linalg.norm(x, axis=1) - np.linalg.norm(ref, axis=1)) \
+            / np.linalg.norm(ref, axis=1)
+    return float(np.median(scalar(a, ad))), float(np.median(scalar(a + ac, ad + ac)))
+
+
+@pytest.mark.slow
+def test_fig4_accuracy_matches_paper(orc):
+    """Sect. 4.2 with Fig. 4: at theta_min = 0.5 the relative acceleration error is of
+    the order of 1e-5 at p = 3 and 1e-7 at p = 6, on 4e5 moonlets between 1 and 10
+    Earth radii of total mass 0.024 (here 1e5 of them: the medians differ from 4e5 by
+    about 10 %).  The printed magnitudes are those of the acceleration with the
+    central mass (the mutual field alone of a disk is a residual of near-cancelling
+    terms, and its relative error is ~10^2 larger).  Constant theta lands within 3x
+    of both printed values; the mass-dependent angle of reading R3 (which the paper
+    says it uses) within 3x at p = 3 and about 5x at p = 6.  A wrong mass exponent in
+    theta(M) (-1/2 instead of -1/3 doubles the opening of small cells) drives the
+    p = 6 error above 1e-6 and fails here; so do a dropped expansion order or a
+    wrong-signed term (errors of 1e-4 and up)."""
+    gold = json.load(open(GOLDEN))["accuracy_theta_min_0.5"]
+    res = {(p, mode): _fig4_errors(orc, p, mode) for p in (3, 6) for mode in (0, 1)}
+    for (p, mode), (mut, tot) in res.items():
+        print(f"p={p} theta_mode={mode}: median mutual {mut:.2e}, with central mass {tot:.2e}")
+    # constant theta: within a factor 3 of the printed values at both orders
+    assert gold["p3"] / 3 < res[(3, 1)][1] < 3 * gold["p3"]
+    assert gold["p6"] / 3 < res[(6, 1)][1] < 3 * gold["p6"]
+    # mass-dependent theta (R3): 3x at p = 3; at p = 6 within 6x
+    assert gold["p3"] / 3 < res[(3, 0)][1] < 3 * gold["p3"]
+    assert gold["p6"] / 3 < res[(6, 0)][1] < 6 * gold["p6"]
+    # the mass-dependent angle opens cells more widely, never less
+    for p in (3, 6):
+        assert res[(p, 0)][1] >= res[(p, 1)][1]
+    # two orders of magnitude from p = 3 to p = 6 (printed: 1e-5 -> 1e-7)
+    assert res[(3, 1)][1] / res[(6, 1)][1] > 30
+    assert res[(3, 0)][1] / res[(6, 0)][1] > 20
+    # the mutual-only error is far above the printed values (the other family)
+    for key, (mut, tot) in res.items():
+        assert mut > 20 * tot
+
+
+def test_plummer_sphere_field(orc):
+    """A Plummer sphere of mass M and scale b has the radial field
+    -G M(<r)/r^2 with M(<r) = M r^3/(r^2 + b^2)^(3/2) (truncated at 10 b here, so the
+    masses are those of the sphere inside 10 b).  The oracle tree, averaged over
+    shells (an unsoftened field scatters by discreteness noise moonlet by moonlet),
+    follows it from the core to the halo, and the direct sum does too."""
+    N = 20000
+    d = inputs.plummer_sphere(N, seed=3)
+    P = np.stack([d["x"], d["y"], d["z"]], 1)
+    r = np.linalg.norm(P, axis=1)
+    u = P / r[:, None]
+    inside_10b = 1000.0 / 101.0 ** 1.5            # M_P(<10 b) / M of the untruncated sphere
+    field = -(r ** 3 / (r * r + 1.0) ** 1.5) / inside_10b / (r * r)
+    a, _, _ = orc.tree_accel(d, p=4, s=16, ncs=64, ncc_pre=8, ncc_post=64)
+    tg = np.arange(0, N, 7)
+    ad = orc.direct_sum(d["x"], d["y"], d["z"], d["m"], targets=tg)
+    ar = (a * u).sum(1)
+    ard = (ad * u[tg]).sum(1)
+    # the core's field follows the random realisation of its ~2000 moonlets (seeds
+    # scatter by ~5 % there), the outer shells are set by many more
+    for lo, hi, tol in ((0.2, 0.5, 0.12), (0.5, 1.0, 0.03), (1.0, 2.0, 0.02), (2.0, 4.0, 0.02)):
+        sel = (r > lo) & (r < hi)
+        assert abs(np.mean(ar[sel] / field[sel]) - 1.0) < tol, (lo, hi)
+        seld = (r[tg] > lo) & (r[tg] < hi)
+        assert abs(np.mean(ard[seld] / field[tg][seld]) - 1.0) < tol + 0.01, (lo, hi)
+    # the tangential field averages to zero
+    at = a - ar[:, None] * u
+    assert np.abs(at.mean(0)).max() < 0.02 * np.abs(field).mean()
+    assert _errs(a[tg], ad)[0] < 1e-2
 
 
 def test_rmax_bounds_and_corner_clamp(orc):
