@@ -270,6 +270,33 @@ int ncorp_step_batched(ncorp_ctx *ctx, const int64_t *disk_offsets, int n_disks,
                        int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, void *workspace,
                        int64_t ws_bytes, void *stream);
 
+/* ---- allocation-free form --------------------------------------------------
+ * For callers that cannot allocate device memory or bring a workspace: code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * ncorp_step_noalloc is ncorp_step (same arguments, minus the workspace; same
+ * results, pair format and errors) with the workspace taken from a fixed array
+ * inside the library, NCORP_STATIC_WORKSPACE_BYTES on every GPU it runs on, set up
+ * by the first call on that GPU (the device current at the call) and held until
+ * the process ends.  Nothing is allocated or freed by the call.
+ *  - Size limit: n must satisfy ncorp_workspace_bytes(params, n, 1) <=
+ *    NCORP_STATIC_WORKSPACE_BYTES (with the default capacities up to 19 001 moonlets
+ *    at p = 6 and 20 032 at p = 4, leaf size 52, and 7 088 at p = 3, leaf size 17;
+ *    a larger leaf size allows more); a larger n returns
+ *    NCORP_E_INVALID at once, before anything touches the GPU.  The part of the
+ *    array the layout does not use holds the colliding pairs of the step.
+ *  - Sharing: all calls on one GPU use that GPU's one array, which keeps the last
+ *    call's contents.  Each call starts from cleared device state and uses nothing an
+ *    earlier call left, so calls of different contexts may follow each other in
+ *    stream order; calls that overlap in time on one GPU (different streams or
+ *    threads without ordering between them) race and give undefined results.
+ *  - Afterwards ncorp_get_status, ncorp_tree_info and ncorp_export_host on this
+ *    context read the array, which is valid only until the next call on that GPU. */
+#define NCORP_STATIC_WORKSPACE_BYTES (128LL * 1024 * 1024)
+int ncorp_step_noalloc(ncorp_ctx *ctx, double *x, double *y, double *z, double *vx,
+                       double *vy, double *vz, const double *m, const double *R, int64_t n,
+                       double dt, int n_steps, int64_t *pairs, int64_t cap,
+                       int64_t *n_pairs_dev, void *stream);
+
 /* Waits for the context's last stream, then reports the device status word:
  * NCORP_OK, NCORP_E_CAPACITY (required_capacity, if not NULL, receives the size
  * that would have sufficed for the list that overflowed), NCORP_E_INVALID (bad

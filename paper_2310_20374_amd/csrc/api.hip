@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "ncorp_internal.h"
@@ -764,6 +766,70 @@ extern "C" int ncorp_step_batched(ncorp_ctx *c, const int64_t *disk_offsets, int
     if (r != NCORP_OK) return r;
     return step_impl(c, disk_offsets, n_disks, x, y, z, vx, vy, vz, m, R, n, dt, n_steps, pairs,
                      cap, n_pairs_dev, workspace, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------- allocation-free form
+// The workspace of ncorp_step_noalloc: a fixed array in the library's code object.
+// Every GPU the library runs on holds its own copy, from the first use on that GPU
+// until the process ends.  In host code `scratch` names a host-side stand-in, never
+// the device memory: its device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[NCORP_STATIC_WORKSPACE_BYTES];
+
+static constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+static int scratch_of_current_device(ncorp_ctx *c, void **out) {
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(c, NCORP_E_UNSUPPORTED, "allocation-free form: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255u) != 0)
+            return fail(c, NCORP_E_HIP, "allocation-free form: scratch address not usable");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NCORP_OK;
+}
+
+extern "C" int ncorp_step_noalloc(ncorp_ctx *c, double *x, double *y, double *z, double *vx,
+                                  double *vy, double *vz, const double *m, const double *R,
+                                  int64_t n, double dt, int n_steps, int64_t *pairs, int64_t cap,
+                                  int64_t *n_pairs_dev, void *stream) {
+    if (!c) return NCORP_E_INVALID;
+    // argument and size checks need no device: reject before anything touches the GPU
+    if (!x || !y || !z || !vx || !vy || !vz || !m || !R || !n_pairs_dev || (cap > 0 && !pairs))
+        return fail(c, NCORP_E_INVALID, "array pointer is NULL");
+    if (n < 1 || n > INT32_MAX - 1) return fail(c, NCORP_E_INVALID, "n must be in 1..2^31-2");
+    if (n_steps < 1) return fail(c, NCORP_E_INVALID, "n_steps must be >= 1");
+    if (!(dt > 0.0)) return fail(c, NCORP_E_INVALID, "dt must be > 0");
+    if (cap < 0) return fail(c, NCORP_E_INVALID, "cap must be >= 0");
+    Workspace probe;
+    const int64_t need = layout_workspace(probe, c->prm, n, 1);
+    if (need > (int64_t)NCORP_STATIC_WORKSPACE_BYTES) {
+        std::snprintf(c->err, sizeof(c->err),
+                      "allocation-free form: n=%lld needs %lld workspace bytes, the fixed "
+                      "array holds %lld",
+                      (long long)n, (long long)need, (long long)NCORP_STATIC_WORKSPACE_BYTES);
+        return NCORP_E_INVALID;
+    }
+    void *ws = nullptr;
+    int r = scratch_of_current_device(c, &ws);
+    if (r != NCORP_OK) return r;
+    // Another call (of any context) may have used this GPU's array since this context
+    // last did: forget every binding so the call starts from cleared device state
+    // (status word, walk queue, mesh state), as on a new workspace.
+    c->ws = Workspace{};
+    c->mesh_init = false;
+    c->have_mesh = false;
+    c->have_tree = false;
+    return step_impl(c, nullptr, 1, x, y, z, vx, vy, vz, m, R, n, dt, n_steps, pairs, cap,
+                     n_pairs_dev, ws, (int64_t)NCORP_STATIC_WORKSPACE_BYTES, stream);
 }
 
 static int sync_state(ncorp_ctx *c, DevState &h) {

@@ -34,8 +34,9 @@ EXPORTED_SYMBOLS = ("ncorp_params_default", "ncorp_create", "ncorp_destroy",
                     "ncorp_collide", "ncorp_step", "ncorp_get_status", "ncorp_last_error",
                     "ncorp_tree_info", "ncorp_export_host", "ncorp_set_timing",
                     "ncorp_phase_times", "ncorp_build_tree_batched", "ncorp_step_batched",
-                    "ncorp_build_mesh", "ncorp_mesh_state")
+                    "ncorp_build_mesh", "ncorp_mesh_state", "ncorp_step_noalloc")
 MAX_DISKS = 65536
+STATIC_WORKSPACE_BYTES = 128 * 1024 * 1024     # NCORP_STATIC_WORKSPACE_BYTES
 
 
 class Params(C.Structure):
@@ -103,6 +104,9 @@ def lib():
     L.ncorp_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, d, i32, vp, i64, vp, vp,
                              i64, vp]
     L.ncorp_step.restype = i32
+    L.ncorp_step_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, d, i32, vp, i64,
+                                     vp, vp]
+    L.ncorp_step_noalloc.restype = i32
     L.ncorp_build_tree_batched.argtypes = [vp, vp, i32, vp, vp, vp, i64, vp, i64, vp]
     L.ncorp_build_tree_batched.restype = i32
     L.ncorp_step_batched.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i64, d, i32,
@@ -158,12 +162,17 @@ class Context:
 
     def __init__(self, prm: Params, n_max: int, pair_capacity: int = 1 << 16,
                  device: str = "cuda:0"):
+        """n_max = 0: no workspace (only ncorp_step_noalloc can then be called)."""
         import torch
         self.prm = prm
         self.h = C.c_void_p()
         r = lib().ncorp_create(C.byref(prm), C.byref(self.h))
         if r != OK:
             raise NcorpError(r, "ncorp_create rejected the parameters")
+        self.device = device
+        if n_max == 0:
+            self._raw, self.ws, self.ws_bytes = None, None, 0
+            return
         self.ws_bytes = workspace_bytes(prm, n_max, pair_capacity)
         raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         off = (-raw.data_ptr()) % 256
@@ -223,6 +232,16 @@ class Context:
                                      int(n_steps), _ptr(pairs), cap, _ptr(n_pairs_dev),
                                      _ptr(self.ws), self.ws_bytes, _stream(stream)),
                     "ncorp_step")
+
+    def step_noalloc(self, x, y, z, vx, vy, vz, m, R, dt, n_steps, pairs, n_pairs_dev,
+                     stream=None):
+        """ncorp_step on the library's fixed per-GPU workspace (no workspace argument)."""
+        cap = pairs.shape[0] if pairs is not None else 0
+        self._check(lib().ncorp_step_noalloc(self.h, _ptr(x), _ptr(y), _ptr(z), _ptr(vx),
+                                             _ptr(vy), _ptr(vz), _ptr(m), _ptr(R), x.numel(),
+                                             float(dt), int(n_steps), _ptr(pairs), cap,
+                                             _ptr(n_pairs_dev), _stream(stream)),
+                    "ncorp_step_noalloc")
 
     def build_tree_batched(self, offsets, x, y, z, stream=None):
         """offsets: int64 device tensor of n_disks + 1 entries."""

@@ -107,6 +107,30 @@ def test_batched_argument_checks(nc):
     L.ncorp_destroy(h)
 
 
+def test_noalloc_rejects_sizes_beyond_its_array(nc):
+    """The allocation-free step refuses an n whose workspace would not fit its fixed
+    per-GPU array, and bad arguments, on the host before any GPU work."""
+    L = nc.lib()
+    h = C.c_void_p()
+    prm = nc.params_default(6)
+    assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.OK
+    dummy = C.c_void_p(256)          # never dereferenced: the checks come first
+    limit = nc.STATIC_WORKSPACE_BYTES
+    n_small = 2000
+    assert nc.workspace_bytes(prm, n_small, 1) <= limit
+    n_big = 10 ** 6
+    assert nc.workspace_bytes(prm, n_big, 1) > limit
+    args = [dummy] * 8
+    assert L.ncorp_step_noalloc(h, *args, n_big, 1e-3, 1, dummy, 16, dummy, None) == nc.E_INVALID
+    assert b"allocation-free" in L.ncorp_last_error(h)
+    assert L.ncorp_step_noalloc(h, *args, 0, 1e-3, 1, dummy, 16, dummy, None) == nc.E_INVALID
+    assert L.ncorp_step_noalloc(h, *args, n_small, 0.0, 1, dummy, 16, dummy, None) == nc.E_INVALID
+    assert L.ncorp_step_noalloc(h, *args, n_small, 1e-3, 0, dummy, 16, dummy, None) == nc.E_INVALID
+    assert L.ncorp_step_noalloc(h, None, *args[1:], n_small, 1e-3, 1, dummy, 16, dummy,
+                                None) == nc.E_INVALID
+    L.ncorp_destroy(h)
+
+
 def test_autotune_cache_key():
     from paper_2310_20374_amd import autotune
     assert autotune.cache_key(4, 1, 788736) == "p4-prec1-n2^19"
