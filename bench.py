@@ -214,10 +214,17 @@ def _errors(orc, d, acc, samples):
         e = np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
         return float(np.sqrt(np.mean(e * e))), float(e.max()), float(np.median(e))
 
+    def scalar_median(a, ref):
+        # the paper's measure (Fig. 4): |a - a_ref| / a_ref of the scalar accelerations
+        na, nr = np.linalg.norm(a, axis=1), np.linalg.norm(ref, axis=1)
+        return float(np.median(np.abs(na - nr) / nr))
+
     tot = stats(acc[tg] + ac, ad + ac)
     mut = stats(acc[tg], ad)
     return {"rms_total": tot[0], "max_total": tot[1], "median_total": tot[2],
             "rms_mutual": mut[0], "max_mutual": mut[1], "median_mutual": mut[2],
+            "scalar_median_total": scalar_median(acc[tg] + ac, ad + ac),
+            "scalar_median_mutual": scalar_median(acc[tg], ad),
             "samples": int(len(tg))}
 
 
@@ -371,6 +378,66 @@ def _run_batched(nc, args, device):
     }
 
 
+def _run_clustered(nc, args, device, leaf_size, cmode):
+    """The clustered stress workload: N = 4e6 moonlets, half a cold disk and half in
+    200 Plummer clumps (scale 0.05, clump weights dM ~ M^-2 dM), FP32-bulk, p = 6,
+    theta_min = 0.5, the main line's FP32-bulk leaf size, collisions resolved as in the
+    main line.  Reports the step rate, the pairs per step, the load balance of the last
+    gravity evaluation (the gravity walk's per-wave busy clock cycles, max over mean; the
+    direct sums' source moonlets per target moonlet, max over mean), and the complete pair
+    set of one search on the initial state against the oracle's exact grid scan."""
+    import numpy as np
+    import torch
+    from paper_2310_20374_amd import inputs
+    n = args.clustered_n
+    d = inputs.clumps(n, seed=0)
+    prm = nc.params_default(6, theta_min=args.theta, precision=nc.FP32_BULK,
+                            collision_mode=cmode, collision_f=2.0, leaf_size=int(leaf_size))
+    steps = args.clustered_steps
+    r = _run(nc, prm, d, args.dt, steps, 1, True, device)
+    info = r["info"]
+    ph = r["phases"]
+    out = {"workload": "clustered: half a cold disk, half in 200 Plummer clumps "
+                       "(scale 0.05), FP32-bulk",
+           "n": n, "p": 6, "theta_min": args.theta, "leaf_size": int(leaf_size),
+           "steps": steps, "ms_per_step": r["wall_s"] * 1e3 / steps,
+           "particle_steps_per_s": n * steps / r["wall_s"],
+           "pairs_per_step": r["pairs"] / steps,
+           "phases_ms_per_step": {k: round(v[0] / steps, 4) for k, v in ph.items()},
+           "tree": {k: info[k] for k in ("ncells", "nleaves", "maxlevel", "m2l", "p2p",
+                                         "visited", "p2p_inter", "m2l_maxlist",
+                                         "p2p_maxlist")},
+           "load_balance": {
+               "walk_busy_cycles_max": info["walk_busy_max"],
+               "walk_busy_cycles_mean": info["walk_busy_mean"],
+               "walk_busy_max_over_mean": info["walk_busy_max"] / max(info["walk_busy_mean"], 1),
+               "direct_sum_sources_max": info["p2p_src_max"],
+               "direct_sum_sources_mean": info["p2p_inter"] / n,
+               "direct_sum_sources_max_over_mean": info["p2p_src_max"] * n / max(
+                   info["p2p_inter"], 1),
+               "m2l_list_max": info["m2l_maxlist"],
+               "m2l_list_mean": info["m2l_dir"] / max(info["ncells"], 1)}}
+    # the complete pair set of one search on the seeded state, against the oracle
+    t = {k: torch.tensor(v, device=device) for k, v in d.items()}
+    cap = 1 << 20
+    ctx = nc.Context(prm, n, pair_capacity=cap, device=device)
+    pairs = torch.zeros((cap, 2), dtype=torch.int64, device=device)
+    npairs = torch.zeros(1, dtype=torch.int64, device=device)
+    a = [torch.empty(n, dtype=torch.float64, device=device) for _ in range(3)]
+    ctx.build_tree(t["x"], t["y"], t["z"])
+    ctx.gravity(t["m"], *a)
+    ctx.collide(t["vx"], t["vy"], t["vz"], t["R"], args.dt, pairs, npairs)
+    torch.cuda.synchronize()
+    ctx.check_status()
+    k = int(npairs.item())
+    got = pairs[:k].cpu().numpy()
+    del ctx, t, a, pairs
+    out["_d"] = d
+    out["_acc"] = r["acc"]
+    out["_pairs"] = got
+    return out
+
+
 def _cpu_baseline(orc, n_sample, p, theta, s, thr, dt):
     """The oracle as it stands (single-threaded FP64 tree, recursive walk, full
     3^n tensors) for one step of a sub-disk drawn from the same distribution."""
@@ -423,6 +490,10 @@ def main():
                     help="extra opening angles timed and error-checked beside --theta "
                          "(both precision forms, 10 steps each); '' for none")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-clustered", action="store_true",
+                    help="skip the clustered stress workload (4e6 moonlets, disk + clumps)")
+    ap.add_argument("--clustered-n", type=int, default=4_000_000)
+    ap.add_argument("--clustered-steps", type=int, default=5)
     ap.add_argument("--no-mesh", action="store_true",
                     help="skip the mesh-module step loop (gravity and collisions on the mesh)")
     ap.add_argument("--no-method-comparison", action="store_true",
@@ -512,6 +583,13 @@ def main():
                                             for k, v in row.items() if k != "theta_min"),
               file=sys.stderr, flush=True)
 
+    clustered = None
+    if not args.no_clustered:
+        clustered = _run_clustered(ncorp, args, device, prm32.leaf_size, cmode)
+        print(f"# clustered: {clustered['ms_per_step']:.3f} ms/step, "
+              f"{clustered['pairs_per_step']:.0f} pairs/step, "
+              f"balance {clustered['load_balance']}", file=sys.stderr, flush=True)
+
     batched = None
     if not args.no_batched:
         batched = _run_batched(ncorp, args, device)
@@ -548,6 +626,17 @@ def main():
                 acc = row[name].pop("acc")
                 if not args.no_errors:
                     row[name]["errors"] = _errors(orc, d, acc, args.samples)
+    if clustered is not None:
+        dcl = clustered.pop("_d")
+        acc_cl = clustered.pop("_acc")
+        got = clustered.pop("_pairs")
+        if not args.no_errors:
+            clustered["errors"] = _errors(orc, dcl, acc_cl, args.samples)
+            want = orc.pairs_grid(dcl, args.dt)
+            clustered["pair_check"] = {"dt": args.dt, "pairs": int(len(got)),
+                                       "oracle_pairs": int(len(want)),
+                                       "bit_exact": bool(np.array_equal(got, want))}
+        del dcl, acc_cl, got
     if mesh is not None and not args.no_errors:
         mesh["errors"] = _errors(orc, d, mesh_acc, args.samples)
     if methods is not None:
@@ -630,6 +719,7 @@ def main():
         "tree": info,
         "collision_pairs_in_timed_steps": r32["pairs"],
         "batched": batched,
+        "clustered": clustered,
         "gravity_methods": methods,
         "mesh_module": mesh,
         "leaf_size_autotune": tuned,

@@ -313,6 +313,7 @@ enum {
     NCORP_INFO_M2L, NCORP_INFO_P2P, NCORP_INFO_VISITED, NCORP_INFO_COL_CAND,
     NCORP_INFO_COL_TESTS, NCORP_INFO_M2L_DIR, NCORP_INFO_P2P_INTER, NCORP_INFO_M2L_MAXLIST,
     NCORP_INFO_P2P_MAXLIST, NCORP_INFO_NROOTS, NCORP_INFO_LONG_M2L, NCORP_INFO_LONG_P2P,
+    NCORP_INFO_WALK_BUSY_MAX, NCORP_INFO_WALK_BUSY_MEAN, NCORP_INFO_P2P_SRC_MAX,
     NCORP_INFO_COUNT
 };
 /* Waits for the stream and fills info[NCORP_INFO_COUNT] with sizes of the last
@@ -326,7 +327,10 @@ enum {
  * the number of roots (level-0 cells: 1, or the non-empty disks of a batched
  * call), and the numbers of cells and leaves whose M2L or direct-sum lists were too
  * long for one LDS batch of their consumer (sorted by a pre-pass; the direct sums of
- * such leaves are split over several waves). */
+ * such leaves are split over several waves); and, again only while phase timing is on,
+ * the load balance of the last gravity evaluation: the largest and the mean number of
+ * shader clock cycles (clock64) the gravity walk's persistent waves were busy, and the
+ * most source moonlets of one leaf's direct sums (the mean is p2p_inter / n). */
 int ncorp_tree_info(ncorp_ctx *ctx, int64_t *info);
 
 enum {

@@ -566,6 +566,7 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
     }
     {
         PhaseTimer t(c, NCORP_PHASE_GWALK, s);
+        ws.timing = c->timing;
         HIPCHK(c, launch_walk(ws, 0, c->prm.ncs, c->prm.ncc_pre, c->prm.ncc_post, s));
     }
     {
@@ -885,6 +886,9 @@ extern "C" int ncorp_tree_info(ncorp_ctx *c, int64_t *info) {
     info[NCORP_INFO_P2P_INTER] = h.p2p_inter;
     info[NCORP_INFO_M2L_MAXLIST] = h.m2l_maxlist;
     info[NCORP_INFO_P2P_MAXLIST] = h.p2p_maxlist;
+    info[NCORP_INFO_WALK_BUSY_MAX] = h.walk_busy_max;
+    info[NCORP_INFO_WALK_BUSY_MEAN] = h.walk_busy_sum / kWalkWaves;
+    info[NCORP_INFO_P2P_SRC_MAX] = h.p2p_src_max;
     return NCORP_OK;
 }
 

@@ -106,6 +106,11 @@ struct DevState {
     int64_t npairs;            // colliding pairs found (may exceed capacity)
     int64_t pair_cursor;       // pairs already written by earlier steps of ncorp_step
     int64_t p2p_inter;         // directed moonlet pairs (i != j) of the direct sums
+    // load balance of the last gravity evaluation (timing runs only): busy cycles of
+    // the gravity walk's waves (sum and max over the persistent waves) and the most
+    // source moonlets any leaf's direct sums take
+    int64_t walk_busy_sum, walk_busy_max;
+    int64_t p2p_src_max;
 };
 
 // ---------------------------------------------------------------- mesh module
@@ -288,6 +293,7 @@ struct Workspace {
     unsigned long long *count_part = nullptr;         // per-block counter partials
     int64_t count_part_n = 0;
     DevState *st = nullptr;
+    bool timing = false;                              // phase timing on: load-balance counters
     bool clear_queue = false;                         // new buffer: clear before next walk
     bool clear_mesh = false;                          // new buffer: clear the mesh state
 };

@@ -84,6 +84,7 @@ __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, int64_
     if (mode == 0) {
         st->nm2l = 0; st->np2p = 0; st->m2l_slots = 0; st->p2p_slots = 0; st->visited = 0;
         st->nlong_m2l = 0; st->nlong_p2p = 0;
+        st->walk_busy_sum = 0; st->walk_busy_max = 0;
     } else {
         st->ncand = 0; st->cand_slots = 0;
     }
@@ -106,6 +107,7 @@ struct WalkArgs {
     int32_t *m2l_cnt, *m2l_seg, *p2p_cnt, *p2p_seg;
     int32_t *long_m2l, *long_p2p;        // targets whose list outgrew the LDS sort
     int m2l_stride, p2p_stride;
+    int timing;                          // record the waves' busy cycles
 };
 
 // Stores v at slot k of target t's list (slot order is arbitrary); k came from
@@ -326,6 +328,7 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
     WalkQueue *wq = A.wq;
     const int ncells = A.st->ncells;
     const uint32_t tag = A.epoch & 0xffffu;
+    const long long t_start = (MODE == 0 && A.timing) ? clock64() : 0;
     uint64_t spins = 0;
     int64_t visited = 0;
     bool finished = false;
@@ -442,6 +445,11 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
     }
     if (lane == 0 && visited)
         atomicAdd((unsigned long long *)&A.st->visited, (unsigned long long)visited);
+    if (MODE == 0 && A.timing && lane == 0) {
+        const unsigned long long busy = (unsigned long long)(clock64() - t_start);
+        atomicAdd((unsigned long long *)&A.st->walk_busy_sum, busy);
+        atomicMax((unsigned long long *)&A.st->walk_busy_max, busy);
+    }
 }
 
 hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post,
@@ -461,6 +469,7 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
         A.m2l_cnt = ws.m2l_cnt; A.m2l_seg = ws.m2l_seg; A.m2l_stride = ws.m2l_stride;
         A.p2p_cnt = ws.p2p_cnt; A.p2p_seg = ws.p2p_seg; A.p2p_stride = ws.p2p_stride;
         A.long_m2l = ws.long_m2l; A.long_p2p = ws.long_p2p;
+        A.timing = ws.timing ? 1 : 0;
         k_walk<0><<<kWalkGridGravity, kWalkBlock, 0, s>>>(A);
     } else {
         A.cell = ws.wc;
@@ -513,6 +522,7 @@ __global__ void k_count_inter(DevState *st, const int32_t *__restrict__ ent_cell
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     unsigned long long tot = 0;
+    long long smax = 0;
     int lp = 0, lm = 0;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K || e < st->ncells;
          e += gridDim.x * blockDim.x) {
@@ -524,17 +534,21 @@ __global__ void k_count_inter(DevState *st, const int32_t *__restrict__ ent_cell
         long long srcs = 0;
         for (int q = 0; q < p2p_cnt[e]; q++) srcs += c_count[seg[q]];
         tot += (unsigned long long)(nt * srcs - nt);
+        smax = srcs > smax ? srcs : smax;
     }
     for (int o = kWave / 2; o > 0; o >>= 1) {
         tot += __shfl_xor(tot, o);
         const int a = __shfl_xor(lp, o), b = __shfl_xor(lm, o);
         lp = a > lp ? a : lp;
         lm = b > lm ? b : lm;
+        const long long c = __shfl_xor(smax, o);
+        smax = c > smax ? c : smax;
     }
     if (threadIdx.x % kWave == 0) {
         if (tot) atomicAdd((unsigned long long *)&st->p2p_inter, tot);
         if (lp) atomicMax(&st->p2p_maxlist, lp);
         if (lm) atomicMax(&st->m2l_maxlist, lm);
+        if (smax) atomicMax((unsigned long long *)&st->p2p_src_max, (unsigned long long)smax);
     }
 }
 
@@ -543,6 +557,7 @@ __global__ void k_zero_inter(DevState *st) {
         st->p2p_inter = 0;
         st->m2l_maxlist = 0;
         st->p2p_maxlist = 0;
+        st->p2p_src_max = 0;
     }
 }
 
