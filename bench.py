@@ -263,8 +263,9 @@ def _phase_rooflines(phases, info, n, p, precision_fp32):
                 "20 flop per directed moonlet pair"),
         "l2p": ("hbm", (72.0 * n + 8.0 * nl * leaves) / hbm,
                 "read positions and direct sums, leaf C; write accelerations"),
-        "collide": ("hbm+valu", (124.0 * n) / hbm + 25.0 * info["col_tests"] / (PEAK_FP64_TFLOPS * 1e12),
-                    "gather velocities and radii, read the climb's inputs; 25 flop per pair test"),
+        "collide": ("hbm+valu", (124.0 * n) / hbm + 10.0 * info["col_tests"] / (PEAK_FP64_TFLOPS * 1e12),
+                    "gather velocities and radii, read positions; 10 flop per moonlet pair "
+                    "examined (distance against the reaches; Eqs. 1-2 only within reach)"),
         "integrate": ("hbm", 84.0 * n / hbm, "a kick or a drift: about 84 B per moonlet"),
     }
     out, roof_sum, meas_sum = {}, 0.0, 0.0

@@ -284,6 +284,8 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.vzs = (double *)take(8 * n);
     ws.rads = (double *)take(8 * n);
     ws.pcol = (double4 *)take(32 * n);
+    ws.cbox = (double4 *)take(2 * 32 * cell_cap);
+    ws.vcol = (double4 *)take(32 * n);
     ws.acc = (double *)take(3 * 8 * n);
     ws.acc_s = (double *)take(3 * 8 * n);
     ws.ent_start = (int32_t *)take(4 * n);
@@ -628,13 +630,18 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
         HIPCHK(c, launch_standard_tree_collide(ws, n, c->prm.ncb_pre, c->prm.ncb_post, dt, s));
     } else {
         HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
-        HIPCHK(c, launch_collision_climb(ws, n, dt, s));
-        if (c->grav_lists)
+        if (c->grav_lists) {
+            // candidates from the gravity walk's lists of this tree, culled with the
+            // moonlets' bounding boxes (no collision climb needed)
+            HIPCHK(c, launch_leaf_boxes(ws, n, dt, s));
             HIPCHK(c, launch_candidates_from_lists(ws, s));
-        else
+            HIPCHK(c, launch_collide_pairs(ws, n, dt, true, s));
+        } else {
+            HIPCHK(c, launch_collision_climb(ws, n, dt, s));
             HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col,
                                   c->prm.ncc_post_col, s));
-        HIPCHK(c, launch_collide_pairs(ws, n, dt, s));
+            HIPCHK(c, launch_collide_pairs(ws, n, dt, false, s));
+        }
     }
     if (state && c->prm.collision_mode == NCORP_COLLISIONS_RESOLVE)
         HIPCHK(c, launch_resolve(ws, state[0], state[1], state[2], state[3], state[4], state[5],

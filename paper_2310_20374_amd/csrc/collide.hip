@@ -9,6 +9,22 @@
 
 namespace ncorp {
 
+// Value of lane `src` (the same for every lane of the wave) on all lanes: scalar
+// reads, where a general shuffle would go through LDS permutes.
+__device__ __forceinline__ int bcast_i(int v, int src) {
+    return __builtin_amdgcn_readlane(v, src);
+}
+__device__ __forceinline__ double bcast_d(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double4 bcast4(double4 v, int src) {
+    return make_double4(bcast_d(v.x, src), bcast_d(v.y, src), bcast_d(v.z, src),
+                        bcast_d(v.w, src));
+}
+
 __device__ __forceinline__ int wave_excl_sum_c(int v, int lane, int &total) {
     int x = v;
 #pragma unroll
@@ -24,18 +40,54 @@ __device__ __forceinline__ int wave_excl_sum_c(int v, int lane, int &total) {
 // A's moonlets sit on the lanes, and when A has fewer than 64 the lanes split
 // B's moonlets into groups.  In a self pair only j > i is tested.
 struct PState {
-    double x, y, z, vx, vy, vz, R;
+    double x, y, z, vx, vy, vz, R, reach;    // reach = R + dt |v|
     uint32_t id;
 };
 
-// Moonlets of cell C (first f, count n) that can reach the sphere (centre s, radius
-// rc) of the other cell within the step: |r_a - s| <= R_a + dt |v_a| + rc.  Every
-// colliding pair passes (r_crit of a cell bounds R + dt|v| plus the distance of
-// each of its moonlets from its centre); the relative margin 1e-9 dwarfs the
-// rounding of either side, so no pair the exact test accepts is dropped.  The
-// survivors are compacted into out[] in moonlet order; returns their number, or
-// -1 if more than `limit` survive.
-__device__ __forceinline__ int cull_cell(int f, int n, double4 sph,
+// A pair that touches at a time t in [0, dt] starts at most R_a + R_b + dt |v_a - v_b|
+// <= reach_a + reach_b apart: the cheap distance check rejects nearly every pair before
+// Eqs. (1)-(2) are evaluated (relative margin 1e-9, far above rounding).
+__device__ __forceinline__ bool within_reach(const PState &a, const PState &b) {
+    const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    const double rs = a.reach + b.reach;
+    return dx * dx + dy * dy + dz * dz <= rs * rs * (1.0 + 1e-9);
+}
+
+__device__ __forceinline__ void test_pair(const PState &p, const PState &o, double dt,
+                                          int64_t *out, int64_t cap, DevState *st) {
+    if (within_reach(p, o) &&
+        pair_test(p.x, p.y, p.z, p.vx, p.vy, p.vz, p.R, o.x, o.y, o.z, o.vx, o.vy, o.vz, o.R, dt))
+        record(out, cap, (unsigned long long *)&st->npairs, p.id, o.id);
+}
+
+// Can moonlet p = (x, y, z, R + dt |v|) meet a moonlet of the other cell within the
+// step?  A pair that touches at a time t in [0, dt] starts at most R_a + R_b +
+// dt (|v_a| + |v_b|) apart.  Spheres (BOXES = false, from the collision climb): the
+// other cell's moonlets lie within r_crit - (R + dt |v|) of its centre, so
+// |r_a - s| <= R_a + dt |v_a| + r_crit (a = centre, radius).  Boxes (BOXES = true):
+// the other leaf's moonlets lie in the box [a.xyz, b.xyz], each with a reach of at
+// most a.w, so the distance from r_a to the box is at most R_a + dt |v_a| + a.w.
+// The relative margin 1e-9 dwarfs the rounding of either side, so no pair the exact
+// test accepts is dropped.
+template <bool BOXES>
+__device__ __forceinline__ bool can_reach(const double4 &p, const double4 &a, const double4 &b) {
+    if (BOXES) {
+        const double gx = fmax(0.0, fmax(a.x - p.x, p.x - b.x));
+        const double gy = fmax(0.0, fmax(a.y - p.y, p.y - b.y));
+        const double gz = fmax(0.0, fmax(a.z - p.z, p.z - b.z));
+        const double rs = p.w + a.w;
+        return gx * gx + gy * gy + gz * gz <= rs * rs * (1.0 + 1e-9);
+    }
+    const double reach = p.w + a.w;
+    const double dx = p.x - a.x, dy = p.y - a.y, dz = p.z - a.z;
+    return dx * dx + dy * dy + dz * dz <= reach * reach * (1.0 + 1e-9);
+}
+
+// Moonlets of cell C (first f, count n) that can reach the other cell within the
+// step (can_reach).  The survivors are compacted into out[] in moonlet order;
+// returns their number, or -1 if more than `limit` survive.
+template <bool BOXES>
+__device__ __forceinline__ int cull_cell(int f, int n, double4 oa, double4 ob,
                                          const double4 *__restrict__ pcol,
                                          const double *__restrict__ vxs,
                                          const double *__restrict__ vys,
@@ -51,12 +103,10 @@ __device__ __forceinline__ int cull_cell(int f, int n, double4 sph,
         int k = 0;
         if (c0 + lane < n) {
             k = f + c0 + lane;
-            // position and R + dt |v|, as the collision climb stored them
+            // position and R + dt |v|, as the climb or the box pass stored them
             const double4 p = pcol[k];
-            ps.x = p.x; ps.y = p.y; ps.z = p.z;
-            const double reach = p.w + sph.w;
-            const double dx = ps.x - sph.x, dy = ps.y - sph.y, dz = ps.z - sph.z;
-            keep = dx * dx + dy * dy + dz * dz <= reach * reach * (1.0 + 1e-9);
+            ps.x = p.x; ps.y = p.y; ps.z = p.z; ps.reach = p.w;
+            keep = can_reach<BOXES>(p, oa, ob);
         }
         if (keep) {
             ps.vx = vxs[k]; ps.vy = vys[k]; ps.vz = vzs[k]; ps.R = rads[k];
@@ -72,20 +122,64 @@ __device__ __forceinline__ int cull_cell(int f, int n, double4 sph,
     return kept;
 }
 
+// All pairs of one cell of n <= 64 moonlets staged in sb: (i, i + d mod n) for
+// d = 1 .. n/2 (for even n, d = n/2 only from i < n/2) is every unordered pair once.
+// Lane groups of S >= n lanes take different d, so the rounds stay full instead of
+// shrinking as i grows.
+__device__ __forceinline__ void self_pairs_staged(int n, const PState *sb,
+                                                  const double4 *spos, double dt,
+                                                  int64_t *out, int64_t cap, DevState *st,
+                                                  unsigned long long &tests) {
+    const int lane = threadIdx.x;
+    int S = 1;
+    while (S < n) S <<= 1;
+    const int G = kWave / S, i = lane % S, grp = lane / S, dmax = n / 2;
+    if (i >= n) return;
+    const PState me = sb[i];
+    for (int d0 = 1; d0 <= dmax; d0 += G) {
+        const int d = d0 + grp;
+        if (d > dmax || (2 * d == n && i >= d)) continue;
+        int j = i + d;
+        if (j >= n) j -= n;
+        tests++;
+        const double4 o = spos[j];
+        const double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
+        const double rs = me.reach + o.w;
+        if (dx * dx + dy * dy + dz * dz <= rs * rs * (1.0 + 1e-9)) test_pair(me, sb[j], dt, out, cap, st);
+    }
+}
+
 // Every moonlet pair of the candidate cell pair (A, B) (i < j when A == B): lanes
 // take moonlets of A, B's moonlets are staged in LDS 64 at a time and split over
 // lane groups when A holds fewer than 64.
 __device__ __forceinline__ void test_cell_pair(
-    int2 pr, PState *sb, const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
+    int2 pr, PState *sb, double4 *spos, const int32_t *__restrict__ c_first,
+    const int32_t *__restrict__ c_count,
     const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
     const double *__restrict__ vxs, const double *__restrict__ vys,
     const double *__restrict__ vzs, const double *__restrict__ rads,
-    const uint32_t *__restrict__ perm, double dt, int64_t *out, int64_t cap, DevState *st,
-    unsigned long long &tests) {
+    const uint32_t *__restrict__ perm, const double4 *__restrict__ pcol, double dt, int64_t *out,
+    int64_t cap, DevState *st, unsigned long long &tests) {
     const int lane = threadIdx.x;
     const int fa = c_first[pr.x], na = c_count[pr.x];
     const int fb = c_first[pr.y], nb = c_count[pr.y];
     const bool self = pr.x == pr.y;
+    if (self && na <= kWave) {
+        __syncthreads();
+        if (lane < na) {
+            const int b = fa + lane;
+            PState ps;
+            ps.x = xs[b]; ps.y = ys[b]; ps.z = zs[b];
+            ps.vx = vxs[b]; ps.vy = vys[b]; ps.vz = vzs[b]; ps.R = rads[b];
+            ps.reach = pcol[b].w;
+            ps.id = perm[b];
+            sb[lane] = ps;
+            spos[lane] = make_double4(ps.x, ps.y, ps.z, ps.reach);
+        }
+        __syncthreads();
+        self_pairs_staged(na, sb, spos, dt, out, cap, st, tests);
+        return;
+    }
     for (int a0 = 0; a0 < na; a0 += 64) {
         const int nac = na - a0 < 64 ? na - a0 : 64;
         int S = 1;
@@ -94,9 +188,11 @@ __device__ __forceinline__ void test_cell_pair(
         const bool act = tl < nac;
         const int ia = a0 + (act ? tl : 0);
         const int a = fa + ia;
-        const double x1 = xs[a], y1 = ys[a], z1 = zs[a], vx1 = vxs[a], vy1 = vys[a],
-                     vz1 = vzs[a], R1 = rads[a];
-        const uint32_t id1 = perm[a];
+        PState me;
+        me.x = xs[a]; me.y = ys[a]; me.z = zs[a];
+        me.vx = vxs[a]; me.vy = vys[a]; me.vz = vzs[a]; me.R = rads[a];
+        me.reach = pcol[a].w;
+        me.id = perm[a];
         for (int b0 = self ? a0 : 0; b0 < nb; b0 += 64) {
             const int nbc = nb - b0 < 64 ? nb - b0 : 64;
             __syncthreads();
@@ -105,6 +201,7 @@ __device__ __forceinline__ void test_cell_pair(
                 PState ps;
                 ps.x = xs[b]; ps.y = ys[b]; ps.z = zs[b];
                 ps.vx = vxs[b]; ps.vy = vys[b]; ps.vz = vzs[b]; ps.R = rads[b];
+                ps.reach = pcol[b].w;
                 ps.id = perm[b];
                 sb[lane] = ps;
             }
@@ -114,11 +211,8 @@ __device__ __forceinline__ void test_cell_pair(
             // first j >= jlo with j = grp (mod G)
             int j = jlo + ((grp - jlo % G) % G + G) % G;
             for (; j < nbc; j += G) {
-                const PState &o = sb[j];
                 tests++;
-                if (pair_test(x1, y1, z1, vx1, vy1, vz1, R1, o.x, o.y, o.z, o.vx, o.vy, o.vz,
-                              o.R, dt))
-                    record(out, cap, (unsigned long long *)&st->npairs, id1, o.id);
+                test_pair(me, sb[j], dt, out, cap, st);
             }
         }
     }
@@ -128,16 +222,23 @@ __device__ __forceinline__ void test_cell_pair(
 // sides of all of them are loaded in one go
 constexpr int kCandRound = 8;
 
+// BOXES: the candidates are leaf pairs with bounding boxes (cbox: low corner and
+// largest reach, high corner, per cell); otherwise cell pairs with the collision
+// climb's spheres (ccell).
+template <bool BOXES>
 __global__ void __launch_bounds__(64)
 k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
           const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
-          const double4 *__restrict__ ccell, const double *__restrict__ xs,
+          const double4 *__restrict__ ccell, const double4 *__restrict__ cbox,
+          const double *__restrict__ xs,
           const double *__restrict__ ys, const double *__restrict__ zs,
           const double *__restrict__ vxs, const double *__restrict__ vys,
           const double *__restrict__ vzs, const double *__restrict__ rads,
-          const uint32_t *__restrict__ perm, const double4 *__restrict__ pcol, double dt,
+          const uint32_t *__restrict__ perm, const double4 *__restrict__ pcol,
+          const double4 *__restrict__ vcol, const int32_t *__restrict__ ent_cell, double dt,
           int64_t *out, int64_t cap, unsigned long long *tests_part) {
     __shared__ PState sp[kWave];    // survivors of both sides (or a staged tile of B)
+    __shared__ double4 spos[kWave];
     if (st->status & kSkipMask) {
         if (threadIdx.x == 0) tests_part[blockIdx.x] = 0;
         return;
@@ -157,75 +258,146 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
         const bool side = lane < 2 * kCandRound && qa >= 0;
         const int mine = lane < kCandRound ? qa : qb, other = lane < kCandRound ? qb : qa;
         int cf = 0, cn = 0;
-        double4 sph = make_double4(0.0, 0.0, 0.0, 0.0);
+        double4 sph = make_double4(0.0, 0.0, 0.0, 0.0), shi = sph;
         if (side) {
             cf = c_first[mine];
             cn = c_count[mine];
-            sph = ccell[other];
+            if (BOXES) {
+                sph = cbox[2 * (int64_t)other];
+                shi = cbox[2 * (int64_t)other + 1];
+            } else {
+                sph = ccell[other];
+            }
         }
         uint64_t live = __ballot(lane < kCandRound && cq.x >= 0);   // gaps are skipped
         while (live) {
             const int l = __ffsll((unsigned long long)live) - 1;
             live &= live - 1;
-            const int2 pr = make_int2(__shfl(cq.x, l), __shfl(cq.y, l));
+            const int2 pr = make_int2(bcast_i(cq.x, l), bcast_i(cq.y, l));
             if (pr.x != pr.y) {
                 // distinct cells: keep only moonlets that can reach the other cell
                 const int lb = kCandRound + l;
-                const int fa = __shfl(cf, l), na = __shfl(cn, l);
-                const int fb = __shfl(cf, lb), nb = __shfl(cn, lb);
+                const int fa = bcast_i(cf, l), na = bcast_i(cn, l);
+                const int fb = bcast_i(cf, lb), nb = bcast_i(cn, lb);
                 int ka = -1, kb = -1;
                 __syncthreads();
-                if (na + nb <= kWave) {
+                if (BOXES && na + nb <= 2 * kWave) {
+                    // both sides at once, two moonlets per lane (item t = lane, lane + 64
+                    // is A[t] for t < na, else B[t - na]), whole records loaded together:
+                    // one dependent round trip per candidate
+                    const double4 oA = bcast4(sph, l), hA = bcast4(shi, l);
+                    const double4 oB = bcast4(sph, lb), hB = bcast4(shi, lb);
+                    PState ps[2];
+                    bool keep[2], isA[2];
+#pragma unroll
+                    for (int u = 0; u < 2; u++) {
+                        const int t = lane + u * kWave;
+                        isA[u] = t < na;
+                        keep[u] = false;
+                        if (t < na + nb) {
+                            const int k = isA[u] ? fa + t : fb + (t - na);
+                            const double4 p = pcol[k], v = vcol[k];
+                            ps[u].x = p.x; ps[u].y = p.y; ps[u].z = p.z; ps[u].reach = p.w;
+                            ps[u].vx = v.x; ps[u].vy = v.y; ps[u].vz = v.z; ps[u].R = v.w;
+                            ps[u].id = perm[k];
+                            // an A moonlet is culled against B's box and the other way round
+                            keep[u] = isA[u] ? can_reach<true>(p, oA, hA)
+                                             : can_reach<true>(p, oB, hB);
+                        }
+                    }
+                    const uint64_t mA0 = __ballot(keep[0] && isA[0]);
+                    const uint64_t mA1 = __ballot(keep[1] && isA[1]);
+                    const uint64_t mB0 = __ballot(keep[0] && !isA[0]);
+                    const uint64_t mB1 = __ballot(keep[1] && !isA[1]);
+                    const int a0 = __popcll(mA0), b0 = __popcll(mB0);
+                    ka = a0 + __popcll(mA1);
+                    kb = b0 + __popcll(mB1);
+                    if (ka + kb <= kWave) {
+                        if (keep[0])
+                            sp[isA[0] ? __popcll(mA0 & lt) : ka + __popcll(mB0 & lt)] = ps[0];
+                        if (keep[1])
+                            sp[isA[1] ? a0 + __popcll(mA1 & lt) : ka + b0 + __popcll(mB1 & lt)] =
+                                ps[1];
+                    } else {
+                        ka = kb = -1;
+                    }
+                } else if (na + nb <= kWave) {
                     // both sides in one round: lanes [0, na) hold A, [na, na + nb) hold B
                     const bool inA = lane < na, inB = !inA && lane < na + nb;
                     const int sl = inA ? l : lb;
                     const double4 s4 = make_double4(__shfl(sph.x, sl), __shfl(sph.y, sl),
                                                     __shfl(sph.z, sl), __shfl(sph.w, sl));
+                    double4 h4 = s4;
+                    if (BOXES)
+                        h4 = make_double4(__shfl(shi.x, sl), __shfl(shi.y, sl),
+                                          __shfl(shi.z, sl), 0.0);
                     bool keep = false;
                     int k = 0;
                     double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
                     if (inA || inB) {
                         k = inA ? fa + lane : fb + (lane - na);
                         p = pcol[k];
-                        const double reach = p.w + s4.w;
-                        const double dx = p.x - s4.x, dy = p.y - s4.y, dz = p.z - s4.z;
-                        keep = dx * dx + dy * dy + dz * dz <= reach * reach * (1.0 + 1e-9);
+                        keep = can_reach<BOXES>(p, s4, h4);
                     }
                     const uint64_t mA = __ballot(keep && inA), mB = __ballot(keep && inB);
                     ka = __popcll(mA);
                     kb = __popcll(mB);
                     if (keep) {
                         PState ps;
-                        ps.x = p.x; ps.y = p.y; ps.z = p.z;
+                        ps.x = p.x; ps.y = p.y; ps.z = p.z; ps.reach = p.w;
                         ps.vx = vxs[k]; ps.vy = vys[k]; ps.vz = vzs[k]; ps.R = rads[k];
                         ps.id = perm[k];
                         sp[inA ? __popcll(mA & lt) : ka + __popcll(mB & lt)] = ps;
                     }
                 } else {
-                    const double4 sA = make_double4(__shfl(sph.x, l), __shfl(sph.y, l),
-                                                    __shfl(sph.z, l), __shfl(sph.w, l));
-                    const double4 sB = make_double4(__shfl(sph.x, lb), __shfl(sph.y, lb),
-                                                    __shfl(sph.z, lb), __shfl(sph.w, lb));
-                    ka = cull_cell(fa, na, sA, pcol, vxs, vys, vzs, rads, perm, sp, kWave);
+                    const double4 sA = bcast4(sph, l), sB = bcast4(sph, lb);
+                    const double4 hA = bcast4(shi, l), hB = bcast4(shi, lb);
+                    ka = cull_cell<BOXES>(fa, na, sA, hA, pcol, vxs, vys, vzs, rads, perm, sp,
+                                          kWave);
                     kb = ka < 0 ? -1
-                                : cull_cell(fb, nb, sB, pcol, vxs, vys, vzs, rads, perm, sp + ka,
-                                            kWave - ka);
+                                : cull_cell<BOXES>(fb, nb, sB, hB, pcol, vxs, vys, vzs, rads,
+                                                   perm, sp + ka, kWave - ka);
                 }
                 __syncthreads();
                 if (ka >= 0 && kb >= 0) {
                     const int tot = ka * kb;
                     for (int t = lane; t < tot; t += kWave) {
-                        const PState &p = sp[t / kb], &o = sp[ka + t % kb];
                         tests++;
-                        if (pair_test(p.x, p.y, p.z, p.vx, p.vy, p.vz, p.R, o.x, o.y, o.z, o.vx,
-                                      o.vy, o.vz, o.R, dt))
-                            record(out, cap, (unsigned long long *)&st->npairs, p.id, o.id);
+                        test_pair(sp[t / kb], sp[ka + t % kb], dt, out, cap, st);
                     }
                     continue;
                 }
             }
-            test_cell_pair(pr, sp, c_first, c_count, xs, ys, zs, vxs, vys, vzs, rads, perm, dt,
-                           out, cap, st, tests);
+            test_cell_pair(pr, sp, spos, c_first, c_count, xs, ys, zs, vxs, vys, vzs, rads, perm, pcol,
+                           dt, out, cap, st, tests);
+        }
+    }
+    if (BOXES) {
+        // then every leaf with itself (the candidates hold distinct leaves only); blocks
+        // that finish their candidates early start here, so both kinds of work overlap
+        const int K = st->nleaves;
+        for (int e = blockIdx.x; e < K; e += gridDim.x) {
+            const int c = ent_cell[e];
+            const int n = c_count[c];
+            if (n < 2) continue;
+            if (n > kWave) {
+                test_cell_pair(make_int2(c, c), sp, spos, c_first, c_count, xs, ys, zs, vxs, vys,
+                               vzs, rads, perm, pcol, dt, out, cap, st, tests);
+                continue;
+            }
+            __syncthreads();
+            if (lane < n) {
+                const int k = c_first[c] + lane;
+                const double4 p = pcol[k], v = vcol[k];
+                PState ps;
+                ps.x = p.x; ps.y = p.y; ps.z = p.z; ps.reach = p.w;
+                ps.vx = v.x; ps.vy = v.y; ps.vz = v.z; ps.R = v.w;
+                ps.id = perm[k];
+                sp[lane] = ps;
+                spos[lane] = p;
+            }
+            __syncthreads();
+            self_pairs_staged(n, sp, spos, dt, out, cap, st, tests);
         }
     }
     // per-block partials, summed by k_sum_u64: one atomic per wave on a single
@@ -323,53 +495,84 @@ __global__ void k_pairs_done(DevState *st, int64_t *n_pairs_dev, int64_t cap, in
     }
     if (triple) *cursor = base + n;
 }
+// ---------------------------------------------------------------- candidates from lists
+// Collision candidates from the gravity walk's lists of the same tree (well-separated
+// cell pairs, direct-sum cell pairs, direct-sum self cells).  Those lists cover every
+// moonlet pair exactly once, so the leaf pairs below their interactions, minus those
+// that provably cannot collide, are candidates covering every colliding pair once:
+// the pair set is the collision walk's.  A pair that touches within the step starts
+// at most R_a + R_b + dt (|v_a| + |v_b|) apart, so two cells can hold a colliding pair
+// only if their bounding boxes, each grown by its largest R + dt |v|, overlap.  A leaf's
+// box is the tight box of its moonlets (k_leaf_boxes); an interaction with an internal
+// cell is first tested on the gravity climb's spheres (cells_may_meet).  The pairs
+// inside each leaf are searched apart from the candidates (by k_collide, after them).
+struct CBox {
+    double lx, ly, lz, hx, hy, hz, r;
+};
 
-// ---------------------------------------------------------------- candidates
-// Collision candidates from the gravity walk of the same tree.  That walk splits
-// the set of all moonlet pairs into its interactions exactly once each (well-
-// separated cell pairs, direct-sum cell pairs, direct-sum self cells).  A moonlet
-// pair of an interaction (A, B) can collide only if the collision spheres of the
-// two leaves holding them overlap (Eqs. 8-9 bound every moonlet's reach by its
-// leaf's r_crit), and, for a well-separated pair, only if the spheres of A and B
-// themselves overlap.  So the leaf pairs of all interactions whose spheres overlap
-// (and every leaf with two moonlets or more, with itself) are candidates covering
-// every colliding pair exactly once: the pair set is the collision walk's.  The
-// spheres are compared with a relative margin of 1e-9, far above rounding.
-__device__ __forceinline__ bool spheres_meet(const double4 &a, const double4 &b) {
-    const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-    const double rs = (a.w + b.w) * (1.0 + 1e-9);
-    return dx * dx + dy * dy + dz * dz < rs * rs;
+__device__ __forceinline__ bool boxes_meet(const CBox &a, const CBox &b) {
+    const double gx = fmax(0.0, fmax(b.lx - a.hx, a.lx - b.hx));
+    const double gy = fmax(0.0, fmax(b.ly - a.hy, a.ly - b.hy));
+    const double gz = fmax(0.0, fmax(b.lz - a.hz, a.lz - b.hz));
+    const double rs = (a.r + b.r) * (1.0 + 1e-9);
+    return gx * gx + gy * gy + gz * gz <= rs * rs;
+}
+
+__device__ __forceinline__ CBox leaf_box(const double4 *__restrict__ cbox, int c) {
+    const double4 lo = cbox[2 * (int64_t)c], hi = cbox[2 * (int64_t)c + 1];
+    return CBox{lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, lo.w};
+}
+
+struct BoxArgs {
+    const double4 *cbox;
+    const double4 *gcell;         // gravity climb: centre of mass (x, y, z)
+    const double *c_rmax;         // gravity climb: r_max (bounds every moonlet's distance)
+};
+
+// May cells a and b hold a colliding pair?  Their gravity climb spheres, grown by the
+// largest reach of all moonlets, must overlap: every moonlet of a cell lies within
+// r_max of its centre of mass (Eq. 11 and the corner clamp), so the pair's moonlets
+// are at least |s_a - s_b| - r_max,a - r_max,b apart.  (The walk's well-separated
+// pairs are far apart on that scale and drop here; the leaf pairs below the others
+// are then tested on their boxes.)
+__device__ __forceinline__ bool cells_may_meet(const BoxArgs &B, const DevState *st, int a,
+                                               int b) {
+    const double4 sa = B.gcell[a], sb = B.gcell[b];
+    const double r = __longlong_as_double((long long)st->reach_max);
+    const double dx = sa.x - sb.x, dy = sa.y - sb.y, dz = sa.z - sb.z;
+    const double rs = (B.c_rmax[a] + B.c_rmax[b] + 2.0 * r) * (1.0 + 1e-9);
+    return dx * dx + dy * dy + dz * dz <= rs * rs;
 }
 
 // Counts (out == nullptr) or writes the candidate leaf pairs of one interaction.
-__device__ __forceinline__ int leaf_candidates(int2 pr, bool separated,
-                                               const double4 *__restrict__ ccell,
+__device__ __forceinline__ int leaf_candidates(int2 pr, const BoxArgs &B, const DevState *st,
                                                const int32_t *__restrict__ c_entry,
                                                const int32_t *__restrict__ c_nent,
                                                const int32_t *__restrict__ c_count,
                                                const int32_t *__restrict__ ent_cell, int2 *out,
                                                int64_t pos, int64_t cap) {
     if (pr.x < 0) return 0;
-    if (separated && !spheres_meet(ccell[pr.x], ccell[pr.y])) return 0;
     const bool self = pr.x == pr.y;
+    if (!self && !cells_may_meet(B, st, pr.x, pr.y)) return 0;
     const int ea = c_entry[pr.x], na = c_nent[pr.x];
     const int eb = c_entry[pr.y], nb = c_nent[pr.y];
     int k = 0;
     for (int i = 0; i < na; i++) {
         const int la = ent_cell[ea + i];
-        const double4 sa = ccell[la];
+        const CBox sa = leaf_box(B.cbox, la);
         // four leaves of B at a time: their loads are independent of each other
         for (int j0 = self ? i : 0; j0 < nb; j0 += 4) {
             int lb[4];
-            double4 sb[4];
+            CBox sb[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) lb[u] = j0 + u < nb ? ent_cell[eb + j0 + u] : la;
 #pragma unroll
-            for (int u = 0; u < 4; u++) sb[u] = ccell[lb[u]];
+            for (int u = 0; u < 4; u++) sb[u] = leaf_box(B.cbox, lb[u]);
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 if (j0 + u >= nb) continue;
-                const bool take = la == lb[u] ? c_count[la] > 1 : spheres_meet(sa, sb[u]);
+                // a leaf with itself is searched by k_collide after the candidates
+                const bool take = la != lb[u] && boxes_meet(sa, sb[u]);
                 if (!take) continue;
                 if (out && pos + k < cap) out[pos + k] = make_int2(la, lb[u]);
                 k++;
@@ -377,6 +580,88 @@ __device__ __forceinline__ int leaf_candidates(int2 pr, bool separated,
         }
     }
     return k;
+}
+
+// One wave per leaf: every moonlet's (x, y, z, R + dt |v|) record for the culling, the
+// tight box of the leaf's moonlets with their largest R + dt |v|, and the largest of
+// all moonlets (for the cubes of internal cells).
+__global__ void __launch_bounds__(kWave)
+k_leaf_boxes(DevState *st, const double *__restrict__ xs, const double *__restrict__ ys,
+             const double *__restrict__ zs, const double *__restrict__ vxs,
+             const double *__restrict__ vys, const double *__restrict__ vzs,
+             const double *__restrict__ rads, double dt, const int32_t *__restrict__ ent_cell,
+             const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
+             double4 *__restrict__ cbox, double4 *__restrict__ pcol,
+             double4 *__restrict__ vcol, unsigned long long *__restrict__ part) {
+    if (st->status & kSkipMask) {
+        if (threadIdx.x == 0) part[blockIdx.x] = 0ull;
+        return;
+    }
+    const int K = st->nleaves;
+    const int lane = threadIdx.x;
+    double wmax = 0.0;
+    for (int e = blockIdx.x; e < K; e += gridDim.x) {
+        const int c = ent_cell[e];
+        const int f = c_first[c], cnt = c_count[c];
+        double lx = INFINITY, ly = INFINITY, lz = INFINITY;
+        double hx = -INFINITY, hy = -INFINITY, hz = -INFINITY, ex = 0.0;
+        for (int c0 = lane; c0 < cnt; c0 += kWave) {
+            const int k = f + c0;
+            const double x = xs[k], y = ys[k], z = zs[k];
+            const double v = sqrt(vxs[k] * vxs[k] + vys[k] * vys[k] + vzs[k] * vzs[k]);
+            const double ee = (rads[k] + dt * v) - 0.0;
+            pcol[k] = make_double4(x, y, z, ee);
+            vcol[k] = make_double4(vxs[k], vys[k], vzs[k], rads[k]);
+            lx = fmin(lx, x); ly = fmin(ly, y); lz = fmin(lz, z);
+            hx = fmax(hx, x); hy = fmax(hy, y); hz = fmax(hz, z);
+            ex = fmax(ex, ee);
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            lx = fmin(lx, __shfl_xor(lx, o)); ly = fmin(ly, __shfl_xor(ly, o));
+            lz = fmin(lz, __shfl_xor(lz, o));
+            hx = fmax(hx, __shfl_xor(hx, o)); hy = fmax(hy, __shfl_xor(hy, o));
+            hz = fmax(hz, __shfl_xor(hz, o));
+            ex = fmax(ex, __shfl_xor(ex, o));
+        }
+        if (lane == 0) {
+            cbox[2 * (int64_t)c] = make_double4(lx, ly, lz, ex);
+            cbox[2 * (int64_t)c + 1] = make_double4(hx, hy, hz, 0.0);
+        }
+        wmax = fmax(wmax, ex);
+    }
+    // per-block partial maxima (reaches are >= 0, so their bit patterns order like the
+    // values); one atomic per block on a single word would serialise the grid
+    if (lane == 0) part[blockIdx.x] = (unsigned long long)__double_as_longlong(wmax);
+}
+
+// st->reach_max = the largest of the n partials
+__global__ void __launch_bounds__(1024)
+k_max_u64(const unsigned long long *__restrict__ part, int64_t n, DevState *st) {
+    __shared__ unsigned long long red[1024 / kWave];
+    unsigned long long v = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) v = part[i] > v ? part[i] : v;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < 1024 / kWave; k++) t = red[k] > t ? red[k] : t;
+        st->reach_max = t;
+    }
+}
+
+constexpr int kBoxGrid = 16384;
+
+hipError_t launch_leaf_boxes(const Workspace &ws, int64_t n, double dt, hipStream_t s) {
+    (void)n;
+    k_leaf_boxes<<<kBoxGrid, kWave, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs,
+                                            ws.rads, dt, ws.ent_cell, ws.c_first, ws.c_count,
+                                            ws.cbox, ws.pcol, ws.vcol, ws.count_part);
+    k_max_u64<<<1, 1024, 0, s>>>(ws.count_part, kBoxGrid, ws.st);
+    return hipGetLastError();
 }
 
 constexpr int kCandBlock = 256;
@@ -421,7 +706,7 @@ __device__ __forceinline__ int block_excl(int v, int &excl, int *wtot) {
 
 __global__ void __launch_bounds__(kCandBlock)
 k_cand_count(const DevState *__restrict__ st, const int2 *__restrict__ m2l, int64_t m2l_cap,
-             const int2 *__restrict__ p2p, int64_t p2p_cap, const double4 *__restrict__ ccell,
+             const int2 *__restrict__ p2p, int64_t p2p_cap, const BoxArgs B,
              const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent,
              const int32_t *__restrict__ c_count, const int32_t *__restrict__ ent_cell,
              int32_t *__restrict__ blk) {
@@ -433,10 +718,9 @@ k_cand_count(const DevState *__restrict__ st, const int2 *__restrict__ m2l, int6
          q0 += (int64_t)gridDim.x * kCandBlock) {
         const int64_t q = q0 + threadIdx.x;
         int2 pr = make_int2(-1, -1);
-        const bool sep = q < L.nm;
-        if (q < L.total) pr = sep ? L.m2l[q] : L.p2p[q - L.nm];        // gaps are (-1, -1)
-        const int cnt = leaf_candidates(pr, sep, ccell, c_entry, c_nent, c_count, ent_cell,
-                                        nullptr, 0, 0);
+        if (q < L.total) pr = q < L.nm ? L.m2l[q] : L.p2p[q - L.nm];   // gaps are (-1, -1)
+        const int cnt = leaf_candidates(pr, B, st, c_entry, c_nent, c_count, ent_cell, nullptr,
+                                        0, 0);
         int excl;
         sum += block_excl(cnt, excl, wtot);
     }
@@ -476,7 +760,7 @@ __global__ void __launch_bounds__(1024) k_cand_scan(DevState *st, int32_t *blk, 
 
 __global__ void __launch_bounds__(kCandBlock)
 k_cand_write(DevState *st, const int2 *__restrict__ m2l, int64_t m2l_cap,
-             const int2 *__restrict__ p2p, int64_t p2p_cap, const double4 *__restrict__ ccell,
+             const int2 *__restrict__ p2p, int64_t p2p_cap, const BoxArgs B,
              const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent,
              const int32_t *__restrict__ c_count, const int32_t *__restrict__ ent_cell,
              const int32_t *__restrict__ blk, int2 *cand, int64_t cand_cap) {
@@ -488,14 +772,13 @@ k_cand_write(DevState *st, const int2 *__restrict__ m2l, int64_t m2l_cap,
          q0 += (int64_t)gridDim.x * kCandBlock) {
         const int64_t q = q0 + threadIdx.x;
         int2 pr = make_int2(-1, -1);
-        const bool sep = q < L.nm;
-        if (q < L.total) pr = sep ? L.m2l[q] : L.p2p[q - L.nm];
-        const int cnt = leaf_candidates(pr, sep, ccell, c_entry, c_nent, c_count, ent_cell,
-                                        nullptr, 0, 0);
+        if (q < L.total) pr = q < L.nm ? L.m2l[q] : L.p2p[q - L.nm];
+        const int cnt = leaf_candidates(pr, B, st, c_entry, c_nent, c_count, ent_cell, nullptr,
+                                        0, 0);
         int excl;
         const int all = block_excl(cnt, excl, wtot);
         const int64_t pos = run + excl;
-        if (cnt) leaf_candidates(pr, sep, ccell, c_entry, c_nent, c_count, ent_cell, cand, pos,
+        if (cnt) leaf_candidates(pr, B, st, c_entry, c_nent, c_count, ent_cell, cand, pos,
                                  cand_cap);
         if (cnt && pos + cnt > cand_cap) {
             atomicOr(&st->status, (int32_t)ST_CAP_P2P);
@@ -510,13 +793,17 @@ hipError_t launch_candidates_from_lists(const Workspace &ws, hipStream_t s) {
     int64_t g = (ws.m2l_cap + ws.p2p_cap + kCandBlock - 1) / kCandBlock;
     if (g > kCandGrid) g = kCandGrid;
     if (g < 1) g = 1;
-    k_cand_count<<<(int)g, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap,
-                                               ws.ccell, ws.c_entry, ws.c_nent, ws.c_count,
-                                               ws.ent_cell, ws.cand_blk);
+    BoxArgs B;
+    B.cbox = ws.cbox;
+    B.gcell = ws.gcell;
+    B.c_rmax = ws.c_rmax;
+    k_cand_count<<<(int)g, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap, B,
+                                               ws.c_entry, ws.c_nent, ws.c_count, ws.ent_cell,
+                                               ws.cand_blk);
     k_cand_scan<<<1, 1024, 0, s>>>(ws.st, ws.cand_blk, (int)g);
-    k_cand_write<<<(int)g, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap,
-                                               ws.ccell, ws.c_entry, ws.c_nent, ws.c_count,
-                                               ws.ent_cell, ws.cand_blk, ws.cand, ws.p2p_cap);
+    k_cand_write<<<(int)g, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap, B,
+                                               ws.c_entry, ws.c_nent, ws.c_count, ws.ent_cell,
+                                               ws.cand_blk, ws.cand, ws.p2p_cap);
     return hipGetLastError();
 }
 
@@ -676,12 +963,24 @@ hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, 
     return hipGetLastError();
 }
 
-hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipStream_t s) {
+hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, bool boxes,
+                                hipStream_t s) {
     (void)n;
     k_collide_init<<<1, 64, 0, s>>>(ws.st);
-    k_collide<<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count, ws.ccell,
-                                   ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, ws.idx,
-                                   ws.pcol, dt, ws.pairs_tmp, ws.pair_cap, ws.count_part);
+    if (boxes) {
+        k_collide<true><<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count,
+                                             ws.ccell, ws.cbox, ws.xs, ws.ys, ws.zs, ws.vxs,
+                                             ws.vys, ws.vzs, ws.rads, ws.idx, ws.pcol, ws.vcol,
+                                             ws.ent_cell, dt, ws.pairs_tmp, ws.pair_cap,
+                                             ws.count_part);
+        return launch_sum_u64(ws.count_part, 16384, (unsigned long long *)&ws.st->col_tests,
+                              true, s);
+    }
+    k_collide<false><<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count,
+                                          ws.ccell, ws.cbox, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys,
+                                          ws.vzs, ws.rads, ws.idx, ws.pcol, ws.vcol,
+                                          ws.ent_cell, dt, ws.pairs_tmp, ws.pair_cap,
+                                          ws.count_part);
     return launch_sum_u64(ws.count_part, 16384, (unsigned long long *)&ws.st->col_tests, true,
                           s);
 }

@@ -111,6 +111,8 @@ struct DevState {
     // source moonlets any leaf's direct sums take
     int64_t walk_busy_sum, walk_busy_max;
     int64_t p2p_src_max;
+    // collisions: the largest R + dt |v| of any moonlet (bit pattern of a double >= 0)
+    unsigned long long reach_max;
 };
 
 // ---------------------------------------------------------------- mesh module
@@ -221,6 +223,9 @@ struct Workspace {
     // collision search
     double4 *pack4 = nullptr;
     double4 *pcol = nullptr;                          // x, y, z, R + dt |v| (collisions)
+    double4 *vcol = nullptr;                          // vx, vy, vz, R (tree order, collisions)
+    double4 *cbox = nullptr;                          // per leaf: box low corner + largest
+                                                      // R + dt |v|, box high corner
     double *acc = nullptr;                            // 3 x n, input order (step)
     double *acc_s = nullptr;                          // 3 x n, tree order (direct sums)
     // leaves in moonlet order ("entries")
@@ -352,7 +357,9 @@ hipError_t launch_standard_tree_collide(const Workspace &ws, int64_t n, int ncb_
 // standard tree code (Alg. 1): accelerations of all moonlets, input order
 hipError_t launch_standard_tree(const Workspace &ws, int64_t n, int p, int ncb_pre, int ncb_post,
                                 double *ax, double *ay, double *az, hipStream_t s);
-hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, hipStream_t s);
+hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, bool boxes,
+                                hipStream_t s);
+hipError_t launch_leaf_boxes(const Workspace &ws, int64_t n, double dt, hipStream_t s);
 // collision candidates from the gravity walk's lists of the same tree (in place of
 // the collision walk)
 hipError_t launch_candidates_from_lists(const Workspace &ws, hipStream_t s);
