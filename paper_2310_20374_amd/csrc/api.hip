@@ -611,6 +611,9 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
                         const double *R, double dt, int64_t *pairs, int64_t cap,
                         int64_t *n_pairs_dev, int triple, int step, hipStream_t s,
                         double *const *state = nullptr, const double *m = nullptr) {
+    // inside ncorp_step the kick before the search already wrote the packed (v, R)
+    // records in input order
+    const bool packed = state != nullptr;
     Workspace &ws = c->ws;
     const int64_t n = c->n;
     PhaseTimer t(c, NCORP_PHASE_COLLIDE, s);
@@ -620,23 +623,25 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
     } else if (c->prm.collision_method == NCORP_COLLISIONS_BRUTE_FORCE) {
         if (ws.ndisks > 1)
             return fail(c, NCORP_E_UNSUPPORTED, "brute-force collisions take plain calls only");
-        HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
+        HIPCHK(c, launch_gather_vr(ws, packed, vx, vy, vz, R, n, s));
         HIPCHK(c, launch_collide_reset(ws, s));
         HIPCHK(c, launch_brute_collide(ws, n, dt, s));
     } else if (c->prm.collision_method == NCORP_COLLISIONS_STANDARD_TREE) {
-        HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
+        HIPCHK(c, launch_gather_vr(ws, packed, vx, vy, vz, R, n, s));
         HIPCHK(c, launch_collision_climb(ws, n, dt, s));
         HIPCHK(c, launch_collide_reset(ws, s));
         HIPCHK(c, launch_standard_tree_collide(ws, n, c->prm.ncb_pre, c->prm.ncb_post, dt, s));
     } else {
-        HIPCHK(c, launch_gather_vr(ws, vx, vy, vz, R, n, s));
         if (c->grav_lists) {
             // candidates from the gravity walk's lists of this tree, culled with the
-            // moonlets' bounding boxes (no collision climb needed)
+            // moonlets' bounding boxes (no collision climb needed); the box pass gathers
+            // the packed (v, R) records itself
+            if (!packed) HIPCHK(c, launch_pack_vr(ws, vx, vy, vz, R, n, s));
             HIPCHK(c, launch_leaf_boxes(ws, n, dt, s));
             HIPCHK(c, launch_candidates_from_lists(ws, s));
             HIPCHK(c, launch_collide_pairs(ws, n, dt, true, s));
         } else {
+            HIPCHK(c, launch_gather_vr(ws, packed, vx, vy, vz, R, n, s));
             HIPCHK(c, launch_collision_climb(ws, n, dt, s));
             HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col,
                                   c->prm.ncc_post_col, s));
@@ -732,7 +737,7 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
     {
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
         HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, 0.5 * dt,
-                              central_body(c->prm, c->clock), s));
+                              central_body(c->prm, c->clock), R, ws.pack4, s));
     }
     for (int k = 0; k < n_steps; k++) {
         double *const state[6] = {x, y, z, vx, vy, vz};
@@ -747,7 +752,8 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
         const double h = (k == n_steps - 1) ? 0.5 * dt : dt;
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
         HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, h,
-                              central_body(c->prm, c->clock + (double)(k + 1) * dt), s));
+                              central_body(c->prm, c->clock + (double)(k + 1) * dt), R,
+                              ws.pack4, s));
     }
     c->clock += (double)n_steps * dt;
     c->last = s;

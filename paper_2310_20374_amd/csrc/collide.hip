@@ -89,10 +89,7 @@ __device__ __forceinline__ bool can_reach(const double4 &p, const double4 &a, co
 template <bool BOXES>
 __device__ __forceinline__ int cull_cell(int f, int n, double4 oa, double4 ob,
                                          const double4 *__restrict__ pcol,
-                                         const double *__restrict__ vxs,
-                                         const double *__restrict__ vys,
-                                         const double *__restrict__ vzs,
-                                         const double *__restrict__ rads,
+                                         const double4 *__restrict__ vcol,
                                          const uint32_t *__restrict__ perm, PState *out,
                                          int limit) {
     const int lane = threadIdx.x;
@@ -109,7 +106,8 @@ __device__ __forceinline__ int cull_cell(int f, int n, double4 oa, double4 ob,
             keep = can_reach<BOXES>(p, oa, ob);
         }
         if (keep) {
-            ps.vx = vxs[k]; ps.vy = vys[k]; ps.vz = vzs[k]; ps.R = rads[k];
+            const double4 v = vcol[k];
+            ps.vx = v.x; ps.vy = v.y; ps.vz = v.z; ps.R = v.w;
             ps.id = perm[k];
         }
         const uint64_t m = __ballot(keep);
@@ -154,11 +152,8 @@ __device__ __forceinline__ void self_pairs_staged(int n, const PState *sb,
 // lane groups when A holds fewer than 64.
 __device__ __forceinline__ void test_cell_pair(
     int2 pr, PState *sb, double4 *spos, const int32_t *__restrict__ c_first,
-    const int32_t *__restrict__ c_count,
-    const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
-    const double *__restrict__ vxs, const double *__restrict__ vys,
-    const double *__restrict__ vzs, const double *__restrict__ rads,
-    const uint32_t *__restrict__ perm, const double4 *__restrict__ pcol, double dt, int64_t *out,
+    const int32_t *__restrict__ c_count, const uint32_t *__restrict__ perm,
+    const double4 *__restrict__ pcol, const double4 *__restrict__ vcol, double dt, int64_t *out,
     int64_t cap, DevState *st, unsigned long long &tests) {
     const int lane = threadIdx.x;
     const int fa = c_first[pr.x], na = c_count[pr.x];
@@ -169,12 +164,12 @@ __device__ __forceinline__ void test_cell_pair(
         if (lane < na) {
             const int b = fa + lane;
             PState ps;
-            ps.x = xs[b]; ps.y = ys[b]; ps.z = zs[b];
-            ps.vx = vxs[b]; ps.vy = vys[b]; ps.vz = vzs[b]; ps.R = rads[b];
-            ps.reach = pcol[b].w;
+            const double4 p = pcol[b], v = vcol[b];
+            ps.x = p.x; ps.y = p.y; ps.z = p.z; ps.reach = p.w;
+            ps.vx = v.x; ps.vy = v.y; ps.vz = v.z; ps.R = v.w;
             ps.id = perm[b];
             sb[lane] = ps;
-            spos[lane] = make_double4(ps.x, ps.y, ps.z, ps.reach);
+            spos[lane] = p;
         }
         __syncthreads();
         self_pairs_staged(na, sb, spos, dt, out, cap, st, tests);
@@ -189,9 +184,11 @@ __device__ __forceinline__ void test_cell_pair(
         const int ia = a0 + (act ? tl : 0);
         const int a = fa + ia;
         PState me;
-        me.x = xs[a]; me.y = ys[a]; me.z = zs[a];
-        me.vx = vxs[a]; me.vy = vys[a]; me.vz = vzs[a]; me.R = rads[a];
-        me.reach = pcol[a].w;
+        {
+            const double4 p = pcol[a], v = vcol[a];
+            me.x = p.x; me.y = p.y; me.z = p.z; me.reach = p.w;
+            me.vx = v.x; me.vy = v.y; me.vz = v.z; me.R = v.w;
+        }
         me.id = perm[a];
         for (int b0 = self ? a0 : 0; b0 < nb; b0 += 64) {
             const int nbc = nb - b0 < 64 ? nb - b0 : 64;
@@ -199,9 +196,9 @@ __device__ __forceinline__ void test_cell_pair(
             if (lane < nbc) {
                 const int b = fb + b0 + lane;
                 PState ps;
-                ps.x = xs[b]; ps.y = ys[b]; ps.z = zs[b];
-                ps.vx = vxs[b]; ps.vy = vys[b]; ps.vz = vzs[b]; ps.R = rads[b];
-                ps.reach = pcol[b].w;
+                const double4 p = pcol[b], v = vcol[b];
+                ps.x = p.x; ps.y = p.y; ps.z = p.z; ps.reach = p.w;
+                ps.vx = v.x; ps.vy = v.y; ps.vz = v.z; ps.R = v.w;
                 ps.id = perm[b];
                 sb[lane] = ps;
             }
@@ -230,10 +227,6 @@ __global__ void __launch_bounds__(64)
 k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
           const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
           const double4 *__restrict__ ccell, const double4 *__restrict__ cbox,
-          const double *__restrict__ xs,
-          const double *__restrict__ ys, const double *__restrict__ zs,
-          const double *__restrict__ vxs, const double *__restrict__ vys,
-          const double *__restrict__ vzs, const double *__restrict__ rads,
           const uint32_t *__restrict__ perm, const double4 *__restrict__ pcol,
           const double4 *__restrict__ vcol, const int32_t *__restrict__ ent_cell, double dt,
           int64_t *out, int64_t cap, unsigned long long *tests_part) {
@@ -345,18 +338,18 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
                     if (keep) {
                         PState ps;
                         ps.x = p.x; ps.y = p.y; ps.z = p.z; ps.reach = p.w;
-                        ps.vx = vxs[k]; ps.vy = vys[k]; ps.vz = vzs[k]; ps.R = rads[k];
+                        const double4 v = vcol[k];
+                        ps.vx = v.x; ps.vy = v.y; ps.vz = v.z; ps.R = v.w;
                         ps.id = perm[k];
                         sp[inA ? __popcll(mA & lt) : ka + __popcll(mB & lt)] = ps;
                     }
                 } else {
                     const double4 sA = bcast4(sph, l), sB = bcast4(sph, lb);
                     const double4 hA = bcast4(shi, l), hB = bcast4(shi, lb);
-                    ka = cull_cell<BOXES>(fa, na, sA, hA, pcol, vxs, vys, vzs, rads, perm, sp,
-                                          kWave);
+                    ka = cull_cell<BOXES>(fa, na, sA, hA, pcol, vcol, perm, sp, kWave);
                     kb = ka < 0 ? -1
-                                : cull_cell<BOXES>(fb, nb, sB, hB, pcol, vxs, vys, vzs, rads,
-                                                   perm, sp + ka, kWave - ka);
+                                : cull_cell<BOXES>(fb, nb, sB, hB, pcol, vcol, perm, sp + ka,
+                                                   kWave - ka);
                 }
                 __syncthreads();
                 if (ka >= 0 && kb >= 0) {
@@ -368,8 +361,8 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
                     continue;
                 }
             }
-            test_cell_pair(pr, sp, spos, c_first, c_count, xs, ys, zs, vxs, vys, vzs, rads, perm, pcol,
-                           dt, out, cap, st, tests);
+            test_cell_pair(pr, sp, spos, c_first, c_count, perm, pcol, vcol, dt, out, cap, st,
+                           tests);
         }
     }
     if (BOXES) {
@@ -381,8 +374,8 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
             const int n = c_count[c];
             if (n < 2) continue;
             if (n > kWave) {
-                test_cell_pair(make_int2(c, c), sp, spos, c_first, c_count, xs, ys, zs, vxs, vys,
-                               vzs, rads, perm, pcol, dt, out, cap, st, tests);
+                test_cell_pair(make_int2(c, c), sp, spos, c_first, c_count, perm, pcol, vcol, dt,
+                               out, cap, st, tests);
                 continue;
             }
             __syncthreads();
@@ -587,9 +580,8 @@ __device__ __forceinline__ int leaf_candidates(int2 pr, const BoxArgs &B, const 
 // all moonlets (for the cubes of internal cells).
 __global__ void __launch_bounds__(kWave)
 k_leaf_boxes(DevState *st, const double *__restrict__ xs, const double *__restrict__ ys,
-             const double *__restrict__ zs, const double *__restrict__ vxs,
-             const double *__restrict__ vys, const double *__restrict__ vzs,
-             const double *__restrict__ rads, double dt, const int32_t *__restrict__ ent_cell,
+             const double *__restrict__ zs, const double4 *__restrict__ pack4,
+             const uint32_t *__restrict__ perm, double dt, const int32_t *__restrict__ ent_cell,
              const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
              double4 *__restrict__ cbox, double4 *__restrict__ pcol,
              double4 *__restrict__ vcol, unsigned long long *__restrict__ part) {
@@ -608,10 +600,11 @@ k_leaf_boxes(DevState *st, const double *__restrict__ xs, const double *__restri
         for (int c0 = lane; c0 < cnt; c0 += kWave) {
             const int k = f + c0;
             const double x = xs[k], y = ys[k], z = zs[k];
-            const double v = sqrt(vxs[k] * vxs[k] + vys[k] * vys[k] + vzs[k] * vzs[k]);
-            const double ee = (rads[k] + dt * v) - 0.0;
+            const double4 w = pack4[perm[k]];          // (vx, vy, vz, R), input order
+            const double v = sqrt(w.x * w.x + w.y * w.y + w.z * w.z);
+            const double ee = (w.w + dt * v) - 0.0;
             pcol[k] = make_double4(x, y, z, ee);
-            vcol[k] = make_double4(vxs[k], vys[k], vzs[k], rads[k]);
+            vcol[k] = w;
             lx = fmin(lx, x); ly = fmin(ly, y); lz = fmin(lz, z);
             hx = fmax(hx, x); hy = fmax(hy, y); hz = fmax(hz, z);
             ex = fmax(ex, ee);
@@ -657,8 +650,8 @@ constexpr int kBoxGrid = 16384;
 
 hipError_t launch_leaf_boxes(const Workspace &ws, int64_t n, double dt, hipStream_t s) {
     (void)n;
-    k_leaf_boxes<<<kBoxGrid, kWave, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs,
-                                            ws.rads, dt, ws.ent_cell, ws.c_first, ws.c_count,
+    k_leaf_boxes<<<kBoxGrid, kWave, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.pack4, ws.idx, dt,
+                                            ws.ent_cell, ws.c_first, ws.c_count,
                                             ws.cbox, ws.pcol, ws.vcol, ws.count_part);
     k_max_u64<<<1, 1024, 0, s>>>(ws.count_part, kBoxGrid, ws.st);
     return hipGetLastError();
@@ -969,16 +962,14 @@ hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, bool 
     k_collide_init<<<1, 64, 0, s>>>(ws.st);
     if (boxes) {
         k_collide<true><<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count,
-                                             ws.ccell, ws.cbox, ws.xs, ws.ys, ws.zs, ws.vxs,
-                                             ws.vys, ws.vzs, ws.rads, ws.idx, ws.pcol, ws.vcol,
+                                             ws.ccell, ws.cbox, ws.idx, ws.pcol, ws.vcol,
                                              ws.ent_cell, dt, ws.pairs_tmp, ws.pair_cap,
                                              ws.count_part);
         return launch_sum_u64(ws.count_part, 16384, (unsigned long long *)&ws.st->col_tests,
                               true, s);
     }
     k_collide<false><<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count,
-                                          ws.ccell, ws.cbox, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys,
-                                          ws.vzs, ws.rads, ws.idx, ws.pcol, ws.vcol,
+                                          ws.ccell, ws.cbox, ws.idx, ws.pcol, ws.vcol,
                                           ws.ent_cell, dt, ws.pairs_tmp, ws.pair_cap,
                                           ws.count_part);
     return launch_sum_u64(ws.count_part, 16384, (unsigned long long *)&ws.st->col_tests, true,

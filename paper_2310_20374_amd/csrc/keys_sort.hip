@@ -581,7 +581,8 @@ __global__ void k_pack4(const double *__restrict__ a, const double *__restrict__
 
 __global__ void k_gather_vr(const double4 *__restrict__ pack4, const uint32_t *__restrict__ idx,
                             int64_t n, double *__restrict__ as, double *__restrict__ bs,
-                            double *__restrict__ cs, double *__restrict__ ds) {
+                            double *__restrict__ cs, double *__restrict__ ds,
+                            double4 *__restrict__ vcol) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double4 v = pack4[idx[i]];
@@ -589,6 +590,7 @@ __global__ void k_gather_vr(const double4 *__restrict__ pack4, const uint32_t *_
         bs[i] = v.y;
         cs[i] = v.z;
         ds[i] = v.w;
+        vcol[i] = v;
     }
 }
 
@@ -599,14 +601,17 @@ hipError_t launch_pack_vr(const Workspace &ws, const double *vx, const double *v
     return hipGetLastError();
 }
 
-// velocities and radii in tree order: packed first, then one record per moonlet
-// instead of four scattered words
-hipError_t launch_gather_vr(const Workspace &ws, const double *vx, const double *vy,
-                            const double *vz, const double *R, int64_t n, hipStream_t s) {
-    hipError_t e = launch_pack_vr(ws, vx, vy, vz, R, n, s);
-    if (e != hipSuccess) return e;
+// velocities and radii in tree order: packed first (unless `packed`: the kick did it),
+// then one record per moonlet instead of four scattered words
+hipError_t launch_gather_vr(const Workspace &ws, bool packed, const double *vx,
+                            const double *vy, const double *vz, const double *R, int64_t n,
+                            hipStream_t s) {
+    if (!packed) {
+        hipError_t e = launch_pack_vr(ws, vx, vy, vz, R, n, s);
+        if (e != hipSuccess) return e;
+    }
     k_gather_vr<<<grid_for(n, 256), 256, 0, s>>>(ws.pack4, ws.idx, n, ws.vxs, ws.vys, ws.vzs,
-                                                 ws.rads);
+                                                 ws.rads, ws.vcol);
     return hipGetLastError();
 }
 

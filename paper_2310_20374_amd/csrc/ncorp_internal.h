@@ -325,7 +325,7 @@ hipError_t launch_gather(const Workspace &ws, const double *src, double *dst, in
 // velocities and radii into tree order, one pass
 hipError_t launch_pack_vr(const Workspace &ws, const double *vx, const double *vy,
                           const double *vz, const double *R, int64_t n, hipStream_t s);
-hipError_t launch_gather_vr(const Workspace &ws, const double *vx, const double *vy,
+hipError_t launch_gather_vr(const Workspace &ws, bool packed, const double *vx, const double *vy,
                             const double *vz, const double *R, int64_t n, hipStream_t s);
 hipError_t launch_build_tree(const Workspace &ws, int64_t n, int leaf_size, hipStream_t s);
 
@@ -397,7 +397,7 @@ struct CentralBody {
 hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax,
                        const double *ay, const double *az, const double *x,
                        const double *y, const double *z, int64_t n, double h,
-                       const CentralBody &b, hipStream_t s);
+                       const CentralBody &b, const double *R, double4 *pack, hipStream_t s);
 hipError_t launch_drift(double *x, double *y, double *z, const double *vx,
                         const double *vy, const double *vz, int64_t n, double dt,
                         hipStream_t s);

@@ -12,7 +12,8 @@ __global__ void k_kick(double *__restrict__ vx, double *__restrict__ vy, double 
                        const double *__restrict__ ax, const double *__restrict__ ay,
                        const double *__restrict__ az, const double *__restrict__ x,
                        const double *__restrict__ y, const double *__restrict__ z, int64_t n,
-                       double h, CentralBody b) {
+                       double h, CentralBody b, const double *__restrict__ R,
+                       double4 *__restrict__ pack) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double px = x[i], py = y[i], pz = z[i];
@@ -35,9 +36,12 @@ __global__ void k_kick(double *__restrict__ vx, double *__restrict__ vy, double 
             gz += g * (pz - q * b.sz);
         }
         if (ax) { gx += ax[i]; gy += ay[i]; gz += az[i]; }
-        vx[i] += h * gx;
-        vy[i] += h * gy;
-        vz[i] += h * gz;
+        const double ux = vx[i] + h * gx, uy = vy[i] + h * gy, uz = vz[i] + h * gz;
+        vx[i] = ux;
+        vy[i] = uy;
+        vz[i] = uz;
+        // the (v, R) record the next collision search gathers into tree order
+        if (pack) pack[i] = make_double4(ux, uy, uz, R[i]);
     }
 }
 
@@ -59,8 +63,9 @@ static int grid1(int64_t n) {
 
 hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax, const double *ay,
                        const double *az, const double *x, const double *y, const double *z,
-                       int64_t n, double h, const CentralBody &b, hipStream_t s) {
-    k_kick<<<grid1(n), 256, 0, s>>>(vx, vy, vz, ax, ay, az, x, y, z, n, h, b);
+                       int64_t n, double h, const CentralBody &b, const double *R,
+                       double4 *pack, hipStream_t s) {
+    k_kick<<<grid1(n), 256, 0, s>>>(vx, vy, vz, ax, ay, az, x, y, z, n, h, b, R, pack);
     return hipGetLastError();
 }
 
