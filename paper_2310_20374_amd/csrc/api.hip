@@ -260,7 +260,7 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.nm = n_mult(prm.p);
     ws.nl = n_local(prm.p);
     const int64_t nb = (n + 1023) / 1024;
-    const int64_t ntiles = (n + 4095) / 4096;
+    const int64_t ntiles = (n + kSortTileItems - 1) / kSortTileItems;
     int64_t off = 0;
     auto take = [&](int64_t bytes) {
         int64_t o = off;

@@ -46,6 +46,8 @@ enum StatusBits : int32_t {
 // then do nothing rather than follow indices that were never written.
 // persistent walk: waves, and list slots a wave reserves at a time (the plain
 // cell-pair lists carry up to kWalkWaves * kListChunk slots of gaps)
+// items per tile of the radix sort's passes (the workspace sizes its histograms by it)
+constexpr int kSortTileItems = 2048;
 constexpr int kWalkBlock = 256;
 // persistent blocks: the gravity walk runs 1024 waves, the collision walk (less
 // work per item) 512; more only adds contention on the queue counters
