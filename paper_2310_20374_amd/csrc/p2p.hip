@@ -151,10 +151,11 @@ template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 // r^2 floor: a moonlet meets itself (dx = 0) in its own leaf; the floor keeps
 // 1/r^3 finite there so the term is exactly 0, and is far below any pair distance
-// (FP32: added to r^2; FP64: a lower bound on r^2)
+// (FP32: added to r^2; FP64: a lower bound on r^2).  m / floor^(3/2) stays finite for
+// G m up to ~3e11 (FP32) and ~1e158 (FP64).
 template <typename T> __device__ __forceinline__ T r2_floor();
-template <> __device__ __forceinline__ float r2_floor<float>() { return 1e-24f; }
-template <> __device__ __forceinline__ double r2_floor<double>() { return 1e-200; }
+template <> __device__ __forceinline__ float r2_floor<float>() { return 1e-18f; }
+template <> __device__ __forceinline__ double r2_floor<double>() { return 1e-100; }
 
 constexpr int kP2PTile = 256;       // source moonlets staged per LDS tile
 constexpr int kP2PSrc = kWave;      // source cells per batch, one per lane (prefix sums in LDS)
@@ -241,8 +242,10 @@ __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_fir
         if constexpr (NT == 1) {
 #pragma unroll 4
             for (int j = j0; j < nj; j += G) interact<T, NT>(tile[j], xi, yi, zi, px, py, pz);
-        } else {
+        } else if constexpr (NT == 2) {
 #pragma unroll 2
+            for (int j = j0; j < nj; j += G) interact<T, NT>(tile[j], xi, yi, zi, px, py, pz);
+        } else {
             for (int j = j0; j < nj; j += G) interact<T, NT>(tile[j], xi, yi, zi, px, py, pz);
         }
 #pragma unroll
@@ -325,6 +328,56 @@ __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1,
     }
 }
 
+// Targets per lane for a chunk of ntc <= 64 targets: lpg = ceil(ntc / NT) lanes hold
+// them, G = 64 / lpg lane groups split every tile, so a round keeps ntc * G of the
+// 64 * NT lane slots busy.  The NT in 1..4 with the largest share wins (the smaller
+// on ties): 43 targets use 3 per lane (4 groups of 15 lanes, 90 % busy) where one or
+// two per lane leave a third of the lanes idle.
+__device__ __forceinline__ int targets_per_lane(int ntc) {
+    int best = 1, best_score = -1;
+#pragma unroll
+    for (int nt = 1; nt <= 4; nt++) {
+        const int lpg = (ntc + nt - 1) / nt;
+        const int score = ntc * (kWave / lpg) * (12 / nt);
+        if (score > best_score) { best = nt; best_score = score; }
+    }
+    return best;
+}
+
+template <typename T>
+__device__ __forceinline__ void p2p_targets_any(int ntc, int tb, bool one, int tot1, int len,
+                                                int b0, int bstep,
+                                                const int32_t *__restrict__ list,
+                                                int32_t *s_first, int32_t *s_pref,
+                                                typename Vec4<T>::type *tile,
+                                                const double *__restrict__ xs,
+                                                const double *__restrict__ ys,
+                                                const double *__restrict__ zs,
+                                                const double *__restrict__ mus,
+                                                const int32_t *__restrict__ c_first,
+                                                const int32_t *__restrict__ c_count,
+                                                const double4 g, double *__restrict__ out,
+                                                int64_t n) {
+    switch (targets_per_lane(ntc)) {
+        case 1:
+            p2p_targets<T, 1>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
+                              xs, ys, zs, mus, c_first, c_count, g, out, n);
+            break;
+        case 2:
+            p2p_targets<T, 2>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
+                              xs, ys, zs, mus, c_first, c_count, g, out, n);
+            break;
+        case 3:
+            p2p_targets<T, 3>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
+                              xs, ys, zs, mus, c_first, c_count, g, out, n);
+            break;
+        default:
+            p2p_targets<T, 4>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
+                              xs, ys, zs, mus, c_first, c_count, g, out, n);
+            break;
+    }
+}
+
 constexpr int kP2PWaves = 4;        // independent waves per block
 static_assert(kP2PListLDS == kP2PSrc, "one LDS batch holds a list the pre-pass leaves unsorted");
 
@@ -367,15 +420,8 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
             wave_sync();                              // this wave's LDS is free again
             for (int t0 = 0; t0 < nt; t0 += kWave) {
                 const int ntc = nt - t0 < kWave ? nt - t0 : kWave;
-                const int lpg2 = (ntc + 1) / 2;
-                if ((kWave / lpg2) * ntc > 2 * (kWave / ntc) * ntc)
-                    p2p_targets<T, 2>(ntc, f + t0, false, 0, len, slot, kLongSlots, list,
-                                      s_first, s_pref, tile, xs, ys, zs, mus, c_first, c_count,
-                                      g, out, n);
-                else
-                    p2p_targets<T, 1>(ntc, f + t0, false, 0, len, slot, kLongSlots, list,
-                                      s_first, s_pref, tile, xs, ys, zs, mus, c_first, c_count,
-                                      g, out, n);
+                p2p_targets_any<T>(ntc, f + t0, false, 0, len, slot, kLongSlots, list, s_first,
+                                   s_pref, tile, xs, ys, zs, mus, c_first, c_count, g, out, n);
             }
             continue;
         }
@@ -412,14 +458,8 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
         wave_sync();
         for (int t0 = 0; t0 < nt; t0 += kWave) {
             const int ntc = nt - t0 < kWave ? nt - t0 : kWave;
-            // one or two targets per lane, whichever leaves fewer lanes idle
-            const int lpg2 = (ntc + 1) / 2;
-            if ((kWave / lpg2) * ntc > 2 * (kWave / ntc) * ntc)
-                p2p_targets<T, 2>(ntc, f + t0, true, tot1, len, 0, 1, list, s_first, s_pref,
-                                  tile, xs, ys, zs, mus, c_first, c_count, g, acc_s, n);
-            else
-                p2p_targets<T, 1>(ntc, f + t0, true, tot1, len, 0, 1, list, s_first, s_pref,
-                                  tile, xs, ys, zs, mus, c_first, c_count, g, acc_s, n);
+            p2p_targets_any<T>(ntc, f + t0, true, tot1, len, 0, 1, list, s_first, s_pref, tile,
+                               xs, ys, zs, mus, c_first, c_count, g, acc_s, n);
         }
     }
 }
