@@ -279,8 +279,8 @@ int ncorp_step_batched(ncorp_ctx *ctx, const int64_t *disk_offsets, int n_disks,
  * by the first call on that GPU (the device current at the call) and held until
  * the process ends.  Nothing is allocated or freed by the call.
  *  - Size limit: n must satisfy ncorp_workspace_bytes(params, n, 1) <=
- *    NCORP_STATIC_WORKSPACE_BYTES (with the default capacities up to 19 001 moonlets
- *    at p = 6 and 20 032 at p = 4, leaf size 52, and 7 088 at p = 3, leaf size 17;
+ *    NCORP_STATIC_WORKSPACE_BYTES (with the default capacities up to 18 823 moonlets
+ *    at p = 6 and 19 837 at p = 4, leaf size 52, and 7 050 at p = 3, leaf size 17;
  *    a larger leaf size allows more); a larger n returns
  *    NCORP_E_INVALID at once, before anything touches the GPU.  The part of the
  *    array the layout does not use holds the colliding pairs of the step.
@@ -314,6 +314,7 @@ enum {
     NCORP_INFO_COL_TESTS, NCORP_INFO_M2L_DIR, NCORP_INFO_P2P_INTER, NCORP_INFO_M2L_MAXLIST,
     NCORP_INFO_P2P_MAXLIST, NCORP_INFO_NROOTS, NCORP_INFO_LONG_M2L, NCORP_INFO_LONG_P2P,
     NCORP_INFO_WALK_BUSY_MAX, NCORP_INFO_WALK_BUSY_MEAN, NCORP_INFO_P2P_SRC_MAX,
+    NCORP_INFO_SORT_PREV, NCORP_INFO_SORT_SPILL,
     NCORP_INFO_COUNT
 };
 /* Waits for the stream and fills info[NCORP_INFO_COUNT] with sizes of the last
@@ -330,7 +331,10 @@ enum {
  * such leaves are split over several waves); and, again only while phase timing is on,
  * the load balance of the last gravity evaluation: the largest and the mean number of
  * shader clock cycles (clock64) the gravity walk's persistent waves were busy, and the
- * most source moonlets of one leaf's direct sums (the mean is p2p_inter / n). */
+ * most source moonlets of one leaf's direct sums (the mean is p2p_inter / n).  The
+ * last two describe the sort of the last plain tree build (Sect. 3.4.6): 1 if its
+ * buckets came from the order of the build before it (0: from a sample of the keys),
+ * and the number of buckets too large for one LDS batch, sorted by merging. */
 int ncorp_tree_info(ncorp_ctx *ctx, int64_t *info);
 
 enum {

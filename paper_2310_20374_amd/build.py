@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build", "ncorp")
 LIB = os.path.join(HERE, "libncorp.so")
-SOURCES = ["api.hip", "keys_sort.hip", "scan.hip", "tree.hip", "climb.hip", "walk.hip",
+SOURCES = ["api.hip", "keys_sort.hip", "bucket_sort.hip", "scan.hip", "tree.hip", "climb.hip", "walk.hip",
            "m2l.hip", "p2p.hip", "collide.hip", "step.hip", "stdtree.hip", "mesh.hip", "brute.hip"]
 ARCH = os.environ.get("NCORP_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

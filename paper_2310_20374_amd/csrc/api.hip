@@ -330,6 +330,16 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.cnt_a = (int32_t *)take(4 * cnt);
     ws.scan_part = (int32_t *)take(4 * (nb + 4096));
     ws.hist = (uint32_t *)take(4 * 256 * (ntiles + 1));
+    {
+        int64_t nbk = (n + kBucketMean - 1) / kBucketMean;
+        if (nbk > kMaxBuckets) nbk = kMaxBuckets;
+        const int64_t nbt = (n + kBucketTile - 1) / kBucketTile;
+        ws.bs_split = (SplitKey *)take(sizeof(SplitKey) * nbk);
+        ws.bs_prev = (SplitKey *)take(sizeof(SplitKey) * nbk);
+        ws.bs_cm = (uint32_t *)take(4 * nbk * nbt);
+        ws.bs_total = (uint32_t *)take(4 * nbk);
+        ws.bs_off = (uint32_t *)take(4 * (nbk + 1));
+    }
     ws.seg = (uint16_t *)take(2 * n);
     ws.disk_max = (unsigned long long *)take(8 * (int64_t)kMaxDisks);
     ws.disk_L = (double *)take(8 * (int64_t)kMaxDisks);
@@ -405,6 +415,8 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
     // unknown bytes, so the next walk clears it
     ws.clear_queue = !(c->ws.base == ws.base && c->ws.queue == ws.queue &&
                        c->ws.queue_cap == ws.queue_cap) || c->ws.clear_queue;
+    // the bucket sort's boundaries from the last build are usable only where it wrote them
+    ws.sort_prev = c->ws.base == ws.base && c->ws.bs_prev == ws.bs_prev && c->ws.sort_prev;
     // so does the mesh state
     if (ws.mesh) {
         const bool same = c->ws.base == ws.base && c->ws.mesh == ws.mesh &&
@@ -431,7 +443,12 @@ static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const
     }
     {
         PhaseTimer t(c, NCORP_PHASE_SORT, s);
-        HIPCHK(c, launch_sort(ws, n, s));
+        if (bucket_sort_applies(ws, n)) {
+            HIPCHK(c, launch_bucket_sort(ws, n, s));
+            ws.sort_prev = true;
+        } else {
+            HIPCHK(c, launch_sort(ws, n, s));
+        }
     }
     {
         PhaseTimer t(c, NCORP_PHASE_TREE, s);
@@ -902,6 +919,8 @@ extern "C" int ncorp_tree_info(ncorp_ctx *c, int64_t *info) {
     info[NCORP_INFO_WALK_BUSY_MAX] = h.walk_busy_max;
     info[NCORP_INFO_WALK_BUSY_MEAN] = h.walk_busy_sum / kWalkWaves;
     info[NCORP_INFO_P2P_SRC_MAX] = h.p2p_src_max;
+    info[NCORP_INFO_SORT_PREV] = h.bs_prev_used;
+    info[NCORP_INFO_SORT_SPILL] = h.bs_spill;
     return NCORP_OK;
 }
 

@@ -8,6 +8,10 @@ namespace ncorp {
 __global__ void k_reset_state(DevState *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         DevState z{};
+        // the bucket sort's boundaries for the next build outlive a fresh build
+        z.bs_L = st->bs_L;
+        z.bs_valid = st->bs_valid;
+        z.bs_n = st->bs_n;
         *st = z;
     }
 }
@@ -270,9 +274,9 @@ static int disk_passes(int nd) { return nd <= 1 ? 0 : (nd <= 256 ? 1 : 2); }
 hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                        const double *z, int64_t n, double root_half_width,
                        const int64_t *disk_off, hipStream_t s) {
-    // the sort ends in ws.keys / ws.idx: with an odd number of passes start in the
-    // other buffers
-    const bool odd = (8 + disk_passes(ws.ndisks)) % 2 == 1;
+    // the sort ends in ws.keys / ws.idx: the bucket sort and an odd number of radix
+    // passes start in the other buffers
+    const bool odd = bucket_sort_applies(ws, n) || (8 + disk_passes(ws.ndisks)) % 2 == 1;
     uint64_t *kout = odd ? ws.keys_alt : ws.keys;
     uint32_t *vout = odd ? ws.idx_alt : ws.idx;
     if (disk_off) {

@@ -48,6 +48,14 @@ enum StatusBits : int32_t {
 // cell-pair lists carry up to kWalkWaves * kListChunk slots of gaps)
 // items per tile of the radix sort's passes (the workspace sizes its histograms by it)
 constexpr int kSortTileItems = 2048;
+// bucket sort of a plain tree build: buckets of kBucketMean moonlets on average, a
+// bucket of up to kBucketLDS sorted in LDS by one block (larger ones in such chunks,
+// merged); at most kMaxBuckets buckets (more moonlets: the radix sort); the count and
+// scatter passes take kBucketTile moonlets per block
+constexpr int kBucketMean = 1792;
+constexpr int kBucketLDS = 4096;
+constexpr int kMaxBuckets = 3200;
+constexpr int kBucketTile = 2048;
 constexpr int kWalkBlock = 256;
 // persistent blocks: the gravity walk runs 1024 waves, the collision walk (less
 // work per item) 512; more only adds contention on the queue counters
@@ -115,6 +123,19 @@ struct DevState {
     int64_t p2p_src_max;
     // collisions: the largest R + dt |v| of any moonlet (bit pattern of a double >= 0)
     unsigned long long reach_max;
+    // bucket sort: the splitters the last bucket sort left for the next one are valid
+    // (bs_valid) for bs_n moonlets under root half-width bs_L (kept by the reset of a
+    // fresh build); the last sort took its buckets from them (bs_prev_used) and sorted
+    // bs_spill buckets too large for one LDS batch by merging
+    double bs_L;
+    int32_t bs_valid, bs_n;
+    int32_t bs_prev_used, bs_spill;
+};
+
+// a bucket boundary of the bucket sort: the (key, input index) pair that starts it
+struct SplitKey {
+    uint64_t k;
+    uint32_t i, pad;
 };
 
 // ---------------------------------------------------------------- mesh module
@@ -272,6 +293,14 @@ struct Workspace {
     // scratch for scans and sorts
     int32_t *scan_part = nullptr;                     // block partials
     uint32_t *hist = nullptr;                         // radix histograms
+    // bucket sort: this build's bucket boundaries, those for the next build (the keys
+    // at ranks j kBucketMean of this one), moonlets per (bucket, tile) (bucket-major,
+    // then their exclusive prefix over the tiles), moonlets per bucket, bucket starts
+    // (n_buckets + 1); sort_prev: a bucket sort on this binding wrote bs_prev (the
+    // device still checks n and the root cube)
+    SplitKey *bs_split = nullptr, *bs_prev = nullptr;
+    uint32_t *bs_cm = nullptr, *bs_total = nullptr, *bs_off = nullptr;
+    bool sort_prev = false;
     // batched calls: disk of each moonlet (input order; the sort keeps disks
     // contiguous, so it is also the disk of each tree position), per-disk max
     // |coordinate| and root half-width
@@ -321,6 +350,10 @@ hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                        const double *z, int64_t n, double root_half_width,
                        const int64_t *disk_off, hipStream_t s);
 hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s);
+// plain builds of up to kMaxBuckets buckets use the bucket sort (launch_keys then
+// writes where it starts)
+bool bucket_sort_applies(const Workspace &ws, int64_t n);
+hipError_t launch_bucket_sort(const Workspace &ws, int64_t n, hipStream_t s);
 hipError_t launch_gather_pos(const Workspace &ws, int64_t n, hipStream_t s);
 hipError_t launch_gather(const Workspace &ws, const double *src, double *dst, int64_t n,
                          hipStream_t s);

@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "ok", -1: "invalid", -2: "capacity", -3: "hip", -4: "unsuppor
 
 INFO_FIELDS = ("n", "ncells", "nleaves", "maxlevel", "m2l", "p2p", "visited", "col_cand",
                "col_tests", "m2l_dir", "p2p_inter", "m2l_maxlist", "p2p_maxlist", "nroots",
-               "long_m2l", "long_p2p", "walk_busy_max", "walk_busy_mean", "p2p_src_max")
+               "long_m2l", "long_p2p", "walk_busy_max", "walk_busy_mean", "p2p_src_max",
+               "sort_prev", "sort_spill")
 PHASES = ("keys", "sort", "tree", "gclimb", "gwalk", "m2l", "descent", "p2p", "l2p", "collide",
           "integrate")
 EXPORT = {"keys": 0, "perm": 1, "cells": 2, "gcells": 3, "ccells": 4, "multipoles": 5,
