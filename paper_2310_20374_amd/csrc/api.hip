@@ -336,9 +336,13 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
         const int64_t nbt = (n + kBucketTile - 1) / kBucketTile;
         ws.bs_split = (SplitKey *)take(sizeof(SplitKey) * nbk);
         ws.bs_prev = (SplitKey *)take(sizeof(SplitKey) * nbk);
+        const int64_t nsub = (n + kSubStride - 1) / kSubStride;
+        ws.bs_sub[0] = (SplitKey *)take(sizeof(SplitKey) * nsub);
+        ws.bs_sub[1] = (SplitKey *)take(sizeof(SplitKey) * nsub);
         ws.bs_cm = (uint32_t *)take(4 * nbk * nbt);
         ws.bs_total = (uint32_t *)take(4 * nbk);
         ws.bs_off = (uint32_t *)take(4 * (nbk + 1));
+        ws.bs_done = (uint32_t *)take(4 * nbk);
     }
     ws.seg = (uint16_t *)take(2 * n);
     ws.disk_max = (unsigned long long *)take(8 * (int64_t)kMaxDisks);

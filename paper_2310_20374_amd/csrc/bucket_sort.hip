@@ -121,7 +121,10 @@ k_bs_splitters(DevState *st, const uint64_t *__restrict__ keys, const uint32_t *
     __shared__ uint32_t cnt[kMaxBuckets];
     __shared__ int bad;
     const int tid = threadIdx.x;
-    if (tid == 0) st->bs_spill = 0;
+    if (tid == 0) {
+        st->bs_spill = 0;
+        st->bs_sub_rd = st->bs_sub_wr & 1;
+    }
     if (nb <= 1) {
         if (tid == 0) st->bs_prev_used = 0;
         return;
@@ -384,15 +387,233 @@ k_bs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
 }
 
 // ------------------------------------------------------------------ local sorts
-// LDS of a local sort: the pairs, per-wave digit counters, digit starts
+// sub-ranges of the one-pass local sort, and the most pairs it ranks by comparison
+// in one sub-range (more: the radix sort)
+constexpr int kSubBits = 11;
+constexpr int kSubs = 1 << kSubBits;
+constexpr int kSubLimit = 64;
+constexpr int kAuxWords = 2 * kSubs + 1 > kBsLocalWaves * 256 ? 2 * kSubs + 1 : kBsLocalWaves * 256;
+// finer boundaries per bucket (previous order)
+constexpr int kSubPer = kBucketMean / kSubStride;
+static_assert(kBucketMean % kSubStride == 0 && kSubPer <= 255, "finer boundaries of a bucket");
+
+// LDS of a local sort: the pairs; per-wave digit counters (radix sort) or sub-range
+// starts and cursors (one-pass sort); digit starts; reductions
 struct LocalLds {
     uint64_t k[kBucketLDS];
     uint32_t v[kBucketLDS];
-    uint32_t wcnt[kBsLocalWaves][256];
+    uint32_t aux[kAuxWords];
     uint32_t dstart[256];
     uint32_t wsum[kBsLocalWaves];
     uint64_t wmin[kBsLocalWaves], wmax[kBsLocalWaves];
+    int crowded;
 };
+
+// the fast local sort (previous order): threads per bucket, most pairs per bucket
+constexpr int kFastThreads = 256;
+constexpr int kFastCap = 2560;
+constexpr int kFastRounds = kFastCap / kFastThreads;
+
+// LDS of the fast local sort
+struct SubLds {
+    uint64_t k[kFastCap];
+    uint32_t v[kFastCap];
+    uint8_t sb[kFastCap];                    // sub-range of each placed pair
+    uint32_t start[kSubPer + 2], cur[kSubPer + 1];
+    uint64_t bk[kSubPer];                    // finer boundaries of the bucket
+    uint32_t bi[kSubPer];
+    uint32_t wsum[kFastThreads / kWave];
+    int crowded;
+};
+
+// Loads this block's pairs (size <= kBucketLDS, kBsLocalThreads threads, R rounds
+// per wave as in radix_sort_local) and the smallest and largest key.
+__device__ __forceinline__ void load_local(const uint64_t *kin, const uint32_t *vin, int size,
+                                           uint64_t *key, uint32_t *val, bool *valid,
+                                           uint64_t &kmin, uint64_t &kmax, LocalLds &L) {
+    const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+    const int R = (size + kBsLocalThreads - 1) / kBsLocalThreads;
+    const int wbase = w * R * kWave;
+    kmin = ~0ull;
+    kmax = 0;
+#pragma unroll
+    for (int r = 0; r < kBsRounds; r++) {
+        const int p = wbase + r * kWave + lane;
+        valid[r] = r < R && p < size;
+        key[r] = 0;
+        val[r] = 0;
+        if (valid[r]) {
+            key[r] = kin[p];
+            val[r] = vin[p];
+            kmin = key[r] < kmin ? key[r] : kmin;
+            kmax = key[r] > kmax ? key[r] : kmax;
+        }
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint64_t a = ((uint64_t)__shfl_xor((uint32_t)(kmin >> 32), o) << 32) |
+                           __shfl_xor((uint32_t)kmin, o);
+        const uint64_t b = ((uint64_t)__shfl_xor((uint32_t)(kmax >> 32), o) << 32) |
+                           __shfl_xor((uint32_t)kmax, o);
+        kmin = a < kmin ? a : kmin;
+        kmax = b > kmax ? b : kmax;
+    }
+    if (lane == 0) {
+        L.wmin[w] = kmin;
+        L.wmax[w] = kmax;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kBsLocalWaves; k++) {
+        kmin = L.wmin[k] < kmin ? L.wmin[k] : kmin;
+        kmax = L.wmax[k] > kmax ? L.wmax[k] : kmax;
+    }
+}
+
+// Local sort on the previous build's order: the keys it had at every kSubStride-th
+// rank of this bucket (subs[0..nsub), subs[0] the bucket's own start) split the
+// bucket into nsub sub-ranges of about kSubStride pairs; each pair finds its
+// sub-range by binary search, sub-ranges get slots (counts, exclusive scan, atomics
+// in any order), and a pair's place in its sub-range is the number of pairs of that
+// sub-range below it by (key, index).  Writes (kout, vout) and returns true, or
+// writes nothing and returns false when some sub-range holds more than kSubLimit
+// pairs (moonlets moved far).
+__device__ __forceinline__ bool subsplit_sort_local(const uint64_t *kin, const uint32_t *vin,
+                                                    int size, const SplitKey *subs, int nsub,
+                                                    uint64_t *kout, uint32_t *vout, SubLds &L) {
+    const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+    const int R = (size + kFastThreads - 1) / kFastThreads;
+    const int wbase = w * R * kWave;
+    const int m = nsub - 1;                  // inner boundaries subs[1..nsub)
+    uint32_t *start = L.start;               // m + 2
+    uint32_t *cur = L.cur;                   // m + 1
+    for (int q = t; q < m; q += kFastThreads) {
+        L.bk[q] = subs[q + 1].k;
+        L.bi[q] = subs[q + 1].i;
+    }
+    for (int q = t; q <= m; q += kFastThreads) start[q] = 0;
+    if (t == 0) L.crowded = 0;
+    uint64_t key[kFastRounds];
+    uint32_t val[kFastRounds];
+    bool valid[kFastRounds];
+    int sb[kFastRounds];
+#pragma unroll
+    for (int r = 0; r < kFastRounds; r++) {
+        const int p = wbase + r * kWave + lane;
+        valid[r] = r < R && p < size;
+        key[r] = 0;
+        val[r] = 0;
+        sb[r] = 0;
+        if (valid[r]) {
+            key[r] = kin[p];
+            val[r] = vin[p];
+        }
+    }
+    __syncthreads();
+    int top = 1;
+    while (top * 2 <= m) top *= 2;
+    for (int step = m > 0 ? top : 0; step > 0; step >>= 1) {
+#pragma unroll
+        for (int r = 0; r < kFastRounds; r++) {
+            const int c = sb[r] + step;
+            if (c <= m && !pair_less(key[r], val[r], L.bk[c - 1], L.bi[c - 1])) sb[r] = c;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kFastRounds; r++)
+        if (valid[r]) atomicAdd(&start[sb[r]], 1u);
+    __syncthreads();
+    const uint32_t c = t <= m ? start[t] : 0u;
+    if (c > (uint32_t)kSubLimit) L.crowded = 1;
+    uint32_t tot;
+    const uint32_t ex = block_scan<kFastThreads>(c, L.wsum, &tot);
+    if (t <= m) {
+        start[t] = ex;
+        cur[t] = ex;
+    }
+    if (t == 0) start[m + 1] = (uint32_t)size;
+    __syncthreads();
+    if (L.crowded) return false;
+#pragma unroll
+    for (int r = 0; r < kFastRounds; r++)
+        if (valid[r]) {
+            const uint32_t slot = atomicAdd(&cur[sb[r]], 1u);
+            L.k[slot] = key[r];
+            L.v[slot] = val[r];
+            L.sb[slot] = (uint8_t)sb[r];
+        }
+    __syncthreads();
+    for (int j = t; j < size; j += kFastThreads) {
+        const uint64_t kj = L.k[j];
+        const uint32_t vj = L.v[j];
+        const int q = L.sb[j];
+        const int s0 = (int)start[q], s1 = (int)start[q + 1];
+        int rank = 0;
+        for (int u = s0; u < s1; u++) rank += pair_less(L.k[u], L.v[u], kj, vj) ? 1 : 0;
+        kout[s0 + rank] = kj;
+        vout[s0 + rank] = vj;
+    }
+    return true;
+}
+
+// One-pass local sort: the pairs go to 2^kSubBits sub-ranges by the top bits of
+// key - min (counts, exclusive scan, slots claimed by atomics in any order); each
+// pair's place in its sub-range is then the number of pairs of that sub-range below
+// it by (key, index).  Writes (kout, vout) and returns true, or writes nothing and
+// returns false when some sub-range holds more than kSubLimit pairs.
+__device__ __forceinline__ bool onepass_sort_local(const uint64_t *kin, const uint32_t *vin,
+                                                   int size, uint64_t *kout, uint32_t *vout,
+                                                   LocalLds &L) {
+    const int t = threadIdx.x;
+    uint64_t key[kBsRounds];
+    uint32_t val[kBsRounds];
+    bool valid[kBsRounds];
+    uint64_t kmin, kmax;
+    load_local(kin, vin, size, key, val, valid, kmin, kmax, L);
+    const uint64_t span = kmax - kmin;
+    const int nbits = span ? 64 - __clzll((long long)span) : 0;
+    const int sh = nbits > kSubBits ? nbits - kSubBits : 0;
+    uint32_t *start = L.aux;                 // kSubs + 1
+    uint32_t *cur = L.aux + kSubs + 1;       // kSubs
+    for (int i = t; i < kSubs; i += kBsLocalThreads) start[i] = 0;
+    if (t == 0) L.crowded = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kBsRounds; r++)
+        if (valid[r]) atomicAdd(&start[(uint32_t)((key[r] - kmin) >> sh)], 1u);
+    __syncthreads();
+    static_assert(kSubs == 2 * kBsLocalThreads, "two sub-ranges per thread");
+    const uint32_t c0 = start[2 * t], c1 = start[2 * t + 1];
+    if (c0 > (uint32_t)kSubLimit || c1 > (uint32_t)kSubLimit) L.crowded = 1;
+    uint32_t tot;
+    const uint32_t ex = block_scan<kBsLocalThreads>(c0 + c1, L.wsum, &tot);
+    start[2 * t] = ex;
+    start[2 * t + 1] = ex + c0;
+    cur[2 * t] = ex;
+    cur[2 * t + 1] = ex + c0;
+    if (t == 0) start[kSubs] = (uint32_t)size;
+    __syncthreads();
+    if (L.crowded) return false;
+#pragma unroll
+    for (int r = 0; r < kBsRounds; r++)
+        if (valid[r]) {
+            const uint32_t slot = atomicAdd(&cur[(uint32_t)((key[r] - kmin) >> sh)], 1u);
+            L.k[slot] = key[r];
+            L.v[slot] = val[r];
+        }
+    __syncthreads();
+    for (int j = t; j < size; j += kBsLocalThreads) {
+        const uint64_t kj = L.k[j];
+        const uint32_t vj = L.v[j];
+        const uint32_t sb = (uint32_t)((kj - kmin) >> sh);
+        const int s0 = (int)start[sb], s1 = (int)start[sb + 1];
+        int rank = 0;
+        for (int q = s0; q < s1; q++) rank += pair_less(L.k[q], L.v[q], kj, vj) ? 1 : 0;
+        kout[s0 + rank] = kj;
+        vout[s0 + rank] = vj;
+    }
+    return true;
+}
 
 // lanes of this wave whose 8-bit digit equals d (among the active ones)
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t act) {
@@ -423,40 +644,8 @@ __device__ __forceinline__ void radix_sort_local(const uint64_t *kin, const uint
     uint64_t key[kBsRounds];
     uint32_t val[kBsRounds];
     bool valid[kBsRounds];
-    uint64_t kmin = ~0ull, kmax = 0;
-#pragma unroll
-    for (int r = 0; r < kBsRounds; r++) {
-        const int p = wbase + r * kWave + lane;
-        valid[r] = r < R && p < size;
-        key[r] = 0;
-        val[r] = 0;
-        if (valid[r]) {
-            key[r] = kin[p];
-            val[r] = vin[p];
-            kmin = key[r] < kmin ? key[r] : kmin;
-            kmax = key[r] > kmax ? key[r] : kmax;
-        }
-    }
-    // the keys' range: the pass digits are those of key - min
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        const uint64_t a = ((uint64_t)__shfl_xor((uint32_t)(kmin >> 32), o) << 32) |
-                           __shfl_xor((uint32_t)kmin, o);
-        const uint64_t b = ((uint64_t)__shfl_xor((uint32_t)(kmax >> 32), o) << 32) |
-                           __shfl_xor((uint32_t)kmax, o);
-        kmin = a < kmin ? a : kmin;
-        kmax = b > kmax ? b : kmax;
-    }
-    if (lane == 0) {
-        L.wmin[w] = kmin;
-        L.wmax[w] = kmax;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kBsLocalWaves; k++) {
-        kmin = L.wmin[k] < kmin ? L.wmin[k] : kmin;
-        kmax = L.wmax[k] > kmax ? L.wmax[k] : kmax;
-    }
+    uint64_t kmin, kmax;
+    load_local(kin, vin, size, key, val, valid, kmin, kmax, L);
     const uint64_t span = kmax - kmin;
     const int nbits = span ? 64 - __clzll((long long)span) : 0;
     const int passes = (nbits + 7) / 8;
@@ -466,7 +655,7 @@ __device__ __forceinline__ void radix_sort_local(const uint64_t *kin, const uint
         const int shift = 8 * pass;
         if (t < 256)
 #pragma unroll
-            for (int k = 0; k < kBsLocalWaves; k++) L.wcnt[k][t] = 0;
+            for (int k = 0; k < kBsLocalWaves; k++) L.aux[k * 256 + t] = 0;
         __syncthreads();
         uint64_t peers[kBsRounds];
 #pragma unroll
@@ -477,7 +666,7 @@ __device__ __forceinline__ void radix_sort_local(const uint64_t *kin, const uint
                 const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
                 peers[r] = digit_peers(d, act);
                 if (valid[r] && (peers[r] & lt) == 0ull)
-                    atomicAdd(&L.wcnt[w][d], (uint32_t)__popcll(peers[r]));
+                    atomicAdd(&L.aux[w * 256 + d], (uint32_t)__popcll(peers[r]));
             }
         }
         __syncthreads();
@@ -487,8 +676,8 @@ __device__ __forceinline__ void radix_sort_local(const uint64_t *kin, const uint
         if (t < 256)
 #pragma unroll
             for (int k = 0; k < kBsLocalWaves; k++) {
-                const uint32_t c = L.wcnt[k][t];
-                L.wcnt[k][t] = run;
+                const uint32_t c = L.aux[k * 256 + t];
+                L.aux[k * 256 + t] = run;
                 run += c;
             }
         uint32_t tot;
@@ -500,12 +689,12 @@ __device__ __forceinline__ void radix_sort_local(const uint64_t *kin, const uint
             if (valid[r]) {
                 const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
                 const uint64_t lower = peers[r] & lt;
-                const uint32_t before = L.wcnt[w][d];
+                const uint32_t before = L.aux[w * 256 + d];
                 const uint32_t pos = L.dstart[d] + before + (uint32_t)__popcll(lower);
                 L.k[pos] = key[r];
                 L.v[pos] = val[r];
                 __builtin_amdgcn_wave_barrier();
-                if (lower == 0ull) L.wcnt[w][d] = before + (uint32_t)__popcll(peers[r]);
+                if (lower == 0ull) L.aux[w * 256 + d] = before + (uint32_t)__popcll(peers[r]);
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -545,40 +734,94 @@ __device__ __forceinline__ int count_below(const uint64_t *ka, const uint32_t *i
     return lo - lo0;
 }
 
-// One block per bucket.  A bucket of at most kBucketLDS pairs is sorted in LDS; a
-// larger one in kBucketLDS batches (written to the alternate buffers), then merged
-// pairwise in global memory until one run remains.  The block also stores the pairs
-// at ranks j kBucketMean (1 <= j < nb) that fall in its bucket: the next build's
-// boundaries.  LDS: LocalLds (dynamic).
-// (at most 64 registers: two blocks per compute unit)
-__global__ void __launch_bounds__(kBsLocalThreads, 8)
-k_bs_local(DevState *st, const uint32_t *__restrict__ off, int nb, int n,
-           uint64_t *__restrict__ keys, uint32_t *__restrict__ idx, uint64_t *__restrict__ kalt,
-           uint32_t *__restrict__ ialt, SplitKey *__restrict__ next) {
+// The next build's boundaries from this sorted bucket [o, o + size): the pairs at
+// ranks j kBucketMean (1 <= j < nb) and at ranks k kSubStride.
+template <int NT>
+__device__ __forceinline__ void write_boundaries(const uint64_t *keys, const uint32_t *idx, int o,
+                                                 int size, int nb, SplitKey *next,
+                                                 SplitKey *subn) {
+    const int tid = threadIdx.x;
+    const int j0 = (o + kBucketMean - 1) / kBucketMean > 1 ? (o + kBucketMean - 1) / kBucketMean : 1;
+    for (int j = j0 + tid; j < nb && j * kBucketMean < o + size; j += NT) {
+        const int p = j * kBucketMean;
+        SplitKey v;
+        v.k = keys[p];
+        v.i = idx[p];
+        v.pad = 0;
+        next[j - 1] = v;
+    }
+    const int q0 = (o + kSubStride - 1) / kSubStride;
+    for (int q = q0 + tid; q * kSubStride < o + size; q += NT) {
+        const int p = q * kSubStride;
+        SplitKey v;
+        v.k = keys[p];
+        v.i = idx[p];
+        v.pad = 0;
+        subn[q] = v;
+    }
+}
+
+// Fast local sorts: one block per bucket, for buckets taken from the previous
+// order and of at most kFastCap pairs (sub-split sort); a bucket it sorts is marked
+// done, with its share of the next build's boundaries written.
+__global__ void __launch_bounds__(kFastThreads)
+k_bs_fast(const DevState *st, const uint32_t *__restrict__ off, int nb, int n,
+          uint64_t *__restrict__ keys, uint32_t *__restrict__ idx, SplitKey *__restrict__ next,
+          const SplitKey *sub0, const SplitKey *sub1, SplitKey *nsub0, SplitKey *nsub1,
+          uint32_t *__restrict__ done) {
+    static_assert(kSubPer < kFastThreads, "one sub-range count per thread");
+    __shared__ SubLds L;
+    const int b = blockIdx.x;
+    const int o = (int)off[b];
+    const int size = (int)off[b + 1] - o;
+    bool ok = false;
+    if (st->bs_prev_used && size > 0 && size <= kFastCap) {
+        const SplitKey *subs = st->bs_sub_rd ? sub1 : sub0;
+        const int ntot = (n + kSubStride - 1) / kSubStride;
+        const int nsub = ntot - b * kSubPer < kSubPer ? ntot - b * kSubPer : kSubPer;
+        ok = subsplit_sort_local(keys + o, idx + o, size, subs + (int64_t)b * kSubPer, nsub,
+                                 keys + o, idx + o, L);
+    }
+    if (ok) {
+        __threadfence_block();
+        __syncthreads();
+        write_boundaries<kFastThreads>(keys, idx, o, size, nb, next,
+                                       st->bs_sub_rd ? nsub0 : nsub1);
+    }
+    if (threadIdx.x == 0) done[b] = ok || size <= 0 ? 1u : 0u;
+}
+
+// The other buckets, one block each: at most kBucketLDS pairs sorted in LDS (one pass
+// over sub-ranges of the key range, or the radix sort where a sub-range is
+// crowded); a larger one in kBucketLDS batches (written to the alternate buffers),
+// then merged pairwise in global memory until one run remains.  The block also
+// stores its share of the next build's boundaries.  LDS: LocalLds (dynamic).
+__global__ void __launch_bounds__(kBsLocalThreads)
+k_bs_slow(DevState *st, const uint32_t *__restrict__ off, int nb, int n,
+          uint64_t *__restrict__ keys, uint32_t *__restrict__ idx, uint64_t *__restrict__ kalt,
+          uint32_t *__restrict__ ialt, SplitKey *__restrict__ next, SplitKey *sub0,
+          SplitKey *sub1, const uint32_t *__restrict__ done) {
     extern __shared__ __align__(16) unsigned char smem[];
     LocalLds &L = *reinterpret_cast<LocalLds *>(smem);
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
-    const int o = (int)off[b];
-    const int size = (int)off[b + 1] - o;
+    const int rd = st->bs_sub_rd;
+    SplitKey *subn = rd ? sub0 : sub1;
     if (b == 0 && tid == 0) {
         st->bs_valid = 1;
         st->bs_n = n;
         st->bs_L = st->L;
+        st->bs_sub_wr = 1 - rd;
     }
-    if (size <= 0) return;
-    // ranks j kBucketMean inside this bucket
-    const int j0 = (o + kBucketMean - 1) / kBucketMean > 1 ? (o + kBucketMean - 1) / kBucketMean : 1;
+    if (done[b]) return;
+    const int o = (int)off[b];
+    const int size = (int)off[b + 1] - o;
     if (size <= kBucketLDS) {
-        radix_sort_local(keys + o, idx + o, size, keys + o, idx + o, L);
-        for (int j = j0 + tid; j < nb && j * kBucketMean < o + size; j += kBsLocalThreads) {
-            const int p = j * kBucketMean - o;
-            SplitKey v;
-            v.k = L.k[p];
-            v.i = L.v[p];
-            v.pad = 0;
-            next[j - 1] = v;
-        }
+        if (!onepass_sort_local(keys + o, idx + o, size, keys + o, idx + o, L))
+            radix_sort_local(keys + o, idx + o, size, keys + o, idx + o, L);
+        __threadfence_block();
+        __syncthreads();
+        write_boundaries<kBsLocalThreads>(keys, idx, o, size, nb, next, subn);
         return;
     }
     // batches of kBucketLDS, sorted, into the alternate buffers
@@ -618,14 +861,7 @@ k_bs_local(DevState *st, const uint32_t *__restrict__ off, int nb, int n,
         __threadfence_block();
         __syncthreads();
     }
-    for (int j = j0 + tid; j < nb && j * kBucketMean < o + size; j += kBsLocalThreads) {
-        const int p = j * kBucketMean;
-        SplitKey v;
-        v.k = keys[p];
-        v.i = idx[p];
-        v.pad = 0;
-        next[j - 1] = v;
-    }
+    write_boundaries<kBsLocalThreads>(keys, idx, o, size, nb, next, subn);
 }
 
 // ------------------------------------------------------------------ host side
@@ -647,9 +883,13 @@ hipError_t launch_bucket_sort(const Workspace &ws, int64_t n, hipStream_t s) {
     k_bs_scatter<<<ntiles, kBsThreads, (size_t)nb * 4 * (2 + kBsWaves), s>>>(
         ws.keys_alt, ws.idx_alt, ws.code, (int)n, nb, ntiles, ws.bs_cm, ws.bs_total, ws.bs_off,
         ws.keys, ws.idx);
-    k_bs_local<<<nb, kBsLocalThreads, sizeof(LocalLds), s>>>(ws.st, ws.bs_off, nb, (int)n, ws.keys,
-                                                        ws.idx, ws.keys_alt, ws.idx_alt,
-                                                        ws.bs_prev);
+    k_bs_fast<<<nb, kFastThreads, 0, s>>>(ws.st, ws.bs_off, nb, (int)n, ws.keys, ws.idx,
+                                          ws.bs_prev, ws.bs_sub[0], ws.bs_sub[1], ws.bs_sub[0],
+                                          ws.bs_sub[1], ws.bs_done);
+    k_bs_slow<<<nb, kBsLocalThreads, sizeof(LocalLds), s>>>(ws.st, ws.bs_off, nb, (int)n, ws.keys,
+                                                       ws.idx, ws.keys_alt, ws.idx_alt,
+                                                       ws.bs_prev, ws.bs_sub[0], ws.bs_sub[1],
+                                                       ws.bs_done);
     return hipGetLastError();
 }
 

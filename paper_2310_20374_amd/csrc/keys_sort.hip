@@ -12,6 +12,7 @@ __global__ void k_reset_state(DevState *st) {
         z.bs_L = st->bs_L;
         z.bs_valid = st->bs_valid;
         z.bs_n = st->bs_n;
+        z.bs_sub_wr = st->bs_sub_wr;
         *st = z;
     }
 }

@@ -56,6 +56,8 @@ constexpr int kBucketMean = 1792;
 constexpr int kBucketLDS = 4096;
 constexpr int kMaxBuckets = 3200;
 constexpr int kBucketTile = 2048;
+// the previous build's keys at every kSubStride-th rank split each bucket again
+constexpr int kSubStride = 8;
 constexpr int kWalkBlock = 256;
 // persistent blocks: the gravity walk runs 1024 waves, the collision walk (less
 // work per item) 512; more only adds contention on the queue counters
@@ -130,6 +132,9 @@ struct DevState {
     double bs_L;
     int32_t bs_valid, bs_n;
     int32_t bs_prev_used, bs_spill;
+    // which of the two sub-boundary buffers the last sort wrote (kept like bs_valid),
+    // and which this sort reads
+    int32_t bs_sub_wr, bs_sub_rd;
 };
 
 // a bucket boundary of the bucket sort: the (key, input index) pair that starts it
@@ -294,12 +299,16 @@ struct Workspace {
     int32_t *scan_part = nullptr;                     // block partials
     uint32_t *hist = nullptr;                         // radix histograms
     // bucket sort: this build's bucket boundaries, those for the next build (the keys
-    // at ranks j kBucketMean of this one), moonlets per (bucket, tile) (bucket-major,
+    // at ranks j kBucketMean of this one), the finer boundaries (keys at ranks
+    // k kSubStride, one buffer read while the other is written), moonlets per
+    // (bucket, tile) (bucket-major,
     // then their exclusive prefix over the tiles), moonlets per bucket, bucket starts
     // (n_buckets + 1); sort_prev: a bucket sort on this binding wrote bs_prev (the
     // device still checks n and the root cube)
     SplitKey *bs_split = nullptr, *bs_prev = nullptr;
+    SplitKey *bs_sub[2] = {nullptr, nullptr};         // keys at ranks k kSubStride
     uint32_t *bs_cm = nullptr, *bs_total = nullptr, *bs_off = nullptr;
+    uint32_t *bs_done = nullptr;                      // bucket sorted by the fast pass
     bool sort_prev = false;
     // batched calls: disk of each moonlet (input order; the sort keeps disks
     // contiguous, so it is also the disk of each tree position), per-disk max
