@@ -431,26 +431,43 @@ hipError_t launch_collide_reset(const Workspace &ws, hipStream_t s) {
     return hipGetLastError();
 }
 
-// rank sort of the (distinct) pair keys: rank = number of smaller keys
-__global__ void __launch_bounds__(256)
+// Rank sort of the (distinct) pair keys: rank = number of smaller keys.  One wave per
+// 64 keys (a lane each); the wave walks the whole list in chunks of 256 keys, loaded
+// coalesced (the next chunk while the current one is compared) and read back from
+// LDS as wave-wide broadcasts.
+constexpr int kRankGrid = 2048;
+constexpr int kRankChunk = 4 * kWave;
+__global__ void __launch_bounds__(kWave)
 k_rank_pairs(const DevState *__restrict__ st, const int64_t *__restrict__ in, int64_t cap,
              int64_t *__restrict__ out) {
-    __shared__ int64_t tile[1024];
+    __shared__ int64_t tile[kRankChunk];
     int64_t n = st->npairs;
     if (n > cap) n = cap;
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
-        const int64_t i = base + threadIdx.x;
-        const int64_t v = i < n ? in[i] : 0;
-        int64_t r = 0;
-        for (int64_t t0 = 0; t0 < n; t0 += 1024) {
-            __syncthreads();
-            for (int k = threadIdx.x; k < 1024; k += 256)
-                tile[k] = t0 + k < n ? in[t0 + k] : INT64_MAX;
-            __syncthreads();
-            const int lim = n - t0 < 1024 ? (int)(n - t0) : 1024;
-            for (int k = 0; k < lim; k++) r += tile[k] < v;
+    const int lane = threadIdx.x;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
+        const int64_t i = base + lane;
+        const int64_t v = i < n ? in[i] : INT64_MAX;
+        int64_t r0 = 0, r1 = 0;
+        int64_t nxt[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) nxt[u] = u * kWave + lane < n ? in[u * kWave + lane] : INT64_MAX;
+        for (int64_t t0 = 0; t0 < n; t0 += kRankChunk) {
+            wave_sync();
+#pragma unroll
+            for (int u = 0; u < 4; u++) tile[u * kWave + lane] = nxt[u];
+            wave_sync();
+            const int64_t t1 = t0 + kRankChunk;
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                nxt[u] = t1 + u * kWave + lane < n ? in[t1 + u * kWave + lane] : INT64_MAX;
+            // padding keys (INT64_MAX) are never below a real key
+#pragma unroll 8
+            for (int k = 0; k < kRankChunk; k += 2) {
+                r0 += tile[k] < v;
+                r1 += tile[k + 1] < v;
+            }
         }
-        if (i < n) out[r] = v;
+        if (i < n) out[r0 + r1] = v;
     }
 }
 
@@ -807,6 +824,7 @@ hipError_t launch_candidates_from_lists(const Workspace &ws, hipStream_t s) {
 // is the earliest live pair of both its moonlets (the earliest live pair of all is
 // always one, so every round makes progress) and dropping the live pairs that
 // touch a moonlet just matched -- the same set as taking the pairs one by one.
+// Each round visits only the pairs still live.
 // The pair list is sorted by (i, j), so its index breaks ties of dt_c.
 __device__ __forceinline__ bool earlier(const double *dtc, int p, int q) {
     return dtc[p] < dtc[q] || (dtc[p] == dtc[q] && p < q);
@@ -822,29 +840,57 @@ __device__ __forceinline__ void keep_earliest(int32_t *slot, int p, const double
 }
 
 constexpr int kResolveThreads = 1024;
+constexpr int kResolveGrid = 512;      // blocks of the per-pair passes
 
-__global__ void __launch_bounds__(kResolveThreads)
-k_resolve(DevState *st, const int64_t *__restrict__ keys, int64_t pair_cap, double *x,
-          double *y, double *z, double *vx, double *vy, double *vz,
-          const double *__restrict__ m, const double *__restrict__ R, double dt, double f,
-          double *dtc, int32_t *flag, int32_t *mbest, int32_t *mmatch, int64_t *pairs,
-          int64_t cap, int64_t *n_pairs_dev, int step, int64_t *cursor) {
-    __shared__ int wsum[kResolveThreads / kWave];
-    __shared__ int64_t s_run, s_base;
-    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
-    const int T = blockDim.x;
-    int64_t np = st->npairs;
-    if (np > pair_cap) {                  // the list is incomplete: resolve nothing
-        if (tid == 0) {
-            atomicOr(&st->status, (int32_t)ST_CAP_PAIRS);
-            atomicMax((unsigned long long *)&st->required, (unsigned long long)np);
-        }
-        np = 0;
+// exclusive prefix of v >= 0 over the block (wsum: one word per wave), and the
+// block's total
+__device__ __forceinline__ int block_int_prefix(int v, int *wsum, int *total) {
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
-    if (st->status & kSkipMask) np = 0;
-    // flag: 0 dropped, 1 live, 2 resolved
-    for (int64_t p = tid; p < np; p += T) {
-        const int i = (int)(keys[p] >> 32), j = (int)(keys[p] & 0xffffffffll);
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int k = 0; k < (int)blockDim.x / kWave; k++) {
+        if (k < w) before += wsum[k];
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+}
+
+__device__ __forceinline__ int pair_i(int64_t key) { return (int)(key >> 32); }
+__device__ __forceinline__ int pair_j(int64_t key) { return (int)(key & 0xffffffffll); }
+
+// pairs per thread and pass of the one-block rounds
+constexpr int kResolveUnroll = 4;
+
+// number of pairs the resolution takes: 0 when the list overflowed (the status then
+// says so) or an earlier pass failed
+__device__ __forceinline__ int resolve_count(const DevState *st, int64_t pair_cap) {
+    const int64_t np = st->npairs;
+    if (np > pair_cap || (st->status & kSkipMask)) return 0;
+    return (int)np;                       // pair indices are 32-bit (the capacity is)
+}
+
+// Contact time of every pair found (Eq. 2) and the per-moonlet state of the rounds;
+// spread over the whole GPU (the loads are scattered over the moonlet arrays).
+__global__ void __launch_bounds__(256)
+k_resolve_init(const DevState *__restrict__ st, const int64_t *__restrict__ keys,
+               int64_t pair_cap, const double *__restrict__ x, const double *__restrict__ y,
+               const double *__restrict__ z, const double *__restrict__ vx,
+               const double *__restrict__ vy, const double *__restrict__ vz,
+               const double *__restrict__ R, double dt, double *__restrict__ dtc,
+               int32_t *__restrict__ flag, int32_t *__restrict__ mmatch) {
+    const int np = resolve_count(st, pair_cap);
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+        const int64_t k = keys[p];
+        const int i = pair_i(k), j = pair_j(k);
         const double t = contact_time(x[i], y[i], z[i], vx[i], vy[i], vz[i], R[i], x[j], y[j],
                                       z[j], vx[j], vy[j], vz[j], R[j], dt);
         dtc[p] = t;
@@ -852,43 +898,168 @@ k_resolve(DevState *st, const int64_t *__restrict__ keys, int64_t pair_cap, doub
         mmatch[i] = 0;
         mmatch[j] = 0;
     }
+}
+
+// The rounds of the matching and the list of resolved pairs, one block.
+__global__ void __launch_bounds__(kResolveThreads)
+k_resolve(DevState *st, const int64_t *__restrict__ keys, int64_t pair_cap,
+          const double *__restrict__ dtc, int32_t *flag, int32_t *mbest, int32_t *mmatch,
+          int32_t *live, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
+          int64_t *cursor) {
+    constexpr int U = kResolveUnroll;
+    __shared__ int wsum[kResolveThreads / kWave];
+    const int tid = threadIdx.x;
+    const int T = blockDim.x;
+    if (st->npairs > pair_cap && !(st->status & kSkipMask) && tid == 0) {
+        // the list is incomplete: nothing is resolved
+        atomicOr(&st->status, (int32_t)ST_CAP_PAIRS);
+        atomicMax((unsigned long long *)&st->required, (unsigned long long)st->npairs);
+    }
+    const int np = resolve_count(st, pair_cap);
+    // flag: 0 dropped, 1 live, 2 resolved; the live pairs' indices are kept compacted
+    // in `live`, so later rounds visit only what is left
+    int nlive = 0;
+    for (int c0 = 0; c0 < np; c0 += U * T) {
+        int cnt = 0;
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int p = c0 + U * tid + u;
+            ok[u] = p < np && flag[p] == 1;
+            cnt += ok[u] ? 1 : 0;
+        }
+        int tot;
+        int o = nlive + block_int_prefix(cnt, wsum, &tot);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (ok[u]) live[o++] = c0 + U * tid + u;
+        nlive += tot;
+    }
     __syncthreads();
-    for (int64_t round = 0; round <= np; round++) {
-        for (int64_t p = tid; p < np; p += T)
-            if (flag[p] == 1) {
-                mbest[(int)(keys[p] >> 32)] = -1;
-                mbest[(int)(keys[p] & 0xffffffffll)] = -1;
-            }
-        __syncthreads();
-        for (int64_t p = tid; p < np; p += T)
-            if (flag[p] == 1) {
-                keep_earliest(&mbest[(int)(keys[p] >> 32)], (int)p, dtc);
-                keep_earliest(&mbest[(int)(keys[p] & 0xffffffffll)], (int)p, dtc);
-            }
-        __syncthreads();
-        for (int64_t p = tid; p < np; p += T)
-            if (flag[p] == 1) {
-                const int i = (int)(keys[p] >> 32), j = (int)(keys[p] & 0xffffffffll);
-                if (mbest[i] == (int)p && mbest[j] == (int)p) {
-                    flag[p] = 2;
-                    mmatch[i] = 1;
-                    mmatch[j] = 1;
+    while (nlive > 0) {
+        for (int c0 = 0; c0 < nlive; c0 += U * T)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int q = c0 + u * T + tid;
+                if (q < nlive) {
+                    const int64_t k = keys[live[q]];
+                    mbest[pair_i(k)] = -1;
+                    mbest[pair_j(k)] = -1;
                 }
             }
         __syncthreads();
-        int live = 0;
-        for (int64_t p = tid; p < np; p += T)
-            if (flag[p] == 1) {
-                const int i = (int)(keys[p] >> 32), j = (int)(keys[p] & 0xffffffffll);
-                if (mmatch[i] || mmatch[j]) flag[p] = 0;
-                else live = 1;
+        for (int c0 = 0; c0 < nlive; c0 += U * T)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int q = c0 + u * T + tid;
+                if (q < nlive) {
+                    const int p = live[q];
+                    const int64_t k = keys[p];
+                    keep_earliest(&mbest[pair_i(k)], p, dtc);
+                    keep_earliest(&mbest[pair_j(k)], p, dtc);
+                }
             }
-        if (!__syncthreads_or(live)) break;
+        __syncthreads();
+        for (int c0 = 0; c0 < nlive; c0 += U * T)
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int q = c0 + u * T + tid;
+                if (q < nlive) {
+                    const int p = live[q];
+                    const int64_t k = keys[p];
+                    const int i = pair_i(k), j = pair_j(k);
+                    if (mbest[i] == p && mbest[j] == p) {
+                        flag[p] = 2;
+                        mmatch[i] = 1;
+                        mmatch[j] = 1;
+                    }
+                }
+            }
+        __syncthreads();
+        // drop what touches a moonlet just matched; compact the rest in place (a pass
+        // reads all its entries before any is written, and writes only below them)
+        int kept = 0;
+        for (int c0 = 0; c0 < nlive; c0 += U * T) {
+            bool keep[U];
+            int pv[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int q = c0 + u * T + tid;
+                keep[u] = false;
+                pv[u] = 0;
+                if (q < nlive) {
+                    pv[u] = live[q];
+                    if (flag[pv[u]] == 1) {
+                        const int64_t k = keys[pv[u]];
+                        if (mmatch[pair_i(k)] || mmatch[pair_j(k)]) flag[pv[u]] = 0;
+                        else keep[u] = true;
+                    }
+                }
+            }
+            int cnt = 0;
+#pragma unroll
+            for (int u = 0; u < U; u++) cnt += keep[u] ? 1 : 0;
+            int tot;
+            int o = kept + block_int_prefix(cnt, wsum, &tot);
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (keep[u]) live[o++] = pv[u];
+            kept += tot;
+        }
+        nlive = kept;
+        __syncthreads();
     }
-    // impulses of the resolved pairs (disjoint moonlets): 1 = i, 2 = j
-    for (int64_t p = tid; p < np; p += T) {
+    // the resolved pairs, in (i, j) order, as (step, i, j) after the earlier steps';
+    // a thread takes U consecutive pairs per pass
+    const int64_t base = *cursor;
+    int64_t run = 0;
+    for (int c0 = 0; c0 < np; c0 += U * T) {
+        bool acc[U];
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int p = c0 + U * tid + u;
+            acc[u] = p < np && flag[p] == 2;
+            cnt += acc[u] ? 1 : 0;
+        }
+        int tot;
+        int64_t o = base + run + block_int_prefix(cnt, wsum, &tot);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (acc[u]) {
+                const int p = c0 + U * tid + u;
+                if (o < cap) {
+                    pairs[3 * o] = step;
+                    pairs[3 * o + 1] = keys[p] >> 32;
+                    pairs[3 * o + 2] = keys[p] & 0xffffffffll;
+                }
+                o++;
+            }
+        run += tot;
+    }
+    if (tid == 0) {
+        *n_pairs_dev = run;
+        if (base + run > cap) {
+            atomicOr(&st->status, (int32_t)ST_CAP_PAIRS);
+            atomicMax((unsigned long long *)&st->required, (unsigned long long)(base + run));
+        }
+        *cursor = base + run;
+    }
+}
+
+// Impulses of the resolved pairs (disjoint moonlets: 1 = i, 2 = j), over the whole GPU.
+__global__ void __launch_bounds__(256)
+k_resolve_apply(const DevState *__restrict__ st, const int64_t *__restrict__ keys,
+                int64_t pair_cap, const int32_t *__restrict__ flag,
+                const double *__restrict__ dtc, double *__restrict__ x,
+                double *__restrict__ y, double *__restrict__ z, double *__restrict__ vx,
+                double *__restrict__ vy, double *__restrict__ vz, const double *__restrict__ m,
+                const double *__restrict__ R, double f) {
+    const int np = resolve_count(st, pair_cap);
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
         if (flag[p] != 2) continue;
-        const int i = (int)(keys[p] >> 32), j = (int)(keys[p] & 0xffffffffll);
+        const int64_t k = keys[p];
+        const int i = pair_i(k), j = pair_j(k);
         const double t = dtc[p];
         const double x1 = x[i] + t * vx[i], y1 = y[i] + t * vy[i], z1 = z[i] + t * vz[i];
         const double x2 = x[j] + t * vx[j], y2 = y[j] + t * vy[j], z2 = z[j] + t * vz[j];
@@ -908,51 +1079,23 @@ k_resolve(DevState *st, const int64_t *__restrict__ keys, int64_t pair_cap, doub
         vx[i] = u1x; vy[i] = u1y; vz[i] = u1z;
         vx[j] = u2x; vy[j] = u2y; vz[j] = u2z;
     }
-    // the resolved pairs, in (i, j) order, as (step, i, j) after the earlier steps'
-    if (tid == 0) { s_run = 0; s_base = *cursor; }
-    __syncthreads();
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t c0 = 0; c0 < np; c0 += T) {
-        const int64_t p = c0 + tid;
-        const bool acc = p < np && flag[p] == 2;
-        const uint64_t b = __ballot(acc);
-        if (lane == 0) wsum[w] = __popcll(b);
-        __syncthreads();
-        int before = 0, tot = 0;
-        for (int k = 0; k < T / kWave; k++) {
-            if (k < w) before += wsum[k];
-            tot += wsum[k];
-        }
-        if (acc) {
-            const int64_t o = s_base + s_run + before + __popcll(b & lt);
-            if (o < cap) {
-                pairs[3 * o] = step;
-                pairs[3 * o + 1] = keys[p] >> 32;
-                pairs[3 * o + 2] = keys[p] & 0xffffffffll;
-            }
-        }
-        __syncthreads();
-        if (tid == 0) s_run += tot;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        *n_pairs_dev = s_run;
-        if (s_base + s_run > cap) {
-            atomicOr(&st->status, (int32_t)ST_CAP_PAIRS);
-            atomicMax((unsigned long long *)&st->required, (unsigned long long)(s_base + s_run));
-        }
-        *cursor = s_base + s_run;
-    }
 }
 
 hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, double *vx,
                           double *vy, double *vz, const double *m, const double *R, double dt,
                           double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
                           int64_t *cursor, hipStream_t s) {
-    k_rank_pairs<<<256, 256, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap, ws.pairs_alt);
-    k_resolve<<<1, kResolveThreads, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, x, y, z, vx, vy,
-                                            vz, m, R, dt, f, ws.pair_dt, ws.pair_flag, ws.mbest,
-                                            ws.mmatch, pairs, cap, n_pairs_dev, step, cursor);
+    k_rank_pairs<<<kRankGrid, kWave, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap, ws.pairs_alt);
+    k_resolve_init<<<kResolveGrid, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, x, y, z, vx,
+                                                vy, vz, R, dt, ws.pair_dt, ws.pair_flag,
+                                                ws.mmatch);
+    // the unsorted list is no longer needed: its buffer holds the live pair indices
+    k_resolve<<<1, kResolveThreads, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, ws.pair_dt,
+                                            ws.pair_flag, ws.mbest, ws.mmatch,
+                                            (int32_t *)ws.pairs_tmp, pairs, cap, n_pairs_dev,
+                                            step, cursor);
+    k_resolve_apply<<<kResolveGrid, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, ws.pair_flag,
+                                                 ws.pair_dt, x, y, z, vx, vy, vz, m, R, f);
     return hipGetLastError();
 }
 
@@ -979,7 +1122,7 @@ hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, bool 
 hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,
                              int64_t *n_pairs_dev, int triple, int step, int64_t *cursor,
                              hipStream_t s) {
-    k_rank_pairs<<<256, 256, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap, ws.pairs_alt);
+    k_rank_pairs<<<kRankGrid, kWave, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap, ws.pairs_alt);
     k_emit_pairs<<<256, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, pairs, cap, n_pairs_dev,
                                      triple, step, cursor);
     k_pairs_done<<<1, 64, 0, s>>>(ws.st, n_pairs_dev, cap, ws.pair_cap, triple, cursor);
