@@ -299,9 +299,11 @@ def _run_batched(nc, args, device):
                             collision_mode=nc.COLLISIONS_RESOLVE if args.collisions == "resolve"
                             else nc.COLLISIONS_REPORT, collision_f=2.0)
     t0 = time.perf_counter()
-    best, table = autotune.tune_leaf_size(nc, prm, base, offd, dt=args.dt, steps=3)
+    prm, tuning = autotune.tune_step(nc, prm, base, offd, dt=args.dt, steps=3,
+                                     samples=min(args.samples, 2048), device=device)
     tune_s = time.perf_counter() - t0
-    prm.leaf_size = best
+    best = prm.leaf_size
+    table = {s: v["ms_per_step"] for s, v in tuning["leaf_size"].items()}
     ns = args.batched_steps
     ctx = nc.Context(prm, n, pair_capacity=1 << 18, device=device)
     st = {k: v.clone() for k, v in base.items()}
@@ -370,6 +372,7 @@ def _run_batched(nc, args, device):
         "n_disks": 64, "n": int(n), "p": 4, "theta_min": 0.5, "precision": "fp32-bulk",
         "collisions": args.collisions,
         "leaf_size": int(best), "autotune_ms_per_step": table, "autotune_seconds": tune_s,
+        "autotune": tuning,
         "graph_steps": ns, "replays": args.batched_replays,
         "value": n * total_steps / wall, "unit": "particle-steps/s",
         "ms_per_step": wall * 1e3 / total_steps,
@@ -546,10 +549,14 @@ def main():
                                  ("fp64", prm64, LEAF_CANDIDATES_FP64)):
             if name == "fp64" and args.fp32_only:
                 continue
-            best, table = autotune.tune_leaf_size(ncorp, prm, base, dt=args.dt, steps=3,
-                                                  candidates=cands, device=device)
-            prm.leaf_size = int(best)
-            tuned[name] = {"leaf_size": int(best), "ms_per_step": table}
+            tp, tab = autotune.tune_step(ncorp, prm, base, dt=args.dt, steps=3,
+                                         leaf_sizes=cands, samples=min(args.samples, 2048),
+                                         device=device)
+            for k in ("leaf_size", "p2p_tile", "p2p_targets_max", "walk_waves"):
+                setattr(prm, k, int(getattr(tp, k)))
+            tuned[name] = {"leaf_size": int(prm.leaf_size),
+                           "ms_per_step": {s: v["ms_per_step"] for s, v in tab["leaf_size"].items()},
+                           "step_tuning": tab}
         del base
         print(f"# autotuned leaf sizes: {tuned}", file=sys.stderr, flush=True)
     else:

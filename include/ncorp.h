@@ -139,6 +139,16 @@ typedef struct {
     int32_t collision_method;
     int32_t mesh_cells;
     double mesh_neighbours, mesh_aspect, mesh_rmax, mesh_min_side, mesh_gamma;
+    /* launch shape of the falcON gravity evaluation (results do not depend on the last
+     * two; the tile moves the FP32 direct sums' rounding, not their accuracy class):
+     *   p2p_tile: source moonlets a direct-sum wave stages in LDS at a time, 128, 256
+     *     or 512 (0 = 256);
+     *   p2p_targets_max: the most target moonlets one lane of the direct sums holds,
+     *     1..4 (0 = 4); each leaf takes the count in 1..max that keeps most lanes busy;
+     *   walk_waves: persistent waves of the gravity walk, 256, 512, 1024 or 2048
+     *     (0 = 1024); each claims 128 queue items at a time, so this sets how many
+     *     items of the walk's queue are in flight. */
+    int32_t p2p_tile, p2p_targets_max, walk_waves;
 } ncorp_params;
 
 enum { NCORP_COLLISIONS_REPORT = 0, NCORP_COLLISIONS_RESOLVE = 1 };

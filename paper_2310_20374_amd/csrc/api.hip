@@ -174,6 +174,16 @@ static bool params_ok(const ncorp_params *p, char *why, size_t len) {
         std::snprintf(why, len, "Eq. (4) needs mesh_aspect > 0 (or give mesh_gamma)");
         return false;
     }
+    if (p->p2p_tile != 0 && p->p2p_tile != 128 && p->p2p_tile != 256 && p->p2p_tile != 512) {
+        std::snprintf(why, len, "p2p_tile must be 0, 128, 256 or 512"); return false;
+    }
+    if (p->p2p_targets_max < 0 || p->p2p_targets_max > 4) {
+        std::snprintf(why, len, "p2p_targets_max must be in 0..4"); return false;
+    }
+    if (p->walk_waves != 0 && p->walk_waves != 256 && p->walk_waves != 512 &&
+        p->walk_waves != 1024 && p->walk_waves != kWalkWavesMax) {
+        std::snprintf(why, len, "walk_waves must be 0, 256, 512, 1024 or 2048"); return false;
+    }
     return true;
 }
 
@@ -208,6 +218,9 @@ extern "C" int ncorp_params_default(ncorp_params *o, int p) {
     o->mesh_rmax = 0.0;
     o->mesh_min_side = 0.0;
     o->mesh_gamma = 0.0;
+    o->p2p_tile = 0;
+    o->p2p_targets_max = 0;
+    o->walk_waves = 0;
     return NCORP_OK;
 }
 
@@ -241,7 +254,7 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     int64_t cell_cap = prm.cell_capacity > 0 ? prm.cell_capacity : 8 * n / s + 1024;
     if (cell_cap > (1 << 24) - 2) cell_cap = (1 << 24) - 2;
     // plain pair lists: entries plus at most one partly used chunk per walk wave
-    const int64_t slack = (int64_t)kWalkWaves * kListChunk;
+    const int64_t slack = (int64_t)kWalkWavesMax * kListChunk;
     int64_t m2l_cap = (prm.m2l_capacity > 0 ? prm.m2l_capacity : 64 * cell_cap + 4096) + slack;
     int64_t p2p_cap = (prm.p2p_capacity > 0 ? prm.p2p_capacity : 32 * cell_cap + 4096) + slack;
     int64_t q_cap = prm.queue_capacity > 0 ? prm.queue_capacity
@@ -590,7 +603,8 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
     {
         PhaseTimer t(c, NCORP_PHASE_GWALK, s);
         ws.timing = c->timing;
-        HIPCHK(c, launch_walk(ws, 0, c->prm.ncs, c->prm.ncc_pre, c->prm.ncc_post, s));
+        HIPCHK(c, launch_walk(ws, 0, c->prm.ncs, c->prm.ncc_pre, c->prm.ncc_post,
+                              walk_waves(c->prm), s));
     }
     {
         PhaseTimer t(c, NCORP_PHASE_M2L, s);
@@ -603,7 +617,8 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
     }
     {
         PhaseTimer t(c, NCORP_PHASE_P2P, s);
-        HIPCHK(c, launch_p2p(ws, n, c->prm.precision, s));
+        HIPCHK(c, launch_p2p(ws, n, c->prm.precision, c->prm.p2p_tile, c->prm.p2p_targets_max,
+                             s));
     }
     {
         PhaseTimer t(c, NCORP_PHASE_L2P, s);
@@ -665,7 +680,7 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
             HIPCHK(c, launch_gather_vr(ws, packed, vx, vy, vz, R, n, s));
             HIPCHK(c, launch_collision_climb(ws, n, dt, s));
             HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col,
-                                  c->prm.ncc_post_col, s));
+                                  c->prm.ncc_post_col, 0, s));
             HIPCHK(c, launch_collide_pairs(ws, n, dt, false, s));
         }
     }
@@ -921,7 +936,7 @@ extern "C" int ncorp_tree_info(ncorp_ctx *c, int64_t *info) {
     info[NCORP_INFO_M2L_MAXLIST] = h.m2l_maxlist;
     info[NCORP_INFO_P2P_MAXLIST] = h.p2p_maxlist;
     info[NCORP_INFO_WALK_BUSY_MAX] = h.walk_busy_max;
-    info[NCORP_INFO_WALK_BUSY_MEAN] = h.walk_busy_sum / kWalkWaves;
+    info[NCORP_INFO_WALK_BUSY_MEAN] = h.walk_busy_sum / walk_waves(c->prm);
     info[NCORP_INFO_P2P_SRC_MAX] = h.p2p_src_max;
     info[NCORP_INFO_SORT_PREV] = h.bs_prev_used;
     info[NCORP_INFO_SORT_SPILL] = h.bs_spill;

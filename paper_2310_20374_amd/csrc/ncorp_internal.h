@@ -64,6 +64,9 @@ constexpr int kWalkBlock = 256;
 constexpr int kWalkGridGravity = 256;
 constexpr int kWalkGridCollide = 128;
 constexpr int kWalkWaves = kWalkGridGravity * kWalkBlock / kWave;
+constexpr int kWalkWavesMax = 2048;       // the largest walk_waves (list gap slack)
+// persistent waves of the gravity walk under these parameters
+inline int walk_waves(const ncorp_params &p) { return p.walk_waves > 0 ? p.walk_waves : kWalkWaves; }
 constexpr int kListChunk = 256;
 // the walk's tail shares a 64-bit word with the processed count (32 bits each); an
 // item pushes at most 36 children, so a queue of this many slots keeps the tail
@@ -378,7 +381,7 @@ hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_para
 hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hipStream_t s);
 
 // walk: mode 0 gravity (M2L + P2P lists), 1 collisions (candidate list in p2p)
-hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post,
+hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post, int waves,
                        hipStream_t s);
 hipError_t launch_count_interactions(const Workspace &ws, hipStream_t s);
 // sorts, in place, the per-target lists longer than the consumers sort in LDS
@@ -386,7 +389,8 @@ hipError_t launch_sort_long_lists(const Workspace &ws, hipStream_t s);
 
 hipError_t launch_m2l(const Workspace &ws, int p, int precision, hipStream_t s);
 hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s);
-hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s);
+hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, int tile, int tmax,
+                      hipStream_t s);
 hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,
                       hipStream_t s);
 // brute-force module (every pair): accelerations by input index; colliding pairs

@@ -157,7 +157,7 @@ template <typename T> __device__ __forceinline__ T r2_floor();
 template <> __device__ __forceinline__ float r2_floor<float>() { return 1e-18f; }
 template <> __device__ __forceinline__ double r2_floor<double>() { return 1e-100; }
 
-constexpr int kP2PTile = 256;       // source moonlets staged per LDS tile
+constexpr int kP2PTile = 256;       // source moonlets staged per LDS tile (default)
 constexpr int kP2PSrc = kWave;      // source cells per batch, one per lane (prefix sums in LDS)
 
 // Exclusive prefix sums of the moonlet counts of a batch's source cells (one per
@@ -199,9 +199,9 @@ __device__ __forceinline__ void interact(const typename Vec4<T>::type &v, const 
 
 // Direct sums of the NT targets a lane holds over a batch of source cells whose
 // moonlet ranges are s_first[k] .. + (s_pref[k+1] - s_pref[k]), k < nsb, tot
-// moonlets in all; the batch is streamed through LDS kP2PTile moonlets at a time and
+// moonlets in all; the batch is streamed through LDS TILE moonlets at a time and
 // the lane's group takes sources j0, j0 + G, ... of every tile.
-template <typename T, int NT>
+template <typename T, int NT, int TILE>
 __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_first,
                                           const int32_t *s_pref,
                                           typename Vec4<T>::type *tile,
@@ -213,12 +213,12 @@ __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_fir
                                           int j0, int G, Acc3<T> (&acc)[NT]) {
     using V = typename Vec4<T>::type;
     const int lane = threadIdx.x & (kWave - 1);
-    for (int p0 = 0; p0 < tot; p0 += kP2PTile) {
-        const int nj = tot - p0 < kP2PTile ? tot - p0 : kP2PTile;
+    for (int p0 = 0; p0 < tot; p0 += TILE) {
+        const int nj = tot - p0 < TILE ? tot - p0 : TILE;
         // stage the tile: source moonlet q of the batch -> its cell by binary
         // search over the prefix sums
 #pragma unroll
-        for (int k = 0; k < kP2PTile / 64; k++) {
+        for (int k = 0; k < TILE / 64; k++) {
             const int q = p0 + lane + 64 * k;
             if (q < tot) {
                 int lo = 0, hi = nsb;          // s_pref[lo] <= q < s_pref[hi]
@@ -260,7 +260,7 @@ __device__ __forceinline__ void p2p_batch(int tot, int nsb, const int32_t *s_fir
 // lanes; lane li of a group holds targets li and li + lpg (NT = 2), and the groups
 // split every tile's sources.  The group partials are added in group order and
 // written to out[d * n + i], d = x, y, z.
-template <typename T, int NT>
+template <typename T, int NT, int TILE>
 __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1, int len,
                                             int b0, int bstep,
                                             const int32_t *__restrict__ list, int32_t *s_first,
@@ -285,10 +285,10 @@ __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1,
         yi[k] = (T)(ys[i] - g.y);
         zi[k] = (T)(zs[i] - g.z);
     }
-    const int j0 = grp < G ? grp : kP2PTile;       // lanes beyond the groups idle
+    const int j0 = grp < G ? grp : TILE;           // lanes beyond the groups idle
     Acc3<T> acc[NT];
     if (one) {
-        p2p_batch<T, NT>(tot1, len, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi, j0,
+        p2p_batch<T, NT, TILE>(tot1, len, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi, j0,
                          G, acc);
     } else {
         for (int sb = b0 * kP2PSrc; sb < len; sb += bstep * kP2PSrc) {
@@ -303,7 +303,7 @@ __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1,
             s_first[lane] = cf;
             const int tot = batch_prefix(cn, s_pref, lane);
             wave_sync();
-            p2p_batch<T, NT>(tot, nsb, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi,
+            p2p_batch<T, NT, TILE>(tot, nsb, s_first, s_pref, tile, xs, ys, zs, mus, g, xi, yi, zi,
                              j0, G, acc);
         }
     }
@@ -333,10 +333,11 @@ __device__ __forceinline__ void p2p_targets(int ntc, int tb, bool one, int tot1,
 // 64 * NT lane slots busy.  The NT in 1..4 with the largest share wins (the smaller
 // on ties): 43 targets use 3 per lane (4 groups of 15 lanes, 90 % busy) where one or
 // two per lane leave a third of the lanes idle.
-__device__ __forceinline__ int targets_per_lane(int ntc) {
+__device__ __forceinline__ int targets_per_lane(int ntc, int tmax) {
     int best = 1, best_score = -1;
 #pragma unroll
     for (int nt = 1; nt <= 4; nt++) {
+        if (nt > tmax) break;
         const int lpg = (ntc + nt - 1) / nt;
         const int score = ntc * (kWave / lpg) * (12 / nt);
         if (score > best_score) { best = nt; best_score = score; }
@@ -344,9 +345,9 @@ __device__ __forceinline__ int targets_per_lane(int ntc) {
     return best;
 }
 
-template <typename T>
-__device__ __forceinline__ void p2p_targets_any(int ntc, int tb, bool one, int tot1, int len,
-                                                int b0, int bstep,
+template <typename T, int TILE>
+__device__ __forceinline__ void p2p_targets_any(int ntc, int tmax, int tb, bool one, int tot1,
+                                                int len, int b0, int bstep,
                                                 const int32_t *__restrict__ list,
                                                 int32_t *s_first, int32_t *s_pref,
                                                 typename Vec4<T>::type *tile,
@@ -358,21 +359,21 @@ __device__ __forceinline__ void p2p_targets_any(int ntc, int tb, bool one, int t
                                                 const int32_t *__restrict__ c_count,
                                                 const double4 g, double *__restrict__ out,
                                                 int64_t n) {
-    switch (targets_per_lane(ntc)) {
+    switch (targets_per_lane(ntc, tmax)) {
         case 1:
-            p2p_targets<T, 1>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
+            p2p_targets<T, 1, TILE>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
                               xs, ys, zs, mus, c_first, c_count, g, out, n);
             break;
         case 2:
-            p2p_targets<T, 2>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
+            p2p_targets<T, 2, TILE>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
                               xs, ys, zs, mus, c_first, c_count, g, out, n);
             break;
         case 3:
-            p2p_targets<T, 3>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
+            p2p_targets<T, 3, TILE>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
                               xs, ys, zs, mus, c_first, c_count, g, out, n);
             break;
         default:
-            p2p_targets<T, 4>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
+            p2p_targets<T, 4, TILE>(ntc, tb, one, tot1, len, b0, bstep, list, s_first, s_pref, tile,
                               xs, ys, zs, mus, c_first, c_count, g, out, n);
             break;
     }
@@ -388,7 +389,7 @@ static_assert(kP2PListLDS == kP2PSrc, "one LDS batch holds a list the pre-pass l
 // writes its partial sums to part[slot], which the evaluation kernel adds in slot
 // order.  The split items come first, so they start first and the short leaves fill
 // in around them within the same launch.
-template <typename T>
+template <typename T, int TILE>
 __global__ void __launch_bounds__(kWave * kP2PWaves)
 k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const double *__restrict__ ys, const double *__restrict__ zs,
@@ -396,9 +397,10 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
       const double4 *__restrict__ gcell, const int32_t *__restrict__ p2p_cnt,
       int32_t *__restrict__ p2p_seg, int stride, const int32_t *__restrict__ longs,
-      double *__restrict__ part, double *__restrict__ acc_s, int64_t n) {
+      double *__restrict__ part, double *__restrict__ acc_s, int64_t n, int tmax) {
     using V = typename Vec4<T>::type;
-    __shared__ __align__(16) V tiles[kP2PWaves][kP2PTile];
+    static_assert(TILE >= 128 && TILE % 64 == 0, "the tile doubles as the sort's scratch");
+    __shared__ __align__(16) V tiles[kP2PWaves][TILE];
     __shared__ int32_t firsts[kP2PWaves][kP2PSrc], prefs[kP2PWaves][kP2PSrc + 1];
     if (st->status & kSkipMask) return;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -420,8 +422,9 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
             wave_sync();                              // this wave's LDS is free again
             for (int t0 = 0; t0 < nt; t0 += kWave) {
                 const int ntc = nt - t0 < kWave ? nt - t0 : kWave;
-                p2p_targets_any<T>(ntc, f + t0, false, 0, len, slot, kLongSlots, list, s_first,
-                                   s_pref, tile, xs, ys, zs, mus, c_first, c_count, g, out, n);
+                p2p_targets_any<T, TILE>(ntc, tmax, f + t0, false, 0, len, slot, kLongSlots,
+                                         list, s_first, s_pref, tile, xs, ys, zs, mus, c_first,
+                                         c_count, g, out, n);
             }
             continue;
         }
@@ -458,8 +461,9 @@ k_p2p(const DevState *__restrict__ st, const double *__restrict__ xs,
         wave_sync();
         for (int t0 = 0; t0 < nt; t0 += kWave) {
             const int ntc = nt - t0 < kWave ? nt - t0 : kWave;
-            p2p_targets_any<T>(ntc, f + t0, true, tot1, len, 0, 1, list, s_first, s_pref, tile,
-                               xs, ys, zs, mus, c_first, c_count, g, acc_s, n);
+            p2p_targets_any<T, TILE>(ntc, tmax, f + t0, true, tot1, len, 0, 1, list, s_first,
+                                     s_pref, tile, xs, ys, zs, mus, c_first, c_count, g, acc_s,
+                                     n);
         }
     }
 }
@@ -563,20 +567,32 @@ hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T>
-static void launch_p2p_t(const Workspace &ws, int64_t n, hipStream_t s) {
+template <typename T, int TILE>
+static void launch_p2p_t(const Workspace &ws, int64_t n, int tmax, hipStream_t s) {
     // one item per leaf plus kLongSlots - 1 more per long leaf; the grid strides
     int64_t g = (ws.leaf_cap + kP2PWaves - 1) / kP2PWaves + kLongGrid;
     g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
-    k_p2p<T><<<(int)g, kWave * kP2PWaves, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell,
-                                                   ws.c_first, ws.c_count, ws.gcell, ws.p2p_cnt,
-                                                   ws.p2p_seg, ws.p2p_stride, ws.long_p2p,
-                                                   ws.p2p_part, ws.acc_s, n);
+    k_p2p<T, TILE><<<(int)g, kWave * kP2PWaves, 0, s>>>(
+        ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell, ws.c_first, ws.c_count, ws.gcell,
+        ws.p2p_cnt, ws.p2p_seg, ws.p2p_stride, ws.long_p2p, ws.p2p_part, ws.acc_s, n, tmax);
 }
 
-hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, hipStream_t s) {
-    if (precision == NCORP_FP32_BULK) launch_p2p_t<float>(ws, n, s);
-    else launch_p2p_t<double>(ws, n, s);
+template <typename T>
+static void launch_p2p_tile(const Workspace &ws, int64_t n, int tile, int tmax, hipStream_t s) {
+    switch (tile) {
+        case 128: launch_p2p_t<T, 128>(ws, n, tmax, s); break;
+        case 512: launch_p2p_t<T, 512>(ws, n, tmax, s); break;
+        default: launch_p2p_t<T, kP2PTile>(ws, n, tmax, s); break;
+    }
+}
+
+// tile: source moonlets per LDS tile (128, 256, 512; 0 = 256); tmax: most targets per
+// lane (1..4; 0 = 4)
+hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, int tile, int tmax,
+                      hipStream_t s) {
+    const int tm = tmax > 0 ? tmax : 4;
+    if (precision == NCORP_FP32_BULK) launch_p2p_tile<float>(ws, n, tile, tm, s);
+    else launch_p2p_tile<double>(ws, n, tile, tm, s);
     return hipGetLastError();
 }
 

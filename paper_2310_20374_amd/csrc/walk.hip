@@ -452,7 +452,8 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
     }
 }
 
-hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post,
+// waves: persistent waves of the gravity walk (the collision walk runs its own count)
+hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post, int waves,
                        hipStream_t s) {
     k_walk_epoch<<<1, 64, 0, s>>>(ws.wq, ws.clear_queue ? 1 : 0);
     ws.clear_queue = false;
@@ -470,7 +471,8 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
         A.p2p_cnt = ws.p2p_cnt; A.p2p_seg = ws.p2p_seg; A.p2p_stride = ws.p2p_stride;
         A.long_m2l = ws.long_m2l; A.long_p2p = ws.long_p2p;
         A.timing = ws.timing ? 1 : 0;
-        k_walk<0><<<kWalkGridGravity, kWalkBlock, 0, s>>>(A);
+        const int grid = (waves > 0 ? waves : kWalkWaves) / (kWalkBlock / kWave);
+        k_walk<0><<<grid, kWalkBlock, 0, s>>>(A);
     } else {
         A.cell = ws.wc;
         A.m2l = ws.m2l; A.m2l_cap = 0; A.nm2l = &ws.st->nm2l;

@@ -57,6 +57,7 @@ class Params(C.Structure):
         ("collision_method", C.c_int32), ("mesh_cells", C.c_int32),
         ("mesh_neighbours", C.c_double), ("mesh_aspect", C.c_double),
         ("mesh_rmax", C.c_double), ("mesh_min_side", C.c_double), ("mesh_gamma", C.c_double),
+        ("p2p_tile", C.c_int32), ("p2p_targets_max", C.c_int32), ("walk_waves", C.c_int32),
     ]
 
     def as_dict(self):

@@ -43,6 +43,7 @@ def test_params_default_and_validation(nc):
         assert (prm.gravity_method, prm.ncb_pre, prm.ncb_post) == (nc.GRAVITY_FALCON, 6, 16)
         assert (prm.collision_method, prm.mesh_cells, prm.mesh_neighbours,
                 prm.mesh_aspect, prm.mesh_gamma) == (nc.COLLISIONS_TREE, 256, 8.0, 0.05, 0.0)
+        assert (prm.p2p_tile, prm.p2p_targets_max, prm.walk_waves) == (0, 0, 0)
     bad = nc.Params()
     assert L.ncorp_params_default(C.byref(bad), 7) == nc.E_INVALID
     h = C.c_void_p()
@@ -53,7 +54,9 @@ def test_params_default_and_validation(nc):
                        ("obliquity", float("nan")), ("gravity_method", 4), ("ncb_pre", -1),
                        ("ncb_post", -1), ("collision_method", 4), ("mesh_cells", 0),
                        ("mesh_cells", -3), ("mesh_neighbours", 0.0), ("mesh_gamma", -1.0),
-                       ("mesh_aspect", float("inf")), ("mesh_rmax", -1.0)):
+                       ("mesh_aspect", float("inf")), ("mesh_rmax", -1.0),
+                       ("p2p_tile", 64), ("p2p_tile", 300), ("p2p_targets_max", 5),
+                       ("p2p_targets_max", -1), ("walk_waves", 128), ("walk_waves", 4096)):
         prm = nc.params_default(3)
         setattr(prm, field, val)
         assert L.ncorp_create(C.byref(prm), C.byref(h)) == nc.E_INVALID, field
