@@ -42,11 +42,9 @@ FLOPS_PER_INTERACTION = 20  # directed moonlet pair, the usual N-body convention
 # reported only while it is unchanged.
 # Measured per leaf size (the direct sums' work depends on it).
 P2P_TRAFFIC = {"source": "paper_2310_20374_amd/csrc/p2p.hip",
-               "blob": "bb1912686fb499fa373cca5a1a1e89a038232ea5",
+               "blob": "6ba4f09d4d714dd89f5f307e2771bfad79713ef1",
                "fetch_scale": 2.00, "write_scale": 1.00,
-               "by_leaf_size": {80: {"fetch_kib": (182036.7,), "write_kib": (25559.4,)},
-                                96: {"fetch_kib": (198651.1,), "write_kib": (25617.4,)},
-                                112: {"fetch_kib": (221137.4,), "write_kib": (25600.2,)}}}
+               "by_leaf_size": {96: {"fetch_kib": (198895.1,), "write_kib": (25535.4,)}}}
 
 
 def _git_blob(path):
@@ -442,32 +440,45 @@ def _run_clustered(nc, args, device, leaf_size, cmode):
     return out
 
 
-def _cpu_baseline(orc, n_sample, p, theta, s, thr, dt):
-    """The oracle as it stands (single-threaded FP64 tree, recursive walk, full
-    3^n tensors) for one step of a sub-disk drawn from the same distribution."""
-    import numpy as np
+def _cpu_step(orc, n, p, theta, s, thr, dt):
+    """One steady-state step of the oracle as it stands (single-threaded FP64 tree,
+    recursive walk, full 3^n tensors) on an N-moonlet cold disk: a tree build and the
+    gravity evaluation, then a tree build and the collision walk (the drift and kicks
+    are negligible beside them).  Returns (gravity seconds, collision seconds)."""
     from paper_2310_20374_amd import inputs
-    d = inputs.disk(n_sample, seed=0)
+    d = inputs.disk(n, seed=0)
     t0 = time.perf_counter()
+    orc.tree_accel(d, p=p, theta_min=theta, s=s, ncs=thr[0], ncc_pre=thr[1], ncc_post=thr[2])
+    t1 = time.perf_counter()
+    t = orc.Tree(d["x"], d["y"], d["z"], s)
+    orc.Collide(t, d["vx"], d["vy"], d["vz"], d["R"], dt).run(12, 0, 16)
+    t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
 
-    def accel(st):
-        a, _, _ = orc.tree_accel(st, p=p, theta_min=theta, s=s, ncs=thr[0], ncc_pre=thr[1],
-                                 ncc_post=thr[2])
-        return a
 
-    def collide(st, h):
-        t = orc.Tree(st["x"], st["y"], st["z"], s)
-        c = orc.Collide(t, st["vx"], st["vy"], st["vz"], st["R"], h)
-        return c.run(12, 0, 16)
+def _cpu_baseline(orc, n_sample, p, theta, s, thr, dt):
+    """The oracle timed on one host core for one steady-state step of the headline's
+    disk (N = n_sample, same distribution and settings)."""
+    g, c = _cpu_step(orc, n_sample, p, theta, s, thr, dt)
+    return {"value": n_sample / (g + c), "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one steady-state step of an N={n_sample} cold disk (same distribution, "
+                      f"p={p}, theta_min={theta}, s={s}): tree build + FP64 oracle gravity, "
+                      f"tree build + collision walk; single-threaded",
+            "seconds": g + c, "gravity_seconds": g, "collision_seconds": c}
 
-    orc.kdk_steps(d, dt, 1, accel, collide_fn=collide)
-    el = time.perf_counter() - t0
-    # kdk_steps evaluates gravity twice for one step (start and end); count one step
-    return {"value": n_sample / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"one KDK step of an N={n_sample} cold disk (same distribution, p={p}, "
-                      f"theta_min={theta}, s={s}) with the FP64 oracle tree (gravity at both "
-                      f"ends of the step) and its tree collision walk; single-threaded",
-            "seconds": el}
+
+def _cpu_configs(orc, dt):
+    """The oracle's per-step rate on the two small configurations of the benchmark:
+    N = 2000, p = 3, s = 16, and N = 1e5, p = 6 (its default leaf size, s = 52); one
+    steady-state step each, single-threaded."""
+    out = {}
+    for name, n, p, s, thr in (("n2000_p3_fp64", 2000, 3, 16, (64, 8, 64)),
+                               ("n100000_p6_fp64", 100_000, 6, 52, (256, 256, 512))):
+        g, c = _cpu_step(orc, n, p, 0.5, s, thr, dt)
+        out[name] = {"value": n / (g + c), "unit": "particle-steps/s", "cores": 1,
+                     "gravity_seconds": g, "collision_seconds": c}
+    return out
 
 
 def main():
@@ -480,7 +491,7 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--samples", type=int, default=4096)
-    ap.add_argument("--cpu-sample", type=int, default=400_000)
+    ap.add_argument("--cpu-sample", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
@@ -678,6 +689,7 @@ def main():
         cpu = _cpu_baseline(orc, args.cpu_sample, args.p, args.theta, prm64.leaf_size, thr,
                             args.dt)
         cpu["cores"] = 1
+        cpu["other_configs"] = _cpu_configs(orc, args.dt)
 
     phase_roof, step_frac = _phase_rooflines(ph, info, args.n, args.p, True)
 

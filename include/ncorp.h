@@ -289,8 +289,8 @@ int ncorp_step_batched(ncorp_ctx *ctx, const int64_t *disk_offsets, int n_disks,
  * by the first call on that GPU (the device current at the call) and held until
  * the process ends.  Nothing is allocated or freed by the call.
  *  - Size limit: n must satisfy ncorp_workspace_bytes(params, n, 1) <=
- *    NCORP_STATIC_WORKSPACE_BYTES (with the default capacities up to 18 823 moonlets
- *    at p = 6 and 19 837 at p = 4, leaf size 52, and 7 050 at p = 3, leaf size 17;
+ *    NCORP_STATIC_WORKSPACE_BYTES (with the default capacities up to 18 810 moonlets
+ *    at p = 6 and 19 824 at p = 4, leaf size 52, and 7 048 at p = 3, leaf size 17;
  *    a larger leaf size allows more); a larger n returns
  *    NCORP_E_INVALID at once, before anything touches the GPU.  The part of the
  *    array the layout does not use holds the colliding pairs of the step.

@@ -253,8 +253,11 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     const int s = prm.leaf_size;
     int64_t cell_cap = prm.cell_capacity > 0 ? prm.cell_capacity : 8 * n / s + 1024;
     if (cell_cap > (1 << 24) - 2) cell_cap = (1 << 24) - 2;
-    // plain pair lists: entries plus at most one partly used chunk per walk wave
-    const int64_t slack = (int64_t)kWalkWavesMax * kListChunk;
+    // plain pair lists: entries plus at most one partly used chunk per walk wave (the
+    // gravity walk's waves, or the collision walk's if it runs more)
+    const int collide_waves = kWalkGridCollide * (kWalkBlock / kWave);
+    const int64_t slack =
+        (int64_t)(walk_waves(prm) > collide_waves ? walk_waves(prm) : collide_waves) * kListChunk;
     int64_t m2l_cap = (prm.m2l_capacity > 0 ? prm.m2l_capacity : 64 * cell_cap + 4096) + slack;
     int64_t p2p_cap = (prm.p2p_capacity > 0 ? prm.p2p_capacity : 32 * cell_cap + 4096) + slack;
     int64_t q_cap = prm.queue_capacity > 0 ? prm.queue_capacity
@@ -436,8 +439,12 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
     ws.sort_prev = c->ws.base == ws.base && c->ws.bs_prev == ws.bs_prev && c->ws.sort_prev;
     // so does the mesh state
     if (ws.mesh) {
+        // the O(N) grid clear reads the last dense build's keys and grid: every mesh
+        // buffer must be where it was
         const bool same = c->ws.base == ws.base && c->ws.mesh == ws.mesh &&
-                          c->ws.mtab == ws.mtab && c->mesh_init;
+                          c->ws.mtab == ws.mtab && c->ws.mtab_n == ws.mtab_n &&
+                          c->ws.mgrid == ws.mgrid && c->ws.mgrid_n == ws.mgrid_n &&
+                          c->ws.mkeys == ws.mkeys && c->ws.midx == ws.midx && c->mesh_init;
         ws.clear_mesh = !same || c->ws.clear_mesh;
         if (!same) { c->mesh_init = false; c->have_mesh = false; }
     }

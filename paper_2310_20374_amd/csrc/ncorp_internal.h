@@ -64,7 +64,7 @@ constexpr int kWalkBlock = 256;
 constexpr int kWalkGridGravity = 256;
 constexpr int kWalkGridCollide = 128;
 constexpr int kWalkWaves = kWalkGridGravity * kWalkBlock / kWave;
-constexpr int kWalkWavesMax = 2048;       // the largest walk_waves (list gap slack)
+constexpr int kWalkWavesMax = 2048;       // the largest walk_waves
 // persistent waves of the gravity walk under these parameters
 inline int walk_waves(const ncorp_params &p) { return p.walk_waves > 0 ? p.walk_waves : kWalkWaves; }
 constexpr int kListChunk = 256;

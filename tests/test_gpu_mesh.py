@@ -235,3 +235,39 @@ def test_mesh_collisions_with_tree_gravity(nc, orc):
         off += cnt[step]
         assert np.array_equal(mine[:, 1:], ref_pairs[step]), step
     assert ctx.mesh_state()["gamma"] == pytest.approx(clk.history[-1][0], rel=1e-13)
+
+
+def test_one_context_dense_hashed_dense(nc, orc):
+    """One context, four meshes in a row: a dense grid, a larger dense grid, a box too
+    large for the dense grid (hashed cells) and a dense grid again.  The clear of the
+    grid between dense builds reads the previous dense build's keys; every build must
+    still give the oracle's accelerations and pairs at its own mesh size (Eq. 6 moves
+    gamma from build to build)."""
+    import torch
+    n, dt = 3000, 0.005
+    base = inputs.gas_box(n, seed=11, radius=0.01)
+
+    def scaled(f):
+        d = {k: v.copy() for k, v in base.items()}
+        for k in ("x", "y", "z"):
+            d[k] = d[k] * f
+        return d
+
+    ctx = nc.Context(_prm(nc, 0.05, 64), n, pair_capacity=1 << 16, device="cuda:0")
+    a = [torch.empty(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    pairs = torch.zeros((1 << 16, 2), dtype=torch.int64, device="cuda:0")
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    for name, d in (("dense", base), ("dense, larger", base), ("hashed", scaled(4.0)),
+                    ("dense again", base)):
+        print(f"build: {name}", flush=True)
+        t = dev_arrays(d)
+        ctx.build_mesh(t["x"], t["y"], t["z"], t["R"])
+        ctx.gravity(t["m"], *a)
+        ctx.collide(t["vx"], t["vy"], t["vz"], t["R"], dt, pairs, npairs)
+        torch.cuda.synchronize()
+        ctx.check_status()
+        g = ctx.mesh_state()["gamma"]
+        acc = torch.stack(a, 1).cpu().numpy()
+        assert rel_err(acc, orc.mesh_accel(d, g))[1] < 1e-11, name
+        k = int(npairs.item())
+        assert np.array_equal(pairs[:k].cpu().numpy(), orc.mesh_pairs(d, g, dt)), name
