@@ -501,6 +501,10 @@ def main():
     ap.add_argument("--leaf-size", default="auto",
                     help="leaf size s of the main line: 'auto' (the autotuner, each precision "
                          "form on its own) or an integer")
+    ap.add_argument("--launch-shape", default="",
+                    help="with an integer --leaf-size: 'TILExTMAX:WAVES' pins the direct-sum "
+                         "tile shape and the walk's wave count (e.g. 256x4:512); '' keeps the "
+                         "library's defaults")
     ap.add_argument("--thetas", default="0.3,0.7",
                     help="extra opening angles timed and error-checked beside --theta "
                          "(both precision forms, 10 steps each); '' for none")
@@ -572,6 +576,11 @@ def main():
         print(f"# autotuned leaf sizes: {tuned}", file=sys.stderr, flush=True)
     else:
         prm32.leaf_size = prm64.leaf_size = int(args.leaf_size)
+        if args.launch_shape:
+            tile, waves = args.launch_shape.split(":")
+            t, tmax = (int(v) for v in tile.split("x"))
+            for prm in (prm32, prm64):
+                prm.p2p_tile, prm.p2p_targets_max, prm.walk_waves = t, tmax, int(waves)
     thr = (prm64.ncs, prm64.ncc_pre, prm64.ncc_post)
     print(f"# bench: N={args.n} p={args.p} theta_min={args.theta} s={prm64.leaf_size} "
           f"steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)

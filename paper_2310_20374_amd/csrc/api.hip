@@ -317,6 +317,7 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.c_nent = (int32_t *)take(4 * cell_cap);
     ws.c_prefix = (uint64_t *)take(8 * cell_cap);
     ws.c_arrive = (int32_t *)take(4 * cell_cap);
+    ws.climb_next = (int32_t *)take(4 * kXcds * 32);
     ws.gcell = (double4 *)take(32 * cell_cap);
     ws.c_mass = (double *)take(8 * cell_cap);
     ws.c_rmax = (double *)take(8 * cell_cap);

@@ -51,6 +51,49 @@ __device__ double far_corner(double sx, double sy, double sz, double px, double 
 // s of them, typically a few dozen)
 constexpr int kPowChunk = 32;
 
+// Leaves of the climbs in XCD slices: the leaves, in tree order, are cut into 8
+// contiguous slices and the waves of XCD x (workgroups b with b mod 8 = x) take the
+// leaves of slice x in order: the first of each wave by its position, later ones
+// one at a time from a counter of that slice.  Siblings
+// and most of their ancestors' chains then stay on one XCD and every XCD gets the
+// same number of leaves (with leaves dealt round robin, an XCD that falls behind
+// arrives last more often, inherits more of the upward chains and falls further
+// behind).  The waves are persistent, as many as fit on the chip at once, so no
+// leaf waits for a workgroup launch.
+constexpr int kCtrStride = 32;                      // one counter per 128-byte line
+
+template <int KERNEL_ID>
+static int climb_grid(const void *kernel, int64_t leaf_cap) {
+    static int cached[64] = {};                     // per device, for this kernel
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int g = dev >= 0 && dev < 64 ? cached[dev] : 0;
+    if (g == 0) {
+        int per_cu = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            per_cu < 1 || ncu < 1) {
+            (void)hipGetLastError();
+            per_cu = 16;
+            ncu = 256;
+        }
+        g = per_cu * ncu / kXcds * kXcds;
+        if (g < kXcds) g = kXcds;
+        if (dev >= 0 && dev < 64) cached[dev] = g;
+    }
+    int64_t want = (leaf_cap + kXcds - 1) / kXcds * kXcds;
+    if (want < kXcds) want = kXcds;
+    return (int)(want < g ? want : g);
+}
+
+// next leaf index of this wave's slice after the first round (lane 0 takes it from
+// the slice's counter; every lane reads it later)
+__device__ __forceinline__ int take_leaf(int32_t *ctr) {
+    int i = 0;
+    if (threadIdx.x == 0) i = atomicAdd(ctr, 1) + (int)(gridDim.x / kXcds);
+    return i;
+}
+
 // ---------------------------------------------------------------- wave helpers
 // Cell results are handed from wave to wave inside one launch: they are written
 // with agent-coherent stores and read back with agent-coherent loads, and a wave
@@ -70,9 +113,31 @@ __device__ __forceinline__ bool arrive_last(int32_t *counter, int nchild) {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     int old = 0;
     if (threadIdx.x == 0) old = atomicAdd(counter, 1);
-    old = __shfl(old, 0);
+    old = __builtin_amdgcn_readlane(old, 0);       // wave-uniform: a scalar branch
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     return old == nchild - 1;
+}
+
+// M2M sums of lane j's shift terms over NQ children (children nch..NQ-1 of the
+// staged tables are zeros): one partial sum per child, added in child order
+template <int NQ, int NE, int NMS>
+__device__ __forceinline__ double m2m_terms(const uint16_t *sterm, int t0, int t1,
+                                            const double (*cm)[NMS], const double (*ue)[NE]) {
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) acc[q] = 0.0;
+    int w = sterm[t0];                  // sterm has one entry past the last term
+    for (int t = t0; t < t1; t++) {
+        const int wn = sterm[t + 1];
+        const int src = w & 63, ex = w >> 6;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) acc[q] += cm[q][src] * ue[q][ex];
+        w = wn;
+    }
+    double s = acc[0];
+#pragma unroll
+    for (int q = 1; q < NQ; q++) s += acc[q];
+    return s;
 }
 
 // value of lane k (k uniform)
@@ -105,9 +170,22 @@ __host__ __device__ constexpr void mult_index(int j, int &a, int &b, int &c) {
     a = n - k;
 }
 
+// multi-index (a, b, c) of position s among all orders (inverse of sidx)
+__host__ __device__ constexpr void sidx_inverse(int s, int &a, int &b, int &c) {
+    int n = 0;
+    while (off_order(n + 1) <= s) n++;
+    const int r = s - off_order(n);
+    int k = 0;
+    while (tri(k + 1) <= r) k++;
+    c = r - tri(k);
+    b = k - c;
+    a = n - k;
+}
+
 // Terms of the App. C shift Mt_a(s') = sum_{b <= a, |b| != 1} Mt_b(s) u^(a-b)/(a-b)!
 // for every multipole slot: term t of slot j (first[j] <= t < first[j+1]) packs
-// the source slot and the three exponents (6 + 3 x 3 bits).
+// the source slot (6 bits) and the position of the exponent e = a - b among all
+// multi-indices of order < p (sidx, 6 bits).
 template <int P> struct ShiftTerms {
     static constexpr int NM = n_mult(P);
     static constexpr int count() {
@@ -135,22 +213,26 @@ template <int P> struct ShiftTerms {
                 for (int b2 = 0; b2 <= b; b2++)
                     for (int c2 = 0; c2 <= c; c2++)
                         if (a2 + b2 + c2 != 1)
-                            term[t++] = (uint16_t)(midx(a2, b2, c2) | ((a - a2) << 6) |
-                                                   ((b - b2) << 9) | ((c - c2) << 12));
+                            term[t++] = (uint16_t)(midx(a2, b2, c2) |
+                                                   (sidx(a - a2, b - b2, c - c2) << 6));
         }
         first[NM] = (uint16_t)t;
     }
 };
 template <int P> __constant__ ShiftTerms<P> kShift = ShiftTerms<P>();
 
-// Gravity climb.  One wave per cell.  Centre of mass: every lane forms the same
-// sum over moonlets (leaves) or children (internal cells) in a fixed sequential
-// order, so it is reproducible bit for bit; r_max is an exact wave maximum.
+// Gravity climb.  One wave per cell.  Centre of mass: the sums over moonlets
+// (leaves) or children (internal cells) are formed in a fixed sequential order, so
+// they are reproducible bit for bit (at a leaf lane j < 4 forms the sum of
+// mu * (1, x, y, z)_j, mu * 1 being mu exactly); r_max is an exact wave maximum.
 // Moments: lane j owns multipole slot j.  At a leaf each lane first stages its
 // moonlet's scaled powers u^k/k! in LDS, then lane j sums mu u^a/a! over the
 // moonlets in order (Eq. 20).  At an internal cell the children's moments and the
-// scaled powers of their offsets are staged in LDS and lane j applies the shift
-// terms of its slot, child by child.
+// products u^e/e! of their offsets' scaled powers (one exponent e per lane, every
+// e of order < p) are staged in LDS, and lane j sums its slot's shift terms for
+// each child.  Between levels a wave issues the parent's tree links before it
+// waits for its own stores, and every load of the parent's inputs at once after the
+// arrival counter; the cell index and the child count are wave-uniform throughout.
 template <int P>
 __global__ void __launch_bounds__(kWave)
 k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
@@ -159,53 +241,78 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
                 const int32_t *__restrict__ c_level, const int32_t *__restrict__ c_first,
                 const int32_t *__restrict__ c_count, const int32_t *__restrict__ c_child,
                 const int32_t *__restrict__ c_nchild, const int32_t *__restrict__ c_parent,
-                int32_t *c_arrive, double4 *gcell, double *c_mass, double *c_rmax,
+                int32_t *c_arrive, int32_t *climb_next, double4 *gcell, double *c_mass,
+                double *c_rmax,
                 double *mult, float *mult32, const uint16_t *__restrict__ seg,
                 const double *__restrict__ disk_L) {
     constexpr int NM = n_mult(P);
     constexpr int NP = P > 1 ? P : 1;               // powers 0..P-1
     constexpr int NMS = NM > 0 ? NM : 1;
-    // LDS, reused between the two phases: the leaf (P2M) holds scaled powers and
-    // masses of kPowChunk moonlets, a parent (M2M) the powers of its <= 8 children's
-    // offsets and their moments (placed after those 8 entries)
+    constexpr int NE = off_order(P) > 0 ? off_order(P) : 1;   // exponents of order < P
+    static_assert(NE <= kWave && NM <= kWave, "one lane per exponent and per slot");
+    // LDS, reused between the phases: the leaf's centre of mass stages (1, x, y, z)
+    // and the masses of 64 moonlets, its P2M the scaled powers and masses of
+    // kPowChunk moonlets; a parent (M2M) the powers of its <= 8 children's offsets,
+    // then their products U[child][e] and the children's moments
+    constexpr int kComDbl = kWave * 5;
     constexpr int kLeafDbl = kPowChunk * 3 * NP + kPowChunk;
-    constexpr int kParentDbl = 8 * 3 * NP + 8 * NMS;
-    __shared__ double buf[kLeafDbl > kParentDbl ? kLeafDbl : kParentDbl];
+    constexpr int kParentDbl = 8 * NE + 8 * NMS;
+    constexpr int kA = kComDbl > kLeafDbl ? kComDbl : kLeafDbl;
+    constexpr int kB = kParentDbl > 8 * 3 * NP ? kParentDbl : 8 * 3 * NP;
+    __shared__ double buf[kA > kB ? kA : kB];
+    double (*sq)[4] = reinterpret_cast<double (*)[4]>(buf);           // leaf COM: (1, x, y, z)
+    double *sqm = buf + kWave * 4;                                    // leaf COM: masses
     double (*pw)[3][NP] = reinterpret_cast<double (*)[3][NP]>(buf);   // [moonlet/child][axis][k]
-    double *smu = buf + kPowChunk * 3 * NP;                           // leaf: moonlet masses
-    double (*cm)[NMS] = reinterpret_cast<double (*)[NMS]>(buf + 8 * 3 * NP);  // parent
-    __shared__ uint16_t sterm[ShiftTerms<P>::NT];   // shift terms (from constant memory)
+    double *smu = buf + kPowChunk * 3 * NP;                           // leaf P2M: masses
+    double (*ue)[NE] = reinterpret_cast<double (*)[NE]>(buf);         // parent: U[child][e]
+    double (*cm)[NMS] = reinterpret_cast<double (*)[NMS]>(buf + 8 * NE);  // parent: moments
+    __shared__ uint16_t sterm[ShiftTerms<P>::NT + 1];   // shift terms (from constant memory)
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     const double L = st->L;
     const int lane = threadIdx.x;
-    int ja = 0, jb = 0, jc = 0, t0 = 0, t1 = 0;
+    int ja = 0, jb = 0, jc = 0, t0 = 0, t1 = 0, ea = 0, eb = 0, ec = 0;
     if (lane < NM) {
         mult_index(lane, ja, jb, jc);
         t0 = kShift<P>.first[lane];
         t1 = kShift<P>.first[lane + 1];
     }
+    if (lane < NE) sidx_inverse(lane, ea, eb, ec);
     for (int t = lane; t < ShiftTerms<P>::NT; t += kWave) sterm[t] = kShift<P>.term[t];
+    if (lane == 0) sterm[ShiftTerms<P>::NT] = 0;
     __syncthreads();
-    for (int e = blockIdx.x; e < K; e += gridDim.x) {
-        int c = ent_cell[e];
-        // ---- leaf: moonlets f .. f+cnt-1, 64 per chunk
+    const int per = (K + kXcds - 1) / kXcds;       // leaves per XCD slice
+    const int xcd = (int)blockIdx.x % kXcds;
+    int32_t *ctr = climb_next + xcd * kCtrStride;
+    int nxt = (int)blockIdx.x / kXcds;             // first round: one leaf per wave, no counter
+    for (;;) {
+        const int i = __builtin_amdgcn_readlane(nxt, 0);
+        const int e = xcd * per + i;
+        if (i >= per || e >= K) break;
+        nxt = take_leaf(ctr);                       // the next one, in flight meanwhile
+        int c = __builtin_amdgcn_readfirstlane(ent_cell[e]);
+        int par = __builtin_amdgcn_readfirstlane(c_parent[c]);
+        // ---- leaf: moonlets f .. f+cnt-1
         {
-            const int f = c_first[c], cnt = c_count[c];
-            double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+            const int f = __builtin_amdgcn_readfirstlane(c_first[c]);
+            const int cnt = __builtin_amdgcn_readfirstlane(c_count[c]);
+            double acc4 = 0.0;
             for (int c0 = 0; c0 < cnt; c0 += kWave) {
-                const int k = f + c0 + (c0 + lane < cnt ? lane : 0);
+                const bool in = c0 + lane < cnt;
+                const int k = f + c0 + (in ? lane : 0);
                 const double mu = mus[k], x = xs[k], y = ys[k], z = zs[k];
+                __syncthreads();
+                sq[lane][0] = 1.0; sq[lane][1] = x; sq[lane][2] = y; sq[lane][3] = z;
+                sqm[lane] = mu;
+                __syncthreads();
                 const int nk = cnt - c0 < kWave ? cnt - c0 : kWave;
-                for (int q = 0; q < nk; q++) {
-                    const double m = rl(mu, q);
-                    M += m;
-                    sx += m * rl(x, q);
-                    sy += m * rl(y, q);
-                    sz += m * rl(z, q);
+                if (lane < 4) {
+#pragma unroll 8
+                    for (int q = 0; q < nk; q++) acc4 += sqm[q] * sq[q][lane];
                 }
             }
-            sx = sx / M; sy = sy / M; sz = sz / M;
+            const double M = rl(acc4, 0);
+            const double sx = rl(acc4, 1) / M, sy = rl(acc4, 2) / M, sz = rl(acc4, 3) / M;
             double rm = 0.0, acc = 0.0;
             for (int c0 = 0; c0 < cnt; c0 += kPowChunk) {
                 const bool in = lane < kPowChunk && c0 + lane < cnt;
@@ -255,36 +362,45 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
             }
         }
         // ---- walk up while this wave is the last child to arrive
-        for (int up = 0; up < kMaxDepth; up++) {      // at most one step per level
-            const int par = c_parent[c];
-            if (par < 0) break;
-            if (!arrive_last(&c_arrive[par], c_nchild[par])) break;
+        for (int up = 0; up < kMaxDepth && par >= 0; up++) {   // one step per level
+            // the parent's tree links are fixed during the climb: plain loads, in flight
+            // while this wave's stores complete
+            const int a0 = __builtin_amdgcn_readfirstlane(c_child[par]);
+            const int nch = __builtin_amdgcn_readfirstlane(c_nchild[par]);
+            const int f = __builtin_amdgcn_readfirstlane(c_first[par]);
+            const int lev = __builtin_amdgcn_readfirstlane(c_level[par]);
+            const int gpar = __builtin_amdgcn_readfirstlane(c_parent[par]);
+            if (!arrive_last(&c_arrive[par], nch)) break;
             c = par;
-            const int a0 = c_child[c], nch = c_nchild[c];
+            par = gpar;
             const bool in = lane < nch;
             const int a = a0 + (in ? lane : 0);
             const double ma_ = ld_c(&c_mass[a]);
-            const double4 ga = make_double4(ld_c(&gcell[a].x), ld_c(&gcell[a].y),
-                                            ld_c(&gcell[a].z), 0.0);
+            const double gx = ld_c(&gcell[a].x), gy = ld_c(&gcell[a].y), gz = ld_c(&gcell[a].z);
             const double ra = ld_c(&c_rmax[a]);
+            double mq[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++)
+                mq[q] = (NM > 0 && q < nch && lane < NM)
+                            ? ld_c(&mult[(int64_t)(a0 + q) * NM + lane]) : 0.0;
+            const double px = xs[f], py = ys[f], pz = zs[f];
+            const double Lc = seg ? disk_L[seg[f]] : L;
             double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
             for (int q = 0; q < nch; q++) M += rl(ma_, q);
             for (int q = 0; q < nch; q++) {
                 const double m = rl(ma_, q);
-                sx += m * rl(ga.x, q);
-                sy += m * rl(ga.y, q);
-                sz += m * rl(ga.z, q);
+                sx += m * rl(gx, q);
+                sy += m * rl(gy, q);
+                sz += m * rl(gz, q);
             }
             sx = sx / M; sy = sy / M; sz = sz / M;
             double rm = 0.0;
             if (in) {
-                const double d = ra + dist3(ga.x, ga.y, ga.z, sx, sy, sz);
+                const double d = ra + dist3(gx, gy, gz, sx, sy, sz);
                 if (d > rm) rm = d;
             }
             rm = wave_max(rm);
-            const int f = c_first[c];
-            const double fc = far_corner(sx, sy, sz, xs[f], ys[f], zs[f], c_level[c],
-                                         seg ? disk_L[seg[f]] : L);
+            const double fc = far_corner(sx, sy, sz, px, py, pz, lev, Lc);
             if (fc < rm) rm = fc;
             if (lane == 0) {
                 st_c(&gcell[c].x, sx); st_c(&gcell[c].y, sy); st_c(&gcell[c].z, sz);
@@ -294,11 +410,9 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
             }
             if (NM > 0) {
                 __syncthreads();
-                // children's moments, and u^k/k! of each child's offset (lane = child)
-                for (int q = 0; q < nch; q++)
-                    if (lane < NM) cm[q][lane] = ld_c(&mult[(int64_t)(a0 + q) * NM + lane]);
+                // u^k/k! of each child's offset (lane = child)
                 if (in) {
-                    const double ux = ga.x - sx, uy = ga.y - sy, uz = ga.z - sz;
+                    const double ux = gx - sx, uy = gy - sy, uz = gz - sz;
                     double tx = 1.0, ty = 1.0, tz = 1.0;
                     pw[lane][0][0] = 1.0; pw[lane][1][0] = 1.0; pw[lane][2][0] = 1.0;
 #pragma unroll
@@ -310,17 +424,23 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
                     }
                 }
                 __syncthreads();
-                if (lane < NM) {
-                    double acc = 0.0;
-                    for (int t = t0; t < t1; t++) {
-                        const int w = sterm[t];
-                        const int src = w & 63, ea = (w >> 6) & 7, eb = (w >> 9) & 7,
-                                  ec = (w >> 12) & 7;
+                // U[child][e] = u^e/e!, lane = e
+                double u[8];
 #pragma unroll
-                        for (int q = 0; q < 8; q++)
-                            if (q < nch)
-                                acc += cm[q][src] * (pw[q][0][ea] * pw[q][1][eb] * pw[q][2][ec]);
-                    }
+                for (int q = 0; q < 8; q++)
+                    u[q] = (q < nch && lane < NE)
+                               ? pw[q][0][ea] * pw[q][1][eb] * pw[q][2][ec] : 0.0;
+                __syncthreads();
+                const int nq = nch <= 4 ? 4 : 8;   // staged children, zeros past nch
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    if (q < nq && lane < NE) ue[q][lane] = u[q];
+                    if (q < nq && lane < NM) cm[q][lane] = mq[q];
+                }
+                __syncthreads();
+                if (lane < NM) {
+                    const double acc = nq == 4 ? m2m_terms<4, NE, NMS>(sterm, t0, t1, cm, ue)
+                                               : m2m_terms<8, NE, NMS>(sterm, t0, t1, cm, ue);
                     st_c(&mult[(int64_t)c * NM + lane], acc);
                     mult32[(int64_t)c * NM + lane] = (float)acc;
                 }
@@ -396,10 +516,13 @@ __global__ void k_pack_collision(const DevState *__restrict__ st, const double4 
     }
 }
 
-__global__ void k_arrive_reset(const DevState *__restrict__ st, int32_t *c_arrive) {
+__global__ void k_arrive_reset(const DevState *__restrict__ st, int32_t *c_arrive,
+                               int32_t *climb_next) {
     const int nc = st->ncells;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
         c_arrive[c] = 0;
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < kXcds * kCtrStride; t += blockDim.x) climb_next[t] = 0;
 }
 
 static int cell_grid(int64_t cap, int block) {
@@ -409,10 +532,11 @@ static int cell_grid(int64_t cap, int block) {
 
 template <int P>
 static void launch_gc(const Workspace &ws, hipStream_t s) {
-    const int g = (int)(ws.leaf_cap < 65536 ? (ws.leaf_cap < 1 ? 1 : ws.leaf_cap) : 65536);
+    const int g = climb_grid<P>((const void *)k_gravity_climb<P>, ws.leaf_cap);
     k_gravity_climb<P><<<g, kWave, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.mus, ws.ent_cell,
                                          ws.c_level, ws.c_first, ws.c_count, ws.c_child,
-                                         ws.c_nchild, ws.c_parent, ws.c_arrive, ws.gcell,
+                                         ws.c_nchild, ws.c_parent, ws.c_arrive, ws.climb_next,
+                                         ws.gcell,
                                          ws.c_mass, ws.c_rmax, ws.mult, ws.mult32,
                                          ws.ndisks > 1 ? ws.seg : nullptr, ws.disk_L);
 }
@@ -420,7 +544,8 @@ static void launch_gc(const Workspace &ws, hipStream_t s) {
 hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_params &prm,
                                 hipStream_t s) {
     (void)n;
-    k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive);
+    k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive,
+                                                               ws.climb_next);
     switch (prm.p) {
         case 0: launch_gc<0>(ws, s); break;
         case 1: launch_gc<1>(ws, s); break;
@@ -450,7 +575,8 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
                   const int32_t *__restrict__ ent_cell, const int32_t *__restrict__ c_level,
                   const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_count,
                   const int32_t *__restrict__ c_child, const int32_t *__restrict__ c_nchild,
-                  const int32_t *__restrict__ c_parent, int32_t *c_arrive, double4 *ccell,
+                  const int32_t *__restrict__ c_parent, int32_t *c_arrive,
+                  int32_t *climb_next, double4 *ccell,
                   double *c_crmax,
                   const uint16_t *__restrict__ seg, const double *__restrict__ disk_L,
                   double4 *__restrict__ pcol) {
@@ -458,7 +584,15 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
     const int K = st->nleaves;
     const double L = st->L;
     const int lane = threadIdx.x;
-    for (int e = blockIdx.x; e < K; e += gridDim.x) {
+    const int per = (K + kXcds - 1) / kXcds;       // leaves per XCD slice
+    const int xcd = (int)blockIdx.x % kXcds;
+    int32_t *ctr = climb_next + xcd * kCtrStride;
+    int nxt = (int)blockIdx.x / kXcds;             // first round: one leaf per wave, no counter
+    for (;;) {
+        const int i = __builtin_amdgcn_readlane(nxt, 0);
+        const int e = xcd * per + i;
+        if (i >= per || e >= K) break;
+        nxt = take_leaf(ctr);                       // the next one, in flight meanwhile
         int c = ent_cell[e];
         {
             const int f = c_first[c], cnt = c_count[c];
@@ -543,11 +677,13 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
 
 hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hipStream_t s) {
     (void)n;
-    k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive);
-    const int g = (int)(ws.leaf_cap < 65536 ? (ws.leaf_cap < 1 ? 1 : ws.leaf_cap) : 65536);
+    k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive,
+                                                               ws.climb_next);
+    const int g = climb_grid<100>((const void *)k_collision_climb, ws.leaf_cap);
     k_collision_climb<<<g, kWave, 0, s>>>(
         ws.st, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, dt, ws.ent_cell, ws.c_level,
-        ws.c_first, ws.c_count, ws.c_child, ws.c_nchild, ws.c_parent, ws.c_arrive, ws.ccell,
+        ws.c_first, ws.c_count, ws.c_child, ws.c_nchild, ws.c_parent, ws.c_arrive,
+        ws.climb_next, ws.ccell,
         ws.c_crmax, ws.ndisks > 1 ? ws.seg : nullptr, ws.disk_L, ws.pcol);
     k_pack_collision<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.ccell, ws.c_count,
                                                                  ws.c_child, ws.c_nchild, ws.wc,

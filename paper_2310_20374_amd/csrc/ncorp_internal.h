@@ -13,6 +13,9 @@ namespace ncorp {
 constexpr int kMaxDepth = 21;          // 63-bit keys: 21 levels of 3 bits
 constexpr int kMaxP = 6;
 constexpr int kWave = 64;
+// The hardware deals the workgroups of a launch to the 8 XCDs in turn (workgroup b
+// runs on XCD b mod 8), and each XCD has its own L2.
+constexpr int kXcds = 8;
 
 // ---------------------------------------------------------------- tensor sizes
 // Symmetric tensors are stored per order n as the (n+1)(n+2)/2 components
@@ -270,6 +273,7 @@ struct Workspace {
     int32_t *c_nent = nullptr;                        // number of leaves below
     uint64_t *c_prefix = nullptr;
     int32_t *c_arrive = nullptr;                      // climb counters
+    int32_t *climb_next = nullptr;   // climbs: next leaf of each XCD slice (kXcds x 32)
     double4 *gcell = nullptr;                         // s_x, s_y, s_z, r_crit
     double *c_mass = nullptr, *c_rmax = nullptr, *c_theta = nullptr;
     double *mult = nullptr;                           // cell_cap x nm (FP64)
