@@ -253,7 +253,7 @@ __device__ __forceinline__ void push_children(const Item &it, uint64_t my, const
 // make a stream of appends -- a well-separated pair one to each cell's M2L list, a
 // direct-sum pair one to the list of every leaf below either cell -- whose counter
 // atomics are issued kAppendBatch at a time, so their latencies overlap.
-constexpr int kAppendBatch = 4;
+constexpr int kAppendBatch = 8;
 
 template <int IPL>
 __device__ __forceinline__ void append_targets(const Item (&it)[IPL], const WalkArgs &A) {
