@@ -361,9 +361,12 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
             }
             if (!__any(any_valid)) {
                 // nothing arrived: the walk is over once every pushed item has
-                // been processed (slots beyond the queue were never written)
+                // been processed (slots beyond the queue were never written).  Idle
+                // waves read the shared word only every 8th empty poll and sleep longer
+                // the longer they find nothing, so the working waves' atomics on it
+                // and their loads meet less traffic.
                 int done = 0;
-                if (lane == 0) {
+                if ((spins & 7) == 0 && lane == 0) {
                     const uint64_t v = __hip_atomic_load(&wq->tp, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
                     const uint64_t pr = v & 0xffffffffull;
@@ -378,7 +381,8 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
                     finished = true;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(4);
+                const int nap = spins < 4 ? 1 : (spins < 16 ? 4 : 16);
+                for (int z = 0; z < nap; z++) __builtin_amdgcn_s_sleep(4);
                 continue;
             }
             spins = 0;
