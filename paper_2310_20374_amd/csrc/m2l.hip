@@ -22,11 +22,15 @@ template <int P, typename T> struct M2LSplit { static constexpr int K1 = P, K2 =
 template <> struct M2LSplit<6, double> { static constexpr int K1 = 3, K2 = 5; };
 template <> struct M2LSplit<5, double> { static constexpr int K1 = 3, K2 = 5; };
 
-// Row stride (elements) of the wave-sum buffer: the whole C of a lane when one pass
-// covers every order, else one order; odd, so a lane's row and a column are both
-// free of bank conflicts.
+// Components of C staged per round of the wave sum when one pass covers every order:
+// half of them, so the buffer (and the occupancy it limits) is half as large.
+template <int P> constexpr int red_chunk() { return (n_local(P) + 1) / 2; }
+
+// Row stride (elements) of the wave-sum buffer: one round's components when one pass
+// covers every order, else one order; odd, so a lane's row and a column are both free
+// of bank conflicts.
 template <int P, typename T> constexpr int red_stride() {
-    return (M2LSplit<P, T>::K1 == P ? n_local(P) : ncomp(P)) | 1;
+    return (M2LSplit<P, T>::K1 == P ? red_chunk<P>() : ncomp(P)) | 1;
 }
 
 // one pass over a target's sources for the output orders MLO..MHI
@@ -53,16 +57,23 @@ __device__ __forceinline__ void m2l_pass(const double4 gA, const double4 *__rest
     }
     // wave sum of every component in lane order (FP64)
     if constexpr (MLO == 1 && MHI == P && M2LSplit<P, T>::K1 == P) {
-        // all orders at once: lane k sums component k (and k + 64)
+        // all orders at once, in two rounds of CH components: lane k sums component
+        // c0 + k of the round
+        constexpr int CH = red_chunk<P>();
 #pragma unroll
-        for (int k = 0; k < NA; k++) red[lane * RS + k] = acc[k];
-        __syncthreads();
-        for (int k = lane; k < NA; k += kWave) {
-            double s = 0.0;
-            for (int l = 0; l < kWave; l++) s += (double)red[l * RS + k];
-            out[cidx(MLO, 0, 0) + k] = s;
+        for (int c0 = 0; c0 < NA; c0 += CH) {
+#pragma unroll
+            for (int k = 0; k < CH; k++)
+                if (c0 + k < NA) red[lane * RS + k] = acc[c0 + k];
+            __syncthreads();
+            const int nk = NA - c0 < CH ? NA - c0 : CH;
+            for (int k = lane; k < nk; k += kWave) {
+                double s = 0.0;
+                for (int l = 0; l < kWave; l++) s += (double)red[l * RS + k];
+                out[cidx(MLO, 0, 0) + c0 + k] = s;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     } else {
 #pragma unroll
         for (int m = MLO; m <= MHI; m++) {
