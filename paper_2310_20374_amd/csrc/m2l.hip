@@ -19,7 +19,7 @@ constexpr int kM2LBlock = 64;     // one wave per block, one target per wave
 // FP64 at high order splits the output orders over passes (D is recomputed per
 // pass) so that the accumulators and D stay in registers.
 template <int P, typename T> struct M2LSplit { static constexpr int K1 = P, K2 = P; };
-template <> struct M2LSplit<6, double> { static constexpr int K1 = 3, K2 = 5; };
+template <> struct M2LSplit<6, double> { static constexpr int K1 = 4, K2 = 5; };
 template <> struct M2LSplit<5, double> { static constexpr int K1 = 3, K2 = 5; };
 
 // Components of C staged per round of the wave sum when one pass covers every order:
