@@ -483,19 +483,16 @@ k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const double *__restrict__ part, int64_t n, double *__restrict__ ax,
       double *__restrict__ ay, double *__restrict__ az) {
     constexpr int NL = n_local(P);
-    __shared__ double cl_all[kL2PWaves][NL];
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    double *cl = cl_all[wid];
     for (int e = blockIdx.x * kL2PWaves + wid; e < K; e += gridDim.x * kL2PWaves) {
         const int c = ent_cell[e];
         const int f = c_first[c], nt = c_count[c];
         const double4 g = gcell[c];
         const bool longlist = p2p_cnt[e] > kP2PListLDS;   // direct sums in kLongSlots parts
-        wave_sync();
-        for (int k = lane; k < NL; k += 64) cl[k] = cleaf[(int64_t)e * NL + k];
-        wave_sync();
+        // the leaf's C is wave-uniform: scalar loads, no copy in LDS
+        const double *__restrict__ cle = cleaf + (int64_t)__builtin_amdgcn_readfirstlane(e) * NL;
         for (int t0 = 0; t0 < nt; t0 += 64) {
             const int t = t0 + lane;
             if (t >= nt) continue;
@@ -519,9 +516,9 @@ k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
                     for (int c2 = 0; c2 <= nn - b2; c2++) {
                         const int a2 = nn - b2 - c2;
                         const double w = px[a2] * py[b2] * pz[c2];
-                        lx += cl[cidx(1 + a2, b2, c2)] * w;
-                        ly += cl[cidx(a2, 1 + b2, c2)] * w;
-                        lz += cl[cidx(a2, b2, 1 + c2)] * w;
+                        lx += cle[cidx(1 + a2, b2, c2)] * w;
+                        ly += cle[cidx(a2, 1 + b2, c2)] * w;
+                        lz += cle[cidx(a2, b2, 1 + c2)] * w;
                     }
             double dx = 0.0, dy = 0.0, dz = 0.0;       // direct sums
             if (longlist) {
