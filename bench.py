@@ -42,9 +42,9 @@ FLOPS_PER_INTERACTION = 20  # directed moonlet pair, the usual N-body convention
 # reported only while it is unchanged.
 # Measured per leaf size (the direct sums' work depends on it).
 P2P_TRAFFIC = {"source": "paper_2310_20374_amd/csrc/p2p.hip",
-               "blob": "6ba4f09d4d714dd89f5f307e2771bfad79713ef1",
+               "blob": "1f822c19e629e511ed3d4e4105eaa7751888a34d",
                "fetch_scale": 2.00, "write_scale": 1.00,
-               "by_leaf_size": {96: {"fetch_kib": (198895.1,), "write_kib": (25535.4,)}}}
+               "by_leaf_size": {96: {"fetch_kib": (198986.0,), "write_kib": (25533.7,)}}}
 
 
 def _git_blob(path):
@@ -520,6 +520,9 @@ def main():
                          "each at p = 3 and at --p)")
     ap.add_argument("--batched-only", action="store_true",
                     help="measure only the batched form (its object is printed alone)")
+    ap.add_argument("--clustered-only", action="store_true",
+                    help="measure only the clustered stress workload at --leaf-size (96 when "
+                         "'auto'); its object is printed alone")
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--batched-replays", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -549,8 +552,15 @@ def main():
     if args.batched_only:
         print(json.dumps({"batched": _run_batched(ncorp, args, device)}))
         return 0
-    d = inputs.disk(args.n, seed=0)
     cmode = ncorp.COLLISIONS_RESOLVE if args.collisions == "resolve" else ncorp.COLLISIONS_REPORT
+    if args.clustered_only:
+        s = 96 if args.leaf_size == "auto" else int(args.leaf_size)
+        cl = _run_clustered(ncorp, args, device, s, cmode)
+        for k in ("_d", "_acc", "_pairs"):    # the error and pair checks need the oracle
+            cl.pop(k)
+        print(json.dumps({"clustered": cl}))
+        return 0
+    d = inputs.disk(args.n, seed=0)
     prm64 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP64,
                                  collision_mode=cmode, collision_f=2.0)
     prm32 = ncorp.params_default(args.p, theta_min=args.theta, precision=ncorp.FP32_BULK,
