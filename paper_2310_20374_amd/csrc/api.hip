@@ -453,10 +453,13 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
     return NCORP_OK;
 }
 
-// disk_off: device offsets of a batched call (n_disks + 1 of them), or nullptr
+// disk_off: device offsets of a batched call (n_disks + 1 of them), or nullptr;
+// m: the masses, when the caller has them (the step): G m then comes into tree order
+// with the positions (ws.mus), and the step's gravity evaluation on this tree skips
+// its own gather
 static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const double *z,
                            int64_t n, hipStream_t s, bool fresh, const int64_t *disk_off,
-                           int n_disks) {
+                           int n_disks, const double *m = nullptr) {
     Workspace &ws = c->ws;
     ws.ndisks = disk_off ? n_disks : 1;
     {
@@ -464,7 +467,7 @@ static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const
         if (fresh) HIPCHK(c, launch_reset_state(ws, s));
         else HIPCHK(c, launch_reset_tree_counters(ws, s));
         HIPCHK(c, launch_keys(ws, x, y, z, n, c->prm.root_half_width,
-                              disk_off ? disk_off : nullptr, s));
+                              disk_off ? disk_off : nullptr, m, c->prm.G, s));
     }
     {
         PhaseTimer t(c, NCORP_PHASE_SORT, s);
@@ -477,7 +480,7 @@ static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const
     }
     {
         PhaseTimer t(c, NCORP_PHASE_TREE, s);
-        HIPCHK(c, launch_gather_pos(ws, n, s));
+        HIPCHK(c, launch_gather_pos(ws, n, m != nullptr, s));
         HIPCHK(c, launch_build_tree(ws, n, c->prm.leaf_size, s));
     }
     c->have_tree = true;
@@ -568,8 +571,9 @@ extern "C" int ncorp_build_tree_batched(ncorp_ctx *c, const int64_t *disk_offset
     return build_tree_impl(c, x, y, z, n, (hipStream_t)stream, true, disk_offsets, n_disks);
 }
 
+// mus_packed: the build of the current tree already put G m in ws.mus (the step)
 static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, double *az,
-                        hipStream_t s) {
+                        hipStream_t s, bool mus_packed = false) {
     Workspace &ws = c->ws;
     const int64_t n = c->n;
     if (c->prm.p == 0) {
@@ -597,7 +601,7 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
     }
     {
         PhaseTimer t(c, NCORP_PHASE_GCLIMB, s);
-        HIPCHK(c, launch_gather_scaled(ws, m, c->prm.G, ws.mus, n, s));
+        if (!mus_packed) HIPCHK(c, launch_gather_scaled(ws, m, c->prm.G, ws.mus, n, s));
         HIPCHK(c, launch_gravity_climb(ws, n, c->prm, s));
     }
     if (c->prm.gravity_method == NCORP_GRAVITY_STANDARD_TREE) {
@@ -769,15 +773,16 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
         return fail(c, NCORP_E_UNSUPPORTED, "the mesh module takes plain (not batched) calls");
     auto rebuild = [&](bool fresh) -> int {
         int q = NCORP_OK;
-        if (need_tree && (q = build_tree_impl(c, x, y, z, n, s, fresh, disk_off, n_disks)) !=
-                             NCORP_OK)
+        if (need_tree && (q = build_tree_impl(c, x, y, z, n, s, fresh, disk_off, n_disks,
+                                              mutual ? m : nullptr)) != NCORP_OK)
             return q;
         if (need_mesh) q = build_mesh_impl(c, x, y, z, R, n, s, fresh && !need_tree);
         return q;
     };
     if ((r = rebuild(true)) != NCORP_OK) return r;
     k_zero_cursor<<<1, 64, 0, s>>>(ws.st);
-    if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
+    // each evaluation follows a rebuild that brought G m into tree order
+    if (mutual && (r = gravity_impl(c, m, ax, ay, az, s, true)) != NCORP_OK) return r;
     {
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
         HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, 0.5 * dt,
@@ -792,7 +797,7 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
             HIPCHK(c, launch_drift(x, y, z, vx, vy, vz, n, dt, s));
         }
         if ((r = rebuild(false)) != NCORP_OK) return r;
-        if (mutual && (r = gravity_impl(c, m, ax, ay, az, s)) != NCORP_OK) return r;
+        if (mutual && (r = gravity_impl(c, m, ax, ay, az, s, true)) != NCORP_OK) return r;
         const double h = (k == n_steps - 1) ? 0.5 * dt : dt;
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
         HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, h,

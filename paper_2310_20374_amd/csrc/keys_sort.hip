@@ -249,7 +249,7 @@ __global__ void k_keys(const double *__restrict__ x, const double *__restrict__ 
                        const unsigned long long *__restrict__ mx,
                        const uint16_t *__restrict__ seg, int nd, double *__restrict__ disk_L,
                        DevState *st, uint64_t *__restrict__ keys, uint32_t *__restrict__ idx,
-                       double4 *__restrict__ pack4) {
+                       double4 *__restrict__ pack4, const double *__restrict__ m, double G) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gid < nd) {
         const double L = fixed_L > 0.0 ? fixed_L : root_half_width(mx[gid]);
@@ -264,7 +264,8 @@ __global__ void k_keys(const double *__restrict__ x, const double *__restrict__ 
         keys[i] = hilbert21(quantize(px, L, scale), quantize(py, L, scale),
                             quantize(pz, L, scale));
         idx[i] = (uint32_t)i;
-        pack4[i] = make_double4(px, py, pz, 0.0);   // one record per moonlet for the gather
+        // one record per moonlet for the gather (with G m when the caller has the masses)
+        pack4[i] = make_double4(px, py, pz, m ? G * m[i] : 0.0);
     }
 }
 
@@ -274,7 +275,7 @@ static int disk_passes(int nd) { return nd <= 1 ? 0 : (nd <= 256 ? 1 : 2); }
 
 hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                        const double *z, int64_t n, double root_half_width,
-                       const int64_t *disk_off, hipStream_t s) {
+                       const int64_t *disk_off, const double *m, double G, hipStream_t s) {
     // the sort ends in ws.keys / ws.idx: the bucket sort and an odd number of radix
     // passes start in the other buffers
     const bool odd = bucket_sort_applies(ws, n) || (8 + disk_passes(ws.ndisks)) % 2 == 1;
@@ -290,14 +291,14 @@ hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
         const int64_t cover = n > nd ? n : nd;
         k_keys<<<grid_for(cover, 256), 256, 0, s>>>(x, y, z, n, root_half_width, ws.disk_max,
                                                     ws.seg, nd, ws.disk_L, ws.st, kout, vout,
-                                                    ws.pack4);
+                                                    ws.pack4, m, G);
     } else {
         // few blocks: each ends with one atomic on the same word
         k_max_abs<<<grid_for(n, 256, 256), 256, 0, s>>>(x, y, z, n, ws.st);
         k_keys<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, n, root_half_width,
                                                 (const unsigned long long *)&ws.st->max_abs,
                                                 nullptr, 1, ws.disk_L, ws.st, kout, vout,
-                                                ws.pack4);
+                                                ws.pack4, m, G);
     }
     return hipGetLastError();
 }
@@ -540,16 +541,18 @@ hipError_t launch_radix_sort(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t 
 
 // ------------------------------------------------------------------ gathers
 // Positions in tree order from the packed records k_keys wrote in input order: one
-// 32-byte record per moonlet instead of three scattered 8-byte words.
+// 32-byte record per moonlet instead of three scattered 8-byte words (and the scaled
+// masses G m from the same record, when k_keys had them: mus != nullptr).
 __global__ void k_gather_pack4(const double4 *__restrict__ pack4, const uint32_t *__restrict__ idx,
                               int64_t n, double *__restrict__ xs, double *__restrict__ ys,
-                              double *__restrict__ zs) {
+                              double *__restrict__ zs, double *__restrict__ mus) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double4 p = pack4[idx[i]];
         xs[i] = p.x;
         ys[i] = p.y;
         zs[i] = p.z;
+        if (mus) mus[i] = p.w;
     }
 }
 
@@ -560,8 +563,9 @@ __global__ void k_gather1(const double *__restrict__ src, const uint32_t *__rest
         dst[i] = src[idx[i]];
 }
 
-hipError_t launch_gather_pos(const Workspace &ws, int64_t n, hipStream_t s) {
-    k_gather_pack4<<<grid_for(n, 256), 256, 0, s>>>(ws.pack4, ws.idx, n, ws.xs, ws.ys, ws.zs);
+hipError_t launch_gather_pos(const Workspace &ws, int64_t n, bool with_mus, hipStream_t s) {
+    k_gather_pack4<<<grid_for(n, 256), 256, 0, s>>>(ws.pack4, ws.idx, n, ws.xs, ws.ys, ws.zs,
+                                                    with_mus ? ws.mus : nullptr);
     return hipGetLastError();
 }
 

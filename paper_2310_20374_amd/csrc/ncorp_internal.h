@@ -361,16 +361,18 @@ hipError_t launch_reset_state(const Workspace &ws, hipStream_t s);
 hipError_t launch_reset_tree_counters(const Workspace &ws, hipStream_t s);
 hipError_t launch_gather_scaled(const Workspace &ws, const double *src, double scale,
                                 double *dst, int64_t n, hipStream_t s);
-// disk_off: n_disks + 1 device offsets of a batched call (nullptr for a plain call)
+// disk_off: n_disks + 1 device offsets of a batched call (nullptr for a plain call);
+// m: masses (input order) to pack as G m beside the positions, or nullptr
 hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                        const double *z, int64_t n, double root_half_width,
-                       const int64_t *disk_off, hipStream_t s);
+                       const int64_t *disk_off, const double *m, double G, hipStream_t s);
 hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s);
 // plain builds of up to kMaxBuckets buckets use the bucket sort (launch_keys then
 // writes where it starts)
 bool bucket_sort_applies(const Workspace &ws, int64_t n);
 hipError_t launch_bucket_sort(const Workspace &ws, int64_t n, hipStream_t s);
-hipError_t launch_gather_pos(const Workspace &ws, int64_t n, hipStream_t s);
+// with_mus: the keys packed G m, which lands in ws.mus too
+hipError_t launch_gather_pos(const Workspace &ws, int64_t n, bool with_mus, hipStream_t s);
 hipError_t launch_gather(const Workspace &ws, const double *src, double *dst, int64_t n,
                          hipStream_t s);
 // velocities and radii into tree order, one pass
