@@ -648,6 +648,9 @@ k_leaf_boxes(DevState *st, const double *__restrict__ xs, const double *__restri
 __global__ void __launch_bounds__(1024)
 k_max_u64(const unsigned long long *__restrict__ part, int64_t n, DevState *st) {
     __shared__ unsigned long long red[1024 / kWave];
+    // the box pass precedes every search on the gravity lists: the pair and test
+    // counts of that search start here
+    if (threadIdx.x == 0) { st->npairs = 0; st->col_tests = 0; }
     unsigned long long v = 0;
     for (int64_t i = threadIdx.x; i < n; i += 1024) v = part[i] > v ? part[i] : v;
     for (int o = 32; o > 0; o >>= 1) {
@@ -1102,7 +1105,7 @@ hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, 
 hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, bool boxes,
                                 hipStream_t s) {
     (void)n;
-    k_collide_init<<<1, 64, 0, s>>>(ws.st);
+    if (!boxes) k_collide_init<<<1, 64, 0, s>>>(ws.st);   // boxes: done by the box pass
     if (boxes) {
         k_collide<true><<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count,
                                              ws.ccell, ws.cbox, ws.idx, ws.pcol, ws.vcol,

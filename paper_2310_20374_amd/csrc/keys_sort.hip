@@ -22,15 +22,6 @@ hipError_t launch_reset_state(const Workspace &ws, hipStream_t s) {
     return hipGetLastError();
 }
 
-// before every (re)build: only what the build accumulates into
-__global__ void k_reset_tree_counters(DevState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->max_abs = 0.0;
-}
-
-hipError_t launch_reset_tree_counters(const Workspace &ws, hipStream_t s) {
-    k_reset_tree_counters<<<1, 64, 0, s>>>(ws.st);
-    return hipGetLastError();
-}
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;

@@ -358,7 +358,6 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max,
 // ---------------------------------------------------------------- launchers
 // (each returns hipSuccess or the first launch error)
 hipError_t launch_reset_state(const Workspace &ws, hipStream_t s);
-hipError_t launch_reset_tree_counters(const Workspace &ws, hipStream_t s);
 hipError_t launch_gather_scaled(const Workspace &ws, const double *src, double scale,
                                 double *dst, int64_t n, hipStream_t s);
 // disk_off: n_disks + 1 device offsets of a batched call (nullptr for a plain call);

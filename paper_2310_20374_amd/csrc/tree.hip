@@ -292,11 +292,15 @@ __global__ void k_cell_ranges(const DevState *__restrict__ st, int64_t n,
     }
 }
 
-// an overflowed tree is unusable: expose no cells or leaves to later passes
+// an overflowed tree is unusable: expose no cells or leaves to later passes.  Also
+// clears the coordinate maximum the key pass accumulates into, for the next build.
 __global__ void k_tree_guard(DevState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && (st->status & ST_CAP_CELLS)) {
-        st->ncells = 0;
-        st->nleaves = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (st->status & ST_CAP_CELLS) {
+            st->ncells = 0;
+            st->nleaves = 0;
+        }
+        st->max_abs = 0.0;
     }
 }
 
