@@ -431,35 +431,48 @@ hipError_t launch_collide_reset(const Workspace &ws, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Rank sort of the (distinct) pair keys: rank = number of smaller keys.  One wave per
-// 64 keys (a lane each); the wave walks the whole list in chunks of 256 keys, loaded
-// coalesced (the next chunk while the current one is compared) and read back from
-// LDS as wave-wide broadcasts.
+// Rank sort of the (distinct) pair keys: rank = number of smaller keys.  A block of
+// kRankSplit waves takes 64 keys (a lane each); wave w counts the smaller keys in the
+// w-th of kRankSplit equal segments of the list, walking it in chunks of 256 keys
+// loaded coalesced (the next chunk while the current one is compared) and read back
+// from LDS as wave-wide broadcasts; the block then adds the counts of its waves.
+constexpr int kRankSplit = 8;
 constexpr int kRankGrid = 2048;
 constexpr int kRankChunk = 4 * kWave;
-__global__ void __launch_bounds__(kWave)
+__global__ void __launch_bounds__(kWave * kRankSplit)
 k_rank_pairs(const DevState *__restrict__ st, const int64_t *__restrict__ in, int64_t cap,
              int64_t *__restrict__ out) {
-    __shared__ int64_t tile[kRankChunk];
+    __shared__ int64_t tile_all[kRankSplit][kRankChunk];
+    __shared__ int64_t part[kRankSplit][kWave];
     int64_t n = st->npairs;
     if (n > cap) n = cap;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int64_t *tile = tile_all[w];
+    // this wave's segment of the list
+    const int64_t seg = (n + kRankSplit - 1) / kRankSplit;
+    const int64_t s0 = seg * w < n ? seg * w : n;
+    const int64_t s1 = s0 + seg < n ? s0 + seg : n;
     for (int64_t base = (int64_t)blockIdx.x * kWave; base < n; base += (int64_t)gridDim.x * kWave) {
         const int64_t i = base + lane;
         const int64_t v = i < n ? in[i] : INT64_MAX;
         int64_t r0 = 0, r1 = 0;
         int64_t nxt[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) nxt[u] = u * kWave + lane < n ? in[u * kWave + lane] : INT64_MAX;
-        for (int64_t t0 = 0; t0 < n; t0 += kRankChunk) {
+        for (int u = 0; u < 4; u++) {
+            const int64_t q = s0 + u * kWave + lane;
+            nxt[u] = q < s1 ? in[q] : INT64_MAX;
+        }
+        for (int64_t t0 = s0; t0 < s1; t0 += kRankChunk) {
             wave_sync();
 #pragma unroll
             for (int u = 0; u < 4; u++) tile[u * kWave + lane] = nxt[u];
             wave_sync();
             const int64_t t1 = t0 + kRankChunk;
 #pragma unroll
-            for (int u = 0; u < 4; u++)
-                nxt[u] = t1 + u * kWave + lane < n ? in[t1 + u * kWave + lane] : INT64_MAX;
+            for (int u = 0; u < 4; u++) {
+                const int64_t q = t1 + u * kWave + lane;
+                nxt[u] = q < s1 ? in[q] : INT64_MAX;
+            }
             // padding keys (INT64_MAX) are never below a real key
 #pragma unroll 8
             for (int k = 0; k < kRankChunk; k += 2) {
@@ -467,7 +480,15 @@ k_rank_pairs(const DevState *__restrict__ st, const int64_t *__restrict__ in, in
                 r1 += tile[k + 1] < v;
             }
         }
-        if (i < n) out[r0 + r1] = v;
+        part[w][lane] = r0 + r1;
+        __syncthreads();
+        if (w == 0 && i < n) {
+            int64_t r = 0;
+#pragma unroll
+            for (int k = 0; k < kRankSplit; k++) r += part[k][lane];
+            out[r] = v;
+        }
+        __syncthreads();
     }
 }
 
@@ -1088,7 +1109,8 @@ hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, 
                           double *vy, double *vz, const double *m, const double *R, double dt,
                           double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
                           int64_t *cursor, hipStream_t s) {
-    k_rank_pairs<<<kRankGrid, kWave, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap, ws.pairs_alt);
+    k_rank_pairs<<<kRankGrid, kWave * kRankSplit, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap,
+                                                          ws.pairs_alt);
     k_resolve_init<<<kResolveGrid, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, x, y, z, vx,
                                                 vy, vz, R, dt, ws.pair_dt, ws.pair_flag,
                                                 ws.mmatch);
@@ -1125,7 +1147,8 @@ hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, bool 
 hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,
                              int64_t *n_pairs_dev, int triple, int step, int64_t *cursor,
                              hipStream_t s) {
-    k_rank_pairs<<<kRankGrid, kWave, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap, ws.pairs_alt);
+    k_rank_pairs<<<kRankGrid, kWave * kRankSplit, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap,
+                                                          ws.pairs_alt);
     k_emit_pairs<<<256, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, pairs, cap, n_pairs_dev,
                                      triple, step, cursor);
     k_pairs_done<<<1, 64, 0, s>>>(ws.st, n_pairs_dev, cap, ws.pair_cap, triple, cursor);
