@@ -84,7 +84,7 @@ constexpr int kDefaultM2LPerCell = 2048;
 constexpr int kDefaultP2PPerLeaf = 4096;
 constexpr int kMaxPerTarget = 8192;
 // lists up to these lengths are sorted in LDS by their consumer; longer ones (the
-// walk records them) by a pre-pass of kSortLongBlocks single-wave blocks
+// walk records them) by a pre-pass of kSortLongBlocks single-wave blocks per kind
 constexpr int kM2LListLDS = 512;
 constexpr int kP2PListLDS = kWave;
 constexpr int kSortLongBlocks = 1024;
@@ -193,8 +193,8 @@ struct WalkQueue {
                                // processed (low 32 bits), updated by one atomic
     uint64_t pad1[15];
     uint64_t pad2[16];
-    uint32_t epoch;            // tag of valid items in this walk (advanced on the device)
-    uint32_t wrapped;          // the tag wrapped: the queue must be cleared first
+    uint32_t epoch;            // tag of the last walk's items (advanced on the device)
+    uint32_t epoch_next;       // tag of this walk's items (written by its init pass)
     uint32_t pad3[30];
 };
 

@@ -45,29 +45,30 @@ __device__ __forceinline__ int wave_excl_sum(int v, int lane, int &total) {
     return x - v;
 }
 
-// Advances the queue tag on the device, so a captured and replayed sequence of
-// walks never meets a stale item carrying its own tag.  When the 16-bit tag wraps
-// (or the host asks, for a new buffer) the queue is cleared before the walk.
-__global__ void k_walk_epoch(WalkQueue *wq, int force_clear) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint32_t e = (wq->epoch + 1u) & 0xffffu;
-    uint32_t w = force_clear ? 1u : 0u;
-    if (e == 0u) { e = 1u; w = 1u; }
-    wq->epoch = e;
-    wq->wrapped = w;
+// Every walk tags its items with a fresh 16-bit tag, advanced on the device, so a
+// captured and replayed sequence of walks never meets a stale item carrying its own
+// tag.  The init pass derives the walk's tag from the last walk's (which nothing
+// writes while it runs) and leaves it in epoch_next, which the walk reads and copies
+// to epoch.  When the tag wraps (or the host asks, for a new buffer) the init pass
+// clears the queue.
+__device__ __forceinline__ uint32_t next_epoch(uint32_t e, bool &wrap) {
+    uint32_t n = (e + 1u) & 0xffffu;
+    wrap = n == 0u;
+    return wrap ? 1u : n;
 }
 
 // Resets the queue (one root pair (r, r) per tree of the forest) and, for the
 // gravity walk, the per-target list counters.
 __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, int64_t qcap,
-                            int mode, int32_t *m2l_cnt, int32_t *p2p_cnt) {
+                            int mode, int32_t *m2l_cnt, int32_t *p2p_cnt, int force_clear) {
     const int nc = st->ncells;
-    const uint32_t epoch = wq->epoch;
+    bool wrap = false;
+    const uint32_t epoch = next_epoch(wq->epoch, wrap);
     const bool go = nc > 0 && !(st->status & kSkipMask);
     const int nroots = go ? st->level_count[0] : 0;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
-    if (wq->wrapped)
+    if (wrap || force_clear)
         for (int64_t i = nroots + gid; i < qcap; i += gstride) queue[i] = 0ull;
     if (mode == 0 && m2l_cnt) {
         const int nl = st->nleaves;
@@ -80,6 +81,7 @@ __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, int64_
         __hip_atomic_store(&queue[r], make_item(epoch, (int)r, (int)r), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     if (gid != 0) return;
+    wq->epoch_next = epoch;
     wq->head = 0;
     if (mode == 0) {
         st->nm2l = 0; st->np2p = 0; st->m2l_slots = 0; st->p2p_slots = 0; st->visited = 0;
@@ -102,7 +104,7 @@ struct WalkArgs {
     int64_t m2l_cap, p2p_cap;
     int32_t *nm2l, *np2p;                // exact counts
     int32_t *m2l_slots, *p2p_slots;      // reserved slots
-    uint32_t epoch;                      // read from the queue state at kernel start
+    uint32_t epoch;                      // this walk's tag, read at kernel start
     // gravity: per-target lists
     int32_t *m2l_cnt, *m2l_seg, *p2p_cnt, *p2p_seg;
     int32_t *long_m2l, *long_p2p;        // targets whose list outgrew the LDS sort
@@ -323,7 +325,8 @@ template <int MODE>
 __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
     constexpr int IPL = kItemsPerLane;
     WalkArgs A = A0;
-    A.epoch = A0.wq->epoch;
+    A.epoch = A0.wq->epoch_next;
+    if (blockIdx.x == 0 && threadIdx.x == 0) A0.wq->epoch = A.epoch;   // nothing here reads it
     const int lane = threadIdx.x % kWave;
     WalkQueue *wq = A.wq;
     const int ncells = A.st->ncells;
@@ -459,10 +462,9 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
 // waves: persistent waves of the gravity walk (the collision walk runs its own count)
 hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post, int waves,
                        hipStream_t s) {
-    k_walk_epoch<<<1, 64, 0, s>>>(ws.wq, ws.clear_queue ? 1 : 0);
-    ws.clear_queue = false;
     k_walk_init<<<1024, 256, 0, s>>>(ws.st, ws.wq, ws.queue, ws.queue_cap, mode, ws.m2l_cnt,
-                                     ws.p2p_cnt);
+                                     ws.p2p_cnt, ws.clear_queue ? 1 : 0);
+    ws.clear_queue = false;
     WalkArgs A = {};
     A.st = ws.st; A.wq = ws.wq; A.queue = ws.queue; A.qcap = ws.queue_cap;
     A.ncs = ncs; A.ncc_pre = ncc_pre; A.ncc_post = ncc_post;
@@ -490,13 +492,22 @@ hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_po
 // Lists too long for the consumers' LDS sort (the walk recorded their targets)
 // are sorted here, in place, one single-wave block per list (rank sort in LDS).
 __global__ void __launch_bounds__(kWave)
-k_sort_long_lists(const DevState *__restrict__ st, int which, const int32_t *__restrict__ cnt,
-                  int32_t *seg, int stride, const int32_t *__restrict__ longs) {
-    extern __shared__ __align__(16) int32_t scr[];   // round_up(stride, 4) ints
+k_sort_long_lists(const DevState *__restrict__ st, const int32_t *__restrict__ m2l_cnt,
+                  int32_t *m2l_seg, int m2l_stride, const int32_t *__restrict__ long_m2l,
+                  const int32_t *__restrict__ p2p_cnt, int32_t *p2p_seg, int p2p_stride,
+                  const int32_t *__restrict__ long_p2p) {
+    extern __shared__ __align__(16) int32_t scr[];   // round_up(largest stride, 4) ints
     if (st->status & kSkipMask) return;
+    // the first half of the blocks sorts the M2L lists, the second the direct-sum lists
+    const int half = (int)gridDim.x / 2;
+    const int which = (int)blockIdx.x < half ? 0 : 1;
+    const int32_t *cnt = which == 0 ? m2l_cnt : p2p_cnt;
+    int32_t *seg = which == 0 ? m2l_seg : p2p_seg;
+    const int stride = which == 0 ? m2l_stride : p2p_stride;
+    const int32_t *longs = which == 0 ? long_m2l : long_p2p;
     const int nl = which == 0 ? st->nlong_m2l : st->nlong_p2p;
     const int lane = threadIdx.x;
-    for (int q = blockIdx.x; q < nl; q += gridDim.x) {
+    for (int q = (int)blockIdx.x - which * half; q < nl; q += half) {
         const int t = longs[q];
         const int len = cnt[t];
         int32_t *list = seg + (int64_t)t * stride;
@@ -571,10 +582,9 @@ hipError_t launch_sort_long_lists(const Workspace &ws, hipStream_t s) {
     if (!ws.m2l_cnt) return hipSuccess;
     const size_t lm = (size_t)((ws.m2l_stride + 3) & ~3) * sizeof(int32_t);
     const size_t lp = (size_t)((ws.p2p_stride + 3) & ~3) * sizeof(int32_t);
-    k_sort_long_lists<<<kSortLongBlocks, kWave, lm, s>>>(ws.st, 0, ws.m2l_cnt, ws.m2l_seg,
-                                                         ws.m2l_stride, ws.long_m2l);
-    k_sort_long_lists<<<kSortLongBlocks, kWave, lp, s>>>(ws.st, 1, ws.p2p_cnt, ws.p2p_seg,
-                                                         ws.p2p_stride, ws.long_p2p);
+    k_sort_long_lists<<<2 * kSortLongBlocks, kWave, lm > lp ? lm : lp, s>>>(
+        ws.st, ws.m2l_cnt, ws.m2l_seg, ws.m2l_stride, ws.long_m2l, ws.p2p_cnt, ws.p2p_seg,
+        ws.p2p_stride, ws.long_p2p);
     return hipGetLastError();
 }
 
