@@ -464,7 +464,7 @@ static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const
     ws.ndisks = disk_off ? n_disks : 1;
     {
         PhaseTimer t(c, NCORP_PHASE_KEYS, s);
-        // a rebuild needs only max_abs cleared, which the last build's guard did
+        // a rebuild needs only max_abs cleared, which the last build's cell-range pass did
         if (fresh) HIPCHK(c, launch_reset_state(ws, s));
         HIPCHK(c, launch_keys(ws, x, y, z, n, c->prm.root_half_width,
                               disk_off ? disk_off : nullptr, m, c->prm.G, s));

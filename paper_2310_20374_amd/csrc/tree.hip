@@ -174,29 +174,14 @@ k_level_scan(int32_t *lcount, const int32_t *nleaves_dev, DevState *st, int64_t 
     if (threadIdx.x == 0) st->level_count[l] = carry;
 }
 
-__global__ void k_level_offsets(DevState *st, int64_t cell_cap) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int32_t off = 0, maxl = 0;
-    for (int l = 0; l < kNLev; l++) {
-        st->level_off[l] = off;
-        off += st->level_count[l];
-        if (st->level_count[l] > 0) maxl = l;
-    }
-    st->level_off[kNLev] = off;
-    st->ncells = off;
-    st->maxlevel = maxl;
-    if (off > cell_cap) {
-        atomicOr(&st->status, (int32_t)ST_CAP_CELLS);
-        atomicMax((unsigned long long *)&st->required, (unsigned long long)off);
-        st->ncells = (int32_t)cell_cap;   // later passes only see what was written
-    }
-}
 
-// every entry writes the cells it starts, with parent / first-child links
+// every entry writes the cells it starts, with parent / first-child links.  Each block
+// forms the level offsets from the level totals itself; block 0 also publishes them
+// with the cell count and depth (and latches an overflow of cell_cap).
 __global__ void __launch_bounds__(kTreeBlock)
 k_emit_cells(const int32_t *__restrict__ ent_start, const uint32_t *__restrict__ ent_code,
              const uint64_t *__restrict__ keys, const int32_t *__restrict__ lcount,
-             const DevState *__restrict__ st, int64_t cell_cap, int32_t *__restrict__ c_level,
+             DevState *st, int64_t cell_cap, int32_t *__restrict__ c_level,
              int32_t *__restrict__ c_first, int32_t *__restrict__ c_child,
              int32_t *__restrict__ c_nchild, int32_t *__restrict__ c_parent,
              int32_t *__restrict__ c_entry, uint64_t *__restrict__ c_prefix,
@@ -206,7 +191,25 @@ k_emit_cells(const int32_t *__restrict__ ent_start, const uint32_t *__restrict__
     __shared__ int32_t loff[kNLev];
     const int K = st->nleaves;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    if (threadIdx.x < kNLev) loff[threadIdx.x] = st->level_off[threadIdx.x];
+    if (threadIdx.x == 0) {
+        int32_t off = 0, maxl = 0;
+        for (int l = 0; l < kNLev; l++) {
+            loff[l] = off;
+            off += st->level_count[l];
+            if (st->level_count[l] > 0) maxl = l;
+        }
+        if (blockIdx.x == 0) {
+            for (int l = 0; l < kNLev; l++) st->level_off[l] = loff[l];
+            st->level_off[kNLev] = off;
+            st->ncells = off;
+            st->maxlevel = maxl;
+            if (off > cell_cap) {
+                atomicOr(&st->status, (int32_t)ST_CAP_CELLS);
+                atomicMax((unsigned long long *)&st->required, (unsigned long long)off);
+                st->ncells = (int32_t)cell_cap;   // later passes only see what was written
+            }
+        }
+    }
     const int64_t e = (int64_t)blockIdx.x * kTreeBlock + threadIdx.x;
     int L = -1, dv = 1, start = 0;
     uint64_t key = 0;
@@ -265,12 +268,23 @@ k_emit_cells(const int32_t *__restrict__ ent_start, const uint32_t *__restrict__
 }
 
 // child counts, moonlet counts and leaf ranges: walk up while this cell (or its
-// ancestor) is the last child; the next sibling then starts where it ends.
-__global__ void k_cell_ranges(const DevState *__restrict__ st, int64_t n,
+// ancestor) is the last child; the next sibling then starts where it ends.  An
+// overflowed tree is unusable: it exposes no cells or leaves to later passes.  Also
+// clears the coordinate maximum the key pass accumulates into, for the next build.
+__global__ void k_cell_ranges(DevState *st, int64_t n,
                               const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_child,
                               const int32_t *__restrict__ c_parent, const int32_t *__restrict__ c_entry,
                               int32_t *__restrict__ c_count, int32_t *__restrict__ c_nchild,
                               int32_t *__restrict__ c_nent) {
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    if (first) st->max_abs = 0.0;
+    if (st->status & ST_CAP_CELLS) {
+        if (first) {
+            st->ncells = 0;
+            st->nleaves = 0;
+        }
+        return;
+    }
     const int nc = st->ncells, K = st->nleaves;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
         int par = c_parent[c];
@@ -292,17 +306,6 @@ __global__ void k_cell_ranges(const DevState *__restrict__ st, int64_t n,
     }
 }
 
-// an overflowed tree is unusable: expose no cells or leaves to later passes.  Also
-// clears the coordinate maximum the key pass accumulates into, for the next build.
-__global__ void k_tree_guard(DevState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (st->status & ST_CAP_CELLS) {
-            st->ncells = 0;
-            st->nleaves = 0;
-        }
-        st->max_abs = 0.0;
-    }
-}
 
 hipError_t launch_build_tree(const Workspace &ws, int64_t n, int s, hipStream_t st) {
     int nb = (int)((n + kTreeBlock - 1) / kTreeBlock);
@@ -317,7 +320,6 @@ hipError_t launch_build_tree(const Workspace &ws, int64_t n, int s, hipStream_t 
     int32_t *lcount = ws.cnt_a;   // nb x kNLev scratch
     k_level_counts<<<nb, kTreeBlock, 0, st>>>(ws.ent_code, &ws.st->nleaves, lcount);
     k_level_scan<<<kNLev, 256, 0, st>>>(lcount, &ws.st->nleaves, ws.st, ws.cell_cap);
-    k_level_offsets<<<1, 64, 0, st>>>(ws.st, ws.cell_cap);
     k_emit_cells<<<nb, kTreeBlock, 0, st>>>(ws.ent_start, ws.ent_code, ws.keys, lcount, ws.st,
                                             ws.cell_cap, ws.c_level, ws.c_first, ws.c_child,
                                             ws.c_nchild, ws.c_parent, ws.c_entry, ws.c_prefix,
@@ -326,7 +328,6 @@ hipError_t launch_build_tree(const Workspace &ws, int64_t n, int s, hipStream_t 
     if (g > 2048) g = 2048;
     k_cell_ranges<<<g, 256, 0, st>>>(ws.st, n, ws.c_first, ws.c_child, ws.c_parent, ws.c_entry,
                                      ws.c_count, ws.c_nchild, ws.c_nent);
-    k_tree_guard<<<1, 64, 0, st>>>(ws.st);
     return hipGetLastError();
 }
 
