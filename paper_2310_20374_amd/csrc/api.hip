@@ -459,15 +459,16 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
 // its own gather
 static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const double *z,
                            int64_t n, hipStream_t s, bool fresh, const int64_t *disk_off,
-                           int n_disks, const double *m = nullptr) {
+                           int n_disks, const double *m = nullptr, bool max_ready = false) {
     Workspace &ws = c->ws;
     ws.ndisks = disk_off ? n_disks : 1;
     {
         PhaseTimer t(c, NCORP_PHASE_KEYS, s);
-        // a rebuild needs only max_abs cleared, which the last build's cell-range pass did
+        // a rebuild needs only max_abs cleared, which the last build's cell-range pass
+        // did (max_ready: a step's drift has since formed it)
         if (fresh) HIPCHK(c, launch_reset_state(ws, s));
         HIPCHK(c, launch_keys(ws, x, y, z, n, c->prm.root_half_width,
-                              disk_off ? disk_off : nullptr, m, c->prm.G, s));
+                              disk_off ? disk_off : nullptr, m, c->prm.G, s, max_ready));
     }
     {
         PhaseTimer t(c, NCORP_PHASE_SORT, s);
@@ -771,10 +772,13 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
     const bool need_tree = (mutual && !mesh_gravity(c->prm)) || !mesh_collisions(c->prm);
     if (need_mesh && disk_off)
         return fail(c, NCORP_E_UNSUPPORTED, "the mesh module takes plain (not batched) calls");
+    // a plain tree build after the drift takes max |coordinate| from the drift
+    const bool drift_max = need_tree && !disk_off;
     auto rebuild = [&](bool fresh) -> int {
         int q = NCORP_OK;
         if (need_tree && (q = build_tree_impl(c, x, y, z, n, s, fresh, disk_off, n_disks,
-                                              mutual ? m : nullptr)) != NCORP_OK)
+                                              mutual ? m : nullptr,
+                                              !fresh && drift_max)) != NCORP_OK)
             return q;
         if (need_mesh) q = build_mesh_impl(c, x, y, z, R, n, s, fresh && !need_tree);
         return q;
@@ -794,7 +798,7 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
         if (r != NCORP_OK) return r;
         {
             PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
-            HIPCHK(c, launch_drift(x, y, z, vx, vy, vz, n, dt, s));
+            HIPCHK(c, launch_drift(x, y, z, vx, vy, vz, n, dt, s, drift_max ? ws.st : nullptr));
         }
         if ((r = rebuild(false)) != NCORP_OK) return r;
         if (mutual && (r = gravity_impl(c, m, ax, ay, az, s, true)) != NCORP_OK) return r;

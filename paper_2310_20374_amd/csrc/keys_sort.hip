@@ -266,7 +266,8 @@ static int disk_passes(int nd) { return nd <= 1 ? 0 : (nd <= 256 ? 1 : 2); }
 
 hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                        const double *z, int64_t n, double root_half_width,
-                       const int64_t *disk_off, const double *m, double G, hipStream_t s) {
+                       const int64_t *disk_off, const double *m, double G, hipStream_t s,
+                       bool max_ready) {
     // the sort ends in ws.keys / ws.idx: the bucket sort and an odd number of radix
     // passes start in the other buffers
     const bool odd = bucket_sort_applies(ws, n) || (8 + disk_passes(ws.ndisks)) % 2 == 1;
@@ -285,7 +286,7 @@ hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                                                     ws.pack4, m, G);
     } else {
         // few blocks: each ends with one atomic on the same word
-        k_max_abs<<<grid_for(n, 256, 256), 256, 0, s>>>(x, y, z, n, ws.st);
+        if (!max_ready) k_max_abs<<<grid_for(n, 256, 256), 256, 0, s>>>(x, y, z, n, ws.st);
         k_keys<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, n, root_half_width,
                                                 (const unsigned long long *)&ws.st->max_abs,
                                                 nullptr, 1, ws.disk_L, ws.st, kout, vout,

@@ -361,10 +361,12 @@ hipError_t launch_reset_state(const Workspace &ws, hipStream_t s);
 hipError_t launch_gather_scaled(const Workspace &ws, const double *src, double scale,
                                 double *dst, int64_t n, hipStream_t s);
 // disk_off: n_disks + 1 device offsets of a batched call (nullptr for a plain call);
-// m: masses (input order) to pack as G m beside the positions, or nullptr
+// m: masses (input order) to pack as G m beside the positions, or nullptr;
+// max_ready (plain calls): the step's drift has already formed max |coordinate|
 hipError_t launch_keys(const Workspace &ws, const double *x, const double *y,
                        const double *z, int64_t n, double root_half_width,
-                       const int64_t *disk_off, const double *m, double G, hipStream_t s);
+                       const int64_t *disk_off, const double *m, double G, hipStream_t s,
+                       bool max_ready = false);
 hipError_t launch_sort(const Workspace &ws, int64_t n, hipStream_t s);
 // plain builds of up to kMaxBuckets buckets use the bucket sort (launch_keys then
 // writes where it starts)
@@ -451,9 +453,11 @@ hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax,
                        const double *ay, const double *az, const double *x,
                        const double *y, const double *z, int64_t n, double h,
                        const CentralBody &b, const double *R, double4 *pack, hipStream_t s);
+// st non-null: also max |coordinate| of the new positions into st->max_abs, as the key
+// pass of a plain build forms it (the previous build's cell-range pass cleared it)
 hipError_t launch_drift(double *x, double *y, double *z, const double *vx,
                         const double *vy, const double *vz, int64_t n, double dt,
-                        hipStream_t s);
+                        hipStream_t s, DevState *st = nullptr);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 

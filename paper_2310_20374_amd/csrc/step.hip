@@ -56,6 +56,62 @@ __global__ void k_drift(double *__restrict__ x, double *__restrict__ y, double *
     }
 }
 
+// The drift of a step whose next build takes its root cube from the new positions:
+// also their largest |coordinate| (bit patterns of the non-negative values, so the
+// integer maximum is the value's; non-finite coordinates latched), the same word the
+// key pass of a plain build forms.  Few blocks, four moonlets per thread and round,
+// one atomic per block on the word.
+__global__ void k_drift_max(double *__restrict__ x, double *__restrict__ y,
+                            double *__restrict__ z, const double *__restrict__ vx,
+                            const double *__restrict__ vy, const double *__restrict__ vz,
+                            int64_t n, double dt, DevState *st) {
+    __shared__ unsigned long long red[256 / kWave];
+    constexpr int kBatch = 4;
+    unsigned long long m = 0ull;
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < n;
+         i0 += kBatch * stride) {
+        double p[kBatch][3];
+#pragma unroll
+        for (int b = 0; b < kBatch; b++) {
+            const int64_t i = i0 + b * stride;
+            if (i < n) {
+                p[b][0] = x[i] + dt * vx[i];
+                p[b][1] = y[i] + dt * vy[i];
+                p[b][2] = z[i] + dt * vz[i];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; b++) {
+            const int64_t i = i0 + b * stride;
+            if (i >= n) continue;
+            x[i] = p[b][0];
+            y[i] = p[b][1];
+            z[i] = p[b][2];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const double a = fabs(p[b][k]);
+                if (!(a <= 1.79769313486231570e308)) { bad = true; continue; }
+                const unsigned long long u = (unsigned long long)__double_as_longlong(a);
+                m = u > m ? u : m;
+            }
+        }
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(m, o);
+        m = t > m ? t : m;
+    }
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) red[w] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x / kWave); k++) m = red[k] > m ? red[k] : m;
+        atomicMax((unsigned long long *)&st->max_abs, m);
+    }
+    if (__any(bad) && l == 0) atomicOr(&st->status, (int32_t)ST_NONFINITE);
+}
+
 static int grid1(int64_t n) {
     int64_t g = (n + 255) / 256;
     return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
@@ -70,8 +126,13 @@ hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax, con
 }
 
 hipError_t launch_drift(double *x, double *y, double *z, const double *vx, const double *vy,
-                        const double *vz, int64_t n, double dt, hipStream_t s) {
-    k_drift<<<grid1(n), 256, 0, s>>>(x, y, z, vx, vy, vz, n, dt);
+                        const double *vz, int64_t n, double dt, hipStream_t s, DevState *st) {
+    if (st) {
+        const int64_t g = (n + 255) / 256;
+        k_drift_max<<<(int)(g > 256 ? 256 : g), 256, 0, s>>>(x, y, z, vx, vy, vz, n, dt, st);
+    } else {
+        k_drift<<<grid1(n), 256, 0, s>>>(x, y, z, vx, vy, vz, n, dt);
+    }
     return hipGetLastError();
 }
 

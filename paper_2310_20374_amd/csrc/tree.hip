@@ -270,7 +270,8 @@ k_emit_cells(const int32_t *__restrict__ ent_start, const uint32_t *__restrict__
 // child counts, moonlet counts and leaf ranges: walk up while this cell (or its
 // ancestor) is the last child; the next sibling then starts where it ends.  An
 // overflowed tree is unusable: it exposes no cells or leaves to later passes.  Also
-// clears the coordinate maximum the key pass accumulates into, for the next build.
+// clears the coordinate maximum that the next build's key pass (or a step's drift
+// before it) accumulates into.
 __global__ void k_cell_ranges(DevState *st, int64_t n,
                               const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_child,
                               const int32_t *__restrict__ c_parent, const int32_t *__restrict__ c_entry,
