@@ -666,6 +666,7 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
     Workspace &ws = c->ws;
     const int64_t n = c->n;
     PhaseTimer t(c, NCORP_PHASE_COLLIDE, s);
+    bool tree_tests = false;    // the tree's pair tests left per-block counts to add
     if (mesh_collisions(c->prm)) {
         HIPCHK(c, launch_mesh_collide(ws, vx, vy, vz, R, n, dt, !c->mesh_counted, s));
         c->mesh_counted = true;
@@ -681,6 +682,7 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
         HIPCHK(c, launch_collide_reset(ws, s));
         HIPCHK(c, launch_standard_tree_collide(ws, n, c->prm.ncb_pre, c->prm.ncb_post, dt, s));
     } else {
+        tree_tests = true;
         if (c->grav_lists) {
             // candidates from the gravity walk's lists of this tree, culled with the
             // moonlets' bounding boxes (no collision climb needed); the box pass gathers
@@ -700,10 +702,12 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
     if (state && c->prm.collision_mode == NCORP_COLLISIONS_RESOLVE)
         HIPCHK(c, launch_resolve(ws, state[0], state[1], state[2], state[3], state[4], state[5],
                                  m, R, dt, c->prm.collision_f, pairs, cap, n_pairs_dev, step,
-                                 &ws.st->pair_cursor, s));
+                                 &ws.st->pair_cursor, tree_tests ? ws.count_part : nullptr,
+                                 kCollideGrid, s));
     else
         HIPCHK(c, launch_emit_pairs(ws, pairs, cap, n_pairs_dev, triple, step,
-                                    &ws.st->pair_cursor, s));
+                                    &ws.st->pair_cursor, tree_tests ? ws.count_part : nullptr,
+                                    kCollideGrid, s));
     c->last = s;
     return NCORP_OK;
 }

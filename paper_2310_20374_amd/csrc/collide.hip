@@ -393,8 +393,8 @@ k_collide(DevState *st, const int2 *__restrict__ cand, int64_t cand_cap,
             self_pairs_staged(n, sp, spos, dt, out, cap, st, tests);
         }
     }
-    // per-block partials, summed by k_sum_u64: one atomic per wave on a single
-    // counter would serialise all blocks of the grid
+    // per-block partials, summed by the pair ranking that follows: one atomic per wave
+    // on a single counter would serialise all blocks of the grid
     for (int o = 32; o > 0; o >>= 1) tests += __shfl_xor(tests, o);
     if (lane == 0) tests_part[blockIdx.x] = tests;
 }
@@ -438,12 +438,34 @@ hipError_t launch_collide_reset(const Workspace &ws, hipStream_t s) {
 // from LDS as wave-wide broadcasts; the block then adds the counts of its waves.
 constexpr int kRankSplit = 8;
 constexpr int kRankGrid = 2048;
+constexpr int kRankSumBlocks = 16;   // blocks that also add up the pair-test counts
 constexpr int kRankChunk = 4 * kWave;
 __global__ void __launch_bounds__(kWave * kRankSplit)
-k_rank_pairs(const DevState *__restrict__ st, const int64_t *__restrict__ in, int64_t cap,
-             int64_t *__restrict__ out) {
+k_rank_pairs(DevState *__restrict__ st, const int64_t *__restrict__ in, int64_t cap,
+             int64_t *__restrict__ out, const unsigned long long *__restrict__ tests_part,
+             int n_part) {
     __shared__ int64_t tile_all[kRankSplit][kRankChunk];
     __shared__ int64_t part[kRankSplit][kWave];
+    const int sum_b = (int)blockIdx.x - ((int)gridDim.x - kRankSumBlocks);
+    if (tests_part && sum_b >= 0) {
+        // the pair tests' per-block counts, summed by the last kRankSumBlocks blocks
+        // (which have no keys to rank unless the list is long), one integer atomic each
+        const int per = (n_part + kRankSumBlocks - 1) / kRankSumBlocks;
+        const int i0 = sum_b * per, i1 = i0 + per < n_part ? i0 + per : n_part;
+        unsigned long long v = 0;
+        for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) v += tests_part[i];
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        unsigned long long *red = (unsigned long long *)&part[0][0];
+        __syncthreads();
+        if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int k = 0; k < (int)blockDim.x / kWave; k++) t += red[k];
+            atomicAdd((unsigned long long *)&st->col_tests, t);
+        }
+        __syncthreads();
+    }
     int64_t n = st->npairs;
     if (n > cap) n = cap;
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -1108,9 +1130,10 @@ k_resolve_apply(const DevState *__restrict__ st, const int64_t *__restrict__ key
 hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, double *vx,
                           double *vy, double *vz, const double *m, const double *R, double dt,
                           double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
-                          int64_t *cursor, hipStream_t s) {
+                          int64_t *cursor, const unsigned long long *tests_part, int n_part,
+                          hipStream_t s) {
     k_rank_pairs<<<kRankGrid, kWave * kRankSplit, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap,
-                                                          ws.pairs_alt);
+                                                          ws.pairs_alt, tests_part, n_part);
     k_resolve_init<<<kResolveGrid, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, x, y, z, vx,
                                                 vy, vz, R, dt, ws.pair_dt, ws.pair_flag,
                                                 ws.mmatch);
@@ -1129,26 +1152,24 @@ hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, bool 
     (void)n;
     if (!boxes) k_collide_init<<<1, 64, 0, s>>>(ws.st);   // boxes: done by the box pass
     if (boxes) {
-        k_collide<true><<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count,
-                                             ws.ccell, ws.cbox, ws.idx, ws.pcol, ws.vcol,
-                                             ws.ent_cell, dt, ws.pairs_tmp, ws.pair_cap,
-                                             ws.count_part);
-        return launch_sum_u64(ws.count_part, 16384, (unsigned long long *)&ws.st->col_tests,
-                              true, s);
+        k_collide<true><<<kCollideGrid, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first,
+                                                    ws.c_count, ws.ccell, ws.cbox, ws.idx,
+                                                    ws.pcol, ws.vcol, ws.ent_cell, dt,
+                                                    ws.pairs_tmp, ws.pair_cap, ws.count_part);
+        return hipGetLastError();
     }
-    k_collide<false><<<16384, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first, ws.c_count,
-                                          ws.ccell, ws.cbox, ws.idx, ws.pcol, ws.vcol,
-                                          ws.ent_cell, dt, ws.pairs_tmp, ws.pair_cap,
-                                          ws.count_part);
-    return launch_sum_u64(ws.count_part, 16384, (unsigned long long *)&ws.st->col_tests, true,
-                          s);
+    k_collide<false><<<kCollideGrid, 64, 0, s>>>(ws.st, ws.cand, ws.p2p_cap, ws.c_first,
+                                                 ws.c_count, ws.ccell, ws.cbox, ws.idx, ws.pcol,
+                                                 ws.vcol, ws.ent_cell, dt, ws.pairs_tmp,
+                                                 ws.pair_cap, ws.count_part);
+    return hipGetLastError();
 }
 
 hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,
                              int64_t *n_pairs_dev, int triple, int step, int64_t *cursor,
-                             hipStream_t s) {
+                             const unsigned long long *tests_part, int n_part, hipStream_t s) {
     k_rank_pairs<<<kRankGrid, kWave * kRankSplit, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap,
-                                                          ws.pairs_alt);
+                                                          ws.pairs_alt, tests_part, n_part);
     k_emit_pairs<<<256, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, pairs, cap, n_pairs_dev,
                                      triple, step, cursor);
     k_pairs_done<<<1, 64, 0, s>>>(ws.st, n_pairs_dev, cap, ws.pair_cap, triple, cursor);

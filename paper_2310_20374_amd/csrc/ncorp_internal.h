@@ -412,21 +412,27 @@ hipError_t launch_standard_tree_collide(const Workspace &ws, int64_t n, int ncb_
 // standard tree code (Alg. 1): accelerations of all moonlets, input order
 hipError_t launch_standard_tree(const Workspace &ws, int64_t n, int p, int ncb_pre, int ncb_post,
                                 double *ax, double *ay, double *az, hipStream_t s);
+// blocks of the tree's pair tests: each leaves its number of examined pairs in
+// ws.count_part, which the pair ranking that follows adds to st->col_tests
+constexpr int kCollideGrid = 16384;
 hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, bool boxes,
                                 hipStream_t s);
 hipError_t launch_leaf_boxes(const Workspace &ws, int64_t n, double dt, hipStream_t s);
 // collision candidates from the gravity walk's lists of the same tree (in place of
 // the collision walk)
 hipError_t launch_candidates_from_lists(const Workspace &ws, hipStream_t s);
+// tests_part: n_part per-block counts of examined pairs to add to st->col_tests (the
+// tree's pair tests leave them), or nullptr
 hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,
                              int64_t *n_pairs_dev, int triple, int step, int64_t *cursor,
-                             hipStream_t s);
+                             const unsigned long long *tests_part, int n_part, hipStream_t s);
 // sorts the pairs found, resolves them (caller arrays in input order, updated in
 // place) and writes the resolved ones as (step, i, j) triples
 hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, double *vx,
                           double *vy, double *vz, const double *m, const double *R, double dt,
                           double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
-                          int64_t *cursor, hipStream_t s);
+                          int64_t *cursor, const unsigned long long *tests_part, int n_part,
+                          hipStream_t s);
 
 // dst (+)= sum of n per-block partials (one block, fixed order)
 hipError_t launch_sum_u64(const unsigned long long *part, int64_t n, unsigned long long *dst,
