@@ -573,8 +573,16 @@ extern "C" int ncorp_build_tree_batched(ncorp_ctx *c, const int64_t *disk_offset
 }
 
 // mus_packed: the build of the current tree already put G m in ws.mus (the step)
+// Does a gravity evaluation end in the falcON L2P pass (which can write packed records)?
+static bool gravity_by_l2p(const ncorp_params &p) {
+    return p.p > 0 && p.gravity_method == NCORP_GRAVITY_FALCON;
+}
+
+// acc4 (falcON evaluations, gravity_by_l2p): the accelerations as (ax, ay, az, 0)
+// records in input order instead of the three arrays
 static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, double *az,
-                        hipStream_t s, bool mus_packed = false) {
+                        hipStream_t s, bool mus_packed = false, double4 *acc4 = nullptr) {
+    if (!gravity_by_l2p(c->prm)) acc4 = nullptr;
     Workspace &ws = c->ws;
     const int64_t n = c->n;
     if (c->prm.p == 0) {
@@ -635,7 +643,7 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
     }
     {
         PhaseTimer t(c, NCORP_PHASE_L2P, s);
-        HIPCHK(c, launch_l2p(ws, n, c->prm.p, ax, ay, az, s));
+        HIPCHK(c, launch_l2p(ws, n, c->prm.p, ax, ay, az, s, acc4));
     }
     if (c->timing) HIPCHK(c, launch_count_interactions(ws, s));
     c->grav_lists = true;
@@ -789,12 +797,16 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
     };
     if ((r = rebuild(true)) != NCORP_OK) return r;
     k_zero_cursor<<<1, 64, 0, s>>>(ws.st);
+    // falcON evaluations hand the kick one (ax, ay, az, 0) record per moonlet: the
+    // collision records' buffer is free from the evaluation to the kick after it (the
+    // next search rewrites it)
+    double4 *const acc4 = mutual && gravity_by_l2p(c->prm) ? ws.pcol : nullptr;
     // each evaluation follows a rebuild that brought G m into tree order
-    if (mutual && (r = gravity_impl(c, m, ax, ay, az, s, true)) != NCORP_OK) return r;
+    if (mutual && (r = gravity_impl(c, m, ax, ay, az, s, true, acc4)) != NCORP_OK) return r;
     {
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
         HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, 0.5 * dt,
-                              central_body(c->prm, c->clock), R, ws.pack4, s));
+                              central_body(c->prm, c->clock), R, ws.pack4, s, acc4));
     }
     for (int k = 0; k < n_steps; k++) {
         double *const state[6] = {x, y, z, vx, vy, vz};
@@ -805,12 +817,12 @@ static int step_impl(ncorp_ctx *c, const int64_t *disk_off, int n_disks, double 
             HIPCHK(c, launch_drift(x, y, z, vx, vy, vz, n, dt, s, drift_max ? ws.st : nullptr));
         }
         if ((r = rebuild(false)) != NCORP_OK) return r;
-        if (mutual && (r = gravity_impl(c, m, ax, ay, az, s, true)) != NCORP_OK) return r;
+        if (mutual && (r = gravity_impl(c, m, ax, ay, az, s, true, acc4)) != NCORP_OK) return r;
         const double h = (k == n_steps - 1) ? 0.5 * dt : dt;
         PhaseTimer t(c, NCORP_PHASE_INTEGRATE, s);
         HIPCHK(c, launch_kick(vx, vy, vz, mutual ? ax : nullptr, ay, az, x, y, z, n, h,
                               central_body(c->prm, c->clock + (double)(k + 1) * dt), R,
-                              ws.pack4, s));
+                              ws.pack4, s, acc4));
     }
     c->clock += (double)n_steps * dt;
     c->last = s;

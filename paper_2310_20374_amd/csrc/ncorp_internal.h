@@ -398,8 +398,10 @@ hipError_t launch_m2l(const Workspace &ws, int p, int precision, hipStream_t s);
 hipError_t launch_l2l(const Workspace &ws, int p, hipStream_t s);
 hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, int tile, int tmax,
                       hipStream_t s);
+// acc4 non-null: the accelerations as one (ax, ay, az, 0) record per moonlet in
+// input order instead of the three arrays (one scattered record, not three words)
 hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,
-                      hipStream_t s);
+                      hipStream_t s, double4 *acc4 = nullptr);
 // brute-force module (every pair): accelerations by input index; colliding pairs
 hipError_t launch_brute_gravity(const Workspace &ws, int64_t n, double *ax, double *ay,
                                 double *az, hipStream_t s);
@@ -455,10 +457,12 @@ hipError_t launch_mesh_collide(const Workspace &ws, const double *vx, const doub
 struct CentralBody {
     double GM, GMR2J2, GMsun, sx, sy, sz, a2, a3;
 };
+// acc4 non-null: the accelerations as (ax, ay, az, 0) records (ax .. az unused)
 hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax,
                        const double *ay, const double *az, const double *x,
                        const double *y, const double *z, int64_t n, double h,
-                       const CentralBody &b, const double *R, double4 *pack, hipStream_t s);
+                       const CentralBody &b, const double *R, double4 *pack, hipStream_t s,
+                       const double4 *acc4 = nullptr);
 // st non-null: also max |coordinate| of the new positions into st->max_abs, as the key
 // pass of a plain build forms it (the previous build's cell-range pass cleared it)
 hipError_t launch_drift(double *x, double *y, double *z, const double *vx,

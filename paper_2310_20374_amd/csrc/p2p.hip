@@ -481,7 +481,7 @@ k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
       const double4 *__restrict__ gcell, const double *__restrict__ cleaf,
       const double *__restrict__ acc_s, const int32_t *__restrict__ p2p_cnt,
       const double *__restrict__ part, int64_t n, double *__restrict__ ax,
-      double *__restrict__ ay, double *__restrict__ az) {
+      double *__restrict__ ay, double *__restrict__ az, double4 *__restrict__ acc4) {
     constexpr int NL = n_local(P);
     if (st->status & kSkipMask) return;
     const int K = st->nleaves;
@@ -535,9 +535,13 @@ k_l2p(const DevState *__restrict__ st, const double *__restrict__ xs,
                 dz = acc_s[2 * n + i];
             }
             const uint32_t o = perm[i];
-            ax[o] = dx + lx;
-            ay[o] = dy + ly;
-            az[o] = dz + lz;
+            if (acc4) {
+                acc4[o] = make_double4(dx + lx, dy + ly, dz + lz, 0.0);
+            } else {
+                ax[o] = dx + lx;
+                ay[o] = dy + ly;
+                az[o] = dz + lz;
+            }
         }
     }
 }
@@ -595,23 +599,23 @@ hipError_t launch_p2p(const Workspace &ws, int64_t n, int precision, int tile, i
 
 template <int P>
 static void launch_l2p_p(const Workspace &ws, int64_t n, double *ax, double *ay, double *az,
-                         hipStream_t s) {
+                         hipStream_t s, double4 *acc4) {
     int64_t g = (ws.leaf_cap + kL2PWaves - 1) / kL2PWaves;
     g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
     k_l2p<P><<<(int)g, kWave * kL2PWaves, 0, s>>>(ws.st, ws.xs, ws.ys, ws.zs, ws.idx, ws.ent_cell, ws.c_first,
                               ws.c_count, ws.gcell, ws.cleaf, ws.acc_s, ws.p2p_cnt, ws.p2p_part, n,
-                              ax, ay, az);
+                              ax, ay, az, acc4);
 }
 
 hipError_t launch_l2p(const Workspace &ws, int64_t n, int p, double *ax, double *ay, double *az,
-                      hipStream_t s) {
+                      hipStream_t s, double4 *acc4) {
     switch (p) {
-        case 1: launch_l2p_p<1>(ws, n, ax, ay, az, s); break;
-        case 2: launch_l2p_p<2>(ws, n, ax, ay, az, s); break;
-        case 3: launch_l2p_p<3>(ws, n, ax, ay, az, s); break;
-        case 4: launch_l2p_p<4>(ws, n, ax, ay, az, s); break;
-        case 5: launch_l2p_p<5>(ws, n, ax, ay, az, s); break;
-        case 6: launch_l2p_p<6>(ws, n, ax, ay, az, s); break;
+        case 1: launch_l2p_p<1>(ws, n, ax, ay, az, s, acc4); break;
+        case 2: launch_l2p_p<2>(ws, n, ax, ay, az, s, acc4); break;
+        case 3: launch_l2p_p<3>(ws, n, ax, ay, az, s, acc4); break;
+        case 4: launch_l2p_p<4>(ws, n, ax, ay, az, s, acc4); break;
+        case 5: launch_l2p_p<5>(ws, n, ax, ay, az, s, acc4); break;
+        case 6: launch_l2p_p<6>(ws, n, ax, ay, az, s, acc4); break;
         default: break;
     }
     return hipGetLastError();

@@ -13,7 +13,7 @@ __global__ void k_kick(double *__restrict__ vx, double *__restrict__ vy, double 
                        const double *__restrict__ az, const double *__restrict__ x,
                        const double *__restrict__ y, const double *__restrict__ z, int64_t n,
                        double h, CentralBody b, const double *__restrict__ R,
-                       double4 *__restrict__ pack) {
+                       double4 *__restrict__ pack, const double4 *__restrict__ acc4) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double px = x[i], py = y[i], pz = z[i];
@@ -35,7 +35,12 @@ __global__ void k_kick(double *__restrict__ vx, double *__restrict__ vy, double 
             gy += g * (py - q * b.sy);
             gz += g * (pz - q * b.sz);
         }
-        if (ax) { gx += ax[i]; gy += ay[i]; gz += az[i]; }
+        if (acc4) {
+            const double4 a = acc4[i];
+            gx += a.x; gy += a.y; gz += a.z;
+        } else if (ax) {
+            gx += ax[i]; gy += ay[i]; gz += az[i];
+        }
         const double ux = vx[i] + h * gx, uy = vy[i] + h * gy, uz = vz[i] + h * gz;
         vx[i] = ux;
         vy[i] = uy;
@@ -120,8 +125,8 @@ static int grid1(int64_t n) {
 hipError_t launch_kick(double *vx, double *vy, double *vz, const double *ax, const double *ay,
                        const double *az, const double *x, const double *y, const double *z,
                        int64_t n, double h, const CentralBody &b, const double *R,
-                       double4 *pack, hipStream_t s) {
-    k_kick<<<grid1(n), 256, 0, s>>>(vx, vy, vz, ax, ay, az, x, y, z, n, h, b, R, pack);
+                       double4 *pack, hipStream_t s, const double4 *acc4) {
+    k_kick<<<grid1(n), 256, 0, s>>>(vx, vy, vz, ax, ay, az, x, y, z, n, h, b, R, pack, acc4);
     return hipGetLastError();
 }
 
