@@ -42,9 +42,9 @@ FLOPS_PER_INTERACTION = 20  # directed moonlet pair, the usual N-body convention
 # reported only while it is unchanged.
 # Measured per leaf size (the direct sums' work depends on it).
 P2P_TRAFFIC = {"source": "paper_2310_20374_amd/csrc/p2p.hip",
-               "blob": "1f822c19e629e511ed3d4e4105eaa7751888a34d",
+               "blob": "24806f309f8c8f758dd3293823e9518d4bee879f",
                "fetch_scale": 2.00, "write_scale": 1.00,
-               "by_leaf_size": {96: {"fetch_kib": (198986.0,), "write_kib": (25533.7,)}}}
+               "by_leaf_size": {96: {"fetch_kib": (198843.8,), "write_kib": (25534.3,)}}}
 
 
 def _git_blob(path):
