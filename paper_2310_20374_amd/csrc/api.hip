@@ -438,6 +438,9 @@ static int setup_workspace(ncorp_ctx *c, int64_t n, void *workspace, int64_t ws_
                        c->ws.queue_cap == ws.queue_cap) || c->ws.clear_queue;
     // the bucket sort's boundaries from the last build are usable only where it wrote them
     ws.sort_prev = c->ws.base == ws.base && c->ws.bs_prev == ws.bs_prev && c->ws.sort_prev;
+    // so are the cleared climb counters
+    ws.arrive_clean = c->ws.base == ws.base && c->ws.c_arrive == ws.c_arrive &&
+                      c->ws.climb_next == ws.climb_next && c->ws.arrive_clean;
     // so does the mesh state
     if (ws.mesh) {
         // the O(N) grid clear reads the last dense build's keys and grid: every mesh
@@ -483,6 +486,7 @@ static int build_tree_impl(ncorp_ctx *c, const double *x, const double *y, const
         PhaseTimer t(c, NCORP_PHASE_TREE, s);
         HIPCHK(c, launch_gather_pos(ws, n, m != nullptr, s));
         HIPCHK(c, launch_build_tree(ws, n, c->prm.leaf_size, s));
+        ws.arrive_clean = true;       // its cell-range pass cleared the climbs' counters
     }
     c->have_tree = true;
     c->grav_lists = false;
@@ -611,7 +615,9 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
     {
         PhaseTimer t(c, NCORP_PHASE_GCLIMB, s);
         if (!mus_packed) HIPCHK(c, launch_gather_scaled(ws, m, c->prm.G, ws.mus, n, s));
-        HIPCHK(c, launch_gravity_climb(ws, n, c->prm, s));
+        const bool reset = !ws.arrive_clean;
+        ws.arrive_clean = false;
+        HIPCHK(c, launch_gravity_climb(ws, n, c->prm, s, reset));
     }
     if (c->prm.gravity_method == NCORP_GRAVITY_STANDARD_TREE) {
         PhaseTimer t(c, NCORP_PHASE_GWALK, s);
@@ -686,7 +692,11 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
         HIPCHK(c, launch_brute_collide(ws, n, dt, s));
     } else if (c->prm.collision_method == NCORP_COLLISIONS_STANDARD_TREE) {
         HIPCHK(c, launch_gather_vr(ws, packed, vx, vy, vz, R, n, s));
-        HIPCHK(c, launch_collision_climb(ws, n, dt, s));
+        {
+            const bool reset = !ws.arrive_clean;
+            ws.arrive_clean = false;
+            HIPCHK(c, launch_collision_climb(ws, n, dt, s, reset));
+        }
         HIPCHK(c, launch_collide_reset(ws, s));
         HIPCHK(c, launch_standard_tree_collide(ws, n, c->prm.ncb_pre, c->prm.ncb_post, dt, s));
     } else {
@@ -701,7 +711,11 @@ static int collide_impl(ncorp_ctx *c, const double *vx, const double *vy, const 
             HIPCHK(c, launch_collide_pairs(ws, n, dt, true, s));
         } else {
             HIPCHK(c, launch_gather_vr(ws, packed, vx, vy, vz, R, n, s));
-            HIPCHK(c, launch_collision_climb(ws, n, dt, s));
+            {
+                const bool reset = !ws.arrive_clean;
+                ws.arrive_clean = false;
+                HIPCHK(c, launch_collision_climb(ws, n, dt, s, reset));
+            }
             HIPCHK(c, launch_walk(ws, 1, c->prm.ncs_col, c->prm.ncc_pre_col,
                                   c->prm.ncc_post_col, 0, s));
             HIPCHK(c, launch_collide_pairs(ws, n, dt, false, s));

@@ -60,7 +60,6 @@ constexpr int kPowChunk = 32;
 // arrives last more often, inherits more of the upward chains and falls further
 // behind).  The waves are persistent, as many as fit on the chip at once, so no
 // leaf waits for a workgroup launch.
-constexpr int kCtrStride = 32;                      // one counter per 128-byte line
 
 template <int KERNEL_ID>
 static int climb_grid(const void *kernel, int64_t leaf_cap) {
@@ -542,10 +541,11 @@ static void launch_gc(const Workspace &ws, hipStream_t s) {
 }
 
 hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_params &prm,
-                                hipStream_t s) {
+                                hipStream_t s, bool reset) {
     (void)n;
-    k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive,
-                                                               ws.climb_next);
+    if (reset)
+        k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive,
+                                                                   ws.climb_next);
     switch (prm.p) {
         case 0: launch_gc<0>(ws, s); break;
         case 1: launch_gc<1>(ws, s); break;
@@ -675,10 +675,12 @@ k_collision_climb(const DevState *__restrict__ st, const double *__restrict__ xs
     }
 }
 
-hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hipStream_t s) {
+hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hipStream_t s,
+                                  bool reset) {
     (void)n;
-    k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive,
-                                                               ws.climb_next);
+    if (reset)
+        k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive,
+                                                                   ws.climb_next);
     const int g = climb_grid<100>((const void *)k_collision_climb, ws.leaf_cap);
     k_collision_climb<<<g, kWave, 0, s>>>(
         ws.st, ws.xs, ws.ys, ws.zs, ws.vxs, ws.vys, ws.vzs, ws.rads, dt, ws.ent_cell, ws.c_level,

@@ -786,12 +786,18 @@ k_cand_count(const DevState *__restrict__ st, const int2 *__restrict__ m2l, int6
 // exclusive scan of the block counts (one block); the total is the candidate count
 __global__ void __launch_bounds__(1024) k_cand_scan(DevState *st, int32_t *blk, int nb) {
     __shared__ int32_t wtot[1024 / kWave];
+    constexpr int kPer = 8;          // consecutive counts per thread: one round up to 8192
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     int32_t carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += 1024) {
-        const int i = b0 + threadIdx.x;
-        const int32_t x = i < nb ? blk[i] : 0;
-        int32_t v = x;
+    for (int b0 = 0; b0 < nb; b0 += 1024 * kPer) {
+        const int i0 = b0 + threadIdx.x * kPer;
+        int32_t x[kPer], sum = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            x[u] = i0 + u < nb ? blk[i0 + u] : 0;
+            sum += x[u];
+        }
+        int32_t v = sum;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
             const int32_t y = __shfl_up(v, o);
@@ -804,7 +810,12 @@ __global__ void __launch_bounds__(1024) k_cand_scan(DevState *st, int32_t *blk, 
             if (k < w) before += wtot[k];
             all += wtot[k];
         }
-        if (i < nb) blk[i] = carry + before + v - x;
+        int32_t run = carry + before + v - sum;
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            if (i0 + u < nb) blk[i0 + u] = run;
+            run += x[u];
+        }
         carry += all;
         __syncthreads();
     }

@@ -16,6 +16,8 @@ constexpr int kWave = 64;
 // The hardware deals the workgroups of a launch to the 8 XCDs in turn (workgroup b
 // runs on XCD b mod 8), and each XCD has its own L2.
 constexpr int kXcds = 8;
+// the climbs' per-XCD leaf counters: one counter per 128-byte line
+constexpr int kCtrStride = 32;
 
 // ---------------------------------------------------------------- tensor sizes
 // Symmetric tensors are stored per order n as the (n+1)(n+2)/2 components
@@ -348,6 +350,9 @@ struct Workspace {
     bool timing = false;                              // phase timing on: load-balance counters
     bool clear_queue = false;                         // new buffer: clear before next walk
     bool clear_mesh = false;                          // new buffer: clear the mesh state
+    // the climbs' arrival and leaf counters are zero: the last tree build's cell-range
+    // pass cleared them and no climb has run since
+    bool arrive_clean = false;
 };
 
 // Layout of the workspace for given capacities; with base == nullptr only the
@@ -383,9 +388,11 @@ hipError_t launch_gather_vr(const Workspace &ws, bool packed, const double *vx, 
                             const double *vz, const double *R, int64_t n, hipStream_t s);
 hipError_t launch_build_tree(const Workspace &ws, int64_t n, int leaf_size, hipStream_t s);
 
+// reset: clear the arrival and leaf counters first (not needed right after a build)
 hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_params &prm,
-                                hipStream_t s);
-hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hipStream_t s);
+                                hipStream_t s, bool reset = true);
+hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hipStream_t s,
+                                  bool reset = true);
 
 // walk: mode 0 gravity (M2L + P2P lists), 1 collisions (candidate list in p2p)
 hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post, int waves,

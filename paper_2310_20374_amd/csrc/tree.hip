@@ -271,14 +271,17 @@ k_emit_cells(const int32_t *__restrict__ ent_start, const uint32_t *__restrict__
 // ancestor) is the last child; the next sibling then starts where it ends.  An
 // overflowed tree is unusable: it exposes no cells or leaves to later passes.  Also
 // clears the coordinate maximum that the next build's key pass (or a step's drift
-// before it) accumulates into.
+// before it) accumulates into, and the first climb's arrival and leaf counters.
 __global__ void k_cell_ranges(DevState *st, int64_t n,
                               const int32_t *__restrict__ c_first, const int32_t *__restrict__ c_child,
                               const int32_t *__restrict__ c_parent, const int32_t *__restrict__ c_entry,
                               int32_t *__restrict__ c_count, int32_t *__restrict__ c_nchild,
-                              int32_t *__restrict__ c_nent) {
+                              int32_t *__restrict__ c_nent, int32_t *__restrict__ c_arrive,
+                              int32_t *__restrict__ climb_next) {
     const bool first = blockIdx.x == 0 && threadIdx.x == 0;
     if (first) st->max_abs = 0.0;
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < kXcds * kCtrStride; t += blockDim.x) climb_next[t] = 0;
     if (st->status & ST_CAP_CELLS) {
         if (first) {
             st->ncells = 0;
@@ -288,6 +291,7 @@ __global__ void k_cell_ranges(DevState *st, int64_t n,
     }
     const int nc = st->ncells, K = st->nleaves;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+        c_arrive[c] = 0;
         int par = c_parent[c];
         bool last_child = par >= 0 && (c + 1 >= nc || c_parent[c + 1] != par);
         if (last_child) c_nchild[par] = c - c_child[par] + 1;
@@ -328,7 +332,8 @@ hipError_t launch_build_tree(const Workspace &ws, int64_t n, int s, hipStream_t 
     int g = (int)((ws.cell_cap + 255) / 256);
     if (g > 2048) g = 2048;
     k_cell_ranges<<<g, 256, 0, st>>>(ws.st, n, ws.c_first, ws.c_child, ws.c_parent, ws.c_entry,
-                                     ws.c_count, ws.c_nchild, ws.c_nent);
+                                     ws.c_count, ws.c_nchild, ws.c_nent, ws.c_arrive,
+                                     ws.climb_next);
     return hipGetLastError();
 }
 

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2310_20374_amd import inputs
-from tests.gpu_util import rel_err, run_gravity
+from tests.gpu_util import dev_arrays, rel_err, run_gravity
 
 pytestmark = pytest.mark.gpu
 
@@ -185,6 +185,36 @@ def test_repeat_is_bit_identical(nc, prec):
     for _ in range(3):
         _, a1 = run_gravity(nc, d, prm, ctx=ctx)
         assert np.array_equal(a0, a1)
+
+
+def test_climbs_repeated_on_one_tree(nc, orc):
+    """The tree build clears the climbs' arrival counters for the first climb; a later
+    climb on the same tree clears them itself.  Two collision searches (collision climb)
+    and then two gravity evaluations (gravity climb) on one build must each give what a
+    fresh build gives."""
+    import torch
+    d = inputs.clumps(20000, seed=5, n_clumps=20)
+    prm = nc.params_default(4, leaf_size=24)
+    _, a_ref = run_gravity(nc, d, prm)
+    want = orc.pairs_brute(d, 0.01)
+    n = len(d["x"])
+    ctx = nc.Context(prm, n, pair_capacity=1 << 16, device="cuda:0")
+    t = dev_arrays(d)
+    ctx.build_tree(t["x"], t["y"], t["z"])
+    for _ in range(2):
+        pairs = torch.zeros((1 << 16, 2), dtype=torch.int64, device="cuda:0")
+        npairs = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+        ctx.collide(t["vx"], t["vy"], t["vz"], t["R"], 0.01, pairs, npairs)
+        torch.cuda.synchronize()
+        ctx.check_status()
+        got = pairs[: int(npairs.item())].cpu().numpy()
+        assert np.array_equal(got, want)
+    for _ in range(2):
+        a = [torch.empty(n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+        ctx.gravity(t["m"], *a)
+        torch.cuda.synchronize()
+        ctx.check_status()
+        assert np.array_equal(torch.stack(a, 1).cpu().numpy(), a_ref)
 
 
 @pytest.mark.parametrize("field", ["m2l_per_cell", "p2p_per_leaf"])
