@@ -94,7 +94,8 @@ double orc_collision_time(double x1, double y1, double z1, double vx1, double vy
 }
 
 /* ------------------------------------------------------------------------- */
-/* Collision resolution, Sect. 5.1 and 5.2 (readings R28-R30).                 */
+/* Collision resolution, Sect. 5.1 and 5.2 (the order rule below is a reading: */
+/* the paper gives none).                                                      */
 /* The colliding pairs (i < j, one row each) are taken in increasing order of  */
 /* (dt_c, i, j); a pair is resolved unless one of its moonlets already was in  */
 /* this step.  Resolving (1 = i, 2 = j): both move on straight lines to the    */

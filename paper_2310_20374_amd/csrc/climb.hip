@@ -448,7 +448,8 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
     }
 }
 
-// theta(M) of Dehnen's relation, solved with only + - * / (reading R3):
+// theta(M) of Dehnen's relation (recalled from Dehnen 2002; the paper's text does not
+// print it), solved with only + - * /:
 //   theta^15 M = K^3 M_root (1 - theta)^6,  K = theta_min^5 / (1 - theta_min)^2
 __device__ double theta_of_mass(double M, double Mroot, double tmin) {
     if (!(M < Mroot)) return tmin;

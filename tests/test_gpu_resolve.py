@@ -1,4 +1,5 @@
-"""GPU collision resolution in the leapfrog (Sect. 5.1-5.2, readings R28-R30) against
+"""GPU collision resolution in the leapfrog (Sect. 5.1-5.2; one collision per moonlet and
+step, the earliest contact first) against
 the oracle: without gravity the arithmetic is the same on both sides, so states and
 resolved pairs must agree bit for bit; with tree gravity the states agree to FP64
 rounding and the resolved pairs exactly.  Momentum and (for f = 2) kinetic energy

@@ -1,6 +1,6 @@
 """Pins for the oracle's gravity: derivative tensors (Eq. 17), multipoles
-(Eq. 20), interaction tensors (Eq. 25), the shift (Eq. 26), the opening angle
-reading R3 and the complete falcON walk (Alg. 2) against closed forms, invariants
+(Eq. 20), interaction tensors (Eq. 25), the shift (Eq. 26), the mass-dependent
+opening angle (recalled from Dehnen 2002) and the complete falcON walk (Alg. 2) against closed forms, invariants
 and the paper's printed accuracy."""
 import json
 import math
@@ -172,9 +172,10 @@ def test_shift_is_exact_reexpansion(orc):
     assert np.allclose(accel(Cout, x), accel(Cin, x + d), rtol=1e-12, atol=1e-12)
 
 
-# --------------------------------------------------------------- reading R3
+# ------------------------------------------------- mass-dependent opening angle
 def test_theta_of_mass(orc):
-    """Self-consistency of the bisection only (the relation is reading R3); what pins
+    """Self-consistency of the bisection only (the relation is recalled from Dehnen
+    2002, not printed in the paper); what pins
     theta(M) to the paper is the Fig. 4 accuracy test below."""
     tmin = 0.5
     assert orc.theta_of_mass(1.0, 1.0, tmin) == tmin
@@ -299,8 +300,8 @@ def test_fig4_accuracy_matches_paper(orc):
     about 10 %).  The printed magnitudes are those of the acceleration with the
     central mass (the mutual field alone of a disk is a residual of near-cancelling
     terms, and its relative error is ~10^2 larger).  Constant theta lands within 3x
-    of both printed values; the mass-dependent angle of reading R3 (which the paper
-    says it uses) within 3x at p = 3 and about 5x at p = 6.  A wrong mass exponent in
+    of both printed values; the mass-dependent angle, which the paper says it uses (its
+    form recalled from Dehnen 2002), within 3x at p = 3 and about 5x at p = 6.  A wrong mass exponent in
     theta(M) (-1/2 instead of -1/3 doubles the opening of small cells) drives the
     p = 6 error above 1e-6 and fails here; so do a dropped expansion order or a
     wrong-signed term (errors of 1e-4 and up)."""
@@ -311,7 +312,7 @@ def test_fig4_accuracy_matches_paper(orc):
     # constant theta: within a factor 3 of the printed values at both orders
     assert gold["p3"] / 3 < res[(3, 1)][1] < 3 * gold["p3"]
     assert gold["p6"] / 3 < res[(6, 1)][1] < 3 * gold["p6"]
-    # mass-dependent theta (R3): 3x at p = 3; at p = 6 within 6x
+    # mass-dependent theta: 3x at p = 3; at p = 6 within 6x
     assert gold["p3"] / 3 < res[(3, 0)][1] < 3 * gold["p3"]
     assert gold["p6"] / 3 < res[(6, 0)][1] < 6 * gold["p6"]
     # the mass-dependent angle opens cells more widely, never less

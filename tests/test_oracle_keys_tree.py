@@ -163,7 +163,8 @@ def test_tree_independent_of_insertion_order(orc):
 
 
 def test_tree_depth_cap(orc):
-    """Reading R4: more than s coincident moonlets stay in a depth-21 leaf."""
+    """Depth cap of 21 levels (the paper states none): more than s coincident moonlets
+    stay in a depth-21 leaf."""
     x = np.full(5, 0.25); y = np.full(5, -0.5); z = np.full(5, 3.0)
     x = np.concatenate([x, [5.0]]); y = np.concatenate([y, [5.0]]); z = np.concatenate([z, [5.0]])
     t = orc.Tree(x, y, z, 2)

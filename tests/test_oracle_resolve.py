@@ -1,6 +1,6 @@
 """Pins of the oracle's collision resolution (Sect. 5.1 hard-sphere impulse, Sect. 5.2
-inelastic coefficient f, readings R28-R31): closed forms and invariants that do
-not re-type the oracle's own arithmetic."""
+inelastic coefficient f; one collision per moonlet and step, the earliest first):
+closed forms and invariants that do not re-type the oracle's own arithmetic."""
 import math
 
 import numpy as np
@@ -95,7 +95,7 @@ def test_conservation_and_energy_change(orc, f):
 
 
 def test_greedy_takes_earliest_contact(orc):
-    """A moonlet collides at most once per step; the earliest contact wins (R29)."""
+    """A moonlet collides at most once per step; the earliest contact wins."""
     R = 0.01
     # 0 meets 1 at t = 0.01; 1 would meet 2 at t = 0.02 -> only (0, 1)
     s = _state([(-0.04, 0, 0, 1.0, 0, 0, 1e-6, R), (0.0, 0, 0, 0.0, 0, 0, 1e-6, R),
