@@ -617,7 +617,9 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
         if (!mus_packed) HIPCHK(c, launch_gather_scaled(ws, m, c->prm.G, ws.mus, n, s));
         const bool reset = !ws.arrive_clean;
         ws.arrive_clean = false;
-        HIPCHK(c, launch_gravity_climb(ws, n, c->prm, s, reset));
+        // falcON: the walk's init pass forms the critical radii
+        HIPCHK(c, launch_gravity_climb(ws, n, c->prm, s, reset,
+                                       c->prm.gravity_method == NCORP_GRAVITY_STANDARD_TREE));
     }
     if (c->prm.gravity_method == NCORP_GRAVITY_STANDARD_TREE) {
         PhaseTimer t(c, NCORP_PHASE_GWALK, s);
@@ -631,7 +633,7 @@ static int gravity_impl(ncorp_ctx *c, const double *m, double *ax, double *ay, d
         PhaseTimer t(c, NCORP_PHASE_GWALK, s);
         ws.timing = c->timing;
         HIPCHK(c, launch_walk(ws, 0, c->prm.ncs, c->prm.ncc_pre, c->prm.ncc_post,
-                              walk_waves(c->prm), s));
+                              walk_waves(c->prm), s, &c->prm));
     }
     {
         PhaseTimer t(c, NCORP_PHASE_M2L, s);

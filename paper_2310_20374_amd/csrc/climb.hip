@@ -12,6 +12,7 @@
 // Operation order of the centres, radii and angles is fixed (children or moonlets
 // in tree order, no contraction) so they are reproducible bit for bit.
 #include "ncorp_internal.h"
+#include "rcrit.h"
 
 namespace ncorp {
 
@@ -448,53 +449,11 @@ k_gravity_climb(const DevState *__restrict__ st, const double *__restrict__ xs,
     }
 }
 
-// theta(M) of Dehnen's relation (recalled from Dehnen 2002; the paper's text does not
-// print it), solved with only + - * /:
-//   theta^15 M = K^3 M_root (1 - theta)^6,  K = theta_min^5 / (1 - theta_min)^2
-__device__ double theta_of_mass(double M, double Mroot, double tmin) {
-    if (!(M < Mroot)) return tmin;
-    double tm = tmin, um = 1.0 - tmin;
-    double tm2 = tm * tm, tm4 = tm2 * tm2, tm5 = tm4 * tm;
-    double um2 = um * um;
-    double K = tm5 / um2;
-    double K3 = K * K * K;
-    double rhs0 = K3 * Mroot;
-    double lo = tmin, hi = 1.0;
-    for (int it = 0; it < 64; it++) {
-        double mid = 0.5 * (lo + hi);
-        double t2 = mid * mid, t4 = t2 * t2, t8 = t4 * t4;
-        double t15 = t8 * t4 * t2 * mid;
-        double u = 1.0 - mid, u2 = u * u, u4 = u2 * u2, u6 = u4 * u2;
-        double g = t15 * M - rhs0 * u6;
-        if (g <= 0.0) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-__global__ void k_rcrit(const DevState *__restrict__ st, const double *__restrict__ c_mass,
-                        const double *__restrict__ c_rmax, double4 *gcell, double *c_theta,
-                        double theta_min, int theta_mode, const int32_t *__restrict__ c_count,
-                        const int32_t *__restrict__ c_child, const int32_t *__restrict__ c_nchild,
-                        WCell *__restrict__ wg, const uint16_t *__restrict__ seg,
-                        const int32_t *__restrict__ c_first, const int32_t *__restrict__ disk_root,
-                        const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent) {
+__global__ void k_rcrit(const DevState *__restrict__ st, const RcritArgs R) {
     const int nc = st->ncells;
     if (nc <= 0 || (st->status & kSkipMask)) return;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
-        // M_root: mass of the root of this cell's own tree (its disk's)
-        const double Mroot = c_mass[seg ? disk_root[seg[c_first[c]]] : 0];
-        double th = theta_mode == 1 ? theta_min : theta_of_mass(c_mass[c], Mroot, theta_min);
-        c_theta[c] = th;
-        const double rc = c_rmax[c] / th;
-        double4 g = gcell[c];
-        g.w = rc;
-        gcell[c] = g;
-        WCell w;
-        w.x = g.x; w.y = g.y; w.z = g.z; w.rcrit = rc;
-        w.count = c_count[c]; w.child = c_child[c]; w.nchild = c_nchild[c];
-        w.entry = c_entry[c]; w.nent = c_nent[c]; w.first = c_first[c]; w.pad[0] = w.pad[1] = 0;
-        wg[c] = w;
-    }
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
+        rcrit_cell(R, c);
 }
 
 __global__ void k_pack_collision(const DevState *__restrict__ st, const double4 *__restrict__ ccell,
@@ -542,7 +501,7 @@ static void launch_gc(const Workspace &ws, hipStream_t s) {
 }
 
 hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_params &prm,
-                                hipStream_t s, bool reset) {
+                                hipStream_t s, bool reset, bool rcrit) {
     (void)n;
     if (reset)
         k_arrive_reset<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_arrive,
@@ -556,12 +515,8 @@ hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_para
         case 5: launch_gc<5>(ws, s); break;
         default: launch_gc<6>(ws, s); break;
     }
-    k_rcrit<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, ws.c_mass, ws.c_rmax, ws.gcell,
-                                                        ws.c_theta, prm.theta_min, prm.theta_mode,
-                                                        ws.c_count, ws.c_child, ws.c_nchild, ws.wg,
-                                                        ws.ndisks > 1 ? ws.seg : nullptr,
-                                                        ws.c_first, ws.disk_root, ws.c_entry,
-                                                        ws.c_nent);
+    if (rcrit)
+        k_rcrit<<<cell_grid(ws.cell_cap, 256), 256, 0, s>>>(ws.st, rcrit_args(ws, prm));
     return hipGetLastError();
 }
 

@@ -388,15 +388,19 @@ hipError_t launch_gather_vr(const Workspace &ws, bool packed, const double *vx, 
                             const double *vz, const double *R, int64_t n, hipStream_t s);
 hipError_t launch_build_tree(const Workspace &ws, int64_t n, int leaf_size, hipStream_t s);
 
-// reset: clear the arrival and leaf counters first (not needed right after a build)
+// reset: clear the arrival and leaf counters first (not needed right after a build);
+// rcrit: then the opening angles and critical radii (a gravity walk's init pass can
+// do them instead)
 hipError_t launch_gravity_climb(const Workspace &ws, int64_t n, const ncorp_params &prm,
-                                hipStream_t s, bool reset = true);
+                                hipStream_t s, bool reset = true, bool rcrit = true);
 hipError_t launch_collision_climb(const Workspace &ws, int64_t n, double dt, hipStream_t s,
                                   bool reset = true);
 
 // walk: mode 0 gravity (M2L + P2P lists), 1 collisions (candidate list in p2p)
+// rcrit_prm (gravity walk): its init pass also forms the opening angles and critical
+// radii the climb left out
 hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post, int waves,
-                       hipStream_t s);
+                       hipStream_t s, const ncorp_params *rcrit_prm = nullptr);
 hipError_t launch_count_interactions(const Workspace &ws, hipStream_t s);
 // sorts, in place, the per-target lists longer than the consumers sort in LDS
 hipError_t launch_sort_long_lists(const Workspace &ws, hipStream_t s);

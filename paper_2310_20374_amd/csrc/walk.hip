@@ -21,6 +21,7 @@
 // every leaf below either cell).  Their order depends on timing; the consumers
 // sort a list before using it, so every sum is independent of the walk's timing.
 #include "ncorp_internal.h"
+#include "rcrit.h"
 
 namespace ncorp {
 
@@ -58,9 +59,11 @@ __device__ __forceinline__ uint32_t next_epoch(uint32_t e, bool &wrap) {
 }
 
 // Resets the queue (one root pair (r, r) per tree of the forest) and, for the
-// gravity walk, the per-target list counters.
+// gravity walk, the per-target list counters; with do_rcrit also the cells' opening
+// angles, critical radii and walk records (the gravity climb then leaves them out).
 __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, int64_t qcap,
-                            int mode, int32_t *m2l_cnt, int32_t *p2p_cnt, int force_clear) {
+                            int mode, int32_t *m2l_cnt, int32_t *p2p_cnt, int force_clear,
+                            const RcritArgs R, int do_rcrit) {
     const int nc = st->ncells;
     bool wrap = false;
     const uint32_t epoch = next_epoch(wq->epoch, wrap);
@@ -68,6 +71,8 @@ __global__ void k_walk_init(DevState *st, WalkQueue *wq, uint64_t *queue, int64_
     const int nroots = go ? st->level_count[0] : 0;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+    if (do_rcrit && go)
+        for (int64_t c = gid; c < nc; c += gstride) rcrit_cell(R, (int)c);
     if (wrap || force_clear)
         for (int64_t i = nroots + gid; i < qcap; i += gstride) queue[i] = 0ull;
     if (mode == 0 && m2l_cnt) {
@@ -461,9 +466,11 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(WalkArgs A0) {
 
 // waves: persistent waves of the gravity walk (the collision walk runs its own count)
 hipError_t launch_walk(Workspace &ws, int mode, int ncs, int ncc_pre, int ncc_post, int waves,
-                       hipStream_t s) {
+                       hipStream_t s, const ncorp_params *rcrit_prm) {
+    RcritArgs R = {};
+    if (rcrit_prm) R = rcrit_args(ws, *rcrit_prm);
     k_walk_init<<<1024, 256, 0, s>>>(ws.st, ws.wq, ws.queue, ws.queue_cap, mode, ws.m2l_cnt,
-                                     ws.p2p_cnt, ws.clear_queue ? 1 : 0);
+                                     ws.p2p_cnt, ws.clear_queue ? 1 : 0, R, rcrit_prm ? 1 : 0);
     ws.clear_queue = false;
     WalkArgs A = {};
     A.st = ws.st; A.wq = ws.wq; A.queue = ws.queue; A.qcap = ws.queue_cap;
