@@ -440,10 +440,19 @@ constexpr int kRankSplit = 8;
 constexpr int kRankGrid = 2048;
 constexpr int kRankSumBlocks = 16;   // blocks that also add up the pair-test counts
 constexpr int kRankChunk = 4 * kWave;
+// The resolution's per-pair start (when dtc is non-null): contact time (Eq. 2) of
+// every ranked pair at its rank, its live flag, and its moonlets' matched flags cleared
+struct RankResolve {
+    const double *x, *y, *z, *vx, *vy, *vz, *R;
+    double dt;
+    double *dtc;
+    int32_t *flag, *mmatch;
+};
+
 __global__ void __launch_bounds__(kWave * kRankSplit)
 k_rank_pairs(DevState *__restrict__ st, const int64_t *__restrict__ in, int64_t cap,
              int64_t *__restrict__ out, const unsigned long long *__restrict__ tests_part,
-             int n_part) {
+             int n_part, const RankResolve RR) {
     __shared__ int64_t tile_all[kRankSplit][kRankChunk];
     __shared__ int64_t part[kRankSplit][kWave];
     const int sum_b = (int)blockIdx.x - ((int)gridDim.x - kRankSumBlocks);
@@ -467,6 +476,8 @@ k_rank_pairs(DevState *__restrict__ st, const int64_t *__restrict__ in, int64_t 
         __syncthreads();
     }
     int64_t n = st->npairs;
+    // the resolution takes no pair of an overflowed list or after a failed pass
+    const bool resolve = RR.dtc && n <= cap && !(st->status & kSkipMask);
     if (n > cap) n = cap;
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     int64_t *tile = tile_all[w];
@@ -509,6 +520,16 @@ k_rank_pairs(DevState *__restrict__ st, const int64_t *__restrict__ in, int64_t 
 #pragma unroll
             for (int k = 0; k < kRankSplit; k++) r += part[k][lane];
             out[r] = v;
+            if (resolve) {
+                const int a = (int)(v >> 32), b = (int)(v & 0xffffffffll);
+                const double t = contact_time(RR.x[a], RR.y[a], RR.z[a], RR.vx[a], RR.vy[a],
+                                              RR.vz[a], RR.R[a], RR.x[b], RR.y[b], RR.z[b],
+                                              RR.vx[b], RR.vy[b], RR.vz[b], RR.R[b], RR.dt);
+                RR.dtc[r] = t;
+                RR.flag[r] = t >= 0.0 ? 1 : 0;
+                RR.mmatch[a] = 0;
+                RR.mmatch[b] = 0;
+            }
         }
         __syncthreads();
     }
@@ -935,28 +956,6 @@ __device__ __forceinline__ int resolve_count(const DevState *st, int64_t pair_ca
     return (int)np;                       // pair indices are 32-bit (the capacity is)
 }
 
-// Contact time of every pair found (Eq. 2) and the per-moonlet state of the rounds;
-// spread over the whole GPU (the loads are scattered over the moonlet arrays).
-__global__ void __launch_bounds__(256)
-k_resolve_init(const DevState *__restrict__ st, const int64_t *__restrict__ keys,
-               int64_t pair_cap, const double *__restrict__ x, const double *__restrict__ y,
-               const double *__restrict__ z, const double *__restrict__ vx,
-               const double *__restrict__ vy, const double *__restrict__ vz,
-               const double *__restrict__ R, double dt, double *__restrict__ dtc,
-               int32_t *__restrict__ flag, int32_t *__restrict__ mmatch) {
-    const int np = resolve_count(st, pair_cap);
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
-        const int64_t k = keys[p];
-        const int i = pair_i(k), j = pair_j(k);
-        const double t = contact_time(x[i], y[i], z[i], vx[i], vy[i], vz[i], R[i], x[j], y[j],
-                                      z[j], vx[j], vy[j], vz[j], R[j], dt);
-        dtc[p] = t;
-        flag[p] = t >= 0.0 ? 1 : 0;
-        mmatch[i] = 0;
-        mmatch[j] = 0;
-    }
-}
-
 // The rounds of the matching and the list of resolved pairs, one block.
 __global__ void __launch_bounds__(kResolveThreads)
 k_resolve(DevState *st, const int64_t *__restrict__ keys, int64_t pair_cap,
@@ -1143,11 +1142,9 @@ hipError_t launch_resolve(const Workspace &ws, double *x, double *y, double *z, 
                           double f, int64_t *pairs, int64_t cap, int64_t *n_pairs_dev, int step,
                           int64_t *cursor, const unsigned long long *tests_part, int n_part,
                           hipStream_t s) {
+    const RankResolve RR = {x, y, z, vx, vy, vz, R, dt, ws.pair_dt, ws.pair_flag, ws.mmatch};
     k_rank_pairs<<<kRankGrid, kWave * kRankSplit, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap,
-                                                          ws.pairs_alt, tests_part, n_part);
-    k_resolve_init<<<kResolveGrid, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, x, y, z, vx,
-                                                vy, vz, R, dt, ws.pair_dt, ws.pair_flag,
-                                                ws.mmatch);
+                                                          ws.pairs_alt, tests_part, n_part, RR);
     // the unsorted list is no longer needed: its buffer holds the live pair indices
     k_resolve<<<1, kResolveThreads, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, ws.pair_dt,
                                             ws.pair_flag, ws.mbest, ws.mmatch,
@@ -1180,7 +1177,8 @@ hipError_t launch_emit_pairs(const Workspace &ws, int64_t *pairs, int64_t cap,
                              int64_t *n_pairs_dev, int triple, int step, int64_t *cursor,
                              const unsigned long long *tests_part, int n_part, hipStream_t s) {
     k_rank_pairs<<<kRankGrid, kWave * kRankSplit, 0, s>>>(ws.st, ws.pairs_tmp, ws.pair_cap,
-                                                          ws.pairs_alt, tests_part, n_part);
+                                                          ws.pairs_alt, tests_part, n_part,
+                                                          RankResolve{});
     k_emit_pairs<<<256, 256, 0, s>>>(ws.st, ws.pairs_alt, ws.pair_cap, pairs, cap, n_pairs_dev,
                                      triple, step, cursor);
     k_pairs_done<<<1, 64, 0, s>>>(ws.st, n_pairs_dev, cap, ws.pair_cap, triple, cursor);
