@@ -786,7 +786,7 @@ k_cand_count(const DevState *__restrict__ st, const int2 *__restrict__ m2l, int6
              const int2 *__restrict__ p2p, int64_t p2p_cap, const BoxArgs B,
              const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent,
              const int32_t *__restrict__ c_count, const int32_t *__restrict__ ent_cell,
-             int32_t *__restrict__ blk) {
+             int32_t *__restrict__ blk, uint64_t *__restrict__ live_bits) {
     __shared__ int wtot[kCandBlock / kWave];
     const CandLists L = cand_lists(st, m2l, m2l_cap, p2p, p2p_cap);
     const bool skip = (st->status & kSkipMask) != 0;
@@ -798,6 +798,11 @@ k_cand_count(const DevState *__restrict__ st, const int2 *__restrict__ m2l, int6
         if (q < L.total) pr = q < L.nm ? L.m2l[q] : L.p2p[q - L.nm];   // gaps are (-1, -1)
         const int cnt = leaf_candidates(pr, B, st, c_entry, c_nent, c_count, ent_cell, nullptr,
                                         0, 0);
+        // one bit per slot with candidates (a wave's 64 slots are one aligned word)
+        if (live_bits) {
+            const uint64_t m = __ballot(cnt > 0);
+            if ((threadIdx.x & (kWave - 1)) == 0) live_bits[(q0 + threadIdx.x) / kWave] = m;
+        }
         int excl;
         sum += block_excl(cnt, excl, wtot);
     }
@@ -851,7 +856,8 @@ k_cand_write(DevState *st, const int2 *__restrict__ m2l, int64_t m2l_cap,
              const int2 *__restrict__ p2p, int64_t p2p_cap, const BoxArgs B,
              const int32_t *__restrict__ c_entry, const int32_t *__restrict__ c_nent,
              const int32_t *__restrict__ c_count, const int32_t *__restrict__ ent_cell,
-             const int32_t *__restrict__ blk, int2 *cand, int64_t cand_cap) {
+             const int32_t *__restrict__ blk, int2 *cand, int64_t cand_cap,
+             const uint64_t *__restrict__ live_bits) {
     __shared__ int wtot[kCandBlock / kWave];
     if (st->status & kSkipMask) return;
     const CandLists L = cand_lists(st, m2l, m2l_cap, p2p, p2p_cap);
@@ -859,8 +865,11 @@ k_cand_write(DevState *st, const int2 *__restrict__ m2l, int64_t m2l_cap,
     for (int64_t q0 = (int64_t)blockIdx.x * kCandBlock; q0 < L.total;
          q0 += (int64_t)gridDim.x * kCandBlock) {
         const int64_t q = q0 + threadIdx.x;
+        // the count pass's bits: slots without candidates need no second look
+        const bool live = !live_bits ||
+                          ((live_bits[(q0 + threadIdx.x) / kWave] >> (threadIdx.x & (kWave - 1))) & 1ull);
         int2 pr = make_int2(-1, -1);
-        if (q < L.total) pr = q < L.nm ? L.m2l[q] : L.p2p[q - L.nm];
+        if (q < L.total && live) pr = q < L.nm ? L.m2l[q] : L.p2p[q - L.nm];
         const int cnt = leaf_candidates(pr, B, st, c_entry, c_nent, c_count, ent_cell, nullptr,
                                         0, 0);
         int excl;
@@ -885,13 +894,17 @@ hipError_t launch_candidates_from_lists(const Workspace &ws, hipStream_t s) {
     B.cbox = ws.cbox;
     B.gcell = ws.gcell;
     B.c_rmax = ws.c_rmax;
+    // one bit per list slot in the tree-order direct sums' buffer (3n words, free during
+    // a collision search), where the slots fit
+    const int64_t words = (ws.m2l_cap + ws.p2p_cap + kWave - 1) / kWave + kCandBlock / kWave;
+    uint64_t *bits = words <= 3 * ws.n_max ? (uint64_t *)ws.acc_s : nullptr;
     k_cand_count<<<(int)g, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap, B,
                                                ws.c_entry, ws.c_nent, ws.c_count, ws.ent_cell,
-                                               ws.cand_blk);
+                                               ws.cand_blk, bits);
     k_cand_scan<<<1, 1024, 0, s>>>(ws.st, ws.cand_blk, (int)g);
     k_cand_write<<<(int)g, kCandBlock, 0, s>>>(ws.st, ws.m2l, ws.m2l_cap, ws.p2p, ws.p2p_cap, B,
                                                ws.c_entry, ws.c_nent, ws.c_count, ws.ent_cell,
-                                               ws.cand_blk, ws.cand, ws.p2p_cap);
+                                               ws.cand_blk, ws.cand, ws.p2p_cap, bits);
     return hipGetLastError();
 }
 
