@@ -44,7 +44,8 @@ FLOPS_PER_INTERACTION = 20  # directed moonlet pair, the usual N-body convention
 P2P_TRAFFIC = {"source": "paper_2310_20374_amd/csrc/p2p.hip",
                "blob": "24806f309f8c8f758dd3293823e9518d4bee879f",
                "fetch_scale": 2.00, "write_scale": 1.00,
-               "by_leaf_size": {96: {"fetch_kib": (198843.8,), "write_kib": (25534.3,)}}}
+               # measured launch shape: (leaf size, source tile, most targets per lane)
+               "by_shape": {(96, 256, 4): {"fetch_kib": (198843.8,), "write_kib": (25534.3,)}}}
 
 
 def _git_blob(path):
@@ -53,10 +54,13 @@ def _git_blob(path):
     return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
 
 
-def _p2p_traffic(args, leaf_size):
+def _p2p_traffic(args, prm):
+    """HBM bytes of one direct-sum launch from the stored counters, when they were taken
+    on this source, this workload and this launch shape; else None."""
     t = P2P_TRAFFIC
     default = args.n == 1_000_000 and args.p == 6 and args.theta == 0.5
-    m = t["by_leaf_size"].get(int(leaf_size))
+    shape = (int(prm.leaf_size), int(prm.p2p_tile) or 256, int(prm.p2p_targets_max) or 4)
+    m = t["by_shape"].get(shape)
     if not default or m is None or _git_blob(os.path.join(ROOT, t["source"])) != t["blob"]:
         return None
     kib = sum(m["fetch_kib"]) * t["fetch_scale"] + sum(m["write_kib"]) * t["write_scale"]
@@ -698,7 +702,7 @@ def main():
                 "kernel": "direct sums, FP32 VALU (k_p2p<float>, one "
                           "gravity evaluation)",
                 "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": _p2p_traffic(args, prm32.leaf_size),
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": _p2p_traffic(args, prm32),
                 "avg_launch_us": p2p_avg_s * 1e6, "launches": p2p_launches,
                 "interactions_per_launch": info["p2p_inter"],
                 "flops_per_interaction": FLOPS_PER_INTERACTION}
