@@ -45,7 +45,8 @@ P2P_TRAFFIC = {"source": "paper_2310_20374_amd/csrc/p2p.hip",
                "blob": "24806f309f8c8f758dd3293823e9518d4bee879f",
                "fetch_scale": 2.00, "write_scale": 1.00,
                # measured launch shape: (leaf size, source tile, most targets per lane)
-               "by_shape": {(96, 256, 4): {"fetch_kib": (198843.8,), "write_kib": (25534.3,)}}}
+               "by_shape": {(96, 256, 4): {"fetch_kib": (198843.8,), "write_kib": (25534.3,)},
+                            (96, 128, 4): {"fetch_kib": (197890.7,), "write_kib": (25499.9,)}}}
 
 
 def _git_blob(path):
