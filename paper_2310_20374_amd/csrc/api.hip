@@ -372,8 +372,9 @@ int64_t layout_workspace(Workspace &ws, const ncorp_params &prm, int64_t n_max, 
     ws.mbest = (int32_t *)take(4 * n);
     ws.mmatch = (int32_t *)take(4 * n);
     ws.cand_blk = (int32_t *)take(4 * 8192);
-    // per-block partials: 16384 collision blocks, 2 per mesh block plus 1024, or one per
-    // standard-tree wave, whichever needs most
+    // per-block partials: the box pass's 16384 and the pair tests' kCollideGrid blocks,
+    // 2 per mesh block plus 1024, or one per standard-tree wave, whichever needs most
+    static_assert(kCollideGrid <= 2 * 16384 + 1024 + 128, "pair-test partials must fit");
     ws.count_part_n = n / 64 + 2 * 16384 + 1024 + 128;
     ws.count_part = (unsigned long long *)take(8 * ws.count_part_n);
     if (prm.gravity_method == NCORP_GRAVITY_MESH ||

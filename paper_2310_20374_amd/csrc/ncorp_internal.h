@@ -425,9 +425,10 @@ hipError_t launch_standard_tree_collide(const Workspace &ws, int64_t n, int ncb_
 // standard tree code (Alg. 1): accelerations of all moonlets, input order
 hipError_t launch_standard_tree(const Workspace &ws, int64_t n, int p, int ncb_pre, int ncb_post,
                                 double *ax, double *ay, double *az, hipStream_t s);
-// blocks of the tree's pair tests: each leaves its number of examined pairs in
-// ws.count_part, which the pair ranking that follows adds to st->col_tests
-constexpr int kCollideGrid = 16384;
+// blocks of the tree's pair tests (one wave each): each leaves its number of examined
+// pairs in ws.count_part (at least 33 920 entries at any n), which the pair ranking that
+// follows adds to st->col_tests
+constexpr int kCollideGrid = 32768;
 hipError_t launch_collide_pairs(const Workspace &ws, int64_t n, double dt, bool boxes,
                                 hipStream_t s);
 hipError_t launch_leaf_boxes(const Workspace &ws, int64_t n, double dt, hipStream_t s);
